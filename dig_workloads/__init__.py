@@ -1,0 +1,149 @@
+"""Seeded synthetic workloads shared by the HIP library's tests/bench and the oracle.
+
+This module only describes inputs (geometry, gas parameters, boundary
+conditions, seeds, initial fields and counts); it holds none of the method's
+arithmetic.  Every workload is synthetic, with the structure of the paper's
+cases: equilibrium Maxwellian starts, tens to thousands of particles per cell,
+fully diffuse isothermal walls, nitrogen-like VHS parameters (omega = 0.74,
+alpha = 1, two rotational degrees of freedom).
+
+Time steps are stated as a fraction of the mean collision time at unit density
+and temperature; ``TAU_C_PER_KN`` is that time per unit Knudsen number for
+omega = 0.74 (the oracle test suite checks it against the oracle's collision
+rate).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+OMEGA_N2 = 0.74
+TAU_C_PER_KN = 0.5167738723407999      # (5-2w)(7-2w) sqrt(2/pi) / 30 at w = 0.74
+LID_MA03 = 0.35496478698597694         # 0.3 * sqrt(1.4)
+U_INF_MA5 = 5.916079783099616          # 5 * sqrt(1.4)
+
+
+def _bc(kind, T=1.0, U=(0.0, 0.0, 0.0)):
+    return (kind, float(T), tuple(float(u) for u in U))
+
+
+def box(dim, nx, ny=1, lx=1.0, ly=1.0, kn=0.05, zrot=5.0, omega=OMEGA_N2, ppc=50,
+        dt_frac=0.2, bc=None, seed=1, instance=0, rho=1.0, u=(0.0, 0.0, 0.0), Tt=1.0,
+        Tr=None, tref=None, dt=None):
+    """A uniform box workload with uniform initial fields."""
+    if bc is None:
+        bc = [_bc("periodic")] * 4
+    ny = ny if dim == 2 else 1
+    vol = (lx / nx) * ((ly / ny) if dim == 2 else 1.0)
+    Tr = Tt if Tr is None else Tr
+    if dt is None:
+        dt = dt_frac * TAU_C_PER_KN * kn
+    temps = [Tt, Tr] + [b[1] for b in bc if b[0] == "diffuse"]
+    return dict(dim=dim, nx=nx, ny=ny, lx=lx, ly=ly, kn=kn, omega=omega, alpha=1.0, dr=2,
+                zrot=zrot, dt=dt, weight=rho * vol / ppc, bc=bc, seed=seed,
+                instance=instance, ppc=ppc,
+                init=dict(rho=rho, u=tuple(u), Tt=Tt, Tr=Tr),
+                tref=max(temps) if tref is None else tref)
+
+
+def fields_uniform(w):
+    """Initial fields [rho, ux, uy, uz, Tt, Tr] (6 x ncell) of a workload."""
+    nc = w["nx"] * w["ny"]
+    i = w["init"]
+    f = np.empty((6, nc), dtype=np.float64)
+    f[0] = i["rho"]
+    f[1], f[2], f[3] = i["u"]
+    f[4] = i["Tt"]
+    f[5] = i["Tr"]
+    return f
+
+
+# ---------------------------------------------------------------------------
+# The five configurations.
+
+def fourier_1d(seed=1001, nx=100, ppc=50, kn=0.05, zrot=5.0):
+    """1D Fourier heat transfer between diffuse plates at T = 1.0 and 1.5."""
+    bc = [_bc("diffuse", 1.0), _bc("diffuse", 1.5), _bc("periodic"), _bc("periodic")]
+    w = box(1, nx, kn=kn, zrot=zrot, ppc=ppc, bc=bc, seed=seed, Tt=1.25, Tr=1.25)
+    w["steps"] = 2000
+    w["name"] = f"fourier1d_{nx}c_{ppc}ppc_kn{kn}"
+    return w
+
+
+def cavity_2d(seed=2001, n=200, ppc=50, kn=0.01, lid=LID_MA03, zrot=5.0):
+    """Lid-driven cavity: diffuse walls at T = 1, lid (y = 1) moving in +x."""
+    bc = [_bc("diffuse", 1.0), _bc("diffuse", 1.0), _bc("diffuse", 1.0),
+          _bc("diffuse", 1.0, (lid, 0.0, 0.0))]
+    w = box(2, n, n, kn=kn, zrot=zrot, ppc=ppc, bc=bc, seed=seed)
+    w["ns"] = 50
+    w["name"] = f"cavity2d_{n}x{n}_{ppc}ppc_kn{kn}"
+    return w
+
+
+BATCH_CELLS = [100, 139, 193, 268, 373, 518, 720, 1000]
+BATCH_PPC = [20, 39, 75, 144, 278, 537, 1036, 2000]
+
+
+def batch_1d(n_inst=64, seed_base=3000, scale=1.0):
+    """64 uneven 1D instances: Kn log-spaced 1e-3..1, Z in {3, 5, 10}, even
+    instances Fourier (walls 1.0 / 1.5), odd instances Couette (T = 1, walls
+    moving -0.5 / +0.5 in y).  ``scale`` < 1 shrinks particle counts for tests."""
+    out = []
+    for i in range(n_inst):
+        nx = BATCH_CELLS[i % 8]
+        ppc = max(2, int(round(BATCH_PPC[(i // 8) % 8] * scale)))
+        kn = 10.0 ** (-3.0 + 3.0 * ((29 * i) % 64) / 63.0)
+        zrot = [3.0, 5.0, 10.0][i % 3]
+        if i % 2 == 0:
+            bc = [_bc("diffuse", 1.0), _bc("diffuse", 1.5), _bc("periodic"), _bc("periodic")]
+            T0 = 1.25
+        else:
+            bc = [_bc("diffuse", 1.0, (0, -0.5, 0)), _bc("diffuse", 1.0, (0, 0.5, 0)),
+                  _bc("periodic"), _bc("periodic")]
+            T0 = 1.0
+        dx = 1.0 / nx
+        dt = min(0.2 * TAU_C_PER_KN * kn, 0.5 * dx / math.sqrt(8.0 * 1.5 / math.pi))
+        w = box(1, nx, kn=kn, zrot=zrot, ppc=ppc, bc=bc, seed=seed_base + i, instance=i,
+                Tt=T0, Tr=T0, dt=dt)
+        w["name"] = f"batch{i}"
+        out.append(w)
+    return out
+
+
+def scaled(w, **kw):
+    v = copy.deepcopy(w)
+    v.update(kw)
+    return v
+
+
+def random_sorted_state(w, seed, n_per_cell_mean=None, rng_kind="poisson"):
+    """A cell-sorted random particle state for injection into both sides:
+    per-cell counts (Poisson), positions uniform in the cell (grid units),
+    Maxwellian velocities around the initial flow, exponential rotational
+    energies.  Returns (x, y, vx, vy, vz, er, id, start) in float32/uint32."""
+    rng = np.random.default_rng(seed)
+    nc = w["nx"] * w["ny"]
+    lam = w["ppc"] if n_per_cell_mean is None else n_per_cell_mean
+    counts = rng.poisson(lam, size=nc) if rng_kind == "poisson" else np.full(nc, lam)
+    start = np.zeros(nc + 1, dtype=np.int64)
+    start[1:] = np.cumsum(counts)
+    n = int(start[-1])
+    cell = np.repeat(np.arange(nc), counts)
+    ix = cell % w["nx"]
+    iy = cell // w["nx"]
+    x = (ix + rng.random(n)).astype(np.float32)
+    y = ((iy + rng.random(n)) if w["dim"] == 2 else np.zeros(n)).astype(np.float32)
+    # keep positions strictly inside their cell after rounding to float32
+    x = np.minimum(x, np.nextafter((ix + 1).astype(np.float32), np.float32(0)))
+    if w["dim"] == 2:
+        y = np.minimum(y, np.nextafter((iy + 1).astype(np.float32), np.float32(0)))
+    i = w["init"]
+    s = math.sqrt(i["Tt"])
+    vx = (i["u"][0] + s * rng.standard_normal(n)).astype(np.float32)
+    vy = (i["u"][1] + s * rng.standard_normal(n)).astype(np.float32)
+    vz = (i["u"][2] + s * rng.standard_normal(n)).astype(np.float32)
+    er = (i["Tr"] * rng.exponential(size=n)).astype(np.float32)
+    ids = rng.permutation(n).astype(np.uint32)
+    return dict(x=x, y=y, vx=vx, vy=vy, vz=vz, er=er, id=ids, start=start)

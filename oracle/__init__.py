@@ -1,0 +1,331 @@
+"""FP64 CPU oracle for the DSMC + DIG hot path (arXiv:2501.10965).
+
+TEST INFRASTRUCTURE ONLY.  The tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are the only callers; the product path never
+imports this package.  The C source (``dsmc_oracle.c``) is a plain, single
+threaded, double precision transcription of the method: Philox streams,
+initialisation, free flight with diffuse walls, stable counting sort, NTC/VHS
+collisions with Borgnakke-Larsen exchange, moment sampling, DIG particle
+modification and closure assembly.  ``synth.py`` and ``mlp.py`` hold the
+synthetic-equation and learned-closure oracles (numpy, FP64).
+
+The HIP library shares no code with this package; both are driven from the
+same workload descriptions in ``dig_workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_DIR = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_DIR, "liboracle.so")
+_SRC = [os.path.join(_DIR, "dsmc_oracle.c")]
+
+BC = {"periodic": 0, "diffuse": 1, "specular": 2}
+TAG = {"init": 1, "init_n": 2, "wall": 3, "ncand": 4, "coll": 5, "dig_n": 6,
+       "dig_del": 7, "dig_src": 8, "dig_empty": 9}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with plain IEEE double arithmetic (no contraction)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", _SO] + _SRC + ["-lm"]
+        subprocess.run(cmd, check=True)
+    return _SO
+
+
+class Config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double),
+                ("kn", C.c_double), ("omega", C.c_double), ("alpha", C.c_double),
+                ("dr", C.c_int32), ("zrot", C.c_double),
+                ("dt", C.c_double), ("weight", C.c_double),
+                ("bc_type", C.c_int32 * 4), ("bc_T", C.c_double * 4),
+                ("bc_U", (C.c_double * 3) * 4),
+                ("seed", C.c_uint64), ("instance", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("candidates", C.c_int64), ("accepted", C.c_int64),
+                ("inelastic", C.c_int64), ("saturated", C.c_int64)]
+
+
+_lib = None
+
+_d = C.POINTER(C.c_double)
+_f = C.POINTER(C.c_float)
+_u32 = C.POINTER(C.c_uint32)
+_i32 = C.POINTER(C.c_int32)
+_i64 = C.POINTER(C.c_int64)
+_u8 = C.POINTER(C.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        cp = C.POINTER(Config)
+        L.orc_philox.argtypes = [_u32, _u32, _u32]
+        L.orc_draw.argtypes = [cp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _u32]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_pick.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_pick.restype = C.c_uint32
+        for fn in ("orc_mu0", "orc_csigma", "orc_pinelastic", "orc_cell_volume"):
+            getattr(L, fn).argtypes = [cp]
+            getattr(L, fn).restype = C.c_double
+        L.orc_init.argtypes = [cp, _d, C.c_int32, C.c_int64, _d, _d, _d, _d, _d, _d, _u32]
+        L.orc_init.restype = C.c_int64
+        L.orc_move.argtypes = [cp, C.c_int64, _d, _d, _d, _d, _d, _d, _u32, C.c_uint32]
+        L.orc_move.restype = C.c_int64
+        L.orc_cell_index.argtypes = [cp, C.c_int64, _d, _d, _i32]
+        L.orc_sort.argtypes = [C.c_int64, _i32, C.c_int32, _i64, _i64]
+        L.orc_collide.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _f, C.c_uint32,
+                                  C.POINTER(Stats), _d]
+        L.orc_sample_sums.argtypes = [C.c_int32, _i64, _d, _d, _d, _d, _d]
+        L.orc_sums_to_fields.argtypes = [cp, C.c_int32, _d, C.c_double, _d]
+        L.orc_adjust.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _d, _d, _u32, _d,
+                                 C.c_uint32, C.c_uint64, C.c_int64, _d, _d, _d, _d, _d,
+                                 _d, _u32, _i64, _i64, C.POINTER(C.c_uint64)]
+        L.orc_adjust.restype = C.c_int
+        L.orc_closure.argtypes = [cp, _d, _d, C.c_double, _d, _u8, _d, _d]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(t)
+
+
+def make_config(w: dict) -> Config:
+    """Oracle configuration from a workload description (see dig_workloads)."""
+    c = Config()
+    c.dim = w["dim"]
+    c.nx = w["nx"]
+    c.ny = w.get("ny", 1)
+    c.lx = w["lx"]
+    c.ly = w.get("ly", 1.0)
+    c.kn = w["kn"]
+    c.omega = w["omega"]
+    c.alpha = w.get("alpha", 1.0)
+    c.dr = w.get("dr", 2)
+    c.zrot = w["zrot"]
+    c.dt = w["dt"]
+    c.weight = w["weight"]
+    for f, bc in enumerate(w["bc"]):
+        c.bc_type[f] = BC[bc[0]]
+        c.bc_T[f] = bc[1]
+        for k in range(3):
+            c.bc_U[f][k] = bc[2][k]
+    c.seed = w["seed"]
+    c.instance = w.get("instance", 0)
+    return c
+
+
+# --------------------------------------------------------------------------
+def philox(ctr, key):
+    a = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(_p(a, _u32), _p(k, _u32), _p(out, _u32))
+    return out
+
+
+def csigma(w):
+    return lib().orc_csigma(C.byref(make_config(w)))
+
+
+def pinelastic(w):
+    return lib().orc_pinelastic(C.byref(make_config(w)))
+
+
+def mu0(w):
+    return lib().orc_mu0(C.byref(make_config(w)))
+
+
+def cell_volume(w):
+    return lib().orc_cell_volume(C.byref(make_config(w)))
+
+
+class State:
+    """Particle state of one instance in FP64 (positions in grid units)."""
+
+    def __init__(self, w: dict, cap: int):
+        self.w = w
+        self.cfg = make_config(w)
+        self.ncell = w["nx"] * w.get("ny", 1)
+        self.cap = int(cap)
+        z = lambda: np.zeros(self.cap, dtype=np.float64)
+        self.x, self.y, self.vx, self.vy, self.vz, self.er = z(), z(), z(), z(), z(), z()
+        self.id = np.zeros(self.cap, dtype=np.uint32)
+        self.n = 0
+        self.start = np.zeros(self.ncell + 1, dtype=np.int64)
+        self.sgmax = np.zeros(self.ncell, dtype=np.float32)
+        self.acc = np.zeros((self.ncell, 17), dtype=np.float64)
+        self.nsamp = 0
+        self.step_no = 0
+        self.next_id = 0
+
+    # -- state injection --------------------------------------------------
+    def load(self, x, y, vx, vy, vz, er, id_, start=None, sgmax=None, step=None,
+             next_id=None):
+        n = len(x)
+        assert n <= self.cap
+        for dst, src in ((self.x, x), (self.y, y), (self.vx, vx), (self.vy, vy),
+                         (self.vz, vz), (self.er, er)):
+            dst[:n] = np.asarray(src, dtype=np.float64)
+        self.id[:n] = np.asarray(id_, dtype=np.uint32)
+        self.n = n
+        if start is not None:
+            self.start[:] = np.asarray(start, dtype=np.int64)
+        if sgmax is not None:
+            self.sgmax[:] = np.asarray(sgmax, dtype=np.float32)
+        if step is not None:
+            self.step_no = int(step)
+        if next_id is not None:
+            self.next_id = int(next_id)
+
+    def arrays(self):
+        n = self.n
+        return dict(x=self.x[:n].copy(), y=self.y[:n].copy(), vx=self.vx[:n].copy(),
+                    vy=self.vy[:n].copy(), vz=self.vz[:n].copy(), er=self.er[:n].copy(),
+                    id=self.id[:n].copy())
+
+    # -- steps -------------------------------------------------------------
+    def init(self, fields: np.ndarray, ppc: int, sgmax0: float):
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        n = lib().orc_init(C.byref(self.cfg), _p(f, _d), int(ppc), self.cap, _p(self.x, _d),
+                           _p(self.y, _d), _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d),
+                           _p(self.er, _d), _p(self.id, _u32))
+        if n < 0:
+            raise RuntimeError("oracle init: capacity exceeded")
+        self.n = int(n)
+        self.next_id = self.n
+        self.sgmax[:] = np.float32(sgmax0)
+        cell = self.cells()
+        self.start[:] = np.searchsorted(cell, np.arange(self.ncell + 1), side="left")
+
+    def move(self):
+        return lib().orc_move(C.byref(self.cfg), self.n, _p(self.x, _d), _p(self.y, _d),
+                              _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d),
+                              _p(self.er, _d), _p(self.id, _u32), self.step_no)
+
+    def cells(self):
+        cell = np.zeros(max(self.n, 1), dtype=np.int32)
+        lib().orc_cell_index(C.byref(self.cfg), self.n, _p(self.x, _d), _p(self.y, _d),
+                             _p(cell, _i32))
+        return cell[: self.n]
+
+    def sort(self):
+        """Stable counting sort by cell; returns the permutation applied."""
+        cell = np.ascontiguousarray(self.cells())
+        perm = np.zeros(max(self.n, 1), dtype=np.int64)
+        lib().orc_sort(self.n, _p(cell, _i32), self.ncell, _p(perm, _i64),
+                       _p(self.start, _i64))
+        perm = perm[: self.n]
+        for a in (self.x, self.y, self.vx, self.vy, self.vz, self.er, self.id):
+            a[: self.n] = a[: self.n][perm]
+        return perm
+
+    def collide(self, with_obs=False):
+        st = Stats()
+        obs = np.zeros(self.ncell, dtype=np.float64)
+        lib().orc_collide(C.byref(self.cfg), self.ncell, _p(self.start, _i64),
+                          _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d), _p(self.er, _d),
+                          _p(self.sgmax, _f), self.step_no, C.byref(st), _p(obs, _d))
+        res = dict(candidates=st.candidates, accepted=st.accepted, inelastic=st.inelastic,
+                   saturated=st.saturated)
+        if with_obs:
+            res["obs"] = obs
+        return res
+
+    def sums(self):
+        s = np.zeros((self.ncell, 17), dtype=np.float64)
+        lib().orc_sample_sums(self.ncell, _p(self.start, _i64), _p(self.vx, _d),
+                              _p(self.vy, _d), _p(self.vz, _d), _p(self.er, _d), _p(s, _d))
+        return s
+
+    def step(self, sample=True):
+        """One DSMC step: move, index + stable sort, collide, sample."""
+        self.move()
+        self.sort()
+        st = self.collide()
+        if sample:
+            self.acc += self.sums()
+            self.nsamp += 1
+        self.step_no += 1
+        return st
+
+    def fields(self, sums=None, nsteps=None):
+        if sums is None:
+            sums, nsteps = self.acc, max(self.nsamp, 1)
+        s = np.ascontiguousarray(sums, dtype=np.float64)
+        out = np.zeros((20, self.ncell), dtype=np.float64)
+        lib().orc_sums_to_fields(C.byref(self.cfg), self.ncell, _p(s, _d), float(nsteps),
+                                 _p(out, _d))
+        return out
+
+    def reset_average(self):
+        self.acc[:] = 0.0
+        self.nsamp = 0
+
+    def adjust(self, target: np.ndarray, dig_iter: int):
+        t = np.ascontiguousarray(target, dtype=np.float64)
+        out = State(self.w, self.cap)
+        n_out = C.c_int64(0)
+        nid = C.c_uint64(0)
+        rc = lib().orc_adjust(C.byref(self.cfg), self.ncell, _p(self.start, _i64),
+                              _p(self.x, _d), _p(self.y, _d), _p(self.vx, _d), _p(self.vy, _d),
+                              _p(self.vz, _d), _p(self.er, _d), _p(self.id, _u32), _p(t, _d),
+                              int(dig_iter), self.next_id, self.cap, _p(out.x, _d),
+                              _p(out.y, _d), _p(out.vx, _d), _p(out.vy, _d), _p(out.vz, _d),
+                              _p(out.er, _d), _p(out.id, _u32), _p(out.start, _i64),
+                              C.byref(n_out), C.byref(nid))
+        if rc != 0:
+            return rc
+        for name in ("x", "y", "vx", "vy", "vz", "er", "id", "start"):
+            setattr(self, name, getattr(out, name))
+        self.n = int(n_out.value)
+        self.next_id = int(nid.value)
+        return 0
+
+
+def closure(w: dict, fields: np.ndarray, A, kn_ref: float):
+    cfg = make_config(w)
+    ncell = w["nx"] * w.get("ny", 1)
+    f = np.ascontiguousarray(fields, dtype=np.float64)
+    a = np.ascontiguousarray(A, dtype=np.float64)
+    hot = np.zeros((12, ncell))
+    nsf = np.zeros((12, ncell))
+    mask = np.zeros(ncell, dtype=np.uint8)
+    kn = np.zeros(ncell)
+    lib().orc_closure(C.byref(cfg), _p(f, _d), _p(a, _d), float(kn_ref), _p(hot, _d),
+                      _p(mask, _u8), _p(kn, _d), _p(nsf, _d))
+    return hot, mask, kn, nsf
+
+
+def sgmax_default(w: dict) -> float:
+    """Initial majorant of sigma_T g per cell: the VHS value at a relative speed
+    of six times the relative-velocity spread at the workload's reference
+    temperature (raised later to the observed maximum)."""
+    g = 6.0 * np.sqrt(2.0 * w["tref"])
+    return csigma(w) * g ** (2.0 - 2.0 * w["omega"])
+
+
+def new_state(w: dict, cap_factor: float = 1.3, cap: int | None = None) -> "State":
+    """Oracle state of a workload, initialised with its uniform fields."""
+    import dig_workloads as _wl  # input recipes only
+
+    nc = w["nx"] * w.get("ny", 1)
+    if cap is None:
+        cap = int(nc * w["ppc"] * cap_factor) + 64
+    s = State(w, cap)
+    s.init(_wl.fields_uniform(w), w["ppc"], sgmax_default(w))
+    return s

@@ -1,0 +1,676 @@
+/*
+ * FP64 CPU oracle for the DSMC + DIG hot path (arXiv:2501.10965).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  Written for
+ * readability, single threaded, in the order the paper states the steps.
+ *
+ * Readings where the paper is silent are the ones listed in the design notes
+ * of the repository (NTC candidate count by Iround, sgmax frozen within a
+ * step, rotational energy stored per unit mass, Bird's double relaxation in
+ * pick order, Beta(1, 5/2 - omega) energy split for two rotational degrees of
+ * freedom, survivors-then-clones particle order after the DIG count change).
+ */
+#include "dsmc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of two
+ * 32x32->64 multiplies and xors, with a Weyl key schedule between rounds. */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* Counter layout: (entity, step, tag << 24 | instance, draw); key = seed. */
+void orc_draw(const orc_config* c, uint32_t entity, uint32_t step, uint32_t tag,
+              uint32_t draw, uint32_t out[4]) {
+  uint32_t ctr[4] = {entity, step, (tag << 24) | (c->instance & 0xFFFFFFu), draw};
+  uint32_t key[2] = {(uint32_t)(c->seed & 0xFFFFFFFFu), (uint32_t)(c->seed >> 32)};
+  orc_philox(ctr, key, out);
+}
+
+/* Uniform in (0,1): the top 23 bits centred in their interval; exactly
+ * representable in single precision, so both precisions see the same value. */
+double orc_u01(uint32_t r) { return ((double)(r >> 9) + 0.5) * (1.0 / 8388608.0); }
+
+/* Uniform integer in [0, n). */
+uint32_t orc_pick(uint32_t r, uint32_t n) { return (uint32_t)(((uint64_t)r * n) >> 32); }
+
+/* ------------------------------------------------------------------------ */
+/* Gas constants.  The Knudsen number definition of Section 2 gives
+ * mu(T0) = Kn sqrt(2/pi) in paper units; mu = mu0 T^omega. */
+double orc_mu0(const orc_config* c) { return c->kn * sqrt(2.0 / M_PI); }
+
+/* VHS: sigma_T * g = C g^(2 - 2 omega).  C is fixed so that the equilibrium
+ * collision frequency n <sigma_T g> equals the VHS value
+ * 30 p / ((5 - 2w)(7 - 2w) mu), which ties the collision rate to the
+ * viscosity mu0 T^omega above. */
+double orc_csigma(const orc_config* c) {
+  double w = c->omega;
+  double num = 15.0 * M_PI;
+  double den = sqrt(2.0) * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) * pow(4.0, 1.0 - w) *
+               tgamma(2.5 - w) * c->kn;
+  return num / den;
+}
+
+/* Fraction of inelastic collisions, equation P_inelastic (Section 2.2). */
+double orc_pinelastic(const orc_config* c) {
+  double w = c->omega, a = c->alpha;
+  return a * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) / (5.0 * (a + 1.0) * (a + 2.0) * c->zrot);
+}
+
+double orc_cell_volume(const orc_config* c) {
+  double dx = c->lx / c->nx;
+  if (c->dim == 1) return dx;
+  return dx * (c->ly / c->ny);
+}
+
+static double iround(double x, double u) {
+  double f = floor(x);
+  return f + ((u < x - f) ? 1.0 : 0.0);
+}
+
+static void box_muller(double ua, double ub, double* z0, double* z1) {
+  double r = sqrt(-2.0 * log(ua));
+  *z0 = r * cos(2.0 * M_PI * ub);
+  *z1 = r * sin(2.0 * M_PI * ub);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initialisation (DIG step 1, Section 3): particles drawn from the local
+ * equilibrium of fields [rho, ux, uy, uz, Tt, Tr] (each an array of ncell).
+ * ppc > 0 puts exactly ppc particles in every cell; otherwise the count is
+ * Iround(rho V / N_eff) as in the particle-number rule of Section 3.2. */
+int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t cap,
+                 double* x, double* y, double* vx, double* vy, double* vz, double* er,
+                 uint32_t* id) {
+  int32_t ncell = c->nx * c->ny;
+  double V = orc_cell_volume(c);
+  const double *rho = fields, *ux = fields + ncell, *uy = fields + 2 * ncell,
+               *uz = fields + 3 * ncell, *tt = fields + 4 * ncell, *tr = fields + 5 * ncell;
+  int64_t n = 0;
+  for (int32_t cell = 0; cell < ncell; ++cell) {
+    int64_t cnt;
+    if (ppc > 0) {
+      cnt = ppc;
+    } else {
+      uint32_t w[4];
+      orc_draw(c, (uint32_t)cell, 0, ORC_TAG_INIT_N, 0, w);
+      cnt = (int64_t)iround(rho[cell] * V / c->weight, orc_u01(w[0]));
+    }
+    if (n + cnt > cap) return -1;
+    int32_t ix = cell % c->nx, iy = cell / c->nx;
+    double st = sqrt(tt[cell]);
+    for (int64_t k = 0; k < cnt; ++k, ++n) {
+      uint32_t a[4], b[4];
+      orc_draw(c, (uint32_t)n, 0, ORC_TAG_INIT, 0, a);
+      orc_draw(c, (uint32_t)n, 0, ORC_TAG_INIT, 1, b);
+      double z0, z1, z2, z3;
+      box_muller(orc_u01(a[2]), orc_u01(a[3]), &z0, &z1);
+      box_muller(orc_u01(b[0]), orc_u01(b[1]), &z2, &z3);
+      x[n] = ix + orc_u01(a[0]);
+      y[n] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
+      vx[n] = ux[cell] + st * z0;
+      vy[n] = uy[cell] + st * z1;
+      vz[n] = uz[cell] + st * z2;
+      er[n] = -tr[cell] * log(orc_u01(b[2]));
+      id[n] = (uint32_t)n;
+    }
+  }
+  return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Free flight with fully diffuse (or specular) walls, Section 2.2 and the
+ * gas-surface model stated in Section 4.  Wall events are taken in time
+ * order; a tie goes to the x face.  Periodic axes wrap at the end. */
+#define ORC_MAXHIT 8
+
+static int is_wall(int t) { return t == ORC_BC_DIFFUSE || t == ORC_BC_SPECULAR; }
+
+int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* vx,
+                 double* vy, double* vz, double* er, const uint32_t* id, uint32_t step) {
+  double dx = c->lx / c->nx, dy = (c->dim == 2) ? c->ly / c->ny : 1.0;
+  double gx = c->nx, gy = c->ny;
+  int64_t hits_total = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    double t = c->dt;
+    int hit = 0;
+    for (;;) {
+      double sx = vx[p] / dx, sy = (c->dim == 2) ? vy[p] / dy : 0.0;
+      int face = -1;
+      double th = t;
+      double xe = x[p] + sx * t;
+      if (xe < 0.0 && is_wall(c->bc_type[0])) {
+        double tf = (0.0 - x[p]) / sx;
+        if (tf <= th) { th = tf; face = 0; }
+      } else if (xe > gx && is_wall(c->bc_type[1])) {
+        double tf = (gx - x[p]) / sx;
+        if (tf <= th) { th = tf; face = 1; }
+      }
+      if (c->dim == 2) {
+        double ye = y[p] + sy * t;
+        if (ye < 0.0 && is_wall(c->bc_type[2])) {
+          double tf = (0.0 - y[p]) / sy;
+          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 2; }
+        } else if (ye > gy && is_wall(c->bc_type[3])) {
+          double tf = (gy - y[p]) / sy;
+          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 3; }
+        }
+      }
+      if (face < 0 || hit >= ORC_MAXHIT) {
+        x[p] += sx * t;
+        if (c->dim == 2) y[p] += sy * t;
+        if (hit >= ORC_MAXHIT) { /* pathological: clamp into the box */
+          if (is_wall(c->bc_type[0]) && x[p] < 0.0) x[p] = 0.0;
+          if (is_wall(c->bc_type[1]) && x[p] > gx) x[p] = gx;
+          if (c->dim == 2) {
+            if (is_wall(c->bc_type[2]) && y[p] < 0.0) y[p] = 0.0;
+            if (is_wall(c->bc_type[3]) && y[p] > gy) y[p] = gy;
+          }
+        }
+        break;
+      }
+      /* advance to the wall and put the particle exactly on it */
+      x[p] += sx * th;
+      if (c->dim == 2) y[p] += sy * th;
+      if (face == 0) x[p] = 0.0;
+      if (face == 1) x[p] = gx;
+      if (face == 2) y[p] = 0.0;
+      if (face == 3) y[p] = gy;
+      t -= th;
+      int axis = face / 2;
+      double inward = (face % 2 == 0) ? 1.0 : -1.0;
+      if (c->bc_type[face] == ORC_BC_SPECULAR) {
+        if (axis == 0) vx[p] = -vx[p]; else vy[p] = -vy[p];
+      } else {
+        uint32_t w[4];
+        orc_draw(c, id[p], step, ORC_TAG_WALL, (uint32_t)hit, w);
+        double T = c->bc_T[face];
+        double vn = sqrt(-2.0 * T * log(orc_u01(w[0])));
+        double z0, z1;
+        box_muller(orc_u01(w[1]), orc_u01(w[2]), &z0, &z1);
+        double s = sqrt(T);
+        if (axis == 0) {
+          vx[p] = inward * vn;
+          vy[p] = c->bc_U[face][1] + s * z0;
+        } else {
+          vy[p] = inward * vn;
+          vx[p] = c->bc_U[face][0] + s * z0;
+        }
+        vz[p] = c->bc_U[face][2] + s * z1;
+        er[p] = -T * log(orc_u01(w[3]));
+      }
+      ++hit;
+      ++hits_total;
+    }
+    if (c->bc_type[0] == ORC_BC_PERIODIC) x[p] -= gx * floor(x[p] / gx);
+    if (c->dim == 2 && c->bc_type[2] == ORC_BC_PERIODIC) y[p] -= gy * floor(y[p] / gy);
+  }
+  return hits_total;
+}
+
+/* Cell of a grid-unit position: floor, clamped to the last cell when a
+ * particle sits exactly on the upper face. */
+void orc_cell_index(const orc_config* c, int64_t n, const double* x, const double* y,
+                    int32_t* cell) {
+  for (int64_t p = 0; p < n; ++p) {
+    int32_t ix = (int32_t)floor(x[p]);
+    if (ix < 0) ix = 0;
+    if (ix > c->nx - 1) ix = c->nx - 1;
+    int32_t iy = 0;
+    if (c->dim == 2) {
+      iy = (int32_t)floor(y[p]);
+      if (iy < 0) iy = 0;
+      if (iy > c->ny - 1) iy = c->ny - 1;
+    }
+    cell[p] = ix + c->nx * iy;
+  }
+}
+
+/* Stable counting sort: new slot k holds old particle perm[k]; particles of a
+ * cell keep their previous relative order. */
+void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int64_t* start) {
+  int64_t* fill = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
+  for (int32_t c = 0; c <= ncell; ++c) start[c] = 0;
+  for (int64_t p = 0; p < n; ++p) start[cell[p] + 1] += 1;
+  for (int32_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+  for (int64_t p = 0; p < n; ++p) {
+    int32_t c = cell[p];
+    perm[start[c] + fill[c]] = p;
+    fill[c] += 1;
+  }
+  free(fill);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collisions in every cell (Section 2.2): no-time-counter candidate pairs,
+ * VHS acceptance, Borgnakke-Larsen exchange with double relaxation, isotropic
+ * scattering (VSS with alpha = 1).  The state arrays are in cell order. */
+void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
+                 double* vy, double* vz, double* er, float* sgmax, uint32_t step,
+                 orc_collide_stats* st, double* obs_out) {
+  double csig = orc_csigma(c);
+  double pin = orc_pinelastic(c);
+  double V = orc_cell_volume(c);
+  double expo = 1.0 - c->omega;            /* sigma g = C (g^2)^(1 - omega) */
+  double beta_inv = 1.0 / (2.5 - c->omega); /* Beta(1, 5/2 - omega) inverse CDF */
+  for (int32_t cell = 0; cell < ncell; ++cell) {
+    int64_t b = start[cell];
+    int64_t N = start[cell + 1] - b;
+    double sgm = (double)sgmax[cell];
+    double obs = 0.0;
+    int64_t ncand = 0;
+    if (N >= 2) {
+      uint32_t w[4];
+      orc_draw(c, (uint32_t)cell, step, ORC_TAG_NCAND, 0, w);
+      double xc = 0.5 * (double)N * (double)(N - 1) * c->weight * sgm * c->dt / V;
+      ncand = (int64_t)iround(xc, orc_u01(w[0]));
+    }
+    for (int64_t k = 0; k < ncand; ++k) {
+      uint32_t r0[4], r1[4], r2[4];
+      orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k), r0);
+      int64_t i = orc_pick(r0[0], (uint32_t)N);
+      int64_t j = orc_pick(r0[1], (uint32_t)(N - 1));
+      if (j >= i) j += 1;
+      i += b;
+      j += b;
+      double gxv = vx[i] - vx[j], gyv = vy[i] - vy[j], gzv = vz[i] - vz[j];
+      double g2 = gxv * gxv + gyv * gyv + gzv * gzv;
+      double sg = csig * pow(g2, expo);
+      if (sg > obs) obs = sg;
+      double ratio = sg / sgm;
+      if (st) st->candidates += 1;
+      if (ratio > 1.0 && st) st->saturated += 1;
+      if (!(orc_u01(r0[2]) < ratio)) continue;
+      if (st) st->accepted += 1;
+      orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 1), r1);
+      orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 2), r2);
+      double et = 0.25 * g2; /* relative translational energy, reduced mass 1/2 */
+      /* first picked particle, then the second: Bird's double relaxation */
+      if (orc_u01(r0[3]) < pin) {
+        double ec = et + er[i];
+        double frac = 1.0 - pow(orc_u01(r1[0]), beta_inv);
+        er[i] = frac * ec;
+        et = ec - er[i];
+        if (st) st->inelastic += 1;
+      }
+      if (orc_u01(r1[1]) < pin) {
+        double ec = et + er[j];
+        double frac = 1.0 - pow(orc_u01(r1[2]), beta_inv);
+        er[j] = frac * ec;
+        et = ec - er[j];
+        if (st) st->inelastic += 1;
+      }
+      double gp = 2.0 * sqrt(et);
+      double ct = 2.0 * orc_u01(r1[3]) - 1.0;
+      double stt = sqrt(1.0 - ct * ct);
+      double ph = 2.0 * M_PI * orc_u01(r2[0]);
+      double nx = ct, ny = stt * cos(ph), nz = stt * sin(ph);
+      double cx = 0.5 * (vx[i] + vx[j]), cy = 0.5 * (vy[i] + vy[j]), cz = 0.5 * (vz[i] + vz[j]);
+      vx[i] = cx + 0.5 * gp * nx;
+      vy[i] = cy + 0.5 * gp * ny;
+      vz[i] = cz + 0.5 * gp * nz;
+      vx[j] = cx - 0.5 * gp * nx;
+      vy[j] = cy - 0.5 * gp * ny;
+      vz[j] = cz - 0.5 * gp * nz;
+    }
+    if (obs_out) obs_out[cell] = obs;
+    if (obs > sgm) {
+      float f = (float)obs;
+      if ((double)f < obs) f = nextafterf(f, INFINITY);
+      sgmax[cell] = f;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Raw per-cell sums behind the sampled moments of equation DSMC_macroscopic:
+ * [N, Sv(3), Svv(xx,yy,zz,xy,xz,yz), Sv|v|^2(3), Ser, Sv er(3)]. */
+void orc_sample_sums(int32_t ncell, const int64_t* start, const double* vx,
+                     const double* vy, const double* vz, const double* er, double* sums) {
+  for (int32_t c = 0; c < ncell; ++c) {
+    double* s = sums + 17 * (int64_t)c;
+    for (int f = 0; f < 17; ++f) s[f] = 0.0;
+    for (int64_t p = start[c]; p < start[c + 1]; ++p) {
+      double a = vx[p], b = vy[p], d = vz[p], e = er[p];
+      double v2 = a * a + b * b + d * d;
+      s[0] += 1.0;
+      s[1] += a;
+      s[2] += b;
+      s[3] += d;
+      s[4] += a * a;
+      s[5] += b * b;
+      s[6] += d * d;
+      s[7] += a * b;
+      s[8] += a * d;
+      s[9] += b * d;
+      s[10] += a * v2;
+      s[11] += b * v2;
+      s[12] += d * v2;
+      s[13] += e;
+      s[14] += a * e;
+      s[15] += b * e;
+      s[16] += d * e;
+    }
+  }
+}
+
+/* Sums pooled over nsteps steps -> fields [20][ncell]:
+ * rho, ux, uy, uz, Tt, Tr, sxx, syy, szz, sxy, sxz, syz, qtx, qty, qtz,
+ * qrx, qry, qrz, T, mean particle count.  Equation DSMC_macroscopic, with the
+ * rotational energy per unit mass er = I_r / 2 (so Tr = 2<er>/d_r and
+ * q_r = rho <c er>). */
+void orc_sums_to_fields(const orc_config* c, int32_t ncell, const double* sums,
+                        double nsteps, double* fields) {
+  double V = orc_cell_volume(c);
+  for (int32_t cell = 0; cell < ncell; ++cell) {
+    const double* s = sums + 17 * (int64_t)cell;
+    double out[20];
+    for (int f = 0; f < 20; ++f) out[f] = 0.0;
+    double N = s[0];
+    if (N > 0.0) {
+      double rho = c->weight * N / (V * nsteps);
+      double u[3] = {s[1] / N, s[2] / N, s[3] / N};
+      /* central second moments <c_i c_j> */
+      double m2[3][3];
+      m2[0][0] = s[4] / N - u[0] * u[0];
+      m2[1][1] = s[5] / N - u[1] * u[1];
+      m2[2][2] = s[6] / N - u[2] * u[2];
+      m2[0][1] = m2[1][0] = s[7] / N - u[0] * u[1];
+      m2[0][2] = m2[2][0] = s[8] / N - u[0] * u[2];
+      m2[1][2] = m2[2][1] = s[9] / N - u[1] * u[2];
+      double tr = m2[0][0] + m2[1][1] + m2[2][2];
+      double Tt = tr / 3.0;
+      double Tr = 2.0 * (s[13] / N) / c->dr;
+      /* raw second moments <v_i v_j> */
+      double r2[3][3] = {{s[4] / N, s[7] / N, s[8] / N},
+                         {s[7] / N, s[5] / N, s[9] / N},
+                         {s[8] / N, s[9] / N, s[6] / N}};
+      double rtr = r2[0][0] + r2[1][1] + r2[2][2];
+      double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      out[0] = rho;
+      out[1] = u[0];
+      out[2] = u[1];
+      out[3] = u[2];
+      out[4] = Tt;
+      out[5] = Tr;
+      out[6] = rho * (m2[0][0] - tr / 3.0);
+      out[7] = rho * (m2[1][1] - tr / 3.0);
+      out[8] = rho * (m2[2][2] - tr / 3.0);
+      out[9] = rho * m2[0][1];
+      out[10] = rho * m2[0][2];
+      out[11] = rho * m2[1][2];
+      for (int i = 0; i < 3; ++i) {
+        /* <c_i |c|^2> expanded in raw moments */
+        double m3 = s[10 + i] / N;
+        double ru = r2[i][0] * u[0] + r2[i][1] * u[1] + r2[i][2] * u[2];
+        double cc = m3 - 2.0 * ru - u[i] * rtr + 2.0 * u[i] * uu;
+        out[12 + i] = 0.5 * rho * cc;
+        out[15 + i] = rho * (s[14 + i] / N - u[i] * (s[13] / N));
+      }
+      out[18] = (3.0 * Tt + c->dr * Tr) / (3.0 + c->dr);
+      out[19] = N / nsteps;
+    }
+    for (int f = 0; f < 20; ++f) fields[f * (int64_t)ncell + cell] = out[f];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* DIG particle modification (Section 3.2): target count by Iround, random
+ * deletion (partial Fisher-Yates) or cloning of random existing particles at
+ * uniform positions, then the linear transform v <- a v + b, er <- c er that
+ * makes u, Tt, Tr of the cell equal to the target [rho, ux, uy, uz, Tt, Tr].
+ * Returns 0, 1 for an invalid target, 2 when the capacity would overflow; on
+ * an error nothing is written. */
+int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const double* x,
+               const double* y, const double* vx, const double* vy, const double* vz,
+               const double* er, const uint32_t* id, const double* target, uint32_t dig_iter,
+               uint64_t next_id, int64_t cap, double* ox, double* oy, double* ovx,
+               double* ovy, double* ovz, double* oer, uint32_t* oid, int64_t* ostart,
+               int64_t* n_out, uint64_t* next_id_out) {
+  double V = orc_cell_volume(c);
+  const double *trho = target, *tux = target + ncell, *tuy = target + 2 * ncell,
+               *tuz = target + 3 * ncell, *ttt = target + 4 * ncell, *ttr = target + 5 * ncell;
+  /* validation and target counts */
+  int64_t* nt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+  int64_t total = 0;
+  for (int32_t cell = 0; cell < ncell; ++cell) {
+    double r = trho[cell];
+    if (!isfinite(r) || r < 0.0 || !isfinite(tux[cell]) || !isfinite(tuy[cell]) ||
+        !isfinite(tuz[cell]) || !isfinite(ttt[cell]) || !isfinite(ttr[cell]) ||
+        (r > 0.0 && (ttt[cell] <= 0.0 || ttr[cell] < 0.0))) {
+      free(nt);
+      return 1;
+    }
+    uint32_t w[4];
+    orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_N, 0, w);
+    nt[cell] = (int64_t)iround(r * V / c->weight, orc_u01(w[0]));
+    total += nt[cell];
+  }
+  if (total > cap) {
+    free(nt);
+    return 2;
+  }
+  int64_t pos = 0;
+  uint64_t created = 0;
+  for (int32_t cell = 0; cell < ncell; ++cell) {
+    int64_t b = start[cell], N = start[cell + 1] - b, Nt = nt[cell];
+    int32_t ix = cell % c->nx, iy = cell / c->nx;
+    int64_t begin = pos;
+    ostart[cell] = begin;
+    if (Nt <= N) {
+      int64_t D = N - Nt;
+      int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+      unsigned char* del = (unsigned char*)calloc((size_t)(N > 0 ? N : 1), 1);
+      for (int64_t k = 0; k < N; ++k) idx[k] = k;
+      for (int64_t k = 0; k < D; ++k) {
+        uint32_t w[4];
+        orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_DEL, (uint32_t)(k >> 2), w);
+        int64_t j = k + orc_pick(w[k & 3], (uint32_t)(N - k));
+        int64_t t = idx[k];
+        idx[k] = idx[j];
+        idx[j] = t;
+      }
+      for (int64_t k = 0; k < D; ++k) del[idx[k]] = 1;
+      for (int64_t k = 0; k < N; ++k) {
+        if (del[k]) continue;
+        int64_t p = b + k;
+        ox[pos] = x[p]; oy[pos] = y[p];
+        ovx[pos] = vx[p]; ovy[pos] = vy[p]; ovz[pos] = vz[p];
+        oer[pos] = er[p]; oid[pos] = id[p];
+        ++pos;
+      }
+      free(idx);
+      free(del);
+    } else if (N > 0) {
+      for (int64_t k = 0; k < N; ++k) {
+        int64_t p = b + k;
+        ox[pos] = x[p]; oy[pos] = y[p];
+        ovx[pos] = vx[p]; ovy[pos] = vy[p]; ovz[pos] = vz[p];
+        oer[pos] = er[p]; oid[pos] = id[p];
+        ++pos;
+      }
+      for (int64_t k = 0; k < Nt - N; ++k) {
+        uint32_t w[4];
+        orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_SRC, (uint32_t)k, w);
+        int64_t src = b + orc_pick(w[0], (uint32_t)N);
+        ox[pos] = ix + orc_u01(w[1]);
+        oy[pos] = (c->dim == 2) ? iy + orc_u01(w[2]) : 0.0;
+        ovx[pos] = vx[src]; ovy[pos] = vy[src]; ovz[pos] = vz[src];
+        oer[pos] = er[src];
+        oid[pos] = (uint32_t)(next_id + created);
+        ++created;
+        ++pos;
+      }
+    } else {
+      /* empty cell: draw the new particles from the target equilibrium */
+      double st = sqrt(ttt[cell]);
+      for (int64_t k = 0; k < Nt; ++k) {
+        uint32_t a[4], bb[4];
+        orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_EMPTY, (uint32_t)(2 * k), a);
+        orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_EMPTY, (uint32_t)(2 * k + 1), bb);
+        double z0, z1, z2, z3;
+        box_muller(orc_u01(a[2]), orc_u01(a[3]), &z0, &z1);
+        box_muller(orc_u01(bb[0]), orc_u01(bb[1]), &z2, &z3);
+        ox[pos] = ix + orc_u01(a[0]);
+        oy[pos] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
+        ovx[pos] = tux[cell] + st * z0;
+        ovy[pos] = tuy[cell] + st * z1;
+        ovz[pos] = tuz[cell] + st * z2;
+        oer[pos] = -ttr[cell] * log(orc_u01(bb[2]));
+        oid[pos] = (uint32_t)(next_id + created);
+        ++created;
+        ++pos;
+      }
+    }
+    /* step iii: temporary moments of the current particles; step iv: transform */
+    int64_t m = pos - begin;
+    if (m > 0) {
+      double su[3] = {0, 0, 0}, se = 0.0;
+      for (int64_t p = begin; p < pos; ++p) {
+        su[0] += ovx[p];
+        su[1] += ovy[p];
+        su[2] += ovz[p];
+        se += oer[p];
+      }
+      double us[3] = {su[0] / m, su[1] / m, su[2] / m};
+      double sc = 0.0;
+      for (int64_t p = begin; p < pos; ++p) {
+        double a = ovx[p] - us[0], bq = ovy[p] - us[1], d = ovz[p] - us[2];
+        sc += a * a + bq * bq + d * d;
+      }
+      double tts = sc / (3.0 * m);
+      double trs = 2.0 * (se / m) / c->dr;
+      double a = (m >= 2 && tts > 0.0) ? sqrt(ttt[cell] / tts) : 1.0;
+      double bx = tux[cell] - a * us[0], by = tuy[cell] - a * us[1], bz = tuz[cell] - a * us[2];
+      double cr = (trs > 0.0) ? ttr[cell] / trs : 1.0;
+      for (int64_t p = begin; p < pos; ++p) {
+        ovx[p] = a * ovx[p] + bx;
+        ovy[p] = a * ovy[p] + by;
+        ovz[p] = a * ovz[p] + bz;
+        oer[p] = cr * oer[p];
+      }
+    }
+  }
+  ostart[ncell] = pos;
+  *n_out = pos;
+  *next_id_out = next_id + created;
+  free(nt);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closure assembly (Sections 2.3 and 3.1).  fields = [20][ncell] as produced
+ * by orc_sums_to_fields.  Outputs hot = [12][ncell] (sigma xx,yy,zz,xy,xz,yz,
+ * q_t xyz, q_r xyz) = DSMC - NSF, zeroed where Kn_GLL < kn_ref (mask = 1);
+ * nsf (optional) = the NSF terms themselves. */
+static double grad_axis(const orc_config* c, const double* f, int32_t ix, int32_t iy, int axis) {
+  int32_t n = (axis == 0) ? c->nx : c->ny;
+  if (axis == 1 && c->dim == 1) return 0.0;
+  if (n < 2) return 0.0;
+  double h = (axis == 0) ? c->lx / c->nx : c->ly / c->ny;
+  int32_t i = (axis == 0) ? ix : iy;
+  int periodic = c->bc_type[2 * axis] == ORC_BC_PERIODIC;
+#define AT(ii) ((axis == 0) ? f[(ii) + c->nx * iy] : f[ix + c->nx * (ii)])
+  if (i > 0 && i < n - 1) return (AT(i + 1) - AT(i - 1)) / (2.0 * h);
+  if (periodic) {
+    int32_t ip = (i + 1) % n, im = (i - 1 + n) % n;
+    return (AT(ip) - AT(im)) / (2.0 * h);
+  }
+  if (i == 0) return (AT(1) - AT(0)) / h;
+  return (AT(n - 1) - AT(n - 2)) / h;
+#undef AT
+}
+
+void orc_closure(const orc_config* c, const double* fields, const double A[4], double kn_ref,
+                 double* hot, uint8_t* mask, double* kn_gll, double* nsf) {
+  int32_t ncell = c->nx * c->ny;
+  const double *rho = fields, *ux = fields + ncell, *uy = fields + 2 * ncell,
+               *uz = fields + 3 * ncell, *tt = fields + 4 * ncell, *tr = fields + 5 * ncell;
+  double* speed = (double*)malloc(sizeof(double) * (size_t)ncell);
+  for (int32_t k = 0; k < ncell; ++k)
+    speed[k] = sqrt(ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
+  double mu0 = orc_mu0(c);
+  double det = A[0] * A[3] - A[1] * A[2];
+  double gam = (5.0 + c->dr) / (3.0 + c->dr);
+  for (int32_t k = 0; k < ncell; ++k) {
+    int32_t ix = k % c->nx, iy = k / c->nx;
+    double out_nsf[12] = {0};
+    double h[12] = {0};
+    double kn = INFINITY;
+    if (rho[k] > 0.0 && tt[k] > 0.0) {
+      double dux[2] = {grad_axis(c, ux, ix, iy, 0), grad_axis(c, ux, ix, iy, 1)};
+      double duy[2] = {grad_axis(c, uy, ix, iy, 0), grad_axis(c, uy, ix, iy, 1)};
+      double duz[2] = {grad_axis(c, uz, ix, iy, 0), grad_axis(c, uz, ix, iy, 1)};
+      double dtt[2] = {grad_axis(c, tt, ix, iy, 0), grad_axis(c, tt, ix, iy, 1)};
+      double dtr[2] = {grad_axis(c, tr, ix, iy, 0), grad_axis(c, tr, ix, iy, 1)};
+      double drho[2] = {grad_axis(c, rho, ix, iy, 0), grad_axis(c, rho, ix, iy, 1)};
+      double dsp[2] = {grad_axis(c, speed, ix, iy, 0), grad_axis(c, speed, ix, iy, 1)};
+      double mu = mu0 * pow(tt[k], c->omega);
+      double div = dux[0] + duy[1];
+      /* equation ns_constitutive (d/dz = 0) */
+      out_nsf[0] = -mu * (2.0 * dux[0] - 2.0 / 3.0 * div);
+      out_nsf[1] = -mu * (2.0 * duy[1] - 2.0 / 3.0 * div);
+      out_nsf[2] = -mu * (0.0 - 2.0 / 3.0 * div);
+      out_nsf[3] = -mu * (dux[1] + duy[0]);
+      out_nsf[4] = -mu * (duz[0]);
+      out_nsf[5] = -mu * (duz[1]);
+      /* equation kappa_A: [kt, kr] = mu/2 A^-1 [5, dr] */
+      double kt = 0.5 * mu * (A[3] * 5.0 - A[1] * c->dr) / det;
+      double kr = 0.5 * mu * (-A[2] * 5.0 + A[0] * c->dr) / det;
+      out_nsf[6] = -kt * dtt[0];
+      out_nsf[7] = -kt * dtt[1];
+      out_nsf[8] = 0.0;
+      out_nsf[9] = -kr * dtr[0];
+      out_nsf[10] = -kr * dtr[1];
+      out_nsf[11] = 0.0;
+      /* equation hot_constitutive: HoT = DSMC - NSF */
+      for (int f = 0; f < 12; ++f) h[f] = fields[(6 + f) * (int64_t)ncell + k] - out_nsf[f];
+      /* gradient-length local Knudsen number, Section 3.1 */
+      double lam = mu / (rho[k] * tt[k]) * sqrt(M_PI * tt[k] / 2.0);
+      double g = sqrt(drho[0] * drho[0] + drho[1] * drho[1]) / rho[k];
+      double us = speed[k];
+      double cs = sqrt(gam * tt[k]);
+      double gu = sqrt(dsp[0] * dsp[0] + dsp[1] * dsp[1]) / (us > cs ? us : cs);
+      double gt = sqrt(dtt[0] * dtt[0] + dtt[1] * dtt[1]) / tt[k];
+      double gr = (tr[k] > 0.0) ? sqrt(dtr[0] * dtr[0] + dtr[1] * dtr[1]) / tr[k] : 0.0;
+      double m = g;
+      if (gu > m) m = gu;
+      if (gt > m) m = gt;
+      if (gr > m) m = gr;
+      kn = lam * m;
+    }
+    uint8_t eq = (kn < kn_ref) ? 1 : 0;
+    for (int f = 0; f < 12; ++f) {
+      hot[f * (int64_t)ncell + k] = (eq || !(rho[k] > 0.0 && tt[k] > 0.0)) ? 0.0 : h[f];
+      if (nsf) nsf[f * (int64_t)ncell + k] = out_nsf[f];
+    }
+    mask[k] = eq;
+    kn_gll[k] = kn;
+  }
+  free(speed);
+}

@@ -1,0 +1,100 @@
+/*
+ * FP64 CPU oracle for the DSMC + DIG hot path of "Multiscale simulation of
+ * rarefied polyatomic gas flow via DIG method" (Luo, Huang, Li, Wu,
+ * arXiv:2501.10965).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plainly written
+ * reference that the HIP path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it.  It shares no code, header, table or constant
+ * generator with the HIP library.
+ *
+ * Units are the paper's (Section 2): length L0, density rho0, temperature T0,
+ * speed sqrt(R T0); molecular mass = 1, so rho is the number density times
+ * the particle weight.  Positions are held in grid units (x/dx, y/dy) so that
+ * the cell index is floor() of the position.
+ */
+#ifndef DSMC_ORACLE_H
+#define DSMC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIFFUSE = 1, ORC_BC_SPECULAR = 2 };
+
+/* Philox stream tags (third counter word, high byte). */
+enum {
+  ORC_TAG_INIT = 1, ORC_TAG_INIT_N = 2, ORC_TAG_WALL = 3, ORC_TAG_NCAND = 4,
+  ORC_TAG_COLL = 5, ORC_TAG_DIG_N = 6, ORC_TAG_DIG_DEL = 7, ORC_TAG_DIG_SRC = 8,
+  ORC_TAG_DIG_EMPTY = 9
+};
+
+typedef struct {
+  int32_t  dim;          /* 1 or 2 */
+  int32_t  nx, ny;       /* cells per axis (ny = 1 for dim 1) */
+  double   lx, ly;       /* domain lengths (ly ignored for dim 1) */
+  double   kn, omega, alpha;
+  int32_t  dr;           /* rotational degrees of freedom (2) */
+  double   zrot;         /* rotational collision number Z */
+  double   dt, weight;   /* time step; particle weight N_eff (mass per particle) */
+  int32_t  bc_type[4];   /* faces x-, x+, y-, y+ */
+  double   bc_T[4];
+  double   bc_U[4][3];
+  uint64_t seed;
+  uint32_t instance;
+} orc_config;
+
+typedef struct {
+  int64_t candidates, accepted, inelastic, saturated;
+} orc_collide_stats;
+
+/* Philox4x32-10 block (Salmon et al., SC'11). */
+void     orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void     orc_draw(const orc_config* c, uint32_t entity, uint32_t step, uint32_t tag,
+                  uint32_t draw, uint32_t out[4]);
+double   orc_u01(uint32_t r);
+uint32_t orc_pick(uint32_t r, uint32_t n);
+
+double orc_mu0(const orc_config* c);
+double orc_csigma(const orc_config* c);
+double orc_pinelastic(const orc_config* c);
+double orc_cell_volume(const orc_config* c);
+
+int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t cap,
+                 double* x, double* y, double* vx, double* vy, double* vz, double* er,
+                 uint32_t* id);
+
+int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* vx,
+                 double* vy, double* vz, double* er, const uint32_t* id, uint32_t step);
+
+void orc_cell_index(const orc_config* c, int64_t n, const double* x, const double* y,
+                    int32_t* cell);
+
+void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int64_t* start);
+
+void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
+                 double* vy, double* vz, double* er, float* sgmax, uint32_t step,
+                 orc_collide_stats* st, double* obs_out);
+
+void orc_sample_sums(int32_t ncell, const int64_t* start, const double* vx,
+                     const double* vy, const double* vz, const double* er, double* sums);
+
+void orc_sums_to_fields(const orc_config* c, int32_t ncell, const double* sums,
+                        double nsteps, double* fields);
+
+int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const double* x,
+               const double* y, const double* vx, const double* vy, const double* vz,
+               const double* er, const uint32_t* id, const double* target, uint32_t dig_iter,
+               uint64_t next_id, int64_t cap, double* ox, double* oy, double* ovx,
+               double* ovy, double* ovz, double* oer, uint32_t* oid, int64_t* ostart,
+               int64_t* n_out, uint64_t* next_id_out);
+
+void orc_closure(const orc_config* c, const double* fields, const double A[4], double kn_ref,
+                 double* hot, uint8_t* mask, double* kn_gll, double* nsf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,257 @@
+"""Oracle pins against closed forms and invariants of the DSMC model.
+
+Each test checks the oracle against something other than itself: a value the
+paper prints, a kinetic-theory closed form, a conservation law, or a library
+routine.  Tolerances are statistical (k sigma) where the quantity is random.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dig_workloads as wl
+import oracle
+
+
+def zero_d_box(n, kn=0.1, omega=0.74, zrot=5.0, Tt=1.0, Tr=None, seed=7, dt_frac=0.2):
+    """A single periodic cell: collisions only (0D relaxation box)."""
+    w = wl.box(1, 1, kn=kn, omega=omega, zrot=zrot, ppc=n, seed=seed, Tt=Tt,
+               Tr=Tt if Tr is None else Tr, dt_frac=dt_frac, tref=max(Tt, Tr or Tt))
+    s = oracle.new_state(w, cap=n)
+    return w, s
+
+
+def temps(s):
+    n = s.n
+    v = np.stack([s.vx[:n], s.vy[:n], s.vz[:n]])
+    u = v.mean(axis=1, keepdims=True)
+    Tt = ((v - u) ** 2).sum(axis=0).mean() / 3.0
+    Tr = s.er[:n].mean()  # d_r = 2: Tr = 2<er>/d_r
+    return Tt, Tr
+
+
+# ---------------------------------------------------------------------------
+def test_p_inelastic_matches_paper_value():
+    """Section 4 states Z = 2.59 corresponds to P_inelastic = 0.25 (omega 0.74, alpha 1)."""
+    w = wl.box(1, 1, zrot=2.59)
+    assert abs(oracle.pinelastic(w) - 0.25) < 5e-4
+    w5 = wl.box(1, 1, zrot=5.0)
+    assert oracle.pinelastic(w5) == pytest.approx(19.4304 / 150.0, rel=1e-12)
+
+
+def test_knudsen_definition_reynolds_of_cavity_table():
+    """Table 1: Kn = 0.1 / 0.01 with U_w = sqrt(2) give Re = 17.73 / 177.3, i.e.
+    Re = U_w / (mu0 at rho = T = 1) with mu0 = Kn sqrt(2/pi)."""
+    for kn, re in ((0.1, 17.73), (0.01, 177.3)):
+        w = wl.box(1, 1, kn=kn)
+        assert math.sqrt(2.0) / oracle.mu0(w) == pytest.approx(re, rel=2e-3)
+
+
+@pytest.mark.parametrize("omega", [0.74, 0.5])
+def test_ntc_vhs_equilibrium_collision_rate(omega):
+    """Accepted collisions per unit time in an equilibrium box equal
+    (N/2) nu (N-1)/N with nu = 30 p / ((5-2w)(7-2w) mu) (VHS; for w = 1/2 the
+    hard-sphere sqrt(2) n pi d^2 cbar).  No majorant saturation allowed."""
+    n = 4000
+    w, s = zero_d_box(n, omega=omega, seed=11 if omega > 0.6 else 12)
+    mu0 = oracle.mu0(w)
+    acc = 0
+    expect = 0.0
+    sat = 0
+    for step in range(1000):
+        s.step_no = step
+        Tt, _ = temps(s)
+        p = 1.0 * Tt
+        nu = 30.0 * p / ((5 - 2 * omega) * (7 - 2 * omega) * mu0 * Tt ** omega)
+        expect += 0.5 * n * nu * w["dt"] * (n - 1) / n
+        st = s.collide()
+        acc += st["accepted"]
+        sat += st["saturated"]
+    assert sat == 0
+    z = (acc - expect) / math.sqrt(expect)
+    assert abs(z) < 4.0, (acc, expect, z)
+    if omega == 0.74:
+        # the workload time unit: one mean collision time per TAU_C_PER_KN * Kn
+        tau_c = 1.0 / (30.0 / ((5 - 2 * omega) * (7 - 2 * omega) * mu0))
+        assert tau_c == pytest.approx(wl.TAU_C_PER_KN * w["kn"], rel=1e-12)
+
+
+def test_collisions_conserve_momentum_and_energy_exactly():
+    n = 300
+    w, s = zero_d_box(n, Tt=1.3, Tr=0.7, seed=3)
+    s.sgmax[:] *= 4.0  # many candidates
+    for step in range(5):
+        s.step_no = step
+        v = np.stack([s.vx[:n], s.vy[:n], s.vz[:n]])
+        p0 = v.sum(axis=1)
+        e0 = 0.5 * (v ** 2).sum() + s.er[:n].sum()
+        st = s.collide()
+        assert st["accepted"] > 10
+        v = np.stack([s.vx[:n], s.vy[:n], s.vz[:n]])
+        assert np.allclose(v.sum(axis=1), p0, rtol=0, atol=1e-12 * np.abs(v).sum())
+        e1 = 0.5 * (v ** 2).sum() + s.er[:n].sum()
+        assert abs(e1 - e0) <= 1e-12 * e0
+        assert (s.er[:n] >= 0).all()
+
+
+def test_jeans_landau_rotational_relaxation_rate():
+    """0D box from Tt = 1.05, Tr = 0.925 (T = 1): Tr - T decays at the Jeans
+    rate p / (mu Z) (equation Jeans_Landau) within 5 %."""
+    n = 200_000
+    zrot = 5.0
+    w, s = zero_d_box(n, zrot=zrot, Tt=1.05, Tr=0.925, seed=21)
+    mu0 = oracle.mu0(w)
+    ts, ys = [], []
+    for step in range(60):
+        Tt, Tr = temps(s)
+        T = (3 * Tt + 2 * Tr) / 5.0
+        ts.append(step * w["dt"])
+        ys.append(Tr - T)
+        s.step_no = step
+        s.collide()
+    ts, ys = np.array(ts), np.array(ys)
+    keep = np.abs(ys) > 0.012
+    slope = np.polyfit(ts[keep], np.log(np.abs(ys[keep])), 1)[0]
+    T = 1.0
+    rate_jeans = (1.0 * T) / (mu0 * T ** 0.74 * zrot)
+    ratio = -slope / rate_jeans
+    assert abs(ratio - 1.0) < 0.05, ratio
+
+
+def test_borgnakke_larsen_keeps_equilibrium():
+    """Equal Tt and Tr stay equal, and er stays exponential (d_r = 2)."""
+    n = 20000
+    w, s = zero_d_box(n, Tt=1.0, Tr=1.0, seed=5)
+    Tt0, Tr0 = temps(s)
+    E0 = (3 * Tt0 + 2 * Tr0) / 5
+    for step in range(150):
+        s.step_no = step
+        s.collide()
+    Tt, Tr = temps(s)
+    # Tr fluctuates like a mean of n exponentials around the conserved T
+    assert abs(Tr - E0) < 5.0 * E0 / math.sqrt(n) * 1.5
+    er = np.sort(s.er[:n] / Tr)
+    cdf = 1.0 - np.exp(-er)
+    d = np.max(np.maximum(np.arange(1, n + 1) / n - cdf, cdf - np.arange(n) / n))
+    assert d * math.sqrt(n) < 1.95
+
+
+def test_diffuse_wall_reemission_moments():
+    """Flux-weighted half-range Maxwellian at the wall: <v_n> = sqrt(pi T/2),
+    <v_n^2> = 2T, tangential mean U and variance T, <er> = T (d_r = 2)."""
+    Tw, U = 1.3, (0.0, 0.4, -0.2)
+    bc = [("diffuse", Tw, U), ("diffuse", 1.0, (0, 0, 0)), ("periodic", 1.0, (0, 0, 0)),
+          ("periodic", 1.0, (0, 0, 0))]
+    n = 200_000
+    w = wl.box(1, 10, bc=bc, ppc=1, seed=9, dt=1e-3)
+    s = oracle.State(w, n)
+    s.load(np.full(n, 0.005), np.zeros(n), np.full(n, -1.0), np.zeros(n), np.zeros(n),
+           np.zeros(n), np.arange(n, dtype=np.uint32), step=4)
+    hits = s.move()
+    assert hits == n
+    vx, vy, vz, er = s.vx[:n], s.vy[:n], s.vz[:n], s.er[:n]
+    k = 4.5 / math.sqrt(n)
+    assert abs(vx.mean() / math.sqrt(math.pi * Tw / 2) - 1) < k * 0.53
+    assert abs((vx ** 2).mean() / (2 * Tw) - 1) < k * 1.0
+    assert abs(vy.mean() - U[1]) < k * math.sqrt(Tw)
+    assert abs(vz.mean() - U[2]) < k * math.sqrt(Tw)
+    assert abs(vy.var() / Tw - 1) < k * 1.5
+    assert abs(er.mean() / Tw - 1) < k * 1.0
+    assert (vx > 0).all()
+    # post-hit flight continues for the remaining time from the wall
+    t_hit = 0.005 * (1.0 / 10) / 1.0
+    np.testing.assert_allclose(s.x[:n], vx * (w["dt"] - t_hit) * 10, rtol=1e-9, atol=1e-12)
+
+
+def test_closed_box_equilibrium_with_walls():
+    """Gas and all walls at T_w: temperatures and flow stay put; no net heat flux."""
+    bc = [("diffuse", 1.0, (0, 0, 0))] * 4
+    w = wl.box(2, 8, 8, kn=0.05, ppc=60, bc=bc, seed=17)
+    s = oracle.new_state(w)
+    for _ in range(150):
+        s.step()
+    f = s.fields()
+    N = f[19].sum() * s.nsamp
+    assert abs(np.average(f[4], weights=f[19]) - 1.0) < 5 / math.sqrt(N) * 3
+    assert abs(np.average(f[5], weights=f[19]) - 1.0) < 5 / math.sqrt(N) * 3
+    assert np.abs(np.average(f[1], weights=f[19])) < 5 / math.sqrt(N) * 3
+
+
+def test_free_flight_periodic_exact():
+    rng = np.random.default_rng(1)
+    w = wl.box(2, 7, 5, lx=2.0, ly=1.5, seed=2, dt=0.37)
+    n = 1000
+    s = oracle.State(w, n)
+    x, y = rng.random(n) * 7, rng.random(n) * 5
+    vx, vy, vz = rng.standard_normal((3, n)) * 3
+    s.load(x, y, vx, vy, vz, np.ones(n), np.arange(n, dtype=np.uint32))
+    assert s.move() == 0
+    ex = np.mod(x + vx * w["dt"] / (2.0 / 7), 7)
+    ey = np.mod(y + vy * w["dt"] / (1.5 / 5), 5)
+    np.testing.assert_allclose(s.x[:n], ex, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(s.y[:n], ey, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(s.vx[:n], vx)
+
+
+def test_specular_walls_mirror():
+    bc = [("specular", 1, (0, 0, 0))] * 2 + [("specular", 1, (0, 0, 0))] * 2
+    w = wl.box(2, 4, 4, bc=bc, seed=2, dt=1.0)
+    s = oracle.State(w, 2)
+    # one particle bouncing off x = 0 then flying on; one off the y = 4 face
+    s.load([0.5, 2.0], [2.0, 3.5], [-1.0, 0.0], [0.0, 2.0], [0.0, 0.0], [1, 1],
+           np.array([0, 1], np.uint32))
+    s.move()
+    # grid units: dx = 0.25, so speed 1 = 4 cells per unit time
+    assert s.x[0] == pytest.approx(3.5)
+    assert s.vx[0] == 1.0
+    # 8 cells per unit time: up 0.5 to y = 4, down 4 to y = 0, up 3.5
+    assert s.y[1] == pytest.approx(3.5)
+    assert s.vy[1] == 2.0
+
+
+def test_stable_counting_sort_matches_library_sort():
+    rng = np.random.default_rng(4)
+    n, nc = 50_000, 997
+    cell = rng.integers(0, nc, n).astype(np.int32)
+    perm = np.zeros(n, np.int64)
+    start = np.zeros(nc + 1, np.int64)
+    L = oracle.lib()
+    L.orc_sort(n, oracle._p(cell, oracle._i32), nc, oracle._p(perm, oracle._i64),
+               oracle._p(start, oracle._i64))
+    np.testing.assert_array_equal(perm, np.argsort(cell, kind="stable"))
+    np.testing.assert_array_equal(start, np.searchsorted(np.sort(cell), np.arange(nc + 1)))
+
+
+def test_init_equilibrium_statistics():
+    w = wl.box(2, 20, 10, ppc=100, seed=8, u=(0.3, -0.2, 0.1), Tt=1.4, Tr=0.8)
+    s = oracle.new_state(w)
+    n = s.n
+    assert n == 20 * 10 * 100
+    cells = s.cells()
+    np.testing.assert_array_equal(np.bincount(cells, minlength=200), 100)
+    assert (np.diff(cells) >= 0).all()
+    k = 4.5 / math.sqrt(n)
+    for v, m in ((s.vx[:n], 0.3), (s.vy[:n], -0.2), (s.vz[:n], 0.1)):
+        assert abs(v.mean() - m) < k * math.sqrt(1.4)
+        assert abs(v.var() / 1.4 - 1) < k * math.sqrt(2)
+    assert abs(s.er[:n].mean() / 0.8 - 1) < k
+    z = np.sort((s.vx[:n] - 0.3) / math.sqrt(1.4))
+    from scipy.stats import norm
+    cdf = norm.cdf(z)
+    d = np.max(np.maximum(np.arange(1, n + 1) / n - cdf, cdf - np.arange(n) / n))
+    assert d * math.sqrt(n) < 1.95
+    np.testing.assert_array_equal(s.id[:n], np.arange(n))
+
+
+def test_iround_counts_expectation_and_variance():
+    """Initial counts from Iround(rho V / N_eff) have mean x and variance f(1-f)."""
+    w = wl.box(2, 50, 40, ppc=10, seed=31)
+    w["weight"] = w["weight"] * 10 / 7.3  # x = 7.3 per cell
+    nc = 2000
+    s = oracle.State(w, nc * 9)
+    f = wl.fields_uniform(w)
+    s.init(f, 0, 1.0)
+    counts = np.bincount(s.cells(), minlength=nc)
+    assert set(np.unique(counts)) <= {7, 8}
+    frac = (counts == 8).mean()
+    assert abs(frac - 0.3) < 4.5 * math.sqrt(0.3 * 0.7 / nc)
