@@ -1,0 +1,195 @@
+/*
+ * dig.h -- C ABI of the MI355X (gfx950) DSMC + DIG hot-path library (libdig).
+ *
+ * Method: "Multiscale simulation of rarefied polyatomic gas flow via DIG
+ * method" (Luo, Huang, Li, Wu; arXiv:2501.10965).  The library advances
+ * simulation particles of a polyatomic gas (velocity v, rotational energy)
+ * with the DSMC scheme of Section 2.2 and applies the DIG particle
+ * modification of Section 3.2; the algorithm loop is the four-step DIG
+ * iteration of Section 3 (initialise from a macroscopic field, N_s DSMC
+ * steps with time averaging, synthetic solve, particle modification).
+ *
+ * Units (Section 2): lengths in L0, density in rho0, temperature in T0,
+ * speed in sqrt(R T0); molecular mass 1.  Kn = mu(T0)/(p0 L0) sqrt(pi R T0/2),
+ * so mu(T) = Kn sqrt(2/pi) T^omega.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HBM) owned by the caller;
+ *    pointers named *_host are host pointers.  The library never frees caller
+ *    memory and allocates no device memory after dsmc_create returns, except
+ *    synth_solve's host-side scratch.
+ *  - Every call that takes a dig_stream_t enqueues its work on that HIP stream
+ *    (NULL = the default stream) and returns without waiting, unless its
+ *    comment says it synchronises.
+ *  - Return value: DIG_OK or an error code; dig_last_error() returns a
+ *    thread-local message for the last failure.  No entry point aborts or
+ *    throws.  Invalid arguments are rejected before any device work.
+ *  - Array layouts: "field-major [F][C]" means element (f, c) at f*C + c,
+ *    C = total cell count of the context (cells of all instances,
+ *    instance after instance, x fastest then y).
+ */
+#ifndef DIG_H
+#define DIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dig_ctx dig_ctx;
+typedef void* dig_stream_t; /* a hipStream_t */
+
+typedef enum {
+  DIG_OK = 0,
+  DIG_ERR_INVALID = 1,  /* bad argument or configuration */
+  DIG_ERR_CAPACITY = 2, /* particle capacity would overflow */
+  DIG_ERR_HIP = 3,      /* a HIP runtime call failed */
+  DIG_ERR_STATE = 4,    /* call not valid in the context's current state */
+  DIG_ERR_NUMERIC = 5   /* non-finite or non-positive target values */
+} dig_status;
+
+/* Boundary condition of one domain face. */
+enum { DIG_BC_PERIODIC = 0, DIG_BC_DIFFUSE = 1, DIG_BC_SPECULAR = 2 };
+typedef struct {
+  int32_t type; /* DIG_BC_* ; both faces of an axis periodic or neither */
+  double T;     /* wall temperature (diffuse) */
+  double U[3];  /* wall velocity (diffuse); its normal component must be 0 */
+} dig_bc;
+
+/* One simulation instance (Section 4 gas: VSS/VHS omega 0.74, alpha 1,
+ * d_r = 2, constant Z).  Faces are ordered x-, x+, y-, y+. */
+typedef struct {
+  int32_t dim;          /* 1 (slab, positions x) or 2 (positions x, y) */
+  int32_t nx, ny;       /* uniform cells per axis; ny = 1 when dim = 1 */
+  double lx, ly;        /* domain lengths; cell volume (lx/nx)(ly/ny), 2D, or lx/nx, 1D */
+  double kn;            /* Knudsen number (Section 2) */
+  double omega, alpha;  /* viscosity index in [0.5, 1]; alpha must be 1 */
+  int32_t dr;           /* rotational degrees of freedom; must be 2 */
+  double zrot;          /* rotational collision number Z; P_inelastic <= 1 */
+  double dt, weight;    /* time step; particle weight N_eff (mass per particle) */
+  dig_bc bc[4];
+  uint64_t seed;        /* Philox key */
+  uint32_t instance_id; /* Philox counter word 2, low 24 bits */
+  double sgmax_init;    /* initial majorant of sigma_T g; <= 0: default below */
+  double tref;          /* default majorant = C (6 sqrt(2 tref))^(2 - 2 omega) */
+} dig_config;
+
+/* Byte offsets of the device arrays inside the caller's workspace.  Particle
+ * arrays hold `capacity` elements, cell arrays `ncell`.  Buffer `cur`
+ * (returned by dsmc_query) holds the current, cell-sorted particle state. */
+typedef struct {
+  size_t total_bytes;
+  int64_t capacity, ncell;
+  size_t x[2], y[2], vx[2], vy[2], vz[2], er[2], id[2]; /* f32 x4 (grid units), f32, u32 */
+  size_t cell, rank, perm_raw, perm;                    /* i32 per particle */
+  size_t start;      /* i32 [ncell + 1]: first particle of each cell */
+  size_t count;      /* i32 [ncell] */
+  size_t sgmax;      /* f32 [ncell]: majorant of sigma_T g */
+  size_t acc;        /* f64 [ncell][17]: time-accumulated raw sums */
+  size_t sums;       /* f64 [ncell][17]: scratch for instantaneous sums */
+  size_t cell_inst;  /* i32 [ncell]: instance of each cell */
+  size_t counters;   /* dig_counters */
+} dig_layout;
+
+/* Device-side counters (read with dsmc_query). */
+typedef struct {
+  int64_t n;          /* particles in the current buffer */
+  int64_t step;       /* DSMC steps taken (Philox step counter) */
+  int64_t nsamp;      /* steps accumulated into acc since the last reset */
+  int64_t next_id;    /* next particle id handed out by dig_adjust */
+  int64_t candidates, accepted, inelastic, saturated, wall_hits;
+  uint32_t err;       /* DIG_EBIT_* */
+  uint32_t cur;       /* current particle buffer (0 or 1) */
+} dig_counters;
+
+enum {
+  DIG_EBIT_SORT_OVERFLOW = 1u, /* a cell group exceeded the run table (slow path used) */
+  DIG_EBIT_GROUPS = 2u,        /* more cell groups than launched: state invalid */
+  DIG_EBIT_TARGET = 4u,        /* dig_adjust target non-finite or non-positive */
+  DIG_EBIT_CAPACITY = 8u       /* dig_adjust would exceed the capacity */
+};
+
+/* Workspace planning.  cfgs[n_inst] describe the instances advanced
+ * together (batching; all must share dim).  capacity = particle capacity of
+ * the whole batch.  Fills *out; no device work.  Errors: DIG_ERR_INVALID. */
+dig_status dig_plan(const dig_config* cfgs_host, int32_t n_inst, int64_t capacity,
+                    dig_layout* out_host);
+
+/* Creates a context over a caller-owned device workspace of at least
+ * layout.total_bytes bytes (256-byte aligned).  Zeroes counters, counts and
+ * accumulators and sets every cell's majorant; enqueued on `stream`.
+ * group_particles / group_cells: cell-group size used by the sort and collide
+ * kernels (0 = defaults 1024 / 256).  Errors: DIG_ERR_INVALID, DIG_ERR_HIP. */
+dig_status dsmc_create(const dig_config* cfgs_host, int32_t n_inst, int64_t capacity,
+                       void* workspace_dev, size_t workspace_bytes, int32_t group_particles,
+                       int32_t group_cells, dig_stream_t stream, dig_ctx** out);
+
+/* Initialisation, DIG step 1 (Section 3): particles from the local
+ * equilibrium of fields_dev = field-major [6][C] (rho, ux, uy, uz, Tt, Tr).
+ * ppc > 0: exactly ppc particles per cell; ppc = 0: Iround(rho V / N_eff).
+ * Velocities Maxwellian (Box-Muller), rotational energy exponential with mean
+ * Tr (d_r = 2), positions uniform in the cell.  Synchronises once to read the
+ * particle count.  Errors: DIG_ERR_INVALID, DIG_ERR_CAPACITY (state untouched). */
+dig_status dsmc_init(dig_ctx* ctx, const double* fields_dev, int32_t ppc, dig_stream_t stream);
+
+/* State injection: the caller has written a cell-sorted state of n particles
+ * into buffer `cur` and the matching start array (i32 [C+1]).  Sets the
+ * particle count, the step counter and the next id; enqueued. */
+dig_status dsmc_inject(dig_ctx* ctx, int64_t n, int64_t step, int64_t next_id,
+                       dig_stream_t stream);
+
+/* One DSMC step = move (free flight, walls) + cell index + stable counting
+ * sort + collide (NTC, VHS, Borgnakke-Larsen) + accumulate raw sums, Section
+ * 2.2.  dsmc_step runs nsteps of them; dsmc_stage runs the selected stages of
+ * one step (DIG_STAGE_* mask, in order), for inspection.  Capture-safe. */
+enum { DIG_STAGE_MOVE = 1, DIG_STAGE_SORT = 2, DIG_STAGE_COLLIDE = 4, DIG_STAGE_ALL = 7 };
+dig_status dsmc_step(dig_ctx* ctx, int32_t nsteps, dig_stream_t stream);
+dig_status dsmc_stage(dig_ctx* ctx, int32_t stage_mask, dig_stream_t stream);
+
+/* Moment sampling, equation DSMC_macroscopic.  out_dev = field-major [20][C]:
+ * rho, ux, uy, uz, Tt, Tr, sigma xx yy zz xy xz yz, q_t xyz, q_r xyz, T,
+ * mean particle count.  Rotational energy is stored per unit mass, so
+ * Tr = 2<er>/d_r and q_r = rho <c er>.  Modes: INSTANT (current state),
+ * AVERAGE (raw sums pooled over the steps since the last RESET), RESET (zero
+ * the accumulator; out_dev may be NULL).  Empty cells give all-zero fields. */
+enum { DIG_SAMPLE_INSTANT = 0, DIG_SAMPLE_AVERAGE = 1, DIG_SAMPLE_RESET = 2 };
+dig_status dsmc_sample(dig_ctx* ctx, int32_t mode, double* out_dev, dig_stream_t stream);
+
+/* DIG particle modification, Section 3.2, single-instance contexts only.
+ * target_dev = field-major [6][C] (rho, ux, uy, uz, Tt, Tr).  Per cell: target
+ * count Iround(rho V / N_eff); random deletion (partial Fisher-Yates) or
+ * clones of random existing particles at uniform positions (empty cells draw
+ * from the target equilibrium); then v <- a v + b, er <- c er so that u, Tt,
+ * Tr equal the target.  FP64 arithmetic, FP32 storage.  Synchronises once.
+ * Errors: DIG_ERR_NUMERIC (bad target), DIG_ERR_CAPACITY; on error the
+ * particle state is unchanged. */
+dig_status dig_adjust(dig_ctx* ctx, const double* target_dev, uint32_t dig_iter,
+                      dig_stream_t stream);
+
+/* Closure assembly, Sections 2.3 and 3.1, single-instance contexts only.
+ * fields_dev = [20][C] from dsmc_sample.  A_host = relaxation matrix
+ * (Att, Atr, Art, Arr) of equation kappa_A.  Outputs: hot_dev [12][C]
+ * (sigma xx yy zz xy xz yz, q_t xyz, q_r xyz) = DSMC - NSF, zeroed where
+ * Kn_GLL < kn_ref; mask_dev [C] (1 = equilibrium, HoT zeroed); kngll_dev [C];
+ * nsf_dev [12][C] or NULL.  Gradients: central, one-sided at walls. */
+dig_status closure_assemble(dig_ctx* ctx, const double* fields_dev, const double* A_host,
+                            double kn_ref, double* hot_dev, uint8_t* mask_dev,
+                            double* kngll_dev, double* nsf_dev, dig_stream_t stream);
+
+/* Synchronises and copies the device counters into *out. */
+dig_status dsmc_query(dig_ctx* ctx, dig_counters* out_host, dig_stream_t stream);
+
+/* Gas constants of instance `inst` as the library computes them:
+ * out[0] = C (sigma_T g = C g^(2-2 omega)), out[1] = P_inelastic,
+ * out[2] = mu0, out[3] = cell volume, out[4] = default majorant. */
+dig_status dig_constants(dig_ctx* ctx, int32_t inst, double* out_host5);
+
+const char* dig_last_error(void);
+void dsmc_destroy(dig_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

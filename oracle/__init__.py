@@ -87,7 +87,7 @@ def lib():
         L.orc_cell_index.argtypes = [cp, C.c_int64, _d, _d, _i32]
         L.orc_sort.argtypes = [C.c_int64, _i32, C.c_int32, _i64, _i64]
         L.orc_collide.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _f, C.c_uint32,
-                                  C.POINTER(Stats), _d]
+                                  C.POINTER(Stats), _d, _d]
         L.orc_sample_sums.argtypes = [C.c_int32, _i64, _d, _d, _d, _d, _d]
         L.orc_sums_to_fields.argtypes = [cp, C.c_int32, _d, C.c_double, _d]
         L.orc_adjust.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _d, _d, _u32, _d,
@@ -237,13 +237,16 @@ class State:
     def collide(self, with_obs=False):
         st = Stats()
         obs = np.zeros(self.ncell, dtype=np.float64)
+        margin = np.zeros(self.ncell, dtype=np.float64)
         lib().orc_collide(C.byref(self.cfg), self.ncell, _p(self.start, _i64),
                           _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d), _p(self.er, _d),
-                          _p(self.sgmax, _f), self.step_no, C.byref(st), _p(obs, _d))
+                          _p(self.sgmax, _f), self.step_no, C.byref(st), _p(obs, _d),
+                          _p(margin, _d))
         res = dict(candidates=st.candidates, accepted=st.accepted, inelastic=st.inelastic,
                    saturated=st.saturated)
         if with_obs:
             res["obs"] = obs
+            res["margin"] = margin
         return res
 
     def sums(self):

@@ -272,7 +272,7 @@ void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int6
  * scattering (VSS with alpha = 1).  The state arrays are in cell order. */
 void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
                  double* vy, double* vz, double* er, float* sgmax, uint32_t step,
-                 orc_collide_stats* st, double* obs_out) {
+                 orc_collide_stats* st, double* obs_out, double* margin_out) {
   double csig = orc_csigma(c);
   double pin = orc_pinelastic(c);
   double V = orc_cell_volume(c);
@@ -283,6 +283,7 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
     int64_t N = start[cell + 1] - b;
     double sgm = (double)sgmax[cell];
     double obs = 0.0;
+    double margin = INFINITY; /* smallest |u - threshold| of the cell's decisions */
     int64_t ncand = 0;
     if (N >= 2) {
       uint32_t w[4];
@@ -305,11 +306,14 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
       double ratio = sg / sgm;
       if (st) st->candidates += 1;
       if (ratio > 1.0 && st) st->saturated += 1;
+      if (fabs(orc_u01(r0[2]) - ratio) < margin) margin = fabs(orc_u01(r0[2]) - ratio);
       if (!(orc_u01(r0[2]) < ratio)) continue;
       if (st) st->accepted += 1;
       orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 1), r1);
       orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 2), r2);
       double et = 0.25 * g2; /* relative translational energy, reduced mass 1/2 */
+      if (fabs(orc_u01(r0[3]) - pin) < margin) margin = fabs(orc_u01(r0[3]) - pin);
+      if (fabs(orc_u01(r1[1]) - pin) < margin) margin = fabs(orc_u01(r1[1]) - pin);
       /* first picked particle, then the second: Bird's double relaxation */
       if (orc_u01(r0[3]) < pin) {
         double ec = et + er[i];
@@ -339,6 +343,7 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
       vz[j] = cz - 0.5 * gp * nz;
     }
     if (obs_out) obs_out[cell] = obs;
+    if (margin_out) margin_out[cell] = margin;
     if (obs > sgm) {
       float f = (float)obs;
       if ((double)f < obs) f = nextafterf(f, INFINITY);

@@ -76,7 +76,7 @@ void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int6
 
 void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
                  double* vy, double* vz, double* er, float* sgmax, uint32_t step,
-                 orc_collide_stats* st, double* obs_out);
+                 orc_collide_stats* st, double* obs_out, double* margin_out);
 
 void orc_sample_sums(int32_t ncell, const int64_t* start, const double* vx,
                      const double* vy, const double* vz, const double* er, double* sums);

@@ -1,0 +1,130 @@
+"""ctypes declarations of the libdig C ABI (include/dig.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdig.so")
+
+DIG_OK, DIG_ERR_INVALID, DIG_ERR_CAPACITY, DIG_ERR_HIP, DIG_ERR_STATE, DIG_ERR_NUMERIC = range(6)
+BC = {"periodic": 0, "diffuse": 1, "specular": 2}
+STAGE_MOVE, STAGE_SORT, STAGE_COLLIDE, STAGE_ALL = 1, 2, 4, 7
+SAMPLE_INSTANT, SAMPLE_AVERAGE, SAMPLE_RESET = 0, 1, 2
+EBIT_SORT_OVERFLOW, EBIT_GROUPS, EBIT_TARGET, EBIT_CAPACITY = 1, 2, 4, 8
+
+
+class DigBC(C.Structure):
+    _fields_ = [("type", C.c_int32), ("T", C.c_double), ("U", C.c_double * 3)]
+
+
+class DigConfig(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("kn", C.c_double),
+                ("omega", C.c_double), ("alpha", C.c_double), ("dr", C.c_int32),
+                ("zrot", C.c_double), ("dt", C.c_double), ("weight", C.c_double),
+                ("bc", DigBC * 4), ("seed", C.c_uint64), ("instance_id", C.c_uint32),
+                ("sgmax_init", C.c_double), ("tref", C.c_double)]
+
+
+class DigLayout(C.Structure):
+    _fields_ = [("total_bytes", C.c_size_t), ("capacity", C.c_int64), ("ncell", C.c_int64),
+                ("x", C.c_size_t * 2), ("y", C.c_size_t * 2), ("vx", C.c_size_t * 2),
+                ("vy", C.c_size_t * 2), ("vz", C.c_size_t * 2), ("er", C.c_size_t * 2),
+                ("id", C.c_size_t * 2), ("cell", C.c_size_t), ("rank", C.c_size_t),
+                ("perm_raw", C.c_size_t), ("perm", C.c_size_t), ("start", C.c_size_t),
+                ("count", C.c_size_t), ("sgmax", C.c_size_t), ("acc", C.c_size_t),
+                ("sums", C.c_size_t), ("cell_inst", C.c_size_t), ("counters", C.c_size_t)]
+
+
+class DigCounters(C.Structure):
+    _fields_ = [("n", C.c_int64), ("step", C.c_int64), ("nsamp", C.c_int64),
+                ("next_id", C.c_int64), ("candidates", C.c_int64), ("accepted", C.c_int64),
+                ("inelastic", C.c_int64), ("saturated", C.c_int64), ("wall_hits", C.c_int64),
+                ("err", C.c_uint32), ("cur", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every exported entry point of include/dig.h
+EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
+           "dsmc_sample", "dig_adjust", "closure_assemble", "dsmc_query", "dig_constants",
+           "dig_last_error", "dsmc_destroy"]
+
+_lib = None
+
+
+class DigError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdig error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libdig.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdig.so not built at {path}; run __graft_entry__.build()")
+    # PyTorch's HIP runtime must be the process's HIP runtime: load it first so
+    # that libdig's libamdhip64.so.7 dependency binds to it.
+    import torch  # noqa: F401
+
+    L = C.CDLL(path)
+    vp, cp = C.c_void_p, C.POINTER(DigConfig)
+    L.dig_plan.argtypes = [cp, C.c_int32, C.c_int64, C.POINTER(DigLayout)]
+    L.dsmc_create.argtypes = [cp, C.c_int32, C.c_int64, vp, C.c_size_t, C.c_int32, C.c_int32,
+                              vp, C.POINTER(vp)]
+    L.dsmc_init.argtypes = [vp, vp, C.c_int32, vp]
+    L.dsmc_inject.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, vp]
+    L.dsmc_step.argtypes = [vp, C.c_int32, vp]
+    L.dsmc_stage.argtypes = [vp, C.c_int32, vp]
+    L.dsmc_sample.argtypes = [vp, C.c_int32, vp, vp]
+    L.dig_adjust.argtypes = [vp, vp, C.c_uint32, vp]
+    L.closure_assemble.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, vp, vp, vp, vp,
+                                   vp]
+    L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
+    L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+    L.dig_last_error.restype = C.c_char_p
+    L.dsmc_destroy.argtypes = [vp]
+    L.dsmc_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("dig_last_error", "dsmc_destroy"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != DIG_OK:
+        raise DigError(code, load().dig_last_error().decode())
+    return code
+
+
+def make_config(w: dict) -> DigConfig:
+    """libdig configuration from a workload description."""
+    c = DigConfig()
+    c.dim = w["dim"]
+    c.nx = w["nx"]
+    c.ny = w.get("ny", 1)
+    c.lx = w["lx"]
+    c.ly = w.get("ly", 1.0)
+    c.kn = w["kn"]
+    c.omega = w["omega"]
+    c.alpha = w.get("alpha", 1.0)
+    c.dr = w.get("dr", 2)
+    c.zrot = w["zrot"]
+    c.dt = w["dt"]
+    c.weight = w["weight"]
+    for f, bc in enumerate(w["bc"]):
+        c.bc[f].type = BC[bc[0]]
+        c.bc[f].T = bc[1]
+        for k in range(3):
+            c.bc[f].U[k] = bc[2][k]
+    c.seed = w["seed"]
+    c.instance_id = w.get("instance", 0)
+    c.sgmax_init = w.get("sgmax_init", 0.0)
+    c.tref = w.get("tref", 1.0)
+    return c

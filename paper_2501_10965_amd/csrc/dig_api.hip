@@ -1,0 +1,534 @@
+// Host side of libdig: validation, workspace layout, launches, errors.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "dig_internal.h"
+
+using namespace dig;
+
+namespace {
+
+thread_local std::string g_err;
+
+dig_status fail(dig_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+dig_status hip_fail(hipError_t e, const char* where) {
+  return fail(DIG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Internal {
+  size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart;
+  int64_t gfirst_len;
+};
+
+// Gas constants in paper units (Section 2): mu0 from the Knudsen number, the
+// VHS constant that gives the collision frequency 30 p / ((5-2w)(7-2w) mu),
+// and P_inelastic of equation P_inelastic.
+double vhs_constant(const dig_config& c) {
+  const double w = c.omega;
+  return 15.0 * M_PI /
+         (sqrt(2.0) * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) * pow(4.0, 1.0 - w) * tgamma(2.5 - w) *
+          c.kn);
+}
+double p_inelastic(const dig_config& c) {
+  const double w = c.omega, a = c.alpha;
+  return a * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) / (5.0 * (a + 1.0) * (a + 2.0) * c.zrot);
+}
+double cell_volume(const dig_config& c) {
+  const double dx = c.lx / c.nx;
+  return c.dim == 1 ? dx : dx * (c.ly / c.ny);
+}
+double default_majorant(const dig_config& c) {
+  if (c.sgmax_init > 0.0) return c.sgmax_init;
+  return vhs_constant(c) * pow(6.0 * sqrt(2.0 * c.tref), 2.0 - 2.0 * c.omega);
+}
+
+dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, int64_t* ncell) {
+  if (!cfgs) return fail(DIG_ERR_INVALID, "null config");
+  if (n_inst < 1) return fail(DIG_ERR_INVALID, "n_inst must be >= 1");
+  if (capacity < 1 || capacity > (int64_t)INT32_MAX - 1024)
+    return fail(DIG_ERR_INVALID, "capacity out of range");
+  int64_t C = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const dig_config& c = cfgs[i];
+    const std::string at = "instance " + std::to_string(i) + ": ";
+    if (c.dim != 1 && c.dim != 2) return fail(DIG_ERR_INVALID, at + "dim must be 1 or 2");
+    if (c.dim != cfgs[0].dim) return fail(DIG_ERR_INVALID, at + "all instances must share dim");
+    if (c.nx < 1 || c.ny < 1 || (c.dim == 1 && c.ny != 1))
+      return fail(DIG_ERR_INVALID, at + "bad cell counts");
+    if (!(c.lx > 0.0) || (c.dim == 2 && !(c.ly > 0.0)))
+      return fail(DIG_ERR_INVALID, at + "bad domain size");
+    if (!(c.kn > 0.0)) return fail(DIG_ERR_INVALID, at + "Kn must be > 0");
+    if (!(c.omega >= 0.5 && c.omega <= 1.0))
+      return fail(DIG_ERR_INVALID, at + "omega must lie in [0.5, 1]");
+    if (c.alpha != 1.0) return fail(DIG_ERR_INVALID, at + "alpha must be 1 (VHS scattering)");
+    if (c.dr != 2) return fail(DIG_ERR_INVALID, at + "d_r must be 2");
+    if (!(c.zrot > 0.0) || p_inelastic(c) > 1.0)
+      return fail(DIG_ERR_INVALID, at + "Z must give P_inelastic <= 1");
+    if (!(c.dt > 0.0) || !(c.weight > 0.0))
+      return fail(DIG_ERR_INVALID, at + "dt and weight must be > 0");
+    if (c.instance_id > 0xFFFFFFu) return fail(DIG_ERR_INVALID, at + "instance_id >= 2^24");
+    if (!(c.sgmax_init > 0.0) && !(c.tref > 0.0))
+      return fail(DIG_ERR_INVALID, at + "need sgmax_init > 0 or tref > 0");
+    const int nf = c.dim == 1 ? 2 : 4;
+    for (int f = 0; f < nf; ++f) {
+      const dig_bc& b = c.bc[f];
+      if (b.type < 0 || b.type > 2) return fail(DIG_ERR_INVALID, at + "bad bc type");
+      if (b.type == DIG_BC_DIFFUSE) {
+        if (!(b.T > 0.0)) return fail(DIG_ERR_INVALID, at + "diffuse wall needs T > 0");
+        if (b.U[f / 2] != 0.0)
+          return fail(DIG_ERR_INVALID, at + "wall velocity must be tangential");
+      }
+    }
+    for (int ax = 0; ax < nf / 2; ++ax)
+      if ((c.bc[2 * ax].type == DIG_BC_PERIODIC) != (c.bc[2 * ax + 1].type == DIG_BC_PERIODIC))
+        return fail(DIG_ERR_INVALID, at + "periodic faces must come in pairs");
+    C += (int64_t)c.nx * c.ny;
+  }
+  if (C > (int64_t)INT32_MAX / 32) return fail(DIG_ERR_INVALID, "too many cells");
+  *ncell = C;
+  return DIG_OK;
+}
+
+void plan_layout(int64_t cap, int64_t C, int32_t n_inst, dig_layout* L, Internal* I) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  memset(L, 0, sizeof(*L));
+  L->capacity = cap;
+  L->ncell = C;
+  for (int b = 0; b < 2; ++b) {
+    L->x[b] = take(4 * cap);
+    L->y[b] = take(4 * cap);
+    L->vx[b] = take(4 * cap);
+    L->vy[b] = take(4 * cap);
+    L->vz[b] = take(4 * cap);
+    L->er[b] = take(4 * cap);
+    L->id[b] = take(4 * cap);
+  }
+  L->cell = take(4 * cap);
+  L->rank = take(4 * cap);
+  L->perm_raw = take(4 * cap);
+  L->perm = take(4 * cap);
+  L->start = take(4 * (C + 1));
+  L->count = take(4 * C);
+  L->sgmax = take(4 * C);
+  L->acc = take(8 * 17 * C);
+  L->sums = take(8 * 17 * C);
+  L->cell_inst = take(4 * C);
+  L->counters = take(sizeof(dig_counters));
+  I->gfirst_len = cap / kMinGroupParticles + C / kMinGroupCells + 4;
+  I->gfirst = take(4 * I->gfirst_len);
+  I->inst_pstart = take(8 * (n_inst + 1));
+  I->params = take(sizeof(InstParam) * n_inst);
+  I->owner = take(4 * cap);
+  I->newcount = take(4 * C);
+  I->ccount = take(4 * C);
+  I->newstart = take(4 * (C + 1));
+  I->cstart = take(4 * (C + 1));
+  L->total_bytes = o;
+}
+
+InstParam make_param(const dig_config& c, int32_t cell0) {
+  InstParam p;
+  memset(&p, 0, sizeof(p));
+  p.dim = c.dim;
+  p.nx = c.nx;
+  p.ny = c.ny;
+  p.cell0 = cell0;
+  p.ncell = c.nx * c.ny;
+  p.dr = c.dr;
+  for (int f = 0; f < 4; ++f) {
+    const bool used = c.dim == 2 || f < 2;
+    p.bc_type[f] = used ? c.bc[f].type : DIG_BC_PERIODIC;
+    p.bc_T[f] = (float)c.bc[f].T;
+    for (int k = 0; k < 3; ++k) p.bc_U[f][k] = (float)c.bc[f].U[k];
+  }
+  p.dx = c.lx / c.nx;
+  p.dy = c.dim == 2 ? c.ly / c.ny : 1.0;
+  p.inv_dx = (float)(1.0 / p.dx);
+  p.inv_dy = (float)(1.0 / p.dy);
+  p.gx = (float)c.nx;
+  p.gy = (float)c.ny;
+  p.dtf = (float)c.dt;
+  p.csig = (float)vhs_constant(c);
+  p.expo = (float)(1.0 - c.omega);
+  p.beta_inv = (float)(1.0 / (2.5 - c.omega));
+  p.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+  p.key1 = (uint32_t)(c.seed >> 32);
+  p.inst = c.instance_id;
+  p.pin = p_inelastic(c);
+  p.weight = c.weight;
+  p.dt = c.dt;
+  p.vol = cell_volume(c);
+  p.mu0 = c.kn * sqrt(2.0 / M_PI);
+  p.omega = c.omega;
+  return p;
+}
+
+}  // namespace
+
+struct dig_ctx {
+  std::vector<dig_config> cfg;
+  std::vector<InstParam> params;
+  std::vector<int32_t> cell_inst_host;
+  dig_layout L;
+  Internal I;
+  unsigned char* ws = nullptr;
+  int32_t n_inst = 0, ncell = 0, dim = 1;
+  int64_t capacity = 0, n_host = 0;
+  int cur = 0;
+  int32_t T = 1024, Gc = 256, Lp = 2048;
+  bool has_state = false;
+  int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
+};
+
+namespace {
+
+StepArgs args(const dig_ctx* c) {
+  StepArgs a;
+  memset(&a, 0, sizeof(a));
+  unsigned char* w = c->ws;
+  const dig_layout& L = c->L;
+  const int s = c->cur, d = 1 - c->cur;
+  a.A = DevState{(float*)(w + L.x[s]), (float*)(w + L.y[s]), (float*)(w + L.vx[s]),
+                 (float*)(w + L.vy[s]), (float*)(w + L.vz[s]), (float*)(w + L.er[s]),
+                 (uint32_t*)(w + L.id[s])};
+  a.B = DevState{(float*)(w + L.x[d]), (float*)(w + L.y[d]), (float*)(w + L.vx[d]),
+                 (float*)(w + L.vy[d]), (float*)(w + L.vz[d]), (float*)(w + L.er[d]),
+                 (uint32_t*)(w + L.id[d])};
+  a.cell = (int32_t*)(w + L.cell);
+  a.rank = (int32_t*)(w + L.rank);
+  a.perm_raw = (int32_t*)(w + L.perm_raw);
+  a.perm = (int32_t*)(w + L.perm);
+  a.start = (int32_t*)(w + L.start);
+  a.count = (int32_t*)(w + L.count);
+  a.cell_inst = (int32_t*)(w + L.cell_inst);
+  a.gfirst = (int32_t*)(w + c->I.gfirst);
+  a.sgmax = (float*)(w + L.sgmax);
+  a.acc = (double*)(w + L.acc);
+  a.sums = (double*)(w + L.sums);
+  a.inst_pstart = (int64_t*)(w + c->I.inst_pstart);
+  a.owner = (uint32_t*)(w + c->I.owner);
+  a.params = (const InstParam*)(w + c->I.params);
+  a.ctr = (dig_counters*)(w + L.counters);
+  a.n_inst = c->n_inst;
+  a.ncell = c->ncell;
+  a.dim = c->dim;
+  a.group_particles = c->T;
+  a.group_cells = c->Gc;
+  a.lds_particles = c->Lp;
+  a.n_upper = c->n_host;
+  return a;
+}
+
+__global__ void k_counts_from_start(const int32_t* start, int32_t* counts, int C) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C) counts[c] = start[c + 1] - start[c];
+}
+
+__global__ void k_add_i64(int64_t* p, int64_t v) { *p += v; }
+__global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
+__global__ void k_clear_err(uint32_t* p, uint32_t bits) { *p &= ~bits; }
+
+dig_status check_ctx(dig_ctx* c) {
+  if (!c) return fail(DIG_ERR_INVALID, "null context");
+  return DIG_OK;
+}
+
+// Stages must run in order (move, sort, collide): the sort consumes the
+// reservations of the move and the collide consumes the sorted permutation.
+dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
+  StepArgs a = args(c);
+  if (mask & DIG_STAGE_MOVE) {
+    if (c->phase != 0) return fail(DIG_ERR_STATE, "move needs a completed previous step");
+    HIP_TRY(launch_move(a, s));
+    c->phase = 1;
+  }
+  if (mask & DIG_STAGE_SORT) {
+    if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
+    HIP_TRY(launch_scan(a, a.count, true, s));
+    HIP_TRY(launch_place(a, s));
+    HIP_TRY(launch_order(a, s));
+    c->phase = 2;
+  }
+  if (mask & DIG_STAGE_COLLIDE) {
+    if (c->phase != 2) return fail(DIG_ERR_STATE, "collide needs the sort stage first");
+    HIP_TRY(launch_collide(a, true, true, s));
+    HIP_TRY(launch_step_end(a, true, s));
+    c->cur ^= 1;
+    c->phase = 0;
+  }
+  return DIG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dig_last_error(void) { return g_err.c_str(); }
+
+dig_status dig_plan(const dig_config* cfgs, int32_t n_inst, int64_t capacity, dig_layout* out) {
+  if (!out) return fail(DIG_ERR_INVALID, "null layout");
+  int64_t C = 0;
+  dig_status st = validate(cfgs, n_inst, capacity, &C);
+  if (st != DIG_OK) return st;
+  Internal I;
+  plan_layout(capacity, C, n_inst, out, &I);
+  return DIG_OK;
+}
+
+dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity, void* ws,
+                       size_t ws_bytes, int32_t group_particles, int32_t group_cells,
+                       dig_stream_t stream, dig_ctx** out) {
+  if (!out) return fail(DIG_ERR_INVALID, "null output");
+  *out = nullptr;
+  int64_t C = 0;
+  dig_status st = validate(cfgs, n_inst, capacity, &C);
+  if (st != DIG_OK) return st;
+  if (!ws) return fail(DIG_ERR_INVALID, "null workspace");
+  if (((uintptr_t)ws) % kAlign) return fail(DIG_ERR_INVALID, "workspace not 256-byte aligned");
+  const int32_t T = group_particles > 0 ? group_particles : 1024;
+  const int32_t Gc = group_cells > 0 ? group_cells : 256;
+  if (T < kMinGroupParticles || T > 16384)
+    return fail(DIG_ERR_INVALID, "group_particles must lie in [256, 16384]");
+  if (Gc < kMinGroupCells || Gc > 1024)
+    return fail(DIG_ERR_INVALID, "group_cells must lie in [32, 1024]");
+  dig_ctx* c = new dig_ctx;
+  c->cfg.assign(cfgs, cfgs + n_inst);
+  c->n_inst = n_inst;
+  c->ncell = (int32_t)C;
+  c->dim = cfgs[0].dim;
+  c->capacity = capacity;
+  c->n_host = capacity;
+  c->T = T;
+  c->Gc = Gc;
+  // LDS particle stage: twice the group target, within 64 KiB of LDS
+  int32_t Lp = 2 * T;
+  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 64 * 1024) Lp -= 256;
+  c->Lp = Lp;
+  plan_layout(capacity, C, n_inst, &c->L, &c->I);
+  if (ws_bytes < c->L.total_bytes) {
+    const std::string msg =
+        "workspace too small: need " + std::to_string(c->L.total_bytes) + " bytes";
+    delete c;
+    return fail(DIG_ERR_INVALID, msg);
+  }
+  c->ws = (unsigned char*)ws;
+  int32_t cell0 = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    c->params.push_back(make_param(cfgs[i], cell0));
+    for (int k = 0; k < cfgs[i].nx * cfgs[i].ny; ++k) c->cell_inst_host.push_back(i);
+    cell0 += cfgs[i].nx * cfgs[i].ny;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StepArgs a = args(c);
+  hipError_t e = hipMemcpyAsync((void*)a.params, c->params.data(),
+                                sizeof(InstParam) * n_inst, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(a.cell_inst, c->cell_inst_host.data(), 4 * C, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_i32(a.count, C, 0, s);
+  if (e == hipSuccess) e = launch_fill_f64(a.acc, 17 * C, 0.0, s);
+  for (int i = 0; i < n_inst && e == hipSuccess; ++i)
+    e = launch_fill_f32(a.sgmax + c->params[i].cell0, c->params[i].ncell,
+                        (float)default_majorant(cfgs[i]), s);
+  if (e == hipSuccess) e = launch_set_counters(a.ctr, 0, 0, 0, true, s);
+  // the host copies above read host vectors owned by the context: wait for them
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "dsmc_create");
+  }
+  *out = c;
+  return DIG_OK;
+}
+
+dig_status dsmc_init(dig_ctx* c, const double* fields, int32_t ppc, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!fields) return fail(DIG_ERR_INVALID, "null fields");
+  if (ppc < 0) return fail(DIG_ERR_INVALID, "ppc must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  c->cur = 0;
+  c->phase = 0;
+  c->n_host = c->capacity;
+  StepArgs a = args(c);
+  HIP_TRY(launch_set_counters(a.ctr, 0, 0, 0, true, s));
+  HIP_TRY(launch_init(a, fields, ppc, s, 0));
+  HIP_TRY(launch_scan(a, a.count, true, s));
+  int32_t total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, a.start + c->ncell, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (total > c->capacity) {
+    c->has_state = false;
+    return fail(DIG_ERR_CAPACITY, "initial particle count " + std::to_string(total) +
+                                      " exceeds capacity");
+  }
+  c->n_host = total;
+  a = args(c);
+  HIP_TRY(launch_init(a, fields, ppc, s, 1));
+  HIP_TRY(launch_set_counters(a.ctr, total, 0, total, false, s));
+  c->has_state = true;
+  return DIG_OK;
+}
+
+dig_status dsmc_inject(dig_ctx* c, int64_t n, int64_t step, int64_t next_id,
+                       dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (n < 0 || n > c->capacity) return fail(DIG_ERR_CAPACITY, "n outside [0, capacity]");
+  hipStream_t s = (hipStream_t)stream;
+  c->n_host = n > 0 ? n : 1;
+  c->phase = 0;
+  StepArgs a = args(c);
+  hipLaunchKernelGGL(k_counts_from_start, dim3((c->ncell + 255) / 256), dim3(256), 0, s,
+                     a.start, a.count, c->ncell);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_scan(a, a.count, false, s));
+  HIP_TRY(launch_set_counters(a.ctr, n, step, next_id, false, s));
+  c->n_host = n;
+  c->has_state = true;
+  return DIG_OK;
+}
+
+dig_status dsmc_step(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state (call dsmc_init)");
+  if (nsteps < 0) return fail(DIG_ERR_INVALID, "nsteps < 0");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  for (int k = 0; k < nsteps; ++k) {
+    dig_status st = run_stages(c, DIG_STAGE_ALL, (hipStream_t)stream);
+    if (st != DIG_OK) return st;
+  }
+  return DIG_OK;
+}
+
+dig_status dsmc_stage(dig_ctx* c, int32_t mask, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
+  if (mask & ~DIG_STAGE_ALL) return fail(DIG_ERR_INVALID, "bad stage mask");
+  return run_stages(c, mask, (hipStream_t)stream);
+}
+
+dig_status dsmc_sample(dig_ctx* c, int32_t mode, double* out, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  StepArgs a = args(c);
+  if (mode == DIG_SAMPLE_RESET) {
+    HIP_TRY(launch_fill_f64(a.acc, 17 * (int64_t)c->ncell, 0.0, s));
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &a.ctr->nsamp, (int64_t)0);
+    HIP_TRY(hipGetLastError());
+    return DIG_OK;
+  }
+  if (!out) return fail(DIG_ERR_INVALID, "null output");
+  if (mode == DIG_SAMPLE_INSTANT) {
+    if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
+    HIP_TRY(launch_sample_state(a, s));
+    HIP_TRY(launch_convert(a, a.sums, false, out, s));
+    return DIG_OK;
+  }
+  if (mode == DIG_SAMPLE_AVERAGE) {
+    HIP_TRY(launch_convert(a, a.acc, true, out, s));
+    return DIG_OK;
+  }
+  return fail(DIG_ERR_INVALID, "bad sample mode");
+}
+
+dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!target) return fail(DIG_ERR_INVALID, "null target");
+  if (c->n_inst != 1) return fail(DIG_ERR_INVALID, "dig_adjust needs a single-instance context");
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  hipStream_t s = (hipStream_t)stream;
+  StepArgs a = args(c);
+  unsigned char* w = c->ws;
+  int32_t* newcount = (int32_t*)(w + c->I.newcount);
+  int32_t* ccount = (int32_t*)(w + c->I.ccount);
+  int32_t* newstart = (int32_t*)(w + c->I.newstart);
+  int32_t* cstart = (int32_t*)(w + c->I.cstart);
+  HIP_TRY(launch_adjust_count(a, target, iter, newcount, ccount, s));
+  HIP_TRY(launch_exscan(newcount, newstart, c->ncell, s));
+  HIP_TRY(launch_exscan(ccount, cstart, c->ncell, s));
+  int32_t tot[2] = {0, 0};
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&tot[0], newstart + c->ncell, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tot[1], cstart + c->ncell, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&err, &a.ctr->err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err & DIG_EBIT_TARGET) {
+    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(1), 0, s, &a.ctr->err,
+                       (uint32_t)DIG_EBIT_TARGET);
+    HIP_TRY(hipGetLastError());
+    return fail(DIG_ERR_NUMERIC, "dig_adjust: non-finite or non-positive target");
+  }
+  if (tot[0] > c->capacity)
+    return fail(DIG_ERR_CAPACITY, "dig_adjust: " + std::to_string(tot[0]) +
+                                      " particles exceed the capacity");
+  HIP_TRY(launch_adjust_build(a, target, iter, newstart, cstart, s));
+  c->cur ^= 1;
+  c->n_host = tot[0] > 0 ? tot[0] : 1;
+  a = args(c);
+  HIP_TRY(launch_scan(a, newcount, true, s));
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, s, &a.ctr->next_id, (int64_t)tot[1]);
+  HIP_TRY(hipGetLastError());
+  c->n_host = tot[0];
+  return DIG_OK;
+}
+
+dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, double kn_ref,
+                            double* hot, uint8_t* mask, double* kngll, double* nsf,
+                            dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!fields || !A || !hot || !mask || !kngll) return fail(DIG_ERR_INVALID, "null argument");
+  const double det = A[0] * A[3] - A[1] * A[2];
+  if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
+  StepArgs a = args(c);
+  HIP_TRY(launch_closure(a, fields, A[0], A[1], A[2], A[3], kn_ref, hot, mask, kngll, nsf,
+                         (hipStream_t)stream));
+  return DIG_OK;
+}
+
+dig_status dsmc_query(dig_ctx* c, dig_counters* out, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!out) return fail(DIG_ERR_INVALID, "null output");
+  hipStream_t s = (hipStream_t)stream;
+  StepArgs a = args(c);
+  HIP_TRY(hipMemcpyAsync(out, a.ctr, sizeof(dig_counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out->cur = (uint32_t)c->cur;
+  return DIG_OK;
+}
+
+dig_status dig_constants(dig_ctx* c, int32_t inst, double* out) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!out || inst < 0 || inst >= c->n_inst) return fail(DIG_ERR_INVALID, "bad instance");
+  const dig_config& g = c->cfg[inst];
+  out[0] = vhs_constant(g);
+  out[1] = p_inelastic(g);
+  out[2] = g.kn * sqrt(2.0 / M_PI);
+  out[3] = cell_volume(g);
+  out[4] = default_majorant(g);
+  return DIG_OK;
+}
+
+void dsmc_destroy(dig_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations of libdig shared by the kernels and the host API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dig.h"
+
+namespace dig {
+
+// Philox stream tags (high byte of counter word 2).
+enum : uint32_t {
+  TAG_INIT = 1, TAG_INIT_N = 2, TAG_WALL = 3, TAG_NCAND = 4, TAG_COLL = 5,
+  TAG_DIG_N = 6, TAG_DIG_DEL = 7, TAG_DIG_SRC = 8, TAG_DIG_EMPTY = 9
+};
+
+constexpr int kMaxHits = 8;      // wall events per particle and step
+constexpr int kRunMax = 4096;    // run table of the sort kernel
+constexpr int kCandChunk = 512;  // candidates staged per round set
+constexpr int kMinGroupParticles = 256;
+constexpr int kMinGroupCells = 32;
+
+// Per-instance constants, resident in the workspace.
+struct InstParam {
+  int32_t dim, nx, ny, cell0;
+  int32_t ncell, dr, pad0, pad1;
+  int32_t bc_type[4];
+  float bc_T[4];
+  float bc_U[4][3];
+  float inv_dx, inv_dy, gx, gy;
+  float dtf, csig, expo, beta_inv;
+  uint32_t key0, key1, inst, pad2;
+  double pin;            // P_inelastic (decisions taken in double)
+  double weight, dt, vol;
+  double mu0, omega, dx, dy;
+};
+
+struct DevState {
+  float *x, *y, *vx, *vy, *vz, *er;
+  uint32_t* id;
+};
+
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 draw(const InstParam& P, uint32_t entity, uint32_t step,
+                                      uint32_t tag, uint32_t idx) {
+  return philox10(entity, step, (tag << 24) | (P.inst & 0xFFFFFFu), idx, P.key0, P.key1);
+}
+
+// (k + 1/2) 2^-23 for the top 23 bits k: exact in single precision.
+__device__ __forceinline__ float u01f(uint32_t r) {
+  return (float)(r >> 9) * 0x1p-23f + 0x1p-24f;
+}
+__device__ __forceinline__ double u01d(uint32_t r) {
+  return (double)(r >> 9) * 0x1p-23 + 0x1p-24;
+}
+__device__ __forceinline__ uint32_t pick(uint32_t r, uint32_t n) { return __umulhi(r, n); }
+
+// Launch plumbing implemented in dig_kernels.hip.
+struct StepArgs {
+  DevState A, B;
+  int32_t *cell, *rank, *perm_raw, *perm, *start, *count, *cell_inst, *gfirst;
+  float* sgmax;
+  double *acc, *sums;
+  int64_t* inst_pstart;
+  uint32_t* owner;
+  const InstParam* params;
+  dig_counters* ctr;
+  int32_t n_inst, ncell, dim;
+  int32_t group_particles, group_cells, lds_particles;
+  int64_t n_upper;
+};
+
+int64_t group_launch(const StepArgs& a);
+size_t collide_lds_bytes(int lds_particles, int group_cells);
+hipError_t launch_move(const StepArgs& a, hipStream_t s);
+hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s);
+hipError_t launch_place(const StepArgs& a, hipStream_t s);
+hipError_t launch_order(const StepArgs& a, hipStream_t s);
+hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStream_t s);
+hipError_t launch_step_end(const StepArgs& a, bool sample, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_set_counters(dig_counters* c, int64_t n, int64_t step, int64_t next_id,
+                               bool reset_all, hipStream_t s);
+hipError_t launch_init(const StepArgs& a, const double* fields, int32_t ppc, hipStream_t s,
+                       int phase);
+hipError_t launch_sample_state(const StepArgs& a, hipStream_t s);
+hipError_t launch_convert(const StepArgs& a, const double* sums, bool average, double* out,
+                          hipStream_t s);
+hipError_t launch_adjust_count(const StepArgs& a, const double* target, uint32_t iter,
+                               int32_t* newcount, int32_t* ccount, hipStream_t s);
+hipError_t launch_exscan(const int32_t* in, int32_t* out, int32_t n, hipStream_t s);
+hipError_t launch_adjust_build(const StepArgs& a, const double* target, uint32_t iter,
+                               const int32_t* newstart, const int32_t* cstart,
+                               hipStream_t s);
+hipError_t launch_closure(const StepArgs& a, const double* fields, double Att, double Atr,
+                          double Art, double Arr, double kn_ref, double* hot, uint8_t* mask,
+                          double* kngll, double* nsf, hipStream_t s);
+
+}  // namespace dig

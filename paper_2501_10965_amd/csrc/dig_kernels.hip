@@ -1,0 +1,1183 @@
+// HIP kernels of libdig for gfx950 (CDNA4, wave64).
+//
+// One DSMC step (Section 2.2 of arXiv:2501.10965) is five launches:
+//   k_move     free flight + walls + cell index + wave-aggregated reservation
+//   k_scan     cell counts -> cell starts, cell groups, instance ranges
+//   k_place    provisional placement by the reserved rank
+//   k_order    per-cell ordering of the provisional runs (stable sort result)
+//   k_collide  gather into the other buffer, NTC/VHS/BL collisions in LDS,
+//              FP64 moment sums accumulated per cell
+// plus a one-thread step counter update.  Every result is a deterministic
+// function of (seed, step, state): no floating-point atomics, and the
+// reservation atomics only decide the order of runs, which k_order restores.
+#include <math.h>
+
+#include "dig_internal.h"
+
+namespace dig {
+
+static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Instance of particle slot p (instance particle ranges are contiguous).
+static __device__ __forceinline__ int find_inst(const int64_t* pstart, int n_inst, int64_t p) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pstart[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Largest i in [0, n) with a[i] <= v (a non-decreasing, a[0] <= v).
+template <typename T>
+static __device__ __forceinline__ int floor_index(const T* a, int n, T v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Iround of Section 3.2 with the products taken in a fixed order and no
+// contraction, so the host oracle and the device agree bit for bit.
+static __device__ __noinline__ double ncand_mean(int N, double w, double sg, double dt,
+                                                 double vol) {
+#pragma clang fp contract(off)
+  return 0.5 * (double)N * (double)(N - 1) * w * sg * dt / vol;
+}
+static __device__ __noinline__ double count_mean(double rho, double vol, double w) {
+#pragma clang fp contract(off)
+  return rho * vol / w;
+}
+static __device__ __forceinline__ int iround(double x, uint32_t r) {
+  const double f = floor(x);
+  return (int)f + ((u01d(r) < x - f) ? 1 : 0);
+}
+
+static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
+  // position ix + u rounded to float must stay below the upper cell face
+  const float top = (float)(cellidx + 1);
+  return v < top ? v : __uint_as_float(__float_as_uint(top) - 1u);  // largest float below top
+}
+
+// ---------------------------------------------------------------------------
+// Free flight with diffuse / specular walls, then cell index and reservation.
+__global__ __launch_bounds__(256) void k_move(StepArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.ctr->n;
+  const uint32_t step = (uint32_t)a.ctr->step;
+  const bool valid = p < n;
+  int cell = 0;
+  int hits_here = 0;
+  if (valid) {
+    const int inst = find_inst(a.inst_pstart, a.n_inst, p);
+    const InstParam& P = a.params[inst];
+    const bool two = P.dim == 2;
+    float x = a.A.x[p];
+    float y = two ? a.A.y[p] : 0.0f;
+    float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
+    float t = P.dtf;
+    int hit = 0;
+    bool wall_hit = false, er_set = false;
+    float er = 0.0f;
+    for (;;) {
+      const float sx = vx * P.inv_dx;
+      const float sy = two ? vy * P.inv_dy : 0.0f;
+      int face = -1;
+      float th = t;
+      const float xe = x + sx * t;
+      const bool w0 = P.bc_type[0] != DIG_BC_PERIODIC, w1 = P.bc_type[1] != DIG_BC_PERIODIC;
+      if (xe < 0.0f && w0) {
+        float tf = (0.0f - x) / sx;
+        if (tf <= th) { th = tf; face = 0; }
+      } else if (xe > P.gx && w1) {
+        float tf = (P.gx - x) / sx;
+        if (tf <= th) { th = tf; face = 1; }
+      }
+      if (two) {
+        const float ye = y + sy * t;
+        const bool w2 = P.bc_type[2] != DIG_BC_PERIODIC, w3 = P.bc_type[3] != DIG_BC_PERIODIC;
+        if (ye < 0.0f && w2) {
+          float tf = (0.0f - y) / sy;
+          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 2; }
+        } else if (ye > P.gy && w3) {
+          float tf = (P.gy - y) / sy;
+          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 3; }
+        }
+      }
+      if (face < 0 || hit >= kMaxHits) {
+        x += sx * t;
+        if (two) y += sy * t;
+        if (hit >= kMaxHits) {
+          if (P.bc_type[0] != DIG_BC_PERIODIC && x < 0.0f) x = 0.0f;
+          if (P.bc_type[1] != DIG_BC_PERIODIC && x > P.gx) x = P.gx;
+          if (two) {
+            if (P.bc_type[2] != DIG_BC_PERIODIC && y < 0.0f) y = 0.0f;
+            if (P.bc_type[3] != DIG_BC_PERIODIC && y > P.gy) y = P.gy;
+          }
+        }
+        break;
+      }
+      x += sx * th;
+      if (two) y += sy * th;
+      if (face == 0) x = 0.0f;
+      if (face == 1) x = P.gx;
+      if (face == 2) y = 0.0f;
+      if (face == 3) y = P.gy;
+      t -= th;
+      const int axis = face >> 1;
+      const float inward = (face & 1) ? -1.0f : 1.0f;
+      if (P.bc_type[face] == DIG_BC_SPECULAR) {
+        if (axis == 0) vx = -vx; else vy = -vy;
+      } else {
+        const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
+        const float T = P.bc_T[face];
+        const float vn = sqrtf(-2.0f * T * logf(u01f(w.x)));
+        const float r = sqrtf(-2.0f * logf(u01f(w.y)));
+        float sn, cs;
+        sincospif(2.0f * u01f(w.z), &sn, &cs);
+        const float s = sqrtf(T);
+        if (axis == 0) {
+          vx = inward * vn;
+          vy = P.bc_U[face][1] + s * (r * cs);
+        } else {
+          vy = inward * vn;
+          vx = P.bc_U[face][0] + s * (r * cs);
+        }
+        vz = P.bc_U[face][2] + s * (r * sn);
+        er = -T * logf(u01f(w.w));
+        er_set = true;
+      }
+      wall_hit = true;
+      ++hit;
+    }
+    if (P.bc_type[0] == DIG_BC_PERIODIC) x -= P.gx * floorf(x / P.gx);
+    if (two && P.bc_type[2] == DIG_BC_PERIODIC) y -= P.gy * floorf(y / P.gy);
+    a.A.x[p] = x;
+    if (two) a.A.y[p] = y;
+    if (wall_hit) {
+      a.A.vx[p] = vx;
+      a.A.vy[p] = vy;
+      a.A.vz[p] = vz;
+      if (er_set) a.A.er[p] = er;  // diffuse re-emission draws er; specular keeps it
+    }
+    hits_here = hit;
+    int ix = (int)floorf(x);
+    ix = ix < 0 ? 0 : (ix > P.nx - 1 ? P.nx - 1 : ix);
+    int iy = 0;
+    if (two) {
+      iy = (int)floorf(y);
+      iy = iy < 0 ? 0 : (iy > P.ny - 1 ? P.ny - 1 : iy);
+    }
+    cell = P.cell0 + ix + P.nx * iy;
+  }
+  // wave-aggregated reservation: one atomic per (wave, destination cell); the
+  // lanes of a run get consecutive ranks in lane (= slot) order
+  unsigned long long todo = __ballot(valid);
+  int rank = 0;
+  while (todo) {
+    const int leader = __ffsll(todo) - 1;
+    const int lc = __shfl(cell, leader);
+    const unsigned long long m = __ballot(valid && cell == lc);
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&a.count[lc], __popcll(m));
+    base = __shfl(base, leader);
+    if (valid && cell == lc) rank = base + __popcll(m & __lanemask_lt());
+    todo &= ~m;
+  }
+  if (valid) {
+    a.cell[p] = cell;
+    a.rank[p] = rank;
+  }
+  // wall-hit statistics: one atomic per wave
+  int hsum = hits_here;
+  for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
+  if (lane_id() == 0 && hsum) atomicAdd((unsigned long long*)&a.ctr->wall_hits,
+                                        (unsigned long long)hsum);
+}
+
+// ---------------------------------------------------------------------------
+// Single-workgroup scan of cell counts; also cell groups and instance ranges.
+__global__ __launch_bounds__(1024) void k_scan(StepArgs a, int32_t* counts, int32_t glaunch,
+                                               int set_n) {
+  __shared__ int64_t s_tot[1024];
+  const int tid = threadIdx.x;
+  const int C = a.ncell;
+  const int per = (C + 1023) / 1024;
+  const int c0 = min(C, tid * per), c1 = min(C, c0 + per);
+  int64_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += counts[c];
+  s_tot[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = (tid >= off) ? s_tot[tid - off] : 0;
+    __syncthreads();
+    s_tot[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = s_tot[tid] - sum;
+  for (int c = c0; c < c1; ++c) {
+    a.start[c] = (int32_t)run;
+    run += counts[c];
+    counts[c] = 0;
+  }
+  if (tid == 0) a.start[C] = (int32_t)s_tot[1023];
+  __threadfence_block();
+  __syncthreads();
+  const int64_t T = a.group_particles, G = a.group_cells;
+  for (int c = c0; c < c1; ++c) {
+    const int64_t key = a.start[c] / T + c / G;
+    const int64_t kp = (c == 0) ? -1 : (a.start[c - 1] / T + (c - 1) / G);
+    for (int64_t g = kp + 1; g <= key; ++g) {
+      if (g <= glaunch) a.gfirst[g] = c;
+      else atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_GROUPS);
+    }
+  }
+  const int64_t klast = a.start[C - 1] / T + (C - 1) / G;
+  for (int64_t g = klast + 1 + tid; g <= glaunch; g += 1024) a.gfirst[g] = C;
+  for (int i = tid; i <= a.n_inst; i += 1024)
+    a.inst_pstart[i] = (i == a.n_inst) ? a.start[C] : a.start[a.params[i].cell0];
+  if (tid == 0 && set_n) a.ctr->n = a.start[C];
+}
+
+__global__ __launch_bounds__(256) void k_place(StepArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.ctr->n) return;
+  a.perm_raw[a.start[a.cell[p]] + a.rank[p]] = (int32_t)p;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of 0/1 flags (blockDim = 256).
+static __device__ __forceinline__ int block_flag_scan(bool f, int* s_w, int* total) {
+  const unsigned long long b = __ballot(f);
+  const int w = threadIdx.x >> 6;
+  const int pre = __popcll(b & __lanemask_lt());
+  if (lane_id() == 0) s_w[w] = __popcll(b);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    if (k < w) off += s_w[k];
+    tot += s_w[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + pre;
+}
+
+// Restores (cell, slot) order inside each cell.  The provisional segment of a
+// cell is a concatenation of runs, one per reserving wave; a run is increasing
+// and the runs of different waves cover disjoint slot ranges, so ordering the
+// runs by their first slot yields the stable counting-sort order.
+__global__ __launch_bounds__(256) void k_order(StepArgs a) {
+  __shared__ int s_start[1025];
+  __shared__ uint32_t s_key[kRunMax];
+  __shared__ uint32_t s_re[kRunMax + 1];
+  __shared__ uint32_t s_off[kRunMax];
+  __shared__ int s_w[8];
+  __shared__ int s_nr;
+  const int g = blockIdx.x;
+  const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
+  if (c_lo >= c_hi) return;
+  const int nc = c_hi - c_lo;
+  const int e_lo = a.start[c_lo];
+  const int ng = a.start[c_hi] - e_lo;
+  for (int c = threadIdx.x; c <= nc; c += blockDim.x) s_start[c] = a.start[c_lo + c] - e_lo;
+  if (threadIdx.x == 0) s_nr = 0;
+  __syncthreads();
+  if (ng == 0) return;
+  const int32_t* src = a.perm_raw + e_lo;
+  int32_t* dst = a.perm + e_lo;
+  bool overflow = false;
+  for (int base = 0; base < ng; base += blockDim.x) {
+    const int e = base + threadIdx.x;
+    bool flag = false;
+    uint32_t s = 0;
+    if (e < ng) {
+      s = (uint32_t)src[e];
+      const int c = floor_index(s_start, nc + 1, e);
+      flag = (e == s_start[c]) || ((s >> 6) != ((uint32_t)src[e - 1] >> 6));
+    }
+    int total;
+    const int idx = block_flag_scan(flag, s_w, &total);
+    const int r = s_nr + idx;
+    if (flag && r < kRunMax) {
+      s_key[r] = s;
+      s_re[r] = (uint32_t)e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_nr += total;
+    __syncthreads();
+    if (s_nr > kRunMax) { overflow = true; break; }
+  }
+  if (!overflow) {
+    const int nr = s_nr;
+    if (threadIdx.x == 0) s_re[nr] = (uint32_t)ng;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+      const int e = (int)s_re[r];
+      const int c = floor_index(s_start, nc + 1, e);
+      // runs of cell c: those starting in [s_start[c], s_start[c+1])
+      const int r0 = floor_index(s_re, nr + 1, (uint32_t)s_start[c]);
+      const uint32_t key = s_key[r];
+      uint32_t off = (uint32_t)s_start[c];
+      for (int q = r0; q < nr && s_re[q] < (uint32_t)s_start[c + 1]; ++q)
+        if (s_key[q] < key) off += s_re[q + 1] - s_re[q];
+      s_off[r] = off;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+      const int r = floor_index(s_re, nr + 1, (uint32_t)e);
+      dst[s_off[r] + (uint32_t)e - s_re[r]] = src[e];
+    }
+  } else {
+    // slow path: rank each entry against its cell by direct counting
+    if (threadIdx.x == 0) atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_SORT_OVERFLOW);
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+      const int c = floor_index(s_start, nc + 1, e);
+      const int32_t s = src[e];
+      int rank = 0;
+      for (int q = s_start[c]; q < s_start[c + 1]; ++q) rank += (src[q] < s);
+      dst[s_start[c] + rank] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Collisions.  Particle store in LDS (fast) or in the destination buffer.
+struct LdsStore {
+  float4* v;
+  __device__ float4 ld(int i) const { return v[i]; }
+  __device__ void st(int i, float4 q) const { v[i] = q; }
+};
+struct GlobalStore {
+  float *vx, *vy, *vz, *er;
+  __device__ float4 ld(int i) const { return make_float4(vx[i], vy[i], vz[i], er[i]); }
+  __device__ void st(int i, float4 q) const {
+    vx[i] = q.x;
+    vy[i] = q.y;
+    vz[i] = q.z;
+    er[i] = q.w;
+  }
+};
+
+struct CollideShared {
+  int* start;   // [Gc+1]
+  int* coff;    // [Gc+1]
+  float* sgm;   // [Gc]
+  uint32_t* obs;  // [Gc]
+  int* inst;    // [Gc]
+  int* ci;      // [KC]
+  int* cj;
+  int* cc;
+  uint32_t* w2;
+  uint32_t* w3;
+  uint8_t* pend;
+  int* stat;    // [4]
+  int* wsum;    // [8]
+};
+
+template <class Store>
+static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
+                                     uint32_t* owner, int nc, int c_lo, uint32_t step) {
+  // candidate counts, FP64 Iround as in the oracle
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int N = S.start[c + 1] - S.start[c];
+    int k = 0;
+    if (N >= 2) {
+      const InstParam& I = a.params[S.inst[c]];
+      const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_NCAND, 0);
+      k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, I.vol), r.x);
+    }
+    S.coff[c + 1] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.coff[0] = 0;
+    for (int c = 0; c < nc; ++c) S.coff[c + 1] += S.coff[c];
+  }
+  __syncthreads();
+  const int K = S.coff[nc];
+  int l_cand = 0, l_acc = 0, l_inel = 0, l_sat = 0;
+  for (int kb = 0; kb < K; kb += kCandChunk) {
+    const int kc = min(kCandChunk, K - kb);
+    for (int q = threadIdx.x; q < kc; q += blockDim.x) {
+      const int k = kb + q;
+      const int c = floor_index(S.coff, nc + 1, k);
+      const int kk = k - S.coff[c];
+      const int N = S.start[c + 1] - S.start[c];
+      const InstParam& I = a.params[S.inst[c]];
+      const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_COLL, 3u * (uint32_t)kk);
+      int i = (int)pick(r.x, (uint32_t)N);
+      int j = (int)pick(r.y, (uint32_t)(N - 1));
+      j += (j >= i);
+      S.ci[q] = S.start[c] + i;
+      S.cj[q] = S.start[c] + j;
+      S.cc[q] = c;
+      S.w2[q] = r.z;
+      S.w3[q] = r.w;
+      S.pend[q] = 1;
+    }
+    __syncthreads();
+    for (;;) {
+      for (int q = threadIdx.x; q < kc; q += blockDim.x)
+        if (S.pend[q]) {
+          owner[S.ci[q]] = 0xFFFFFFFFu;
+          owner[S.cj[q]] = 0xFFFFFFFFu;
+        }
+      __syncthreads();
+      for (int q = threadIdx.x; q < kc; q += blockDim.x)
+        if (S.pend[q]) {
+          atomicMin(&owner[S.ci[q]], (uint32_t)q);
+          atomicMin(&owner[S.cj[q]], (uint32_t)q);
+        }
+      __syncthreads();
+      int more = 0;
+      for (int q = threadIdx.x; q < kc; q += blockDim.x) {
+        if (!S.pend[q]) continue;
+        const int i = S.ci[q], j = S.cj[q];
+        if (owner[i] != (uint32_t)q || owner[j] != (uint32_t)q) {
+          more = 1;
+          continue;
+        }
+        S.pend[q] = 0;
+        const int c = S.cc[q];
+        const InstParam& I = a.params[S.inst[c]];
+        float4 va = P.ld(i), vb = P.ld(j);
+        const float gx = va.x - vb.x, gy = va.y - vb.y, gz = va.z - vb.z;
+        const float g2 = gx * gx + gy * gy + gz * gz;
+        const float sg = g2 > 0.0f ? I.csig * powf(g2, I.expo) : 0.0f;
+        atomicMax(&S.obs[c], __float_as_uint(sg));
+        const float ratio = sg / S.sgm[c];
+        ++l_cand;
+        l_sat += ratio > 1.0f;
+        if (!(u01f(S.w2[q]) < ratio)) continue;
+        ++l_acc;
+        const int kk = kb + q - S.coff[c];
+        const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+        const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+        const uint4 r2 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u);
+        float et = 0.25f * g2;
+        if (u01d(S.w3[q]) < I.pin) {
+          const float ec = et + va.w;
+          va.w = (1.0f - powf(u01f(r1.x), I.beta_inv)) * ec;
+          et = ec - va.w;
+          ++l_inel;
+        }
+        if (u01d(r1.y) < I.pin) {
+          const float ec = et + vb.w;
+          vb.w = (1.0f - powf(u01f(r1.z), I.beta_inv)) * ec;
+          et = ec - vb.w;
+          ++l_inel;
+        }
+        const float hg = sqrtf(et);  // half of |g'| = 2 sqrt(et)
+        const float ct = 2.0f * u01f(r1.w) - 1.0f;
+        const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        float sp, cp;
+        sincospif(2.0f * u01f(r2.x), &sp, &cp);
+        const float nx = ct, ny = st * cp, nz = st * sp;
+        const float cx = 0.5f * (va.x + vb.x), cy = 0.5f * (va.y + vb.y), cz = 0.5f * (va.z + vb.z);
+        va.x = cx + hg * nx;
+        va.y = cy + hg * ny;
+        va.z = cz + hg * nz;
+        vb.x = cx - hg * nx;
+        vb.y = cy - hg * ny;
+        vb.z = cz - hg * nz;
+        P.st(i, va);
+        P.st(j, vb);
+      }
+      if (!__syncthreads_or(more)) break;
+    }
+  }
+  atomicAdd(&S.stat[0], l_cand);
+  atomicAdd(&S.stat[1], l_acc);
+  atomicAdd(&S.stat[2], l_inel);
+  atomicAdd(&S.stat[3], l_sat);
+}
+
+// FP64 raw sums of one cell by one wave: lane-strided partial sums in slot
+// order, then a fixed xor butterfly, so the bits depend only on the cell's
+// particle order.
+template <class Store>
+static __device__ void wave_cell_sums(Store P, int b, int N, double s[17]) {
+#pragma unroll
+  for (int f = 0; f < 17; ++f) s[f] = 0.0;
+  for (int k = lane_id(); k < N; k += 64) {
+    const float4 v = P.ld(b + k);
+    const double x = v.x, y = v.y, z = v.z, e = v.w;
+    const double v2 = x * x + y * y + z * z;
+    s[0] += 1.0;
+    s[1] += x;
+    s[2] += y;
+    s[3] += z;
+    s[4] += x * x;
+    s[5] += y * y;
+    s[6] += z * z;
+    s[7] += x * y;
+    s[8] += x * z;
+    s[9] += y * z;
+    s[10] += x * v2;
+    s[11] += y * v2;
+    s[12] += z * v2;
+    s[13] += e;
+    s[14] += x * e;
+    s[15] += y * e;
+    s[16] += z * e;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int f = 0; f < 17; ++f) s[f] += __shfl_xor(s[f], off);
+}
+
+static __device__ __forceinline__ double select17(const double s[17], int f) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < 17; ++k) r = (f == k) ? s[k] : r;
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_collide(StepArgs a, int do_collide, int do_sample) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int g = blockIdx.x;
+  const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
+  if (c_lo >= c_hi) return;
+  const int nc = c_hi - c_lo;
+  const int Gc = a.group_cells;
+  const int L = a.lds_particles;
+  const uint32_t step = (uint32_t)a.ctr->step;
+  // shared layout
+  unsigned char* p = smem;
+  float4* sv = (float4*)p;              p += sizeof(float4) * L;
+  uint32_t* s_owner = (uint32_t*)p;     p += sizeof(uint32_t) * L;
+  CollideShared S;
+  S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
+  S.coff = (int*)p;                     p += sizeof(int) * (Gc + 1);
+  S.sgm = (float*)p;                    p += sizeof(float) * Gc;
+  S.obs = (uint32_t*)p;                 p += sizeof(uint32_t) * Gc;
+  S.inst = (int*)p;                     p += sizeof(int) * Gc;
+  S.ci = (int*)p;                       p += sizeof(int) * kCandChunk;
+  S.cj = (int*)p;                       p += sizeof(int) * kCandChunk;
+  S.cc = (int*)p;                       p += sizeof(int) * kCandChunk;
+  S.w2 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
+  S.w3 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
+  S.stat = (int*)p;                     p += sizeof(int) * 4;
+  S.wsum = (int*)p;                     p += sizeof(int) * 8;
+  S.pend = (uint8_t*)p;
+
+  const int e_lo = a.start[c_lo];
+  const int ng = a.start[c_hi] - e_lo;
+  for (int c = threadIdx.x; c <= nc; c += blockDim.x) {
+    S.start[c] = a.start[c_lo + c] - e_lo;
+    if (c < nc) {
+      S.sgm[c] = a.sgmax[c_lo + c];
+      S.obs[c] = 0u;
+      S.inst[c] = a.cell_inst[c_lo + c];
+    }
+  }
+  if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
+  const bool fast = ng <= L;
+  // gather: position and id go straight to the destination buffer
+  const bool two = a.dim == 2;
+  for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+    const int src = a.perm[e_lo + e];
+    const int d = e_lo + e;
+    a.B.x[d] = a.A.x[src];
+    if (two) a.B.y[d] = a.A.y[src];
+    a.B.id[d] = a.A.id[src];
+    const float4 v = make_float4(a.A.vx[src], a.A.vy[src], a.A.vz[src], a.A.er[src]);
+    if (fast) {
+      sv[e] = v;
+    } else {
+      a.B.vx[d] = v.x;
+      a.B.vy[d] = v.y;
+      a.B.vz[d] = v.z;
+      a.B.er[d] = v.w;
+    }
+  }
+  __syncthreads();
+  LdsStore ls{sv};
+  GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
+  if (do_collide) {
+    if (fast) collide_cells(a, S, ls, s_owner, nc, c_lo, step);
+    else collide_cells(a, S, gs, a.owner + e_lo, nc, c_lo, step);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      const float o = __uint_as_float(S.obs[c]);
+      if (o > S.sgm[c]) a.sgmax[c_lo + c] = o;
+    }
+    if (threadIdx.x == 0) {
+      atomicAdd((unsigned long long*)&a.ctr->candidates, (unsigned long long)S.stat[0]);
+      atomicAdd((unsigned long long*)&a.ctr->accepted, (unsigned long long)S.stat[1]);
+      atomicAdd((unsigned long long*)&a.ctr->inelastic, (unsigned long long)S.stat[2]);
+      atomicAdd((unsigned long long*)&a.ctr->saturated, (unsigned long long)S.stat[3]);
+    }
+  }
+  if (fast) {
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+      const float4 v = sv[e];
+      const int d = e_lo + e;
+      a.B.vx[d] = v.x;
+      a.B.vy[d] = v.y;
+      a.B.vz[d] = v.z;
+      a.B.er[d] = v.w;
+    }
+  }
+  if (do_sample) {
+    __syncthreads();
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = w; c < nc; c += nw) {
+      const int b = S.start[c], N = S.start[c + 1] - b;
+      double s[17];
+      if (fast) wave_cell_sums(ls, b, N, s);
+      else wave_cell_sums(gs, b, N, s);
+      const int f = lane_id();
+      if (f < 17) a.acc[(int64_t)(c_lo + c) * 17 + f] += select17(s, f);
+    }
+  }
+}
+
+__global__ void k_step_end(dig_counters* c, int sample) {
+  c->step += 1;
+  if (sample) c->nsamp += 1;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_set_counters(dig_counters* c, int64_t n, int64_t step, int64_t next_id,
+                               int reset_all) {
+  c->n = n;
+  c->step = step;
+  c->next_id = next_id;
+  if (reset_all) {
+    c->nsamp = 0;
+    c->candidates = c->accepted = c->inelastic = c->saturated = c->wall_hits = 0;
+    c->err = 0;
+    c->cur = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation from fields [6][C].
+__global__ void k_init_count(StepArgs a, const double* fields, int32_t ppc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.ncell) return;
+  if (ppc > 0) {
+    a.count[c] = ppc;
+    return;
+  }
+  const InstParam& I = a.params[a.cell_inst[c]];
+  const uint4 r = draw(I, (uint32_t)(c - I.cell0), 0, TAG_INIT_N, 0);
+  a.count[c] = iround(count_mean(fields[c], I.vol, I.weight), r.x);
+}
+
+__global__ void k_init_fill(StepArgs a, const double* fields) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.ctr->n;
+  if (p >= n) return;
+  const int C = a.ncell;
+  const int c = floor_index(a.start, C + 1, (int32_t)p);
+  const int inst = a.cell_inst[c];
+  const InstParam& I = a.params[inst];
+  const uint32_t id = (uint32_t)(p - a.inst_pstart[inst]);
+  const int lc = c - I.cell0;
+  const int ix = lc % I.nx, iy = lc / I.nx;
+  const uint4 r0 = draw(I, id, 0, TAG_INIT, 0);
+  const uint4 r1 = draw(I, id, 0, TAG_INIT, 1);
+  const float st = sqrtf((float)fields[4 * C + c]);
+  float s0, c0, s1, c1;
+  const float ra = sqrtf(-2.0f * logf(u01f(r0.z)));
+  sincospif(2.0f * u01f(r0.w), &s0, &c0);
+  const float rb = sqrtf(-2.0f * logf(u01f(r1.x)));
+  sincospif(2.0f * u01f(r1.y), &s1, &c1);
+  a.A.x[p] = keep_inside((float)ix + u01f(r0.x), ix);
+  if (I.dim == 2) a.A.y[p] = keep_inside((float)iy + u01f(r0.y), iy);
+  a.A.vx[p] = (float)fields[1 * C + c] + st * (ra * c0);
+  a.A.vy[p] = (float)fields[2 * C + c] + st * (ra * s0);
+  a.A.vz[p] = (float)fields[3 * C + c] + st * (rb * c1);
+  a.A.er[p] = -(float)fields[5 * C + c] * logf(u01f(r1.z));
+  a.A.id[p] = id;
+}
+
+// ---------------------------------------------------------------------------
+// Instantaneous sums of the current state: one wave per cell.
+__global__ __launch_bounds__(256) void k_sample_state(StepArgs a) {
+  const int waves = (gridDim.x * blockDim.x) >> 6;
+  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  GlobalStore gs{a.A.vx, a.A.vy, a.A.vz, a.A.er};
+  for (int c = w0; c < a.ncell; c += waves) {
+    const int b = a.start[c], N = a.start[c + 1] - b;
+    double s[17];
+    wave_cell_sums(gs, b, N, s);
+    const int f = lane_id();
+    if (f < 17) a.sums[(int64_t)c * 17 + f] = select17(s, f);
+  }
+}
+
+// Raw sums -> sampled fields, equation DSMC_macroscopic.
+__global__ void k_convert(StepArgs a, const double* sums, int average, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const InstParam& I = a.params[a.cell_inst[c]];
+  const double ns = average ? (double)(a.ctr->nsamp > 0 ? a.ctr->nsamp : 1) : 1.0;
+  const double* s = sums + (int64_t)c * 17;
+  double o[20];
+  for (int f = 0; f < 20; ++f) o[f] = 0.0;
+  const double N = s[0];
+  if (N > 0.0) {
+    const double rho = I.weight * N / (I.vol * ns);
+    const double ux = s[1] / N, uy = s[2] / N, uz = s[3] / N;
+    const double mxx = s[4] / N, myy = s[5] / N, mzz = s[6] / N;
+    const double mxy = s[7] / N, mxz = s[8] / N, myz = s[9] / N;
+    const double cxx = mxx - ux * ux, cyy = myy - uy * uy, czz = mzz - uz * uz;
+    const double cxy = mxy - ux * uy, cxz = mxz - ux * uz, cyz = myz - uy * uz;
+    const double tr = cxx + cyy + czz;
+    const double Tt = tr / 3.0;
+    const double Tr = 2.0 * (s[13] / N) / I.dr;
+    const double rtr = mxx + myy + mzz;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double u[3] = {ux, uy, uz};
+    const double r2[3][3] = {{mxx, mxy, mxz}, {mxy, myy, myz}, {mxz, myz, mzz}};
+    o[0] = rho;
+    o[1] = ux;
+    o[2] = uy;
+    o[3] = uz;
+    o[4] = Tt;
+    o[5] = Tr;
+    o[6] = rho * (cxx - tr / 3.0);
+    o[7] = rho * (cyy - tr / 3.0);
+    o[8] = rho * (czz - tr / 3.0);
+    o[9] = rho * cxy;
+    o[10] = rho * cxz;
+    o[11] = rho * cyz;
+    for (int i = 0; i < 3; ++i) {
+      const double ru = r2[i][0] * ux + r2[i][1] * uy + r2[i][2] * uz;
+      const double c3 = s[10 + i] / N - 2.0 * ru - u[i] * rtr + 2.0 * u[i] * uu;
+      o[12 + i] = 0.5 * rho * c3;
+      o[15 + i] = rho * (s[14 + i] / N - u[i] * (s[13] / N));
+    }
+    o[18] = (3.0 * Tt + I.dr * Tr) / (3.0 + I.dr);
+    o[19] = N / ns;
+  }
+  for (int f = 0; f < 20; ++f) out[(int64_t)f * C + c] = o[f];
+}
+
+// ---------------------------------------------------------------------------
+// DIG particle modification.
+__global__ void k_adjust_count(StepArgs a, const double* target, uint32_t iter,
+                               int32_t* newcount, int32_t* ccount) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const InstParam& I = a.params[a.cell_inst[c]];
+  const double r = target[c], ux = target[C + c], uy = target[2 * C + c],
+               uz = target[3 * C + c], tt = target[4 * C + c], trr = target[5 * C + c];
+  const bool bad = !isfinite(r) || r < 0.0 || !isfinite(ux) || !isfinite(uy) ||
+                   !isfinite(uz) || !isfinite(tt) || !isfinite(trr) ||
+                   (r > 0.0 && (tt <= 0.0 || trr < 0.0));
+  if (bad) {
+    atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_TARGET);
+    newcount[c] = 0;
+    ccount[c] = 0;
+    return;
+  }
+  const uint4 w = draw(I, (uint32_t)(c - I.cell0), iter, TAG_DIG_N, 0);
+  const int nt = iround(count_mean(r, I.vol, I.weight), w.x);
+  const int N = a.start[c + 1] - a.start[c];
+  newcount[c] = nt;
+  ccount[c] = (N == 0) ? nt : (nt > N ? nt - N : 0);
+}
+
+__global__ __launch_bounds__(1024) void k_exscan(const int32_t* in, int32_t* out, int32_t n) {
+  __shared__ int64_t s_tot[1024];
+  const int tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
+  int64_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += in[c];
+  s_tot[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = (tid >= off) ? s_tot[tid - off] : 0;
+    __syncthreads();
+    s_tot[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = s_tot[tid] - sum;
+  for (int c = c0; c < c1; ++c) {
+    out[c] = (int32_t)run;
+    run += in[c];
+  }
+  if (tid == 0) out[n] = (int32_t)s_tot[1023];
+}
+
+struct Slot {
+  float x, y, vx, vy, vz, er;
+  uint32_t id;
+};
+
+// One wave per cell: deletion by partial Fisher-Yates, clones, then the
+// FP64 linear transform; writes the cell's new particles into buffer B.
+constexpr int kAdjLds = 2048;
+__global__ __launch_bounds__(256) void k_adjust_build(StepArgs a, const double* target,
+                                                      uint32_t iter, const int32_t* newstart,
+                                                      const int32_t* cstart) {
+  __shared__ uint32_t s_idx[4][kAdjLds];
+  __shared__ uint8_t s_del[4][kAdjLds];
+  const int wl = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int waves = (gridDim.x * blockDim.x) >> 6;
+  const int C = a.ncell;
+  const int64_t next_id = a.ctr->next_id;
+  for (int c = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; c < C; c += waves) {
+    const InstParam& I = a.params[a.cell_inst[c]];
+    const int b = a.start[c], N = a.start[c + 1] - b;
+    const int ob = newstart[c], Nt = newstart[c + 1] - ob;
+    const uint32_t ent = (uint32_t)(c - I.cell0);
+    const int lc = c - I.cell0, ix = lc % I.nx, iy = lc / I.nx;
+    const bool big = N > kAdjLds;
+    uint32_t* idx = big ? (uint32_t*)(a.perm_raw + b) : s_idx[wl];
+    uint8_t* del = big ? (uint8_t*)(a.rank + b) : s_del[wl];
+    int nsurv = N;
+    if (Nt < N) {
+      const int D = N - Nt;
+      for (int k = lane; k < N; k += 64) {
+        idx[k] = (uint32_t)k;
+        del[k] = 0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) {
+        uint4 w = make_uint4(0, 0, 0, 0);
+        for (int k = 0; k < D; ++k) {
+          if ((k & 3) == 0) w = draw(I, ent, iter, TAG_DIG_DEL, (uint32_t)(k >> 2));
+          const uint32_t r = (k & 3) == 0 ? w.x : (k & 3) == 1 ? w.y : (k & 3) == 2 ? w.z : w.w;
+          const int j = k + (int)pick(r, (uint32_t)(N - k));
+          const uint32_t t = idx[k];
+          idx[k] = idx[j];
+          idx[j] = t;
+        }
+        for (int k = 0; k < D; ++k) del[idx[k]] = 1;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      // compact survivors in slot order into idx
+      int base = 0;
+      for (int k0 = 0; k0 < N; k0 += 64) {
+        const int k = k0 + lane;
+        const bool keep = k < N && !del[k];
+        const unsigned long long m = __ballot(keep);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        if (keep) idx[base + __popcll(m & __lanemask_lt())] = (uint32_t)k;
+        base += __popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+      }
+      nsurv = Nt;
+    }
+    const double tux = target[C + c], tuy = target[2 * C + c], tuz = target[3 * C + c];
+    const double ttt = target[4 * C + c], ttr = target[5 * C + c];
+    auto load_slot = [&](int o) -> Slot {
+      Slot s;
+      if (o < nsurv) {
+        const int q = b + (Nt < N ? (int)idx[o] : o);
+        s.x = a.A.x[q];
+        s.y = I.dim == 2 ? a.A.y[q] : 0.0f;
+        s.vx = a.A.vx[q];
+        s.vy = a.A.vy[q];
+        s.vz = a.A.vz[q];
+        s.er = a.A.er[q];
+        s.id = a.A.id[q];
+      } else if (N > 0) {
+        const int k = o - N;
+        const uint4 w = draw(I, ent, iter, TAG_DIG_SRC, (uint32_t)k);
+        const int q = b + (int)pick(w.x, (uint32_t)N);
+        s.x = keep_inside((float)ix + u01f(w.y), ix);
+        s.y = I.dim == 2 ? keep_inside((float)iy + u01f(w.z), iy) : 0.0f;
+        s.vx = a.A.vx[q];
+        s.vy = a.A.vy[q];
+        s.vz = a.A.vz[q];
+        s.er = a.A.er[q];
+        s.id = (uint32_t)(next_id + cstart[c] + k);
+      } else {
+        const int k = o;
+        const uint4 r0 = draw(I, ent, iter, TAG_DIG_EMPTY, 2u * (uint32_t)k);
+        const uint4 r1 = draw(I, ent, iter, TAG_DIG_EMPTY, 2u * (uint32_t)k + 1u);
+        const double st = sqrt(ttt);
+        const double ra = sqrt(-2.0 * log(u01d(r0.z)));
+        const double rb = sqrt(-2.0 * log(u01d(r1.x)));
+        const double p0 = 2.0 * M_PI * u01d(r0.w), p1 = 2.0 * M_PI * u01d(r1.y);
+        s.x = keep_inside((float)ix + u01f(r0.x), ix);
+        s.y = I.dim == 2 ? keep_inside((float)iy + u01f(r0.y), iy) : 0.0f;
+        s.vx = (float)(tux + st * (ra * cos(p0)));
+        s.vy = (float)(tuy + st * (ra * sin(p0)));
+        s.vz = (float)(tuz + st * (rb * cos(p1)));
+        s.er = (float)(-ttr * log(u01d(r1.z)));
+        s.id = (uint32_t)(next_id + cstart[c] + k);
+      }
+      return s;
+    };
+    // temporary moments (two passes, FP64), step iii
+    double su[4] = {0, 0, 0, 0};
+    for (int o = lane; o < Nt; o += 64) {
+      const Slot s = load_slot(o);
+      su[0] += s.vx;
+      su[1] += s.vy;
+      su[2] += s.vz;
+      su[3] += s.er;
+    }
+    for (int off = 32; off > 0; off >>= 1)
+      for (int f = 0; f < 4; ++f) su[f] += __shfl_xor(su[f], off);
+    const double m = (double)Nt;
+    double us[3] = {0, 0, 0}, sc = 0.0;
+    if (Nt > 0) {
+      us[0] = su[0] / m;
+      us[1] = su[1] / m;
+      us[2] = su[2] / m;
+      for (int o = lane; o < Nt; o += 64) {
+        const Slot s = load_slot(o);
+        const double dx = s.vx - us[0], dy = s.vy - us[1], dz = s.vz - us[2];
+        sc += dx * dx + dy * dy + dz * dz;
+      }
+      for (int off = 32; off > 0; off >>= 1) sc += __shfl_xor(sc, off);
+    }
+    const double tts = Nt > 0 ? sc / (3.0 * m) : 0.0;
+    const double trs = Nt > 0 ? 2.0 * (su[3] / m) / I.dr : 0.0;
+    const double ca = (Nt >= 2 && tts > 0.0) ? sqrt(ttt / tts) : 1.0;
+    const double bx = tux - ca * us[0], by = tuy - ca * us[1], bz = tuz - ca * us[2];
+    const double cr = trs > 0.0 ? ttr / trs : 1.0;
+    // step iv: transform and write
+    for (int o = lane; o < Nt; o += 64) {
+      const Slot s = load_slot(o);
+      const int d = ob + o;
+      a.B.x[d] = s.x;
+      if (I.dim == 2) a.B.y[d] = s.y;
+      a.B.id[d] = s.id;
+      a.B.vx[d] = (float)(ca * (double)s.vx + bx);
+      a.B.vy[d] = (float)(ca * (double)s.vy + by);
+      a.B.vz[d] = (float)(ca * (double)s.vz + bz);
+      a.B.er[d] = (float)(cr * (double)s.er);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Closure assembly: NSF terms, HoT = DSMC - NSF, Kn_GLL and the adaptive mask.
+static __device__ double grad_axis(const InstParam& I, const double* f, int C, int base,
+                                   int ix, int iy, int axis) {
+  if (axis == 1 && I.dim == 1) return 0.0;
+  const int n = axis == 0 ? I.nx : I.ny;
+  if (n < 2) return 0.0;
+  const double h = axis == 0 ? I.dx : I.dy;
+  const int i = axis == 0 ? ix : iy;
+  auto at = [&](int k) {
+    return axis == 0 ? f[base + k + I.nx * iy] : f[base + ix + I.nx * k];
+  };
+  if (i > 0 && i < n - 1) return (at(i + 1) - at(i - 1)) / (2.0 * h);
+  if (I.bc_type[2 * axis] == DIG_BC_PERIODIC)
+    return (at((i + 1) % n) - at((i - 1 + n) % n)) / (2.0 * h);
+  if (i == 0) return (at(1) - at(0)) / h;
+  return (at(n - 1) - at(n - 2)) / h;
+}
+
+__global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, double Art,
+                          double Arr, double kn_ref, double* hot, uint8_t* mask, double* kngll,
+                          double* nsf, double* speed) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const InstParam& I = a.params[a.cell_inst[c]];
+  const int lc = c - I.cell0, ix = lc % I.nx, iy = lc / I.nx, base = I.cell0;
+  const double rho = F[c], tt = F[4 * C + c], tr = F[5 * C + c];
+  double h[12], q[12];
+  for (int f = 0; f < 12; ++f) h[f] = q[f] = 0.0;
+  double kn = INFINITY;
+  const bool ok = rho > 0.0 && tt > 0.0;
+  if (ok) {
+    const double* ux = F + C;
+    const double* uy = F + 2 * C;
+    const double* uz = F + 3 * C;
+    double d[7][2];
+    const double* arr[7] = {ux, uy, uz, F + 4 * C, F + 5 * C, F, speed};
+    for (int k = 0; k < 7; ++k)
+      for (int ax = 0; ax < 2; ++ax) d[k][ax] = grad_axis(I, arr[k], C, base, ix, iy, ax);
+    const double mu = I.mu0 * pow(tt, I.omega);
+    const double div = d[0][0] + d[1][1];
+    q[0] = -mu * (2.0 * d[0][0] - 2.0 / 3.0 * div);
+    q[1] = -mu * (2.0 * d[1][1] - 2.0 / 3.0 * div);
+    q[2] = -mu * (0.0 - 2.0 / 3.0 * div);
+    q[3] = -mu * (d[0][1] + d[1][0]);
+    q[4] = -mu * d[2][0];
+    q[5] = -mu * d[2][1];
+    const double det = Att * Arr - Atr * Art;
+    const double kt = 0.5 * mu * (Arr * 5.0 - Atr * I.dr) / det;
+    const double kr = 0.5 * mu * (-Art * 5.0 + Att * I.dr) / det;
+    q[6] = -kt * d[3][0];
+    q[7] = -kt * d[3][1];
+    q[9] = -kr * d[4][0];
+    q[10] = -kr * d[4][1];
+    for (int f = 0; f < 12; ++f) h[f] = F[(int64_t)(6 + f) * C + c] - q[f];
+    const double lam = mu / (rho * tt) * sqrt(M_PI * tt / 2.0);
+    const double gam = (5.0 + I.dr) / (3.0 + I.dr);
+    const double cs = sqrt(gam * tt);
+    const double us = speed[c];
+    double m = sqrt(d[5][0] * d[5][0] + d[5][1] * d[5][1]) / rho;
+    m = fmax(m, sqrt(d[6][0] * d[6][0] + d[6][1] * d[6][1]) / (us > cs ? us : cs));
+    m = fmax(m, sqrt(d[3][0] * d[3][0] + d[3][1] * d[3][1]) / tt);
+    if (tr > 0.0) m = fmax(m, sqrt(d[4][0] * d[4][0] + d[4][1] * d[4][1]) / tr);
+    kn = lam * m;
+  }
+  const uint8_t eq = kn < kn_ref ? 1 : 0;
+  for (int f = 0; f < 12; ++f) {
+    hot[(int64_t)f * C + c] = (eq || !ok) ? 0.0 : h[f];
+    if (nsf) nsf[(int64_t)f * C + c] = q[f];
+  }
+  mask[c] = eq;
+  kngll[c] = kn;
+}
+
+__global__ void k_speed(const double* F, int C, double* speed) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const double ux = F[C + c], uy = F[2 * C + c], uz = F[3 * C + c];
+  speed[c] = sqrt(ux * ux + uy * uy + uz * uz);
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers.
+static inline int blocks_for(int64_t n, int bs) {
+  int64_t b = (n + bs - 1) / bs;
+  return (int)(b < 1 ? 1 : b);
+}
+
+int64_t group_launch(const StepArgs& a) {
+  return a.n_upper / a.group_particles + a.ncell / a.group_cells + 2;
+}
+
+size_t collide_lds_bytes(int lds_particles, int group_cells) {
+  return sizeof(float4) * lds_particles + sizeof(uint32_t) * lds_particles +
+         sizeof(int) * 2 * (group_cells + 1) + (sizeof(float) + 2 * sizeof(int)) * group_cells +
+         (5 * sizeof(int) + 1) * kCandChunk + sizeof(int) * 12 + 16;
+}
+
+hipError_t launch_move(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_move, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a, counts, (int32_t)group_launch(a),
+                     set_n ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_place(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_place, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStream_t s) {
+  const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
+  hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(256), lds, s, a,
+                     collide ? 1 : 0, sample ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_end(const StepArgs& a, bool sample, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, a.ctr, sample ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p,
+                     n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<float>, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p, n,
+                     v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<double>, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, s, p,
+                     n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_counters(dig_counters* c, int64_t n, int64_t step, int64_t next_id,
+                               bool reset_all, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counters, dim3(1), dim3(1), 0, s, c, n, step, next_id,
+                     reset_all ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const StepArgs& a, const double* fields, int32_t ppc, hipStream_t s,
+                       int phase) {
+  if (phase == 0)
+    hipLaunchKernelGGL(k_init_count, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, fields,
+                       ppc);
+  else
+    hipLaunchKernelGGL(k_init_fill, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a,
+                       fields);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_state(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_state, dim3(min(blocks_for((int64_t)a.ncell * 64, 256), 8192)),
+                     dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const StepArgs& a, const double* sums, bool average, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_convert, dim3(blocks_for(a.ncell, 128)), dim3(128), 0, s, a, sums,
+                     average ? 1 : 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjust_count(const StepArgs& a, const double* target, uint32_t iter,
+                               int32_t* newcount, int32_t* ccount, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjust_count, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, target,
+                     iter, newcount, ccount);
+  return hipGetLastError();
+}
+
+hipError_t launch_exscan(const int32_t* in, int32_t* out, int32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_exscan, dim3(1), dim3(1024), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjust_build(const StepArgs& a, const double* target, uint32_t iter,
+                               const int32_t* newstart, const int32_t* cstart, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjust_build, dim3(min(blocks_for((int64_t)a.ncell * 64, 256), 4096)),
+                     dim3(256), 0, s, a, target, iter, newstart, cstart);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure(const StepArgs& a, const double* fields, double Att, double Atr,
+                          double Art, double Arr, double kn_ref, double* hot, uint8_t* mask,
+                          double* kngll, double* nsf, hipStream_t s) {
+  // speed of each cell, staged in the sums scratch (C doubles)
+  hipLaunchKernelGGL(k_speed, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, fields, a.ncell,
+                     a.sums);
+  hipLaunchKernelGGL(k_closure, dim3(blocks_for(a.ncell, 128)), dim3(128), 0, s, a, fields, Att,
+                     Atr, Art, Arr, kn_ref, hot, mask, kngll, nsf, a.sums);
+  return hipGetLastError();
+}
+
+}  // namespace dig
