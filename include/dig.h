@@ -121,7 +121,8 @@ dig_status dig_plan(const dig_config* cfgs_host, int32_t n_inst, int64_t capacit
  * layout.total_bytes bytes (256-byte aligned).  Zeroes counters, counts and
  * accumulators and sets every cell's majorant; enqueued on `stream`.
  * group_particles / group_cells: cell-group size used by the sort and collide
- * kernels (0 = defaults 1024 / 256).  Errors: DIG_ERR_INVALID, DIG_ERR_HIP. */
+ * kernels (0 = defaults 1024 / 64; ranges [256, 16384] / [32, 256]); results
+ * do not depend on them.  Errors: DIG_ERR_INVALID, DIG_ERR_HIP. */
 dig_status dsmc_create(const dig_config* cfgs_host, int32_t n_inst, int64_t capacity,
                        void* workspace_dev, size_t workspace_bytes, int32_t group_particles,
                        int32_t group_cells, dig_stream_t stream, dig_ctx** out);
@@ -185,6 +186,15 @@ dig_status dsmc_query(dig_ctx* ctx, dig_counters* out_host, dig_stream_t stream)
  * out[0] = C (sigma_T g = C g^(2-2 omega)), out[1] = P_inelastic,
  * out[2] = mu0, out[3] = cell volume, out[4] = default majorant. */
 dig_status dig_constants(dig_ctx* ctx, int32_t inst, double* out_host5);
+
+/* Per-kernel timing with HIP events recorded on `stream` immediately before
+ * and after every launch of the step and adjust kernels.  mode 1: enable and
+ * reset; mode 0: disable; mode 2: synchronise and read the totals into
+ * ms_host[DIG_NKERNELS] (milliseconds) and launches_host[DIG_NKERNELS]. */
+enum { DIG_K_MOVE = 0, DIG_K_SCAN = 1, DIG_K_PLACE = 2, DIG_K_ORDER = 3, DIG_K_COLLIDE = 4,
+       DIG_K_ADJUST = 5, DIG_K_SAMPLE = 6, DIG_K_CLOSURE = 7, DIG_NKERNELS = 8 };
+dig_status dsmc_profile(dig_ctx* ctx, int32_t mode, double* ms_host, int64_t* launches_host,
+                        dig_stream_t stream);
 
 const char* dig_last_error(void);
 void dsmc_destroy(dig_ctx* ctx);

@@ -50,7 +50,8 @@ class DigCounters(C.Structure):
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
            "dsmc_sample", "dig_adjust", "closure_assemble", "dsmc_query", "dig_constants",
-           "dig_last_error", "dsmc_destroy"]
+           "dsmc_profile", "dig_last_error", "dsmc_destroy"]
+KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
 _lib = None
 
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
                                    vp]
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
+    L.dsmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
     L.dig_last_error.restype = C.c_char_p
     L.dsmc_destroy.argtypes = [vp]
     L.dsmc_destroy.restype = None

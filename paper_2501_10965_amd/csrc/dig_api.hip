@@ -1,5 +1,6 @@
 // Host side of libdig: validation, workspace layout, launches, errors.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -33,7 +34,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
-  size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart;
+  size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
+      stats;
   int64_t gfirst_len;
 };
 
@@ -145,6 +147,9 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, dig_layout* L, Internal
   I->ccount = take(4 * C);
   I->newstart = take(4 * (C + 1));
   I->cstart = take(4 * (C + 1));
+  I->bsum = take(8 * (scan_blocks((int)C) + 1));
+  I->lastcnt = take(4 * (scan_blocks((int)C) + 1));
+  I->stats = take(sizeof(unsigned long long) * kStatSlots * ST_N);
   L->total_bytes = o;
 }
 
@@ -197,9 +202,17 @@ struct dig_ctx {
   int32_t n_inst = 0, ncell = 0, dim = 1;
   int64_t capacity = 0, n_host = 0;
   int cur = 0;
-  int32_t T = 1024, Gc = 256, Lp = 2048;
+  int32_t T = 1024, Gc = 64, Lp = 1536;
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
+  int32_t seq_max = kSeqMaxDefault;
+  // event profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;      // pairs (start, stop)
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  double prof_ms[DIG_NKERNELS] = {0};
+  int64_t prof_n[DIG_NKERNELS] = {0};
 };
 
 namespace {
@@ -228,6 +241,9 @@ StepArgs args(const dig_ctx* c) {
   a.acc = (double*)(w + L.acc);
   a.sums = (double*)(w + L.sums);
   a.inst_pstart = (int64_t*)(w + c->I.inst_pstart);
+  a.bsum = (int64_t*)(w + c->I.bsum);
+  a.lastcnt = (int32_t*)(w + c->I.lastcnt);
+  a.stats = (unsigned long long*)(w + c->I.stats);
   a.owner = (uint32_t*)(w + c->I.owner);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);
@@ -237,8 +253,42 @@ StepArgs args(const dig_ctx* c) {
   a.group_particles = c->T;
   a.group_cells = c->Gc;
   a.lds_particles = c->Lp;
+  a.seq_max = c->seq_max;
   a.n_upper = c->n_host;
   return a;
+}
+
+// Folds the recorded event pairs into the per-kernel totals.
+hipError_t prof_fold(dig_ctx* c, hipStream_t s) {
+  if (c->ev_used == 0) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    c->prof_ms[c->ev_kind[k]] += ms;
+    c->prof_n[c->ev_kind[k]] += 1;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+// Runs one launch, bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(dig_ctx* c, int kind, hipStream_t s, F&& launch) {
+  if (!c->prof) return launch();
+  if (c->ev_used == c->ev_kind.size()) {
+    hipError_t e = prof_fold(c, s);
+    if (e != hipSuccess) return e;
+  }
+  const size_t k = c->ev_used++;
+  c->ev_kind[k] = kind;
+  hipError_t e = hipEventRecord(c->ev[2 * k], s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(c->ev[2 * k + 1], s);
 }
 
 __global__ void k_counts_from_start(const int32_t* start, int32_t* counts, int C) {
@@ -261,19 +311,19 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
   StepArgs a = args(c);
   if (mask & DIG_STAGE_MOVE) {
     if (c->phase != 0) return fail(DIG_ERR_STATE, "move needs a completed previous step");
-    HIP_TRY(launch_move(a, s));
+    HIP_TRY(timed(c, DIG_K_MOVE, s, [&] { return launch_move(a, s); }));
     c->phase = 1;
   }
   if (mask & DIG_STAGE_SORT) {
     if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
-    HIP_TRY(launch_scan(a, a.count, true, s));
-    HIP_TRY(launch_place(a, s));
-    HIP_TRY(launch_order(a, s));
+    HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, true, s); }));
+    HIP_TRY(timed(c, DIG_K_PLACE, s, [&] { return launch_place(a, s); }));
+    HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
     c->phase = 2;
   }
   if (mask & DIG_STAGE_COLLIDE) {
     if (c->phase != 2) return fail(DIG_ERR_STATE, "collide needs the sort stage first");
-    HIP_TRY(launch_collide(a, true, true, s));
+    HIP_TRY(timed(c, DIG_K_COLLIDE, s, [&] { return launch_collide(a, true, true, s); }));
     HIP_TRY(launch_step_end(a, true, s));
     c->cur ^= 1;
     c->phase = 0;
@@ -307,12 +357,13 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   if (st != DIG_OK) return st;
   if (!ws) return fail(DIG_ERR_INVALID, "null workspace");
   if (((uintptr_t)ws) % kAlign) return fail(DIG_ERR_INVALID, "workspace not 256-byte aligned");
+  const char* sm = getenv("DIG_SEQ_MAX");  // collision path threshold (tuning aid)
   const int32_t T = group_particles > 0 ? group_particles : 1024;
-  const int32_t Gc = group_cells > 0 ? group_cells : 256;
+  const int32_t Gc = group_cells > 0 ? group_cells : 64;
   if (T < kMinGroupParticles || T > 16384)
     return fail(DIG_ERR_INVALID, "group_particles must lie in [256, 16384]");
-  if (Gc < kMinGroupCells || Gc > 1024)
-    return fail(DIG_ERR_INVALID, "group_cells must lie in [32, 1024]");
+  if (Gc < kMinGroupCells || Gc > 256)
+    return fail(DIG_ERR_INVALID, "group_cells must lie in [32, 256]");
   dig_ctx* c = new dig_ctx;
   c->cfg.assign(cfgs, cfgs + n_inst);
   c->n_inst = n_inst;
@@ -322,9 +373,11 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->n_host = capacity;
   c->T = T;
   c->Gc = Gc;
-  // LDS particle stage: twice the group target, within 64 KiB of LDS
-  int32_t Lp = 2 * T;
-  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 64 * 1024) Lp -= 256;
+  if (sm) c->seq_max = atoi(sm);
+  // LDS particle stage: the group target plus room for its last cell, within
+  // 48 KiB of LDS; larger groups collide in the destination buffer instead
+  int32_t Lp = T + 512;
+  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
   c->Lp = Lp;
   plan_layout(capacity, C, n_inst, &c->L, &c->I);
   if (ws_bytes < c->L.total_bytes) {
@@ -352,6 +405,8 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
     e = launch_fill_f32(a.sgmax + c->params[i].cell0, c->params[i].ncell,
                         (float)default_majorant(cfgs[i]), s);
   if (e == hipSuccess) e = launch_set_counters(a.ctr, 0, 0, 0, true, s);
+  if (e == hipSuccess)
+    e = launch_fill_f64((double*)a.stats, (int64_t)kStatSlots * ST_N, 0.0, s);
   // the host copies above read host vectors owned by the context: wait for them
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -372,6 +427,7 @@ dig_status dsmc_init(dig_ctx* c, const double* fields, int32_t ppc, dig_stream_t
   c->n_host = c->capacity;
   StepArgs a = args(c);
   HIP_TRY(launch_set_counters(a.ctr, 0, 0, 0, true, s));
+  HIP_TRY(launch_fill_f64((double*)a.stats, (int64_t)kStatSlots * ST_N, 0.0, s));
   HIP_TRY(launch_init(a, fields, ppc, s, 0));
   HIP_TRY(launch_scan(a, a.count, true, s));
   int32_t total = 0;
@@ -440,7 +496,7 @@ dig_status dsmc_sample(dig_ctx* c, int32_t mode, double* out, dig_stream_t strea
   if (!out) return fail(DIG_ERR_INVALID, "null output");
   if (mode == DIG_SAMPLE_INSTANT) {
     if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
-    HIP_TRY(launch_sample_state(a, s));
+    HIP_TRY(timed(c, DIG_K_SAMPLE, s, [&] { return launch_sample_state(a, s); }));
     HIP_TRY(launch_convert(a, a.sums, false, out, s));
     return DIG_OK;
   }
@@ -482,7 +538,8 @@ dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_strea
   if (tot[0] > c->capacity)
     return fail(DIG_ERR_CAPACITY, "dig_adjust: " + std::to_string(tot[0]) +
                                       " particles exceed the capacity");
-  HIP_TRY(launch_adjust_build(a, target, iter, newstart, cstart, s));
+  HIP_TRY(timed(c, DIG_K_ADJUST, s,
+                [&] { return launch_adjust_build(a, target, iter, newstart, cstart, s); }));
   c->cur ^= 1;
   c->n_host = tot[0] > 0 ? tot[0] : 1;
   a = args(c);
@@ -501,8 +558,10 @@ dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, d
   const double det = A[0] * A[3] - A[1] * A[2];
   if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
   StepArgs a = args(c);
-  HIP_TRY(launch_closure(a, fields, A[0], A[1], A[2], A[3], kn_ref, hot, mask, kngll, nsf,
-                         (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(timed(c, DIG_K_CLOSURE, s, [&] {
+    return launch_closure(a, fields, A[0], A[1], A[2], A[3], kn_ref, hot, mask, kngll, nsf, s);
+  }));
   return DIG_OK;
 }
 
@@ -511,9 +570,19 @@ dig_status dsmc_query(dig_ctx* c, dig_counters* out, dig_stream_t stream) {
   if (!out) return fail(DIG_ERR_INVALID, "null output");
   hipStream_t s = (hipStream_t)stream;
   StepArgs a = args(c);
+  unsigned long long slots[kStatSlots * ST_N];
   HIP_TRY(hipMemcpyAsync(out, a.ctr, sizeof(dig_counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(slots, a.stats, sizeof(slots), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   out->cur = (uint32_t)c->cur;
+  int64_t sum[ST_N] = {0};
+  for (int k = 0; k < kStatSlots; ++k)
+    for (int f = 0; f < ST_N; ++f) sum[f] += (int64_t)slots[k * ST_N + f];
+  out->candidates = sum[ST_CAND];
+  out->accepted = sum[ST_ACC];
+  out->inelastic = sum[ST_INEL];
+  out->saturated = sum[ST_SAT];
+  out->wall_hits = sum[ST_HITS];
   return DIG_OK;
 }
 
@@ -529,6 +598,46 @@ dig_status dig_constants(dig_ctx* c, int32_t inst, double* out) {
   return DIG_OK;
 }
 
-void dsmc_destroy(dig_ctx* c) { delete c; }
+dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
+                        dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  if (mode == 1) {
+    if (c->ev.empty()) {
+      const size_t pairs = 4096;
+      c->ev.resize(2 * pairs);
+      c->ev_kind.resize(pairs);
+      for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    c->ev_used = 0;
+    for (int k = 0; k < DIG_NKERNELS; ++k) {
+      c->prof_ms[k] = 0.0;
+      c->prof_n[k] = 0;
+    }
+    c->prof = true;
+    return DIG_OK;
+  }
+  if (mode == 0) {
+    HIP_TRY(prof_fold(c, s));
+    c->prof = false;
+    return DIG_OK;
+  }
+  if (mode == 2) {
+    if (!ms || !launches) return fail(DIG_ERR_INVALID, "null output");
+    HIP_TRY(prof_fold(c, s));
+    for (int k = 0; k < DIG_NKERNELS; ++k) {
+      ms[k] = c->prof_ms[k];
+      launches[k] = c->prof_n[k];
+    }
+    return DIG_OK;
+  }
+  return fail(DIG_ERR_INVALID, "bad profile mode");
+}
+
+void dsmc_destroy(dig_ctx* c) {
+  if (!c) return;
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
 
 }  // extern "C"

@@ -16,8 +16,14 @@ enum : uint32_t {
 
 constexpr int kMaxHits = 8;      // wall events per particle and step
 constexpr int kRunMax = 4096;    // run table of the sort kernel
-constexpr int kCandChunk = 512;  // candidates staged per round set
+constexpr int kCandChunk = 256;  // candidates staged per round set
+constexpr int kSeqMaxDefault = 192;  // cells up to this size: one lane, candidates in order
 constexpr int kMinGroupParticles = 256;
+// Statistics counters are spread over kStatSlots cache lines (slot = block
+// index mod kStatSlots) so that thousands of workgroups do not serialise on
+// one address; dsmc_query sums the slots.
+constexpr int kStatSlots = 64;
+enum { ST_CAND = 0, ST_ACC = 1, ST_INEL = 2, ST_SAT = 3, ST_HITS = 4, ST_N = 8 };
 constexpr int kMinGroupCells = 32;
 
 // Per-instance constants, resident in the workspace.
@@ -44,8 +50,11 @@ __device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32 -> 64-bit product per multiplier gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
@@ -78,15 +87,20 @@ struct StepArgs {
   float* sgmax;
   double *acc, *sums;
   int64_t* inst_pstart;
+  int64_t* bsum;       // chunk sums of the cell scan
+  int32_t* lastcnt;    // last count of each scan chunk
   uint32_t* owner;
+  unsigned long long* stats;  // [kStatSlots][ST_N]
   const InstParam* params;
   dig_counters* ctr;
   int32_t n_inst, ncell, dim;
   int32_t group_particles, group_cells, lds_particles;
+  int32_t seq_max;  // cells with at most this many particles collide on one lane
   int64_t n_upper;
 };
 
 int64_t group_launch(const StepArgs& a);
+int scan_blocks(int ncell);
 size_t collide_lds_bytes(int lds_particles, int group_cells);
 hipError_t launch_move(const StepArgs& a, hipStream_t s);
 hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s);

@@ -55,6 +55,17 @@ static __device__ __forceinline__ int iround(double x, uint32_t r) {
   return (int)f + ((u01d(r) < x - f) ? 1 : 0);
 }
 
+// Hardware transcendentals (about 1 ulp): x^e for x > 0, natural log, square
+// root and reciprocal.
+static __device__ __forceinline__ float fpow(float x, float e) {
+  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x));
+}
+static __device__ __forceinline__ float flog(float x) {
+  return 0.69314718055994531f * __builtin_amdgcn_logf(x);
+}
+static __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+static __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
   // position ix + u rounded to float must stay below the upper cell face
   const float top = (float)(cellidx + 1);
@@ -62,7 +73,109 @@ static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
 }
 
 // ---------------------------------------------------------------------------
-// Free flight with diffuse / specular walls, then cell index and reservation.
+// Free flight with diffuse / specular walls for one particle; returns its cell.
+static __device__ __forceinline__ int move_particle(const StepArgs& a, const InstParam& P,
+                                                    int64_t p, uint32_t step, int* hits) {
+  const bool two = P.dim == 2;
+  float x = a.A.x[p];
+  float y = two ? a.A.y[p] : 0.0f;
+  float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
+  float t = P.dtf;
+  int hit = 0;
+  bool er_set = false;
+  float er = 0.0f;
+  for (;;) {
+    const float sx = vx * P.inv_dx;
+    const float sy = two ? vy * P.inv_dy : 0.0f;
+    int face = -1;
+    float th = t;
+    const float xe = x + sx * t;
+    const bool w0 = P.bc_type[0] != DIG_BC_PERIODIC, w1 = P.bc_type[1] != DIG_BC_PERIODIC;
+    if (xe < 0.0f && w0) {
+      const float tf = (0.0f - x) / sx;
+      if (tf <= th) { th = tf; face = 0; }
+    } else if (xe > P.gx && w1) {
+      const float tf = (P.gx - x) / sx;
+      if (tf <= th) { th = tf; face = 1; }
+    }
+    if (two) {
+      const float ye = y + sy * t;
+      const bool w2 = P.bc_type[2] != DIG_BC_PERIODIC, w3 = P.bc_type[3] != DIG_BC_PERIODIC;
+      if (ye < 0.0f && w2) {
+        const float tf = (0.0f - y) / sy;
+        if (face < 0 ? tf <= th : tf < th) { th = tf; face = 2; }
+      } else if (ye > P.gy && w3) {
+        const float tf = (P.gy - y) / sy;
+        if (face < 0 ? tf <= th : tf < th) { th = tf; face = 3; }
+      }
+    }
+    if (face < 0 || hit >= kMaxHits) {
+      x += sx * t;
+      if (two) y += sy * t;
+      if (hit >= kMaxHits) {
+        if (w0 && x < 0.0f) x = 0.0f;
+        if (w1 && x > P.gx) x = P.gx;
+        if (two) {
+          if (P.bc_type[2] != DIG_BC_PERIODIC && y < 0.0f) y = 0.0f;
+          if (P.bc_type[3] != DIG_BC_PERIODIC && y > P.gy) y = P.gy;
+        }
+      }
+      break;
+    }
+    x += sx * th;
+    if (two) y += sy * th;
+    if (face == 0) x = 0.0f;
+    if (face == 1) x = P.gx;
+    if (face == 2) y = 0.0f;
+    if (face == 3) y = P.gy;
+    t -= th;
+    const int axis = face >> 1;
+    const float inward = (face & 1) ? -1.0f : 1.0f;
+    if (P.bc_type[face] == DIG_BC_SPECULAR) {
+      if (axis == 0) vx = -vx; else vy = -vy;
+    } else {
+      const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
+      const float T = P.bc_T[face];
+      const float vn = fsqrt(-2.0f * T * flog(u01f(w.x)));
+      const float r = fsqrt(-2.0f * flog(u01f(w.y)));
+      const float ph = 6.28318530717958648f * u01f(w.z);
+      const float sn = __sinf(ph), cs = __cosf(ph);
+      const float sT = fsqrt(T);
+      if (axis == 0) {
+        vx = inward * vn;
+        vy = P.bc_U[face][1] + sT * (r * cs);
+      } else {
+        vy = inward * vn;
+        vx = P.bc_U[face][0] + sT * (r * cs);
+      }
+      vz = P.bc_U[face][2] + sT * (r * sn);
+      er = -T * flog(u01f(w.w));
+      er_set = true;
+    }
+    ++hit;
+  }
+  if (P.bc_type[0] == DIG_BC_PERIODIC) x -= P.gx * floorf(x / P.gx);
+  if (two && P.bc_type[2] == DIG_BC_PERIODIC) y -= P.gy * floorf(y / P.gy);
+  a.A.x[p] = x;
+  if (two) a.A.y[p] = y;
+  if (hit) {
+    a.A.vx[p] = vx;
+    a.A.vy[p] = vy;
+    a.A.vz[p] = vz;
+    if (er_set) a.A.er[p] = er;  // diffuse re-emission draws er; specular keeps it
+  }
+  *hits = hit;
+  int ix = (int)floorf(x);
+  ix = ix < 0 ? 0 : (ix > P.nx - 1 ? P.nx - 1 : ix);
+  int iy = 0;
+  if (two) {
+    iy = (int)floorf(y);
+    iy = iy < 0 ? 0 : (iy > P.ny - 1 ? P.ny - 1 : iy);
+  }
+  return P.cell0 + ix + P.nx * iy;
+}
+
+// Free flight, cell index and reservation of a slot in the destination cell.
 __global__ __launch_bounds__(256) void k_move(StepArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = a.ctr->n;
@@ -70,175 +183,146 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
   const bool valid = p < n;
   int cell = 0;
   int hits_here = 0;
-  if (valid) {
-    const int inst = find_inst(a.inst_pstart, a.n_inst, p);
-    const InstParam& P = a.params[inst];
-    const bool two = P.dim == 2;
-    float x = a.A.x[p];
-    float y = two ? a.A.y[p] : 0.0f;
-    float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
-    float t = P.dtf;
-    int hit = 0;
-    bool wall_hit = false, er_set = false;
-    float er = 0.0f;
-    for (;;) {
-      const float sx = vx * P.inv_dx;
-      const float sy = two ? vy * P.inv_dy : 0.0f;
-      int face = -1;
-      float th = t;
-      const float xe = x + sx * t;
-      const bool w0 = P.bc_type[0] != DIG_BC_PERIODIC, w1 = P.bc_type[1] != DIG_BC_PERIODIC;
-      if (xe < 0.0f && w0) {
-        float tf = (0.0f - x) / sx;
-        if (tf <= th) { th = tf; face = 0; }
-      } else if (xe > P.gx && w1) {
-        float tf = (P.gx - x) / sx;
-        if (tf <= th) { th = tf; face = 1; }
-      }
-      if (two) {
-        const float ye = y + sy * t;
-        const bool w2 = P.bc_type[2] != DIG_BC_PERIODIC, w3 = P.bc_type[3] != DIG_BC_PERIODIC;
-        if (ye < 0.0f && w2) {
-          float tf = (0.0f - y) / sy;
-          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 2; }
-        } else if (ye > P.gy && w3) {
-          float tf = (P.gy - y) / sy;
-          if (face < 0 ? tf <= th : tf < th) { th = tf; face = 3; }
-        }
-      }
-      if (face < 0 || hit >= kMaxHits) {
-        x += sx * t;
-        if (two) y += sy * t;
-        if (hit >= kMaxHits) {
-          if (P.bc_type[0] != DIG_BC_PERIODIC && x < 0.0f) x = 0.0f;
-          if (P.bc_type[1] != DIG_BC_PERIODIC && x > P.gx) x = P.gx;
-          if (two) {
-            if (P.bc_type[2] != DIG_BC_PERIODIC && y < 0.0f) y = 0.0f;
-            if (P.bc_type[3] != DIG_BC_PERIODIC && y > P.gy) y = P.gy;
-          }
-        }
-        break;
-      }
-      x += sx * th;
-      if (two) y += sy * th;
-      if (face == 0) x = 0.0f;
-      if (face == 1) x = P.gx;
-      if (face == 2) y = 0.0f;
-      if (face == 3) y = P.gy;
-      t -= th;
-      const int axis = face >> 1;
-      const float inward = (face & 1) ? -1.0f : 1.0f;
-      if (P.bc_type[face] == DIG_BC_SPECULAR) {
-        if (axis == 0) vx = -vx; else vy = -vy;
-      } else {
-        const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
-        const float T = P.bc_T[face];
-        const float vn = sqrtf(-2.0f * T * logf(u01f(w.x)));
-        const float r = sqrtf(-2.0f * logf(u01f(w.y)));
-        float sn, cs;
-        sincospif(2.0f * u01f(w.z), &sn, &cs);
-        const float s = sqrtf(T);
-        if (axis == 0) {
-          vx = inward * vn;
-          vy = P.bc_U[face][1] + s * (r * cs);
-        } else {
-          vy = inward * vn;
-          vx = P.bc_U[face][0] + s * (r * cs);
-        }
-        vz = P.bc_U[face][2] + s * (r * sn);
-        er = -T * logf(u01f(w.w));
-        er_set = true;
-      }
-      wall_hit = true;
-      ++hit;
-    }
-    if (P.bc_type[0] == DIG_BC_PERIODIC) x -= P.gx * floorf(x / P.gx);
-    if (two && P.bc_type[2] == DIG_BC_PERIODIC) y -= P.gy * floorf(y / P.gy);
-    a.A.x[p] = x;
-    if (two) a.A.y[p] = y;
-    if (wall_hit) {
-      a.A.vx[p] = vx;
-      a.A.vy[p] = vy;
-      a.A.vz[p] = vz;
-      if (er_set) a.A.er[p] = er;  // diffuse re-emission draws er; specular keeps it
-    }
-    hits_here = hit;
-    int ix = (int)floorf(x);
-    ix = ix < 0 ? 0 : (ix > P.nx - 1 ? P.nx - 1 : ix);
-    int iy = 0;
-    if (two) {
-      iy = (int)floorf(y);
-      iy = iy < 0 ? 0 : (iy > P.ny - 1 ? P.ny - 1 : iy);
-    }
-    cell = P.cell0 + ix + P.nx * iy;
+  const int inst = valid ? find_inst(a.inst_pstart, a.n_inst, p) : 0;
+  const int iu = __builtin_amdgcn_readfirstlane(inst);
+  if (__all(!valid || inst == iu)) {
+    if (valid) cell = move_particle(a, a.params[iu], p, step, &hits_here);
+  } else if (valid) {
+    cell = move_particle(a, a.params[inst], p, step, &hits_here);
   }
   // wave-aggregated reservation: one atomic per (wave, destination cell); the
   // lanes of a run get consecutive ranks in lane (= slot) order
+  // The runs are found with ballots (no memory traffic); then every run
+  // leader reserves its run with the same atomic instruction.
   unsigned long long todo = __ballot(valid);
-  int rank = 0;
+  int my_leader = 0, in_run = 0, run_len = 0;
   while (todo) {
     const int leader = __ffsll(todo) - 1;
     const int lc = __shfl(cell, leader);
     const unsigned long long m = __ballot(valid && cell == lc);
-    int base = 0;
-    if (lane_id() == leader) base = atomicAdd(&a.count[lc], __popcll(m));
-    base = __shfl(base, leader);
-    if (valid && cell == lc) rank = base + __popcll(m & __lanemask_lt());
+    if (valid && cell == lc) {
+      my_leader = leader;
+      in_run = __popcll(m & __lanemask_lt());
+    }
+    if (lane_id() == leader) run_len = __popcll(m);
     todo &= ~m;
   }
+  int base = 0;
+  if (run_len > 0) base = atomicAdd(&a.count[cell], run_len);
+  base = __shfl(base, my_leader);
   if (valid) {
     a.cell[p] = cell;
-    a.rank[p] = rank;
+    a.rank[p] = base + in_run;
   }
-  // wall-hit statistics: one atomic per wave
+  // wall-hit statistics: one atomic per wave into a spread slot
   int hsum = hits_here;
   for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
-  if (lane_id() == 0 && hsum) atomicAdd((unsigned long long*)&a.ctr->wall_hits,
-                                        (unsigned long long)hsum);
+  if (lane_id() == 0 && hsum)
+    atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_HITS], (unsigned long long)hsum);
 }
 
 // ---------------------------------------------------------------------------
-// Single-workgroup scan of cell counts; also cell groups and instance ranges.
-__global__ __launch_bounds__(1024) void k_scan(StepArgs a, int32_t* counts, int32_t glaunch,
-                                               int set_n) {
-  __shared__ int64_t s_tot[1024];
-  const int tid = threadIdx.x;
+// Cell counts -> cell starts in two passes over chunks of kScanChunk cells:
+// chunk sums, then per-chunk exclusive scans offset by the preceding chunks.
+// The second pass also zeroes the counts, writes the cell-group table (group
+// key = floor(start/T) + floor(c/Gc)), the instance particle ranges and n.
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = 256 * kScanPer;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(StepArgs a, const int32_t* counts) {
+  __shared__ int s_w[4];
   const int C = a.ncell;
-  const int per = (C + 1023) / 1024;
-  const int c0 = min(C, tid * per), c1 = min(C, c0 + per);
-  int64_t sum = 0;
-  for (int c = c0; c < c1; ++c) sum += counts[c];
-  s_tot[tid] = sum;
+  const int c0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k)
+    if (c0 + k < C) sum += counts[c0 + k];
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = (tid >= off) ? s_tot[tid - off] : 0;
-    __syncthreads();
-    s_tot[tid] += v;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    a.bsum[blockIdx.x] = (int64_t)s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    const int last = min(C, (int)(blockIdx.x + 1) * kScanChunk) - 1;
+    a.lastcnt[blockIdx.x] = counts[last];
   }
-  int64_t run = s_tot[tid] - sum;
-  for (int c = c0; c < c1; ++c) {
-    a.start[c] = (int32_t)run;
-    run += counts[c];
-    counts[c] = 0;
-  }
-  if (tid == 0) a.start[C] = (int32_t)s_tot[1023];
-  __threadfence_block();
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(StepArgs a, int32_t* counts, int32_t glaunch,
+                                                    int set_n) {
+  __shared__ int64_t s_off;
+  __shared__ int s_w[4];
+  __shared__ int s_last[256];
+  const int C = a.ncell;
+  const int b = blockIdx.x;
+  const int nb = gridDim.x;
+  const int tid = threadIdx.x;
+  // offset of this chunk: sum of the preceding chunk sums
+  int64_t o = 0;
+  for (int k = tid; k < b; k += 256) o += a.bsum[k];
+  for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
+  if (lane_id() == 0) s_w[tid >> 6] = 0;
+  __shared__ int64_t s_o[4];
+  if (lane_id() == 0) s_o[tid >> 6] = o;
   __syncthreads();
+  if (tid == 0) s_off = s_o[0] + s_o[1] + s_o[2] + s_o[3];
+  const int c0 = b * kScanChunk + tid * kScanPer;
+  int cnt[kScanPer];
+  int mine = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    cnt[k] = (c0 + k < C) ? counts[c0 + k] : 0;
+    mine += cnt[k];
+  }
+  s_last[tid] = cnt[kScanPer - 1];
+  // block exclusive scan of the per-thread sums
+  int incl = mine;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane_id() >= off) incl += v;
+  }
+  if (lane_id() == 63) s_w[tid >> 6] = incl;
+  __syncthreads();
+  int wpre = 0;
+  for (int k = 0; k < (tid >> 6); ++k) wpre += s_w[k];
   const int64_t T = a.group_particles, G = a.group_cells;
-  for (int c = c0; c < c1; ++c) {
-    const int64_t key = a.start[c] / T + c / G;
-    const int64_t kp = (c == 0) ? -1 : (a.start[c - 1] / T + (c - 1) / G);
+  int64_t st = s_off + wpre + incl - mine;
+  // start of the cell before this thread's first cell
+  int64_t prev_start;
+  if (tid > 0) prev_start = st - s_last[tid - 1];
+  else prev_start = (b > 0) ? st - a.lastcnt[b - 1] : -1;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int c = c0 + k;
+    if (c >= C) break;
+    a.start[c] = (int32_t)st;
+    counts[c] = 0;
+    const int64_t key = st / T + c / G;
+    const int64_t kp = (c == 0) ? -1 : (prev_start / T + (c - 1) / G);
     for (int64_t g = kp + 1; g <= key; ++g) {
       if (g <= glaunch) a.gfirst[g] = c;
       else atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_GROUPS);
     }
+    for (int i = 0; i < a.n_inst; ++i)
+      if (a.params[i].cell0 == c) a.inst_pstart[i] = st;
+    prev_start = st;
+    st += cnt[k];
   }
-  const int64_t klast = a.start[C - 1] / T + (C - 1) / G;
-  for (int64_t g = klast + 1 + tid; g <= glaunch; g += 1024) a.gfirst[g] = C;
-  for (int i = tid; i <= a.n_inst; i += 1024)
-    a.inst_pstart[i] = (i == a.n_inst) ? a.start[C] : a.start[a.params[i].cell0];
-  if (tid == 0 && set_n) a.ctr->n = a.start[C];
+  if (b == nb - 1) {
+    // the last chunk holds cell C-1: total, group tail, instance end
+    __shared__ int64_t s_tot, s_klast;
+    if (c0 <= C - 1 && C - 1 < c0 + kScanPer) {
+      s_tot = st;
+      const int64_t slast = st - cnt[(C - 1) - c0];
+      s_klast = slast / T + (C - 1) / G;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.start[C] = (int32_t)s_tot;
+      a.inst_pstart[a.n_inst] = s_tot;
+      if (set_n) a.ctr->n = s_tot;
+    }
+    for (int64_t g = s_klast + 1 + tid; g <= glaunch; g += 256) a.gfirst[g] = C;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_place(StepArgs a) {
@@ -363,7 +447,9 @@ struct GlobalStore {
 
 struct CollideShared {
   int* start;   // [Gc+1]
-  int* coff;    // [Gc+1]
+  int* coff;    // [Gc+1] candidate offsets of the large cells
+  int* soff;    // [Gc+1] candidate offsets of the small cells
+  uint4* words; // [2 KC] pre-drawn words of a chunk of small-cell candidates
   float* sgm;   // [Gc]
   uint32_t* obs;  // [Gc]
   int* inst;    // [Gc]
@@ -377,28 +463,170 @@ struct CollideShared {
   int* wsum;    // [8]
 };
 
-template <class Store>
+// Candidate of a cell (Section 2.2): VHS acceptance of the pair against the
+// majorant with the uniform word w2; returns sigma_T g and the squared
+// relative speed.
+static __device__ __forceinline__ bool vhs_accept(const InstParam& I, float sgm, uint32_t w2,
+                                                  const float4& va, const float4& vb,
+                                                  float* sg_out, float* g2_out) {
+  const float gx = va.x - vb.x, gy = va.y - vb.y, gz = va.z - vb.z;
+  const float g2 = gx * gx + gy * gy + gz * gz;
+  const float sg = g2 > 0.0f ? I.csig * fpow(g2, I.expo) : 0.0f;
+  *sg_out = sg;
+  *g2_out = g2;
+  return u01f(w2) < sg * frcp(sgm);
+}
+
+// Accepted collision: Borgnakke-Larsen exchange for the first then the
+// second particle (double relaxation, tests w3 and r1.y, Beta(1, 5/2 - omega)
+// splits r1.x and r1.z), then isotropic scattering (cos theta from r1.w, phi
+// from w8) that conserves momentum and the total energy.
+static __device__ __forceinline__ void apply_collision(const InstParam& I, float g2, uint32_t w3,
+                                                       uint4 r1, uint32_t w8, float4& va,
+                                                       float4& vb, int* inel) {
+  float et = 0.25f * g2;  // relative translational energy, reduced mass 1/2
+  if (u01d(w3) < I.pin) {
+    const float ec = et + va.w;
+    va.w = (1.0f - fpow(u01f(r1.x), I.beta_inv)) * ec;
+    et = ec - va.w;
+    ++*inel;
+  }
+  if (u01d(r1.y) < I.pin) {
+    const float ec = et + vb.w;
+    vb.w = (1.0f - fpow(u01f(r1.z), I.beta_inv)) * ec;
+    et = ec - vb.w;
+    ++*inel;
+  }
+  const float hg = fsqrt(et);  // half of |g'| = 2 sqrt(et)
+  const float ct = 2.0f * u01f(r1.w) - 1.0f;
+  const float st = fsqrt(fmaxf(0.0f, 1.0f - ct * ct));
+  const float ph = 6.28318530717958648f * u01f(w8);
+  const float sp = __sinf(ph), cp = __cosf(ph);
+  const float nx = ct, ny = st * cp, nz = st * sp;
+  const float cx = 0.5f * (va.x + vb.x), cy = 0.5f * (va.y + vb.y), cz = 0.5f * (va.z + vb.z);
+  va.x = cx + hg * nx;
+  va.y = cy + hg * ny;
+  va.z = cz + hg * nz;
+  vb.x = cx - hg * nx;
+  vb.y = cy - hg * ny;
+  vb.z = cz - hg * nz;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim a multiple of 64).
+static __device__ __forceinline__ int block_exscan(int v, int* s_w, int* total) {
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (lane_id() >= off) incl += t;
+  }
+  if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  int pre = 0, tot = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    if (k < (int)(threadIdx.x >> 6)) pre += s_w[k];
+    tot += s_w[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + incl - v;
+}
+
+// UNI: every cell of the group belongs to instance `iu` (wave-uniform index,
+// so the parameters come through the scalar cache).
+//
+// Cells with at most seq_max particles run their candidates in order on one
+// lane; the Philox words of a chunk of their candidates are drawn beforehand
+// by all lanes together.  Larger cells run in parallel rounds.  Both give the
+// order of the sequential algorithm exactly.
+template <class Store, bool UNI>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
-                                     uint32_t* owner, int nc, int c_lo, uint32_t step) {
-  // candidate counts, FP64 Iround as in the oracle
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+                                     uint32_t* owner, int nc, int c_lo, uint32_t step, int iu) {
+  // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
+  // (nc <= group_cells <= 4 * blockDim)
+  const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int cb = threadIdx.x * per, ce = min(nc, cb + per);
+  int ks[4] = {0, 0, 0, 0}, kg[4] = {0, 0, 0, 0};
+  int tsum_s = 0, tsum_g = 0;
+  for (int c = cb; c < ce; ++c) {
     const int N = S.start[c + 1] - S.start[c];
     int k = 0;
     if (N >= 2) {
-      const InstParam& I = a.params[S.inst[c]];
+      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_NCAND, 0);
       k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, I.vol), r.x);
     }
-    S.coff[c + 1] = k;
+    if (N <= a.seq_max) ks[c - cb] = k; else kg[c - cb] = k;
+    tsum_s += ks[c - cb];
+    tsum_g += kg[c - cb];
   }
-  __syncthreads();
+  int KS, KG;
+  int run_s = block_exscan(tsum_s, S.wsum, &KS);
+  int run_g = block_exscan(tsum_g, S.wsum, &KG);
+  for (int c = cb; c < ce; ++c) {
+    S.soff[c] = run_s;
+    S.coff[c] = run_g;
+    run_s += ks[c - cb];
+    run_g += kg[c - cb];
+  }
   if (threadIdx.x == 0) {
-    S.coff[0] = 0;
-    for (int c = 0; c < nc; ++c) S.coff[c + 1] += S.coff[c];
+    S.soff[nc] = KS;
+    S.coff[nc] = KG;
   }
   __syncthreads();
-  const int K = S.coff[nc];
   int l_cand = 0, l_acc = 0, l_inel = 0, l_sat = 0;
+  // ---- small cells: chunks of candidates in (cell, k) order ----------------
+  float obs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int kb = 0; kb < KS; kb += kCandChunk) {
+    const int kc = min(kCandChunk, KS - kb);
+    for (int q = threadIdx.x; q < kc; q += blockDim.x) {
+      const int k = kb + q;
+      const int c = floor_index(S.soff, nc + 1, k);
+      const int kk = k - S.soff[c];
+      const int N = S.start[c + 1] - S.start[c];
+      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+      const uint4 r0 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk);
+      const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+      const uint4 r2 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u);
+      const uint32_t i = pick(r0.x, (uint32_t)N);
+      uint32_t j = pick(r0.y, (uint32_t)(N - 1));
+      j += (j >= i);
+      uint4* w = S.words + 2 * q;
+      w[0] = make_uint4(i | (j << 16), r0.z, r0.w, r2.x);
+      w[1] = r1;
+    }
+    __syncthreads();
+    for (int c = cb; c < ce; ++c) {
+      const int k0 = max(S.soff[c], kb), k1 = min(S.soff[c + 1], kb + kc);
+      if (k0 >= k1) continue;
+      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const int b = S.start[c];
+      const float sgm = S.sgm[c];
+      for (int k = k0; k < k1; ++k) {
+        const uint4* w = S.words + 2 * (k - kb);
+        const uint4 w0 = w[0];
+        const int i = b + (int)(w0.x & 0xFFFFu), j = b + (int)(w0.x >> 16);
+        float4 va = P.ld(i), vb = P.ld(j);
+        float sg, g2;
+        const bool acc = vhs_accept(I, sgm, w0.y, va, vb, &sg, &g2);
+        obs[c - cb] = fmaxf(obs[c - cb], sg);
+        ++l_cand;
+        l_sat += sg > sgm;
+        if (acc) {
+          apply_collision(I, g2, w0.z, w[1], w0.w, va, vb, &l_inel);
+          ++l_acc;
+          P.st(i, va);
+          P.st(j, vb);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = cb; c < ce; ++c) atomicMax(&S.obs[c], __float_as_uint(obs[c - cb]));
+  // ---- large cells: candidates staged in chunks and executed in rounds; a
+  // candidate runs once it is the earliest pending candidate of both its
+  // particles -------------------------------------------------------------------
+  const int K = KG;
   for (int kb = 0; kb < K; kb += kCandChunk) {
     const int kc = min(kCandChunk, K - kb);
     for (int q = threadIdx.x; q < kc; q += blockDim.x) {
@@ -406,7 +634,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       const int c = floor_index(S.coff, nc + 1, k);
       const int kk = k - S.coff[c];
       const int N = S.start[c + 1] - S.start[c];
-      const InstParam& I = a.params[S.inst[c]];
+      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_COLL, 3u * (uint32_t)kk);
       int i = (int)pick(r.x, (uint32_t)N);
       int j = (int)pick(r.y, (uint32_t)(N - 1));
@@ -442,49 +670,23 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         }
         S.pend[q] = 0;
         const int c = S.cc[q];
-        const InstParam& I = a.params[S.inst[c]];
+        const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
         float4 va = P.ld(i), vb = P.ld(j);
-        const float gx = va.x - vb.x, gy = va.y - vb.y, gz = va.z - vb.z;
-        const float g2 = gx * gx + gy * gy + gz * gz;
-        const float sg = g2 > 0.0f ? I.csig * powf(g2, I.expo) : 0.0f;
+        float sg, g2;
+        const bool acc = vhs_accept(I, S.sgm[c], S.w2[q], va, vb, &sg, &g2);
         atomicMax(&S.obs[c], __float_as_uint(sg));
-        const float ratio = sg / S.sgm[c];
         ++l_cand;
-        l_sat += ratio > 1.0f;
-        if (!(u01f(S.w2[q]) < ratio)) continue;
-        ++l_acc;
-        const int kk = kb + q - S.coff[c];
-        const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
-        const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
-        const uint4 r2 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u);
-        float et = 0.25f * g2;
-        if (u01d(S.w3[q]) < I.pin) {
-          const float ec = et + va.w;
-          va.w = (1.0f - powf(u01f(r1.x), I.beta_inv)) * ec;
-          et = ec - va.w;
-          ++l_inel;
+        l_sat += sg > S.sgm[c];
+        if (acc) {
+          const int kk = kb + q - S.coff[c];
+          const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+          const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+          const uint4 r2 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u);
+          apply_collision(I, g2, S.w3[q], r1, r2.x, va, vb, &l_inel);
+          ++l_acc;
+          P.st(i, va);
+          P.st(j, vb);
         }
-        if (u01d(r1.y) < I.pin) {
-          const float ec = et + vb.w;
-          vb.w = (1.0f - powf(u01f(r1.z), I.beta_inv)) * ec;
-          et = ec - vb.w;
-          ++l_inel;
-        }
-        const float hg = sqrtf(et);  // half of |g'| = 2 sqrt(et)
-        const float ct = 2.0f * u01f(r1.w) - 1.0f;
-        const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-        float sp, cp;
-        sincospif(2.0f * u01f(r2.x), &sp, &cp);
-        const float nx = ct, ny = st * cp, nz = st * sp;
-        const float cx = 0.5f * (va.x + vb.x), cy = 0.5f * (va.y + vb.y), cz = 0.5f * (va.z + vb.z);
-        va.x = cx + hg * nx;
-        va.y = cy + hg * ny;
-        va.z = cz + hg * nz;
-        vb.x = cx - hg * nx;
-        vb.y = cy - hg * ny;
-        vb.z = cz - hg * nz;
-        P.st(i, va);
-        P.st(j, vb);
       }
       if (!__syncthreads_or(more)) break;
     }
@@ -495,14 +697,16 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   atomicAdd(&S.stat[3], l_sat);
 }
 
-// FP64 raw sums of one cell by one wave: lane-strided partial sums in slot
-// order, then a fixed xor butterfly, so the bits depend only on the cell's
-// particle order.
+// FP64 raw sums of a cell by an 8-lane subgroup: lane j of the subgroup sums
+// particles j, j+8, j+16, ... in slot order, then a fixed xor butterfly over
+// the 8 lanes.  The bits depend only on the cell's particle order, never on
+// launch parameters.  All 64 lanes of the wave must call it.
+constexpr int kSub = 8;
 template <class Store>
-static __device__ void wave_cell_sums(Store P, int b, int N, double s[17]) {
+static __device__ void sub_cell_sums(Store P, int b, int N, double s[17]) {
 #pragma unroll
   for (int f = 0; f < 17; ++f) s[f] = 0.0;
-  for (int k = lane_id(); k < N; k += 64) {
+  for (int k = lane_id() & (kSub - 1); k < N; k += kSub) {
     const float4 v = P.ld(b + k);
     const double x = v.x, y = v.y, z = v.z, e = v.w;
     const double v2 = x * x + y * y + z * z;
@@ -525,7 +729,7 @@ static __device__ void wave_cell_sums(Store P, int b, int N, double s[17]) {
     s[16] += z * e;
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
+  for (int off = kSub / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int f = 0; f < 17; ++f) s[f] += __shfl_xor(s[f], off);
 }
@@ -537,7 +741,15 @@ static __device__ __forceinline__ double select17(const double s[17], int f) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_collide(StepArgs a, int do_collide, int do_sample) {
+// One workgroup (a single wave) per cell group: gather the group's particles
+// from the previous buffer in sorted order (positions and ids straight to the
+// destination, velocities and rotational energies into LDS), collide, write
+// back, and add the cells' FP64 raw sums to the accumulator.
+constexpr int kCollideThreads = 64;
+constexpr int kGatherUnroll = 4;
+
+__global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_collide,
+                                                             int do_sample) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int g = blockIdx.x;
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
@@ -549,10 +761,11 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a, int do_collide, int
   // shared layout
   unsigned char* p = smem;
   float4* sv = (float4*)p;              p += sizeof(float4) * L;
-  uint32_t* s_owner = (uint32_t*)p;     p += sizeof(uint32_t) * L;
   CollideShared S;
+  S.words = (uint4*)p;                  p += sizeof(uint4) * 2 * kCandChunk;
   S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
   S.coff = (int*)p;                     p += sizeof(int) * (Gc + 1);
+  S.soff = (int*)p;                     p += sizeof(int) * (Gc + 1);
   S.sgm = (float*)p;                    p += sizeof(float) * Gc;
   S.obs = (uint32_t*)p;                 p += sizeof(uint32_t) * Gc;
   S.inst = (int*)p;                     p += sizeof(int) * Gc;
@@ -577,41 +790,67 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a, int do_collide, int
   }
   if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
   const bool fast = ng <= L;
-  // gather: position and id go straight to the destination buffer
+  // gather, kGatherUnroll particles per lane in flight
   const bool two = a.dim == 2;
-  for (int e = threadIdx.x; e < ng; e += blockDim.x) {
-    const int src = a.perm[e_lo + e];
-    const int d = e_lo + e;
-    a.B.x[d] = a.A.x[src];
-    if (two) a.B.y[d] = a.A.y[src];
-    a.B.id[d] = a.A.id[src];
-    const float4 v = make_float4(a.A.vx[src], a.A.vy[src], a.A.vz[src], a.A.er[src]);
-    if (fast) {
-      sv[e] = v;
-    } else {
-      a.B.vx[d] = v.x;
-      a.B.vy[d] = v.y;
-      a.B.vz[d] = v.z;
-      a.B.er[d] = v.w;
+  for (int e0 = threadIdx.x; e0 < ng; e0 += kGatherUnroll * blockDim.x) {
+    int src[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int e = e0 + u * blockDim.x;
+      src[u] = e < ng ? a.perm[e_lo + e] : -1;
+    }
+    float x[kGatherUnroll], y[kGatherUnroll];
+    float4 v[kGatherUnroll];
+    uint32_t id[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      if (src[u] < 0) continue;
+      const int q = src[u];
+      x[u] = a.A.x[q];
+      y[u] = two ? a.A.y[q] : 0.0f;
+      id[u] = a.A.id[q];
+      v[u] = make_float4(a.A.vx[q], a.A.vy[q], a.A.vz[q], a.A.er[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      if (src[u] < 0) continue;
+      const int e = e0 + u * blockDim.x;
+      const int d = e_lo + e;
+      a.B.x[d] = x[u];
+      if (two) a.B.y[d] = y[u];
+      a.B.id[d] = id[u];
+      if (fast) {
+        sv[e] = v[u];
+      } else {
+        a.B.vx[d] = v[u].x;
+        a.B.vy[d] = v[u].y;
+        a.B.vz[d] = v[u].z;
+        a.B.er[d] = v[u].w;
+      }
     }
   }
   __syncthreads();
   LdsStore ls{sv};
   GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
+  uint32_t* owner = a.owner + e_lo;
   if (do_collide) {
-    if (fast) collide_cells(a, S, ls, s_owner, nc, c_lo, step);
-    else collide_cells(a, S, gs, a.owner + e_lo, nc, c_lo, step);
+    const bool uni = S.inst[0] == S.inst[nc - 1];  // instances are contiguous in c
+    const int iu = __builtin_amdgcn_readfirstlane(S.inst[0]);
+    if (fast) {
+      if (uni) collide_cells<LdsStore, true>(a, S, ls, owner, nc, c_lo, step, iu);
+      else collide_cells<LdsStore, false>(a, S, ls, owner, nc, c_lo, step, iu);
+    } else {
+      if (uni) collide_cells<GlobalStore, true>(a, S, gs, owner, nc, c_lo, step, iu);
+      else collide_cells<GlobalStore, false>(a, S, gs, owner, nc, c_lo, step, iu);
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       const float o = __uint_as_float(S.obs[c]);
       if (o > S.sgm[c]) a.sgmax[c_lo + c] = o;
     }
-    if (threadIdx.x == 0) {
-      atomicAdd((unsigned long long*)&a.ctr->candidates, (unsigned long long)S.stat[0]);
-      atomicAdd((unsigned long long*)&a.ctr->accepted, (unsigned long long)S.stat[1]);
-      atomicAdd((unsigned long long*)&a.ctr->inelastic, (unsigned long long)S.stat[2]);
-      atomicAdd((unsigned long long*)&a.ctr->saturated, (unsigned long long)S.stat[3]);
-    }
+    if (threadIdx.x < 4 && S.stat[threadIdx.x])
+      atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + threadIdx.x],
+                (unsigned long long)S.stat[threadIdx.x]);
   }
   if (fast) {
     for (int e = threadIdx.x; e < ng; e += blockDim.x) {
@@ -626,13 +865,16 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a, int do_collide, int
   if (do_sample) {
     __syncthreads();
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int c = w; c < nc; c += nw) {
-      const int b = S.start[c], N = S.start[c + 1] - b;
+    const int sub = lane_id() / kSub, sl = lane_id() & (kSub - 1);
+    for (int cb = w * (64 / kSub); cb < nc; cb += nw * (64 / kSub)) {
+      const int c = cb + sub;
+      const bool ok = c < nc;
+      const int b = ok ? S.start[c] : 0, N = ok ? S.start[c + 1] - b : 0;
       double s[17];
-      if (fast) wave_cell_sums(ls, b, N, s);
-      else wave_cell_sums(gs, b, N, s);
-      const int f = lane_id();
-      if (f < 17) a.acc[(int64_t)(c_lo + c) * 17 + f] += select17(s, f);
+      if (fast) sub_cell_sums(ls, b, N, s);
+      else sub_cell_sums(gs, b, N, s);
+      if (ok)
+        for (int f = sl; f < 17; f += kSub) a.acc[(int64_t)(c_lo + c) * 17 + f] += select17(s, f);
     }
   }
 }
@@ -708,15 +950,20 @@ __global__ void k_init_fill(StepArgs a, const double* fields) {
 // ---------------------------------------------------------------------------
 // Instantaneous sums of the current state: one wave per cell.
 __global__ __launch_bounds__(256) void k_sample_state(StepArgs a) {
-  const int waves = (gridDim.x * blockDim.x) >> 6;
-  const int w0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int subs = (gridDim.x * blockDim.x) / kSub;
+  const int s0 = (blockIdx.x * blockDim.x + threadIdx.x) / kSub;
+  const int sl = lane_id() & (kSub - 1);
   GlobalStore gs{a.A.vx, a.A.vy, a.A.vz, a.A.er};
-  for (int c = w0; c < a.ncell; c += waves) {
-    const int b = a.start[c], N = a.start[c + 1] - b;
+  // every lane of a wave runs the same number of iterations
+  const int iters = (a.ncell + subs - 1) / subs;
+  for (int it = 0; it < iters; ++it) {
+    const int c = s0 + it * subs;
+    const bool ok = c < a.ncell;
+    const int b = ok ? a.start[c] : 0, N = ok ? a.start[c + 1] - b : 0;
     double s[17];
-    wave_cell_sums(gs, b, N, s);
-    const int f = lane_id();
-    if (f < 17) a.sums[(int64_t)c * 17 + f] = select17(s, f);
+    sub_cell_sums(gs, b, N, s);
+    if (ok)
+      for (int f = sl; f < 17; f += kSub) a.sums[(int64_t)c * 17 + f] = select17(s, f);
   }
 }
 
@@ -1065,9 +1312,10 @@ int64_t group_launch(const StepArgs& a) {
 }
 
 size_t collide_lds_bytes(int lds_particles, int group_cells) {
-  return sizeof(float4) * lds_particles + sizeof(uint32_t) * lds_particles +
-         sizeof(int) * 2 * (group_cells + 1) + (sizeof(float) + 2 * sizeof(int)) * group_cells +
-         (5 * sizeof(int) + 1) * kCandChunk + sizeof(int) * 12 + 16;
+  return sizeof(float4) * lds_particles + sizeof(uint4) * 2 * kCandChunk +
+         sizeof(int) * 3 * (group_cells + 1) +
+         (sizeof(float) + 2 * sizeof(int)) * group_cells + (5 * sizeof(int) + 1) * kCandChunk +
+         sizeof(int) * 12 + 16;
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
@@ -1075,9 +1323,13 @@ hipError_t launch_move(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int scan_blocks(int ncell) { return (ncell + kScanChunk - 1) / kScanChunk; }
+
 hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a, counts, (int32_t)group_launch(a),
-                     set_n ? 1 : 0);
+  const int nb = scan_blocks(a.ncell);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, s, a, counts);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, a, counts,
+                     (int32_t)group_launch(a), set_n ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1093,7 +1345,7 @@ hipError_t launch_order(const StepArgs& a, hipStream_t s) {
 
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
-  hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(256), lds, s, a,
+  hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(kCollideThreads), lds, s, a,
                      collide ? 1 : 0, sample ? 1 : 0);
   return hipGetLastError();
 }
@@ -1138,7 +1390,7 @@ hipError_t launch_init(const StepArgs& a, const double* fields, int32_t ppc, hip
 }
 
 hipError_t launch_sample_state(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample_state, dim3(min(blocks_for((int64_t)a.ncell * 64, 256), 8192)),
+  hipLaunchKernelGGL(k_sample_state, dim3(min(blocks_for((int64_t)a.ncell * kSub, 256), 8192)),
                      dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -189,6 +189,16 @@ class DSMC:
                                           _ptr(nsf) if nsf is not None else None, _stream()))
         return hot, mask, kn, nsf
 
+    def profile(self, mode: str):
+        """'on' (reset and enable), 'off', or 'read' -> {kernel: (ms_total, launches)}."""
+        m = {"off": 0, "on": 1, "read": 2}[mode]
+        ms = (C.c_double * len(L.KERNELS))()
+        nl = (C.c_int64 * len(L.KERNELS))()
+        L.check(self.lib.dsmc_profile(self.ctx, m, ms, nl, _stream()))
+        if m == 2:
+            return {k: (ms[i], nl[i]) for i, k in enumerate(L.KERNELS)}
+        return None
+
     def constants(self, inst: int = 0) -> dict:
         out = (C.c_double * 5)()
         L.check(self.lib.dig_constants(self.ctx, inst, out))

@@ -1,0 +1,207 @@
+"""GPU vs oracle: DIG particle modification, closure assembly, determinism and
+launch-parameter invariance, batched instances."""
+import numpy as np
+import pytest
+import torch
+
+import dig_workloads as wl
+import oracle
+from gpu_common import DSMC, STAGES, gpu_state, np_, oracle_state, rel_close, say
+from paper_2501_10965_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+
+def injected(w, seed, cap_factor=2.0, step=3):
+    arrays = wl.random_sorted_state(w, seed)
+    start = arrays.pop("start")
+    n = len(arrays["x"])
+    nc = w["nx"] * w["ny"]
+    sg = np.full(nc, oracle.sgmax_default(w), np.float32)
+    sim = DSMC(w, capacity=int(n * cap_factor) + 1024)
+    sim.inject(arrays, start, step=step, next_id=n + 17, sgmax=sg)
+    return sim, arrays, start, sg, n
+
+
+def random_target(w, rng, rho_scale=1.0):
+    nc = w["nx"] * w["ny"]
+    t = np.empty((6, nc))
+    t[0] = rho_scale * (1.0 + 0.3 * rng.random(nc) - 0.15)
+    t[1:3] = 0.2 * rng.standard_normal((2, nc))
+    t[3] = 0.05 * rng.standard_normal(nc)
+    t[4] = 1.0 + 0.2 * rng.random(nc)
+    t[5] = 0.8 + 0.4 * rng.random(nc)
+    return t
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_dig_adjust_matches_oracle(dim):
+    w = wl.cavity_2d(seed=61, n=20, ppc=40, kn=0.05) if dim == 2 else \
+        wl.fourier_1d(seed=62, nx=50, ppc=40)
+    say(f"case adjust dim={dim}")
+    sim, arrays, start, sg, n = injected(w, seed=5 + dim)
+    rng = np.random.default_rng(dim)
+    t = random_target(w, rng)
+    t[0, :3] = 0.0          # emptied cells
+    t[0, 3] *= 60.0         # a cell that grows past the LDS table of one wave
+    o = oracle_state(w, arrays, start, sg, 3, cap=4 * n, next_id=n + 17)
+    assert o.adjust(t, dig_iter=9) == 0
+    sim.adjust(torch.tensor(t, device="cuda"), 9)
+    c = sim.counters()
+    assert c["n"] == o.n and c["next_id"] == o.next_id
+    np.testing.assert_array_equal(np_(sim.array("start")), o.start)
+    g = gpu_state(sim)
+    om = o.arrays()
+    np.testing.assert_array_equal(g["id"], om["id"])
+    for k in ("x", "y") if dim == 2 else ("x",):
+        assert rel_close(g[k], om[k], 1e-6).all(), k
+    for k in ("vx", "vy", "vz", "er"):
+        assert rel_close(g[k], om[k], 2e-6).all(), k
+    # refill the emptied cells from the target equilibrium
+    t2 = t.copy()
+    t2[0, :3] = 1.0
+    o.adjust(t2, dig_iter=10)
+    sim.adjust(torch.tensor(t2, device="cuda"), 10)
+    g = gpu_state(sim)
+    om = o.arrays()
+    np.testing.assert_array_equal(g["id"], om["id"])
+    for k in ("vx", "vy", "vz", "er"):
+        assert rel_close(g[k], om[k], 2e-6).all(), k
+    # the library's own instantaneous moments now equal the target
+    f = np_(sim.sample("instant"))
+    occupied = f[19] >= 2
+    np.testing.assert_allclose(f[4][occupied], t2[4][occupied], rtol=2e-6)
+    np.testing.assert_allclose(f[1][occupied], t2[1][occupied], atol=2e-6)
+
+
+def test_dig_adjust_error_paths_leave_state_unchanged():
+    w = wl.cavity_2d(seed=63, n=12, ppc=30, kn=0.05)
+    say("case adjust errors")
+    sim, arrays, start, sg, n = injected(w, seed=9, cap_factor=1.5)
+    before = gpu_state(sim)
+    t = random_target(w, np.random.default_rng(3))
+    t[4, 7] = np.nan
+    with pytest.raises(L.DigError) as e:
+        sim.adjust(torch.tensor(t, device="cuda"), 1)
+    assert e.value.code == L.DIG_ERR_NUMERIC
+    t = random_target(w, np.random.default_rng(3), rho_scale=10.0)
+    with pytest.raises(L.DigError) as e:
+        sim.adjust(torch.tensor(t, device="cuda"), 1)
+    assert e.value.code == L.DIG_ERR_CAPACITY
+    after = gpu_state(sim)
+    for k in before:
+        np.testing.assert_array_equal(before[k], after[k])
+    assert sim.counters()["err"] & L.EBIT_TARGET == 0
+    sim.step(2)  # still steps normally
+
+
+def test_closure_matches_oracle():
+    w = wl.cavity_2d(seed=64, n=24, ppc=10, kn=0.02)
+    say("case closure")
+    nc = 24 * 24
+    rng = np.random.default_rng(4)
+    xc = (np.arange(nc) % 24 + 0.5) / 24
+    yc = (np.arange(nc) // 24 + 0.5) / 24
+    f = np.zeros((20, nc))
+    f[0] = 1.0 + 0.2 * np.sin(3 * xc) * np.cos(2 * yc)
+    f[1] = 0.3 * yc ** 2
+    f[2] = -0.1 * np.sin(4 * xc)
+    f[3] = 0.02 * xc
+    f[4] = 1.0 + 0.3 * xc * yc
+    f[5] = 0.9 + 0.2 * np.cos(3 * yc)
+    f[6:18] = 0.01 * rng.standard_normal((12, nc))
+    f[0, 5] = 0.0  # an empty cell
+    A = [2.0 / 3.0, 0.05, 0.02, 5.0 / (7 - 2 * 0.74)]
+    hot, mask, kn, nsf = oracle.closure(w, f, A, 0.01)
+    sim = DSMC(w)
+    gh, gm, gk, gn = sim.closure(torch.tensor(f, device="cuda"), A, 0.01, with_nsf=True)
+    np.testing.assert_array_equal(np_(gm), mask)
+    fin = np.isfinite(kn)
+    np.testing.assert_array_equal(np.isfinite(np_(gk)), fin)
+    np.testing.assert_allclose(np_(gk)[fin], kn[fin], rtol=1e-12)
+    np.testing.assert_allclose(np_(gh), hot, rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(np_(gn), nsf, rtol=1e-11, atol=1e-15)
+    assert 0 < mask.sum() < nc
+
+
+def _run_cavity(group, steps=30, adjust=True):
+    w = wl.cavity_2d(seed=65, n=40, ppc=30, kn=0.02)
+    sim = DSMC(w, group_particles=group[0], group_cells=group[1])
+    sim.init()
+    sim.step(steps)
+    if adjust:
+        f = sim.sample("average")
+        sim.adjust(f[0:6].clone(), 1)
+        sim.step(5)
+    return gpu_state(sim), np_(sim.array("acc")).copy(), np_(sim.array("sgmax")).copy()
+
+
+def test_bit_identical_reruns_and_group_size_invariance():
+    say("case determinism")
+    ref = _run_cavity((0, 0))
+    again = _run_cavity((0, 0))
+    for g in ((256, 32), (4096, 256), (512, 96)):
+        say(f"  groups {g}")
+        other = _run_cavity(g)
+        for x, y in ((ref, again), (ref, other)):
+            for k in x[0]:
+                np.testing.assert_array_equal(x[0][k], y[0][k], err_msg=k)
+            np.testing.assert_array_equal(x[1], y[1])
+            np.testing.assert_array_equal(x[2], y[2])
+
+
+def test_batched_instances_match_their_own_oracles():
+    """Eight uneven 1D instances (Fourier and Couette, Kn 1e-3..1, 4..400
+    particles per cell) advanced by one launch per stage; each instance
+    compared with an oracle of its own (its seed and instance id)."""
+    ws = [w for w in wl.batch_1d(n_inst=64, scale=0.2)][::8]
+    say("case batch: " + ", ".join(f"{w['nx']}c/{w['ppc']}ppc" for w in ws))
+    per = []
+    for i, w in enumerate(ws):
+        a = wl.random_sorted_state(w, 100 + i)
+        per.append(a)
+    n = sum(len(a["x"]) for a in per)
+    arrays = {k: np.concatenate([a[k] for a in per]) for k in ("x", "y", "vx", "vy", "vz", "er",
+                                                               "id")}
+    starts = []
+    off = 0
+    for a in per:
+        starts.append(a["start"][:-1] + off)
+        off += len(a["x"])
+    start = np.concatenate(starts + [[off]])
+    sgs = np.concatenate([np.full(w["nx"], oracle.sgmax_default(w), np.float32) for w in ws])
+    sim = DSMC(ws, capacity=2 * n + 1024)
+    sim.inject(arrays, start, step=11, next_id=0, sgmax=sgs)
+    c0 = sim.counters()
+    sim.stage(STAGES["move"] | STAGES["sort"])
+    gperm = np_(sim.array("perm"))[:n]
+    gstart = np_(sim.array("start"))
+    moved = {k: np_(v).copy() for k, v in sim.buffer(c0["cur"], n).items()}
+    moved["id"] = moved["id"].view(np.uint32)
+    sim.stage(STAGES["collide"])
+    g = gpu_state(sim)
+    cell0 = 0
+    for i, w in enumerate(ws):
+        nc = w["nx"]
+        p0, p1 = start[cell0], start[cell0 + nc]
+        q0, q1 = gstart[cell0], gstart[cell0 + nc]
+        assert (p0, p1) == (q0, q1), "particles never leave their instance"
+        # move on the oracle from the injected state
+        o = oracle_state(w, {k: v[p0:p1] for k, v in arrays.items()},
+                         start[cell0:cell0 + nc + 1] - p0, sgs[cell0:cell0 + nc], 11)
+        o.move()
+        assert rel_close(moved["x"][p0:p1], o.x[: p1 - p0], 1e-5).all()
+        # sort and collide from the GPU's moved positions
+        om = {k: v[p0:p1] for k, v in moved.items()}
+        o2 = oracle_state(w, om, start[cell0:cell0 + nc + 1] - p0, sgs[cell0:cell0 + nc], 11)
+        perm = o2.sort()
+        np.testing.assert_array_equal(gperm[q0:q1] - p0, perm)
+        res = o2.collide(with_obs=True)
+        cells = np.repeat(np.arange(nc), np.diff(o2.start))
+        bad = np.zeros(p1 - p0, bool)
+        for k in ("vx", "vy", "vz", "er"):
+            bad |= ~rel_close(g[k][q0:q1], getattr(o2, k)[: p1 - p0], 1e-5)
+        badc = np.unique(cells[bad])
+        assert np.all(res["margin"][badc] < 1e-5), (i, badc)
+        np.testing.assert_array_equal(g["id"][q0:q1], o2.id[: p1 - p0])
+        cell0 += nc
