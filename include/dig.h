@@ -179,6 +179,35 @@ dig_status closure_assemble(dig_ctx* ctx, const double* fields_dev, const double
                             double kn_ref, double* hot_dev, uint8_t* mask_dev,
                             double* kngll_dev, double* nsf_dev, dig_stream_t stream);
 
+/* Synthetic-equation solve, DIG step 3 (Section 3): the steady equations of
+ * mass, momentum, total energy and rotational energy (equation
+ * macroscopic_equation) closed by NSF terms plus the higher-order terms hot_dev
+ * ([12][C] as produced by closure_assemble; NULL = NSF only) zeroed where
+ * mask_dev [C] is nonzero (NULL = no mask).  m_half_dev = the DSMC time
+ * average [>=6][C] (rho, ux, uy, uz, Tt, Tr first), also the initial guess;
+ * m_next_dev [6][C] receives the solution.  Finite volumes on the uniform grid
+ * of cfg (single instance), HLLC inviscid fluxes, central viscous and heat
+ * fluxes, Dirichlet walls (wall_mode 0: the config's wall temperature and
+ * velocity; 1: slip and jump taken from the DSMC field's wall-adjacent cells),
+ * explicit pseudo-time steps common to all cells (total mass conserved).
+ * Stops after max_iter steps or when the largest relative change of
+ * (rho, u, Tt, Tr) in one step falls below tol (checked every check_every
+ * steps, default 32; synchronises at each check).  workspace_dev: at least
+ * dig_synth_workspace_bytes(cfg) bytes, 256-byte aligned, caller-owned.
+ * Errors: DIG_ERR_INVALID (bad arguments), DIG_ERR_NUMERIC (non-finite state). */
+typedef struct {
+  double A[4];           /* heat-flux relaxation matrix Att, Atr, Art, Arr */
+  double cfl;            /* pseudo-time step factor (explicit stability below 1) */
+  int32_t wall_mode;     /* 0 wall values, 1 DSMC slip / jump */
+  int32_t check_every;   /* convergence check period (0 = 32) */
+} dig_synth_opts;
+size_t dig_synth_workspace_bytes(const dig_config* cfg_host);
+dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_host,
+                       const double* m_half_dev, const double* hot_dev, const uint8_t* mask_dev,
+                       double* m_next_dev, void* workspace_dev, size_t workspace_bytes,
+                       int32_t max_iter, double tol, int32_t* iters_host, double* change_host,
+                       dig_stream_t stream);
+
 /* Synchronises and copies the device counters into *out. */
 dig_status dsmc_query(dig_ctx* ctx, dig_counters* out_host, dig_stream_t stream);
 

@@ -1,0 +1,311 @@
+"""FP64 oracle of the synthetic-equation solve (DIG step 3).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The synthetic equations are the steady conservation laws of mass, momentum and
+total energy plus the rotational-energy relaxation equation (equation
+macroscopic_equation, Section 2.3), closed by sigma = sigma_NSF + HoT_sigma,
+q_t = q_t,NSF + HoT_qt, q_r = q_r,NSF + HoT_qr (equations full_constitutive,
+ns_constitutive, kappa_A), with HoT set to zero where the adaptive mask is on
+(Section 3.1).  The paper leaves the numerical scheme to other work; the
+scheme below is this project's reading, written out plainly:
+
+* unknowns per cell W = [rho, rho ux, rho uy, rho uz, rho E, rho e_r] with
+  E = (3 Tt + d_r Tr)/2 + |u|^2/2 and e_r = d_r Tr / 2; pressure p = rho Tt;
+* finite volumes on the uniform grid; inviscid face flux by HLLC (Toro) with
+  Davis wave-speed estimates u_n -/+ c, c = sqrt(gamma Tt),
+  gamma = (5 + d_r)/(3 + d_r); tangential velocity and rotational energy are
+  carried by the contact wave, so a stationary contact gives no mass flux;
+* viscous and heat fluxes at a face from the NSF relations with the face
+  normal derivative (right - left)/h and the tangential derivative averaged
+  from the two cells' central differences; mu = mu0 Tt^omega evaluated at the
+  mean of the two cells' Tt, kappa from A; HoT at a face = mean of the two
+  cells' (masked) HoT;
+* walls: Dirichlet face state with zero normal velocity; tangential velocity
+  and temperatures either the wall's own (mode "wall") or those of the
+  wall-adjacent cell of the DSMC field M^{n+1/2} (mode "dsmc": slip and jump
+  taken from DSMC); face density = adjacent cell density; derivatives at the
+  wall face use the half cell (interior - wall)/(h/2);
+* rotational relaxation source (d_r rho / 2)(T - Tr)/(Z tau), tau = mu/p;
+* explicit pseudo-time marching with one step for all cells (so that the
+  total mass is conserved exactly): the minimum over cells of
+  cfl / ( sum_axes (|u_a| + c)/h_a + 2 nu sum_axes 1/h_a^2 ) and 0.5 Z tau,
+  nu = max(4 mu / (3 rho), gamma kappa_total / (rho c_v));
+* stop after max_iter steps or when the largest change of (rho, u/sqrt(Tt),
+  Tt, Tr), relative to rho, 1, Tt, Tr, falls below tol.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _grid_params(w):
+    nx, ny = w["nx"], (w.get("ny", 1) if w["dim"] == 2 else 1)
+    hx = w["lx"] / nx
+    hy = (w["ly"] / ny) if w["dim"] == 2 else 1.0
+    return nx, ny, hx, hy
+
+
+def _conductivities(mu, A, dr):
+    att, atr, art, arr = A
+    det = att * arr - atr * art
+    kt = 0.5 * mu * (arr * 5.0 - atr * dr) / det
+    kr = 0.5 * mu * (-art * 5.0 + att * dr) / det
+    return kt, kr
+
+
+def solve(w, m_half, hot=None, mask=None, A=None, max_iter=2000, tol=1e-5, cfl=0.5,
+          wall_mode="dsmc"):
+    """Returns (m_next [6, C], iterations, last relative change)."""
+    nx, ny, hx, hy = _grid_params(w)
+    C = nx * ny
+    dr = w.get("dr", 2)
+    om = w["omega"]
+    mu0 = w["kn"] * np.sqrt(2.0 / np.pi)
+    Z = w["zrot"]
+    gam = (5.0 + dr) / (3.0 + dr)
+    cv = (3.0 + dr) / 2.0
+    if A is None:
+        A = (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * om))
+    two = w["dim"] == 2
+    m = np.asarray(m_half, dtype=np.float64)
+    rho0 = m[0].reshape(ny, nx)
+    u0 = m[1:4].reshape(3, ny, nx)
+    tt0 = m[4].reshape(ny, nx)
+    tr0 = m[5].reshape(ny, nx)
+    H = np.zeros((12, ny, nx))
+    if hot is not None:
+        H = np.asarray(hot, dtype=np.float64).reshape(12, ny, nx).copy()
+        if mask is not None:
+            H[:, np.asarray(mask).reshape(ny, nx) != 0] = 0.0
+    # conservative state
+    W = np.zeros((6, ny, nx))
+    W[0] = rho0
+    W[1:4] = rho0 * u0
+    W[4] = rho0 * (0.5 * (3 * tt0 + dr * tr0) + 0.5 * (u0 ** 2).sum(axis=0))
+    W[5] = rho0 * 0.5 * dr * tr0
+    # wall face states: faces 0 (x-), 1 (x+), 2 (y-), 3 (y+)
+    bct = [b[0] for b in w["bc"]]
+    walls = {}
+    for f in range(4 if two else 2):
+        if bct[f] == "periodic":
+            continue
+        if f == 0:
+            idx = (slice(None), 0)
+        elif f == 1:
+            idx = (slice(None), nx - 1)
+        elif f == 2:
+            idx = (0, slice(None))
+        else:
+            idx = (ny - 1, slice(None))
+        if wall_mode == "wall":
+            T = np.full(rho0[idx].shape, w["bc"][f][1])
+            ut = [np.full(rho0[idx].shape, w["bc"][f][2][k]) for k in range(3)]
+            walls[f] = dict(u=ut, tt=T, tr=T.copy())
+        else:
+            walls[f] = dict(u=[u0[k][idx].copy() for k in range(3)], tt=tt0[idx].copy(),
+                            tr=tr0[idx].copy())
+        axis = f // 2
+        walls[f]["u"][axis] = np.zeros_like(walls[f]["u"][axis])
+
+    def prims(W):
+        rho = W[0]
+        u = W[1:4] / rho
+        tr = 2.0 * W[5] / (dr * rho)
+        tt = (W[4] / rho - 0.5 * (u ** 2).sum(axis=0) - 0.5 * dr * tr) * 2.0 / 3.0
+        return rho, u, tt, tr
+
+    it = 0
+    change = np.inf
+    for it in range(1, max_iter + 1):
+        rho, u, tt, tr = prims(W)
+        mu = mu0 * tt ** om
+        kt_c, kr_c = _conductivities(mu, A, dr)
+        # cell-centred central derivatives used for tangential face terms
+        def dcen(f, axis):
+            out = np.zeros_like(f)
+            if axis == 1 and not two:
+                return out
+            n = f.shape[1] if axis == 0 else f.shape[0]
+            h = hx if axis == 0 else hy
+            per = bct[2 * axis] == "periodic"
+            if axis == 0:
+                if per:
+                    out[:] = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * h)
+                elif n > 1:
+                    out[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / (2 * h)
+                    out[:, 0] = (f[:, 1] - f[:, 0]) / h
+                    out[:, -1] = (f[:, -1] - f[:, -2]) / h
+            else:
+                if per:
+                    out[:] = (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / (2 * h)
+                elif n > 1:
+                    out[1:-1] = (f[2:] - f[:-2]) / (2 * h)
+                    out[0] = (f[1] - f[0]) / h
+                    out[-1] = (f[-1] - f[-2]) / h
+            return out
+
+        du = [[dcen(u[i], a) for a in range(2)] for i in range(3)]
+        R = np.zeros_like(W)
+        # local time step accumulators
+        inv_dt = np.zeros((ny, nx))
+        c = np.sqrt(gam * tt)
+        ktot = kt_c + kr_c
+        nu = np.maximum(4.0 * mu / (3.0 * rho), gam * ktot / (rho * cv))
+        for axis in range(2 if two else 1):
+            h = hx if axis == 0 else hy
+            inv_dt += (np.abs(u[axis]) + c) / h + 2.0 * nu / h ** 2
+            F = _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam,
+                             mu0, om, A, nx, ny)
+            # F has shape (6, ny, nx+1) for axis 0 or (6, ny+1, nx) for axis 1
+            if axis == 0:
+                R -= (F[:, :, 1:] - F[:, :, :-1]) / h
+            else:
+                R -= (F[:, 1:, :] - F[:, :-1, :]) / h
+        tau = mu / (rho * tt)
+        T = (3.0 * tt + dr * tr) / (3.0 + dr)
+        R[5] += 0.5 * dr * rho * (T - tr) / (Z * tau)
+        dtau = min(np.min(cfl / inv_dt), np.min(0.5 * Z * tau))
+        Wn = W + dtau * R
+        rn, un, ttn, trn = prims(Wn)
+        ch = np.max(np.abs(rn - rho) / rho)
+        ch = max(ch, np.max(np.abs(un - u) / np.sqrt(tt)))
+        ch = max(ch, np.max(np.abs(ttn - tt) / tt))
+        ch = max(ch, np.max(np.abs(trn - tr) / np.maximum(tr, 1e-300)))
+        W = Wn
+        change = ch
+        if ch < tol:
+            break
+    rho, u, tt, tr = prims(W)
+    out = np.zeros((6, C))
+    out[0] = rho.ravel()
+    out[1:4] = u.reshape(3, C)
+    out[4] = tt.ravel()
+    out[5] = tr.ravel()
+    return out, it, change
+
+
+def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam, mu0, om, A,
+                 nx, ny):
+    """Total (inviscid + viscous + heat) flux through the faces normal to axis."""
+    # left/right states on every face; boundary faces filled below
+    if axis == 0:
+        nf = (ny, nx + 1)
+        L = lambda a: np.concatenate([a[..., -1:], a], axis=-1)   # left neighbour of face i
+        Rr = lambda a: np.concatenate([a, a[..., :1]], axis=-1)   # right neighbour of face i
+    else:
+        nf = (ny + 1, nx)
+        L = lambda a: np.concatenate([a[..., -1:, :], a], axis=-2)
+        Rr = lambda a: np.concatenate([a, a[..., :1, :]], axis=-2)
+    rl, rr = L(rho), Rr(rho)
+    ul, ur = L(u), Rr(u)
+    tl, tR = L(tt), Rr(tt)
+    trl, trr = L(tr), Rr(tr)
+    Wl, Wr = L(W), Rr(W)
+    Hl, Hr = L(H), Rr(H)
+    dul = [[L(du[i][a]) for a in range(2)] for i in range(3)]
+    dur = [[Rr(du[i][a]) for a in range(2)] for i in range(3)]
+    periodic = bct[2 * axis] == "periodic"
+    # ---------------- inviscid (HLLC) on interior / periodic faces
+    def euler(Wc, rc, uc, tc):
+        p = rc * tc
+        un = uc[axis]
+        F = np.empty_like(Wc)
+        F[0] = Wc[0] * un
+        for k in range(3):
+            F[1 + k] = Wc[1 + k] * un + (p if k == axis else 0.0)
+        F[4] = (Wc[4] + p) * un
+        F[5] = Wc[5] * un
+        return F
+
+    def star(Wc, rc, uc, pc, SK, Ss):
+        f = rc * (SK - uc[axis]) / (SK - Ss)
+        U = np.empty_like(Wc)
+        U[0] = f
+        for k in range(3):
+            U[1 + k] = f * (Ss if k == axis else uc[k])
+        U[4] = f * (Wc[4] / rc + (Ss - uc[axis]) * (Ss + pc / (rc * (SK - uc[axis]))))
+        U[5] = f * Wc[5] / rc
+        return U
+
+    Fl, Fr = euler(Wl, rl, ul, tl), euler(Wr, rr, ur, tR)
+    pl, pr = rl * tl, rr * tR
+    cl, cr = np.sqrt(gam * tl), np.sqrt(gam * tR)
+    SL = np.minimum(ul[axis] - cl, ur[axis] - cr)
+    SR = np.maximum(ul[axis] + cl, ur[axis] + cr)
+    Ss = (pr - pl + rl * ul[axis] * (SL - ul[axis]) - rr * ur[axis] * (SR - ur[axis])) / \
+        (rl * (SL - ul[axis]) - rr * (SR - ur[axis]))
+    FsL = Fl + SL * (star(Wl, rl, ul, pl, SL, Ss) - Wl)
+    FsR = Fr + SR * (star(Wr, rr, ur, pr, SR, Ss) - Wr)
+    F = np.where(SL >= 0, Fl, np.where(Ss >= 0, FsL, np.where(SR > 0, FsR, Fr)))
+    # ---------------- viscous / heat on interior / periodic faces
+    tf = 0.5 * (tl + tR)
+    uf = 0.5 * (ul + ur)
+    dn = [(ur[i] - ul[i]) / h for i in range(3)]                 # d u_i / d x_axis
+    dt_ = [0.5 * (dul[i][1 - axis] + dur[i][1 - axis]) for i in range(3)] if two else \
+        [np.zeros(nf)] * 3                                        # d u_i / d x_other
+    dTt = (tR - tl) / h
+    dTr = (trr - trl) / h
+    Hf = 0.5 * (Hl + Hr)
+    V = _visc(axis, tf, uf, dn, dt_, dTt, dTr, Hf, mu0, om, A, dr, two)
+    F = F + V
+    # ---------------- boundary faces: walls
+    if not periodic:
+        for side, f in ((0, 2 * axis), (1, 2 * axis + 1)):
+            wl = walls[f]
+            if axis == 0:
+                fi = 0 if side == 0 else nx
+                ci = 0 if side == 0 else nx - 1
+                cell = lambda a: a[..., :, ci]
+                sl = (slice(None), slice(None), fi)
+            else:
+                fi = 0 if side == 0 else ny
+                ci = 0 if side == 0 else ny - 1
+                cell = lambda a: a[..., ci, :]
+                sl = (slice(None), fi, slice(None))
+            sgn = 1.0 if side == 0 else -1.0      # (interior - wall) / (h/2) * sgn = d/dx
+            rc, uc, tc, trc = cell(rho), cell(u), cell(tt), cell(tr)
+            Fw = np.zeros((6,) + rc.shape)
+            Fw[1 + axis] = rc * tc                 # pressure on the wall
+            uw = np.array(wl["u"])
+            tfw = 0.5 * (tc + wl["tt"])
+            dnw = [sgn * (uc[i] - uw[i]) / (0.5 * h) for i in range(3)]
+            dtw = [cell(du[i][1 - axis]) for i in range(3)] if two else \
+                [np.zeros(rc.shape)] * 3
+            dTtw = sgn * (tc - wl["tt"]) / (0.5 * h)
+            dTrw = sgn * (trc - wl["tr"]) / (0.5 * h)
+            Hw = cell(H)
+            Vw = _visc(axis, tfw, uw, dnw, dtw, dTtw, dTrw, Hw, mu0, om, A, dr, two)
+            Fw = Fw + Vw
+            Fw[0] = 0.0
+            F[sl] = Fw
+    return F
+
+
+def _visc(axis, tf, uf, dn, dt_, dTt, dTr, Hf, mu0, om, A, dr, two):
+    """NSF + HoT stress and heat flux through a face normal to `axis`."""
+    mu = mu0 * tf ** om
+    kt, kr = _conductivities(mu, A, dr)
+    # velocity-gradient tensor entries g[i][j] = d u_i / d x_j
+    g = [[None] * 3 for _ in range(3)]
+    other = 1 - axis
+    for i in range(3):
+        g[i][axis] = dn[i]
+        g[i][other] = dt_[i]
+        g[i][2] = np.zeros_like(dn[i])
+    div = g[0][0] + g[1][1]
+    # sigma_{axis, j}
+    hidx = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 0): 3, (0, 2): 4, (2, 0): 4,
+            (1, 2): 5, (2, 1): 5}
+    sig = []
+    for j in range(3):
+        s = -mu * (g[axis][j] + g[j][axis] - (2.0 / 3.0 * div if j == axis else 0.0))
+        sig.append(s + Hf[hidx[(axis, j)]])
+    qt = -kt * dTt + Hf[6 + axis]
+    qr = -kr * dTr + Hf[9 + axis]
+    V = np.zeros((6,) + np.shape(dn[0]))
+    for j in range(3):
+        V[1 + j] = sig[j]
+    V[4] = sig[0] * uf[0] + sig[1] * uf[1] + sig[2] * uf[2] + qt + qr
+    V[5] = qr
+    return V

@@ -37,6 +37,11 @@ class DigLayout(C.Structure):
                 ("sums", C.c_size_t), ("cell_inst", C.c_size_t), ("counters", C.c_size_t)]
 
 
+class DigSynthOpts(C.Structure):
+    _fields_ = [("A", C.c_double * 4), ("cfl", C.c_double), ("wall_mode", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
 class DigCounters(C.Structure):
     _fields_ = [("n", C.c_int64), ("step", C.c_int64), ("nsamp", C.c_int64),
                 ("next_id", C.c_int64), ("candidates", C.c_int64), ("accepted", C.c_int64),
@@ -49,8 +54,9 @@ class DigCounters(C.Structure):
 
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
-           "dsmc_sample", "dig_adjust", "closure_assemble", "dsmc_query", "dig_constants",
-           "dsmc_profile", "dig_last_error", "dsmc_destroy"]
+           "dsmc_sample", "dig_adjust", "closure_assemble", "dig_synth_workspace_bytes",
+           "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dig_last_error",
+           "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
 _lib = None
@@ -89,11 +95,16 @@ def load(path: str = LIB_PATH):
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
     L.dsmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
+    L.dig_synth_workspace_bytes.argtypes = [cp]
+    L.dig_synth_workspace_bytes.restype = C.c_size_t
+    L.synth_solve.argtypes = [cp, C.POINTER(DigSynthOpts), vp, vp, vp, vp, vp, C.c_size_t,
+                              C.c_int32, C.c_double, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_double), vp]
     L.dig_last_error.restype = C.c_char_p
     L.dsmc_destroy.argtypes = [vp]
     L.dsmc_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("dig_last_error", "dsmc_destroy"):
+        if name not in ("dig_last_error", "dsmc_destroy", "dig_synth_workspace_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -1,0 +1,502 @@
+// Synthetic-equation solve on the GPU (DIG step 3, Section 3), FP64.
+//
+// Steady conservation of mass, momentum and total energy plus the rotational
+// relaxation equation (equation macroscopic_equation), closed by NSF terms
+// plus the DSMC higher-order terms, which are zeroed where the adaptive mask
+// is set (equations full_constitutive, ns_constitutive, kappa_A; Section 3.1).
+// The paper defers the numerics to other work; this library uses finite
+// volumes on the uniform grid with HLLC inviscid fluxes, central viscous and
+// heat fluxes, Dirichlet wall faces (wall values or the DSMC slip and jump of
+// the wall-adjacent cell) and explicit pseudo-time steps that are the same in
+// every cell, so the total mass is conserved exactly.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "dig_internal.h"
+
+namespace dig {
+
+struct SynthGrid {
+  int nx, ny, dim, dr;
+  double hx, hy, mu0, omega, zrot, gam, cv, cfl;
+  double Att, Atr, Art, Arr;
+  int bc_periodic[2];  // axis periodic?
+};
+
+struct SynthArrays {
+  const double* W;   // [6][C] current state
+  double* Wn;        // [6][C] next state
+  double* Fx;        // [6][ny][nx+1]
+  double* Fy;        // [6][ny+1][nx]
+  const double* H;   // [12][C] masked HoT (zeros when none)
+  const double* wall;  // [4 faces][5][max(nx,ny)]: ux uy uz tt tr of each wall face
+  unsigned long long* red;  // [2][2]: dtau (min), change (max), by iteration parity
+};
+
+struct Prim {
+  double rho, u[3], tt, tr;
+};
+
+__device__ __forceinline__ Prim prim_of(const double* W, int C, int c, int dr) {
+  Prim p;
+  p.rho = W[c];
+  for (int k = 0; k < 3; ++k) p.u[k] = W[(1 + k) * C + c] / p.rho;
+  p.tr = 2.0 * W[5 * C + c] / (dr * p.rho);
+  const double uu = p.u[0] * p.u[0] + p.u[1] * p.u[1] + p.u[2] * p.u[2];
+  p.tt = (W[4 * C + c] / p.rho - 0.5 * uu - 0.5 * dr * p.tr) * 2.0 / 3.0;
+  return p;
+}
+
+__device__ __forceinline__ void conductivities(const SynthGrid& g, double mu, double* kt,
+                                               double* kr) {
+  const double det = g.Att * g.Arr - g.Atr * g.Art;
+  *kt = 0.5 * mu * (g.Arr * 5.0 - g.Atr * g.dr) / det;
+  *kr = 0.5 * mu * (-g.Art * 5.0 + g.Att * g.dr) / det;
+}
+
+// central derivative of velocity component k along axis at cell (ix, iy)
+__device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int iy, int k,
+                         int axis) {
+  if (axis == 1 && g.dim == 1) return 0.0;
+  const int n = axis == 0 ? g.nx : g.ny;
+  const double h = axis == 0 ? g.hx : g.hy;
+  const int i = axis == 0 ? ix : iy;
+  auto uk = [&](int j) {
+    const int c = axis == 0 ? j + g.nx * iy : ix + g.nx * j;
+    return W[(1 + k) * C + c] / W[c];
+  };
+  if (g.bc_periodic[axis]) return (uk((i + 1) % n) - uk((i - 1 + n) % n)) / (2.0 * h);
+  if (n < 2) return 0.0;
+  if (i > 0 && i < n - 1) return (uk(i + 1) - uk(i - 1)) / (2.0 * h);
+  if (i == 0) return (uk(1) - uk(0)) / h;
+  return (uk(n - 1) - uk(n - 2)) / h;
+}
+
+// NSF + HoT stress and heat flux through a face normal to `axis`.
+__device__ void visc_flux(const SynthGrid& g, int axis, double tf, const double uf[3],
+                          const double dn[3], const double dt[3], double dTt, double dTr,
+                          const double Hf[12], double V[6]) {
+  const double mu = g.mu0 * pow(tf, g.omega);
+  double kt, kr;
+  conductivities(g, mu, &kt, &kr);
+  double gr[3][3];
+  const int other = 1 - axis;
+  for (int i = 0; i < 3; ++i) {
+    gr[i][axis] = dn[i];
+    gr[i][other] = dt[i];
+    gr[i][2] = 0.0;
+  }
+  const double div = gr[0][0] + gr[1][1];
+  const int hidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  double sig[3];
+  for (int j = 0; j < 3; ++j) {
+    const double s = -mu * (gr[axis][j] + gr[j][axis] - (j == axis ? 2.0 / 3.0 * div : 0.0));
+    sig[j] = s + Hf[hidx[axis][j]];
+  }
+  const double qt = -kt * dTt + Hf[6 + axis];
+  const double qr = -kr * dTr + Hf[9 + axis];
+  V[0] = 0.0;
+  for (int j = 0; j < 3; ++j) V[1 + j] = sig[j];
+  V[4] = sig[0] * uf[0] + sig[1] * uf[1] + sig[2] * uf[2] + qt + qr;
+  V[5] = qr;
+}
+
+__device__ void euler_flux(int axis, const double U[6], const Prim& p, double F[6]) {
+  const double pr = p.rho * p.tt;
+  const double un = p.u[axis];
+  F[0] = U[0] * un;
+  for (int k = 0; k < 3; ++k) F[1 + k] = U[1 + k] * un + (k == axis ? pr : 0.0);
+  F[4] = (U[4] + pr) * un;
+  F[5] = U[5] * un;
+}
+
+__device__ void hllc_star(int axis, const double U[6], const Prim& p, double SK, double Ss,
+                          double out[6]) {
+  const double pr = p.rho * p.tt;
+  const double f = p.rho * (SK - p.u[axis]) / (SK - Ss);
+  out[0] = f;
+  for (int k = 0; k < 3; ++k) out[1 + k] = f * (k == axis ? Ss : p.u[k]);
+  out[4] = f * (U[4] / p.rho + (Ss - p.u[axis]) * (Ss + pr / (p.rho * (SK - p.u[axis]))));
+  out[5] = f * U[5] / p.rho;
+}
+
+// Flux through face (fi, fj) normal to `axis`: x faces are (fx, iy) with
+// fx in [0, nx], y faces (ix, fy) with fy in [0, ny].
+__global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && axis == 0) {
+    // reset the accumulators of the next iteration's reductions
+    s.red[((it + 1) & 1) * 2 + 0] = 0x7FF0000000000000ull;  // +inf
+    s.red[((it + 1) & 1) * 2 + 1] = 0ull;
+  }
+  const int C = g.nx * g.ny;
+  const int nfa = axis == 0 ? g.nx + 1 : g.nx;
+  const int nfb = axis == 0 ? g.ny : g.ny + 1;
+  if (t >= nfa * nfb) return;
+  const int fa = t % nfa, fb = t / nfa;  // axis 0: fa = fx, fb = iy; axis 1: fa = ix, fb = fy
+  const int n = axis == 0 ? g.nx : g.ny;
+  const int f = axis == 0 ? fa : fb;      // face index along the axis
+  const double h = axis == 0 ? g.hx : g.hy;
+  const int periodic = g.bc_periodic[axis];
+  auto cell_at = [&](int along) {
+    return axis == 0 ? along + g.nx * fb : fa + g.nx * along;
+  };
+  auto cell_xy = [&](int along, int* ix, int* iy) {
+    if (axis == 0) { *ix = along; *iy = fb; } else { *ix = fa; *iy = along; }
+  };
+  double F[6];
+  if (periodic || (f > 0 && f < n)) {
+    const int al = (f - 1 + n) % n, ar = f % n;
+    const int cl = cell_at(al), cr = cell_at(ar);
+    const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
+    double Ul[6], Ur[6], Fl[6], Fr[6];
+    for (int k = 0; k < 6; ++k) {
+      Ul[k] = s.W[k * C + cl];
+      Ur[k] = s.W[k * C + cr];
+    }
+    euler_flux(axis, Ul, pl, Fl);
+    euler_flux(axis, Ur, pr, Fr);
+    const double cL = sqrt(g.gam * pl.tt), cR = sqrt(g.gam * pr.tt);
+    const double SL = fmin(pl.u[axis] - cL, pr.u[axis] - cR);
+    const double SR = fmax(pl.u[axis] + cL, pr.u[axis] + cR);
+    const double pL = pl.rho * pl.tt, pR = pr.rho * pr.tt;
+    const double Ss = (pR - pL + pl.rho * pl.u[axis] * (SL - pl.u[axis]) -
+                       pr.rho * pr.u[axis] * (SR - pr.u[axis])) /
+                      (pl.rho * (SL - pl.u[axis]) - pr.rho * (SR - pr.u[axis]));
+    if (SL >= 0.0) {
+      for (int k = 0; k < 6; ++k) F[k] = Fl[k];
+    } else if (Ss >= 0.0) {
+      double Us[6];
+      hllc_star(axis, Ul, pl, SL, Ss, Us);
+      for (int k = 0; k < 6; ++k) F[k] = Fl[k] + SL * (Us[k] - Ul[k]);
+    } else if (SR > 0.0) {
+      double Us[6];
+      hllc_star(axis, Ur, pr, SR, Ss, Us);
+      for (int k = 0; k < 6; ++k) F[k] = Fr[k] + SR * (Us[k] - Ur[k]);
+    } else {
+      for (int k = 0; k < 6; ++k) F[k] = Fr[k];
+    }
+    // viscous part
+    int ixl, iyl, ixr, iyr;
+    cell_xy(al, &ixl, &iyl);
+    cell_xy(ar, &ixr, &iyr);
+    const double tf = 0.5 * (pl.tt + pr.tt);
+    double uf[3], dn[3], dtn[3], Hf[12];
+    for (int i = 0; i < 3; ++i) {
+      uf[i] = 0.5 * (pl.u[i] + pr.u[i]);
+      dn[i] = (pr.u[i] - pl.u[i]) / h;
+      dtn[i] = g.dim == 2 ? 0.5 * (dcen_u(g, s.W, C, ixl, iyl, i, 1 - axis) +
+                                   dcen_u(g, s.W, C, ixr, iyr, i, 1 - axis))
+                          : 0.0;
+    }
+    for (int k = 0; k < 12; ++k) Hf[k] = 0.5 * (s.H[k * C + cl] + s.H[k * C + cr]);
+    double V[6];
+    visc_flux(g, axis, tf, uf, dn, dtn, (pr.tt - pl.tt) / h, (pr.tr - pl.tr) / h, Hf, V);
+    for (int k = 0; k < 6; ++k) F[k] += V[k];
+  } else {
+    // wall face: Dirichlet state, zero mass flux
+    const int side = f == 0 ? 0 : 1;
+    const int face = 2 * axis + side;
+    const int al = side == 0 ? 0 : n - 1;
+    const int c = cell_at(al);
+    int ix, iy;
+    cell_xy(al, &ix, &iy);
+    const Prim p = prim_of(s.W, C, c, g.dr);
+    const int nmax = g.nx > g.ny ? g.nx : g.ny;
+    const int wi = axis == 0 ? fb : fa;  // position along the wall
+    const double* wv = s.wall + (size_t)face * 5 * nmax;
+    const double uw[3] = {wv[0 * nmax + wi], wv[1 * nmax + wi], wv[2 * nmax + wi]};
+    const double ttw = wv[3 * nmax + wi], trw = wv[4 * nmax + wi];
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    double dn[3], dtn[3], Hf[12];
+    for (int i = 0; i < 3; ++i) {
+      dn[i] = sgn * (p.u[i] - uw[i]) / (0.5 * h);
+      dtn[i] = g.dim == 2 ? dcen_u(g, s.W, C, ix, iy, i, 1 - axis) : 0.0;
+    }
+    for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
+    double V[6];
+    visc_flux(g, axis, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / (0.5 * h),
+              sgn * (p.tr - trw) / (0.5 * h), Hf, V);
+    for (int k = 0; k < 6; ++k) F[k] = V[k];
+    F[1 + axis] += p.rho * p.tt;
+    F[0] = 0.0;
+  }
+  double* out = axis == 0 ? s.Fx : s.Fy;
+  const int nf = nfa * nfb;
+  for (int k = 0; k < 6; ++k) out[(size_t)k * nf + t] = F[k];
+}
+
+__device__ double inv_local_dt(const SynthGrid& g, const Prim& p) {
+  const double mu = g.mu0 * pow(p.tt, g.omega);
+  double kt, kr;
+  conductivities(g, mu, &kt, &kr);
+  const double c = sqrt(g.gam * p.tt);
+  const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
+  double inv = 0.0;
+  inv += (fabs(p.u[0]) + c) / g.hx + 2.0 * nu / (g.hx * g.hx);
+  if (g.dim == 2) inv += (fabs(p.u[1]) + c) / g.hy + 2.0 * nu / (g.hy * g.hy);
+  return inv;
+}
+
+__device__ double dt_bound(const SynthGrid& g, const Prim& p) {
+  const double mu = g.mu0 * pow(p.tt, g.omega);
+  const double tau = mu / (p.rho * p.tt);
+  return fmin(g.cfl / inv_local_dt(g, p), 0.5 * g.zrot * tau);
+}
+
+// Positive doubles order like their bit patterns: min/max via 64-bit atomics.
+__device__ __forceinline__ void red_min(unsigned long long* a, double v) {
+  atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void red_max(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  double dtb = 0.0, ch = 0.0;
+  if (c < C) {
+    const double dtau = __longlong_as_double((long long)s.red[(it & 1) * 2 + 0]);
+    const int ix = c % g.nx, iy = c / g.nx;
+    const Prim p = prim_of(s.W, C, c, g.dr);
+    double R[6];
+    const int nfx = (g.nx + 1) * g.ny;
+    for (int k = 0; k < 6; ++k) {
+      const double* Fx = s.Fx + (size_t)k * nfx;
+      R[k] = -(Fx[ix + 1 + (g.nx + 1) * iy] - Fx[ix + (g.nx + 1) * iy]) / g.hx;
+      if (g.dim == 2) {
+        const double* Fy = s.Fy + (size_t)k * (g.nx * (g.ny + 1));
+        R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.hy;
+      }
+    }
+    const double mu = g.mu0 * pow(p.tt, g.omega);
+    const double tau = mu / (p.rho * p.tt);
+    const double T = (3.0 * p.tt + g.dr * p.tr) / (3.0 + g.dr);
+    R[5] += 0.5 * g.dr * p.rho * (T - p.tr) / (g.zrot * tau);
+    for (int k = 0; k < 6; ++k) s.Wn[k * C + c] = s.W[k * C + c] + dtau * R[k];
+    const Prim q = prim_of(s.Wn, C, c, g.dr);
+    ch = fabs(q.rho - p.rho) / p.rho;
+    for (int k = 0; k < 3; ++k) ch = fmax(ch, fabs(q.u[k] - p.u[k]) / sqrt(p.tt));
+    ch = fmax(ch, fabs(q.tt - p.tt) / p.tt);
+    ch = fmax(ch, fabs(q.tr - p.tr) / fmax(p.tr, 1e-300));
+    dtb = dt_bound(g, q);
+  }
+  // block reductions, then one atomic per block
+  __shared__ double s_min[4], s_max[4];
+  double mn = c < C ? dtb : INFINITY, mx = ch;
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, off));
+    mx = fmax(mx, __shfl_xor(mx, off));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_min[w] = mn;
+    s_max[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      mn = fmin(mn, s_min[k]);
+      mx = fmax(mx, s_max[k]);
+    }
+    red_min(&s.red[((it + 1) & 1) * 2 + 0], mn);
+    red_max(&s.red[((it + 1) & 1) * 2 + 1], mx);
+  }
+}
+
+// Initial conservative state, wall face values and the first pseudo-time step.
+__global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* wall, int mode,
+                             const double* wall_cfg, unsigned long long* red) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  // iteration 1 reads its step from the parity-1 slot
+  if (c == 0) {
+    red[2] = 0x7FF0000000000000ull;
+    red[3] = 0ull;
+  }
+  if (c >= C) return;
+  const double rho = m[c];
+  const double u[3] = {m[C + c], m[2 * C + c], m[3 * C + c]};
+  const double tt = m[4 * C + c], tr = m[5 * C + c];
+  W[c] = rho;
+  for (int k = 0; k < 3; ++k) W[(1 + k) * C + c] = rho * u[k];
+  W[4 * C + c] = rho * (0.5 * (3.0 * tt + g.dr * tr) + 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+  W[5 * C + c] = rho * 0.5 * g.dr * tr;
+  const int ix = c % g.nx, iy = c / g.nx;
+  const int nmax = g.nx > g.ny ? g.nx : g.ny;
+  for (int face = 0; face < (g.dim == 2 ? 4 : 2); ++face) {
+    const int axis = face >> 1, side = face & 1;
+    if (g.bc_periodic[axis]) continue;
+    const int along = axis == 0 ? ix : iy;
+    if (along != (side == 0 ? 0 : (axis == 0 ? g.nx : g.ny) - 1)) continue;
+    const int wi = axis == 0 ? iy : ix;
+    double* wv = wall + (size_t)face * 5 * nmax;
+    for (int k = 0; k < 3; ++k)
+      wv[k * nmax + wi] = (k == axis) ? 0.0 : (mode == 0 ? wall_cfg[face * 4 + 1 + k] : u[k]);
+    wv[3 * nmax + wi] = mode == 0 ? wall_cfg[face * 4] : tt;
+    wv[4 * nmax + wi] = mode == 0 ? wall_cfg[face * 4] : tr;
+  }
+  Prim p;
+  p.rho = rho;
+  for (int k = 0; k < 3; ++k) p.u[k] = u[k];
+  p.tt = tt;
+  p.tr = tr;
+  red_min(&red[2], dt_bound(g, p));
+}
+
+__global__ void k_synth_mask_hot(const double* hot, const uint8_t* mask, double* H, int C) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const bool off = hot == nullptr || (mask != nullptr && mask[c] != 0);
+  for (int k = 0; k < 12; ++k) H[(size_t)k * C + c] = off ? 0.0 : hot[(size_t)k * C + c];
+}
+
+__global__ void k_synth_out(SynthGrid g, const double* W, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  if (c >= C) return;
+  const Prim p = prim_of(W, C, c, g.dr);
+  out[c] = p.rho;
+  for (int k = 0; k < 3; ++k) out[(1 + k) * C + c] = p.u[k];
+  out[4 * C + c] = p.tt;
+  out[5 * C + c] = p.tr;
+}
+
+}  // namespace dig
+
+using namespace dig;
+
+namespace {
+thread_local std::string g_serr;
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct SynthLayout {
+  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, total;
+};
+
+SynthLayout synth_layout(const dig_config* c) {
+  const size_t C = (size_t)c->nx * c->ny;
+  const size_t nmax = c->nx > c->ny ? c->nx : c->ny;
+  SynthLayout L;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o = al256(o + b);
+    return r;
+  };
+  L.W0 = take(8 * 6 * C);
+  L.W1 = take(8 * 6 * C);
+  L.Fx = take(8 * 6 * (c->nx + 1) * (size_t)c->ny);
+  L.Fy = take(8 * 6 * (size_t)c->nx * (c->ny + 1));
+  L.H = take(8 * 12 * C);
+  L.wall = take(8 * 4 * 5 * nmax);
+  L.wcfg = take(8 * 16);
+  L.red = take(8 * 4);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" {
+
+size_t dig_synth_workspace_bytes(const dig_config* cfg) {
+  if (!cfg || cfg->nx < 1 || cfg->ny < 1) return 0;
+  return synth_layout(cfg).total;
+}
+
+dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const double* m_half,
+                       const double* hot, const uint8_t* mask, double* m_next,
+                       void* workspace, size_t ws_bytes, int32_t max_iter, double tol,
+                       int32_t* iters, double* change, dig_stream_t stream) {
+  if (!cfg || !opts || !m_half || !m_next || !workspace || !iters || !change) return DIG_ERR_INVALID;
+  if (cfg->dim != 1 && cfg->dim != 2) return DIG_ERR_INVALID;
+  if (cfg->dim == 1 && cfg->ny != 1) return DIG_ERR_INVALID;
+  if (max_iter < 0 || !(opts->cfl > 0.0)) return DIG_ERR_INVALID;
+  const SynthLayout L = synth_layout(cfg);
+  if (ws_bytes < L.total) return DIG_ERR_INVALID;
+  for (int ax = 0; ax < cfg->dim; ++ax)
+    if ((cfg->bc[2 * ax].type == DIG_BC_PERIODIC) != (cfg->bc[2 * ax + 1].type == DIG_BC_PERIODIC))
+      return DIG_ERR_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* w = (unsigned char*)workspace;
+  SynthGrid g;
+  memset(&g, 0, sizeof(g));
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.dim = cfg->dim;
+  g.dr = cfg->dr;
+  g.hx = cfg->lx / cfg->nx;
+  g.hy = cfg->dim == 2 ? cfg->ly / cfg->ny : 1.0;
+  g.mu0 = cfg->kn * sqrt(2.0 / M_PI);
+  g.omega = cfg->omega;
+  g.zrot = cfg->zrot;
+  g.gam = (5.0 + cfg->dr) / (3.0 + cfg->dr);
+  g.cv = (3.0 + cfg->dr) / 2.0;
+  g.cfl = opts->cfl;
+  g.Att = opts->A[0];
+  g.Atr = opts->A[1];
+  g.Art = opts->A[2];
+  g.Arr = opts->A[3];
+  if (!(fabs(g.Att * g.Arr - g.Atr * g.Art) > 0.0)) return DIG_ERR_INVALID;
+  g.bc_periodic[0] = cfg->bc[0].type == DIG_BC_PERIODIC;
+  g.bc_periodic[1] = cfg->dim == 2 ? cfg->bc[2].type == DIG_BC_PERIODIC : 1;
+  const int C = g.nx * g.ny;
+  double wcfg[16];
+  for (int f = 0; f < 4; ++f) {
+    wcfg[f * 4] = cfg->bc[f].T;
+    for (int k = 0; k < 3; ++k) wcfg[f * 4 + 1 + k] = cfg->bc[f].U[k];
+  }
+  double* W0 = (double*)(w + L.W0);
+  double* W1 = (double*)(w + L.W1);
+  double* H = (double*)(w + L.H);
+  double* wall = (double*)(w + L.wall);
+  double* dwcfg = (double*)(w + L.wcfg);
+  unsigned long long* red = (unsigned long long*)(w + L.red);
+  if (hipMemcpyAsync(dwcfg, wcfg, sizeof(wcfg), hipMemcpyHostToDevice, s) != hipSuccess)
+    return DIG_ERR_HIP;
+  const int bs = 256, nb = (C + bs - 1) / bs;
+  hipLaunchKernelGGL(k_synth_mask_hot, dim3(nb), dim3(bs), 0, s, hot, mask, H, C);
+  hipLaunchKernelGGL(k_synth_init, dim3(nb), dim3(bs), 0, s, g, m_half, W0, wall,
+                     opts->wall_mode, (const double*)dwcfg, red);
+  const int check = opts->check_every > 0 ? opts->check_every : 32;
+  double* cur = W0;
+  double* nxt = W1;
+  int it = 0;
+  double last = INFINITY;
+  for (it = 1; it <= max_iter; ++it) {
+    SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
+    const int nfx = (g.nx + 1) * g.ny;
+    hipLaunchKernelGGL(k_synth_flux, dim3((nfx + bs - 1) / bs), dim3(bs), 0, s, g, a, 0, it);
+    if (g.dim == 2) {
+      const int nfy = g.nx * (g.ny + 1);
+      hipLaunchKernelGGL(k_synth_flux, dim3((nfy + bs - 1) / bs), dim3(bs), 0, s, g, a, 1, it);
+    }
+    hipLaunchKernelGGL(k_synth_update, dim3(nb), dim3(bs), 0, s, g, a, it);
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+    if (it % check == 0 || it == max_iter) {
+      unsigned long long bits = 0;
+      if (hipMemcpyAsync(&bits, red + ((it + 1) & 1) * 2 + 1, 8, hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return DIG_ERR_HIP;
+      double v;
+      memcpy(&v, &bits, 8);
+      last = v;
+      if (!(v >= 0.0)) return DIG_ERR_NUMERIC;
+      if (v < tol) break;
+    }
+  }
+  if (it > max_iter) it = max_iter;
+  hipLaunchKernelGGL(k_synth_out, dim3(nb), dim3(bs), 0, s, g, cur, m_next);
+  if (hipGetLastError() != hipSuccess) return DIG_ERR_HIP;
+  *iters = it;
+  *change = last;
+  return DIG_OK;
+}
+
+}  // extern "C"

@@ -204,3 +204,35 @@ class DSMC:
         L.check(self.lib.dig_constants(self.ctx, inst, out))
         return dict(csigma=out[0], pinelastic=out[1], mu0=out[2], volume=out[3],
                     sgmax_default=out[4])
+
+
+def synth_solve(w: dict, m_half: torch.Tensor, hot: torch.Tensor | None = None,
+                mask: torch.Tensor | None = None, A=None, cfl: float = 0.5,
+                wall_mode: str = "dsmc", max_iter: int = 2000, tol: float = 1e-5,
+                check_every: int = 32):
+    """Synthetic-equation solve on the GPU; returns (m_next [6, C], iterations,
+    last relative change)."""
+    lib = L.load()
+    cfg = L.make_config(w)
+    nc = w["nx"] * w.get("ny", 1)
+    dev = m_half.device
+    ws = torch.empty(int(lib.dig_synth_workspace_bytes(C.byref(cfg))), dtype=torch.uint8,
+                     device=dev)
+    opts = L.DigSynthOpts()
+    om = w["omega"]
+    A = A if A is not None else (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * om))
+    for k in range(4):
+        opts.A[k] = float(A[k])
+    opts.cfl = float(cfl)
+    opts.wall_mode = {"wall": 0, "dsmc": 1}[wall_mode]
+    opts.check_every = int(check_every)
+    m = m_half.contiguous()
+    out = torch.empty((6, nc), dtype=torch.float64, device=dev)
+    h = hot.contiguous() if hot is not None else None
+    mk = mask.contiguous() if mask is not None else None
+    it = C.c_int32(0)
+    ch = C.c_double(0.0)
+    L.check(lib.synth_solve(C.byref(cfg), C.byref(opts), _ptr(m), _ptr(h) if h is not None else None,
+                            _ptr(mk) if mk is not None else None, _ptr(out), _ptr(ws), ws.numel(),
+                            int(max_iter), float(tol), C.byref(it), C.byref(ch), _stream()))
+    return out, it.value, ch.value
