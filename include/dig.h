@@ -225,6 +225,44 @@ enum { DIG_K_MOVE = 0, DIG_K_SCAN = 1, DIG_K_PLACE = 2, DIG_K_ORDER = 3, DIG_K_C
 dig_status dsmc_profile(dig_ctx* ctx, int32_t mode, double* ms_host, int64_t* launches_host,
                         dig_stream_t stream);
 
+/* Launch configuration of the step kernels.  group_particles / group_cells as
+ * in dsmc_create; seq_max: cells with at most this many particles run their
+ * collision candidates in order on one lane, larger cells in parallel rounds
+ * (range [0, 4096]).  Every choice gives bit-identical results; only the speed
+ * differs.  ms_per_step is filled by dsmc_autotune (0 otherwise). */
+typedef struct {
+  int32_t group_particles;
+  int32_t group_cells;
+  int32_t seq_max;
+  double ms_per_step;
+} dig_tuning;
+
+/* Reads the current tuning into *out (if non-null), then applies *in (if
+ * non-null).  Host only.  Errors: DIG_ERR_INVALID (range; nothing changed),
+ * DIG_ERR_STATE (a partial step is pending). */
+dig_status dsmc_tuning(dig_ctx* ctx, const dig_tuning* in_host, dig_tuning* out_host);
+
+/* Autotuner for the step kernels: coordinate search over group_particles in
+ * {512, 1024, 2048, 4096}, group_cells in {32, 64, 128, 256} and seq_max in
+ * {0, 64, 128, 192, 384}, timing steps_per_trial real steps per candidate with
+ * HIP events on `stream` (one untimed step before each).  The timed steps are
+ * ordinary steps of the simulation: the state advances by every step taken,
+ * exactly as dsmc_step would advance it, whichever configuration ran them.
+ * cache_path (nullable): a text file of lines
+ *   "<arch> <dim> <log2 particles> <log2 cells> <T> <Gc> <seq_max> <ms>";
+ * a line matching this device and size class is applied without trials, and a
+ * new choice is appended.  The choice is applied and copied into *out.
+ * Synchronises.  Errors: DIG_ERR_STATE, DIG_ERR_HIP, DIG_ERR_INVALID. */
+dig_status dsmc_autotune(dig_ctx* ctx, int32_t steps_per_trial, const char* cache_path,
+                         dig_tuning* out_host, dig_stream_t stream);
+
+/* nsteps DSMC steps as one HIP graph launched on `stream`: the first call for
+ * a given (nsteps, buffer parity, particle count, tuning) captures the step
+ * kernels on a stream of the library's own, later calls replay the
+ * instantiated graph.  Results are identical to dsmc_step.  Not available
+ * while dsmc_profile is enabled.  Errors: DIG_ERR_STATE, DIG_ERR_HIP. */
+dig_status dsmc_step_graph(dig_ctx* ctx, int32_t nsteps, dig_stream_t stream);
+
 const char* dig_last_error(void);
 void dsmc_destroy(dig_ctx* ctx);
 

@@ -52,11 +52,19 @@ class DigCounters(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class DigTuning(C.Structure):
+    _fields_ = [("group_particles", C.c_int32), ("group_cells", C.c_int32),
+                ("seq_max", C.c_int32), ("ms_per_step", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
            "dsmc_sample", "dig_adjust", "closure_assemble", "dig_synth_workspace_bytes",
-           "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dig_last_error",
-           "dsmc_destroy"]
+           "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_tuning",
+           "dsmc_autotune", "dsmc_step_graph", "dig_last_error", "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
 _lib = None
@@ -87,6 +95,9 @@ def load(path: str = LIB_PATH):
     L.dsmc_init.argtypes = [vp, vp, C.c_int32, vp]
     L.dsmc_inject.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, vp]
     L.dsmc_step.argtypes = [vp, C.c_int32, vp]
+    L.dsmc_step_graph.argtypes = [vp, C.c_int32, vp]
+    L.dsmc_tuning.argtypes = [vp, C.POINTER(DigTuning), C.POINTER(DigTuning)]
+    L.dsmc_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(DigTuning), vp]
     L.dsmc_stage.argtypes = [vp, C.c_int32, vp]
     L.dsmc_sample.argtypes = [vp, C.c_int32, vp, vp]
     L.dig_adjust.argtypes = [vp, vp, C.c_uint32, vp]

@@ -1,5 +1,6 @@
 // Host side of libdig: validation, workspace layout, launches, errors.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -206,6 +207,15 @@ struct dig_ctx {
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
   int32_t seq_max = kSeqMaxDefault;
+  // captured step graphs, keyed by what the captured launches depend on
+  struct Graph {
+    int32_t nsteps, cur, T, Gc, seq;
+    int64_t n;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t cap = nullptr;  // capture stream, default priority
   // event profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;      // pairs (start, stop)
@@ -305,6 +315,42 @@ dig_status check_ctx(dig_ctx* c) {
   return DIG_OK;
 }
 
+// Largest LDS particle stage for group size T: the group target plus room for
+// its last cell, within 48 KiB of LDS; larger groups collide in the
+// destination buffer instead.
+int32_t lds_particles_for(int32_t T, int32_t Gc) {
+  int32_t Lp = T + 512;
+  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
+  return Lp;
+}
+
+dig_status check_tuning(int32_t T, int32_t Gc, int32_t seq) {
+  if (T < kMinGroupParticles || T > 16384)
+    return fail(DIG_ERR_INVALID, "group_particles must lie in [256, 16384]");
+  if (Gc < kMinGroupCells || Gc > 256)
+    return fail(DIG_ERR_INVALID, "group_cells must lie in [32, 256]");
+  if (seq < 0 || seq > 4096) return fail(DIG_ERR_INVALID, "seq_max must lie in [0, 4096]");
+  return DIG_OK;
+}
+
+void apply_tuning(dig_ctx* c, int32_t T, int32_t Gc, int32_t seq) {
+  c->T = T;
+  c->Gc = Gc;
+  c->seq_max = seq;
+  c->Lp = lds_particles_for(T, Gc);
+}
+
+void drop_graphs(dig_ctx* c) {
+  if (c->graphs.empty()) return;
+  // a replay may still be in flight on the caller's stream
+  (void)hipDeviceSynchronize();
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.x);
+    (void)hipGraphDestroy(g.g);
+  }
+  c->graphs.clear();
+}
+
 // Stages must run in order (move, sort, collide): the sort consumes the
 // reservations of the move and the collide consumes the sorted permutation.
 dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
@@ -357,13 +403,10 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   if (st != DIG_OK) return st;
   if (!ws) return fail(DIG_ERR_INVALID, "null workspace");
   if (((uintptr_t)ws) % kAlign) return fail(DIG_ERR_INVALID, "workspace not 256-byte aligned");
-  const char* sm = getenv("DIG_SEQ_MAX");  // collision path threshold (tuning aid)
   const int32_t T = group_particles > 0 ? group_particles : 1024;
   const int32_t Gc = group_cells > 0 ? group_cells : 64;
-  if (T < kMinGroupParticles || T > 16384)
-    return fail(DIG_ERR_INVALID, "group_particles must lie in [256, 16384]");
-  if (Gc < kMinGroupCells || Gc > 256)
-    return fail(DIG_ERR_INVALID, "group_cells must lie in [32, 256]");
+  st = check_tuning(T, Gc, kSeqMaxDefault);
+  if (st != DIG_OK) return st;
   dig_ctx* c = new dig_ctx;
   c->cfg.assign(cfgs, cfgs + n_inst);
   c->n_inst = n_inst;
@@ -371,14 +414,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->dim = cfgs[0].dim;
   c->capacity = capacity;
   c->n_host = capacity;
-  c->T = T;
-  c->Gc = Gc;
-  if (sm) c->seq_max = atoi(sm);
-  // LDS particle stage: the group target plus room for its last cell, within
-  // 48 KiB of LDS; larger groups collide in the destination buffer instead
-  int32_t Lp = T + 512;
-  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
-  c->Lp = Lp;
+  apply_tuning(c, T, Gc, kSeqMaxDefault);
   plan_layout(capacity, C, n_inst, &c->L, &c->I);
   if (ws_bytes < c->L.total_bytes) {
     const std::string msg =
@@ -634,8 +670,163 @@ dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
   return fail(DIG_ERR_INVALID, "bad profile mode");
 }
 
+dig_status dsmc_tuning(dig_ctx* c, const dig_tuning* in, dig_tuning* out) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (out) {
+    out->group_particles = c->T;
+    out->group_cells = c->Gc;
+    out->seq_max = c->seq_max;
+    out->ms_per_step = 0.0;
+  }
+  if (in) {
+    if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+    dig_status st = check_tuning(in->group_particles, in->group_cells, in->seq_max);
+    if (st != DIG_OK) return st;
+    apply_tuning(c, in->group_particles, in->group_cells, in->seq_max);
+  }
+  return DIG_OK;
+}
+
+dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state (call dsmc_init)");
+  if (nsteps < 0) return fail(DIG_ERR_INVALID, "nsteps < 0");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  if (c->prof) return fail(DIG_ERR_STATE, "graph steps need dsmc_profile disabled");
+  if (nsteps == 0) return DIG_OK;
+  const int cur0 = c->cur;
+  dig_ctx::Graph* hit = nullptr;
+  for (auto& g : c->graphs)
+    if (g.nsteps == nsteps && g.cur == cur0 && g.n == c->n_host && g.T == c->T &&
+        g.Gc == c->Gc && g.seq == c->seq_max)
+      hit = &g;
+  if (!hit) {
+    if (c->graphs.size() >= 8) drop_graphs(c);
+    if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    dig_status st = DIG_OK;
+    for (int k = 0; k < nsteps && st == DIG_OK; ++k) st = run_stages(c, DIG_STAGE_ALL, c->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    // nothing ran during capture: the host view of the state is unchanged
+    c->cur = cur0;
+    c->phase = 0;
+    if (st != DIG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    c->graphs.push_back({nsteps, cur0, c->T, c->Gc, c->seq_max, c->n_host, g, x});
+    hit = &c->graphs.back();
+  }
+  HIP_TRY(hipGraphLaunch(hit->x, (hipStream_t)stream));
+  c->cur = cur0 ^ (nsteps & 1);
+  return DIG_OK;
+}
+
+dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_path,
+                         dig_tuning* out, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state (call dsmc_init)");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  if (steps_per_trial < 1) return fail(DIG_ERR_INVALID, "steps_per_trial must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  auto lg2 = [](int64_t v) {
+    int r = 0;
+    while (v > 1) {
+      v >>= 1;
+      ++r;
+    }
+    return r;
+  };
+  const int ln = lg2(c->n_host), lc = lg2(c->ncell);
+  dig_tuning best{c->T, c->Gc, c->seq_max, 0.0};
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char a[64];
+      int d, n, cl, T, Gc, sq;
+      double ms;
+      bool found = false;
+      while (fscanf(f, "%63s %d %d %d %d %d %d %lf", a, &d, &n, &cl, &T, &Gc, &sq, &ms) == 8)
+        if (arch == a && d == c->dim && n == ln && cl == lc &&
+            check_tuning(T, Gc, sq) == DIG_OK) {
+          best = dig_tuning{T, Gc, sq, ms};
+          found = true;
+        }
+      fclose(f);
+      if (found) {
+        apply_tuning(c, best.group_particles, best.group_cells, best.seq_max);
+        if (out) *out = best;
+        return DIG_OK;
+      }
+    }
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  dig_status st = DIG_OK;
+  auto trial = [&](const dig_tuning& t, double* ms) -> dig_status {
+    apply_tuning(c, t.group_particles, t.group_cells, t.seq_max);
+    dig_status r = run_stages(c, DIG_STAGE_ALL, s);
+    if (r != DIG_OK) return r;
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(DIG_ERR_HIP, "event record");
+    for (int k = 0; k < steps_per_trial; ++k)
+      if ((r = run_stages(c, DIG_STAGE_ALL, s)) != DIG_OK) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(DIG_ERR_HIP, "event synchronise");
+    float f = 0.0f;
+    if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fail(DIG_ERR_HIP, "event time");
+    *ms = (double)f / steps_per_trial;
+    return DIG_OK;
+  };
+  st = trial(best, &best.ms_per_step);
+  const int32_t Ts[] = {512, 1024, 2048, 4096};
+  const int32_t Gcs[] = {32, 64, 128, 256};
+  const int32_t Sqs[] = {0, 64, 128, 192, 384};
+  for (int axis = 0; axis < 3 && st == DIG_OK; ++axis) {
+    const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : Sqs;
+    const int nv = axis == 2 ? 5 : 4;
+    const dig_tuning base = best;
+    for (int k = 0; k < nv && st == DIG_OK; ++k) {
+      dig_tuning t = base;
+      int32_t* field = axis == 0 ? &t.group_particles : axis == 1 ? &t.group_cells : &t.seq_max;
+      if (*field == vals[k]) continue;
+      *field = vals[k];
+      st = trial(t, &t.ms_per_step);
+      if (st == DIG_OK && t.ms_per_step < best.ms_per_step) best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  apply_tuning(c, best.group_particles, best.group_cells, best.seq_max);
+  if (st != DIG_OK) return st;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "%s %d %d %d %d %d %d %.6f\n", arch.c_str(), c->dim, ln, lc,
+              best.group_particles, best.group_cells, best.seq_max, best.ms_per_step);
+      fclose(f);
+    }
+  }
+  if (out) *out = best;
+  return DIG_OK;
+}
+
 void dsmc_destroy(dig_ctx* c) {
   if (!c) return;
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (auto& e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

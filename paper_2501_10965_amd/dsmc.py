@@ -153,8 +153,29 @@ class DSMC:
         nid = n if next_id is None else next_id
         L.check(self.lib.dsmc_inject(self.ctx, n, int(step), int(nid), _stream()))
 
-    def step(self, nsteps: int = 1):
-        L.check(self.lib.dsmc_step(self.ctx, int(nsteps), _stream()))
+    def step(self, nsteps: int = 1, graph: bool = False):
+        """nsteps DSMC steps; graph=True launches them as one captured HIP graph."""
+        fn = self.lib.dsmc_step_graph if graph else self.lib.dsmc_step
+        L.check(fn(self.ctx, int(nsteps), _stream()))
+
+    def tuning(self, group_particles=None, group_cells=None, seq_max=None) -> dict:
+        """Current launch configuration; arguments given replace its fields."""
+        cur = L.DigTuning()
+        L.check(self.lib.dsmc_tuning(self.ctx, None, C.byref(cur)))
+        if group_particles is None and group_cells is None and seq_max is None:
+            return cur.as_dict()
+        new = L.DigTuning(group_particles or cur.group_particles, group_cells or cur.group_cells,
+                          cur.seq_max if seq_max is None else seq_max, 0.0)
+        L.check(self.lib.dsmc_tuning(self.ctx, C.byref(new), None))
+        return new.as_dict()
+
+    def autotune(self, steps_per_trial: int = 10, cache_path: str | None = None) -> dict:
+        """Coordinate search over the launch configuration (advances the state)."""
+        out = L.DigTuning()
+        path = cache_path.encode() if cache_path else None
+        L.check(self.lib.dsmc_autotune(self.ctx, int(steps_per_trial), path, C.byref(out),
+                                       _stream()))
+        return out.as_dict()
 
     def stage(self, mask: int):
         L.check(self.lib.dsmc_stage(self.ctx, int(mask), _stream()))
