@@ -1,23 +1,32 @@
 #!/usr/bin/env python
 """DSMC + DIG hot-path benchmark on one MI355X.
 
-Workload: the DIG-coupled 2D lid-driven cavity (200 x 200 cells, 50 particles
-per cell = 2,000,000 particles, Kn = 0.01, lid Ma = 0.3, omega = 0.74, Z = 5,
-N_s = 50).  A timed "step" is one DSMC step (move + walls, cell index + stable
-sort, NTC/VHS/BL collide, FP64 sampling); every N_s steps the DIG cycle runs
-(time-averaged fields, closure assembly, particle modification).  The
-synthetic-equation solve is not part of the hot path; the DIG target in this
-benchmark is the time-averaged DSMC field itself.
+Default workload: the DIG-coupled 2D lid-driven cavity (200 x 200 cells, 50
+particles per cell = 2,000,000 particles, Kn = 0.01, lid Ma = 0.3,
+omega = 0.74, Z = 5, N_s = 50).  A timed "step" is one DSMC step (move + walls,
+cell index + stable sort, NTC/VHS/BL collide, FP64 sampling); every N_s steps
+the DIG cycle runs (time-averaged fields, closure assembly, particle
+modification).  Inside the timed region the kernels are launched eagerly with
+HIP events around each one (the per-kernel durations of the roofline) and the
+modification target is the time-averaged DSMC field.  Two more regions follow
+and are reported beside it: the same loop with the N_s steps as one captured
+HIP graph ("graph_replay"), and the full DIG loop with the synthetic-equation
+solve as the target ("dig_loop").
+
+--workload batch: 64 uneven 1D instances (13,671,119 particles) advanced
+together by graph replays, plain DSMC.
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
-(HIP-event timing inside the timed region) and the FP64 oracle timed on the
-host for a bounded sample of the same workload.
+(HIP events around every kernel inside the timed region), and the FP64 oracle
+timed on the host for a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,52 +35,122 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DSMC particle-steps/s; time-to-steady-state at fixed error, learned vs plain"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of the collide kernel: state read once and written once
-# (x, y, vx, vy, vz, er, id in FP32/u32) plus per-cell start, majorant,
-# instance tag and the FP64 accumulator read and write (17 doubles each way)
+# algorithmic bytes per particle-step of the whole step: state (x[, y], v, er,
+# id) read once and written once
 STATE_BYTES = {1: 24, 2: 28}
-PER_CELL_BYTES = 4 + 2 * 4 + 4 + 2 * 17 * 8
+# collide kernel: v (3 x f32) and er read and written per particle; per cell
+# the start pair (4 B), majorant read + write (8 B), instance tag (4 B) and
+# the FP64 accumulator of 17 sums read + written
+COLLIDE_PARTICLE_BYTES = 32
+PER_CELL_BYTES = 4 + 8 + 4 + 2 * 17 * 8
+KERNEL_SOURCES = ("paper_2501_10965_amd/csrc/dig_kernels.hip",
+                  "paper_2501_10965_amd/csrc/dig_internal.h")
 
 
 def default_A(omega):
     return [2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * omega)]
 
 
-def gpu_run(args):
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_digest:\s*(\w+)", text)
+    f = re.search(r"fetch_bytes_per_dispatch:\s*([\d.eE+]+)", text)
+    w = re.search(r"write_bytes_per_dispatch:\s*([\d.eE+]+)", text)
+    if not (m and f and w) or m.group(1) != source_digest():
+        return None
+    return float(f.group(1)) + float(w.group(1))
+
+
+def roofline(prof, n_avg, ncell, workload):
+    name, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    avg_s = ms / max(launches, 1) / 1e3
+    if name != "collide":
+        return {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2)}
+    alg = COLLIDE_PARTICLE_BYTES * n_avg + PER_CELL_BYTES * ncell
+    ach = alg / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload),
+            "kernel": "k_collide", "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": int(alg)}
+
+
+def summarise(prof, psteps, sec, nsteps, n_avg, ncell, dim, workload):
+    step_bytes = STATE_BYTES[dim] * 2 + PER_CELL_BYTES * ncell / n_avg
+    step_alg = step_bytes * psteps / sec / 1e9
+    return dict(
+        value=psteps / sec, ms_per_step=sec / nsteps * 1e3,
+        roofline=roofline(prof, n_avg, ncell, workload),
+        kernels_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in prof.items() if v[1]},
+        kernel_launches={k: v[1] for k, v in prof.items() if v[1]},
+        step_roofline={"achieved_algorithmic_GBs": round(step_alg, 1),
+                       "frac": round(step_alg / HBM_PEAK_GBS, 4),
+                       "bytes_per_particle_step": round(step_bytes, 2)})
+
+
+def run_cavity(args):
     import torch
 
     import dig_workloads as wl
-    from paper_2501_10965_amd.dsmc import DSMC
+    from paper_2501_10965_amd.dsmc import DSMC, synth_solve
 
     w = wl.cavity_2d(seed=2001)
     ns = w["ns"]
     sim = DSMC(w, group_particles=args.group_particles, group_cells=args.group_cells)
     sim.init()
     A = default_A(w["omega"])
-    cycle = [0]
+    state = {"step": 0, "cycle": 0, "n": sim.counters()["n"]}
 
-    def dig_cycle():
+    def dig_cycle(target=None):
         f = sim.sample("average")
-        sim.closure(f, A, 0.01)
-        sim.adjust(f[0:6].clone(), cycle[0])
+        hot, mask, _, _ = sim.closure(f, A, 0.01)
+        if target == "synth":
+            tgt, it, ch = synth_solve(w, f, hot, mask, A, wall_mode="dsmc",
+                                      max_iter=args.synth_iters, tol=1e-5)
+        else:
+            tgt, it = f[0:6], 0
+        sim.adjust(tgt, state["cycle"])
         sim.reset_average()
-        cycle[0] += 1
+        state["cycle"] += 1
+        state["n"] = sim.counters()["n"]
+        return it
 
-    def run(nsteps, counts):
+    def run(nsteps, counts, target=None, graph=False):
         done = 0
+        its = []
         while done < nsteps:
-            k = min(ns - (sim_step[0] % ns), nsteps - done)
-            sim.step(k)
-            counts.append((k, n_now[0]))
-            sim_step[0] += k
+            k = min(ns - state["step"] % ns, nsteps - done)
+            sim.step(k, graph=graph)
+            counts.append((k, state["n"]))
+            state["step"] += k
             done += k
-            if sim_step[0] % ns == 0:
-                dig_cycle()
-                n_now[0] = sim.counters()["n"]
+            if state["step"] % ns == 0:
+                its.append(dig_cycle(target))
+        return its
 
-    sim_step = [0]
-    n_now = [sim.counters()["n"]]
-    run(args.warmup, [])
+    tuning = None
+    if not args.no_autotune:
+        tuning = sim.autotune(steps_per_trial=5)
+        taken = sim.counters()["step"]
+        state["step"] = taken
+    # warm up to a cycle boundary at or after the requested warmup
+    tgt = -(-max(args.warmup, state["step"]) // ns) * ns
+    run(tgt - state["step"], [], graph=True)
     torch.cuda.synchronize()
     sim.profile("on")
     counts = []
@@ -84,92 +163,171 @@ def gpu_run(args):
     sim.profile("off")
     ctr = sim.counters()
     psteps = sum(k * n for k, n in counts)
-    sec = t1 - t0
     n_avg = psteps / max(args.steps, 1)
-    # dominant kernel
-    name, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
-    avg_s = ms / max(launches, 1) / 1e3
-    dim = w["dim"]
-    ncell = w["nx"] * w["ny"]
-    roof = None
-    if name == "collide":
-        alg = STATE_BYTES[dim] * 2 * n_avg + PER_CELL_BYTES * ncell
-        ach = alg / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_collide", "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_bytes_per_launch": int(alg)}
-    step_alg = (STATE_BYTES[dim] * 2 + PER_CELL_BYTES * ncell / n_avg) * psteps / sec / 1e9
-    out = dict(value=psteps / sec, ms_per_step=sec / args.steps * 1e3, roofline=roof,
-               kernels_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in prof.items()},
-               kernel_launches={k: v[1] for k, v in prof.items()},
-               step_roofline={"achieved_algorithmic_GBs": round(step_alg, 1),
-                              "frac": round(step_alg / HBM_PEAK_GBS, 4),
-                              "bytes_per_particle_step": STATE_BYTES[dim] * 2 +
-                              round(PER_CELL_BYTES * ncell / n_avg, 2)},
-               particles=int(n_avg), cells=ncell, ns=ns, err_bits=ctr["err"],
+    out = summarise(prof, psteps, t1 - t0, args.steps, n_avg, w["nx"] * w["ny"], 2, "cavity")
+    # the same loop with graph-captured steps
+    run((-state["step"]) % ns, [], graph=True)
+    torch.cuda.synchronize()
+    cg = []
+    tg0 = time.perf_counter()
+    run(args.steps, cg, graph=True)
+    torch.cuda.synchronize()
+    tg1 = time.perf_counter()
+    out["graph_replay"] = {"value": sum(k * n for k, n in cg) / (tg1 - tg0),
+                           "unit": "particle-steps/s", "steps": args.steps,
+                           "ms_per_step": (tg1 - tg0) / args.steps * 1e3}
+    # the full DIG loop: N_s steps + closure + synthetic solve + modification
+    dig = None
+    if args.dig_cycles > 0:
+        run((-state["step"]) % ns, [], graph=True)
+        torch.cuda.synchronize()
+        c2 = []
+        t2 = time.perf_counter()
+        its = run(args.dig_cycles * ns, c2, target="synth", graph=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ps2 = sum(k * n for k, n in c2)
+        dig = {"value": ps2 / (t3 - t2), "unit": "particle-steps/s", "cycles": args.dig_cycles,
+               "synth_iterations": its, "ms_per_cycle": (t3 - t2) / args.dig_cycles * 1e3,
+               "dsmc_ms_per_cycle": ns * out["ms_per_step"]}
+    out.update(particles=int(n_avg), cells=w["nx"] * w["ny"], err_bits=ctr["err"],
                collisions_per_particle_step=ctr["accepted"] * 2 / max(ctr["step"] * n_avg, 1),
-               workload=w["name"])
+               tuning=tuning, dig_loop=dig,
+               workload=f"{w['name']} 200x200 cells, 50 ppc (2M particles), Kn 0.01, lid Ma 0.3,"
+                        " DIG every 50 steps (closure + modification toward the time-averaged "
+                        "field in the timed region)")
     return out, w
 
 
-def cpu_baseline(w, steps):
+def run_batch(args):
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd.dsmc import DSMC
+
+    ws = wl.batch_1d(64)
+    sim = DSMC(ws, cap_factor=1.02, group_particles=args.group_particles,
+               group_cells=args.group_cells)
+    sim.init_batch()
+    n = sim.counters()["n"]
+    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
+    graph = 50
+    k0 = sim.counters()["step"]
+    sim.step(max(args.warmup - k0, 0) // graph * graph + graph, graph=True)
+    torch.cuda.synchronize()
+    sim.profile("on")
+    steps = max(graph, args.steps // graph * graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // graph):
+        sim.step(graph)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile("read")
+    sim.profile("off")
+    ctr = sim.counters()
+    ncell = sim.ncell
+    out = summarise(prof, n * steps, t1 - t0, steps, n, ncell, 1, "batch")
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(steps // graph):
+        sim.step(graph, graph=True)
+    torch.cuda.synchronize()
+    tg1 = time.perf_counter()
+    out["graph_replay"] = {"value": n * steps / (tg1 - tg0), "unit": "particle-steps/s",
+                           "steps": steps, "ms_per_step": (tg1 - tg0) / steps * 1e3}
+    out.update(particles=n, cells=ncell, err_bits=ctr["err"], tuning=tuning, dig_loop=None,
+               steps_run=steps,
+               collisions_per_particle_step=ctr["accepted"] * 2 / max(ctr["step"] * n, 1),
+               workload="64 uneven 1D Couette/Fourier instances, 13,671,119 particles, Kn "
+                        "1e-3..1, plain DSMC, 50-step graphs")
+    args.steps = steps
+    return out, ws[63]
+
+
+def cpu_baseline(w, steps, dig: bool):
     import oracle
 
     nthreads = 1
     s = oracle.new_state(w)
     t0 = time.perf_counter()
-    done = 0
     ps = 0
     A = default_A(w["omega"])
     it = 0
-    while done < steps:
-        k = min(w["ns"], steps - done)
-        for _ in range(k):
-            ps += s.n
-            s.step()
-        done += k
-        if done % w["ns"] == 0:
+    ns = w.get("ns", 50)
+    for done in range(1, steps + 1):
+        ps += s.n
+        s.step()
+        if dig and done % ns == 0:
             f = s.fields()
             oracle.closure(w, f, A, 0.01)
             s.adjust(f[0:6].copy(), it)
             s.reset_average()
             it += 1
     sec = time.perf_counter() - t0
+    what = (f"{steps} DSMC steps with {steps // ns} DIG cycles (closure + modification)"
+            if dig else f"{steps} DSMC steps")
     return {"value": ps / sec, "unit": "particle-steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{w['name']}: {s.n} particles, {steps} DSMC steps with "
-                      f"{steps // w['ns']} DIG cycles (closure + adjust), FP64, single thread",
+            "sample": f"{w['name']}: {s.n} particles, {what}, FP64, single thread",
             "seconds": round(sec, 2)}
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "dispatches": 3}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=150)
+    ap.add_argument("--workload", choices=["cavity", "batch"], default="cavity")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--dig-cycles", type=int, default=2)
+    ap.add_argument("--synth-iters", type=int, default=2000)
     ap.add_argument("--group-particles", type=int, default=0)
     ap.add_argument("--group-cells", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the DSMC domain decomposition "
               "across GPUs is a design, not an implementation); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    res, w = gpu_run(args)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_steps)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.workload == "batch":
+        res, wcpu = run_batch(args)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, 300, dig=False)
+    else:
+        res, wcpu = run_cavity(args)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, args.cpu_steps, dig=True)
     line = {
         "metric": METRIC, "value": res["value"], "unit": "particle-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": res["workload"] + " (DIG-coupled, N_s=50; DIG target = "
-                   "time-averaged DSMC field)", "particles": res["particles"],
-                   "cells": res["cells"], "parallelism": "single GPU"},
+        "config": {"workload": res["workload"], "particles": res["particles"],
+                   "cells": res["cells"], "parallelism": "single GPU",
+                   "tuning": res["tuning"]},
         "roofline": res["roofline"], "cpu_baseline": cpu,
         "step_roofline": res["step_roofline"], "kernels_us": res["kernels_us"],
         "kernel_launches": res["kernel_launches"], "err_bits": res["err_bits"],
         "collisions_per_particle_step": res["collisions_per_particle_step"],
+        "graph_replay": res["graph_replay"], "dig_loop": res["dig_loop"],
+        "kernel_source_digest": source_digest(),
     }
     print(json.dumps(line), flush=True)
 

@@ -257,10 +257,12 @@ dig_status dsmc_autotune(dig_ctx* ctx, int32_t steps_per_trial, const char* cach
                          dig_tuning* out_host, dig_stream_t stream);
 
 /* nsteps DSMC steps as one HIP graph launched on `stream`: the first call for
- * a given (nsteps, buffer parity, particle count, tuning) captures the step
+ * a given (nsteps, buffer parity, particle count rounded up to a 1/64 share
+ * of the capacity, tuning) captures the step
  * kernels on a stream of the library's own, later calls replay the
  * instantiated graph.  Results are identical to dsmc_step.  Not available
- * while dsmc_profile is enabled.  Errors: DIG_ERR_STATE, DIG_ERR_HIP. */
+ * while dsmc_profile is enabled (per-kernel events need eager launches).
+ * Errors: DIG_ERR_STATE, DIG_ERR_HIP. */
 dig_status dsmc_step_graph(dig_ctx* ctx, int32_t nsteps, dig_stream_t stream);
 
 const char* dig_last_error(void);

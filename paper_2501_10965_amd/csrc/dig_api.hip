@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -207,6 +208,12 @@ struct dig_ctx {
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
   int32_t seq_max = kSeqMaxDefault;
+  // event pairs (start, stop) bracketing launches, with the kernel kind of each
+  struct EvPool {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+  };
   // captured step graphs, keyed by what the captured launches depend on
   struct Graph {
     int32_t nsteps, cur, T, Gc, seq;
@@ -218,9 +225,7 @@ struct dig_ctx {
   hipStream_t cap = nullptr;  // capture stream, default priority
   // event profiling
   bool prof = false;
-  std::vector<hipEvent_t> ev;      // pairs (start, stop)
-  std::vector<int> ev_kind;
-  size_t ev_used = 0;
+  EvPool eager;
   double prof_ms[DIG_NKERNELS] = {0};
   int64_t prof_n[DIG_NKERNELS] = {0};
 };
@@ -264,41 +269,73 @@ StepArgs args(const dig_ctx* c) {
   a.group_cells = c->Gc;
   a.lds_particles = c->Lp;
   a.seq_max = c->seq_max;
-  a.n_upper = c->n_host;
+  // launch bound for the particle kernels (they read the exact count on the
+  // device): the host count rounded up to a 1/64 share of the capacity, so
+  // that the small count changes of a DIG adjustment keep captured graphs valid
+  const int64_t q = std::max<int64_t>(4096, c->capacity / 64);
+  a.n_upper = std::max<int64_t>(1, std::min<int64_t>(c->capacity, (c->n_host + q - 1) / q * q));
   return a;
 }
 
-// Folds the recorded event pairs into the per-kernel totals.
+hipError_t pool_grow(dig_ctx::EvPool* p, size_t pairs) {
+  while (p->kind.size() < pairs) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    p->ev.push_back(a);
+    p->ev.push_back(b);
+    p->kind.push_back(0);
+  }
+  return hipSuccess;
+}
+
+void pool_free(dig_ctx::EvPool* p) {
+  for (auto& e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->kind.clear();
+  p->used = 0;
+}
+
+hipError_t pool_fold(dig_ctx* c, const dig_ctx::EvPool& p) {
+  for (size_t k = 0; k < p.used; ++k) {
+    float ms = 0.0f;
+    hipError_t e = hipEventElapsedTime(&ms, p.ev[2 * k], p.ev[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    c->prof_ms[p.kind[k]] += ms;
+    c->prof_n[p.kind[k]] += 1;
+  }
+  return hipSuccess;
+}
+
+// Folds the recorded event pairs into the per-kernel totals; synchronises
+// `s`, where all of them were enqueued.
 hipError_t prof_fold(dig_ctx* c, hipStream_t s) {
-  if (c->ev_used == 0) return hipSuccess;
+  if (c->eager.used == 0) return hipSuccess;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  for (size_t k = 0; k < c->ev_used; ++k) {
-    float ms = 0.0f;
-    e = hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]);
-    if (e != hipSuccess) return e;
-    c->prof_ms[c->ev_kind[k]] += ms;
-    c->prof_n[c->ev_kind[k]] += 1;
-  }
-  c->ev_used = 0;
-  return hipSuccess;
+  e = pool_fold(c, c->eager);
+  c->eager.used = 0;
+  return e;
 }
 
 // Runs one launch, bracketed by events when profiling is on.
 template <class F>
 hipError_t timed(dig_ctx* c, int kind, hipStream_t s, F&& launch) {
   if (!c->prof) return launch();
-  if (c->ev_used == c->ev_kind.size()) {
+  dig_ctx::EvPool* p = &c->eager;
+  if (p->used == p->kind.size()) {
     hipError_t e = prof_fold(c, s);
     if (e != hipSuccess) return e;
   }
-  const size_t k = c->ev_used++;
-  c->ev_kind[k] = kind;
-  hipError_t e = hipEventRecord(c->ev[2 * k], s);
+  const size_t k = p->used++;
+  p->kind[k] = kind;
+  hipError_t e = hipEventRecord(p->ev[2 * k], s);
   if (e != hipSuccess) return e;
   e = launch();
   if (e != hipSuccess) return e;
-  return hipEventRecord(c->ev[2 * k + 1], s);
+  return hipEventRecord(p->ev[2 * k + 1], s);
 }
 
 __global__ void k_counts_from_start(const int32_t* start, int32_t* counts, int C) {
@@ -639,13 +676,8 @@ dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
   if (check_ctx(c)) return DIG_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   if (mode == 1) {
-    if (c->ev.empty()) {
-      const size_t pairs = 4096;
-      c->ev.resize(2 * pairs);
-      c->ev_kind.resize(pairs);
-      for (auto& e : c->ev) HIP_TRY(hipEventCreate(&e));
-    }
-    c->ev_used = 0;
+    HIP_TRY(pool_grow(&c->eager, 4096));
+    c->eager.used = 0;
     for (int k = 0; k < DIG_NKERNELS; ++k) {
       c->prof_ms[k] = 0.0;
       c->prof_n[k] = 0;
@@ -695,10 +727,11 @@ dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
   if (c->prof) return fail(DIG_ERR_STATE, "graph steps need dsmc_profile disabled");
   if (nsteps == 0) return DIG_OK;
   const int cur0 = c->cur;
+  const int64_t nup = args(c).n_upper;
   dig_ctx::Graph* hit = nullptr;
   for (auto& g : c->graphs)
-    if (g.nsteps == nsteps && g.cur == cur0 && g.n == c->n_host && g.T == c->T &&
-        g.Gc == c->Gc && g.seq == c->seq_max)
+    if (g.nsteps == nsteps && g.cur == cur0 && g.n == nup && g.T == c->T && g.Gc == c->Gc &&
+        g.seq == c->seq_max)
       hit = &g;
   if (!hit) {
     if (c->graphs.size() >= 8) drop_graphs(c);
@@ -711,18 +744,17 @@ dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
     // nothing ran during capture: the host view of the state is unchanged
     c->cur = cur0;
     c->phase = 0;
-    if (st != DIG_OK) {
+    if (st != DIG_OK || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return st;
+      return st != DIG_OK ? st : hip_fail(e, "hipStreamEndCapture");
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       (void)hipGraphDestroy(g);
       return hip_fail(e, "hipGraphInstantiate");
     }
-    c->graphs.push_back({nsteps, cur0, c->T, c->Gc, c->seq_max, c->n_host, g, x});
+    c->graphs.push_back({nsteps, cur0, c->T, c->Gc, c->seq_max, nup, g, x});
     hit = &c->graphs.back();
   }
   HIP_TRY(hipGraphLaunch(hit->x, (hipStream_t)stream));
@@ -827,7 +859,7 @@ void dsmc_destroy(dig_ctx* c) {
   if (!c) return;
   drop_graphs(c);
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  pool_free(&c->eager);
   delete c;
 }
 

@@ -182,3 +182,22 @@ def test_full_batch_graph_and_sampled_instance_parity():
         res = _instance_parity(w, sl(pre), st[c0:c1 + 1] - p0, sg[c0:c1], step, sl(moved),
                                gperm[p0:p1] - p0, gstart[c0:c1 + 1] - p0, sl(post))
         assert res["candidates"] > 0
+
+
+def test_graph_steps_refused_while_profiling():
+    """Per-kernel event timing needs eager launches: a graph step with
+    profiling enabled is refused and changes nothing."""
+    from paper_2501_10965_amd import _lib as L
+    w = wl.cavity_2d(seed=304, n=20, ppc=20, kn=0.02)
+    eager, graph = _pair(w)
+    graph.profile("on")
+    with pytest.raises(L.DigError) as e:
+        graph.step(5, graph=True)
+    assert e.value.code == L.DIG_ERR_STATE
+    graph.step(5)
+    prof = graph.profile("read")
+    graph.profile("off")
+    for k in ("move", "scan", "place", "order", "collide"):
+        assert prof[k][1] == 5 and prof[k][0] > 0, (k, prof[k])
+    eager.step(5, graph=True)
+    _assert_same(_full(eager), _full(graph))
