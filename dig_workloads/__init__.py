@@ -147,3 +147,19 @@ def random_sorted_state(w, seed, n_per_cell_mean=None, rng_kind="poisson"):
     er = (i["Tr"] * rng.exponential(size=n)).astype(np.float32)
     ids = rng.permutation(n).astype(np.uint32)
     return dict(x=x, y=y, vx=vx, vy=vy, vz=vz, er=er, id=ids, start=start)
+
+
+def mlp_init(seed=7):
+    """Initial weights of the closure network: Glorot-uniform over the real
+    fan-in/fan-out (9 inputs, 7 outputs), zero padding and zero biases; values
+    representable in FP32.  Returned as float64 arrays keyed W0..W3, b0..b3."""
+    rng = np.random.default_rng(seed)
+    dims = [(32, 128, 9, 128), (128, 128, 128, 128), (128, 128, 128, 128), (128, 16, 128, 7)]
+    p = {}
+    for l, (fin, fout, rin, rout) in enumerate(dims):
+        s = math.sqrt(6.0 / (rin + rout))
+        W = np.zeros((fout, fin))
+        W[:rout, :rin] = rng.uniform(-s, s, size=(rout, rin))
+        p[f"W{l}"] = W.astype(np.float32).astype(np.float64)
+        p[f"b{l}"] = np.zeros(fout)
+    return p
