@@ -265,6 +265,66 @@ dig_status dsmc_autotune(dig_ctx* ctx, int32_t steps_per_trial, const char* cach
  * Errors: DIG_ERR_STATE, DIG_ERR_HIP. */
 dig_status dsmc_step_graph(dig_ctx* ctx, int32_t nsteps, dig_stream_t stream);
 
+/* ---- Learned closure network ------------------------------------------
+ * A multilayer perceptron that predicts the higher-order constitutive terms
+ * (the deviations of sigma and q from their NSF values, Section 3.1) from
+ * local gradients and the local Knudsen number, in place of the noisy DSMC
+ * extraction where the local Knudsen number lies in a band.  Four linear
+ * layers: inputs 9 (padded to 32) -> 128 -> 128 -> 128 -> outputs 7 (padded
+ * to 16), tanh on the hidden layers.  Products run on the matrix cores with
+ * BF16 operands (inputs, weights, hidden activations and back-propagated
+ * pre-activation gradients rounded to bfloat16, nearest even) and FP32
+ * accumulation; master weights, biases and the Adam moments are FP32.
+ *
+ * Parameters live in the caller's workspace as one FP32 array of
+ * DIG_MLP_NPARAM values: W0 [128][32], b0 [128], W1 [128][128], b1 [128],
+ * W2 [128][128], b2 [128], W3 [16][128], b3 [16] (row-major [out][in]).
+ * Padded entries (W0 columns 9..31, W3 rows 7..15, b3[7..15]) must be 0 and
+ * stay 0 under training.  After writing parameters, call mlp_sync. */
+enum { DIG_MLP_NPARAM = 39312, DIG_MLP_IN = 9, DIG_MLP_OUT = 7 };
+typedef struct dig_mlp dig_mlp;
+typedef struct {
+  size_t total_bytes;
+  int32_t max_batch;   /* training batch capacity (multiple of 64) */
+  size_t params;       /* f32 [DIG_MLP_NPARAM] master parameters */
+  size_t grads;        /* f32 [DIG_MLP_NPARAM] gradient of the last mlp_grad */
+  size_t adam_m, adam_v;  /* f32 [DIG_MLP_NPARAM] Adam moments */
+  size_t loss;         /* f32 [1]: loss of the last mlp_grad */
+} dig_mlp_layout;
+
+/* Workspace planning for a training batch of up to max_batch samples. */
+dig_status mlp_plan(int32_t max_batch, dig_mlp_layout* out_host);
+
+/* Creates a network over a caller-owned, 256-byte aligned device workspace
+ * of at least layout.total_bytes; zeroes gradients and Adam moments (the
+ * parameters are the caller's to write).  Enqueued.  Errors: INVALID, HIP. */
+dig_status mlp_create(void* workspace_dev, size_t workspace_bytes, int32_t max_batch,
+                      dig_stream_t stream, dig_mlp** out);
+
+/* Refreshes the BF16 weight copies from the FP32 master parameters. */
+dig_status mlp_sync(dig_mlp* mlp, dig_stream_t stream);
+
+/* Inference: y_dev [n][7] = network(x_dev [n][9]), FP32 in and out, any n. */
+dig_status mlp_forward(dig_mlp* mlp, const float* x_dev, float* y_dev, int64_t n,
+                       dig_stream_t stream);
+
+/* Loss (mean over n samples and 7 outputs of (y - t)^2, written to the
+ * workspace's loss slot) and its gradient for every parameter (overwrites the
+ * gradient array).  n <= max_batch.  Errors: INVALID. */
+dig_status mlp_grad(dig_mlp* mlp, const float* x_dev, const float* t_dev, int64_t n,
+                    dig_stream_t stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) at step number t >= 1
+ * from the stored gradient, then the BF16 copies are refreshed. */
+dig_status mlp_adam(dig_mlp* mlp, float lr, float beta1, float beta2, float eps, int64_t t,
+                    dig_stream_t stream);
+
+/* mlp_grad followed by mlp_adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+dig_status mlp_train_step(dig_mlp* mlp, const float* x_dev, const float* t_dev, int64_t n,
+                          float lr, int64_t t, dig_stream_t stream);
+
+void mlp_destroy(dig_mlp* mlp);
+
 const char* dig_last_error(void);
 void dsmc_destroy(dig_ctx* ctx);
 

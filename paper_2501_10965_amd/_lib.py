@@ -60,11 +60,22 @@ class DigTuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class DigMlpLayout(C.Structure):
+    _fields_ = [("total_bytes", C.c_size_t), ("max_batch", C.c_int32), ("params", C.c_size_t),
+                ("grads", C.c_size_t), ("adam_m", C.c_size_t), ("adam_v", C.c_size_t),
+                ("loss", C.c_size_t)]
+
+
+MLP_NPARAM = 39312
+
+
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
            "dsmc_sample", "dig_adjust", "closure_assemble", "dig_synth_workspace_bytes",
            "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_tuning",
-           "dsmc_autotune", "dsmc_step_graph", "dig_last_error", "dsmc_destroy"]
+           "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
+           "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "dig_last_error",
+           "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
 _lib = None
@@ -96,6 +107,15 @@ def load(path: str = LIB_PATH):
     L.dsmc_inject.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, vp]
     L.dsmc_step.argtypes = [vp, C.c_int32, vp]
     L.dsmc_step_graph.argtypes = [vp, C.c_int32, vp]
+    L.mlp_plan.argtypes = [C.c_int32, C.POINTER(DigMlpLayout)]
+    L.mlp_create.argtypes = [vp, C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
+    L.mlp_sync.argtypes = [vp, vp]
+    L.mlp_forward.argtypes = [vp, vp, vp, C.c_int64, vp]
+    L.mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp]
+    L.mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int64, vp]
+    L.mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_int64, vp]
+    L.mlp_destroy.argtypes = [vp]
+    L.mlp_destroy.restype = None
     L.dsmc_tuning.argtypes = [vp, C.POINTER(DigTuning), C.POINTER(DigTuning)]
     L.dsmc_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(DigTuning), vp]
     L.dsmc_stage.argtypes = [vp, C.c_int32, vp]
@@ -115,7 +135,8 @@ def load(path: str = LIB_PATH):
     L.dsmc_destroy.argtypes = [vp]
     L.dsmc_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("dig_last_error", "dsmc_destroy", "dig_synth_workspace_bytes"):
+        if name not in ("dig_last_error", "dsmc_destroy", "dig_synth_workspace_bytes",
+                        "mlp_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

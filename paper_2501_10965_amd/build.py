@@ -7,7 +7,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdig.so")
-SOURCES = ["dig_api.hip", "dig_kernels.hip", "dig_synth.hip"]
+SOURCES = ["dig_api.hip", "dig_kernels.hip", "dig_synth.hip", "dig_mlp.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

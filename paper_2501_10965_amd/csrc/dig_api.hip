@@ -21,6 +21,13 @@ dig_status fail(dig_status s, const std::string& m) {
   return s;
 }
 
+}  // namespace
+
+// Error reporting for the other translation units of the library.
+dig_status dig::report(dig_status s, const char* msg) { return fail(s, msg); }
+
+namespace {
+
 dig_status hip_fail(hipError_t e, const char* where) {
   return fail(DIG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }

@@ -99,6 +99,9 @@ struct StepArgs {
   int64_t n_upper;
 };
 
+// Sets the thread-local message returned by dig_last_error; returns s.
+dig_status report(dig_status s, const char* msg);
+
 int64_t group_launch(const StepArgs& a);
 int scan_blocks(int ncell);
 size_t collide_lds_bytes(int lds_particles, int group_cells);
