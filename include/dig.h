@@ -256,10 +256,10 @@ dig_status dsmc_tuning(dig_ctx* ctx, const dig_tuning* in_host, dig_tuning* out_
 dig_status dsmc_autotune(dig_ctx* ctx, int32_t steps_per_trial, const char* cache_path,
                          dig_tuning* out_host, dig_stream_t stream);
 
-/* nsteps DSMC steps as one HIP graph launched on `stream`: the first call for
- * a given (nsteps, buffer parity, particle count rounded up to a 1/64 share
- * of the capacity, tuning) captures the step
- * kernels on a stream of the library's own, later calls replay the
+/* nsteps DSMC steps as HIP graphs of at most 64 steps each, launched on
+ * `stream`: the first use of a graph for a given (steps, buffer parity,
+ * particle count rounded up to a 1/64 share of the capacity, tuning) captures
+ * the step kernels on a stream of the library's own, later uses replay the
  * instantiated graph.  Results are identical to dsmc_step.  Not available
  * while dsmc_profile is enabled (per-kernel events need eager launches).
  * Errors: DIG_ERR_STATE, DIG_ERR_HIP. */
@@ -324,6 +324,39 @@ dig_status mlp_train_step(dig_mlp* mlp, const float* x_dev, const float* t_dev, 
                           float lr, int64_t t, dig_stream_t stream);
 
 void mlp_destroy(dig_mlp* mlp);
+
+/* Standardisation of the network's inputs and targets: z = (v - mean)/std. */
+typedef struct {
+  double x_mean[9], x_std[9];
+  double y_mean[7], y_std[7];
+} dig_mlp_scaling;
+
+/* Network inputs (and optionally targets) of every cell from time-averaged
+ * fields_dev [20][C] (dsmc_sample layout), kngll_dev [C] and, for targets,
+ * hot_dev [12][C] (closure_assemble layout).  Inputs, standardised:
+ * lambda/sqrt(Tt) (dux/dx, dux/dy, duy/dx, duy/dy), lambda/Tt (dTt/dx, dTt/dy),
+ * lambda/Tt (dTr/dx, dTr/dy), Kn_GLL, with the gradients and lambda of
+ * closure_assemble.  Targets, standardised: HoT sigma_xx/p, sigma_xy/p,
+ * sigma_yy/p, HoT q_t,x, q_t,y, q_r,x, q_r,y over p sqrt(Tt).  Empty cells:
+ * zeros.  x_dev [C][9] f32; t_dev [C][7] f32 or NULL. */
+dig_status closure_features(dig_ctx* ctx, const double* fields_dev, const double* kngll_dev,
+                            const double* hot_dev, const dig_mlp_scaling* scaling_host,
+                            float* x_dev, float* t_dev, dig_stream_t stream);
+
+/* Three-band adaptive closure (Section 3.1 with the learned terms): cells
+ * with the equilibrium mask set keep HoT = 0 (NSF); cells with
+ * kn_lo <= Kn_GLL < kn_hi take the network's prediction y_dev [C][7]
+ * (de-standardised; sigma_zz = -(sigma_xx + sigma_yy), z components 0)
+ * unless, in some component, |prediction - DSMC| exceeds
+ * judge_abs + judge_rel |DSMC| in the scaled units of the targets (then the
+ * DSMC-extracted term stays); all other cells keep the DSMC-extracted term.
+ * hot_dev [12][C] is updated in place; src_dev [C] (nullable) receives
+ * 0 NSF, 1 DSMC, 2 network, 3 network rejected. */
+dig_status closure_blend(dig_ctx* ctx, const double* fields_dev, const double* kngll_dev,
+                         const uint8_t* mask_dev, const float* y_dev,
+                         const dig_mlp_scaling* scaling_host, double kn_lo, double kn_hi,
+                         double judge_abs, double judge_rel, double* hot_dev, uint8_t* src_dev,
+                         dig_stream_t stream);
 
 const char* dig_last_error(void);
 void dsmc_destroy(dig_ctx* ctx);

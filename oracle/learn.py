@@ -1,0 +1,120 @@
+"""FP64 oracle of the learned-closure plumbing: the network's inputs and
+targets computed from time-averaged fields, and the three-band blend of
+network and DSMC-extracted higher-order terms (Section 3.1, with the learned
+band between Kn_lo and Kn_hi).
+
+TEST INFRASTRUCTURE ONLY: only the test suite may import this module.
+
+Field layout [20][C]: rho, ux, uy, uz, Tt, Tr, sigma (xx, yy, zz, xy, xz, yz),
+q_t (x, y, z), q_r (x, y, z), T, N.  HoT layout [12][C]: sigma (xx, yy, zz,
+xy, xz, yz), q_t (x, y, z), q_r (x, y, z).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+HOT_OF_TARGET = [0, 3, 1, 6, 7, 9, 10]  # sigma_xx, sigma_xy, sigma_yy, qt_x, qt_y, qr_x, qr_y
+
+
+def gradient(w, f, axis):
+    """d f / d x_axis on the uniform grid: central differences inside, one-sided
+    at wall faces, wrapped at periodic faces; zero along y in 1D."""
+    nx = w["nx"]
+    ny = w.get("ny", 1) if w["dim"] == 2 else 1
+    if axis == 1 and w["dim"] == 1:
+        return np.zeros_like(f)
+    g = f.reshape(ny, nx)
+    h = (w["lx"] / nx) if axis == 0 else (w["ly"] / ny)
+    n = nx if axis == 0 else ny
+    out = np.zeros_like(g)
+    if n < 2:
+        return out.reshape(-1)
+    ax = 1 if axis == 0 else 0
+    periodic = w["bc"][2 * axis][0] == "periodic"
+    for i in range(n):
+        sl = [slice(None), slice(None)]
+
+        def at(k):
+            s2 = list(sl)
+            s2[ax] = k
+            return g[tuple(s2)]
+
+        if 0 < i < n - 1:
+            d = (at(i + 1) - at(i - 1)) / (2 * h)
+        elif periodic:
+            d = (at((i + 1) % n) - at((i - 1) % n)) / (2 * h)
+        elif i == 0:
+            d = (at(1) - at(0)) / h
+        else:
+            d = (at(n - 1) - at(n - 2)) / h
+        s3 = list(sl)
+        s3[ax] = i
+        out[tuple(s3)] = d
+    return out.reshape(-1)
+
+
+def features(w, F, kn, scaling, hot=None):
+    """Standardised inputs [C, 9] and (with hot) targets [C, 7]."""
+    C = F.shape[1]
+    rho, tt = F[0], F[4]
+    ok = (rho > 0) & (tt > 0) & np.isfinite(kn)
+    mu0 = w["kn"] * math.sqrt(2.0 / math.pi)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mu = mu0 * np.power(np.where(ok, tt, 1.0), w["omega"])
+        lam = mu / (rho * tt) * np.sqrt(math.pi * tt / 2.0)
+        su, st = lam / np.sqrt(tt), lam / tt
+        f = np.zeros((C, 9))
+        f[:, 0] = su * gradient(w, F[1], 0)
+        f[:, 1] = su * gradient(w, F[1], 1)
+        f[:, 2] = su * gradient(w, F[2], 0)
+        f[:, 3] = su * gradient(w, F[2], 1)
+        f[:, 4] = st * gradient(w, F[4], 0)
+        f[:, 5] = st * gradient(w, F[4], 1)
+        f[:, 6] = st * gradient(w, F[5], 0)
+        f[:, 7] = st * gradient(w, F[5], 1)
+        f[:, 8] = kn
+        y = np.zeros((C, 7))
+        if hot is not None:
+            p = rho * tt
+            pq = p * np.sqrt(tt)
+            for j, hk in enumerate(HOT_OF_TARGET):
+                y[:, j] = hot[hk] / (p if j < 3 else pq)
+    f = (f - np.asarray(scaling["x_mean"])) / np.asarray(scaling["x_std"])
+    y = (y - np.asarray(scaling["y_mean"])) / np.asarray(scaling["y_std"])
+    f[~ok] = 0.0
+    y[~ok] = 0.0
+    return f, (y if hot is not None else None)
+
+
+def blend(F, kn, mask, ypred, scaling, hot, kn_lo, kn_hi, judge_abs, judge_rel):
+    """Returns (new hot [12, C], source code [C]): 0 NSF, 1 DSMC, 2 network,
+    3 network rejected by the judge."""
+    hot = hot.copy()
+    C = F.shape[1]
+    src = np.where(mask != 0, 0, 1).astype(np.uint8)
+    for c in range(C):
+        rho, tt = F[0, c], F[4, c]
+        if mask[c] or not (rho > 0 and tt > 0) or not (kn_lo <= kn[c] < kn_hi):
+            continue
+        p = rho * tt
+        pq = p * math.sqrt(tt)
+        pr = np.empty(7)
+        ok = True
+        for j, hk in enumerate(HOT_OF_TARGET):
+            s = p if j < 3 else pq
+            pr[j] = (ypred[c, j] * scaling["y_std"][j] + scaling["y_mean"][j]) * s
+            ds = hot[hk, c]
+            if abs(pr[j] - ds) / s > judge_abs + judge_rel * abs(ds) / s:
+                ok = False
+        if not ok:
+            src[c] = 3
+            continue
+        new = np.zeros(12)
+        new[0], new[3], new[1] = pr[0], pr[1], pr[2]
+        new[2] = -(pr[0] + pr[2])
+        new[6], new[7], new[9], new[10] = pr[3], pr[4], pr[5], pr[6]
+        hot[:, c] = new
+        src[c] = 2
+    return hot, src

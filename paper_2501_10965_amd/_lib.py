@@ -69,12 +69,27 @@ class DigMlpLayout(C.Structure):
 MLP_NPARAM = 39312
 
 
+class DigMlpScaling(C.Structure):
+    _fields_ = [("x_mean", C.c_double * 9), ("x_std", C.c_double * 9),
+                ("y_mean", C.c_double * 7), ("y_std", C.c_double * 7)]
+
+    @classmethod
+    def of(cls, sc: dict):
+        v = cls()
+        for k in ("x_mean", "x_std", "y_mean", "y_std"):
+            arr = getattr(v, k)
+            for i, val in enumerate(sc[k]):
+                arr[i] = float(val)
+        return v
+
+
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
            "dsmc_sample", "dig_adjust", "closure_assemble", "dig_synth_workspace_bytes",
            "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_tuning",
            "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
-           "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "dig_last_error",
+           "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "closure_features",
+           "closure_blend", "dig_last_error",
            "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
@@ -115,6 +130,9 @@ def load(path: str = LIB_PATH):
     L.mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int64, vp]
     L.mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_int64, vp]
     L.mlp_destroy.argtypes = [vp]
+    L.closure_features.argtypes = [vp, vp, vp, vp, C.POINTER(DigMlpScaling), vp, vp, vp]
+    L.closure_blend.argtypes = [vp, vp, vp, vp, vp, C.POINTER(DigMlpScaling), C.c_double,
+                                C.c_double, C.c_double, C.c_double, vp, vp, vp]
     L.mlp_destroy.restype = None
     L.dsmc_tuning.argtypes = [vp, C.POINTER(DigTuning), C.POINTER(DigTuning)]
     L.dsmc_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(DigTuning), vp]

@@ -645,6 +645,49 @@ dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, d
   return DIG_OK;
 }
 
+static dig_status scaling_of(const dig_mlp_scaling* in, MlpScale* out) {
+  if (!in) return fail(DIG_ERR_INVALID, "null scaling");
+  for (int k = 0; k < 9; ++k) {
+    out->x_mean[k] = in->x_mean[k];
+    out->x_std[k] = in->x_std[k];
+    if (!(in->x_std[k] > 0.0)) return fail(DIG_ERR_INVALID, "scaling std must be > 0");
+  }
+  for (int k = 0; k < 7; ++k) {
+    out->y_mean[k] = in->y_mean[k];
+    out->y_std[k] = in->y_std[k];
+    if (!(in->y_std[k] > 0.0)) return fail(DIG_ERR_INVALID, "scaling std must be > 0");
+  }
+  return DIG_OK;
+}
+
+dig_status closure_features(dig_ctx* c, const double* fields, const double* kngll,
+                            const double* hot, const dig_mlp_scaling* scaling, float* x, float* t,
+                            dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!fields || !kngll || !x || (t && !hot)) return fail(DIG_ERR_INVALID, "null argument");
+  MlpScale sc;
+  dig_status st = scaling_of(scaling, &sc);
+  if (st != DIG_OK) return st;
+  HIP_TRY(launch_learn_features(args(c), fields, kngll, hot, sc, x, t, (hipStream_t)stream));
+  return DIG_OK;
+}
+
+dig_status closure_blend(dig_ctx* c, const double* fields, const double* kngll,
+                         const uint8_t* mask, const float* y, const dig_mlp_scaling* scaling,
+                         double kn_lo, double kn_hi, double judge_abs, double judge_rel,
+                         double* hot, uint8_t* src, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!fields || !kngll || !mask || !y || !hot) return fail(DIG_ERR_INVALID, "null argument");
+  if (!(kn_lo <= kn_hi) || !(judge_abs >= 0.0) || !(judge_rel >= 0.0))
+    return fail(DIG_ERR_INVALID, "bad band or judge tolerance");
+  MlpScale sc;
+  dig_status st = scaling_of(scaling, &sc);
+  if (st != DIG_OK) return st;
+  HIP_TRY(launch_learn_blend(args(c), fields, kngll, mask, y, sc, kn_lo, kn_hi, judge_abs,
+                             judge_rel, hot, src, (hipStream_t)stream));
+  return DIG_OK;
+}
+
 dig_status dsmc_query(dig_ctx* c, dig_counters* out, dig_stream_t stream) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!out) return fail(DIG_ERR_INVALID, "null output");
@@ -726,18 +769,20 @@ dig_status dsmc_tuning(dig_ctx* c, const dig_tuning* in, dig_tuning* out) {
   return DIG_OK;
 }
 
-dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
-  if (check_ctx(c)) return DIG_ERR_INVALID;
-  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state (call dsmc_init)");
-  if (nsteps < 0) return fail(DIG_ERR_INVALID, "nsteps < 0");
-  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
-  if (c->prof) return fail(DIG_ERR_STATE, "graph steps need dsmc_profile disabled");
-  if (nsteps == 0) return DIG_OK;
+}  // extern "C"
+
+namespace {
+
+// Steps per captured graph: longer runs replay it (graph size stays bounded).
+constexpr int32_t kGraphSteps = 64;
+
+// Launches k <= kGraphSteps steps as one graph, capturing it on first use.
+dig_status graph_steps(dig_ctx* c, int32_t k, hipStream_t stream) {
   const int cur0 = c->cur;
   const int64_t nup = args(c).n_upper;
   dig_ctx::Graph* hit = nullptr;
   for (auto& g : c->graphs)
-    if (g.nsteps == nsteps && g.cur == cur0 && g.n == nup && g.T == c->T && g.Gc == c->Gc &&
+    if (g.nsteps == k && g.cur == cur0 && g.n == nup && g.T == c->T && g.Gc == c->Gc &&
         g.seq == c->seq_max)
       hit = &g;
   if (!hit) {
@@ -745,7 +790,7 @@ dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
     if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     dig_status st = DIG_OK;
-    for (int k = 0; k < nsteps && st == DIG_OK; ++k) st = run_stages(c, DIG_STAGE_ALL, c->cap);
+    for (int i = 0; i < k && st == DIG_OK; ++i) st = run_stages(c, DIG_STAGE_ALL, c->cap);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap, &g);
     // nothing ran during capture: the host view of the state is unchanged
@@ -761,11 +806,30 @@ dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
       (void)hipGraphDestroy(g);
       return hip_fail(e, "hipGraphInstantiate");
     }
-    c->graphs.push_back({nsteps, cur0, c->T, c->Gc, c->seq_max, nup, g, x});
+    c->graphs.push_back({k, cur0, c->T, c->Gc, c->seq_max, nup, g, x});
     hit = &c->graphs.back();
   }
-  HIP_TRY(hipGraphLaunch(hit->x, (hipStream_t)stream));
-  c->cur = cur0 ^ (nsteps & 1);
+  HIP_TRY(hipGraphLaunch(hit->x, stream));
+  c->cur = cur0 ^ (k & 1);
+  return DIG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dig_status dsmc_step_graph(dig_ctx* c, int32_t nsteps, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state (call dsmc_init)");
+  if (nsteps < 0) return fail(DIG_ERR_INVALID, "nsteps < 0");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  if (c->prof) return fail(DIG_ERR_STATE, "graph steps need dsmc_profile disabled");
+  for (int32_t done = 0; done < nsteps;) {
+    const int32_t k = nsteps - done < kGraphSteps ? nsteps - done : kGraphSteps;
+    const dig_status st = graph_steps(c, k, (hipStream_t)stream);
+    if (st != DIG_OK) return st;
+    done += k;
+  }
   return DIG_OK;
 }
 

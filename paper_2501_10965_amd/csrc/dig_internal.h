@@ -99,6 +99,18 @@ struct StepArgs {
   int64_t n_upper;
 };
 
+// Standardisation of the closure network's inputs and targets.
+struct MlpScale {
+  double x_mean[9], x_std[9], y_mean[7], y_std[7];
+};
+hipError_t launch_learn_features(const StepArgs& a, const double* F, const double* kn,
+                                 const double* hot, const MlpScale& sc, float* x, float* t,
+                                 hipStream_t s);
+hipError_t launch_learn_blend(const StepArgs& a, const double* F, const double* kn,
+                              const uint8_t* mask, const float* y, const MlpScale& sc,
+                              double kn_lo, double kn_hi, double judge_abs, double judge_rel,
+                              double* hot, uint8_t* src, hipStream_t s);
+
 // Sets the thread-local message returned by dig_last_error; returns s.
 dig_status report(dig_status s, const char* msg);
 

@@ -1293,6 +1293,96 @@ __global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, d
   kngll[c] = kn;
 }
 
+// Inputs and targets of the closure network (Section 3.1 terms, scaled to be
+// dimensionless and standardised): features lambda/sqrt(Tt) du_i/dx_j
+// (xx, xy, yx, yy), lambda/Tt dTt/dx_j, lambda/Tt dTr/dx_j, Kn_GLL; targets
+// HoT sigma_xx/p, sigma_xy/p, sigma_yy/p, HoT q_t,j/(p sqrt(Tt)),
+// HoT q_r,j/(p sqrt(Tt)).  Empty cells get zero features and targets.
+__global__ void k_learn_features(StepArgs a, const double* F, const double* kn,
+                                 const double* hot, MlpScale sc, float* x, float* t) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const InstParam& I = a.params[a.cell_inst[c]];
+  const int lc = c - I.cell0, ix = lc % I.nx, iy = lc / I.nx, base = I.cell0;
+  const double rho = F[c], tt = F[4 * C + c];
+  double f[9], y[7];
+  for (int k = 0; k < 9; ++k) f[k] = 0.0;
+  for (int k = 0; k < 7; ++k) y[k] = 0.0;
+  if (rho > 0.0 && tt > 0.0 && isfinite(kn[c])) {
+    const double mu = I.mu0 * pow(tt, I.omega);
+    const double lam = mu / (rho * tt) * sqrt(M_PI * tt / 2.0);
+    const double su = lam / sqrt(tt), st = lam / tt;
+    f[0] = su * grad_axis(I, F + C, C, base, ix, iy, 0);
+    f[1] = su * grad_axis(I, F + C, C, base, ix, iy, 1);
+    f[2] = su * grad_axis(I, F + 2 * C, C, base, ix, iy, 0);
+    f[3] = su * grad_axis(I, F + 2 * C, C, base, ix, iy, 1);
+    f[4] = st * grad_axis(I, F + 4 * C, C, base, ix, iy, 0);
+    f[5] = st * grad_axis(I, F + 4 * C, C, base, ix, iy, 1);
+    f[6] = st * grad_axis(I, F + 5 * C, C, base, ix, iy, 0);
+    f[7] = st * grad_axis(I, F + 5 * C, C, base, ix, iy, 1);
+    f[8] = kn[c];
+    if (hot) {
+      const double p = rho * tt, pq = p * sqrt(tt);
+      const int hk[7] = {0, 3, 1, 6, 7, 9, 10};
+      for (int k = 0; k < 7; ++k) y[k] = hot[(int64_t)hk[k] * C + c] / (k < 3 ? p : pq);
+    }
+    for (int k = 0; k < 9; ++k) f[k] = (f[k] - sc.x_mean[k]) / sc.x_std[k];
+    for (int k = 0; k < 7; ++k) y[k] = (y[k] - sc.y_mean[k]) / sc.y_std[k];
+  }
+  for (int k = 0; k < 9; ++k) x[(int64_t)c * 9 + k] = (float)f[k];
+  if (t)
+    for (int k = 0; k < 7; ++k) t[(int64_t)c * 7 + k] = (float)y[k];
+}
+
+// Adaptive closure with three bands (Section 3.1 and its learned extension):
+// Kn_GLL < Kn_ref -> NSF (mask set, HoT already 0); Kn_lo <= Kn_GLL < Kn_hi ->
+// the network's prediction, unless it differs from the DSMC-extracted term by
+// more than judge_abs + judge_rel |DSMC| in some component (then DSMC);
+// otherwise the DSMC-extracted term.  src: 0 NSF, 1 DSMC, 2 network,
+// 3 network rejected.
+__global__ void k_learn_blend(StepArgs a, const double* F, const double* kn,
+                              const uint8_t* mask, const float* yp, MlpScale sc, double kn_lo,
+                              double kn_hi, double judge_abs, double judge_rel, double* hot,
+                              uint8_t* src) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const double rho = F[c], tt = F[4 * C + c];
+  uint8_t s = mask[c] ? 0 : 1;
+  const double k = kn[c];
+  if (!mask[c] && rho > 0.0 && tt > 0.0 && k >= kn_lo && k < kn_hi) {
+    const double p = rho * tt, pq = p * sqrt(tt);
+    const int hk[7] = {0, 3, 1, 6, 7, 9, 10};
+    double pr[7];
+    bool ok = true;
+    for (int j = 0; j < 7; ++j) {
+      const double sc_j = j < 3 ? p : pq;
+      pr[j] = ((double)yp[(int64_t)c * 7 + j] * sc.y_std[j] + sc.y_mean[j]) * sc_j;
+      const double ds = hot[(int64_t)hk[j] * C + c];
+      if (fabs(pr[j] - ds) / sc_j > judge_abs + judge_rel * fabs(ds) / sc_j) ok = false;
+    }
+    if (ok) {
+      hot[0 * (int64_t)C + c] = pr[0];
+      hot[1 * (int64_t)C + c] = pr[2];
+      hot[2 * (int64_t)C + c] = -(pr[0] + pr[2]);
+      hot[3 * (int64_t)C + c] = pr[1];
+      hot[4 * (int64_t)C + c] = 0.0;
+      hot[5 * (int64_t)C + c] = 0.0;
+      hot[6 * (int64_t)C + c] = pr[3];
+      hot[7 * (int64_t)C + c] = pr[4];
+      hot[8 * (int64_t)C + c] = 0.0;
+      hot[9 * (int64_t)C + c] = pr[5];
+      hot[10 * (int64_t)C + c] = pr[6];
+      hot[11 * (int64_t)C + c] = 0.0;
+      s = 2;
+    } else {
+      s = 3;
+    }
+  }
+  if (src) src[c] = s;
+}
+
 __global__ void k_speed(const double* F, int C, double* speed) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= C) return;
@@ -1429,6 +1519,23 @@ hipError_t launch_closure(const StepArgs& a, const double* fields, double Att, d
                      a.sums);
   hipLaunchKernelGGL(k_closure, dim3(blocks_for(a.ncell, 128)), dim3(128), 0, s, a, fields, Att,
                      Atr, Art, Arr, kn_ref, hot, mask, kngll, nsf, a.sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_learn_features(const StepArgs& a, const double* F, const double* kn,
+                                 const double* hot, const MlpScale& sc, float* x, float* t,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_learn_features, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, F, kn,
+                     hot, sc, x, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_learn_blend(const StepArgs& a, const double* F, const double* kn,
+                              const uint8_t* mask, const float* y, const MlpScale& sc,
+                              double kn_lo, double kn_hi, double judge_abs, double judge_rel,
+                              double* hot, uint8_t* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_learn_blend, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, F, kn,
+                     mask, y, sc, kn_lo, kn_hi, judge_abs, judge_rel, hot, src);
   return hipGetLastError();
 }
 

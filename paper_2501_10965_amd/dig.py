@@ -42,7 +42,7 @@ class DIG:
         self.A = A if A is not None else default_A(w["omega"])
         self.wall_mode = wall_mode
         self.cfl = cfl
-        self.closure_fn = closure  # optional learned closure: (fields, hot, mask, kn) -> hot
+        self.closure_fn = closure  # optional learned closure: (sim, fields, hot, mask, kn) -> hot
         self.sim = DSMC(w, capacity=capacity, cap_factor=1.6, **dsmc_kw)
         self.ncell = self.sim.ncell
         self.cycle_no = 0
@@ -70,7 +70,7 @@ class DIG:
         if self.mode == "dig":
             hot, mask, kn, _ = self.sim.closure(f, self.A, self.kn_ref)
             if self.closure_fn is not None:
-                hot = self.closure_fn(f, hot, mask, kn)
+                hot = self.closure_fn(self.sim, f, hot, mask, kn)
             m_next, it, ch = synth_solve(self.w, f, hot, mask, self.A, cfl=self.cfl,
                                          wall_mode=self.wall_mode, max_iter=self.n_m,
                                          tol=self.tol)

@@ -210,6 +210,31 @@ class DSMC:
                                           _ptr(nsf) if nsf is not None else None, _stream()))
         return hot, mask, kn, nsf
 
+    def features(self, fields: torch.Tensor, kngll: torch.Tensor, scaling: dict,
+                 hot: torch.Tensor | None = None):
+        """Standardised network inputs [C, 9] (and targets [C, 7] from hot)."""
+        nc = self.ncell
+        x = torch.empty((nc, 9), dtype=torch.float32, device=self.device)
+        t = torch.empty((nc, 7), dtype=torch.float32, device=self.device) if hot is not None \
+            else None
+        sc = L.DigMlpScaling.of(scaling)
+        L.check(self.lib.closure_features(
+            self.ctx, _ptr(fields.contiguous()), _ptr(kngll.contiguous()),
+            _ptr(hot.contiguous()) if hot is not None else None, C.byref(sc), _ptr(x),
+            _ptr(t) if t is not None else None, _stream()))
+        return x, t
+
+    def blend(self, fields, kngll, mask, y, scaling: dict, hot: torch.Tensor, kn_lo: float,
+              kn_hi: float, judge_abs: float, judge_rel: float):
+        """Three-band closure in place on hot; returns the per-cell source code."""
+        src = torch.empty(self.ncell, dtype=torch.uint8, device=self.device)
+        sc = L.DigMlpScaling.of(scaling)
+        L.check(self.lib.closure_blend(
+            self.ctx, _ptr(fields.contiguous()), _ptr(kngll.contiguous()), _ptr(mask.contiguous()),
+            _ptr(y.contiguous()), C.byref(sc), float(kn_lo), float(kn_hi), float(judge_abs),
+            float(judge_rel), _ptr(hot), _ptr(src), _stream()))
+        return src
+
     def profile(self, mode: str):
         """'on' (reset and enable), 'off', or 'read' -> {kernel: (ms_total, launches)}."""
         m = {"off": 0, "on": 1, "read": 2}[mode]

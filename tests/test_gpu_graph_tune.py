@@ -41,7 +41,7 @@ def _pair(w, **kw):
     return sims
 
 
-@pytest.mark.parametrize("nsteps", [10, 3])
+@pytest.mark.parametrize("nsteps", [10, 3, 150])
 def test_graph_steps_match_eager(nsteps):
     """Replays of one captured graph, with eager work and synchronisation in
     between, give bit-identical states to the same steps run eagerly."""

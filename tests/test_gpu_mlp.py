@@ -5,7 +5,7 @@ gradients, ragged batch tails, padding invariants and a training run.
 Tolerances: the oracle rounds the same quantities to bfloat16 but from exact
 sums, the GPU from FP32 accumulations; a value within an FP32 rounding of a
 bfloat16 tie can round the other way (one bf16 unit, 2^-8 relative), so the
-comparisons are norm-wise: outputs 2e-3, gradients 1e-2 of each block's norm
+comparisons are norm-wise: outputs 5e-4, gradients 2e-3 of each block's norm
 (a block is one weight matrix or bias vector), loss 1e-3.  Adam from
 identical gradients is FP32 vs FP64 arithmetic: 1e-5."""
 import numpy as np
@@ -56,7 +56,7 @@ def test_forward_matches_oracle(n):
     ref, _ = omlp.forward(p, x.astype(np.float64))
     assert y.shape == (n, 7)
     say(f"  forward norm-wise error {nrel(y, ref):.2e}")
-    assert nrel(y, ref) < 2e-3, nrel(y, ref)
+    assert nrel(y, ref) < 5e-4, nrel(y, ref)
     assert np.abs(y - ref).max() < 0.05 * (np.abs(ref).max() + 0.1)
 
 
@@ -82,7 +82,7 @@ def test_gradients_match_oracle(n):
     assert abs(loss - lref) <= 1e-3 * lref, (loss, lref)
     say("  gradient errors " + " ".join(f"{k}:{nrel(g[k], gref[k]):.1e}" for k in gref))
     for k in gref:
-        assert nrel(g[k], gref[k]) < 1e-2, (k, nrel(g[k], gref[k]))
+        assert nrel(g[k], gref[k]) < 2e-3, (k, nrel(g[k], gref[k]))
     # padding receives exactly zero gradient
     assert np.all(g["W0"][:, 9:] == 0) and np.all(g["W3"][7:] == 0) and np.all(g["b3"][7:] == 0)
 
