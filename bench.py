@@ -245,6 +245,63 @@ def run_batch(args):
     return out, ws[63]
 
 
+# closure network: multiply-adds of the real (unpadded) layers per sample
+MLP_FWD_FLOP = 2 * (9 * 128 + 128 * 128 + 128 * 128 + 128 * 7)
+MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_mlp(args):
+    """Closure-network training (batch 4096, Adam) and inference throughput."""
+    import numpy as np
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd.mlp import MLP
+
+    batch, n_inf = 4096, 1 << 20
+    net = MLP(wl.mlp_init(7), max_batch=batch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.randn((batch, 9), device="cuda", generator=g)
+    t = torch.tanh(x[:, :7]).contiguous()
+    xi = torch.randn((n_inf, 9), device="cuda", generator=g)
+    yi = torch.empty((n_inf, 7), device="cuda")
+    for _ in range(max(args.warmup, 10)):
+        net.train_step(x, t, 1e-3)
+        net.forward(xi, out=yi)
+    steps = max(args.steps, 10)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e[0].record()
+    for _ in range(steps):
+        net.train_step(x, t, 1e-3)
+    e[1].record()
+    for _ in range(steps):
+        net.forward(xi, out=yi)
+    e[2].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    train_s = e[0].elapsed_time(e[1]) / 1e3 / steps
+    inf_s = e[1].elapsed_time(e[2]) / 1e3 / steps
+    train_tf = MLP_TRAIN_FLOP * batch / train_s / 1e12
+    inf_tf = MLP_FWD_FLOP * n_inf / inf_s / 1e12
+    return {
+        "value": batch * steps / (e[0].elapsed_time(e[1]) / 1e3), "unit": "samples/s",
+        "metric": "closure-network training samples/s (batch 4096, Adam)",
+        "ms_per_step": train_s * 1e3, "steps": steps,
+        "roofline": {"bound": "mfma", "achieved": round(inf_tf, 2),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(inf_tf / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
+                     "kernel": "k_mlp_fwd (inference, 2^20 samples)",
+                     "avg_launch_us": round(inf_s * 1e6, 2),
+                     "algorithmic_flop_per_launch": MLP_FWD_FLOP * n_inf},
+        "training_tflops": round(train_tf, 3), "inference_samples_per_s": n_inf / inf_s,
+        "wall_s": t1 - t0,
+    }
+
+
 def cpu_baseline(w, steps, dig: bool):
     import oracle
 
@@ -291,7 +348,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--workload", choices=["cavity", "batch"], default="cavity")
+    ap.add_argument("--workload", choices=["cavity", "batch", "mlp"], default="cavity")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -307,6 +364,19 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "mlp":
+        res = run_mlp(args)
+        line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"],
+                "n_gpus": 1, "steps": res["steps"], "warmup": args.warmup,
+                "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+                "config": {"workload": "closure network 9-128-128-128-7, batch 4096, "
+                           "inference over 2^20 samples"},
+                "roofline": res["roofline"], "cpu_baseline": None,
+                "training_tflops": res["training_tflops"],
+                "inference_samples_per_s": res["inference_samples_per_s"]}
+        print(json.dumps(line), flush=True)
         return
     if args.workload == "batch":
         res, wcpu = run_batch(args)

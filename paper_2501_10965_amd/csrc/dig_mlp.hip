@@ -43,6 +43,21 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
 }
 
+// tanh for activations that are rounded to bfloat16 right after: from the
+// identity tanh x = sign(x) (1 - e^{-2|x|}) / (1 + e^{-2|x|}) with the
+// hardware exponential and reciprocal, and from the Taylor series
+// x - x^3/3 + 2x^5/15 - 17x^7/315 for |x| < 2^-4, where the identity loses
+// relative accuracy; the result is within a few FP32 ulps of tanh, far below
+// half a bfloat16 unit.
+__device__ __forceinline__ float tanh_act(float x) {
+  const float ax = fabsf(x);
+  const float e = __expf(-2.0f * ax);
+  const float big = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+  const float x2 = x * x;
+  const float small = ax * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f - x2 * (17.0f / 315.0f))));
+  return copysignf(ax < 0.0625f ? small : big, x);
+}
+
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -111,10 +126,10 @@ __device__ void hidden_layer(const uint16_t* __restrict__ W, const float* __rest
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
       const int s = 16 * ct + li;
-      const uint16_t h0 = to_bf16(tanhf(acc[rt][ct][0] + b0));
-      const uint16_t h1 = to_bf16(tanhf(acc[rt][ct][1] + b1));
-      const uint16_t h2 = to_bf16(tanhf(acc[rt][ct][2] + b2));
-      const uint16_t h3 = to_bf16(tanhf(acc[rt][ct][3] + b3));
+      const uint16_t h0 = to_bf16(tanh_act(acc[rt][ct][0] + b0));
+      const uint16_t h1 = to_bf16(tanh_act(acc[rt][ct][1] + b1));
+      const uint16_t h2 = to_bf16(tanh_act(acc[rt][ct][2] + b2));
+      const uint16_t h3 = to_bf16(tanh_act(acc[rt][ct][3] + b3));
       st4(out + s * kLds + n0, h0, h1, h2, h3);
       if (gact) st4(gact + s * kH + n0, h0, h1, h2, h3);
     }

@@ -42,7 +42,9 @@ class DIG:
         self.A = A if A is not None else default_A(w["omega"])
         self.wall_mode = wall_mode
         self.cfl = cfl
-        self.closure_fn = closure  # optional learned closure: (sim, fields, hot, mask, kn) -> hot
+        # optional learned closure: (sim, fields, hot, mask, kn, smooth=...) -> hot, where
+        # smooth holds the latest macroscopic solution in rows 0..5
+        self.closure_fn = closure
         self.sim = DSMC(w, capacity=capacity, cap_factor=1.6, **dsmc_kw)
         self.ncell = self.sim.ncell
         self.cycle_no = 0
@@ -57,6 +59,8 @@ class DIG:
             out, it, ch = synth_solve(self.w, m, None, None, self.A, cfl=self.cfl,
                                       wall_mode="wall", max_iter=iters, tol=self.tol)
             f0 = out
+        # the latest macroscopic solution (inputs of a learned closure)
+        self.m_prev = f0[0:6].clone()
         # counts by Iround(rho V / N_eff), equilibrium velocities, rotational energies
         self.sim.init(f0.contiguous(), ppc=0)
 
@@ -70,11 +74,14 @@ class DIG:
         if self.mode == "dig":
             hot, mask, kn, _ = self.sim.closure(f, self.A, self.kn_ref)
             if self.closure_fn is not None:
-                hot = self.closure_fn(self.sim, f, hot, mask, kn)
+                smooth = torch.zeros((20, self.ncell), dtype=torch.float64, device=f.device)
+                smooth[0:6] = self.m_prev
+                hot = self.closure_fn(self.sim, f, hot, mask, kn, smooth=smooth)
             m_next, it, ch = synth_solve(self.w, f, hot, mask, self.A, cfl=self.cfl,
                                          wall_mode=self.wall_mode, max_iter=self.n_m,
                                          tol=self.tol)
             self.sim.adjust(m_next, self.cycle_no)
+            self.m_prev = m_next
             rec.update(synth_iters=it, synth_change=ch,
                        eq_fraction=float(mask.double().mean().item()))
         torch.cuda.synchronize()

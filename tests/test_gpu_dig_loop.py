@@ -37,3 +37,22 @@ def test_plain_dsmc_mode_matches_dsmc_steps():
     d.cycle()
     c = d.sim.counters()
     assert c["step"] == 10 and c["nsamp"] == 10
+
+
+def test_dig_with_learned_closure_hook():
+    """The learned closure plugs into the DIG loop: inputs from the previous
+    macroscopic solution, network in the band, DSMC terms elsewhere."""
+    import dig_workloads as wl2
+    from paper_2501_10965_amd import learn
+    from paper_2501_10965_amd.mlp import MLP
+    w = wl.cavity_2d(seed=93, n=16, ppc=30, kn=0.1)
+    say("case dig learned hook")
+    net = MLP(wl2.mlp_init(3), max_batch=64)
+    hook = learn.LearnedClosure(net, learn.UNIT_SCALING, kn_lo=0.0, judge_abs=1e9)
+    d = DIG(w, ns=10, n_m=200, closure=hook)
+    for _ in range(2):
+        f = np_(d.cycle())
+        assert np.isfinite(f).all()
+    src = np_(hook.last_src)
+    assert set(np.unique(src)) <= {0, 1, 2, 3}
+    assert (src == 2).sum() > 0
