@@ -163,3 +163,45 @@ def mlp_init(seed=7):
         p[f"W{l}"] = W.astype(np.float32).astype(np.float64)
         p[f"b{l}"] = np.zeros(fout)
     return p
+
+
+def radial_ratio(r_in, r_out, nr, first):
+    """Geometric radial stretch ratio q with first cell width `first`:
+    (r_out - r_in)(q - 1)/(q^nr - 1) = first (bisection)."""
+    span = r_out - r_in
+    if abs(span / nr - first) < 1e-15:
+        return 1.0
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        w1 = span * (mid - 1.0) / (mid ** nr - 1.0)
+        if w1 > first:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def cylinder(seed=5001, nth=500, nr=400, r_in=0.5, r_out=5.5, first=0.002, kn=0.01,
+             mach=5.0, n_target=50_000_000, dt_frac=0.1, zrot=5.0, Tw=1.0, outer="freestream"):
+    """Flow of a diatomic gas past a cylinder of radius r_in: annulus
+    r_in < r < r_out, nth angular x nr radial cells with geometric radial
+    stretching from a first cell of width `first`; isothermal diffuse cylinder
+    wall; freestream (rho = 1, T = 1, U = Mach sqrt(1.4) along +x) at the outer
+    circle.  One particle weight for all cells, set by n_target particles at
+    rho = 1.  Initial gas at rest, rho = 1, T = 1."""
+    q = radial_ratio(r_in, r_out, nr, first)
+    U = mach * math.sqrt(1.4)
+    area = math.pi * (r_out * r_out - r_in * r_in)
+    if outer == "freestream":
+        ob = ("freestream", 1.0, (U, 0.0, 0.0), 1.0)
+    else:
+        ob = _bc(outer, 1.0)
+    bc = [_bc("diffuse", Tw), ob, _bc("periodic"), _bc("periodic")]
+    T0 = 1.0 + 0.2 * mach * mach
+    return dict(dim=2, geometry="annulus", nx=nth, ny=nr, r_in=r_in, r_out=r_out, q=q,
+                lx=1.0, ly=1.0, kn=kn, omega=OMEGA_N2, alpha=1.0, dr=2, zrot=zrot,
+                dt=dt_frac * TAU_C_PER_KN * kn, weight=area / n_target, bc=bc, seed=seed,
+                instance=0, ppc=0, n_target=int(n_target),
+                init=dict(rho=1.0, u=(0.0, 0.0, 0.0), Tt=1.0, Tr=1.0), tref=max(T0, Tw),
+                name=f"cylinder_{nth}x{nr}_kn{kn}_ma{mach}")

@@ -24,9 +24,10 @@ _DIR = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_DIR, "liboracle.so")
 _SRC = [os.path.join(_DIR, "dsmc_oracle.c")]
 
-BC = {"periodic": 0, "diffuse": 1, "specular": 2}
+BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
+GEOM = {"box": 0, "annulus": 1}
 TAG = {"init": 1, "init_n": 2, "wall": 3, "ncand": 4, "coll": 5, "dig_n": 6,
-       "dig_del": 7, "dig_src": 8, "dig_empty": 9}
+       "dig_del": 7, "dig_src": 8, "dig_empty": 9, "inflow": 10}
 
 
 def build(force: bool = True) -> str:
@@ -40,12 +41,13 @@ def build(force: bool = True) -> str:
 
 class Config(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("lx", C.c_double), ("ly", C.c_double),
+                ("lx", C.c_double), ("ly", C.c_double), ("geometry", C.c_int32),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("q", C.c_double),
                 ("kn", C.c_double), ("omega", C.c_double), ("alpha", C.c_double),
                 ("dr", C.c_int32), ("zrot", C.c_double),
                 ("dt", C.c_double), ("weight", C.c_double),
                 ("bc_type", C.c_int32 * 4), ("bc_T", C.c_double * 4),
-                ("bc_U", (C.c_double * 3) * 4),
+                ("bc_U", (C.c_double * 3) * 4), ("bc_rho", C.c_double * 4),
                 ("seed", C.c_uint64), ("instance", C.c_uint32)]
 
 
@@ -80,7 +82,15 @@ def lib():
         for fn in ("orc_mu0", "orc_csigma", "orc_pinelastic", "orc_cell_volume"):
             getattr(L, fn).argtypes = [cp]
             getattr(L, fn).restype = C.c_double
-        L.orc_init.argtypes = [cp, _d, C.c_int32, C.c_int64, _d, _d, _d, _d, _d, _d, _u32]
+        L.orc_cell_volume_at.argtypes = [cp, C.c_int32]
+        L.orc_cell_volume_at.restype = C.c_double
+        L.orc_annulus_face.argtypes = [cp, C.c_int32]
+        L.orc_annulus_face.restype = C.c_double
+        L.orc_inject.argtypes = [cp, C.c_int64, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
+                                 C.c_uint32, C.c_uint64]
+        L.orc_inject.restype = C.c_int64
+        L.orc_init.argtypes = [cp, _d, C.c_int32, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
+                               _i64]
         L.orc_init.restype = C.c_int64
         L.orc_move.argtypes = [cp, C.c_int64, _d, _d, _d, _d, _d, _d, _u32, C.c_uint32]
         L.orc_move.restype = C.c_int64
@@ -110,8 +120,12 @@ def make_config(w: dict) -> Config:
     c.dim = w["dim"]
     c.nx = w["nx"]
     c.ny = w.get("ny", 1)
-    c.lx = w["lx"]
+    c.lx = w.get("lx", 1.0)
     c.ly = w.get("ly", 1.0)
+    c.geometry = GEOM[w.get("geometry", "box")]
+    c.r_in = w.get("r_in", 0.0)
+    c.r_out = w.get("r_out", 0.0)
+    c.q = w.get("q", 1.0)
     c.kn = w["kn"]
     c.omega = w["omega"]
     c.alpha = w.get("alpha", 1.0)
@@ -124,6 +138,7 @@ def make_config(w: dict) -> Config:
         c.bc_T[f] = bc[1]
         for k in range(3):
             c.bc_U[f][k] = bc[2][k]
+        c.bc_rho[f] = bc[3] if len(bc) > 3 else 0.0
     c.seed = w["seed"]
     c.instance = w.get("instance", 0)
     return c
@@ -150,8 +165,14 @@ def mu0(w):
     return lib().orc_mu0(C.byref(make_config(w)))
 
 
-def cell_volume(w):
-    return lib().orc_cell_volume(C.byref(make_config(w)))
+def cell_volume(w, cell=None):
+    if cell is None:
+        return lib().orc_cell_volume(C.byref(make_config(w)))
+    return lib().orc_cell_volume_at(C.byref(make_config(w)), int(cell))
+
+
+def annulus_face(w, j):
+    return lib().orc_annulus_face(C.byref(make_config(w)), int(j))
 
 
 class State:
@@ -203,14 +224,12 @@ class State:
         f = np.ascontiguousarray(fields, dtype=np.float64)
         n = lib().orc_init(C.byref(self.cfg), _p(f, _d), int(ppc), self.cap, _p(self.x, _d),
                            _p(self.y, _d), _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d),
-                           _p(self.er, _d), _p(self.id, _u32))
+                           _p(self.er, _d), _p(self.id, _u32), _p(self.start, _i64))
         if n < 0:
             raise RuntimeError("oracle init: capacity exceeded")
         self.n = int(n)
         self.next_id = self.n
         self.sgmax[:] = np.float32(sgmax0)
-        cell = self.cells()
-        self.start[:] = np.searchsorted(cell, np.arange(self.ncell + 1), side="left")
 
     def move(self):
         return lib().orc_move(C.byref(self.cfg), self.n, _p(self.x, _d), _p(self.y, _d),
@@ -229,10 +248,23 @@ class State:
         perm = np.zeros(max(self.n, 1), dtype=np.int64)
         lib().orc_sort(self.n, _p(cell, _i32), self.ncell, _p(perm, _i64),
                        _p(self.start, _i64))
-        perm = perm[: self.n]
+        n_new = int(self.start[-1])  # particles outside an open boundary are dropped
+        perm = perm[:n_new]
         for a in (self.x, self.y, self.vx, self.vy, self.vz, self.er, self.id):
-            a[: self.n] = a[: self.n][perm]
+            a[:n_new] = a[: self.n][perm]
+        self.n = n_new
         return perm
+
+    def inject(self):
+        """Freestream inflow of this step appended after the current particles."""
+        k = lib().orc_inject(C.byref(self.cfg), self.n, self.cap, _p(self.x, _d),
+                             _p(self.y, _d), _p(self.vx, _d), _p(self.vy, _d), _p(self.vz, _d),
+                             _p(self.er, _d), _p(self.id, _u32), self.step_no, self.next_id)
+        if k < 0:
+            raise RuntimeError("oracle inflow: capacity exceeded")
+        self.n += int(k)
+        self.next_id += int(k)
+        return int(k)
 
     def collide(self, with_obs=False):
         st = Stats()
@@ -256,7 +288,10 @@ class State:
         return s
 
     def step(self, sample=True):
-        """One DSMC step: move, index + stable sort, collide, sample."""
+        """One DSMC step: inflow (open boundaries), move, index + stable sort,
+        collide, sample."""
+        if self.w.get("geometry") == "annulus" and self.w["bc"][1][0] == "freestream":
+            self.inject()
         self.move()
         self.sort()
         st = self.collide()
@@ -328,7 +363,8 @@ def new_state(w: dict, cap_factor: float = 1.3, cap: int | None = None) -> "Stat
 
     nc = w["nx"] * w.get("ny", 1)
     if cap is None:
-        cap = int(nc * w["ppc"] * cap_factor) + 64
+        est = nc * w["ppc"] if w["ppc"] > 0 else w["n_target"]
+        cap = int(est * cap_factor) + 64
     s = State(w, cap)
     s.init(_wl.fields_uniform(w), w["ppc"], sgmax_default(w))
     return s

@@ -88,6 +88,19 @@ double orc_cell_volume(const orc_config* c) {
   return dx * (c->ly / c->ny);
 }
 
+double orc_annulus_face(const orc_config* c, int32_t j) {
+  if (c->q == 1.0) return c->r_in + (c->r_out - c->r_in) * (double)j / (double)c->ny;
+  return c->r_in +
+         (c->r_out - c->r_in) * (pow(c->q, (double)j) - 1.0) / (pow(c->q, (double)c->ny) - 1.0);
+}
+
+double orc_cell_volume_at(const orc_config* c, int32_t cell) {
+  if (c->geometry != ORC_GEOM_ANNULUS) return orc_cell_volume(c);
+  int32_t j = cell / c->nx;
+  double ra = orc_annulus_face(c, j), rb = orc_annulus_face(c, j + 1);
+  return 0.5 * (2.0 * M_PI / (double)c->nx) * (rb * rb - ra * ra);
+}
+
 static double iround(double x, double u) {
   double f = floor(x);
   return f + ((u < x - f) ? 1.0 : 0.0);
@@ -106,9 +119,8 @@ static void box_muller(double ua, double ub, double* z0, double* z1) {
  * Iround(rho V / N_eff) as in the particle-number rule of Section 3.2. */
 int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t cap,
                  double* x, double* y, double* vx, double* vy, double* vz, double* er,
-                 uint32_t* id) {
+                 uint32_t* id, int64_t* start) {
   int32_t ncell = c->nx * c->ny;
-  double V = orc_cell_volume(c);
   const double *rho = fields, *ux = fields + ncell, *uy = fields + 2 * ncell,
                *uz = fields + 3 * ncell, *tt = fields + 4 * ncell, *tr = fields + 5 * ncell;
   int64_t n = 0;
@@ -119,9 +131,10 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
     } else {
       uint32_t w[4];
       orc_draw(c, (uint32_t)cell, 0, ORC_TAG_INIT_N, 0, w);
-      cnt = (int64_t)iround(rho[cell] * V / c->weight, orc_u01(w[0]));
+      cnt = (int64_t)iround(rho[cell] * orc_cell_volume_at(c, cell) / c->weight, orc_u01(w[0]));
     }
     if (n + cnt > cap) return -1;
+    if (start) start[cell] = n;
     int32_t ix = cell % c->nx, iy = cell / c->nx;
     double st = sqrt(tt[cell]);
     for (int64_t k = 0; k < cnt; ++k, ++n) {
@@ -131,8 +144,17 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
       double z0, z1, z2, z3;
       box_muller(orc_u01(a[2]), orc_u01(a[3]), &z0, &z1);
       box_muller(orc_u01(b[0]), orc_u01(b[1]), &z2, &z3);
-      x[n] = ix + orc_u01(a[0]);
-      y[n] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
+      if (c->geometry == ORC_GEOM_ANNULUS) {
+        /* uniform over the cell's area: r^2 uniform between the face radii */
+        double ra = orc_annulus_face(c, iy), rb = orc_annulus_face(c, iy + 1);
+        double r = sqrt(ra * ra + orc_u01(a[0]) * (rb * rb - ra * ra));
+        double th = (2.0 * M_PI / (double)c->nx) * ((double)ix + orc_u01(a[1]));
+        x[n] = r * cos(th);
+        y[n] = r * sin(th);
+      } else {
+        x[n] = ix + orc_u01(a[0]);
+        y[n] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
+      }
       vx[n] = ux[cell] + st * z0;
       vy[n] = uy[cell] + st * z1;
       vz[n] = uz[cell] + st * z2;
@@ -140,6 +162,7 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
       id[n] = (uint32_t)n;
     }
   }
+  if (start) start[ncell] = n;
   return n;
 }
 
@@ -151,8 +174,76 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
 
 static int is_wall(int t) { return t == ORC_BC_DIFFUSE || t == ORC_BC_SPECULAR; }
 
+/* Free flight in an annulus (positions in physical units): reflections at
+ * the inner circle, and at the outer circle when it is a wall, in time order;
+ * diffuse re-emission about the normal into the gas. */
+static int64_t move_annulus(const orc_config* c, int64_t n, double* x, double* y, double* vx,
+                            double* vy, double* vz, double* er, const uint32_t* id,
+                            uint32_t step) {
+  int64_t hits_total = 0;
+  double ri = orc_annulus_face(c, 0), ro = orc_annulus_face(c, c->ny);
+  int outer_wall = c->bc_type[1] != ORC_BC_FREESTREAM;
+  for (int64_t p = 0; p < n; ++p) {
+    double t = c->dt;
+    for (int hit = 0; hit < ORC_MAXHIT; ++hit) {
+      double A = vx[p] * vx[p] + vy[p] * vy[p];
+      if (!(A > 0.0)) break;
+      double B = x[p] * vx[p] + y[p] * vy[p];
+      double R2 = x[p] * x[p] + y[p] * y[p];
+      double th = t;
+      int face = -1;
+      if (B < 0.0) {
+        double D = B * B - A * (R2 - ri * ri);
+        if (D >= 0.0) {
+          double tf = (-B - sqrt(D)) / A;
+          if (tf >= 0.0 && tf <= th) { th = tf; face = 0; }
+        }
+      }
+      if (outer_wall) {
+        double D = B * B - A * (R2 - ro * ro);
+        if (D >= 0.0) {
+          double tf = (-B + sqrt(D)) / A;
+          if (tf >= 0.0 && tf < th) { th = tf; face = 1; }
+        }
+      }
+      if (face < 0) break;
+      x[p] += vx[p] * th;
+      y[p] += vy[p] * th;
+      t -= th;
+      double rr = sqrt(x[p] * x[p] + y[p] * y[p]);
+      double sgn = face == 0 ? 1.0 : -1.0;
+      double nx = sgn * x[p] / rr, ny = sgn * y[p] / rr;
+      double Rw = face == 0 ? ri : ro;
+      x[p] = Rw * (x[p] / rr);
+      y[p] = Rw * (y[p] / rr);
+      if (c->bc_type[face] == ORC_BC_SPECULAR) {
+        double vn = vx[p] * nx + vy[p] * ny;
+        vx[p] -= 2.0 * vn * nx;
+        vy[p] -= 2.0 * vn * ny;
+      } else {
+        uint32_t w[4];
+        orc_draw(c, id[p], step, ORC_TAG_WALL, (uint32_t)hit, w);
+        double T = c->bc_T[face];
+        double vn = sqrt(-2.0 * T * log(orc_u01(w[0])));
+        double z0, z1;
+        box_muller(orc_u01(w[1]), orc_u01(w[2]), &z0, &z1);
+        double vt = sqrt(T) * z0;
+        vx[p] = vn * nx - vt * ny;
+        vy[p] = vn * ny + vt * nx;
+        vz[p] = sqrt(T) * z1;
+        er[p] = -T * log(orc_u01(w[3]));
+      }
+      ++hits_total;
+    }
+    x[p] += vx[p] * t;
+    y[p] += vy[p] * t;
+  }
+  return hits_total;
+}
+
 int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* vx,
                  double* vy, double* vz, double* er, const uint32_t* id, uint32_t step) {
+  if (c->geometry == ORC_GEOM_ANNULUS) return move_annulus(c, n, x, y, vx, vy, vz, er, id, step);
   double dx = c->lx / c->nx, dy = (c->dim == 2) ? c->ly / c->ny : 1.0;
   double gx = c->nx, gy = c->ny;
   int64_t hits_total = 0;
@@ -235,8 +326,39 @@ int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* v
 
 /* Cell of a grid-unit position: floor, clamped to the last cell when a
  * particle sits exactly on the upper face. */
+/* Annulus cell of a position, decided in single precision (the position as
+ * stored in FP32): the squared radius against the FP32 squared face radii,
+ * and the angular sector as the unique i with d_i x p >= 0 > d_{i+1} x p for
+ * the FP32 face directions d_i = (cos 2 pi i/nx, sin 2 pi i/nx).  Outside a
+ * freestream outer circle: -1. */
+static int32_t annulus_cell(const orc_config* c, double xd, double yd) {
+  float x = (float)xd, y = (float)yd;
+  float r2 = x * x + y * y;
+  double ro = orc_annulus_face(c, c->ny);
+  if (c->bc_type[1] == ORC_BC_FREESTREAM && r2 >= (float)(ro * ro)) return -1;
+  int32_t j = 0;
+  for (int32_t k = 1; k < c->ny; ++k) {
+    double rk = orc_annulus_face(c, k);
+    if ((float)(rk * rk) <= r2) j = k;
+  }
+  for (int32_t i = 0; i < c->nx; ++i) {
+    double t0 = 2.0 * M_PI * (double)i / (double)c->nx;
+    double t1 = 2.0 * M_PI * (double)((i + 1) % c->nx) / (double)c->nx;
+    float d0x = (float)cos(t0), d0y = (float)sin(t0);
+    float d1x = (float)cos(t1), d1y = (float)sin(t1);
+    float c0 = d0x * y - d0y * x;
+    float c1 = d1x * y - d1y * x;
+    if (c0 >= 0.0f && c1 < 0.0f) return i + c->nx * j;
+  }
+  return -2; /* no sector: cannot happen for nx >= 3 */
+}
+
 void orc_cell_index(const orc_config* c, int64_t n, const double* x, const double* y,
                     int32_t* cell) {
+  if (c->geometry == ORC_GEOM_ANNULUS) {
+    for (int64_t p = 0; p < n; ++p) cell[p] = annulus_cell(c, x[p], y[p]);
+    return;
+  }
   for (int64_t p = 0; p < n; ++p) {
     int32_t ix = (int32_t)floor(x[p]);
     if (ix < 0) ix = 0;
@@ -256,10 +378,12 @@ void orc_cell_index(const orc_config* c, int64_t n, const double* x, const doubl
 void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int64_t* start) {
   int64_t* fill = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
   for (int32_t c = 0; c <= ncell; ++c) start[c] = 0;
-  for (int64_t p = 0; p < n; ++p) start[cell[p] + 1] += 1;
+  for (int64_t p = 0; p < n; ++p)
+    if (cell[p] >= 0) start[cell[p] + 1] += 1;
   for (int32_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
   for (int64_t p = 0; p < n; ++p) {
     int32_t c = cell[p];
+    if (c < 0) continue;
     perm[start[c] + fill[c]] = p;
     fill[c] += 1;
   }
@@ -275,7 +399,6 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
                  orc_collide_stats* st, double* obs_out, double* margin_out) {
   double csig = orc_csigma(c);
   double pin = orc_pinelastic(c);
-  double V = orc_cell_volume(c);
   double expo = 1.0 - c->omega;            /* sigma g = C (g^2)^(1 - omega) */
   double beta_inv = 1.0 / (2.5 - c->omega); /* Beta(1, 5/2 - omega) inverse CDF */
   for (int32_t cell = 0; cell < ncell; ++cell) {
@@ -288,7 +411,8 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
     if (N >= 2) {
       uint32_t w[4];
       orc_draw(c, (uint32_t)cell, step, ORC_TAG_NCAND, 0, w);
-      double xc = 0.5 * (double)N * (double)(N - 1) * c->weight * sgm * c->dt / V;
+      double xc = 0.5 * (double)N * (double)(N - 1) * c->weight * sgm * c->dt /
+                  orc_cell_volume_at(c, cell);
       ncand = (int64_t)iround(xc, orc_u01(w[0]));
     }
     for (int64_t k = 0; k < ncand; ++k) {
@@ -391,8 +515,8 @@ void orc_sample_sums(int32_t ncell, const int64_t* start, const double* vx,
  * q_r = rho <c er>). */
 void orc_sums_to_fields(const orc_config* c, int32_t ncell, const double* sums,
                         double nsteps, double* fields) {
-  double V = orc_cell_volume(c);
   for (int32_t cell = 0; cell < ncell; ++cell) {
+    double V = orc_cell_volume_at(c, cell);
     const double* s = sums + 17 * (int64_t)cell;
     double out[20];
     for (int f = 0; f < 20; ++f) out[f] = 0.0;
@@ -678,4 +802,58 @@ void orc_closure(const orc_config* c, const double* fields, const double A[4], d
     kn_gll[k] = kn;
   }
   free(speed);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Freestream inflow (open outer circle of an annulus).  The shell between the
+ * outer circle and r_res = r_out + (|U| + 6 sqrt(T)) dt is filled every step
+ * with freestream gas: Iround(rho A / N_eff) particles per angular sector of
+ * area A, positions uniform in the sector (r^2 uniform, angle uniform),
+ * Maxwellian velocities about U, exponential rotational energies.  The shell
+ * radii are taken as the single-precision squares the kernels hold.  Ids
+ * follow next_id in (sector, k) order. */
+int64_t orc_inject(const orc_config* c, int64_t n, int64_t cap, double* x, double* y,
+                   double* vx, double* vy, double* vz, double* er, uint32_t* id,
+                   uint32_t step, uint64_t next_id) {
+  const double T = c->bc_T[1];
+  const double* U = c->bc_U[1];
+  double Um = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+  double rr = c->r_out + (Um + 6.0 * sqrt(T)) * c->dt;
+  double dth = 2.0 * M_PI / (double)c->nx;
+  double mean = c->bc_rho[1] * (0.5 * dth * (rr * rr - c->r_out * c->r_out)) / c->weight;
+  double ro = orc_annulus_face(c, c->ny);
+  double ra2 = (double)(float)(ro * ro), rb2 = (double)(float)(rr * rr);
+  int64_t total = 0;
+  for (int32_t f = 0; f < c->nx; ++f) {
+    uint32_t w[4];
+    orc_draw(c, (uint32_t)f, step, ORC_TAG_INFLOW, 0, w);
+    total += (int64_t)iround(mean, orc_u01(w[0]));
+  }
+  if (n + total > cap) return -1;
+  int64_t q = 0;
+  double sT = sqrt(T);
+  for (int32_t f = 0; f < c->nx; ++f) {
+    uint32_t w[4];
+    orc_draw(c, (uint32_t)f, step, ORC_TAG_INFLOW, 0, w);
+    int64_t k_f = (int64_t)iround(mean, orc_u01(w[0]));
+    for (int64_t k = 0; k < k_f; ++k, ++q) {
+      uint32_t a[4], b[4];
+      orc_draw(c, (uint32_t)f, step, ORC_TAG_INFLOW, (uint32_t)(1 + 2 * k), a);
+      orc_draw(c, (uint32_t)f, step, ORC_TAG_INFLOW, (uint32_t)(2 + 2 * k), b);
+      double r = sqrt(ra2 + orc_u01(a[0]) * (rb2 - ra2));
+      double th = dth * ((double)f + orc_u01(a[1]));
+      double z0, z1, z2, z3;
+      box_muller(orc_u01(a[2]), orc_u01(a[3]), &z0, &z1);
+      box_muller(orc_u01(b[0]), orc_u01(b[1]), &z2, &z3);
+      int64_t p = n + q;
+      x[p] = r * cos(th);
+      y[p] = r * sin(th);
+      vx[p] = U[0] + sT * z0;
+      vy[p] = U[1] + sT * z1;
+      vz[p] = U[2] + sT * z2;
+      er[p] = -T * log(orc_u01(b[2]));
+      id[p] = (uint32_t)(next_id + (uint64_t)q);
+    }
+  }
+  return total;
 }

@@ -22,19 +22,22 @@
 extern "C" {
 #endif
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_DIFFUSE = 1, ORC_BC_SPECULAR = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIFFUSE = 1, ORC_BC_SPECULAR = 2, ORC_BC_FREESTREAM = 3 };
+enum { ORC_GEOM_BOX = 0, ORC_GEOM_ANNULUS = 1 };
 
 /* Philox stream tags (third counter word, high byte). */
 enum {
   ORC_TAG_INIT = 1, ORC_TAG_INIT_N = 2, ORC_TAG_WALL = 3, ORC_TAG_NCAND = 4,
   ORC_TAG_COLL = 5, ORC_TAG_DIG_N = 6, ORC_TAG_DIG_DEL = 7, ORC_TAG_DIG_SRC = 8,
-  ORC_TAG_DIG_EMPTY = 9
+  ORC_TAG_DIG_EMPTY = 9, ORC_TAG_INFLOW = 10
 };
 
 typedef struct {
   int32_t  dim;          /* 1 or 2 */
   int32_t  nx, ny;       /* cells per axis (ny = 1 for dim 1) */
   double   lx, ly;       /* domain lengths (ly ignored for dim 1) */
+  int32_t  geometry;     /* ORC_GEOM_*; annulus: nx angular x ny radial cells */
+  double   r_in, r_out, q; /* annulus radii, radial stretch ratio */
   double   kn, omega, alpha;
   int32_t  dr;           /* rotational degrees of freedom (2) */
   double   zrot;         /* rotational collision number Z */
@@ -42,6 +45,7 @@ typedef struct {
   int32_t  bc_type[4];   /* faces x-, x+, y-, y+ */
   double   bc_T[4];
   double   bc_U[4][3];
+  double   bc_rho[4];    /* freestream density */
   uint64_t seed;
   uint32_t instance;
 } orc_config;
@@ -61,17 +65,32 @@ double orc_mu0(const orc_config* c);
 double orc_csigma(const orc_config* c);
 double orc_pinelastic(const orc_config* c);
 double orc_cell_volume(const orc_config* c);
+/* Volume (area, length) of one cell; the annulus cell (i, j) spans the angle
+ * 2 pi / nx and the radii of faces j and j + 1. */
+double orc_cell_volume_at(const orc_config* c, int32_t cell);
+/* Annulus radial face j: r_in + (r_out - r_in)(q^j - 1)/(q^ny - 1). */
+double orc_annulus_face(const orc_config* c, int32_t j);
+/* Freestream inflow at the outer circle of an annulus: appends the
+ * reservoir-shell particles of this step at index n; returns their number
+ * (or -1 if the capacity would be exceeded). */
+int64_t orc_inject(const orc_config* c, int64_t n, int64_t cap, double* x, double* y,
+                   double* vx, double* vy, double* vz, double* er, uint32_t* id,
+                   uint32_t step, uint64_t next_id);
 
+/* start (nullable, [ncell + 1]) receives the first particle of every cell. */
 int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t cap,
                  double* x, double* y, double* vx, double* vy, double* vz, double* er,
-                 uint32_t* id);
+                 uint32_t* id, int64_t* start);
 
 int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* vx,
                  double* vy, double* vz, double* er, const uint32_t* id, uint32_t step);
 
+/* Cell of every particle; -1 for a particle outside a freestream boundary. */
 void orc_cell_index(const orc_config* c, int64_t n, const double* x, const double* y,
                     int32_t* cell);
 
+/* Stable counting sort; particles with a negative cell are dropped (the
+ * sorted count is start[ncell]). */
 void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int64_t* start);
 
 void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
