@@ -205,3 +205,34 @@ def cylinder(seed=5001, nth=500, nr=400, r_in=0.5, r_out=5.5, first=0.002, kn=0.
                 instance=0, ppc=0, n_target=int(n_target),
                 init=dict(rho=1.0, u=(0.0, 0.0, 0.0), Tt=1.0, Tr=1.0), tref=max(T0, Tw),
                 name=f"cylinder_{nth}x{nr}_kn{kn}_ma{mach}")
+
+
+def random_annulus_state(w, seed, density=1.0, drift=(0.0, 0.0, 0.0), T=1.0):
+    """A random particle state of an annulus workload, listed cell by cell:
+    Poisson counts of mean density x area / weight, positions uniform over each
+    polar cell (r^2 uniform between its face radii, angle uniform), Maxwellian
+    velocities about `drift`, exponential rotational energies.  Float32
+    arrays plus the cell starts."""
+    rng = np.random.default_rng(seed)
+    nth, nr = w["nx"], w["ny"]
+    q, ri, ro = w["q"], w["r_in"], w["r_out"]
+    j = np.arange(nr + 1, dtype=np.float64)
+    faces = ri + (ro - ri) * (j / nr if q == 1.0 else (q ** j - 1.0) / (q ** nr - 1.0))
+    dth = 2.0 * math.pi / nth
+    area = 0.5 * dth * (faces[1:] ** 2 - faces[:-1] ** 2)  # per radial ring
+    lam = np.repeat(density * area / w["weight"], nth)     # cell c = i + nth j
+    counts = rng.poisson(lam)
+    start = np.zeros(len(counts) + 1, dtype=np.int64)
+    start[1:] = np.cumsum(counts)
+    n = int(start[-1])
+    cell = np.repeat(np.arange(len(counts)), counts)
+    ic, jc = cell % nth, cell // nth
+    r = np.sqrt(faces[jc] ** 2 + rng.random(n) * (faces[jc + 1] ** 2 - faces[jc] ** 2))
+    th = dth * (ic + rng.random(n))
+    out = dict(x=(r * np.cos(th)).astype(np.float32), y=(r * np.sin(th)).astype(np.float32),
+               vx=(drift[0] + math.sqrt(T) * rng.standard_normal(n)).astype(np.float32),
+               vy=(drift[1] + math.sqrt(T) * rng.standard_normal(n)).astype(np.float32),
+               vz=(drift[2] + math.sqrt(T) * rng.standard_normal(n)).astype(np.float32),
+               er=(T * rng.exponential(size=n)).astype(np.float32),
+               id=np.arange(n, dtype=np.uint32), start=start)
+    return out

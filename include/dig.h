@@ -50,20 +50,36 @@ typedef enum {
   DIG_ERR_NUMERIC = 5   /* non-finite or non-positive target values */
 } dig_status;
 
-/* Boundary condition of one domain face. */
-enum { DIG_BC_PERIODIC = 0, DIG_BC_DIFFUSE = 1, DIG_BC_SPECULAR = 2 };
+/* Boundary condition of one domain face.  FREESTREAM (annulus outer circle
+ * only): particles that leave are removed and the gas of a reservoir shell
+ * outside the circle (density rho, temperature T, velocity U) enters each
+ * step. */
+enum { DIG_BC_PERIODIC = 0, DIG_BC_DIFFUSE = 1, DIG_BC_SPECULAR = 2, DIG_BC_FREESTREAM = 3 };
 typedef struct {
   int32_t type; /* DIG_BC_* ; both faces of an axis periodic or neither */
-  double T;     /* wall temperature (diffuse) */
-  double U[3];  /* wall velocity (diffuse); its normal component must be 0 */
+  double T;     /* wall / freestream temperature */
+  double U[3];  /* wall velocity (its normal component must be 0) / freestream velocity */
+  double rho;   /* freestream density */
 } dig_bc;
+
+/* Geometry of an instance.  BOX: uniform Cartesian cells, positions held in
+ * grid units.  ANNULUS (dim 2, one instance per context): the region
+ * r_in <= r <= r_out around the origin, nx cells in the angle (face i at
+ * 2 pi i / nx) and ny cells in the radius with faces
+ * r_j = r_in + (r_out - r_in) (q^j - 1) / (q^ny - 1) (q = 1: uniform);
+ * cell (i, j) has index i + nx j; positions in physical units.  Faces:
+ * bc[0] the inner circle (DIFFUSE or SPECULAR), bc[1] the outer circle
+ * (DIFFUSE, SPECULAR or FREESTREAM); bc[2], bc[3] unused. */
+enum { DIG_GEOM_BOX = 0, DIG_GEOM_ANNULUS = 1 };
 
 /* One simulation instance (Section 4 gas: VSS/VHS omega 0.74, alpha 1,
  * d_r = 2, constant Z).  Faces are ordered x-, x+, y-, y+. */
 typedef struct {
   int32_t dim;          /* 1 (slab, positions x) or 2 (positions x, y) */
-  int32_t nx, ny;       /* uniform cells per axis; ny = 1 when dim = 1 */
-  double lx, ly;        /* domain lengths; cell volume (lx/nx)(ly/ny), 2D, or lx/nx, 1D */
+  int32_t nx, ny;       /* cells per axis; ny = 1 when dim = 1 */
+  double lx, ly;        /* box: domain lengths; cell volume (lx/nx)(ly/ny), 2D, or lx/nx, 1D */
+  int32_t geometry;     /* DIG_GEOM_* */
+  double r_in, r_out, q;  /* annulus radii and radial stretch ratio (q >= 1) */
   double kn;            /* Knudsen number (Section 2) */
   double omega, alpha;  /* viscosity index in [0.5, 1]; alpha must be 1 */
   int32_t dr;           /* rotational degrees of freedom; must be 2 */
@@ -90,6 +106,7 @@ typedef struct {
   size_t acc;        /* f64 [ncell][17]: time-accumulated raw sums */
   size_t sums;       /* f64 [ncell][17]: scratch for instantaneous sums */
   size_t cell_inst;  /* i32 [ncell]: instance of each cell */
+  size_t cvol;       /* f64 [ncell]: cell volume (area in 2D, length in 1D) */
   size_t counters;   /* dig_counters */
 } dig_layout;
 
@@ -100,6 +117,7 @@ typedef struct {
   int64_t nsamp;      /* steps accumulated into acc since the last reset */
   int64_t next_id;    /* next particle id handed out by dig_adjust */
   int64_t candidates, accepted, inelastic, saturated, wall_hits;
+  int64_t removed, injected;  /* open boundaries: particles that left / entered */
   uint32_t err;       /* DIG_EBIT_* */
   uint32_t cur;       /* current particle buffer (0 or 1) */
 } dig_counters;
@@ -108,7 +126,8 @@ enum {
   DIG_EBIT_SORT_OVERFLOW = 1u, /* a cell group exceeded the run table (slow path used) */
   DIG_EBIT_GROUPS = 2u,        /* more cell groups than launched: state invalid */
   DIG_EBIT_TARGET = 4u,        /* dig_adjust target non-finite or non-positive */
-  DIG_EBIT_CAPACITY = 8u       /* dig_adjust would exceed the capacity */
+  DIG_EBIT_CAPACITY = 8u,      /* dig_adjust or inflow would exceed the capacity */
+  DIG_EBIT_INFLOW = 16u        /* inflow clamped at the capacity (fewer particles entered) */
 };
 
 /* Workspace planning.  cfgs[n_inst] describe the instances advanced

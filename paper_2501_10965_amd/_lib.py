@@ -8,19 +8,23 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libdig.so")
 
 DIG_OK, DIG_ERR_INVALID, DIG_ERR_CAPACITY, DIG_ERR_HIP, DIG_ERR_STATE, DIG_ERR_NUMERIC = range(6)
-BC = {"periodic": 0, "diffuse": 1, "specular": 2}
+BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
+GEOM = {"box": 0, "annulus": 1}
 STAGE_MOVE, STAGE_SORT, STAGE_COLLIDE, STAGE_ALL = 1, 2, 4, 7
 SAMPLE_INSTANT, SAMPLE_AVERAGE, SAMPLE_RESET = 0, 1, 2
-EBIT_SORT_OVERFLOW, EBIT_GROUPS, EBIT_TARGET, EBIT_CAPACITY = 1, 2, 4, 8
+EBIT_SORT_OVERFLOW, EBIT_GROUPS, EBIT_TARGET, EBIT_CAPACITY, EBIT_INFLOW = 1, 2, 4, 8, 16
 
 
 class DigBC(C.Structure):
-    _fields_ = [("type", C.c_int32), ("T", C.c_double), ("U", C.c_double * 3)]
+    _fields_ = [("type", C.c_int32), ("T", C.c_double), ("U", C.c_double * 3),
+                ("rho", C.c_double)]
 
 
 class DigConfig(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("lx", C.c_double), ("ly", C.c_double), ("kn", C.c_double),
+                ("lx", C.c_double), ("ly", C.c_double), ("geometry", C.c_int32),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("q", C.c_double),
+                ("kn", C.c_double),
                 ("omega", C.c_double), ("alpha", C.c_double), ("dr", C.c_int32),
                 ("zrot", C.c_double), ("dt", C.c_double), ("weight", C.c_double),
                 ("bc", DigBC * 4), ("seed", C.c_uint64), ("instance_id", C.c_uint32),
@@ -34,7 +38,8 @@ class DigLayout(C.Structure):
                 ("id", C.c_size_t * 2), ("cell", C.c_size_t), ("rank", C.c_size_t),
                 ("perm_raw", C.c_size_t), ("perm", C.c_size_t), ("start", C.c_size_t),
                 ("count", C.c_size_t), ("sgmax", C.c_size_t), ("acc", C.c_size_t),
-                ("sums", C.c_size_t), ("cell_inst", C.c_size_t), ("counters", C.c_size_t)]
+                ("sums", C.c_size_t), ("cell_inst", C.c_size_t), ("cvol", C.c_size_t),
+                ("counters", C.c_size_t)]
 
 
 class DigSynthOpts(C.Structure):
@@ -46,6 +51,7 @@ class DigCounters(C.Structure):
     _fields_ = [("n", C.c_int64), ("step", C.c_int64), ("nsamp", C.c_int64),
                 ("next_id", C.c_int64), ("candidates", C.c_int64), ("accepted", C.c_int64),
                 ("inelastic", C.c_int64), ("saturated", C.c_int64), ("wall_hits", C.c_int64),
+                ("removed", C.c_int64), ("injected", C.c_int64),
                 ("err", C.c_uint32), ("cur", C.c_uint32)]
 
     def as_dict(self):
@@ -172,8 +178,12 @@ def make_config(w: dict) -> DigConfig:
     c.dim = w["dim"]
     c.nx = w["nx"]
     c.ny = w.get("ny", 1)
-    c.lx = w["lx"]
+    c.lx = w.get("lx", 1.0)
     c.ly = w.get("ly", 1.0)
+    c.geometry = GEOM[w.get("geometry", "box")]
+    c.r_in = w.get("r_in", 0.0)
+    c.r_out = w.get("r_out", 0.0)
+    c.q = w.get("q", 1.0)
     c.kn = w["kn"]
     c.omega = w["omega"]
     c.alpha = w.get("alpha", 1.0)
@@ -186,6 +196,7 @@ def make_config(w: dict) -> DigConfig:
         c.bc[f].T = bc[1]
         for k in range(3):
             c.bc[f].U[k] = bc[2][k]
+        c.bc[f].rho = bc[3] if len(bc) > 3 else 0.0
     c.seed = w["seed"]
     c.instance_id = w.get("instance", 0)
     c.sgmax_init = w.get("sgmax_init", 0.0)

@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      stats;
+      stats, rf2, dir, inj_off;
   int64_t gfirst_len;
 };
 
@@ -65,6 +65,32 @@ double cell_volume(const dig_config& c) {
   const double dx = c.lx / c.nx;
   return c.dim == 1 ? dx : dx * (c.ly / c.ny);
 }
+
+// Annulus geometry: radius of radial face j, FP32 squared face radii,
+// angular face directions and cell areas, all from FP64 values.
+double annulus_face(const dig_config& c, int j) {
+#pragma clang fp contract(off)
+  if (c.q == 1.0) return c.r_in + (c.r_out - c.r_in) * (double)j / (double)c.ny;
+  return c.r_in + (c.r_out - c.r_in) * (pow(c.q, (double)j) - 1.0) / (pow(c.q, (double)c.ny) - 1.0);
+}
+double annulus_dtheta(const dig_config& c) { return 2.0 * M_PI / (double)c.nx; }
+double annulus_cell_area(const dig_config& c, int j) {
+#pragma clang fp contract(off)
+  const double ra = annulus_face(c, j), rb = annulus_face(c, j + 1);
+  return 0.5 * annulus_dtheta(c) * (rb * rb - ra * ra);
+}
+// Freestream reservoir shell: outer radius and mean particles per sector.
+double reservoir_radius(const dig_config& c) {
+#pragma clang fp contract(off)
+  const dig_bc& b = c.bc[1];
+  const double U = sqrt(b.U[0] * b.U[0] + b.U[1] * b.U[1] + b.U[2] * b.U[2]);
+  return c.r_out + (U + 6.0 * sqrt(b.T)) * c.dt;
+}
+double reservoir_mean(const dig_config& c) {
+#pragma clang fp contract(off)
+  const double rr = reservoir_radius(c);
+  return c.bc[1].rho * (0.5 * annulus_dtheta(c) * (rr * rr - c.r_out * c.r_out)) / c.weight;
+}
 double default_majorant(const dig_config& c) {
   if (c.sgmax_init > 0.0) return c.sgmax_init;
   return vhs_constant(c) * pow(6.0 * sqrt(2.0 * c.tref), 2.0 - 2.0 * c.omega);
@@ -83,8 +109,27 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
     if (c.dim != cfgs[0].dim) return fail(DIG_ERR_INVALID, at + "all instances must share dim");
     if (c.nx < 1 || c.ny < 1 || (c.dim == 1 && c.ny != 1))
       return fail(DIG_ERR_INVALID, at + "bad cell counts");
-    if (!(c.lx > 0.0) || (c.dim == 2 && !(c.ly > 0.0)))
+    if (c.geometry != DIG_GEOM_BOX && c.geometry != DIG_GEOM_ANNULUS)
+      return fail(DIG_ERR_INVALID, at + "unknown geometry");
+    if (c.geometry == DIG_GEOM_ANNULUS) {
+      if (c.dim != 2 || n_inst != 1)
+        return fail(DIG_ERR_INVALID, at + "an annulus is 2D and alone in its context");
+      if (!(c.r_in > 0.0) || !(c.r_out > c.r_in) || !(c.q >= 1.0) || c.nx < 3)
+        return fail(DIG_ERR_INVALID, at + "annulus needs 0 < r_in < r_out, q >= 1, nx >= 3");
+      const int ti = c.bc[0].type, to = c.bc[1].type;
+      if (ti != DIG_BC_DIFFUSE && ti != DIG_BC_SPECULAR)
+        return fail(DIG_ERR_INVALID, at + "inner circle must be a wall");
+      if (to != DIG_BC_DIFFUSE && to != DIG_BC_SPECULAR && to != DIG_BC_FREESTREAM)
+        return fail(DIG_ERR_INVALID, at + "outer circle must be a wall or freestream");
+      for (int f = 0; f < 2; ++f)
+        if (c.bc[f].type == DIG_BC_DIFFUSE &&
+            (!(c.bc[f].T > 0.0) || c.bc[f].U[0] != 0.0 || c.bc[f].U[1] != 0.0))
+          return fail(DIG_ERR_INVALID, at + "annulus walls are at rest with T > 0");
+      if (to == DIG_BC_FREESTREAM && (!(c.bc[1].T > 0.0) || !(c.bc[1].rho > 0.0)))
+        return fail(DIG_ERR_INVALID, at + "freestream needs rho > 0 and T > 0");
+    } else if (!(c.lx > 0.0) || (c.dim == 2 && !(c.ly > 0.0))) {
       return fail(DIG_ERR_INVALID, at + "bad domain size");
+    }
     if (!(c.kn > 0.0)) return fail(DIG_ERR_INVALID, at + "Kn must be > 0");
     if (!(c.omega >= 0.5 && c.omega <= 1.0))
       return fail(DIG_ERR_INVALID, at + "omega must lie in [0.5, 1]");
@@ -97,10 +142,10 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
     if (c.instance_id > 0xFFFFFFu) return fail(DIG_ERR_INVALID, at + "instance_id >= 2^24");
     if (!(c.sgmax_init > 0.0) && !(c.tref > 0.0))
       return fail(DIG_ERR_INVALID, at + "need sgmax_init > 0 or tref > 0");
-    const int nf = c.dim == 1 ? 2 : 4;
+    const int nf = c.geometry == DIG_GEOM_ANNULUS ? 0 : (c.dim == 1 ? 2 : 4);
     for (int f = 0; f < nf; ++f) {
       const dig_bc& b = c.bc[f];
-      if (b.type < 0 || b.type > 2) return fail(DIG_ERR_INVALID, at + "bad bc type");
+      if (b.type < 0 || b.type > 2) return fail(DIG_ERR_INVALID, at + "bad bc type for a box");
       if (b.type == DIG_BC_DIFFUSE) {
         if (!(b.T > 0.0)) return fail(DIG_ERR_INVALID, at + "diffuse wall needs T > 0");
         if (b.U[f / 2] != 0.0)
@@ -117,7 +162,8 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
   return DIG_OK;
 }
 
-void plan_layout(int64_t cap, int64_t C, int32_t n_inst, dig_layout* L, Internal* I) {
+void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t geo_ny,
+                 dig_layout* L, Internal* I) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -146,6 +192,7 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, dig_layout* L, Internal
   L->acc = take(8 * 17 * C);
   L->sums = take(8 * 17 * C);
   L->cell_inst = take(4 * C);
+  L->cvol = take(8 * C);
   L->counters = take(sizeof(dig_counters));
   I->gfirst_len = cap / kMinGroupParticles + C / kMinGroupCells + 4;
   I->gfirst = take(4 * I->gfirst_len);
@@ -159,7 +206,16 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, dig_layout* L, Internal
   I->bsum = take(8 * (scan_blocks((int)C) + 1));
   I->lastcnt = take(4 * (scan_blocks((int)C) + 1));
   I->stats = take(sizeof(unsigned long long) * kStatSlots * ST_N);
+  I->rf2 = take(4 * (geo_ny + 1));
+  I->dir = take(8 * (geo_nx + 1));
+  I->inj_off = take(4 * (geo_nx + 2));
   L->total_bytes = o;
+}
+
+// Table sizes of the annulus geometry (0 for boxes).
+int32_t geo_dims(const dig_config* cfgs, int axis) {
+  if (cfgs[0].geometry != DIG_GEOM_ANNULUS) return 0;
+  return axis == 0 ? cfgs[0].nx : cfgs[0].ny;
 }
 
 InstParam make_param(const dig_config& c, int32_t cell0) {
@@ -196,6 +252,23 @@ InstParam make_param(const dig_config& c, int32_t cell0) {
   p.vol = cell_volume(c);
   p.mu0 = c.kn * sqrt(2.0 / M_PI);
   p.omega = c.omega;
+  p.geom = (uint32_t)c.geometry;
+  if (c.geometry == DIG_GEOM_ANNULUS) {
+    const double ri = annulus_face(c, 0), ro = annulus_face(c, c.ny);
+    p.rin2 = (float)(ri * ri);
+    p.rout2 = (float)(ro * ro);
+    p.rin = (float)ri;
+    p.rout = (float)ro;
+    p.dthf = (float)annulus_dtheta(c);
+    p.vol = annulus_cell_area(c, 0);
+    p.bc_type[2] = p.bc_type[3] = DIG_BC_PERIODIC;
+    if (c.bc[1].type == DIG_BC_FREESTREAM) {
+      const double rr = reservoir_radius(c);
+      p.res2 = (float)(rr * rr);
+      p.res_mean = reservoir_mean(c);
+      p.rho_inf = c.bc[1].rho;
+    }
+  }
   return p;
 }
 
@@ -205,6 +278,8 @@ struct dig_ctx {
   std::vector<dig_config> cfg;
   std::vector<InstParam> params;
   std::vector<int32_t> cell_inst_host;
+  std::vector<double> cvol_host;
+  std::vector<float> rf2_host, dir_host;
   dig_layout L;
   Internal I;
   unsigned char* ws = nullptr;
@@ -215,6 +290,7 @@ struct dig_ctx {
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
   int32_t seq_max = kSeqMaxDefault;
+  int32_t inj_sectors = 0;  // angular sectors with freestream inflow
   // event pairs (start, stop) bracketing launches, with the kernel kind of each
   struct EvPool {
     std::vector<hipEvent_t> ev;
@@ -281,6 +357,14 @@ StepArgs args(const dig_ctx* c) {
   // that the small count changes of a DIG adjustment keep captured graphs valid
   const int64_t q = std::max<int64_t>(4096, c->capacity / 64);
   a.n_upper = std::max<int64_t>(1, std::min<int64_t>(c->capacity, (c->n_host + q - 1) / q * q));
+  // with inflow and outflow the count changes every step on the device
+  if (c->inj_sectors > 0) a.n_upper = c->capacity;
+  a.cvol = (const double*)(w + L.cvol);
+  a.rf2 = (const float*)(w + c->I.rf2);
+  a.dir = (const float2*)(w + c->I.dir);
+  a.inj_off = (int32_t*)(w + c->I.inj_off);
+  a.capacity = c->capacity;
+  a.inj_sectors = c->inj_sectors;
   return a;
 }
 
@@ -401,12 +485,13 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
   StepArgs a = args(c);
   if (mask & DIG_STAGE_MOVE) {
     if (c->phase != 0) return fail(DIG_ERR_STATE, "move needs a completed previous step");
+    if (c->inj_sectors > 0) HIP_TRY(launch_inject(a, s));
     HIP_TRY(timed(c, DIG_K_MOVE, s, [&] { return launch_move(a, s); }));
     c->phase = 1;
   }
   if (mask & DIG_STAGE_SORT) {
     if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
-    HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, true, s); }));
+    HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, false, s); }));
     HIP_TRY(timed(c, DIG_K_PLACE, s, [&] { return launch_place(a, s); }));
     HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
     c->phase = 2;
@@ -433,7 +518,7 @@ dig_status dig_plan(const dig_config* cfgs, int32_t n_inst, int64_t capacity, di
   dig_status st = validate(cfgs, n_inst, capacity, &C);
   if (st != DIG_OK) return st;
   Internal I;
-  plan_layout(capacity, C, n_inst, out, &I);
+  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1), out, &I);
   return DIG_OK;
 }
 
@@ -459,7 +544,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->capacity = capacity;
   c->n_host = capacity;
   apply_tuning(c, T, Gc, kSeqMaxDefault);
-  plan_layout(capacity, C, n_inst, &c->L, &c->I);
+  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1), &c->L, &c->I);
   if (ws_bytes < c->L.total_bytes) {
     const std::string msg =
         "workspace too small: need " + std::to_string(c->L.total_bytes) + " bytes";
@@ -469,9 +554,27 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->ws = (unsigned char*)ws;
   int32_t cell0 = 0;
   for (int i = 0; i < n_inst; ++i) {
-    c->params.push_back(make_param(cfgs[i], cell0));
-    for (int k = 0; k < cfgs[i].nx * cfgs[i].ny; ++k) c->cell_inst_host.push_back(i);
-    cell0 += cfgs[i].nx * cfgs[i].ny;
+    const dig_config& g = cfgs[i];
+    c->params.push_back(make_param(g, cell0));
+    for (int k = 0; k < g.nx * g.ny; ++k) {
+      c->cell_inst_host.push_back(i);
+      c->cvol_host.push_back(g.geometry == DIG_GEOM_ANNULUS ? annulus_cell_area(g, k / g.nx)
+                                                            : cell_volume(g));
+    }
+    cell0 += g.nx * g.ny;
+  }
+  if (cfgs[0].geometry == DIG_GEOM_ANNULUS) {
+    const dig_config& g = cfgs[0];
+    for (int j = 0; j <= g.ny; ++j) {
+      const double r = annulus_face(g, j);
+      c->rf2_host.push_back((float)(r * r));
+    }
+    for (int i = 0; i <= g.nx; ++i) {
+      const double th = 2.0 * M_PI * (double)(i % g.nx) / (double)g.nx;
+      c->dir_host.push_back((float)cos(th));
+      c->dir_host.push_back((float)sin(th));
+    }
+    if (g.bc[1].type == DIG_BC_FREESTREAM) c->inj_sectors = g.nx;
   }
   hipStream_t s = (hipStream_t)stream;
   StepArgs a = args(c);
@@ -479,6 +582,14 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
                                 sizeof(InstParam) * n_inst, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(a.cell_inst, c->cell_inst_host.data(), 4 * C, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((void*)a.cvol, c->cvol_host.data(), 8 * C, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !c->rf2_host.empty())
+    e = hipMemcpyAsync((void*)a.rf2, c->rf2_host.data(), 4 * c->rf2_host.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !c->dir_host.empty())
+    e = hipMemcpyAsync((void*)a.dir, c->dir_host.data(), 4 * c->dir_host.size(),
+                       hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_i32(a.count, C, 0, s);
   if (e == hipSuccess) e = launch_fill_f64(a.acc, 17 * C, 0.0, s);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i)
@@ -591,6 +702,8 @@ dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_strea
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!target) return fail(DIG_ERR_INVALID, "null target");
   if (c->n_inst != 1) return fail(DIG_ERR_INVALID, "dig_adjust needs a single-instance context");
+  if (c->cfg[0].geometry != DIG_GEOM_BOX)
+    return fail(DIG_ERR_INVALID, "dig_adjust supports box geometry only");
   if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
   if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
   hipStream_t s = (hipStream_t)stream;
@@ -637,6 +750,9 @@ dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, d
   if (!fields || !A || !hot || !mask || !kngll) return fail(DIG_ERR_INVALID, "null argument");
   const double det = A[0] * A[3] - A[1] * A[2];
   if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
+  for (const auto& g : c->cfg)
+    if (g.geometry != DIG_GEOM_BOX)
+      return fail(DIG_ERR_INVALID, "closure_assemble supports box geometry only");
   StepArgs a = args(c);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(timed(c, DIG_K_CLOSURE, s, [&] {
@@ -665,6 +781,7 @@ dig_status closure_features(dig_ctx* c, const double* fields, const double* kngl
                             dig_stream_t stream) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!fields || !kngll || !x || (t && !hot)) return fail(DIG_ERR_INVALID, "null argument");
+  if (c->cfg[0].geometry != DIG_GEOM_BOX) return fail(DIG_ERR_INVALID, "box geometry only");
   MlpScale sc;
   dig_status st = scaling_of(scaling, &sc);
   if (st != DIG_OK) return st;
@@ -706,6 +823,8 @@ dig_status dsmc_query(dig_ctx* c, dig_counters* out, dig_stream_t stream) {
   out->inelastic = sum[ST_INEL];
   out->saturated = sum[ST_SAT];
   out->wall_hits = sum[ST_HITS];
+  out->removed = sum[ST_REMOVED];
+  out->injected = sum[ST_INJECTED];
   return DIG_OK;
 }
 

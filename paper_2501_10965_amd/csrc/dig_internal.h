@@ -35,11 +35,18 @@ struct InstParam {
   float bc_U[4][3];
   float inv_dx, inv_dy, gx, gy;
   float dtf, csig, expo, beta_inv;
-  uint32_t key0, key1, inst, pad2;
+  uint32_t key0, key1, inst, geom;
   double pin;            // P_inelastic (decisions taken in double)
   double weight, dt, vol;
   double mu0, omega, dx, dy;
+  // annulus: FP32 squared radii of the inner and outer circles (rounded from
+  // FP64), their radii, the angular width of a cell; freestream reservoir:
+  // outer radius squared, mean particle count per angular sector
+  float rin2, rout2, rin, rout;
+  float res2, dthf, pad3, pad4;
+  double res_mean, rho_inf;
 };
+enum : uint32_t { TAG_INFLOW = 10 };
 
 struct DevState {
   float *x, *y, *vx, *vy, *vz, *er;
@@ -97,7 +104,16 @@ struct StepArgs {
   int32_t group_particles, group_cells, lds_particles;
   int32_t seq_max;  // cells with at most this many particles collide on one lane
   int64_t n_upper;
+  const double* cvol;  // [ncell] cell volumes
+  const float* rf2;    // annulus: [ny + 1] FP32 squared face radii
+  const float2* dir;   // annulus: [nx + 1] FP32 (cos, sin) of the angular faces
+  int32_t* inj_off;    // freestream: [nx + 2] inflow offsets per angular sector
+  int64_t capacity;
+  int32_t inj_sectors;  // angular sectors with inflow (0: closed domain)
 };
+enum { ST_REMOVED = 5, ST_INJECTED = 6 };
+
+hipError_t launch_inject(const StepArgs& a, hipStream_t s);
 
 // Standardisation of the closure network's inputs and targets.
 struct MlpScale {

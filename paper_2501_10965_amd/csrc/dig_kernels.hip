@@ -73,9 +73,140 @@ static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
 }
 
 // ---------------------------------------------------------------------------
+// Annulus cell map.  The radial index compares the FP32 squared radius with
+// the FP32 table of squared face radii; the angular index starts from atan2
+// and is settled by the signs of FP32 cross products with the face
+// directions.  Both are rounded operations without contraction, so the
+// oracle takes the same decisions from the same stored position.
+static __device__ int annulus_cell(const StepArgs& a, const InstParam& I, float x, float y) {
+#pragma clang fp contract(off)
+  const float r2 = x * x + y * y;
+  const int nr = I.ny, nt = I.nx;
+  int lo = 0, hi = nr - 1;  // largest j with rf2[j] <= r2 (clamped to the ring)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.rf2[mid] <= r2) lo = mid; else hi = mid - 1;
+  }
+  const int j = lo;
+  float th = atan2f(y, x);
+  if (th < 0.0f) th += 6.28318530717958648f;
+  int i = (int)(th * (float)nt * 0.15915494309189535f);
+  i = i < 0 ? 0 : (i >= nt ? nt - 1 : i);
+  for (int it = 0; it < 4; ++it) {
+    const float2 d0 = a.dir[i], d1 = a.dir[i + 1];
+    const float c0 = d0.x * y - d0.y * x;  // >= 0: at or past face i
+    const float c1 = d1.x * y - d1.y * x;  // < 0: before face i + 1
+    if (c0 < 0.0f) {
+      i = i == 0 ? nt - 1 : i - 1;
+    } else if (c1 >= 0.0f) {
+      i = i == nt - 1 ? 0 : i + 1;
+    } else {
+      break;
+    }
+  }
+  return I.cell0 + i + nt * j;
+}
+
+// Diffuse re-emission from a circular wall with unit normal (nx, ny) into the
+// gas: normal speed from the flux-weighted Maxwellian, tangential and z
+// components Gaussian, rotational energy exponential (d_r = 2).
+static __device__ __forceinline__ void circle_diffuse(const InstParam& P, int face, uint4 w,
+                                                      float nx, float ny, float* vx, float* vy,
+                                                      float* vz, float* er) {
+  const float T = P.bc_T[face];
+  const float vn = fsqrt(-2.0f * T * flog(u01f(w.x)));
+  const float r = fsqrt(-2.0f * flog(u01f(w.y)));
+  const float ph = 6.28318530717958648f * u01f(w.z);
+  const float sn = __sinf(ph), cs = __cosf(ph);
+  const float sT = fsqrt(T);
+  const float vt = sT * (r * cs);
+  *vx = vn * nx - vt * ny;
+  *vy = vn * ny + vt * nx;
+  *vz = sT * (r * sn);
+  *er = -T * flog(u01f(w.w));
+}
+
+// Free flight in the annulus: reflection at the inner circle (and at the outer
+// circle when it is a wall); with a freestream outer boundary a particle that
+// ends outside it has left (returns -1).  Wall events in time order.
+static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_t p,
+                                   uint32_t step, int* hits) {
+  float x = a.A.x[p], y = a.A.y[p];
+  float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
+  float t = P.dtf;
+  int hit = 0;
+  bool vset = false, er_set = false;
+  float er = 0.0f;
+  const bool outer_wall = P.bc_type[1] != DIG_BC_FREESTREAM;
+  while (hit < kMaxHits) {
+    const float A = vx * vx + vy * vy;
+    if (!(A > 0.0f)) break;
+    const float B = x * vx + y * vy;  // half the linear coefficient
+    const float R2 = x * x + y * y;
+    float th = t;
+    int face = -1;
+    // inner circle, reached from outside while approaching it
+    if (B < 0.0f) {
+      const float D = B * B - A * (R2 - P.rin2);
+      if (D >= 0.0f) {
+        const float tf = (-B - fsqrt(D)) / A;
+        if (tf >= 0.0f && tf <= th) { th = tf; face = 0; }
+      }
+    }
+    if (outer_wall) {
+      const float D = B * B - A * (R2 - P.rout2);
+      if (D >= 0.0f) {
+        const float tf = (-B + fsqrt(D)) / A;
+        if (tf >= 0.0f && tf < th) { th = tf; face = 1; }
+      }
+    }
+    if (face < 0) break;
+    x += vx * th;
+    y += vy * th;
+    t -= th;
+    // back onto the circle; unit normal into the gas
+    const float rr = fsqrt(x * x + y * y);
+    const float nx = (face == 0 ? 1.0f : -1.0f) * x / rr;
+    const float ny = (face == 0 ? 1.0f : -1.0f) * y / rr;
+    const float Rw = face == 0 ? P.rin : P.rout;
+    x = Rw * (x / rr);
+    y = Rw * (y / rr);
+    if (P.bc_type[face] == DIG_BC_SPECULAR) {
+      const float vn = vx * nx + vy * ny;
+      vx -= 2.0f * vn * nx;
+      vy -= 2.0f * vn * ny;
+    } else {
+      const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
+      circle_diffuse(P, face, w, nx, ny, &vx, &vy, &vz, &er);
+      er_set = true;
+    }
+    vset = true;
+    ++hit;
+  }
+  x += vx * t;
+  y += vy * t;
+  a.A.x[p] = x;
+  a.A.y[p] = y;
+  if (vset) {
+    a.A.vx[p] = vx;
+    a.A.vy[p] = vy;
+    a.A.vz[p] = vz;
+    if (er_set) a.A.er[p] = er;
+  }
+  *hits = hit;
+  if (!outer_wall) {
+#pragma clang fp contract(off)
+    const float r2 = x * x + y * y;
+    if (r2 >= P.rout2) return -1;
+  }
+  return annulus_cell(a, P, x, y);
+}
+
+// ---------------------------------------------------------------------------
 // Free flight with diffuse / specular walls for one particle; returns its cell.
 static __device__ __forceinline__ int move_particle(const StepArgs& a, const InstParam& P,
                                                     int64_t p, uint32_t step, int* hits) {
+  if (P.geom == DIG_GEOM_ANNULUS) return move_annulus(a, P, p, step, hits);
   const bool two = P.dim == 2;
   float x = a.A.x[p];
   float y = two ? a.A.y[p] : 0.0f;
@@ -190,17 +321,20 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
   } else if (valid) {
     cell = move_particle(a, a.params[inst], p, step, &hits_here);
   }
+  // a particle that left through an open boundary reserves nothing
+  const bool gone = valid && cell < 0;
+  const bool keep = valid && !gone;
   // wave-aggregated reservation: one atomic per (wave, destination cell); the
   // lanes of a run get consecutive ranks in lane (= slot) order
   // The runs are found with ballots (no memory traffic); then every run
   // leader reserves its run with the same atomic instruction.
-  unsigned long long todo = __ballot(valid);
+  unsigned long long todo = __ballot(keep);
   int my_leader = 0, in_run = 0, run_len = 0;
   while (todo) {
     const int leader = __ffsll(todo) - 1;
     const int lc = __shfl(cell, leader);
-    const unsigned long long m = __ballot(valid && cell == lc);
-    if (valid && cell == lc) {
+    const unsigned long long m = __ballot(keep && cell == lc);
+    if (keep && cell == lc) {
       my_leader = leader;
       in_run = __popcll(m & __lanemask_lt());
     }
@@ -214,11 +348,14 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
     a.cell[p] = cell;
     a.rank[p] = base + in_run;
   }
-  // wall-hit statistics: one atomic per wave into a spread slot
+  // wall-hit and removal statistics: one atomic per wave into a spread slot
   int hsum = hits_here;
   for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
   if (lane_id() == 0 && hsum)
     atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_HITS], (unsigned long long)hsum);
+  const int ngone = __popcll(__ballot(gone));
+  if (lane_id() == 0 && ngone)
+    atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_REMOVED], (unsigned long long)ngone);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +465,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(StepArgs a, int32_t* counts,
 __global__ __launch_bounds__(256) void k_place(StepArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.ctr->n) return;
-  a.perm_raw[a.start[a.cell[p]] + a.rank[p]] = (int32_t)p;
+  const int c = a.cell[p];
+  if (c >= 0) a.perm_raw[a.start[c] + a.rank[p]] = (int32_t)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -553,7 +691,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     if (N >= 2) {
       const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_NCAND, 0);
-      k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, I.vol), r.x);
+      k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, a.cvol[c_lo + c]), r.x);
     }
     if (N <= a.seq_max) ks[c - cb] = k; else kg[c - cb] = k;
     tsum_s += ks[c - cb];
@@ -879,9 +1017,106 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_
   }
 }
 
-__global__ void k_step_end(dig_counters* c, int sample) {
+// End of a step: the sorted count becomes the particle count (particles may
+// have left through an open boundary), the step counter advances.
+__global__ void k_step_end(dig_counters* c, const int32_t* total, int sample) {
+  c->n = *total;
   c->step += 1;
   if (sample) c->nsamp += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Freestream inflow at the outer circle of an annulus: every step a reservoir
+// shell r_out < r < r_res outside the domain is filled with freestream gas
+// (Iround of rho V / N_eff particles per angular sector), appended after the
+// current particles and moved with them; those that do not end inside the
+// domain are removed by the move.  The shell is thicker than the distance a
+// freestream particle travels in one step (|U| + 6 sqrt(T)) dt.
+__global__ __launch_bounds__(256) void k_inject_count(StepArgs a) {
+  __shared__ int s_w[4];
+  __shared__ int s_run;
+  const InstParam& I = a.params[0];
+  const uint32_t step = (uint32_t)a.ctr->step;
+  const int nt = I.nx;
+  if (threadIdx.x == 0) s_run = 0;
+  __syncthreads();
+  for (int f0 = 0; f0 < nt; f0 += 256) {
+    const int f = f0 + threadIdx.x;
+    int k = 0;
+    if (f < nt) {
+      const uint4 r = draw(I, (uint32_t)f, step, TAG_INFLOW, 0);
+      k = iround(I.res_mean, r.x);
+    }
+    int incl = k;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane_id() >= off) incl += v;
+    }
+    if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int pre = s_run;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += s_w[w];
+    if (f < nt) a.inj_off[f] = pre + incl - k;
+    __syncthreads();
+    if (threadIdx.x == 0) s_run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+  }
+  // inj_off[nt]: all sectors; inj_off[nt + 1]: what fits in the capacity
+  if (threadIdx.x == 0) {
+    int64_t tot = s_run;
+    const int64_t n0 = a.ctr->n;
+    a.inj_off[nt] = (int32_t)tot;
+    if (n0 + tot > a.capacity) {
+      tot = a.capacity - n0;
+      atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_INFLOW);
+    }
+    a.inj_off[nt + 1] = (int32_t)tot;
+  }
+}
+
+// One workgroup per angular sector writes that sector's reservoir particles.
+__global__ __launch_bounds__(256) void k_inject_fill(StepArgs a) {
+  const InstParam& I = a.params[0];
+  const int f = blockIdx.x;
+  const int nt = I.nx;
+  const uint32_t step = (uint32_t)a.ctr->step;
+  const int64_t n0 = a.ctr->n;
+  const int total = a.inj_off[nt + 1];
+  const int o0 = a.inj_off[f], o1 = a.inj_off[f + 1];
+  const float T = I.bc_T[1];
+  const float sT = sqrtf(T);
+  const float ra2 = I.rout2, rb2 = I.res2;
+  for (int k = threadIdx.x; k < o1 - o0; k += blockDim.x) {
+    const int q = o0 + k;
+    if (q >= total) break;
+    const uint4 w0 = draw(I, (uint32_t)f, step, TAG_INFLOW, 1u + 2u * (uint32_t)k);
+    const uint4 w1 = draw(I, (uint32_t)f, step, TAG_INFLOW, 2u + 2u * (uint32_t)k);
+    const float r = sqrtf(ra2 + u01f(w0.x) * (rb2 - ra2));
+    const float th = I.dthf * ((float)f + u01f(w0.y));
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    const float g1 = sqrtf(-2.0f * logf(u01f(w0.z)));
+    float s0, c0, s1, c1;
+    sincospif(2.0f * u01f(w0.w), &s0, &c0);
+    const float g2 = sqrtf(-2.0f * logf(u01f(w1.x)));
+    sincospif(2.0f * u01f(w1.y), &s1, &c1);
+    const int64_t p = n0 + q;
+    a.A.x[p] = r * cs;
+    a.A.y[p] = r * sn;
+    a.A.vx[p] = I.bc_U[1][0] + sT * (g1 * c0);
+    a.A.vy[p] = I.bc_U[1][1] + sT * (g1 * s0);
+    a.A.vz[p] = I.bc_U[1][2] + sT * (g2 * c1);
+    a.A.er[p] = -T * logf(u01f(w1.z));
+    a.A.id[p] = (uint32_t)(a.ctr->next_id + q);
+  }
+}
+
+// Adopts the inflow: particle count and next id (one thread, after the fill).
+__global__ void k_inject_end(StepArgs a) {
+  const int total = a.inj_off[a.params[0].nx + 1];
+  a.ctr->n += total;
+  a.ctr->next_id += total;
+  a.stats[ST_INJECTED] += (unsigned long long)total;
 }
 
 // ---------------------------------------------------------------------------
@@ -916,7 +1151,7 @@ __global__ void k_init_count(StepArgs a, const double* fields, int32_t ppc) {
   }
   const InstParam& I = a.params[a.cell_inst[c]];
   const uint4 r = draw(I, (uint32_t)(c - I.cell0), 0, TAG_INIT_N, 0);
-  a.count[c] = iround(count_mean(fields[c], I.vol, I.weight), r.x);
+  a.count[c] = iround(count_mean(fields[c], a.cvol[c], I.weight), r.x);
 }
 
 __global__ void k_init_fill(StepArgs a, const double* fields) {
@@ -938,8 +1173,18 @@ __global__ void k_init_fill(StepArgs a, const double* fields) {
   sincospif(2.0f * u01f(r0.w), &s0, &c0);
   const float rb = sqrtf(-2.0f * logf(u01f(r1.x)));
   sincospif(2.0f * u01f(r1.y), &s1, &c1);
-  a.A.x[p] = keep_inside((float)ix + u01f(r0.x), ix);
-  if (I.dim == 2) a.A.y[p] = keep_inside((float)iy + u01f(r0.y), iy);
+  if (I.geom == DIG_GEOM_ANNULUS) {
+    // uniform over the cell's area: r^2 uniform between its face radii
+    const float ra2 = a.rf2[iy], rb2 = a.rf2[iy + 1];
+    const float r = sqrtf(ra2 + u01f(r0.x) * (rb2 - ra2));
+    float sn, cs;
+    sincosf(I.dthf * ((float)ix + u01f(r0.y)), &sn, &cs);
+    a.A.x[p] = r * cs;
+    a.A.y[p] = r * sn;
+  } else {
+    a.A.x[p] = keep_inside((float)ix + u01f(r0.x), ix);
+    if (I.dim == 2) a.A.y[p] = keep_inside((float)iy + u01f(r0.y), iy);
+  }
   a.A.vx[p] = (float)fields[1 * C + c] + st * (ra * c0);
   a.A.vy[p] = (float)fields[2 * C + c] + st * (ra * s0);
   a.A.vz[p] = (float)fields[3 * C + c] + st * (rb * c1);
@@ -979,7 +1224,8 @@ __global__ void k_convert(StepArgs a, const double* sums, int average, double* o
   for (int f = 0; f < 20; ++f) o[f] = 0.0;
   const double N = s[0];
   if (N > 0.0) {
-    const double rho = I.weight * N / (I.vol * ns);
+    const double vol = a.cvol[c];
+    const double rho = I.weight * N / (vol * ns);
     const double ux = s[1] / N, uy = s[2] / N, uz = s[3] / N;
     const double mxx = s[4] / N, myy = s[5] / N, mzz = s[6] / N;
     const double mxy = s[7] / N, mxz = s[8] / N, myz = s[9] / N;
@@ -1036,7 +1282,7 @@ __global__ void k_adjust_count(StepArgs a, const double* target, uint32_t iter,
     return;
   }
   const uint4 w = draw(I, (uint32_t)(c - I.cell0), iter, TAG_DIG_N, 0);
-  const int nt = iround(count_mean(r, I.vol, I.weight), w.x);
+  const int nt = iround(count_mean(r, a.cvol[c], I.weight), w.x);
   const int N = a.start[c + 1] - a.start[c];
   newcount[c] = nt;
   ccount[c] = (N == 0) ? nt : (nt > N ? nt - N : 0);
@@ -1441,7 +1687,17 @@ hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStrea
 }
 
 hipError_t launch_step_end(const StepArgs& a, bool sample, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, a.ctr, sample ? 1 : 0);
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, a.ctr, a.start + a.ncell,
+                     sample ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(const StepArgs& a, hipStream_t s) {
+  const int nt = a.inj_sectors;
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inject_count, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_inject_fill, dim3(nt), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_inject_end, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
 

@@ -414,6 +414,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   if (!cfg || !opts || !m_half || !m_next || !workspace || !iters || !change) return DIG_ERR_INVALID;
   if (cfg->dim != 1 && cfg->dim != 2) return DIG_ERR_INVALID;
   if (cfg->dim == 1 && cfg->ny != 1) return DIG_ERR_INVALID;
+  if (cfg->geometry != DIG_GEOM_BOX) return report(DIG_ERR_INVALID, "synth_solve: box only");
   if (max_iter < 0 || !(opts->cfl > 0.0)) return DIG_ERR_INVALID;
   const SynthLayout L = synth_layout(cfg);
   if (ws_bytes < L.total) return DIG_ERR_INVALID;

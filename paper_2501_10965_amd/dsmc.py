@@ -44,7 +44,8 @@ class DSMC:
         self.ncell = int(sum(self.ncells))
         self.cell0 = np.concatenate([[0], np.cumsum(self.ncells)]).astype(np.int64)
         if capacity is None:
-            est = sum(nc * w.get("ppc", 1) for nc, w in zip(self.ncells, self.workloads))
+            est = sum(nc * w.get("ppc", 1) if w.get("ppc", 1) > 0 else w["n_target"]
+                      for nc, w in zip(self.ncells, self.workloads))
             capacity = int(est * cap_factor) + 1024
         self.capacity = int(capacity)
         self.layout = L.DigLayout()
