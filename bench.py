@@ -302,9 +302,64 @@ def run_mlp(args):
     }
 
 
+def run_cylinder(args):
+    """Mach 5 flow past a cylinder: 500 x 400 stretched polar cells, ~50M
+    particles, freestream inflow and outflow every step, plain DSMC from a gas
+    at rest (the timed steps are the start of the transient)."""
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd.dsmc import DSMC
+
+    w = wl.cylinder()
+    sim = DSMC(w, cap_factor=1.3, group_particles=args.group_particles,
+               group_cells=args.group_cells)
+    sim.init()
+    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
+    k0 = sim.counters()["step"]
+    sim.step(max(args.warmup - k0, 0), graph=True)
+    torch.cuda.synchronize()
+    steps = args.steps
+    c0 = sim.counters()
+    sim.profile("on")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile("read")
+    sim.profile("off")
+    c1 = sim.counters()
+    n_avg = 0.5 * (c0["n"] + c1["n"])
+    out = summarise(prof, n_avg * steps, t1 - t0, steps, n_avg, sim.ncell, 2, "cylinder")
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    sim.step(steps, graph=True)
+    torch.cuda.synchronize()
+    tg1 = time.perf_counter()
+    c2 = sim.counters()
+    ng = 0.5 * (c1["n"] + c2["n"])
+    out["graph_replay"] = {"value": ng * steps / (tg1 - tg0), "unit": "particle-steps/s",
+                           "steps": steps, "ms_per_step": (tg1 - tg0) / steps * 1e3}
+    out.update(particles=int(n_avg), cells=sim.ncell, err_bits=c2["err"], tuning=tuning,
+               dig_loop=None,
+               inflow_per_step=(c1["injected"] - c0["injected"]) / steps,
+               removed_per_step=(c1["removed"] - c0["removed"]) / steps,
+               collisions_per_particle_step=(c1["accepted"] - c0["accepted"]) * 2 /
+               max(n_avg * steps, 1),
+               workload="Mach 5 cylinder, Kn 0.01, 500x400 stretched polar cells, ~50M "
+                        "particles, freestream inflow/outflow, plain DSMC (early transient)")
+    return out, w
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(w, steps, dig: bool):
     import oracle
 
+    progress(f"oracle baseline on {w['name']}, {steps} steps")
     nthreads = 1
     s = oracle.new_state(w)
     t0 = time.perf_counter()
@@ -348,7 +403,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--workload", choices=["cavity", "batch", "mlp"], default="cavity")
+    ap.add_argument("--workload", choices=["cavity", "batch", "mlp", "cylinder"],
+                    default="cavity")
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -365,6 +421,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    progress(f"workload {args.workload}")
     if args.workload == "mlp":
         res = run_mlp(args)
         line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"],
@@ -381,6 +438,12 @@ def main():
     if args.workload == "batch":
         res, wcpu = run_batch(args)
         cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, 300, dig=False)
+    elif args.workload == "cylinder":
+        res, wcpu = run_cylinder(args)
+        # bounded sample: the same geometry and flow with 4M particles
+        import dig_workloads as wl
+        wsmall = wl.cylinder(n_target=4_000_000)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(wsmall, 50, dig=False)
     else:
         res, wcpu = run_cavity(args)
         cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, args.cpu_steps, dig=True)

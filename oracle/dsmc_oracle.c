@@ -327,28 +327,33 @@ int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* v
 /* Cell of a grid-unit position: floor, clamped to the last cell when a
  * particle sits exactly on the upper face. */
 /* Annulus cell of a position, decided in single precision (the position as
- * stored in FP32): the squared radius against the FP32 squared face radii,
- * and the angular sector as the unique i with d_i x p >= 0 > d_{i+1} x p for
- * the FP32 face directions d_i = (cos 2 pi i/nx, sin 2 pi i/nx).  Outside a
+ * stored in FP32): the squared radius against the FP32 squared face radii
+ * (rf2, ny + 1 entries), and the angular sector as the unique i with
+ * d_i x p >= 0 > d_{i+1} x p for the FP32 face directions
+ * d_i = (cos 2 pi i/nx, sin 2 pi i/nx) (dir, nx + 1 pairs, the last equal to
+ * the first); the search for it starts at the sector of atan2.  Outside a
  * freestream outer circle: -1. */
-static int32_t annulus_cell(const orc_config* c, double xd, double yd) {
+static int32_t annulus_cell(const orc_config* c, const float* rf2, const float* dir, double xd,
+                            double yd) {
   float x = (float)xd, y = (float)yd;
   float r2 = x * x + y * y;
-  double ro = orc_annulus_face(c, c->ny);
-  if (c->bc_type[1] == ORC_BC_FREESTREAM && r2 >= (float)(ro * ro)) return -1;
-  int32_t j = 0;
-  for (int32_t k = 1; k < c->ny; ++k) {
-    double rk = orc_annulus_face(c, k);
-    if ((float)(rk * rk) <= r2) j = k;
+  if (c->bc_type[1] == ORC_BC_FREESTREAM && r2 >= rf2[c->ny]) return -1;
+  int32_t lo = 0, hi = c->ny - 1; /* largest j <= ny - 1 with rf2[j] <= r2, else 0 */
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) / 2;
+    if (rf2[mid] <= r2) lo = mid; else hi = mid - 1;
   }
-  for (int32_t i = 0; i < c->nx; ++i) {
-    double t0 = 2.0 * M_PI * (double)i / (double)c->nx;
-    double t1 = 2.0 * M_PI * (double)((i + 1) % c->nx) / (double)c->nx;
-    float d0x = (float)cos(t0), d0y = (float)sin(t0);
-    float d1x = (float)cos(t1), d1y = (float)sin(t1);
-    float c0 = d0x * y - d0y * x;
-    float c1 = d1x * y - d1y * x;
-    if (c0 >= 0.0f && c1 < 0.0f) return i + c->nx * j;
+  double th = atan2((double)y, (double)x);
+  if (th < 0.0) th += 2.0 * M_PI;
+  int32_t i = (int32_t)(th / (2.0 * M_PI) * c->nx);
+  if (i < 0) i = 0;
+  if (i >= c->nx) i = c->nx - 1;
+  for (int32_t it = 0; it <= c->nx; ++it) {
+    float c0 = dir[2 * i] * y - dir[2 * i + 1] * x;
+    float c1 = dir[2 * i + 2] * y - dir[2 * i + 3] * x;
+    if (c0 < 0.0f) i = (i == 0) ? c->nx - 1 : i - 1;
+    else if (c1 >= 0.0f) i = (i == c->nx - 1) ? 0 : i + 1;
+    else return i + c->nx * lo;
   }
   return -2; /* no sector: cannot happen for nx >= 3 */
 }
@@ -356,7 +361,20 @@ static int32_t annulus_cell(const orc_config* c, double xd, double yd) {
 void orc_cell_index(const orc_config* c, int64_t n, const double* x, const double* y,
                     int32_t* cell) {
   if (c->geometry == ORC_GEOM_ANNULUS) {
-    for (int64_t p = 0; p < n; ++p) cell[p] = annulus_cell(c, x[p], y[p]);
+    float* rf2 = (float*)malloc(sizeof(float) * (size_t)(c->ny + 1));
+    float* dir = (float*)malloc(sizeof(float) * 2 * (size_t)(c->nx + 1));
+    for (int32_t j = 0; j <= c->ny; ++j) {
+      double r = orc_annulus_face(c, j);
+      rf2[j] = (float)(r * r);
+    }
+    for (int32_t i = 0; i <= c->nx; ++i) {
+      double t = 2.0 * M_PI * (double)(i % c->nx) / (double)c->nx;
+      dir[2 * i] = (float)cos(t);
+      dir[2 * i + 1] = (float)sin(t);
+    }
+    for (int64_t p = 0; p < n; ++p) cell[p] = annulus_cell(c, rf2, dir, x[p], y[p]);
+    free(rf2);
+    free(dir);
     return;
   }
   for (int64_t p = 0; p < n; ++p) {
