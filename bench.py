@@ -352,6 +352,67 @@ def run_cylinder(args):
     return out, w
 
 
+def run_steady(args):
+    """Time to steady state at a fixed centreline-velocity error on the
+    cavity: plain DSMC, DIG with DSMC-extracted terms, DIG with the learned
+    closure (trained here on the cavity family; its training time is reported
+    separately)."""
+    import math
+
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd import learn, steady
+    from paper_2501_10965_amd.mlp import MLP
+
+    w = wl.cavity_2d(seed=2001)
+    P, W, thr = 20, 20, args.steady_threshold
+    progress("reference run")
+    ref = steady.reference_profile(w, 60000, 120000, P)
+    arms = {}
+    progress("plain DSMC arm")
+    tr = steady.run_plain(w, ref, w["ns"], 1200, W, thr, P)
+    arms["dsmc"] = tr
+    progress("DIG arm (DSMC-extracted terms)")
+    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, ns=w["ns"],
+                           n_m=args.synth_iters, wall_mode="wall")
+    arms["dig"] = tr
+    progress("closure-network training")
+    KNS = [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5]
+    MAS = [0.1, 0.25, 0.5, 1.0]
+    ws = [wl.cavity_2d(seed=4000 + i, n=100, ppc=50, kn=k, lid=m * math.sqrt(1.4))
+          for i, (k, m) in enumerate((k, m) for k in KNS for m in MAS)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    from paper_2501_10965_amd.dsmc import DSMC
+    batch = DSMC(ws, cap_factor=1.05)
+    batch.init_batch()
+    batch.step(2000, graph=True)
+    x, t, _ = learn.collect(batch, windows=6, window_steps=1000)
+    del batch
+    sc = learn.fit_scaling(x, t)
+    xs, ts = learn.standardise(x, t, sc)
+    net = MLP(wl.mlp_init(7), max_batch=4096)
+    learn.train(net, xs, ts, steps=3000, batch=4096, lr=2e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    progress("DIG arm (learned closure)")
+    hook = learn.LearnedClosure(net, sc, kn_lo=0.01, judge_abs=1.0, judge_rel=0.5)
+    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, closure=hook, ns=w["ns"],
+                           n_m=args.synth_iters, wall_mode="wall")
+    arms["dig_learned"] = tr
+    res = {}
+    for name, tr in arms.items():
+        t = tr.time_to_steady()
+        res[name] = {"seconds": None if t is None else round(t[0], 3),
+                     "steps": None if t is None else t[1],
+                     "final_err": round(tr.history[-1][2], 5) if tr.history else None,
+                     "err_at": [(round(a, 3), b, round(e, 5)) for a, b, e in tr.history[::10]]}
+    res["dig_learned"]["training_seconds"] = round(train_s, 2)
+    base = res["dsmc"]["seconds"]
+    return res, base
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -403,8 +464,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--workload", choices=["cavity", "batch", "mlp", "cylinder"],
+    ap.add_argument("--workload", choices=["cavity", "batch", "mlp", "cylinder", "steady"],
                     default="cavity")
+    ap.add_argument("--steady-threshold", type=float, default=0.02)
+    ap.add_argument("--dig-max-cycles", type=int, default=160)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -422,6 +485,20 @@ def main():
         copy_calibration()
         return
     progress(f"workload {args.workload}")
+    if args.workload == "steady":
+        res, base = run_steady(args)
+        learned = res["dig_learned"]["seconds"]
+        line = {"metric": "time-to-steady-state at fixed error, learned vs plain",
+                "value": learned, "unit": "s", "n_gpus": 1, "steps": None,
+                "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                "config": {"workload": "cavity 200x200, 2M particles, Kn 0.01, lid Ma 0.3; "
+                           "centreline u_x, 20 block averages, window 20 cycles of 50 steps, "
+                           f"RMS error <= {args.steady_threshold} of the reference range; "
+                           "reference 60k + 120k plain-DSMC steps"},
+                "plain_dsmc_seconds": base, "arms": res}
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "mlp":
         res = run_mlp(args)
         line = {"metric": res["metric"], "value": res["value"], "unit": res["unit"],

@@ -75,9 +75,10 @@ __device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int
 }
 
 // NSF + HoT stress and heat flux through a face normal to `axis`.
-__device__ void visc_flux(const SynthGrid& g, int axis, double tf, const double uf[3],
-                          const double dn[3], const double dt[3], double dTt, double dTr,
-                          const double Hf[12], double V[6]) {
+template <int axis>
+__device__ __forceinline__ void visc_flux(const SynthGrid& g, double tf, const double uf[3],
+                                          const double dn[3], const double dt[3], double dTt,
+                                          double dTr, const double Hf[12], double V[6]) {
   const double mu = g.mu0 * pow(tf, g.omega);
   double kt, kr;
   conductivities(g, mu, &kt, &kr);
@@ -103,7 +104,8 @@ __device__ void visc_flux(const SynthGrid& g, int axis, double tf, const double 
   V[5] = qr;
 }
 
-__device__ void euler_flux(int axis, const double U[6], const Prim& p, double F[6]) {
+template <int axis>
+__device__ __forceinline__ void euler_flux(const double U[6], const Prim& p, double F[6]) {
   const double pr = p.rho * p.tt;
   const double un = p.u[axis];
   F[0] = U[0] * un;
@@ -112,8 +114,9 @@ __device__ void euler_flux(int axis, const double U[6], const Prim& p, double F[
   F[5] = U[5] * un;
 }
 
-__device__ void hllc_star(int axis, const double U[6], const Prim& p, double SK, double Ss,
-                          double out[6]) {
+template <int axis>
+__device__ __forceinline__ void hllc_star(const double U[6], const Prim& p, double SK, double Ss,
+                                          double out[6]) {
   const double pr = p.rho * p.tt;
   const double f = p.rho * (SK - p.u[axis]) / (SK - Ss);
   out[0] = f;
@@ -124,13 +127,8 @@ __device__ void hllc_star(int axis, const double U[6], const Prim& p, double SK,
 
 // Flux through face (fi, fj) normal to `axis`: x faces are (fx, iy) with
 // fx in [0, nx], y faces (ix, fy) with fy in [0, ny].
-__global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0 && axis == 0) {
-    // reset the accumulators of the next iteration's reductions
-    s.red[((it + 1) & 1) * 2 + 0] = 0x7FF0000000000000ull;  // +inf
-    s.red[((it + 1) & 1) * 2 + 1] = 0ull;
-  }
+template <int axis>
+__device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays& s, int t) {
   const int C = g.nx * g.ny;
   const int nfa = axis == 0 ? g.nx + 1 : g.nx;
   const int nfb = axis == 0 ? g.ny : g.ny + 1;
@@ -156,8 +154,8 @@ __global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
       Ul[k] = s.W[k * C + cl];
       Ur[k] = s.W[k * C + cr];
     }
-    euler_flux(axis, Ul, pl, Fl);
-    euler_flux(axis, Ur, pr, Fr);
+    euler_flux<axis>(Ul, pl, Fl);
+    euler_flux<axis>(Ur, pr, Fr);
     const double cL = sqrt(g.gam * pl.tt), cR = sqrt(g.gam * pr.tt);
     const double SL = fmin(pl.u[axis] - cL, pr.u[axis] - cR);
     const double SR = fmax(pl.u[axis] + cL, pr.u[axis] + cR);
@@ -169,11 +167,11 @@ __global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
       for (int k = 0; k < 6; ++k) F[k] = Fl[k];
     } else if (Ss >= 0.0) {
       double Us[6];
-      hllc_star(axis, Ul, pl, SL, Ss, Us);
+      hllc_star<axis>(Ul, pl, SL, Ss, Us);
       for (int k = 0; k < 6; ++k) F[k] = Fl[k] + SL * (Us[k] - Ul[k]);
     } else if (SR > 0.0) {
       double Us[6];
-      hllc_star(axis, Ur, pr, SR, Ss, Us);
+      hllc_star<axis>(Ur, pr, SR, Ss, Us);
       for (int k = 0; k < 6; ++k) F[k] = Fr[k] + SR * (Us[k] - Ur[k]);
     } else {
       for (int k = 0; k < 6; ++k) F[k] = Fr[k];
@@ -193,7 +191,7 @@ __global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
     }
     for (int k = 0; k < 12; ++k) Hf[k] = 0.5 * (s.H[k * C + cl] + s.H[k * C + cr]);
     double V[6];
-    visc_flux(g, axis, tf, uf, dn, dtn, (pr.tt - pl.tt) / h, (pr.tr - pl.tr) / h, Hf, V);
+    visc_flux<axis>(g, tf, uf, dn, dtn, (pr.tt - pl.tt) / h, (pr.tr - pl.tr) / h, Hf, V);
     for (int k = 0; k < 6; ++k) F[k] += V[k];
   } else {
     // wall face: Dirichlet state, zero mass flux
@@ -217,8 +215,8 @@ __global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
     }
     for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
     double V[6];
-    visc_flux(g, axis, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / (0.5 * h),
-              sgn * (p.tr - trw) / (0.5 * h), Hf, V);
+    visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / (0.5 * h),
+                    sgn * (p.tr - trw) / (0.5 * h), Hf, V);
     for (int k = 0; k < 6; ++k) F[k] = V[k];
     F[1 + axis] += p.rho * p.tt;
     F[0] = 0.0;
@@ -226,6 +224,22 @@ __global__ void k_synth_flux(SynthGrid g, SynthArrays s, int axis, int it) {
   double* out = axis == 0 ? s.Fx : s.Fy;
   const int nf = nfa * nfb;
   for (int k = 0; k < 6; ++k) out[(size_t)k * nf + t] = F[k];
+}
+
+// Fluxes of every face of the grid: threads [0, nfx) take the x faces, the
+// rest the y faces.  Thread 0 also resets the next iteration's reductions.
+__global__ __launch_bounds__(256) void k_synth_flux(SynthGrid g, SynthArrays s, int it) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    s.red[((it + 1) & 1) * 2 + 0] = 0x7FF0000000000000ull;  // +inf
+    s.red[((it + 1) & 1) * 2 + 1] = 0ull;
+  }
+  const int nfx = (g.nx + 1) * g.ny;
+  if (t < nfx) {
+    face_flux<0>(g, s, t);
+  } else if (g.dim == 2 && t < nfx + g.nx * (g.ny + 1)) {
+    face_flux<1>(g, s, t - nfx);
+  }
 }
 
 __device__ double inv_local_dt(const SynthGrid& g, const Prim& p) {
@@ -469,12 +483,8 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   double last = INFINITY;
   for (it = 1; it <= max_iter; ++it) {
     SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
-    const int nfx = (g.nx + 1) * g.ny;
-    hipLaunchKernelGGL(k_synth_flux, dim3((nfx + bs - 1) / bs), dim3(bs), 0, s, g, a, 0, it);
-    if (g.dim == 2) {
-      const int nfy = g.nx * (g.ny + 1);
-      hipLaunchKernelGGL(k_synth_flux, dim3((nfy + bs - 1) / bs), dim3(bs), 0, s, g, a, 1, it);
-    }
+    const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
+    hipLaunchKernelGGL(k_synth_flux, dim3((nft + bs - 1) / bs), dim3(bs), 0, s, g, a, it);
     hipLaunchKernelGGL(k_synth_update, dim3(nb), dim3(bs), 0, s, g, a, it);
     double* t = cur;
     cur = nxt;

@@ -31,7 +31,8 @@ class DIG:
     def __init__(self, w: dict, mode: str = "dig", ns: int = 50, n_m: int = 2000,
                  tol: float = 1e-5, kn_ref: float = 0.01, A=None, wall_mode: str = "dsmc",
                  closure=None, capacity: int | None = None, cfl: float = 0.5,
-                 nsf_init: bool = True, init_iters: int | None = None, **dsmc_kw):
+                 nsf_init: bool = True, init_iters: int | None = None, graph: bool = True,
+                 **dsmc_kw):
         assert mode in ("dig", "dsmc")
         self.w = w
         self.mode = mode
@@ -42,6 +43,7 @@ class DIG:
         self.A = A if A is not None else default_A(w["omega"])
         self.wall_mode = wall_mode
         self.cfl = cfl
+        self.graph = graph
         # optional learned closure: (sim, fields, hot, mask, kn, smooth=...) -> hot, where
         # smooth holds the latest macroscopic solution in rows 0..5
         self.closure_fn = closure
@@ -68,7 +70,7 @@ class DIG:
         """One DIG iteration (or N_s plain DSMC steps); returns the averaged field."""
         t0 = time.perf_counter()
         self.sim.reset_average()
-        self.sim.step(self.ns)
+        self.sim.step(self.ns, graph=self.graph)
         f = self.sim.sample("average")
         rec = {"cycle": self.cycle_no}
         if self.mode == "dig":

@@ -1,0 +1,113 @@
+"""Time to steady state at a fixed field error, on one GPU: plain DSMC, DIG
+with DSMC-extracted higher-order terms, and DIG with the learned closure.
+
+The convergence observable is the paper's for the cavity (Section 4.1): the
+velocity u_x along the vertical centreline x = 0.5.  It is taken from the
+DSMC samples of every cycle (N_s steps), averaged over a sliding window of the
+last `window` cycles, reduced to `points` block averages along y (the two
+centre columns), and compared with a reference profile from a long plain-DSMC
+run: err = RMS over the points of |profile - reference| / (max - min of the
+reference).  Steady state is the first wall time after which err stays at or
+below the threshold.  Wall time counts every GPU operation of the method (DSMC
+steps, sampling, closure, synthetic solve, particle modification, network
+inference); the error evaluation is excluded.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import torch
+
+from .dig import DIG
+from .dsmc import DSMC
+
+
+def centreline(f: torch.Tensor, nx: int, ny: int, points: int) -> torch.Tensor:
+    ux = f[1].view(ny, nx)[:, nx // 2 - 1: nx // 2 + 1].mean(1)
+    return ux.view(points, ny // points).mean(1)
+
+
+def reference_profile(w: dict, transient: int, average: int, points: int) -> torch.Tensor:
+    """Plain DSMC from rest: `transient` steps, then the average of `average`."""
+    sim = DSMC(w)
+    sim.init()
+    sim.step(transient, graph=True)
+    sim.reset_average()
+    sim.step(average, graph=True)
+    f = sim.sample("average")
+    return centreline(f, w["nx"], w["ny"], points)
+
+
+class Tracker:
+    def __init__(self, ref: torch.Tensor, window: int, threshold: float):
+        self.ref = ref
+        self.range = float(ref.max() - ref.min())
+        self.buf = collections.deque(maxlen=window)
+        self.threshold = threshold
+        self.history = []  # (wall seconds, steps, err)
+
+    def add(self, prof: torch.Tensor, wall: float, steps: int):
+        self.buf.append(prof)
+        if len(self.buf) < self.buf.maxlen:
+            return None
+        avg = torch.stack(list(self.buf)).mean(0)
+        err = float(((avg - self.ref) ** 2).mean().sqrt()) / self.range
+        self.history.append((wall, steps, err))
+        return err
+
+    def time_to_steady(self):
+        """(wall, steps) of the first point after which err stays <= threshold."""
+        t = None
+        for wall, steps, err in self.history:
+            if err <= self.threshold:
+                if t is None:
+                    t = (wall, steps)
+            else:
+                t = None
+        return t
+
+
+def run_plain(w, ref, ns, max_cycles, window, threshold, points):
+    sim = DSMC(w)
+    sim.init()
+    tr = Tracker(ref, window, threshold)
+    wall = 0.0
+    for k in range(max_cycles):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.reset_average()
+        sim.step(ns, graph=True)
+        f = sim.sample("average")
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        tr.add(centreline(f, w["nx"], w["ny"], points), wall, (k + 1) * ns)
+        if _settled(tr, window):
+            break
+    return tr
+
+
+def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, **kw):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = DIG(w, closure=closure, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0  # NSF initialisation counts
+    tr = Tracker(ref, window, threshold)
+    for k in range(max_cycles):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = d.cycle()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        tr.add(centreline(f, w["nx"], w["ny"], points), wall, (k + 1) * d.ns)
+        if _settled(tr, window):
+            break
+    return tr, d
+
+
+def _settled(tr: Tracker, window: int) -> bool:
+    """Stop once the error has stayed below the threshold for 4 windows."""
+    h = tr.history
+    need = 4 * window
+    return len(h) >= need and all(e <= tr.threshold for _, _, e in h[-need:])
