@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      stats, rf2, dir, inj_off;
+      stats, rf2, dir, inj_off, done;
   int64_t gfirst_len;
 };
 
@@ -206,6 +206,7 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->bsum = take(8 * (scan_blocks((int)C) + 1));
   I->lastcnt = take(4 * (scan_blocks((int)C) + 1));
   I->stats = take(sizeof(unsigned long long) * kStatSlots * ST_N);
+  I->done = take(sizeof(uint32_t));
   I->rf2 = take(4 * (geo_ny + 1));
   I->dir = take(8 * (geo_nx + 1));
   I->inj_off = take(4 * (geo_nx + 2));
@@ -342,6 +343,7 @@ StepArgs args(const dig_ctx* c) {
   a.bsum = (int64_t*)(w + c->I.bsum);
   a.lastcnt = (int32_t*)(w + c->I.lastcnt);
   a.stats = (unsigned long long*)(w + c->I.stats);
+  a.done = (uint32_t*)(w + c->I.done);
   a.owner = (uint32_t*)(w + c->I.owner);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);
@@ -498,8 +500,7 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
   }
   if (mask & DIG_STAGE_COLLIDE) {
     if (c->phase != 2) return fail(DIG_ERR_STATE, "collide needs the sort stage first");
-    HIP_TRY(timed(c, DIG_K_COLLIDE, s, [&] { return launch_collide(a, true, true, s); }));
-    HIP_TRY(launch_step_end(a, true, s));
+    HIP_TRY(timed(c, DIG_K_COLLIDE, s, [&] { return launch_collide(a, true, true, true, s); }));
     c->cur ^= 1;
     c->phase = 0;
   }
@@ -591,6 +592,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
     e = hipMemcpyAsync((void*)a.dir, c->dir_host.data(), 4 * c->dir_host.size(),
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_i32(a.count, C, 0, s);
+  if (e == hipSuccess) e = launch_fill_i32((int32_t*)a.done, 1, 0, s);
   if (e == hipSuccess) e = launch_fill_f64(a.acc, 17 * C, 0.0, s);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i)
     e = launch_fill_f32(a.sgmax + c->params[i].cell0, c->params[i].ncell,

@@ -110,6 +110,7 @@ struct StepArgs {
   int32_t* inj_off;    // freestream: [nx + 2] inflow offsets per angular sector
   int64_t capacity;
   int32_t inj_sectors;  // angular sectors with inflow (0: closed domain)
+  uint32_t* done;       // ticket of the workgroups that finished the collide
 };
 enum { ST_REMOVED = 5, ST_INJECTED = 6 };
 
@@ -137,8 +138,8 @@ hipError_t launch_move(const StepArgs& a, hipStream_t s);
 hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s);
 hipError_t launch_place(const StepArgs& a, hipStream_t s);
 hipError_t launch_order(const StepArgs& a, hipStream_t s);
-hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStream_t s);
-hipError_t launch_step_end(const StepArgs& a, bool sample, hipStream_t s);
+hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
+                          hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

@@ -28,6 +28,17 @@ static __device__ __forceinline__ int find_inst(const int64_t* pstart, int n_ins
   return lo;
 }
 
+// Workgroups are dispatched to the eight XCDs round robin (block b to XCD
+// b mod 8), each XCD with its own L2.  Cell groups next to each other share
+// source particles (the gather of particles that changed cells), so give
+// every XCD one contiguous range of groups: a bijection of [0, n).
+constexpr int kXcds = 8;
+static __device__ __forceinline__ int xcd_group(int b, int n) {
+  const int x = b % kXcds, i = b / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Largest i in [0, n) with a[i] <= v (a non-decreasing, a[0] <= v).
 template <typename T>
 static __device__ __forceinline__ int floor_index(const T* a, int n, T v) {
@@ -498,7 +509,7 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a) {
   __shared__ uint32_t s_off[kRunMax];
   __shared__ int s_w[8];
   __shared__ int s_nr;
-  const int g = blockIdx.x;
+  const int g = xcd_group(blockIdx.x, gridDim.x);
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
   if (c_lo >= c_hi) return;
   const int nc = c_hi - c_lo;
@@ -713,6 +724,15 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   __syncthreads();
   int l_cand = 0, l_acc = 0, l_inel = 0, l_sat = 0;
   // ---- small cells: chunks of candidates in (cell, k) order ----------------
+  // In this phase a lane runs one cell's candidates in order; with at least
+  // as many threads as cells the cells are dealt round robin over the waves
+  // (cell l * waves + w to lane l of wave w) so that every SIMD has chains to
+  // run; otherwise each thread keeps its contiguous cells.
+  const int nw = (int)blockDim.x >> 6;
+  const bool spread = nc <= (int)blockDim.x;
+  const int my = lane_id() * nw + ((int)threadIdx.x >> 6);
+  const int sb = spread ? my : cb;
+  const int se = spread ? (my < nc ? my + 1 : my) : ce;
   float obs[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int kb = 0; kb < KS; kb += kCandChunk) {
     const int kc = min(kCandChunk, KS - kb);
@@ -734,7 +754,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       w[1] = r1;
     }
     __syncthreads();
-    for (int c = cb; c < ce; ++c) {
+    for (int c = sb; c < se; ++c) {
       const int k0 = max(S.soff[c], kb), k1 = min(S.soff[c + 1], kb + kc);
       if (k0 >= k1) continue;
       const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
@@ -747,7 +767,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         float4 va = P.ld(i), vb = P.ld(j);
         float sg, g2;
         const bool acc = vhs_accept(I, sgm, w0.y, va, vb, &sg, &g2);
-        obs[c - cb] = fmaxf(obs[c - cb], sg);
+        obs[c - sb] = fmaxf(obs[c - sb], sg);
         ++l_cand;
         l_sat += sg > sgm;
         if (acc) {
@@ -760,7 +780,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     }
     __syncthreads();
   }
-  for (int c = cb; c < ce; ++c) atomicMax(&S.obs[c], __float_as_uint(obs[c - cb]));
+  for (int c = sb; c < se; ++c) atomicMax(&S.obs[c], __float_as_uint(obs[c - sb]));
   // ---- large cells: candidates staged in chunks and executed in rounds; a
   // candidate runs once it is the earliest pending candidate of both its
   // particles -------------------------------------------------------------------
@@ -883,13 +903,12 @@ static __device__ __forceinline__ double select17(const double s[17], int f) {
 // from the previous buffer in sorted order (positions and ids straight to the
 // destination, velocities and rotational energies into LDS), collide, write
 // back, and add the cells' FP64 raw sums to the accumulator.
-constexpr int kCollideThreads = 64;
+constexpr int kCollideThreads = 256;
 constexpr int kGatherUnroll = 4;
 
-__global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_collide,
-                                                             int do_sample) {
+static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int do_collide,
+                                                     int do_sample) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int g = blockIdx.x;
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
   if (c_lo >= c_hi) return;
   const int nc = c_hi - c_lo;
@@ -1017,12 +1036,23 @@ __global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_
   }
 }
 
-// End of a step: the sorted count becomes the particle count (particles may
-// have left through an open boundary), the step counter advances.
-__global__ void k_step_end(dig_counters* c, const int32_t* total, int sample) {
-  c->n = *total;
-  c->step += 1;
-  if (sample) c->nsamp += 1;
+// Collide + sample of one cell group per workgroup.  With end_step, the last
+// workgroup to take a grid-wide ticket closes the step: the sorted count
+// becomes the particle count and the step counter advances.  A workgroup
+// takes its ticket after all its threads have read the step counter (at their
+// start), so no workgroup can read the advanced counter; nothing else the
+// closing workgroup writes is read within this kernel.
+__global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_collide,
+                                                             int do_sample, int end_step) {
+  collide_group(a, xcd_group(blockIdx.x, gridDim.x), do_collide, do_sample);
+  if (!end_step || threadIdx.x != 0) return;
+  const uint32_t prev = atomicAdd(a.done, 1u);
+  if (prev == gridDim.x - 1) {
+    a.ctr->n = a.start[a.ncell];
+    a.ctr->step += 1;
+    if (do_sample) a.ctr->nsamp += 1;
+    atomicExch(a.done, 0u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1679,16 +1709,11 @@ hipError_t launch_order(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, hipStream_t s) {
+hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
+                          hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
   hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(kCollideThreads), lds, s, a,
-                     collide ? 1 : 0, sample ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_step_end(const StepArgs& a, bool sample, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, a.ctr, a.start + a.ncell,
-                     sample ? 1 : 0);
+                     collide ? 1 : 0, sample ? 1 : 0, end_step ? 1 : 0);
   return hipGetLastError();
 }
 
