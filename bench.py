@@ -38,10 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle-step of the whole step: state (x[, y], v, er,
 # id) read once and written once
 STATE_BYTES = {1: 24, 2: 28}
-# collide kernel: v (3 x f32) and er read and written per particle; per cell
-# the start pair (4 B), majorant read + write (8 B), instance tag (4 B) and
-# the FP64 accumulator of 17 sums read + written
-COLLIDE_PARTICLE_BYTES = 32
+# collide kernel (stable order of each cell group, gather, collisions,
+# sampling): per particle its provisional source index (4 B) read, the state
+# read from the unsorted buffer and written to the sorted one; per cell the
+# start pair (4 B), majorant read + write (8 B), instance tag (4 B) and the
+# FP64 accumulator of 17 sums read + written
+def collide_particle_bytes(dim):
+    return 4 + 2 * STATE_BYTES[dim]
+
+
 PER_CELL_BYTES = 4 + 8 + 4 + 2 * 17 * 8
 KERNEL_SOURCES = ("paper_2501_10965_amd/csrc/dig_kernels.hip",
                   "paper_2501_10965_amd/csrc/dig_internal.h")
@@ -75,14 +80,14 @@ def pmc_traffic(kernel: str, workload: str):
     return float(f.group(1)) + float(w.group(1))
 
 
-def roofline(prof, n_avg, ncell, workload):
+def roofline(prof, n_avg, ncell, workload, dim):
     name, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_s = ms / max(launches, 1) / 1e3
     if name != "collide":
         return {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": None, "traffic": None,
                 "avg_launch_us": round(avg_s * 1e6, 2)}
-    alg = COLLIDE_PARTICLE_BYTES * n_avg + PER_CELL_BYTES * ncell
+    alg = collide_particle_bytes(dim) * n_avg + PER_CELL_BYTES * ncell
     ach = alg / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload),
@@ -95,7 +100,7 @@ def summarise(prof, psteps, sec, nsteps, n_avg, ncell, dim, workload):
     step_alg = step_bytes * psteps / sec / 1e9
     return dict(
         value=psteps / sec, ms_per_step=sec / nsteps * 1e3,
-        roofline=roofline(prof, n_avg, ncell, workload),
+        roofline=roofline(prof, n_avg, ncell, workload, dim),
         kernels_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in prof.items() if v[1]},
         kernel_launches={k: v[1] for k, v in prof.items() if v[1]},
         step_roofline={"achieved_algorithmic_GBs": round(step_alg, 1),

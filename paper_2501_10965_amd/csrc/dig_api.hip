@@ -449,7 +449,7 @@ dig_status check_ctx(dig_ctx* c) {
 // its last cell, within 48 KiB of LDS; larger groups collide in the
 // destination buffer instead.
 int32_t lds_particles_for(int32_t T, int32_t Gc) {
-  int32_t Lp = T + 512;
+  int32_t Lp = T + 256;
   while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
   return Lp;
 }
@@ -491,16 +491,21 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
     HIP_TRY(timed(c, DIG_K_MOVE, s, [&] { return launch_move(a, s); }));
     c->phase = 1;
   }
+  // When the sort and the collide run together, the collide puts each cell
+  // group in stable order itself (no separate ordering pass); the sort stage
+  // alone finishes the permutation so that it can be inspected.
+  const bool fused = (mask & DIG_STAGE_SORT) && (mask & DIG_STAGE_COLLIDE);
   if (mask & DIG_STAGE_SORT) {
     if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
     HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, false, s); }));
     HIP_TRY(timed(c, DIG_K_PLACE, s, [&] { return launch_place(a, s); }));
-    HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
+    if (!fused) HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
     c->phase = 2;
   }
   if (mask & DIG_STAGE_COLLIDE) {
     if (c->phase != 2) return fail(DIG_ERR_STATE, "collide needs the sort stage first");
-    HIP_TRY(timed(c, DIG_K_COLLIDE, s, [&] { return launch_collide(a, true, true, true, s); }));
+    HIP_TRY(timed(c, DIG_K_COLLIDE, s,
+                  [&] { return launch_collide(a, true, true, true, fused, s); }));
     c->cur ^= 1;
     c->phase = 0;
   }

@@ -16,7 +16,7 @@ enum : uint32_t {
 
 constexpr int kMaxHits = 8;      // wall events per particle and step
 constexpr int kRunMax = 4096;    // run table of the sort kernel
-constexpr int kCandChunk = 256;  // candidates staged per round set
+constexpr int kCandChunk = 128;  // candidates staged per round set
 constexpr int kSeqMaxDefault = 192;  // cells up to this size: one lane, candidates in order
 constexpr int kMinGroupParticles = 256;
 // Statistics counters are spread over kStatSlots cache lines (slot = block
@@ -139,7 +139,7 @@ hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream
 hipError_t launch_place(const StepArgs& a, hipStream_t s);
 hipError_t launch_order(const StepArgs& a, hipStream_t s);
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
-                          hipStream_t s);
+                          bool fuse_order, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

@@ -849,10 +849,19 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       if (!__syncthreads_or(more)) break;
     }
   }
-  atomicAdd(&S.stat[0], l_cand);
-  atomicAdd(&S.stat[1], l_acc);
-  atomicAdd(&S.stat[2], l_inel);
-  atomicAdd(&S.stat[3], l_sat);
+  // statistics: wave sums first, one shared-memory atomic per wave and value
+  for (int off = 32; off > 0; off >>= 1) {
+    l_cand += __shfl_xor(l_cand, off);
+    l_acc += __shfl_xor(l_acc, off);
+    l_inel += __shfl_xor(l_inel, off);
+    l_sat += __shfl_xor(l_sat, off);
+  }
+  if (lane_id() == 0) {
+    if (l_cand) atomicAdd(&S.stat[0], l_cand);
+    if (l_acc) atomicAdd(&S.stat[1], l_acc);
+    if (l_inel) atomicAdd(&S.stat[2], l_inel);
+    if (l_sat) atomicAdd(&S.stat[3], l_sat);
+  }
 }
 
 // FP64 raw sums of a cell by an 8-lane subgroup: lane j of the subgroup sums
@@ -906,8 +915,73 @@ static __device__ __forceinline__ double select17(const double s[17], int f) {
 constexpr int kCollideThreads = 256;
 constexpr int kGatherUnroll = 4;
 
+// Stable order of a group's particles from the provisional scatter (the
+// algorithm of k_order, for one cell group inside the collide): runs of the
+// provisional segment of a cell (one per reserving wave, increasing sources)
+// are ordered by their first source.  st: cell starts relative to the group
+// (LDS), raw/ord: provisional and ordered sources (LDS or global).  kRunSlots
+// runs per group; more fall back to counting ranks.
+constexpr int kRunSlots = 256;
+template <class Raw, class Ord>
+static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng, Raw raw, Ord ord,
+                                                  uint32_t* rkey, uint32_t* rre, uint32_t* roff,
+                                                  int* s_nr, int* s_w) {
+  if (threadIdx.x == 0) *s_nr = 0;
+  __syncthreads();
+  bool overflow = false;
+  for (int base = 0; base < ng; base += blockDim.x) {
+    const int e = base + threadIdx.x;
+    bool flag = false;
+    uint32_t s = 0;
+    if (e < ng) {
+      s = (uint32_t)raw[e];
+      const int c = floor_index(st, nc + 1, e);
+      flag = (e == st[c]) || ((s >> 6) != ((uint32_t)raw[e - 1] >> 6));
+    }
+    int total;
+    const int idx = block_flag_scan(flag, s_w, &total);
+    const int r = *s_nr + idx;
+    if (flag && r < kRunSlots) {
+      rkey[r] = s;
+      rre[r] = (uint32_t)e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *s_nr += total;
+    __syncthreads();
+    if (*s_nr > kRunSlots) { overflow = true; break; }
+  }
+  if (!overflow) {
+    const int nr = *s_nr;
+    if (threadIdx.x == 0) rre[nr] = (uint32_t)ng;
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+      const int c = floor_index(st, nc + 1, (int)rre[r]);
+      const int r0 = floor_index(rre, nr + 1, (uint32_t)st[c]);
+      const uint32_t key = rkey[r];
+      uint32_t off = (uint32_t)st[c];
+      for (int q = r0; q < nr && rre[q] < (uint32_t)st[c + 1]; ++q)
+        if (rkey[q] < key) off += rre[q + 1] - rre[q];
+      roff[r] = off;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+      const int r = floor_index(rre, nr + 1, (uint32_t)e);
+      ord[roff[r] + (uint32_t)e - rre[r]] = raw[e];
+    }
+  } else {
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+      const int c = floor_index(st, nc + 1, e);
+      const int32_t s = raw[e];
+      int rank = 0;
+      for (int q = st[c]; q < st[c + 1]; ++q) rank += (raw[q] < s);
+      ord[st[c] + rank] = s;
+    }
+  }
+  __syncthreads();
+}
+
 static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int do_collide,
-                                                     int do_sample) {
+                                                     int do_sample, int fuse_order) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
   if (c_lo >= c_hi) return;
@@ -918,6 +992,12 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   // shared layout
   unsigned char* p = smem;
   float4* sv = (float4*)p;              p += sizeof(float4) * L;
+  uint32_t* lown = (uint32_t*)p;        p += sizeof(uint32_t) * L;  // round owners
+  int32_t* sord = (int32_t*)p;          p += sizeof(int32_t) * L;   // ordered sources
+  uint32_t* rkey = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
+  uint32_t* rre = (uint32_t*)p;         p += sizeof(uint32_t) * (kRunSlots + 1);
+  uint32_t* roff = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
+  int* s_nr = (int*)p;                  p += sizeof(int) * 4;
   CollideShared S;
   S.words = (uint4*)p;                  p += sizeof(uint4) * 2 * kCandChunk;
   S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
@@ -947,6 +1027,20 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   }
   if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
   const bool fast = ng <= L;
+  if (fuse_order) {
+    // stable order of the group: the provisional segment staged in LDS (in
+    // the round-owner array, free until the collisions) when it fits
+    __syncthreads();
+    if (fast) {
+      int32_t* sraw = (int32_t*)lown;
+      for (int e = threadIdx.x; e < ng; e += blockDim.x) sraw[e] = a.perm_raw[e_lo + e];
+      order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, s_nr, S.wsum);
+    } else {
+      order_runs(S.start, nc, ng, (const int32_t*)(a.perm_raw + e_lo), a.perm + e_lo, rkey,
+                 rre, roff, s_nr, S.wsum);
+    }
+  }
+  const bool from_lds = fuse_order && fast;  // ordered sources in LDS, else in perm
   // gather, kGatherUnroll particles per lane in flight
   const bool two = a.dim == 2;
   for (int e0 = threadIdx.x; e0 < ng; e0 += kGatherUnroll * blockDim.x) {
@@ -954,7 +1048,7 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 #pragma unroll
     for (int u = 0; u < kGatherUnroll; ++u) {
       const int e = e0 + u * blockDim.x;
-      src[u] = e < ng ? a.perm[e_lo + e] : -1;
+      src[u] = e < ng ? (from_lds ? sord[e] : a.perm[e_lo + e]) : -1;
     }
     float x[kGatherUnroll], y[kGatherUnroll];
     float4 v[kGatherUnroll];
@@ -989,13 +1083,13 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   __syncthreads();
   LdsStore ls{sv};
   GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
-  uint32_t* owner = a.owner + e_lo;
+  uint32_t* owner = a.owner + e_lo;  // round owners of the global-memory path
   if (do_collide) {
     const bool uni = S.inst[0] == S.inst[nc - 1];  // instances are contiguous in c
     const int iu = __builtin_amdgcn_readfirstlane(S.inst[0]);
     if (fast) {
-      if (uni) collide_cells<LdsStore, true>(a, S, ls, owner, nc, c_lo, step, iu);
-      else collide_cells<LdsStore, false>(a, S, ls, owner, nc, c_lo, step, iu);
+      if (uni) collide_cells<LdsStore, true>(a, S, ls, lown, nc, c_lo, step, iu);
+      else collide_cells<LdsStore, false>(a, S, ls, lown, nc, c_lo, step, iu);
     } else {
       if (uni) collide_cells<GlobalStore, true>(a, S, gs, owner, nc, c_lo, step, iu);
       else collide_cells<GlobalStore, false>(a, S, gs, owner, nc, c_lo, step, iu);
@@ -1043,8 +1137,9 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 // start), so no workgroup can read the advanced counter; nothing else the
 // closing workgroup writes is read within this kernel.
 __global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_collide,
-                                                             int do_sample, int end_step) {
-  collide_group(a, xcd_group(blockIdx.x, gridDim.x), do_collide, do_sample);
+                                                             int do_sample, int end_step,
+                                                             int fuse_order) {
+  collide_group(a, xcd_group(blockIdx.x, gridDim.x), do_collide, do_sample, fuse_order);
   if (!end_step || threadIdx.x != 0) return;
   const uint32_t prev = atomicAdd(a.done, 1u);
   if (prev == gridDim.x - 1) {
@@ -1681,7 +1776,8 @@ size_t collide_lds_bytes(int lds_particles, int group_cells) {
   return sizeof(float4) * lds_particles + sizeof(uint4) * 2 * kCandChunk +
          sizeof(int) * 3 * (group_cells + 1) +
          (sizeof(float) + 2 * sizeof(int)) * group_cells + (5 * sizeof(int) + 1) * kCandChunk +
-         sizeof(int) * 12 + 16;
+         sizeof(int) * 12 + 16 + 2 * sizeof(uint32_t) * lds_particles +
+         3 * sizeof(uint32_t) * (kRunSlots + 1) + sizeof(int) * 4;
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
@@ -1710,10 +1806,10 @@ hipError_t launch_order(const StepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
-                          hipStream_t s) {
+                          bool fuse_order, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
   hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(kCollideThreads), lds, s, a,
-                     collide ? 1 : 0, sample ? 1 : 0, end_step ? 1 : 0);
+                     collide ? 1 : 0, sample ? 1 : 0, end_step ? 1 : 0, fuse_order ? 1 : 0);
   return hipGetLastError();
 }
 
