@@ -143,7 +143,8 @@ static __device__ __forceinline__ void circle_diffuse(const InstParam& P, int fa
 static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_t p,
                                    uint32_t step, int* hits) {
   float x = a.A.x[p], y = a.A.y[p];
-  float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
+  float vx = a.A.vx[p], vy = a.A.vy[p];
+  float vz = 0.0f;  // not needed: a diffuse wall redraws it, a specular wall keeps it
   float t = P.dtf;
   int hit = 0;
   bool vset = false, er_set = false;
@@ -201,8 +202,10 @@ static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_
   if (vset) {
     a.A.vx[p] = vx;
     a.A.vy[p] = vy;
-    a.A.vz[p] = vz;
-    if (er_set) a.A.er[p] = er;
+    if (er_set) {
+      a.A.vz[p] = vz;
+      a.A.er[p] = er;
+    }
   }
   *hits = hit;
   if (!outer_wall) {
@@ -221,7 +224,8 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
   const bool two = P.dim == 2;
   float x = a.A.x[p];
   float y = two ? a.A.y[p] : 0.0f;
-  float vx = a.A.vx[p], vy = a.A.vy[p], vz = a.A.vz[p];
+  float vx = a.A.vx[p], vy = a.A.vy[p];
+  float vz = 0.0f;  // not needed: a diffuse wall redraws it, a specular wall keeps it
   float t = P.dtf;
   int hit = 0;
   bool er_set = false;
@@ -303,8 +307,10 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
   if (hit) {
     a.A.vx[p] = vx;
     a.A.vy[p] = vy;
-    a.A.vz[p] = vz;
-    if (er_set) a.A.er[p] = er;  // diffuse re-emission draws er; specular keeps it
+    if (er_set) {  // diffuse re-emission draws vz and er; specular keeps them
+      a.A.vz[p] = vz;
+      a.A.er[p] = er;
+    }
   }
   *hits = hit;
   int ix = (int)floorf(x);
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
 // chunk sums, then per-chunk exclusive scans offset by the preceding chunks.
 // The second pass also zeroes the counts, writes the cell-group table (group
 // key = floor(start/T) + floor(c/Gc)), the instance particle ranges and n.
-constexpr int kScanPer = 8;
+constexpr int kScanPer = 2;
 constexpr int kScanChunk = 256 * kScanPer;
 
 __global__ __launch_bounds__(256) void k_scan_reduce(StepArgs a, const int32_t* counts) {
