@@ -492,14 +492,15 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
     c->phase = 1;
   }
   // When the sort and the collide run together, the collide puts each cell
-  // group in stable order itself (no separate ordering pass); the sort stage
-  // alone finishes the permutation so that it can be inspected.
+  // group that fits its shared-memory stage in stable order itself and the
+  // ordering pass only handles the larger groups; the sort stage alone orders
+  // the whole permutation so that it can be inspected.
   const bool fused = (mask & DIG_STAGE_SORT) && (mask & DIG_STAGE_COLLIDE);
   if (mask & DIG_STAGE_SORT) {
     if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
     HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, false, s); }));
     HIP_TRY(timed(c, DIG_K_PLACE, s, [&] { return launch_place(a, s); }));
-    if (!fused) HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
+    HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, fused, s); }));
     c->phase = 2;
   }
   if (mask & DIG_STAGE_COLLIDE) {

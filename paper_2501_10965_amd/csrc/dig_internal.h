@@ -137,7 +137,7 @@ size_t collide_lds_bytes(int lds_particles, int group_cells);
 hipError_t launch_move(const StepArgs& a, hipStream_t s);
 hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s);
 hipError_t launch_place(const StepArgs& a, hipStream_t s);
-hipError_t launch_order(const StepArgs& a, hipStream_t s);
+hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s);
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
                           bool fuse_order, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -508,7 +508,7 @@ static __device__ __forceinline__ int block_flag_scan(bool f, int* s_w, int* tot
 // cell is a concatenation of runs, one per reserving wave; a run is increasing
 // and the runs of different waves cover disjoint slot ranges, so ordering the
 // runs by their first slot yields the stable counting-sort order.
-__global__ __launch_bounds__(256) void k_order(StepArgs a) {
+__global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
   __shared__ int s_start[1025];
   __shared__ uint32_t s_key[kRunMax];
   __shared__ uint32_t s_re[kRunMax + 1];
@@ -521,6 +521,9 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a) {
   const int nc = c_hi - c_lo;
   const int e_lo = a.start[c_lo];
   const int ng = a.start[c_hi] - e_lo;
+  // in a full step the collide orders the groups that fit its shared-memory
+  // stage; only the larger ones are ordered here
+  if (big_only && ng <= a.lds_particles) return;
   for (int c = threadIdx.x; c <= nc; c += blockDim.x) s_start[c] = a.start[c_lo + c] - e_lo;
   if (threadIdx.x == 0) s_nr = 0;
   __syncthreads();
@@ -1033,18 +1036,14 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   }
   if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
   const bool fast = ng <= L;
-  if (fuse_order) {
+  if (fuse_order && fast) {
     // stable order of the group: the provisional segment staged in LDS (in
-    // the round-owner array, free until the collisions) when it fits
+    // the round-owner array, free until the collisions); groups that do not
+    // fit were ordered by k_order
     __syncthreads();
-    if (fast) {
-      int32_t* sraw = (int32_t*)lown;
-      for (int e = threadIdx.x; e < ng; e += blockDim.x) sraw[e] = a.perm_raw[e_lo + e];
-      order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, s_nr, S.wsum);
-    } else {
-      order_runs(S.start, nc, ng, (const int32_t*)(a.perm_raw + e_lo), a.perm + e_lo, rkey,
-                 rre, roff, s_nr, S.wsum);
-    }
+    int32_t* sraw = (int32_t*)lown;
+    for (int e = threadIdx.x; e < ng; e += blockDim.x) sraw[e] = a.perm_raw[e_lo + e];
+    order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, s_nr, S.wsum);
   }
   const bool from_lds = fuse_order && fast;  // ordered sources in LDS, else in perm
   // gather, kGatherUnroll particles per lane in flight
@@ -1806,8 +1805,11 @@ hipError_t launch_place(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(256), 0, s, a);
+hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s) {
+  // when only the oversize groups are ordered, most workgroups exit at once:
+  // one wave each keeps that cheap
+  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(big_only ? 64 : 256), 0, s, a,
+                     big_only ? 1 : 0);
   return hipGetLastError();
 }
 
