@@ -934,56 +934,67 @@ constexpr int kRunSlots = 256;
 template <class Raw, class Ord>
 static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng, Raw raw, Ord ord,
                                                   uint32_t* rkey, uint32_t* rre, uint32_t* roff,
-                                                  int* s_nr, int* s_w) {
-  if (threadIdx.x == 0) *s_nr = 0;
+                                                  int* s_w) {
+  // each thread walks a block of consecutive elements: runs are counted, the
+  // counts scanned, then written in element order.  The barrier publishes the
+  // caller's writes of st and raw.
   __syncthreads();
-  bool overflow = false;
-  for (int base = 0; base < ng; base += blockDim.x) {
-    const int e = base + threadIdx.x;
-    bool flag = false;
-    uint32_t s = 0;
-    if (e < ng) {
-      s = (uint32_t)raw[e];
-      const int c = floor_index(st, nc + 1, e);
-      flag = (e == st[c]) || ((s >> 6) != ((uint32_t)raw[e - 1] >> 6));
+  const int per = (ng + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int e0 = min(ng, (int)threadIdx.x * per), e1 = min(ng, e0 + per);
+  const int c0 = e0 < ng ? floor_index(st, nc + 1, e0) : nc;
+  const uint32_t p0 = (e0 > 0 && e0 < ng) ? (uint32_t)raw[e0 - 1] : 0u;
+  int cnt = 0;
+  {
+    int c = c0;
+    uint32_t pv = p0;
+    for (int e = e0; e < e1; ++e) {
+      while (st[c + 1] <= e) ++c;
+      const uint32_t sv = (uint32_t)raw[e];
+      cnt += (e == st[c]) || ((sv >> 6) != (pv >> 6));
+      pv = sv;
     }
-    int total;
-    const int idx = block_flag_scan(flag, s_w, &total);
-    const int r = *s_nr + idx;
-    if (flag && r < kRunSlots) {
-      rkey[r] = s;
-      rre[r] = (uint32_t)e;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *s_nr += total;
-    __syncthreads();
-    if (*s_nr > kRunSlots) { overflow = true; break; }
   }
-  if (!overflow) {
-    const int nr = *s_nr;
+  int nr;
+  int r = block_exscan(cnt, s_w, &nr);
+  if (nr <= kRunSlots) {
+    int c = c0;
+    uint32_t pv = p0;
+    for (int e = e0; e < e1; ++e) {
+      while (st[c + 1] <= e) ++c;
+      const uint32_t sv = (uint32_t)raw[e];
+      if ((e == st[c]) || ((sv >> 6) != (pv >> 6))) {
+        rkey[r] = sv;
+        rre[r] = (uint32_t)e;
+        ++r;
+      }
+      pv = sv;
+    }
     if (threadIdx.x == 0) rre[nr] = (uint32_t)ng;
     __syncthreads();
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-      const int c = floor_index(st, nc + 1, (int)rre[r]);
-      const int r0 = floor_index(rre, nr + 1, (uint32_t)st[c]);
-      const uint32_t key = rkey[r];
+    for (int q = threadIdx.x; q < nr; q += blockDim.x) {
+      const int c = floor_index(st, nc + 1, (int)rre[q]);
+      const int q0 = floor_index(rre, nr + 1, (uint32_t)st[c]);
+      const uint32_t key = rkey[q];
       uint32_t off = (uint32_t)st[c];
-      for (int q = r0; q < nr && rre[q] < (uint32_t)st[c + 1]; ++q)
-        if (rkey[q] < key) off += rre[q + 1] - rre[q];
-      roff[r] = off;
+      for (int t = q0; t < nr && rre[t] < (uint32_t)st[c + 1]; ++t)
+        if (rkey[t] < key) off += rre[t + 1] - rre[t];
+      roff[q] = off;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
-      const int r = floor_index(rre, nr + 1, (uint32_t)e);
-      ord[roff[r] + (uint32_t)e - rre[r]] = raw[e];
+    if (e0 < e1) {
+      int q = floor_index(rre, nr + 1, (uint32_t)e0);
+      for (int e = e0; e < e1; ++e) {
+        while (rre[q + 1] <= (uint32_t)e) ++q;
+        ord[roff[q] + (uint32_t)e - rre[q]] = raw[e];
+      }
     }
   } else {
     for (int e = threadIdx.x; e < ng; e += blockDim.x) {
       const int c = floor_index(st, nc + 1, e);
-      const int32_t s = raw[e];
+      const int32_t sv = raw[e];
       int rank = 0;
-      for (int q = st[c]; q < st[c + 1]; ++q) rank += (raw[q] < s);
-      ord[st[c] + rank] = s;
+      for (int q = st[c]; q < st[c + 1]; ++q) rank += (raw[q] < sv);
+      ord[st[c] + rank] = sv;
     }
   }
   __syncthreads();
@@ -1006,7 +1017,7 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   uint32_t* rkey = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
   uint32_t* rre = (uint32_t*)p;         p += sizeof(uint32_t) * (kRunSlots + 1);
   uint32_t* roff = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
-  int* s_nr = (int*)p;                  p += sizeof(int) * 4;
+  p += sizeof(int) * 4;
   CollideShared S;
   S.words = (uint4*)p;                  p += sizeof(uint4) * 2 * kCandChunk;
   S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
@@ -1043,7 +1054,7 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
     __syncthreads();
     int32_t* sraw = (int32_t*)lown;
     for (int e = threadIdx.x; e < ng; e += blockDim.x) sraw[e] = a.perm_raw[e_lo + e];
-    order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, s_nr, S.wsum);
+    order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum);
   }
   const bool from_lds = fuse_order && fast;  // ordered sources in LDS, else in perm
   // gather, kGatherUnroll particles per lane in flight
