@@ -6,9 +6,11 @@ particles per cell = 2,000,000 particles, Kn = 0.01, lid Ma = 0.3,
 omega = 0.74, Z = 5, N_s = 50).  A timed "step" is one DSMC step (move + walls,
 cell index + stable sort, NTC/VHS/BL collide, FP64 sampling); every N_s steps
 the DIG cycle runs (time-averaged fields, closure assembly, particle
-modification).  Inside the timed region the kernels are launched eagerly with
-HIP events around each one (the per-kernel durations of the roofline) and the
-modification target is the time-averaged DSMC field.  Two more regions follow
+modification).  Inside the timed region the kernels are launched eagerly,
+with HIP events around each collide launch (the dominant kernel, whose
+average duration gives the roofline), and the modification target is the
+time-averaged DSMC field.  The per-kernel breakdown comes from a shorter,
+untimed run of the same loop with events around every kernel.  Two more regions follow
 and are reported beside it: the same loop with the N_s steps as one captured
 HIP graph ("graph_replay"), and the full DIG loop with the synthetic-equation
 solve as the target ("dig_loop").
@@ -48,6 +50,8 @@ def collide_particle_bytes(dim):
 
 
 PER_CELL_BYTES = 4 + 8 + 4 + 2 * 17 * 8
+# DIG cycles of the untimed per-kernel breakdown run (cavity)
+BREAKDOWN_CYCLES = 4
 KERNEL_SOURCES = ("paper_2501_10965_amd/csrc/dig_kernels.hip",
                   "paper_2501_10965_amd/csrc/dig_internal.h")
 
@@ -80,8 +84,11 @@ def pmc_traffic(kernel: str, workload: str):
     return float(f.group(1)) + float(w.group(1))
 
 
-def roofline(prof, n_avg, ncell, workload, dim):
-    name, (ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+def roofline(prof, breakdown, n_avg, ncell, workload, dim):
+    """Roofline of the kernel that dominates the breakdown, from its events in
+    the timed region (prof)."""
+    name = max(breakdown.items(), key=lambda kv: kv[1][0])[0]
+    ms, launches = prof[name]
     avg_s = ms / max(launches, 1) / 1e3
     if name != "collide":
         return {"bound": "hbm", "kernel": name, "achieved": None, "peak": HBM_PEAK_GBS,
@@ -95,14 +102,17 @@ def roofline(prof, n_avg, ncell, workload, dim):
             "algorithmic_bytes_per_launch": int(alg)}
 
 
-def summarise(prof, psteps, sec, nsteps, n_avg, ncell, dim, workload):
+def summarise(prof, breakdown, psteps, sec, nsteps, n_avg, ncell, dim, workload):
+    """prof: events of the timed region (the collide only); breakdown: events
+    around every kernel of a separate, untimed run of the same loop."""
     step_bytes = STATE_BYTES[dim] * 2 + PER_CELL_BYTES * ncell / n_avg
     step_alg = step_bytes * psteps / sec / 1e9
     return dict(
         value=psteps / sec, ms_per_step=sec / nsteps * 1e3,
-        roofline=roofline(prof, n_avg, ncell, workload, dim),
-        kernels_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in prof.items() if v[1]},
-        kernel_launches={k: v[1] for k, v in prof.items() if v[1]},
+        roofline=roofline(prof, breakdown, n_avg, ncell, workload, dim),
+        kernels_us={k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in breakdown.items()
+                    if v[1]},
+        kernel_launches={k: v[1] for k, v in breakdown.items() if v[1]},
         step_roofline={"achieved_algorithmic_GBs": round(step_alg, 1),
                        "frac": round(step_alg / HBM_PEAK_GBS, 4),
                        "bytes_per_particle_step": round(step_bytes, 2)})
@@ -156,8 +166,13 @@ def run_cavity(args):
     # warm up to a cycle boundary at or after the requested warmup
     tgt = -(-max(args.warmup, state["step"]) // ns) * ns
     run(tgt - state["step"], [], graph=True)
-    torch.cuda.synchronize()
+    # per-kernel breakdown: events around every kernel, outside the timed region
     sim.profile("on")
+    run(BREAKDOWN_CYCLES * ns, [])
+    breakdown = sim.profile("read")
+    sim.profile("off")
+    torch.cuda.synchronize()
+    sim.profile("on", kinds=["collide"])
     counts = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -169,7 +184,8 @@ def run_cavity(args):
     ctr = sim.counters()
     psteps = sum(k * n for k, n in counts)
     n_avg = psteps / max(args.steps, 1)
-    out = summarise(prof, psteps, t1 - t0, args.steps, n_avg, w["nx"] * w["ny"], 2, "cavity")
+    out = summarise(prof, breakdown, psteps, t1 - t0, args.steps, n_avg, w["nx"] * w["ny"], 2,
+                    "cavity")
     # the same loop with graph-captured steps
     run((-state["step"]) % ns, [], graph=True)
     torch.cuda.synchronize()
@@ -219,8 +235,12 @@ def run_batch(args):
     graph = 50
     k0 = sim.counters()["step"]
     sim.step(max(args.warmup - k0, 0) // graph * graph + graph, graph=True)
-    torch.cuda.synchronize()
     sim.profile("on")
+    sim.step(2 * graph)
+    breakdown = sim.profile("read")
+    sim.profile("off")
+    torch.cuda.synchronize()
+    sim.profile("on", kinds=["collide"])
     steps = max(graph, args.steps // graph * graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -232,7 +252,7 @@ def run_batch(args):
     sim.profile("off")
     ctr = sim.counters()
     ncell = sim.ncell
-    out = summarise(prof, n * steps, t1 - t0, steps, n, ncell, 1, "batch")
+    out = summarise(prof, breakdown, n * steps, t1 - t0, steps, n, ncell, 1, "batch")
     torch.cuda.synchronize()
     tg0 = time.perf_counter()
     for _ in range(steps // graph):
@@ -323,10 +343,14 @@ def run_cylinder(args):
     tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
     k0 = sim.counters()["step"]
     sim.step(max(args.warmup - k0, 0), graph=True)
+    sim.profile("on")
+    sim.step(10)
+    breakdown = sim.profile("read")
+    sim.profile("off")
     torch.cuda.synchronize()
     steps = args.steps
     c0 = sim.counters()
-    sim.profile("on")
+    sim.profile("on", kinds=["collide"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
@@ -336,7 +360,8 @@ def run_cylinder(args):
     sim.profile("off")
     c1 = sim.counters()
     n_avg = 0.5 * (c0["n"] + c1["n"])
-    out = summarise(prof, n_avg * steps, t1 - t0, steps, n_avg, sim.ncell, 2, "cylinder")
+    out = summarise(prof, breakdown, n_avg * steps, t1 - t0, steps, n_avg, sim.ncell, 2,
+                    "cylinder")
     torch.cuda.synchronize()
     tg0 = time.perf_counter()
     sim.step(steps, graph=True)

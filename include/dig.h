@@ -244,6 +244,13 @@ enum { DIG_K_MOVE = 0, DIG_K_SCAN = 1, DIG_K_PLACE = 2, DIG_K_ORDER = 3, DIG_K_C
 dig_status dsmc_profile(dig_ctx* ctx, int32_t mode, double* ms_host, int64_t* launches_host,
                         dig_stream_t stream);
 
+/* Restricts dsmc_profile's events to the kernel kinds whose bit
+ * (1u << DIG_K_*) is set in mask; the other kinds launch without events, so
+ * timing one kernel perturbs the rest of the step as little as possible.
+ * The default (and after dsmc_create) is every kind.  Host only; takes effect
+ * at the next launch.  Errors: DIG_ERR_INVALID (bit beyond DIG_NKERNELS). */
+dig_status dsmc_profile_kinds(dig_ctx* ctx, uint32_t mask);
+
 /* Launch configuration of the step kernels.  group_particles / group_cells as
  * in dsmc_create; seq_max: cells with at most this many particles run their
  * collision candidates in order on one lane, larger cells in parallel rounds

@@ -92,8 +92,8 @@ class DigMlpScaling(C.Structure):
 # every exported entry point of include/dig.h
 EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "dsmc_stage",
            "dsmc_sample", "dig_adjust", "closure_assemble", "dig_synth_workspace_bytes",
-           "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_tuning",
-           "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
+           "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_profile_kinds",
+           "dsmc_tuning", "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
            "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "closure_features",
            "closure_blend", "dig_last_error",
            "dsmc_destroy"]
@@ -150,6 +150,7 @@ def load(path: str = LIB_PATH):
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
     L.dsmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
+    L.dsmc_profile_kinds.argtypes = [vp, C.c_uint32]
     L.dig_synth_workspace_bytes.argtypes = [cp]
     L.dig_synth_workspace_bytes.restype = C.c_size_t
     L.synth_solve.argtypes = [cp, C.POINTER(DigSynthOpts), vp, vp, vp, vp, vp, C.c_size_t,

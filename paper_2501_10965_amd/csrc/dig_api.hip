@@ -309,6 +309,7 @@ struct dig_ctx {
   hipStream_t cap = nullptr;  // capture stream, default priority
   // event profiling
   bool prof = false;
+  uint32_t prof_mask = ~0u;  // kernel kinds timed while profiling
   EvPool eager;
   double prof_ms[DIG_NKERNELS] = {0};
   int64_t prof_n[DIG_NKERNELS] = {0};
@@ -416,7 +417,7 @@ hipError_t prof_fold(dig_ctx* c, hipStream_t s) {
 // Runs one launch, bracketed by events when profiling is on.
 template <class F>
 hipError_t timed(dig_ctx* c, int kind, hipStream_t s, F&& launch) {
-  if (!c->prof) return launch();
+  if (!c->prof || !((c->prof_mask >> kind) & 1u)) return launch();
   dig_ctx::EvPool* p = &c->eager;
   if (p->used == p->kind.size()) {
     hipError_t e = prof_fold(c, s);
@@ -877,6 +878,13 @@ dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
     return DIG_OK;
   }
   return fail(DIG_ERR_INVALID, "bad profile mode");
+}
+
+dig_status dsmc_profile_kinds(dig_ctx* c, uint32_t mask) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (mask >> DIG_NKERNELS) return fail(DIG_ERR_INVALID, "unknown kernel kind in mask");
+  c->prof_mask = mask;
+  return DIG_OK;
 }
 
 dig_status dsmc_tuning(dig_ctx* c, const dig_tuning* in, dig_tuning* out) {

@@ -487,27 +487,30 @@ __global__ __launch_bounds__(256) void k_place(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of 0/1 flags (blockDim = 256).
-static __device__ __forceinline__ int block_flag_scan(bool f, int* s_w, int* total) {
-  const unsigned long long b = __ballot(f);
-  const int w = threadIdx.x >> 6;
-  const int pre = __popcll(b & __lanemask_lt());
-  if (lane_id() == 0) s_w[w] = __popcll(b);
+// Block-wide exclusive scan of one int per thread (blockDim a multiple of 64).
+static __device__ __forceinline__ int block_exscan(int v, int* s_w, int* total) {
+  int incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (lane_id() >= off) incl += t;
+  }
+  if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
   __syncthreads();
-  int off = 0, tot = 0;
+  int pre = 0, tot = 0;
   for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
-    if (k < w) off += s_w[k];
+    if (k < (int)(threadIdx.x >> 6)) pre += s_w[k];
     tot += s_w[k];
   }
   __syncthreads();
   *total = tot;
-  return off + pre;
+  return pre + incl - v;
 }
 
 // Restores (cell, slot) order inside each cell.  The provisional segment of a
 // cell is a concatenation of runs, one per reserving wave; a run is increasing
 // and the runs of different waves cover disjoint slot ranges, so ordering the
 // runs by their first slot yields the stable counting-sort order.
+constexpr int kOrderPer = 4;  // consecutive entries per thread, loaded together
 __global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
   __shared__ int s_start[1025];
   __shared__ uint32_t s_key[kRunMax];
@@ -530,23 +533,40 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
   if (ng == 0) return;
   const int32_t* src = a.perm_raw + e_lo;
   int32_t* dst = a.perm + e_lo;
+  const int chunk = kOrderPer * (int)blockDim.x;
+  // runs: each thread flags run heads among kOrderPer consecutive entries
   bool overflow = false;
-  for (int base = 0; base < ng; base += blockDim.x) {
-    const int e = base + threadIdx.x;
-    bool flag = false;
-    uint32_t s = 0;
-    if (e < ng) {
-      s = (uint32_t)src[e];
-      const int c = floor_index(s_start, nc + 1, e);
-      flag = (e == s_start[c]) || ((s >> 6) != ((uint32_t)src[e - 1] >> 6));
+  for (int base = 0; base < ng; base += chunk) {
+    const int e0 = base + kOrderPer * (int)threadIdx.x;
+    uint32_t v[kOrderPer];
+#pragma unroll
+    for (int u = 0; u < kOrderPer; ++u) v[u] = e0 + u < ng ? (uint32_t)src[e0 + u] : 0u;
+    uint32_t pv = (e0 > 0 && e0 < ng) ? (uint32_t)src[e0 - 1] : 0u;
+    int c = e0 < ng ? floor_index(s_start, nc + 1, e0) : nc;
+    bool head[kOrderPer];
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < kOrderPer; ++u) {
+      const int e = e0 + u;
+      head[u] = false;
+      if (e < ng) {
+        while (s_start[c + 1] <= e) ++c;
+        head[u] = (e == s_start[c]) || ((v[u] >> 6) != (pv >> 6));
+      }
+      pv = v[u];
+      cnt += head[u];
     }
     int total;
-    const int idx = block_flag_scan(flag, s_w, &total);
-    const int r = s_nr + idx;
-    if (flag && r < kRunMax) {
-      s_key[r] = s;
-      s_re[r] = (uint32_t)e;
-    }
+    int r = s_nr + block_exscan(cnt, s_w, &total);
+#pragma unroll
+    for (int u = 0; u < kOrderPer; ++u)
+      if (head[u]) {
+        if (r < kRunMax) {
+          s_key[r] = v[u];
+          s_re[r] = (uint32_t)(e0 + u);
+        }
+        ++r;
+      }
     __syncthreads();
     if (threadIdx.x == 0) s_nr += total;
     __syncthreads();
@@ -568,9 +588,21 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
       s_off[r] = off;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
-      const int r = floor_index(s_re, nr + 1, (uint32_t)e);
-      dst[s_off[r] + (uint32_t)e - s_re[r]] = src[e];
+    for (int base = 0; base < ng; base += chunk) {
+      const int e0 = base + kOrderPer * (int)threadIdx.x;
+      if (e0 >= ng) continue;
+      int32_t v[kOrderPer];
+#pragma unroll
+      for (int u = 0; u < kOrderPer; ++u) v[u] = e0 + u < ng ? src[e0 + u] : 0;
+      int r = floor_index(s_re, nr + 1, (uint32_t)e0);
+#pragma unroll
+      for (int u = 0; u < kOrderPer; ++u) {
+        const int e = e0 + u;
+        if (e < ng) {
+          while (s_re[r + 1] <= (uint32_t)e) ++r;
+          dst[s_off[r] + (uint32_t)e - s_re[r]] = v[u];
+        }
+      }
     }
   } else {
     // slow path: rank each entry against its cell by direct counting
@@ -668,25 +700,6 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
   vb.x = cx - hg * nx;
   vb.y = cy - hg * ny;
   vb.z = cz - hg * nz;
-}
-
-// Block-wide exclusive scan of one int per thread (blockDim a multiple of 64).
-static __device__ __forceinline__ int block_exscan(int v, int* s_w, int* total) {
-  int incl = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(incl, off);
-    if (lane_id() >= off) incl += t;
-  }
-  if (lane_id() == 63) s_w[threadIdx.x >> 6] = incl;
-  __syncthreads();
-  int pre = 0, tot = 0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
-    if (k < (int)(threadIdx.x >> 6)) pre += s_w[k];
-    tot += s_w[k];
-  }
-  __syncthreads();
-  *total = tot;
-  return pre + incl - v;
 }
 
 // UNI: every cell of the group belongs to instance `iu` (wave-uniform index,
@@ -1817,10 +1830,7 @@ hipError_t launch_place(const StepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s) {
-  // when only the oversize groups are ordered, most workgroups exit at once:
-  // one wave each keeps that cheap
-  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(big_only ? 64 : 256), 0, s, a,
-                     big_only ? 1 : 0);
+  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(256), 0, s, a, big_only ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -236,9 +236,14 @@ class DSMC:
             float(judge_rel), _ptr(hot), _ptr(src), _stream()))
         return src
 
-    def profile(self, mode: str):
-        """'on' (reset and enable), 'off', or 'read' -> {kernel: (ms_total, launches)}."""
+    def profile(self, mode: str, kinds=None):
+        """'on' (reset and enable), 'off', or 'read' -> {kernel: (ms_total, launches)}.
+        kinds (with 'on'): the kernel kinds to time, default all."""
         m = {"off": 0, "on": 1, "read": 2}[mode]
+        if m == 1:
+            mask = (1 << len(L.KERNELS)) - 1 if kinds is None else \
+                sum(1 << L.KERNELS.index(k) for k in kinds)
+            L.check(self.lib.dsmc_profile_kinds(self.ctx, mask))
         ms = (C.c_double * len(L.KERNELS))()
         nl = (C.c_int64 * len(L.KERNELS))()
         L.check(self.lib.dsmc_profile(self.ctx, m, ms, nl, _stream()))

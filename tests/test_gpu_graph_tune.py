@@ -201,3 +201,24 @@ def test_graph_steps_refused_while_profiling():
         assert prof[k][1] == 5 and prof[k][0] > 0, (k, prof[k])
     eager.step(5, graph=True)
     _assert_same(_full(eager), _full(graph))
+
+
+def test_profiling_a_subset_of_kernel_kinds():
+    """Events only around the chosen kinds; the others run untimed."""
+    from paper_2501_10965_amd import _lib as L
+    w = wl.cavity_2d(seed=305, n=20, ppc=20, kn=0.02)
+    s = DSMC(w)
+    s.init()
+    s.profile("on", kinds=["collide"])
+    s.step(4)
+    prof = s.profile("read")
+    s.profile("off")
+    assert prof["collide"][1] == 4 and prof["collide"][0] > 0
+    assert all(prof[k] == (0.0, 0) for k in prof if k != "collide")
+    s.profile("on")  # back to every kind
+    s.step(2)
+    prof = s.profile("read")
+    s.profile("off")
+    assert all(prof[k][1] == 2 for k in ("move", "scan", "place", "order", "collide"))
+    with pytest.raises(L.DigError):
+        L.check(s.lib.dsmc_profile_kinds(s.ctx, 1 << len(L.KERNELS)))
