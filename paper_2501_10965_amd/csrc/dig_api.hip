@@ -448,10 +448,11 @@ dig_status check_ctx(dig_ctx* c) {
 
 // Largest LDS particle stage for group size T: the group target plus room for
 // its last cell, within 48 KiB of LDS; larger groups collide in the
-// destination buffer instead.
+// destination buffer instead.  At least 512 (the collide keeps its candidate
+// words in the stage's source arrays).
 int32_t lds_particles_for(int32_t T, int32_t Gc) {
   int32_t Lp = T + 256;
-  while (Lp > 256 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
+  while (Lp > 512 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
   return Lp;
 }
 

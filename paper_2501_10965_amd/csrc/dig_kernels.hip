@@ -711,7 +711,8 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // order of the sequential algorithm exactly.
 template <class Store, bool UNI>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
-                                     uint32_t* owner, int nc, int c_lo, uint32_t step, int iu) {
+                                     uint32_t* owner, int nc, int c_lo, uint32_t step, int iu,
+                                     double my_vol) {
   // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
   // (nc <= group_cells <= 4 * blockDim)
   const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
@@ -724,7 +725,8 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     if (N >= 2) {
       const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_NCAND, 0);
-      k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, a.cvol[c_lo + c]), r.x);
+      const double vol = c == (int)threadIdx.x ? my_vol : a.cvol[c_lo + c];
+      k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, vol), r.x);
     }
     if (N <= a.seq_max) ks[c - cb] = k; else kg[c - cb] = k;
     tsum_s += ks[c - cb];
@@ -936,6 +938,11 @@ static __device__ __forceinline__ double select17(const double s[17], int f) {
 // back, and add the cells' FP64 raw sums to the accumulator.
 constexpr int kCollideThreads = 256;
 constexpr int kGatherUnroll = 4;
+constexpr int kStagePer = 3;   // provisional entries per thread loaded with the cell data
+constexpr int kRankMax = 128;  // cells up to this size are ordered by counting ranks
+// lown and sord hold 2 * 4 * L bytes, L >= 512
+static_assert(2 * sizeof(uint32_t) * 512 >= 2 * sizeof(uint4) * kCandChunk,
+              "candidate words must fit the free source arrays");
 
 // Stable order of a group's particles from the provisional scatter (the
 // algorithm of k_order, for one cell group inside the collide): runs of the
@@ -1022,17 +1029,22 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   const int Gc = a.group_cells;
   const int L = a.lds_particles;
   const uint32_t step = (uint32_t)a.ctr->step;
-  // shared layout
+  // shared layout.  Until the gather fills it, the velocity stage sv holds
+  // the ordering's run tables and entry -> cell map (16 L bytes >= their
+  // 3 (kRunSlots + 1) words + L bytes for every L >= 256).  After the gather
+  // the source arrays lown and sord are free: the one-lane cells' pre-drawn
+  // words use both (8 L >= 32 kCandChunk bytes for L >= 512) before the
+  // round owners of the large cells use lown.
   unsigned char* p = smem;
   float4* sv = (float4*)p;              p += sizeof(float4) * L;
   uint32_t* lown = (uint32_t*)p;        p += sizeof(uint32_t) * L;  // round owners
   int32_t* sord = (int32_t*)p;          p += sizeof(int32_t) * L;   // ordered sources
-  uint32_t* rkey = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
-  uint32_t* rre = (uint32_t*)p;         p += sizeof(uint32_t) * (kRunSlots + 1);
-  uint32_t* roff = (uint32_t*)p;        p += sizeof(uint32_t) * (kRunSlots + 1);
-  p += sizeof(int) * 4;
+  uint32_t* rkey = (uint32_t*)sv;
+  uint32_t* rre = rkey + (kRunSlots + 1);
+  uint32_t* roff = rre + (kRunSlots + 1);
+  uint8_t* ecell = (uint8_t*)(roff + (kRunSlots + 1));  // cell of each staged entry
   CollideShared S;
-  S.words = (uint4*)p;                  p += sizeof(uint4) * 2 * kCandChunk;
+  S.words = (uint4*)lown;
   S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
   S.coff = (int*)p;                     p += sizeof(int) * (Gc + 1);
   S.soff = (int*)p;                     p += sizeof(int) * (Gc + 1);
@@ -1050,6 +1062,19 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 
   const int e_lo = a.start[c_lo];
   const int ng = a.start[c_hi] - e_lo;
+  const bool fast = ng <= L;
+  const bool stage = fuse_order && fast;
+  // the provisional segment is loaded together with the cell data: the first
+  // kStagePer entries of each thread into registers
+  int32_t pre[kStagePer];
+  if (stage) {
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int e = (int)threadIdx.x + u * (int)blockDim.x;
+      pre[u] = e < ng ? a.perm_raw[e_lo + e] : 0;
+    }
+  }
+  const double my_vol = (int)threadIdx.x < nc ? a.cvol[c_lo + threadIdx.x] : 0.0;
   for (int c = threadIdx.x; c <= nc; c += blockDim.x) {
     S.start[c] = a.start[c_lo + c] - e_lo;
     if (c < nc) {
@@ -1059,17 +1084,44 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
     }
   }
   if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
-  const bool fast = ng <= L;
-  if (fuse_order && fast) {
+  if (stage) {
     // stable order of the group: the provisional segment staged in LDS (in
     // the round-owner array, free until the collisions); groups that do not
     // fit were ordered by k_order
-    __syncthreads();
     int32_t* sraw = (int32_t*)lown;
-    for (int e = threadIdx.x; e < ng; e += blockDim.x) sraw[e] = a.perm_raw[e_lo + e];
-    order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum);
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+      const int e = (int)threadIdx.x + u * (int)blockDim.x;
+      if (e < ng) sraw[e] = pre[u];
+    }
+    for (int e = threadIdx.x + kStagePer * blockDim.x; e < ng; e += blockDim.x)
+      sraw[e] = a.perm_raw[e_lo + e];
+    __syncthreads();
+    bool big = false;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      const int b = S.start[c], n = S.start[c + 1] - b;
+      big |= n > kRankMax;
+      if (n <= kRankMax)
+        for (int e = b; e < b + n; ++e) ecell[e] = (uint8_t)c;
+    }
+    if (__syncthreads_or(big)) {
+      order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum);
+    } else {
+      // every cell small: an entry's place in its cell is the number of the
+      // cell's entries with a smaller source (sources are distinct)
+      for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+        const int c = ecell[e];
+        const int b = S.start[c], n = S.start[c + 1] - b;
+        const int32_t key = sraw[e];
+        int rank = 0;
+#pragma unroll 4
+        for (int q = 0; q < n; ++q) rank += sraw[b + q] < key;
+        sord[b + rank] = key;
+      }
+      __syncthreads();
+    }
   }
-  const bool from_lds = fuse_order && fast;  // ordered sources in LDS, else in perm
+  const bool from_lds = stage;  // ordered sources in LDS, else in perm
   // gather, kGatherUnroll particles per lane in flight
   const bool two = a.dim == 2;
   for (int e0 = threadIdx.x; e0 < ng; e0 += kGatherUnroll * blockDim.x) {
@@ -1117,11 +1169,15 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
     const bool uni = S.inst[0] == S.inst[nc - 1];  // instances are contiguous in c
     const int iu = __builtin_amdgcn_readfirstlane(S.inst[0]);
     if (fast) {
-      if (uni) collide_cells<LdsStore, true>(a, S, ls, lown, nc, c_lo, step, iu);
-      else collide_cells<LdsStore, false>(a, S, ls, lown, nc, c_lo, step, iu);
+      if (uni) collide_cells<LdsStore, true>(a, S, ls, lown, nc, c_lo, step, iu,
+                                                        my_vol);
+      else collide_cells<LdsStore, false>(a, S, ls, lown, nc, c_lo, step, iu,
+                                                        my_vol);
     } else {
-      if (uni) collide_cells<GlobalStore, true>(a, S, gs, owner, nc, c_lo, step, iu);
-      else collide_cells<GlobalStore, false>(a, S, gs, owner, nc, c_lo, step, iu);
+      if (uni) collide_cells<GlobalStore, true>(a, S, gs, owner, nc, c_lo, step, iu,
+                                                        my_vol);
+      else collide_cells<GlobalStore, false>(a, S, gs, owner, nc, c_lo, step, iu,
+                                                        my_vol);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -1150,11 +1206,24 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       const int c = cb + sub;
       const bool ok = c < nc;
       const int b = ok ? S.start[c] : 0, N = ok ? S.start[c + 1] - b : 0;
+      // the accumulator is read before the sums, so its latency overlaps them
+      double* acc = a.acc + (int64_t)(c_lo + (ok ? c : 0)) * 17;
+      double prev[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int f = sl + k * kSub;
+        prev[k] = ok && f < 17 ? acc[f] : 0.0;
+      }
       double s[17];
       if (fast) sub_cell_sums(ls, b, N, s);
       else sub_cell_sums(gs, b, N, s);
-      if (ok)
-        for (int f = sl; f < 17; f += kSub) a.acc[(int64_t)(c_lo + c) * 17 + f] += select17(s, f);
+      if (ok) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int f = sl + k * kSub;
+          if (f < 17) acc[f] = prev[k] + select17(s, f);
+        }
+      }
     }
   }
 }
@@ -1802,11 +1871,14 @@ int64_t group_launch(const StepArgs& a) {
 }
 
 size_t collide_lds_bytes(int lds_particles, int group_cells) {
-  return sizeof(float4) * lds_particles + sizeof(uint4) * 2 * kCandChunk +
+  // velocity stage (holding the ordering tables before the gather), round
+  // owners and ordered sources per particle (holding the candidate words
+  // after it); per-cell offsets and data; candidate staging; statistics and
+  // scan slots
+  return sizeof(float4) * lds_particles + 2 * sizeof(uint32_t) * lds_particles +
          sizeof(int) * 3 * (group_cells + 1) +
          (sizeof(float) + 2 * sizeof(int)) * group_cells + (5 * sizeof(int) + 1) * kCandChunk +
-         sizeof(int) * 12 + 16 + 2 * sizeof(uint32_t) * lds_particles +
-         3 * sizeof(uint32_t) * (kRunSlots + 1) + sizeof(int) * 4;
+         sizeof(int) * 12 + 16;
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
