@@ -702,17 +702,19 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
   vb.z = cz - hg * nz;
 }
 
-// UNI: every cell of the group belongs to instance `iu` (wave-uniform index,
-// so the parameters come through the scalar cache).
+// Every cell passed belongs to instance `iu` (wave-uniform index, so the
+// parameters come through the scalar cache); a group spanning instances runs
+// one call per instance segment.  my_vol: the volume of cell threadIdx.x
+// when vol_mine.
 //
 // Cells with at most seq_max particles run their candidates in order on one
 // lane; the Philox words of a chunk of their candidates are drawn beforehand
 // by all lanes together.  Larger cells run in parallel rounds.  Both give the
 // order of the sequential algorithm exactly.
-template <class Store, bool UNI>
+template <class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, int nc, int c_lo, uint32_t step, int iu,
-                                     double my_vol) {
+                                     double my_vol, bool vol_mine) {
   // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
   // (nc <= group_cells <= 4 * blockDim)
   const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
@@ -723,9 +725,9 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     const int N = S.start[c + 1] - S.start[c];
     int k = 0;
     if (N >= 2) {
-      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const InstParam& I = a.params[iu];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_NCAND, 0);
-      const double vol = c == (int)threadIdx.x ? my_vol : a.cvol[c_lo + c];
+      const double vol = vol_mine && c == (int)threadIdx.x ? my_vol : a.cvol[c_lo + c];
       k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, vol), r.x);
     }
     if (N <= a.seq_max) ks[c - cb] = k; else kg[c - cb] = k;
@@ -765,7 +767,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       const int c = floor_index(S.soff, nc + 1, k);
       const int kk = k - S.soff[c];
       const int N = S.start[c + 1] - S.start[c];
-      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const InstParam& I = a.params[iu];
       const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
       const uint4 r0 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk);
       const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
@@ -781,7 +783,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     for (int c = sb; c < se; ++c) {
       const int k0 = max(S.soff[c], kb), k1 = min(S.soff[c + 1], kb + kc);
       if (k0 >= k1) continue;
-      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const InstParam& I = a.params[iu];
       const int b = S.start[c];
       const float sgm = S.sgm[c];
       for (int k = k0; k < k1; ++k) {
@@ -816,7 +818,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       const int c = floor_index(S.coff, nc + 1, k);
       const int kk = k - S.coff[c];
       const int N = S.start[c + 1] - S.start[c];
-      const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+      const InstParam& I = a.params[iu];
       const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_COLL, 3u * (uint32_t)kk);
       int i = (int)pick(r.x, (uint32_t)N);
       int j = (int)pick(r.y, (uint32_t)(N - 1));
@@ -852,7 +854,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         }
         S.pend[q] = 0;
         const int c = S.cc[q];
-        const InstParam& I = UNI ? a.params[iu] : a.params[S.inst[c]];
+        const InstParam& I = a.params[iu];
         float4 va = P.ld(i), vb = P.ld(j);
         float sg, g2;
         const bool acc = vhs_accept(I, S.sgm[c], S.w2[q], va, vb, &sg, &g2);
@@ -1166,18 +1168,24 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
   uint32_t* owner = a.owner + e_lo;  // round owners of the global-memory path
   if (do_collide) {
-    const bool uni = S.inst[0] == S.inst[nc - 1];  // instances are contiguous in c
-    const int iu = __builtin_amdgcn_readfirstlane(S.inst[0]);
-    if (fast) {
-      if (uni) collide_cells<LdsStore, true>(a, S, ls, lown, nc, c_lo, step, iu,
-                                                        my_vol);
-      else collide_cells<LdsStore, false>(a, S, ls, lown, nc, c_lo, step, iu,
-                                                        my_vol);
-    } else {
-      if (uni) collide_cells<GlobalStore, true>(a, S, gs, owner, nc, c_lo, step, iu,
-                                                        my_vol);
-      else collide_cells<GlobalStore, false>(a, S, gs, owner, nc, c_lo, step, iu,
-                                                        my_vol);
+    // instances are contiguous and increasing in c: one call per instance
+    // segment, almost always the whole group
+    for (int c0 = 0; c0 < nc;) {
+      const int iu = __builtin_amdgcn_readfirstlane(S.inst[c0]);
+      const int c1 = __builtin_amdgcn_readfirstlane(floor_index(S.inst, nc, iu) + 1);
+      CollideShared Sg = S;
+      Sg.start += c0;
+      Sg.coff += c0;
+      Sg.soff += c0;
+      Sg.sgm += c0;
+      Sg.obs += c0;
+      Sg.inst += c0;
+      if (fast)
+        collide_cells(a, Sg, ls, lown, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0);
+      else
+        collide_cells(a, Sg, gs, owner, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0);
+      c0 = c1;
+      if (c0 < nc) __syncthreads();  // the next segment reuses the staging arrays
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
@@ -1234,7 +1242,12 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 // takes its ticket after all its threads have read the step counter (at their
 // start), so no workgroup can read the advanced counter; nothing else the
 // closing workgroup writes is read within this kernel.
-__global__ __launch_bounds__(kCollideThreads) void k_collide(StepArgs a, int do_collide,
+// MINW: waves per SIMD the register budget must allow.  6 (80 VGPRs) is
+// launched where the LDS stage leaves room for 6 workgroups per CU, 1 (no
+// constraint) otherwise.
+template <int MINW>
+__global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(MINW)))
+void k_collide(StepArgs a, int do_collide,
                                                              int do_sample, int end_step,
                                                              int fuse_order) {
   collide_group(a, xcd_group(blockIdx.x, gridDim.x), do_collide, do_sample, fuse_order);
@@ -1909,8 +1922,15 @@ hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s) {
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
                           bool fuse_order, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
-  hipLaunchKernelGGL(k_collide, dim3((int)group_launch(a)), dim3(kCollideThreads), lds, s, a,
-                     collide ? 1 : 0, sample ? 1 : 0, end_step ? 1 : 0, fuse_order ? 1 : 0);
+  const dim3 grid((int)group_launch(a)), block(kCollideThreads);
+  const int f0 = collide ? 1 : 0, f1 = sample ? 1 : 0, f2 = end_step ? 1 : 0,
+            f3 = fuse_order ? 1 : 0;
+  // 160 KiB of LDS per CU; 1 KiB per workgroup kept for static LDS and
+  // allocation granularity
+  if (6 * (lds + 1024) <= 160 * 1024)
+    hipLaunchKernelGGL(k_collide<6>, grid, block, lds, s, a, f0, f1, f2, f3);
+  else
+    hipLaunchKernelGGL(k_collide<1>, grid, block, lds, s, a, f0, f1, f2, f3);
   return hipGetLastError();
 }
 
