@@ -1524,27 +1524,31 @@ __global__ void k_adjust_count(StepArgs a, const double* target, uint32_t iter,
   ccount[c] = (N == 0) ? nt : (nt > N ? nt - N : 0);
 }
 
+constexpr int kExPer = 8;
 __global__ __launch_bounds__(1024) void k_exscan(const int32_t* in, int32_t* out, int32_t n) {
-  __shared__ int64_t s_tot[1024];
-  const int tid = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int c0 = min(n, tid * per), c1 = min(n, c0 + per);
-  int64_t sum = 0;
-  for (int c = c0; c < c1; ++c) sum += in[c];
-  s_tot[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int64_t v = (tid >= off) ? s_tot[tid - off] : 0;
-    __syncthreads();
-    s_tot[tid] += v;
-    __syncthreads();
+  // one workgroup, tiles of 1024 x kExPer consecutive counts: each thread
+  // sums its kExPer, a block scan of the thread sums, a carry between tiles
+  __shared__ int s_w[16];
+  int64_t carry = 0;
+  for (int base = 0; base < n; base += 1024 * kExPer) {
+    const int c0 = base + (int)threadIdx.x * kExPer;
+    int v[kExPer];
+    int sum = 0;
+#pragma unroll
+    for (int u = 0; u < kExPer; ++u) {
+      v[u] = c0 + u < n ? in[c0 + u] : 0;
+      sum += v[u];
+    }
+    int tot;
+    int64_t run = carry + block_exscan(sum, s_w, &tot);
+#pragma unroll
+    for (int u = 0; u < kExPer; ++u) {
+      if (c0 + u < n) out[c0 + u] = (int32_t)run;
+      run += v[u];
+    }
+    carry += tot;
   }
-  int64_t run = s_tot[tid] - sum;
-  for (int c = c0; c < c1; ++c) {
-    out[c] = (int32_t)run;
-    run += in[c];
-  }
-  if (tid == 0) out[n] = (int32_t)s_tot[1023];
+  if (threadIdx.x == 0) out[n] = (int32_t)carry;
 }
 
 struct Slot {

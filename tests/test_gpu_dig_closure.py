@@ -34,11 +34,19 @@ def random_target(w, rng, rho_scale=1.0):
     return t
 
 
-@pytest.mark.parametrize("dim", [1, 2])
-def test_dig_adjust_matches_oracle(dim):
-    w = wl.cavity_2d(seed=61, n=20, ppc=40, kn=0.05) if dim == 2 else \
-        wl.fourier_1d(seed=62, nx=50, ppc=40)
-    say(f"case adjust dim={dim}")
+ADJUST_CASES = {
+    1: lambda: wl.fourier_1d(seed=62, nx=50, ppc=40),
+    2: lambda: wl.cavity_2d(seed=61, n=20, ppc=40, kn=0.05),
+    # 9216 cells: the per-cell count scans run over more than one tile
+    "2big": lambda: wl.cavity_2d(seed=63, n=96, ppc=40, kn=0.05),
+}
+
+
+@pytest.mark.parametrize("case", list(ADJUST_CASES))
+def test_dig_adjust_matches_oracle(case):
+    w = ADJUST_CASES[case]()
+    dim = w["dim"]
+    say(f"case adjust {case}")
     sim, arrays, start, sg, n = injected(w, seed=5 + dim)
     rng = np.random.default_rng(dim)
     t = random_target(w, rng)
