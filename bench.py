@@ -337,7 +337,9 @@ def run_cylinder(args):
     from paper_2501_10965_amd.dsmc import DSMC
 
     w = wl.cylinder()
-    sim = DSMC(w, cap_factor=1.3, group_particles=args.group_particles,
+    # the bow shock and the inflow reservoir raise the count well above the
+    # initial 50M over the timed steps
+    sim = DSMC(w, cap_factor=1.7, group_particles=args.group_particles,
                group_cells=args.group_cells)
     sim.init()
     tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
