@@ -241,12 +241,19 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(MlpDev d) {
   back_layer<kH>(d.wbt + qw(1), gA, gB, d.a1 + s0 * kH, d.g0 + s0 * kH, wave, lane);
 }
 
-// Weight and bias gradients: dW_l = sum over samples of g_l (x) a_l, one wave
-// per 16x16 block of a weight matrix, the samples as the MFMA reduction axis.
+// Weight and bias gradients: dW_l = sum over samples of g_l (x) a_l, one
+// workgroup per 16x16 block of a weight matrix, the samples as the MFMA
+// reduction axis.  The kGradWaves waves of a workgroup each reduce a
+// contiguous share of the samples (loads issued kGradAhead MFMA steps ahead),
+// then wave 0 adds the shares in wave order: deterministic, no atomics.
 // Tiles: layer 3 (8), layer 2 (64), layer 1 (64), layer 0 (16).
 constexpr int kGradTiles = 8 + 64 + 64 + 16;
+constexpr int kGradWaves = 8;
+constexpr int kGradAhead = 4;
 
-__global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev d, int64_t rows) {
+__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_wgrad(MlpDev d, int64_t rows) {
+  __shared__ f32x4 s_acc[kGradWaves][64];
+  __shared__ float s_b[kGradWaves][64];
   int tile = blockIdx.x, l;
   if (tile < 8) {
     l = 3;
@@ -265,20 +272,41 @@ __global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDev d, int64_t rows) {
   const uint16_t* g = l == 3 ? d.g3 : l == 2 ? d.g2 : l == 1 ? d.g1 : d.g0;
   const uint16_t* a = l == 3 ? d.a3 : l == 2 ? d.a2 : l == 1 ? d.a1 : d.a0;
   const int ldo = dout(l), ldi = din(l);
-  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  // this wave's steps of 16 samples: [k0, k1)
+  const int64_t steps = rows / 16;
+  const int64_t share = (steps + kGradWaves - 1) / kGradWaves;
+  const int64_t k0 = min(steps, wave * share), k1 = min(steps, k0 + share);
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   float bsum = 0.0f;
-  for (int64_t s0 = 0; s0 < rows; s0 += 16) {
-    bf16x4 A, B;
+  for (int64_t kb = k0; kb < k1; kb += kGradAhead) {
+    bf16x4 A[kGradAhead], B[kGradAhead];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t s = s0 + 4 * lg + j;
-      const uint16_t gv = g[s * ldo + ot * 16 + li];
-      A[j] = (short)gv;
-      B[j] = (short)a[s * ldi + it * 16 + li];
-      bsum += from_bf16(gv);
+    for (int u = 0; u < kGradAhead; ++u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t s = (kb + u) * 16 + 4 * lg + j;
+        const bool ok = kb + u < k1;
+        A[u][j] = ok ? (short)g[s * ldo + ot * 16 + li] : (short)0;
+        B[u][j] = ok ? (short)a[s * ldi + it * 16 + li] : (short)0;
+      }
     }
-    acc = mfma(A, B, acc);
+#pragma unroll
+    for (int u = 0; u < kGradAhead; ++u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bsum += from_bf16((uint16_t)A[u][j]);
+      acc = mfma(A[u], B[u], acc);
+    }
+  }
+  s_acc[wave][lane] = acc;
+  s_b[wave][lane] = bsum;
+  __syncthreads();
+  if (wave != 0) return;
+  for (int w = 1; w < kGradWaves; ++w) {
+    const f32x4 o = s_acc[w][lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += o[r];
+    bsum += s_b[w][lane];
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r)
@@ -467,7 +495,7 @@ dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_s
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(tiles), dim3(kThreads), 0, s, d, x, t, (float*)nullptr,
                      n);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(tiles), dim3(kThreads), 0, s, d);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64), 0, s, d,
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64 * kGradWaves), 0, s, d,
                      (int64_t)tiles * kTile);
   return hip_check("mlp_grad");
 }
