@@ -1,7 +1,9 @@
 """A full step orders each cell group inside the collide kernel; the staged
 path orders the whole permutation in a pass of its own.  Both must give
-bit-identical states, including groups too large for the shared-memory stage
-and steps where particles leave through an open boundary."""
+bit-identical states: small cells (ordered by counting ranks), cells above
+that size in groups that fit the shared-memory stage (ordered from the move's
+runs), groups too large for the stage, and steps where particles leave
+through an open boundary."""
 import numpy as np
 import pytest
 
@@ -25,6 +27,11 @@ def _snap(sim):
 
 CASES = {
     "cavity": lambda: wl.cavity_2d(seed=401, n=32, ppc=40, kn=0.02),
+    # cells of ~200 particles in groups that fit the LDS stage: ordered from
+    # the move's runs (cells above the rank-counting size)
+    "midcells": lambda: wl.box(1, 40, kn=0.05, ppc=200, seed=404,
+                               bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.3, (0, 0, 0)),
+                                   ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))]),
     "bigcells": lambda: wl.box(1, 6, kn=0.2, ppc=3000, seed=402,
                                bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.5, (0, 0, 0)),
                                    ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))]),
