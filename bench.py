@@ -500,7 +500,7 @@ def main():
                     default="cavity")
     ap.add_argument("--steady-threshold", type=float, default=0.02)
     ap.add_argument("--dig-max-cycles", type=int, default=160)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--dig-cycles", type=int, default=2)
