@@ -33,11 +33,10 @@ __host__ __device__ constexpr int dout(int l) { return l == 3 ? kOutP : kH; }
 static_assert(pb(3) + kOutP == DIG_MLP_NPARAM, "parameter layout");
 static_assert(qw(3) + kOutP * kH == kNW, "weight layout");
 
-// bfloat16 from float, round to nearest even (finite inputs)
+// bfloat16 from float, round to nearest even (the gfx950 conversion
+// instruction, two values per instruction where the compiler pairs them)
 __device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
