@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      stats, rf2, dir, inj_off, done;
+      stats, rf2, dir, inj_off, done, big_list, big_count;
   int64_t gfirst_len;
 };
 
@@ -207,6 +207,8 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->lastcnt = take(4 * (scan_blocks((int)C) + 1));
   I->stats = take(sizeof(unsigned long long) * kStatSlots * ST_N);
   I->done = take(sizeof(uint32_t));
+  I->big_list = take(4 * I->gfirst_len);
+  I->big_count = take(sizeof(uint32_t));
   I->rf2 = take(4 * (geo_ny + 1));
   I->dir = take(8 * (geo_nx + 1));
   I->inj_off = take(4 * (geo_nx + 2));
@@ -288,6 +290,7 @@ struct dig_ctx {
   int64_t capacity = 0, n_host = 0;
   int cur = 0;
   int32_t T = 1024, Gc = 64, Lp = 1536;
+  int32_t Lbig = 0;  // particle stage of the oversize-group collide
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
   int32_t seq_max = kSeqMaxDefault;
@@ -345,6 +348,10 @@ StepArgs args(const dig_ctx* c) {
   a.lastcnt = (int32_t*)(w + c->I.lastcnt);
   a.stats = (unsigned long long*)(w + c->I.stats);
   a.done = (uint32_t*)(w + c->I.done);
+  a.big_list = (int32_t*)(w + c->I.big_list);
+  a.big_count = (uint32_t*)(w + c->I.big_count);
+  a.lds_big = c->Lbig;
+  a.big_runs = big_run_slots(c->Lbig, c->Gc);
   a.owner = (uint32_t*)(w + c->I.owner);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);
@@ -447,13 +454,21 @@ dig_status check_ctx(dig_ctx* c) {
 }
 
 // Largest LDS particle stage for group size T: the group target plus room for
-// its last cell, within 48 KiB of LDS; larger groups collide in the
-// destination buffer instead.  At least 512 (the collide keeps its candidate
-// words in the stage's source arrays).
+// its last cell, within 48 KiB of LDS; larger groups go to the oversize-group
+// collide.  At least 512 (the collide keeps its candidate words in the stage's
+// source arrays).
 int32_t lds_particles_for(int32_t T, int32_t Gc) {
   int32_t Lp = T + 256;
   while (Lp > 512 && collide_lds_bytes(Lp, Gc) > 48 * 1024) Lp -= 256;
   return Lp;
+}
+
+// Stage of the oversize-group collide: the largest multiple of 256 particles
+// whose layout fits its LDS budget (about 5900 particles); 0 if none does.
+int32_t lds_big_for(int32_t Gc) {
+  int32_t Lb = (int32_t)(kBigLdsBytes / 24 / 256 * 256);
+  while (Lb > 0 && !big_stage_fits(Lb, Gc)) Lb -= 256;
+  return Lb;
 }
 
 dig_status check_tuning(int32_t T, int32_t Gc, int32_t seq) {
@@ -470,6 +485,7 @@ void apply_tuning(dig_ctx* c, int32_t T, int32_t Gc, int32_t seq) {
   c->Gc = Gc;
   c->seq_max = seq;
   c->Lp = lds_particles_for(T, Gc);
+  c->Lbig = lds_big_for(Gc);
 }
 
 void drop_graphs(dig_ctx* c) {
@@ -493,16 +509,16 @@ dig_status run_stages(dig_ctx* c, int mask, hipStream_t s) {
     HIP_TRY(timed(c, DIG_K_MOVE, s, [&] { return launch_move(a, s); }));
     c->phase = 1;
   }
-  // When the sort and the collide run together, the collide puts each cell
-  // group that fits its shared-memory stage in stable order itself and the
-  // ordering pass only handles the larger groups; the sort stage alone orders
-  // the whole permutation so that it can be inspected.
+  // When the sort and the collide run together, the collide kernels put each
+  // cell group in stable order themselves (k_collide the groups that fit its
+  // stage, k_collide_big the others); the sort stage alone orders the whole
+  // permutation in a pass of its own so that it can be inspected.
   const bool fused = (mask & DIG_STAGE_SORT) && (mask & DIG_STAGE_COLLIDE);
   if (mask & DIG_STAGE_SORT) {
     if (c->phase != 1) return fail(DIG_ERR_STATE, "sort needs the move stage first");
     HIP_TRY(timed(c, DIG_K_SCAN, s, [&] { return launch_scan(a, a.count, false, s); }));
     HIP_TRY(timed(c, DIG_K_PLACE, s, [&] { return launch_place(a, s); }));
-    HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, fused, s); }));
+    if (!fused) HIP_TRY(timed(c, DIG_K_ORDER, s, [&] { return launch_order(a, s); }));
     c->phase = 2;
   }
   if (mask & DIG_STAGE_COLLIDE) {
@@ -561,6 +577,14 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
     return fail(DIG_ERR_INVALID, msg);
   }
   c->ws = (unsigned char*)ws;
+  {
+    // dynamic LDS allowance of the oversize-group collide
+    const hipError_t e = collide_setup();
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "collide_setup");
+    }
+  }
   int32_t cell0 = 0;
   for (int i = 0; i < n_inst; ++i) {
     const dig_config& g = cfgs[i];
@@ -601,6 +625,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_i32(a.count, C, 0, s);
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)a.done, 1, 0, s);
+  if (e == hipSuccess) e = launch_fill_i32((int32_t*)a.big_count, 1, 0, s);
   if (e == hipSuccess) e = launch_fill_f64(a.acc, 17 * C, 0.0, s);
   for (int i = 0; i < n_inst && e == hipSuccess; ++i)
     e = launch_fill_f32(a.sgmax + c->params[i].cell0, c->params[i].ncell,

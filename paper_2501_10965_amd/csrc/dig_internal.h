@@ -111,6 +111,10 @@ struct StepArgs {
   int64_t capacity;
   int32_t inj_sectors;  // angular sectors with inflow (0: closed domain)
   uint32_t* done;       // ticket of the workgroups that finished the collide
+  int32_t lds_big;      // particle stage of the oversize-group collide
+  int32_t big_runs;     // its run-table capacity
+  int32_t* big_list;    // groups too large for the collide's stage, listed by it
+  uint32_t* big_count;  // entries in big_list (emptied by k_collide_big)
 };
 enum { ST_REMOVED = 5, ST_INJECTED = 6 };
 
@@ -134,10 +138,15 @@ dig_status report(dig_status s, const char* msg);
 int64_t group_launch(const StepArgs& a);
 int scan_blocks(int ncell);
 size_t collide_lds_bytes(int lds_particles, int group_cells);
+// LDS of the oversize-group collide: the stage and everything else
+constexpr size_t kBigLdsBytes = 50 * 1024;
+bool big_stage_fits(int lds_big, int group_cells);
+int big_run_slots(int lds_big, int group_cells);
+hipError_t collide_setup();
 hipError_t launch_move(const StepArgs& a, hipStream_t s);
 hipError_t launch_scan(const StepArgs& a, int32_t* counts, bool set_n, hipStream_t s);
 hipError_t launch_place(const StepArgs& a, hipStream_t s);
-hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s);
+hipError_t launch_order(const StepArgs& a, hipStream_t s);
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
                           bool fuse_order, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -12,6 +12,8 @@
 // reservation atomics only decide the order of runs, which k_order restores.
 #include <math.h>
 
+#include <algorithm>
+
 #include "dig_internal.h"
 
 namespace dig {
@@ -511,24 +513,20 @@ static __device__ __forceinline__ int block_exscan(int v, int* s_w, int* total) 
 // and the runs of different waves cover disjoint slot ranges, so ordering the
 // runs by their first slot yields the stable counting-sort order.
 constexpr int kOrderPer = 4;  // consecutive entries per thread, loaded together
-__global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
-  __shared__ int s_start[1025];
-  __shared__ uint32_t s_key[kRunMax];
-  __shared__ uint32_t s_re[kRunMax + 1];
-  __shared__ uint32_t s_off[kRunMax];
-  __shared__ int s_w[8];
-  __shared__ int s_nr;
-  const int g = xcd_group(blockIdx.x, gridDim.x);
+
+// Stable order of one cell group in global memory: perm_raw -> perm.
+// Tables in shared memory supplied by the caller: s_start[group_cells + 1],
+// s_key and s_off[run_max], s_re[run_max + 1], s_w[16], s_nr.
+static __device__ void order_group_global(const StepArgs& a, int g, int* s_start, uint32_t* s_key,
+                                          uint32_t* s_re, uint32_t* s_off, int* s_w, int* s_nr,
+                                          int run_max) {
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
   if (c_lo >= c_hi) return;
   const int nc = c_hi - c_lo;
   const int e_lo = a.start[c_lo];
   const int ng = a.start[c_hi] - e_lo;
-  // in a full step the collide orders the groups that fit its shared-memory
-  // stage; only the larger ones are ordered here
-  if (big_only && ng <= a.lds_particles) return;
   for (int c = threadIdx.x; c <= nc; c += blockDim.x) s_start[c] = a.start[c_lo + c] - e_lo;
-  if (threadIdx.x == 0) s_nr = 0;
+  if (threadIdx.x == 0) *s_nr = 0;
   __syncthreads();
   if (ng == 0) return;
   const int32_t* src = a.perm_raw + e_lo;
@@ -557,23 +555,23 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
       cnt += head[u];
     }
     int total;
-    int r = s_nr + block_exscan(cnt, s_w, &total);
+    int r = *s_nr + block_exscan(cnt, s_w, &total);
 #pragma unroll
     for (int u = 0; u < kOrderPer; ++u)
       if (head[u]) {
-        if (r < kRunMax) {
+        if (r < run_max) {
           s_key[r] = v[u];
           s_re[r] = (uint32_t)(e0 + u);
         }
         ++r;
       }
     __syncthreads();
-    if (threadIdx.x == 0) s_nr += total;
+    if (threadIdx.x == 0) *s_nr += total;
     __syncthreads();
-    if (s_nr > kRunMax) { overflow = true; break; }
+    if (*s_nr > run_max) { overflow = true; break; }
   }
   if (!overflow) {
-    const int nr = s_nr;
+    const int nr = *s_nr;
     if (threadIdx.x == 0) s_re[nr] = (uint32_t)ng;
     __syncthreads();
     for (int r = threadIdx.x; r < nr; r += blockDim.x) {
@@ -609,12 +607,25 @@ __global__ __launch_bounds__(256) void k_order(StepArgs a, int big_only) {
     if (threadIdx.x == 0) atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_SORT_OVERFLOW);
     for (int e = threadIdx.x; e < ng; e += blockDim.x) {
       const int c = floor_index(s_start, nc + 1, e);
-      const int32_t s = src[e];
+      const int32_t sv = src[e];
       int rank = 0;
-      for (int q = s_start[c]; q < s_start[c + 1]; ++q) rank += (src[q] < s);
-      dst[s_start[c] + rank] = s;
+      for (int q = s_start[c]; q < s_start[c + 1]; ++q) rank += (src[q] < sv);
+      dst[s_start[c] + rank] = sv;
     }
   }
+  __syncthreads();
+}
+
+// Ordering pass of a staged sort: every cell group, one workgroup each.
+__global__ __launch_bounds__(256) void k_order(StepArgs a) {
+  __shared__ int s_start[1025];
+  __shared__ uint32_t s_key[kRunMax];
+  __shared__ uint32_t s_re[kRunMax + 1];
+  __shared__ uint32_t s_off[kRunMax];
+  __shared__ int s_w[16];
+  __shared__ int s_nr;
+  order_group_global(a, xcd_group(blockIdx.x, gridDim.x), s_start, s_key, s_re, s_off, s_w,
+                     &s_nr, kRunMax);
 }
 
 // ---------------------------------------------------------------------------
@@ -650,7 +661,7 @@ struct CollideShared {
   uint32_t* w3;
   uint8_t* pend;
   int* stat;    // [4]
-  int* wsum;    // [8]
+  int* wsum;    // [16]
 };
 
 // Candidate of a cell (Section 2.2): VHS acceptance of the pair against the
@@ -950,13 +961,14 @@ static_assert(2 * sizeof(uint32_t) * 512 >= 2 * sizeof(uint4) * kCandChunk,
 // algorithm of k_order, for one cell group inside the collide): runs of the
 // provisional segment of a cell (one per reserving wave, increasing sources)
 // are ordered by their first source.  st: cell starts relative to the group
-// (LDS), raw/ord: provisional and ordered sources (LDS or global).  kRunSlots
-// runs per group; more fall back to counting ranks.
+// (LDS), raw/ord: provisional and ordered sources (LDS or global).  run_slots
+// runs per group (kRunSlots in the small-group collide); more fall back to
+// counting ranks.
 constexpr int kRunSlots = 256;
 template <class Raw, class Ord>
 static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng, Raw raw, Ord ord,
                                                   uint32_t* rkey, uint32_t* rre, uint32_t* roff,
-                                                  int* s_w) {
+                                                  int* s_w, int run_slots) {
   // each thread walks a block of consecutive elements: runs are counted, the
   // counts scanned, then written in element order.  The barrier publishes the
   // caller's writes of st and raw.
@@ -978,7 +990,7 @@ static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng,
   }
   int nr;
   int r = block_exscan(cnt, s_w, &nr);
-  if (nr <= kRunSlots) {
+  if (nr <= run_slots) {
     int c = c0;
     uint32_t pv = p0;
     for (int e = e0; e < e1; ++e) {
@@ -1022,18 +1034,27 @@ static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng,
   __syncthreads();
 }
 
-static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int do_collide,
-                                                     int do_sample, int fuse_order) {
+// What a collide launch does with a cell group:
+//   kModeStaged  every group; the permutation was ordered by k_order.
+//   kModeSmall   groups that fit the stage of L particles are ordered here;
+//                larger ones are listed for k_collide_big and skipped.
+//   kModeBig     a listed group, ordered here in the (larger) stage of L
+//                particles or, when it does not fit, in global memory.
+enum { kModeStaged = 0, kModeSmall = 1, kModeBig = 2 };
+
+template <int mode>
+static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int L,
+                                                     int run_slots, int do_collide,
+                                                     int do_sample) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int c_lo = a.gfirst[g], c_hi = a.gfirst[g + 1];
   if (c_lo >= c_hi) return;
   const int nc = c_hi - c_lo;
   const int Gc = a.group_cells;
-  const int L = a.lds_particles;
   const uint32_t step = (uint32_t)a.ctr->step;
   // shared layout.  Until the gather fills it, the velocity stage sv holds
   // the ordering's run tables and entry -> cell map (16 L bytes >= their
-  // 3 (kRunSlots + 1) words + L bytes for every L >= 256).  After the gather
+  // 3 (run_slots + 1) words + L bytes, checked on the host).  After the gather
   // the source arrays lown and sord are free: the one-lane cells' pre-drawn
   // words use both (8 L >= 32 kCandChunk bytes for L >= 512) before the
   // round owners of the large cells use lown.
@@ -1042,9 +1063,9 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   uint32_t* lown = (uint32_t*)p;        p += sizeof(uint32_t) * L;  // round owners
   int32_t* sord = (int32_t*)p;          p += sizeof(int32_t) * L;   // ordered sources
   uint32_t* rkey = (uint32_t*)sv;
-  uint32_t* rre = rkey + (kRunSlots + 1);
-  uint32_t* roff = rre + (kRunSlots + 1);
-  uint8_t* ecell = (uint8_t*)(roff + (kRunSlots + 1));  // cell of each staged entry
+  uint32_t* rre = rkey + (run_slots + 1);
+  uint32_t* roff = rre + (run_slots + 1);
+  uint8_t* ecell = (uint8_t*)(roff + (run_slots + 1));  // cell of each staged entry
   CollideShared S;
   S.words = (uint4*)lown;
   S.start = (int*)p;                    p += sizeof(int) * (Gc + 1);
@@ -1059,13 +1080,32 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   S.w2 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
   S.w3 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
   S.stat = (int*)p;                     p += sizeof(int) * 4;
-  S.wsum = (int*)p;                     p += sizeof(int) * 8;
+  S.wsum = (int*)p;                     p += sizeof(int) * 16;
   S.pend = (uint8_t*)p;
 
   const int e_lo = a.start[c_lo];
   const int ng = a.start[c_hi] - e_lo;
   const bool fast = ng <= L;
-  const bool stage = fuse_order && fast;
+  if constexpr (mode == kModeSmall) {
+    if (!fast) {
+      if (threadIdx.x == 0) a.big_list[atomicAdd(a.big_count, 1u)] = g;
+      return;
+    }
+  }
+  if constexpr (mode == kModeBig) {
+    if (!fast) {
+      // too large even for this stage: ordered in global memory, with the
+      // tables in the velocity stage (unused by such a group; 16 L bytes hold
+      // them, checked on the host)
+      int* t_start = (int*)sv;
+      uint32_t* t_key = (uint32_t*)(t_start + Gc + 1);
+      uint32_t* t_re = t_key + run_slots;
+      uint32_t* t_off = t_re + run_slots + 1;
+      int* t_w = (int*)(t_off + run_slots);
+      order_group_global(a, g, t_start, t_key, t_re, t_off, t_w, t_w + 16, run_slots);
+    }
+  }
+  const bool stage = mode != kModeStaged && fast;
   // the provisional segment is loaded together with the cell data: the first
   // kStagePer entries of each thread into registers
   int32_t pre[kStagePer];
@@ -1088,8 +1128,7 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   if (threadIdx.x < 4) S.stat[threadIdx.x] = 0;
   if (stage) {
     // stable order of the group: the provisional segment staged in LDS (in
-    // the round-owner array, free until the collisions); groups that do not
-    // fit were ordered by k_order
+    // the round-owner array, free until the collisions)
     int32_t* sraw = (int32_t*)lown;
 #pragma unroll
     for (int u = 0; u < kStagePer; ++u) {
@@ -1107,7 +1146,7 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
         for (int e = b; e < b + n; ++e) ecell[e] = (uint8_t)c;
     }
     if (__syncthreads_or(big)) {
-      order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum);
+      order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum, run_slots);
     } else {
       // every cell small: an entry's place in its cell is the number of the
       // cell's entries with a smaller source (sources are distinct)
@@ -1236,27 +1275,66 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   }
 }
 
-// Collide + sample of one cell group per workgroup.  With end_step, the last
-// workgroup to take a grid-wide ticket closes the step: the sorted count
-// becomes the particle count and the step counter advances.  A workgroup
-// takes its ticket after all its threads have read the step counter (at their
-// start), so no workgroup can read the advanced counter; nothing else the
-// closing workgroup writes is read within this kernel.
+// Collide + sample of one cell group per workgroup (mode kModeStaged or
+// kModeSmall).  With end_step, the last workgroup to take a grid-wide ticket
+// closes the step: the sorted count becomes the particle count and the step
+// counter advances.  A workgroup takes its ticket after all its threads have
+// read the step counter (at their start), so no workgroup can read the
+// advanced counter; nothing else the closing workgroup writes is read within
+// this kernel.
 // MINW: waves per SIMD the register budget must allow.  6 (80 VGPRs) is
 // launched where the LDS stage leaves room for 6 workgroups per CU, 1 (no
 // constraint) otherwise.
-template <int MINW>
+template <int MINW, int mode>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(MINW)))
-void k_collide(StepArgs a, int do_collide,
-                                                             int do_sample, int end_step,
-                                                             int fuse_order) {
-  collide_group(a, xcd_group(blockIdx.x, gridDim.x), do_collide, do_sample, fuse_order);
+void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
+  collide_group<mode>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles, kRunSlots,
+                      do_collide, do_sample);
   if (!end_step || threadIdx.x != 0) return;
   const uint32_t prev = atomicAdd(a.done, 1u);
   if (prev == gridDim.x - 1) {
     a.ctr->n = a.start[a.ncell];
     a.ctr->step += 1;
     if (do_sample) a.ctr->nsamp += 1;
+    atomicExch(a.done, 0u);
+  }
+}
+
+// The groups k_collide listed as larger than its stage: a persistent grid of
+// kBigThreads-thread workgroups (three per CU: the stage of lds_big particles
+// takes a third of the CU's LDS), each taking listed groups in turn.  With
+// groups listed, every workgroup takes a ticket when done and the last one
+// empties the list and, with end_step, closes the step as k_collide does;
+// with none (the common case at moderate cell sizes) workgroup 0 closes the
+// step alone and the others exit at once.
+constexpr int kBigThreads = 256;
+constexpr int kBigGrid = 768;
+__global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_collide,
+                                                             int do_sample, int end_step) {
+  const int nbig = __builtin_amdgcn_readfirstlane((int)*a.big_count);
+  if (nbig == 0) {
+    if (end_step && blockIdx.x == 0 && threadIdx.x == 0) {
+      a.ctr->n = a.start[a.ncell];
+      a.ctr->step += 1;
+      if (do_sample) a.ctr->nsamp += 1;
+    }
+    return;
+  }
+  for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
+    const int g = __builtin_amdgcn_readfirstlane(a.big_list[i]);
+    collide_group<kModeBig>(a, g, a.lds_big, a.big_runs, do_collide, do_sample);
+    __syncthreads();  // the next group reuses the shared memory
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const uint32_t prev = atomicAdd(a.done, 1u);
+  if (prev == gridDim.x - 1) {
+    atomicExch(a.big_count, 0u);
+    if (end_step) {
+      a.ctr->n = a.start[a.ncell];
+      a.ctr->step += 1;
+      if (do_sample) a.ctr->nsamp += 1;
+    }
     atomicExch(a.done, 0u);
   }
 }
@@ -1895,7 +1973,27 @@ size_t collide_lds_bytes(int lds_particles, int group_cells) {
   return sizeof(float4) * lds_particles + 2 * sizeof(uint32_t) * lds_particles +
          sizeof(int) * 3 * (group_cells + 1) +
          (sizeof(float) + 2 * sizeof(int)) * group_cells + (5 * sizeof(int) + 1) * kCandChunk +
-         sizeof(int) * 12 + 16;
+         sizeof(int) * 20 + 16;
+}
+
+int big_run_slots(int lds_big, int group_cells) {
+  // runs that fit the stage next to the entry -> cell map (in-LDS ordering)
+  // and next to the cell starts (global-memory ordering), at most kRunMax
+  const int64_t st = (int64_t)sizeof(float4) * lds_big;
+  const int64_t a = (st - lds_big) / (3 * (int64_t)sizeof(uint32_t)) - 1;
+  const int64_t b = (st - (int64_t)sizeof(int) * (group_cells + 1 + 17) - 4) /
+                    (3 * (int64_t)sizeof(uint32_t));
+  return (int)std::min<int64_t>(kRunMax, std::min(a, b));
+}
+
+bool big_stage_fits(int lds_big, int group_cells) {
+  return lds_big >= 512 && big_run_slots(lds_big, group_cells) >= kRunSlots &&
+         collide_lds_bytes(lds_big, group_cells) <= kBigLdsBytes;
+}
+
+hipError_t collide_setup() {
+  return hipFuncSetAttribute((const void*)k_collide_big,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLdsBytes);
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
@@ -1918,23 +2016,39 @@ hipError_t launch_place(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const StepArgs& a, bool big_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(256), 0, s, a, big_only ? 1 : 0);
+hipError_t launch_order(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_order, dim3((int)group_launch(a)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
-                          bool fuse_order, hipStream_t s) {
+                          bool fused, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
   const dim3 grid((int)group_launch(a)), block(kCollideThreads);
-  const int f0 = collide ? 1 : 0, f1 = sample ? 1 : 0, f2 = end_step ? 1 : 0,
-            f3 = fuse_order ? 1 : 0;
+  const int f0 = collide ? 1 : 0, f1 = sample ? 1 : 0;
+  // fused: small groups here, the listed larger ones in k_collide_big, which
+  // then closes the step
+  const int f2 = (end_step && !fused) ? 1 : 0;
   // 160 KiB of LDS per CU; 1 KiB per workgroup kept for static LDS and
   // allocation granularity
-  if (6 * (lds + 1024) <= 160 * 1024)
-    hipLaunchKernelGGL(k_collide<6>, grid, block, lds, s, a, f0, f1, f2, f3);
-  else
-    hipLaunchKernelGGL(k_collide<1>, grid, block, lds, s, a, f0, f1, f2, f3);
+  const bool six = 6 * (lds + 1024) <= 160 * 1024;
+  if (fused) {
+    if (six)
+      hipLaunchKernelGGL((k_collide<6, kModeSmall>), grid, block, lds, s, a, f0, f1, f2);
+    else
+      hipLaunchKernelGGL((k_collide<1, kModeSmall>), grid, block, lds, s, a, f0, f1, f2);
+  } else {
+    if (six)
+      hipLaunchKernelGGL((k_collide<6, kModeStaged>), grid, block, lds, s, a, f0, f1, f2);
+    else
+      hipLaunchKernelGGL((k_collide<1, kModeStaged>), grid, block, lds, s, a, f0, f1, f2);
+  }
+  if (fused) {
+    if (!big_stage_fits(a.lds_big, a.group_cells)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_collide_big, dim3(kBigGrid), dim3(kBigThreads),
+                       collide_lds_bytes(a.lds_big, a.group_cells), s, a, f0, f1,
+                       end_step ? 1 : 0);
+  }
   return hipGetLastError();
 }
 
