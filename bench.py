@@ -98,7 +98,8 @@ def roofline(prof, breakdown, n_avg, ncell, workload, dim):
     ach = alg / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload),
-            "kernel": "k_collide", "avg_launch_us": round(avg_s * 1e6, 2),
+            "kernel": "k_collide + k_collide_big (collide stage, one launch each per step)",
+            "avg_launch_us": round(avg_s * 1e6, 2),
             "algorithmic_bytes_per_launch": int(alg)}
 
 
