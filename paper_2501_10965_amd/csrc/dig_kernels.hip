@@ -945,6 +945,58 @@ static __device__ __forceinline__ double select17(const double s[17], int f) {
   return r;
 }
 
+// Sum f of one particle, written as in sub_cell_sums.
+static __device__ __forceinline__ double raw_term(int f, double x, double y, double z, double e,
+                                                  double v2) {
+  switch (f) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return x * x;
+    case 5: return y * y;
+    case 6: return z * z;
+    case 7: return x * y;
+    case 8: return x * z;
+    case 9: return y * z;
+    case 10: return x * v2;
+    case 11: return y * v2;
+    case 12: return z * v2;
+    case 13: return e;
+    case 14: return x * e;
+    case 15: return y * e;
+    default: return z * e;
+  }
+}
+
+// Sums F0 .. F0 + NF - 1 of sub_cell_sums, with the same order of additions
+// (so the same bits), for fewer live registers.
+template <int F0, int NF, class Store>
+static __device__ void sub_cell_sums_part(Store P, int b, int N, double s[NF]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) s[f] = 0.0;
+  for (int k = lane_id() & (kSub - 1); k < N; k += kSub) {
+    const float4 v = P.ld(b + k);
+    const double x = v.x, y = v.y, z = v.z, e = v.w;
+    double v2 = 0.0;
+    if constexpr (F0 <= 12 && F0 + NF > 10) v2 = x * x + y * y + z * z;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s[f] += raw_term(F0 + f, x, y, z, e, v2);
+  }
+#pragma unroll
+  for (int off = kSub / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s[f] += __shfl_xor(s[f], off);
+}
+
+template <int NF>
+static __device__ __forceinline__ double select_n(const double s[NF], int f) {
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) r = (f == k) ? s[k] : r;
+  return r;
+}
+
 // One workgroup (a single wave) per cell group: gather the group's particles
 // from the previous buffer in sorted order (positions and ids straight to the
 // destination, velocities and rotational energies into LDS), collide, write
@@ -1042,7 +1094,9 @@ static __device__ __forceinline__ void order_runs(const int* st, int nc, int ng,
 //                particles or, when it does not fit, in global memory.
 enum { kModeStaged = 0, kModeSmall = 1, kModeBig = 2 };
 
-template <int mode>
+// two_pass: the cells' moment sums in two passes (fewer live registers, for
+// the 80-VGPR budget of six waves per SIMD) rather than one.
+template <int mode, bool two_pass = false>
 static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int L,
                                                      int run_slots, int do_collide,
                                                      int do_sample) {
@@ -1253,22 +1307,45 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       const int c = cb + sub;
       const bool ok = c < nc;
       const int b = ok ? S.start[c] : 0, N = ok ? S.start[c + 1] - b : 0;
-      // the accumulator is read before the sums, so its latency overlaps them
+      // the accumulator is read before the sums, so its latency overlaps
+      // them
       double* acc = a.acc + (int64_t)(c_lo + (ok ? c : 0)) * 17;
-      double prev[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int f = sl + k * kSub;
-        prev[k] = ok && f < 17 ? acc[f] : 0.0;
-      }
-      double s[17];
-      if (fast) sub_cell_sums(ls, b, N, s);
-      else sub_cell_sums(gs, b, N, s);
-      if (ok) {
+      if (two_pass && fast) {
+        // from LDS in two passes of 9 and 8 sums: lane sl of the subgroup
+        // adds sums sl and (sl = 0) 8 of the first, 9 + sl of the second
+        const double p0 = ok ? acc[sl] : 0.0;
+        const double p8 = ok && sl == 0 ? acc[8] : 0.0;
+        const double p9 = ok ? acc[9 + sl] : 0.0;
+        {
+          double s[9];
+          sub_cell_sums_part<0, 9>(ls, b, N, s);
+          if (ok) {
+            acc[sl] = p0 + select_n<8>(s, sl);
+            if (sl == 0) acc[8] = p8 + s[8];
+          }
+        }
+        {
+          double s[8];
+          sub_cell_sums_part<9, 8>(ls, b, N, s);
+          if (ok) acc[9 + sl] = p9 + select_n<8>(s, sl);
+        }
+      } else {
+        // one pass, from LDS or global memory
+        double prev[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int f = sl + k * kSub;
-          if (f < 17) acc[f] = prev[k] + select17(s, f);
+          prev[k] = ok && f < 17 ? acc[f] : 0.0;
+        }
+        double s[17];
+        if (fast) sub_cell_sums(ls, b, N, s);
+        else sub_cell_sums(gs, b, N, s);
+        if (ok) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int f = sl + k * kSub;
+            if (f < 17) acc[f] = prev[k] + select17(s, f);
+          }
         }
       }
     }
@@ -1288,8 +1365,8 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 template <int MINW, int mode>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
-  collide_group<mode>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles, kRunSlots,
-                      do_collide, do_sample);
+  collide_group<mode, MINW == 6>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles,
+                                 kRunSlots, do_collide, do_sample);
   if (!end_step || threadIdx.x != 0) return;
   const uint32_t prev = atomicAdd(a.done, 1u);
   if (prev == gridDim.x - 1) {
