@@ -2,8 +2,9 @@
 path orders the whole permutation in a pass of its own.  Both must give
 bit-identical states: small cells (ordered by counting ranks), cells above
 that size in groups that fit the shared-memory stage (ordered from the move's
-runs), groups too large for the stage, and steps where particles leave
-through an open boundary."""
+runs), groups too large for that stage but not for the oversize-group
+kernel's, groups too large for both (ordered in global memory), and steps
+where particles leave through an open boundary."""
 import numpy as np
 import pytest
 
@@ -32,6 +33,11 @@ CASES = {
     "midcells": lambda: wl.box(1, 40, kn=0.05, ppc=200, seed=404,
                                bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.3, (0, 0, 0)),
                                    ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))]),
+    # cells of ~700 particles: groups of two exceed the small-group stage and
+    # are ordered and collided in the oversize-group kernel's LDS stage
+    "stagecells": lambda: wl.box(1, 30, kn=0.1, ppc=700, seed=405,
+                                 bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.2, (0, 0, 0)),
+                                     ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))]),
     "bigcells": lambda: wl.box(1, 6, kn=0.2, ppc=3000, seed=402,
                                bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.5, (0, 0, 0)),
                                    ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))]),
