@@ -238,7 +238,11 @@ dig_status dig_constants(dig_ctx* ctx, int32_t inst, double* out_host5);
 /* Per-kernel timing with HIP events recorded on `stream` immediately before
  * and after every launch of the step and adjust kernels.  mode 1: enable and
  * reset; mode 0: disable; mode 2: synchronise and read the totals into
- * ms_host[DIG_NKERNELS] (milliseconds) and launches_host[DIG_NKERNELS]. */
+ * ms_host[DIG_NKERNELS] (milliseconds) and launches_host[DIG_NKERNELS].
+ * Kinds: DIG_K_SCAN counts both scan kernels as one launch; DIG_K_ORDER is
+ * the ordering pass of a sort stage run on its own (a full step orders each
+ * cell group inside the collide); DIG_K_COLLIDE is the collide stage, the
+ * small-group and the oversize-group kernels timed together as one launch. */
 enum { DIG_K_MOVE = 0, DIG_K_SCAN = 1, DIG_K_PLACE = 2, DIG_K_ORDER = 3, DIG_K_COLLIDE = 4,
        DIG_K_ADJUST = 5, DIG_K_SAMPLE = 6, DIG_K_CLOSURE = 7, DIG_NKERNELS = 8 };
 dig_status dsmc_profile(dig_ctx* ctx, int32_t mode, double* ms_host, int64_t* launches_host,
