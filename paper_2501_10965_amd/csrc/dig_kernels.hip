@@ -1,15 +1,21 @@
 // HIP kernels of libdig for gfx950 (CDNA4, wave64).
 //
-// One DSMC step (Section 2.2 of arXiv:2501.10965) is five launches:
-//   k_move     free flight + walls + cell index + wave-aggregated reservation
-//   k_scan     cell counts -> cell starts, cell groups, instance ranges
-//   k_place    provisional placement by the reserved rank
-//   k_order    per-cell ordering of the provisional runs (stable sort result)
-//   k_collide  gather into the other buffer, NTC/VHS/BL collisions in LDS,
-//              FP64 moment sums accumulated per cell
-// plus a one-thread step counter update.  Every result is a deterministic
-// function of (seed, step, state): no floating-point atomics, and the
-// reservation atomics only decide the order of runs, which k_order restores.
+// One DSMC step (Section 2.2 of arXiv:2501.10965) is six launches:
+//   k_move          free flight + walls + cell index + wave-aggregated
+//                   reservation of slots per destination cell
+//   k_scan_reduce,  cell counts -> cell starts, cell groups, instance ranges
+//   k_scan_apply
+//   k_place         provisional placement by the reserved rank
+//   k_collide       per cell group that fits its LDS stage: stable order of
+//                   the group, gather into the other buffer, NTC/VHS/BL
+//                   collisions, FP64 moment sums accumulated per cell; larger
+//                   groups are listed
+//   k_collide_big   the same for the listed groups, in a larger stage or in
+//                   global memory; closes the step
+// (k_order orders every group when the sort stage runs on its own.)  Every
+// result is a deterministic function of (seed, step, state): no
+// floating-point atomics, and the reservation atomics only decide the order
+// of runs, which the ordering restores.
 #include <math.h>
 
 #include <algorithm>
