@@ -61,10 +61,15 @@ def default_A(omega):
 
 
 def source_digest() -> str:
+    """Hash of the kernel sources' code (comments and whitespace removed), so
+    that counters taken on the same code stay valid across comment edits."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
