@@ -249,11 +249,14 @@ dig_status dsmc_profile(dig_ctx* ctx, int32_t mode, double* ms_host, int64_t* la
                         dig_stream_t stream);
 
 /* Restricts dsmc_profile's events to the kernel kinds whose bit
- * (1u << DIG_K_*) is set in mask; the other kinds launch without events, so
- * timing one kernel perturbs the rest of the step as little as possible.
- * The default (and after dsmc_create) is every kind.  Host only; takes effect
- * at the next launch.  Errors: DIG_ERR_INVALID (bit beyond DIG_NKERNELS). */
-dig_status dsmc_profile_kinds(dig_ctx* ctx, uint32_t mask);
+ * (1u << DIG_K_*) is set in mask, and to one launch of each such kind in
+ * every `every` (counted from dsmc_profile mode 1); other launches run without
+ * events, so that timing perturbs the step as little as possible.  The
+ * launches counts read by dsmc_profile are those timed.  The default (and
+ * after dsmc_create) is every kind, every launch.  Host only; takes effect at
+ * the next launch.  Errors: DIG_ERR_INVALID (bit beyond DIG_NKERNELS, every <
+ * 1). */
+dig_status dsmc_profile_kinds(dig_ctx* ctx, uint32_t mask, int32_t every);
 
 /* Launch configuration of the step kernels.  group_particles / group_cells as
  * in dsmc_create; seq_max: cells with at most this many particles run their

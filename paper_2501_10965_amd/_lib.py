@@ -150,7 +150,7 @@ def load(path: str = LIB_PATH):
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
     L.dsmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
-    L.dsmc_profile_kinds.argtypes = [vp, C.c_uint32]
+    L.dsmc_profile_kinds.argtypes = [vp, C.c_uint32, C.c_int32]
     L.dig_synth_workspace_bytes.argtypes = [cp]
     L.dig_synth_workspace_bytes.restype = C.c_size_t
     L.synth_solve.argtypes = [cp, C.POINTER(DigSynthOpts), vp, vp, vp, vp, vp, C.c_size_t,

@@ -313,6 +313,8 @@ struct dig_ctx {
   // event profiling
   bool prof = false;
   uint32_t prof_mask = ~0u;  // kernel kinds timed while profiling
+  int32_t prof_every = 1;     // time one launch of a kind in every prof_every
+  int64_t prof_seen[DIG_NKERNELS] = {};
   EvPool eager;
   double prof_ms[DIG_NKERNELS] = {0};
   int64_t prof_n[DIG_NKERNELS] = {0};
@@ -378,12 +380,15 @@ StepArgs args(const dig_ctx* c) {
   return a;
 }
 
+// Timing-only events: no system-scope fence at record (its cache write-back
+// and invalidation would stall the next kernel for microseconds); the
+// durations are read after a stream synchronisation.
 hipError_t pool_grow(dig_ctx::EvPool* p, size_t pairs) {
   while (p->kind.size() < pairs) {
     hipEvent_t a, b;
-    hipError_t e = hipEventCreate(&a);
+    hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
     if (e != hipSuccess) return e;
-    e = hipEventCreate(&b);
+    e = hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
     if (e != hipSuccess) return e;
     p->ev.push_back(a);
     p->ev.push_back(b);
@@ -425,6 +430,7 @@ hipError_t prof_fold(dig_ctx* c, hipStream_t s) {
 template <class F>
 hipError_t timed(dig_ctx* c, int kind, hipStream_t s, F&& launch) {
   if (!c->prof || !((c->prof_mask >> kind) & 1u)) return launch();
+  if (c->prof_seen[kind]++ % c->prof_every != 0) return launch();
   dig_ctx::EvPool* p = &c->eager;
   if (p->used == p->kind.size()) {
     hipError_t e = prof_fold(c, s);
@@ -886,6 +892,7 @@ dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
       c->prof_ms[k] = 0.0;
       c->prof_n[k] = 0;
     }
+    for (int k = 0; k < DIG_NKERNELS; ++k) c->prof_seen[k] = 0;
     c->prof = true;
     return DIG_OK;
   }
@@ -906,10 +913,12 @@ dig_status dsmc_profile(dig_ctx* c, int32_t mode, double* ms, int64_t* launches,
   return fail(DIG_ERR_INVALID, "bad profile mode");
 }
 
-dig_status dsmc_profile_kinds(dig_ctx* c, uint32_t mask) {
+dig_status dsmc_profile_kinds(dig_ctx* c, uint32_t mask, int32_t every) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (mask >> DIG_NKERNELS) return fail(DIG_ERR_INVALID, "unknown kernel kind in mask");
+  if (every < 1) return fail(DIG_ERR_INVALID, "every must be >= 1");
   c->prof_mask = mask;
+  c->prof_every = every;
   return DIG_OK;
 }
 

@@ -236,14 +236,15 @@ class DSMC:
             float(judge_rel), _ptr(hot), _ptr(src), _stream()))
         return src
 
-    def profile(self, mode: str, kinds=None):
+    def profile(self, mode: str, kinds=None, every: int = 1):
         """'on' (reset and enable), 'off', or 'read' -> {kernel: (ms_total, launches)}.
-        kinds (with 'on'): the kernel kinds to time, default all."""
+        kinds (with 'on'): the kernel kinds to time, default all; every: time
+        one launch of each in every `every`."""
         m = {"off": 0, "on": 1, "read": 2}[mode]
         if m == 1:
             mask = (1 << len(L.KERNELS)) - 1 if kinds is None else \
                 sum(1 << L.KERNELS.index(k) for k in kinds)
-            L.check(self.lib.dsmc_profile_kinds(self.ctx, mask))
+            L.check(self.lib.dsmc_profile_kinds(self.ctx, mask, int(every)))
         ms = (C.c_double * len(L.KERNELS))()
         nl = (C.c_int64 * len(L.KERNELS))()
         L.check(self.lib.dsmc_profile(self.ctx, m, ms, nl, _stream()))

@@ -221,5 +221,12 @@ def test_profiling_a_subset_of_kernel_kinds():
     prof = s.profile("read")
     s.profile("off")
     assert all(prof[k][1] == 2 for k in ("move", "scan", "place", "collide"))
+    s.profile("on", kinds=["collide", "move"], every=3)  # launches 0, 3, 6 of each
+    s.step(7)
+    prof = s.profile("read")
+    s.profile("off")
+    assert prof["collide"][1] == 3 and prof["move"][1] == 3 and prof["scan"][1] == 0
     with pytest.raises(L.DigError):
-        L.check(s.lib.dsmc_profile_kinds(s.ctx, 1 << len(L.KERNELS)))
+        L.check(s.lib.dsmc_profile_kinds(s.ctx, 1 << len(L.KERNELS), 1))
+    with pytest.raises(L.DigError):
+        L.check(s.lib.dsmc_profile_kinds(s.ctx, 1, 0))
