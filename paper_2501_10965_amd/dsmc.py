@@ -262,9 +262,10 @@ class DSMC:
 def synth_solve(w: dict, m_half: torch.Tensor, hot: torch.Tensor | None = None,
                 mask: torch.Tensor | None = None, A=None, cfl: float = 0.5,
                 wall_mode: str = "dsmc", max_iter: int = 2000, tol: float = 1e-5,
-                check_every: int = 32):
+                check_every: int = 128):
     """Synthetic-equation solve on the GPU; returns (m_next [6, C], iterations,
-    last relative change)."""
+    last relative change).  The change is checked every check_every
+    iterations (each check synchronises the host)."""
     lib = L.load()
     cfg = L.make_config(w)
     nc = w["nx"] * w.get("ny", 1)
