@@ -44,7 +44,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      stats, rf2, dir, inj_off, done, big_list, big_count;
+      xsum, stats, rf2, dir, inj_off, done, big_list, big_count;
   int64_t gfirst_len;
 };
 
@@ -205,6 +205,7 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->cstart = take(4 * (C + 1));
   I->bsum = take(8 * (scan_blocks((int)C) + 1));
   I->lastcnt = take(4 * (scan_blocks((int)C) + 1));
+  I->xsum = take(8 * 2 * (exscan_chunks((int)C) + 1));
   I->stats = take(sizeof(unsigned long long) * kStatSlots * ST_N);
   I->done = take(sizeof(uint32_t));
   I->big_list = take(4 * I->gfirst_len);
@@ -755,8 +756,8 @@ dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_strea
   int32_t* newstart = (int32_t*)(w + c->I.newstart);
   int32_t* cstart = (int32_t*)(w + c->I.cstart);
   HIP_TRY(launch_adjust_count(a, target, iter, newcount, ccount, s));
-  HIP_TRY(launch_exscan(newcount, newstart, c->ncell, s));
-  HIP_TRY(launch_exscan(ccount, cstart, c->ncell, s));
+  HIP_TRY(launch_exscan2(newcount, newstart, ccount, cstart, c->ncell,
+                         (int64_t*)(w + c->I.xsum), s));
   int32_t tot[2] = {0, 0};
   uint32_t err = 0;
   HIP_TRY(hipMemcpyAsync(&tot[0], newstart + c->ncell, 4, hipMemcpyDeviceToHost, s));

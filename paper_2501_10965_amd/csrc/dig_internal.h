@@ -161,7 +161,11 @@ hipError_t launch_convert(const StepArgs& a, const double* sums, bool average, d
                           hipStream_t s);
 hipError_t launch_adjust_count(const StepArgs& a, const double* target, uint32_t iter,
                                int32_t* newcount, int32_t* ccount, hipStream_t s);
-hipError_t launch_exscan(const int32_t* in, int32_t* out, int32_t n, hipStream_t s);
+// Exclusive scans out0 = scan(in0), out1 = scan(in1) of n counts each, with
+// the totals in out0[n] and out1[n]; csum: 2 exscan_chunks(n) int64 of scratch.
+int exscan_chunks(int n);
+hipError_t launch_exscan2(const int32_t* in0, int32_t* out0, const int32_t* in1,
+                          int32_t* out1, int32_t n, int64_t* csum, hipStream_t s);
 hipError_t launch_adjust_build(const StepArgs& a, const double* target, uint32_t iter,
                                const int32_t* newstart, const int32_t* cstart,
                                hipStream_t s);

@@ -464,8 +464,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(StepArgs a, int32_t* counts,
       if (g <= glaunch) a.gfirst[g] = c;
       else atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_GROUPS);
     }
-    for (int i = 0; i < a.n_inst; ++i)
-      if (a.params[i].cell0 == c) a.inst_pstart[i] = st;
+    const int ci = a.cell_inst[c];
+    if (a.params[ci].cell0 == c) a.inst_pstart[ci] = st;
     prev_start = st;
     st += cnt[k];
   }
@@ -1685,31 +1685,58 @@ __global__ void k_adjust_count(StepArgs a, const double* target, uint32_t iter,
   ccount[c] = (N == 0) ? nt : (nt > N ? nt - N : 0);
 }
 
+// Exclusive scans of the two per-cell count arrays of a modification (target
+// counts and clone counts), both in one pair of launches: blockIdx.y selects
+// the array; chunk sums, then per-chunk scans offset by the preceding chunks.
 constexpr int kExPer = 8;
-__global__ __launch_bounds__(1024) void k_exscan(const int32_t* in, int32_t* out, int32_t n) {
-  // one workgroup, tiles of 1024 x kExPer consecutive counts: each thread
-  // sums its kExPer, a block scan of the thread sums, a carry between tiles
-  __shared__ int s_w[16];
-  int64_t carry = 0;
-  for (int base = 0; base < n; base += 1024 * kExPer) {
-    const int c0 = base + (int)threadIdx.x * kExPer;
-    int v[kExPer];
-    int sum = 0;
+constexpr int kExChunk = 256 * kExPer;
+
+__global__ __launch_bounds__(256) void k_exscan_reduce(const int32_t* in0, const int32_t* in1,
+                                                       int32_t n, int64_t* csum) {
+  __shared__ int s_w[4];
+  const int32_t* in = blockIdx.y ? in1 : in0;
+  const int c0 = blockIdx.x * kExChunk + threadIdx.x * kExPer;
+  int sum = 0;
 #pragma unroll
-    for (int u = 0; u < kExPer; ++u) {
-      v[u] = c0 + u < n ? in[c0 + u] : 0;
-      sum += v[u];
-    }
-    int tot;
-    int64_t run = carry + block_exscan(sum, s_w, &tot);
+  for (int u = 0; u < kExPer; ++u)
+    if (c0 + u < n) sum += in[c0 + u];
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    csum[blockIdx.y * gridDim.x + blockIdx.x] = (int64_t)s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+__global__ __launch_bounds__(256) void k_exscan_apply(const int32_t* in0, int32_t* out0,
+                                                      const int32_t* in1, int32_t* out1,
+                                                      int32_t n, const int64_t* csum) {
+  __shared__ int s_w[4];
+  __shared__ int64_t s_o[4];
+  const int32_t* in = blockIdx.y ? in1 : in0;
+  int32_t* out = blockIdx.y ? out1 : out0;
+  const int64_t* cs = csum + blockIdx.y * gridDim.x;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  int64_t o = 0;
+  for (int k = tid; k < b; k += 256) o += cs[k];
+  for (int off = 32; off > 0; off >>= 1) o += __shfl_xor(o, off);
+  if (lane_id() == 0) s_o[tid >> 6] = o;
+  const int c0 = b * kExChunk + tid * kExPer;
+  int v[kExPer];
+  int sum = 0;
 #pragma unroll
-    for (int u = 0; u < kExPer; ++u) {
-      if (c0 + u < n) out[c0 + u] = (int32_t)run;
-      run += v[u];
-    }
-    carry += tot;
+  for (int u = 0; u < kExPer; ++u) {
+    v[u] = c0 + u < n ? in[c0 + u] : 0;
+    sum += v[u];
   }
-  if (threadIdx.x == 0) out[n] = (int32_t)carry;
+  int tot;
+  const int pre = block_exscan(sum, s_w, &tot);  // its barriers publish s_o
+  int64_t run = s_o[0] + s_o[1] + s_o[2] + s_o[3] + pre;
+#pragma unroll
+  for (int u = 0; u < kExPer; ++u) {
+    if (c0 + u < n) out[c0 + u] = (int32_t)run;
+    run += v[u];
+  }
+  if (b == (int)gridDim.x - 1 && tid == 255) out[n] = (int32_t)run;
 }
 
 struct Slot {
@@ -2198,8 +2225,14 @@ hipError_t launch_adjust_count(const StepArgs& a, const double* target, uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_exscan(const int32_t* in, int32_t* out, int32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_exscan, dim3(1), dim3(1024), 0, s, in, out, n);
+int exscan_chunks(int n) { return (n + kExChunk - 1) / kExChunk; }
+
+hipError_t launch_exscan2(const int32_t* in0, int32_t* out0, const int32_t* in1,
+                          int32_t* out1, int32_t n, int64_t* csum, hipStream_t s) {
+  const dim3 grid(std::max(1, exscan_chunks(n)), 2);
+  hipLaunchKernelGGL(k_exscan_reduce, grid, dim3(256), 0, s, in0, in1, n, csum);
+  hipLaunchKernelGGL(k_exscan_apply, grid, dim3(256), 0, s, in0, out0, in1, out1, n,
+                     (const int64_t*)csum);
   return hipGetLastError();
 }
 
