@@ -728,17 +728,27 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // lane; the Philox words of a chunk of their candidates are drawn beforehand
 // by all lanes together.  Larger cells run in parallel rounds.  Both give the
 // order of the sequential algorithm exactly.
+//
+// cw: room for kCandChunk uint4 + kCandChunk words (5 kCandChunk uint32) in
+// which the large cells' candidates keep the words an accepted collision
+// uses, drawn with the pair; null: an accepted candidate draws them in its
+// round.
 template <class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, int nc, int c_lo, uint32_t step, int iu,
-                                     double my_vol, bool vol_mine) {
+                                     double my_vol, bool vol_mine, uint4* cw) {
+  uint32_t* cphi = (uint32_t*)(cw + kCandChunk);
   // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
   // (nc <= group_cells <= 4 * blockDim)
   const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
   const int cb = threadIdx.x * per, ce = min(nc, cb + per);
+  // (loops over u with constant bounds keep ks, kg and obs in registers)
   int ks[4] = {0, 0, 0, 0}, kg[4] = {0, 0, 0, 0};
   int tsum_s = 0, tsum_g = 0;
-  for (int c = cb; c < ce; ++c) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cb + u;
+    if (c >= ce) break;
     const int N = S.start[c + 1] - S.start[c];
     int k = 0;
     if (N >= 2) {
@@ -747,18 +757,21 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       const double vol = vol_mine && c == (int)threadIdx.x ? my_vol : a.cvol[c_lo + c];
       k = iround(ncand_mean(N, I.weight, (double)S.sgm[c], I.dt, vol), r.x);
     }
-    if (N <= a.seq_max) ks[c - cb] = k; else kg[c - cb] = k;
-    tsum_s += ks[c - cb];
-    tsum_g += kg[c - cb];
+    if (N <= a.seq_max) ks[u] = k; else kg[u] = k;
+    tsum_s += ks[u];
+    tsum_g += kg[u];
   }
   int KS, KG;
   int run_s = block_exscan(tsum_s, S.wsum, &KS);
   int run_g = block_exscan(tsum_g, S.wsum, &KG);
-  for (int c = cb; c < ce; ++c) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cb + u;
+    if (c >= ce) break;
     S.soff[c] = run_s;
     S.coff[c] = run_g;
-    run_s += ks[c - cb];
-    run_g += kg[c - cb];
+    run_s += ks[u];
+    run_g += kg[u];
   }
   if (threadIdx.x == 0) {
     S.soff[nc] = KS;
@@ -797,7 +810,10 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       w[1] = r1;
     }
     __syncthreads();
-    for (int c = sb; c < se; ++c) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = sb + u;
+      if (c >= se) break;
       const int k0 = max(S.soff[c], kb), k1 = min(S.soff[c + 1], kb + kc);
       if (k0 >= k1) continue;
       const InstParam& I = a.params[iu];
@@ -810,7 +826,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         float4 va = P.ld(i), vb = P.ld(j);
         float sg, g2;
         const bool acc = vhs_accept(I, sgm, w0.y, va, vb, &sg, &g2);
-        obs[c - sb] = fmaxf(obs[c - sb], sg);
+        obs[u] = fmaxf(obs[u], sg);
         ++l_cand;
         l_sat += sg > sgm;
         if (acc) {
@@ -823,7 +839,9 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     }
     __syncthreads();
   }
-  for (int c = sb; c < se; ++c) atomicMax(&S.obs[c], __float_as_uint(obs[c - sb]));
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (sb + u < se) atomicMax(&S.obs[sb + u], __float_as_uint(obs[u]));
   // ---- large cells: candidates staged in chunks and executed in rounds; a
   // candidate runs once it is the earliest pending candidate of both its
   // particles -------------------------------------------------------------------
@@ -836,7 +854,8 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       const int kk = k - S.coff[c];
       const int N = S.start[c + 1] - S.start[c];
       const InstParam& I = a.params[iu];
-      const uint4 r = draw(I, (uint32_t)(c_lo + c - I.cell0), step, TAG_COLL, 3u * (uint32_t)kk);
+      const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+      const uint4 r = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk);
       int i = (int)pick(r.x, (uint32_t)N);
       int j = (int)pick(r.y, (uint32_t)(N - 1));
       j += (j >= i);
@@ -846,6 +865,10 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       S.w2[q] = r.z;
       S.w3[q] = r.w;
       S.pend[q] = 1;
+      if (cw) {
+        cw[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+        cphi[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
+      }
     }
     __syncthreads();
     for (;;) {
@@ -879,11 +902,18 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         ++l_cand;
         l_sat += sg > S.sgm[c];
         if (acc) {
-          const int kk = kb + q - S.coff[c];
-          const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
-          const uint4 r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
-          const uint4 r2 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u);
-          apply_collision(I, g2, S.w3[q], r1, r2.x, va, vb, &l_inel);
+          uint4 r1;
+          uint32_t w8;
+          if (cw) {
+            r1 = cw[q];
+            w8 = cphi[q];
+          } else {
+            const int kk = kb + q - S.coff[c];
+            const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+            r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+            w8 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
+          }
+          apply_collision(I, g2, S.w3[q], r1, w8, va, vb, &l_inel);
           ++l_acc;
           P.st(i, va);
           P.st(j, vb);
@@ -1266,6 +1296,10 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   LdsStore ls{sv};
   GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
   uint32_t* owner = a.owner + e_lo;  // round owners of the global-memory path
+  // the ordered sources are dead after the gather: the large cells' collision
+  // words go there when it holds a chunk of them (L >= 5 kCandChunk) at a
+  // 16-byte boundary (sord starts at byte 20 L)
+  uint4* cw = (5 * kCandChunk <= L && L % 4 == 0) ? (uint4*)sord : nullptr;
   if (do_collide) {
     // instances are contiguous and increasing in c: one call per instance
     // segment, almost always the whole group
@@ -1280,9 +1314,9 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.obs += c0;
       Sg.inst += c0;
       if (fast)
-        collide_cells(a, Sg, ls, lown, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0);
+        collide_cells(a, Sg, ls, lown, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0, cw);
       else
-        collide_cells(a, Sg, gs, owner, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0);
+        collide_cells(a, Sg, gs, owner, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0, cw);
       c0 = c1;
       if (c0 < nc) __syncthreads();  // the next segment reuses the staging arrays
     }
