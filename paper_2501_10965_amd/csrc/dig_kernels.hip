@@ -844,7 +844,9 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     if (sb + u < se) atomicMax(&S.obs[sb + u], __float_as_uint(obs[u]));
   // ---- large cells: candidates staged in chunks and executed in rounds; a
   // candidate runs once it is the earliest pending candidate of both its
-  // particles -------------------------------------------------------------------
+  // particles.  Ownership keys carry the round, (0xFFFF - r) << 16 | q, so a
+  // key of round r is below every key of earlier rounds: the owner words are
+  // reset once per chunk (in the staging pass), not before every round --------
   const int K = KG;
   for (int kb = 0; kb < K; kb += kCandChunk) {
     const int kc = min(kCandChunk, K - kb);
@@ -861,6 +863,8 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       j += (j >= i);
       S.ci[q] = S.start[c] + i;
       S.cj[q] = S.start[c] + j;
+      owner[S.start[c] + i] = 0xFFFFFFFFu;
+      owner[S.start[c] + j] = 0xFFFFFFFFu;
       S.cc[q] = c;
       S.w2[q] = r.z;
       S.w3[q] = r.w;
@@ -871,24 +875,20 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       }
     }
     __syncthreads();
-    for (;;) {
+    for (uint32_t r = 0;; ++r) {
+      const uint32_t rk = (0xFFFFu - r) << 16;  // r < kCandChunk rounds
       for (int q = threadIdx.x; q < kc; q += blockDim.x)
         if (S.pend[q]) {
-          owner[S.ci[q]] = 0xFFFFFFFFu;
-          owner[S.cj[q]] = 0xFFFFFFFFu;
-        }
-      __syncthreads();
-      for (int q = threadIdx.x; q < kc; q += blockDim.x)
-        if (S.pend[q]) {
-          atomicMin(&owner[S.ci[q]], (uint32_t)q);
-          atomicMin(&owner[S.cj[q]], (uint32_t)q);
+          atomicMin(&owner[S.ci[q]], rk | (uint32_t)q);
+          atomicMin(&owner[S.cj[q]], rk | (uint32_t)q);
         }
       __syncthreads();
       int more = 0;
       for (int q = threadIdx.x; q < kc; q += blockDim.x) {
         if (!S.pend[q]) continue;
         const int i = S.ci[q], j = S.cj[q];
-        if (owner[i] != (uint32_t)q || owner[j] != (uint32_t)q) {
+        const uint32_t key = rk | (uint32_t)q;
+        if (owner[i] != key || owner[j] != key) {
           more = 1;
           continue;
         }
