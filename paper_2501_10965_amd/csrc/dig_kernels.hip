@@ -660,12 +660,6 @@ struct CollideShared {
   float* sgm;   // [Gc]
   uint32_t* obs;  // [Gc]
   int* inst;    // [Gc]
-  int* ci;      // [KC]
-  int* cj;
-  int* cc;
-  uint32_t* w2;
-  uint32_t* w3;
-  uint8_t* pend;
   int* stat;    // [4]
   int* wsum;    // [16]
 };
@@ -847,28 +841,32 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   // particles.  Ownership keys carry the round, (0xFFFF - r) << 16 | q, so a
   // key of round r is below every key of earlier rounds: the owner words are
   // reset once per chunk (in the staging pass), not before every round --------
+  // Thread q keeps candidate q of the chunk in registers (both collide
+  // kernels run kCandChunk or more threads).
   const int K = KG;
+  const int q = threadIdx.x;
   for (int kb = 0; kb < K; kb += kCandChunk) {
     const int kc = min(kCandChunk, K - kb);
-    for (int q = threadIdx.x; q < kc; q += blockDim.x) {
+    bool pend = q < kc;
+    int ci = 0, cj = 0, cc = 0;
+    uint32_t w2 = 0, w3 = 0;
+    if (pend) {
       const int k = kb + q;
-      const int c = floor_index(S.coff, nc + 1, k);
-      const int kk = k - S.coff[c];
-      const int N = S.start[c + 1] - S.start[c];
+      cc = floor_index(S.coff, nc + 1, k);
+      const int kk = k - S.coff[cc];
+      const int N = S.start[cc + 1] - S.start[cc];
       const InstParam& I = a.params[iu];
-      const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
+      const uint32_t ent = (uint32_t)(c_lo + cc - I.cell0);
       const uint4 r = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk);
       int i = (int)pick(r.x, (uint32_t)N);
       int j = (int)pick(r.y, (uint32_t)(N - 1));
       j += (j >= i);
-      S.ci[q] = S.start[c] + i;
-      S.cj[q] = S.start[c] + j;
-      owner[S.start[c] + i] = 0xFFFFFFFFu;
-      owner[S.start[c] + j] = 0xFFFFFFFFu;
-      S.cc[q] = c;
-      S.w2[q] = r.z;
-      S.w3[q] = r.w;
-      S.pend[q] = 1;
+      ci = S.start[cc] + i;
+      cj = S.start[cc] + j;
+      owner[ci] = 0xFFFFFFFFu;
+      owner[cj] = 0xFFFFFFFFu;
+      w2 = r.z;
+      w3 = r.w;
       if (cw) {
         cw[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
         cphi[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
@@ -876,47 +874,43 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     }
     __syncthreads();
     for (uint32_t r = 0;; ++r) {
-      const uint32_t rk = (0xFFFFu - r) << 16;  // r < kCandChunk rounds
-      for (int q = threadIdx.x; q < kc; q += blockDim.x)
-        if (S.pend[q]) {
-          atomicMin(&owner[S.ci[q]], rk | (uint32_t)q);
-          atomicMin(&owner[S.cj[q]], rk | (uint32_t)q);
-        }
+      const uint32_t key = ((0xFFFFu - r) << 16) | (uint32_t)q;  // r < kCandChunk rounds
+      if (pend) {
+        atomicMin(&owner[ci], key);
+        atomicMin(&owner[cj], key);
+      }
       __syncthreads();
       int more = 0;
-      for (int q = threadIdx.x; q < kc; q += blockDim.x) {
-        if (!S.pend[q]) continue;
-        const int i = S.ci[q], j = S.cj[q];
-        const uint32_t key = rk | (uint32_t)q;
-        if (owner[i] != key || owner[j] != key) {
+      if (pend) {
+        if (owner[ci] != key || owner[cj] != key) {
           more = 1;
-          continue;
-        }
-        S.pend[q] = 0;
-        const int c = S.cc[q];
-        const InstParam& I = a.params[iu];
-        float4 va = P.ld(i), vb = P.ld(j);
-        float sg, g2;
-        const bool acc = vhs_accept(I, S.sgm[c], S.w2[q], va, vb, &sg, &g2);
-        atomicMax(&S.obs[c], __float_as_uint(sg));
-        ++l_cand;
-        l_sat += sg > S.sgm[c];
-        if (acc) {
-          uint4 r1;
-          uint32_t w8;
-          if (cw) {
-            r1 = cw[q];
-            w8 = cphi[q];
-          } else {
-            const int kk = kb + q - S.coff[c];
-            const uint32_t ent = (uint32_t)(c_lo + c - I.cell0);
-            r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
-            w8 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
+        } else {
+          pend = false;
+          const InstParam& I = a.params[iu];
+          float4 va = P.ld(ci), vb = P.ld(cj);
+          float sg, g2;
+          const float sgm = S.sgm[cc];
+          const bool acc = vhs_accept(I, sgm, w2, va, vb, &sg, &g2);
+          atomicMax(&S.obs[cc], __float_as_uint(sg));
+          ++l_cand;
+          l_sat += sg > sgm;
+          if (acc) {
+            uint4 r1;
+            uint32_t w8;
+            if (cw) {
+              r1 = cw[q];
+              w8 = cphi[q];
+            } else {
+              const int kk = kb + q - S.coff[cc];
+              const uint32_t ent = (uint32_t)(c_lo + cc - I.cell0);
+              r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+              w8 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
+            }
+            apply_collision(I, g2, w3, r1, w8, va, vb, &l_inel);
+            ++l_acc;
+            P.st(ci, va);
+            P.st(cj, vb);
           }
-          apply_collision(I, g2, S.w3[q], r1, w8, va, vb, &l_inel);
-          ++l_acc;
-          P.st(i, va);
-          P.st(j, vb);
         }
       }
       if (!__syncthreads_or(more)) break;
@@ -1164,14 +1158,8 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   S.sgm = (float*)p;                    p += sizeof(float) * Gc;
   S.obs = (uint32_t*)p;                 p += sizeof(uint32_t) * Gc;
   S.inst = (int*)p;                     p += sizeof(int) * Gc;
-  S.ci = (int*)p;                       p += sizeof(int) * kCandChunk;
-  S.cj = (int*)p;                       p += sizeof(int) * kCandChunk;
-  S.cc = (int*)p;                       p += sizeof(int) * kCandChunk;
-  S.w2 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
-  S.w3 = (uint32_t*)p;                  p += sizeof(uint32_t) * kCandChunk;
   S.stat = (int*)p;                     p += sizeof(int) * 4;
   S.wsum = (int*)p;                     p += sizeof(int) * 16;
-  S.pend = (uint8_t*)p;
 
   const int e_lo = a.start[c_lo];
   const int ng = a.start[c_hi] - e_lo;
@@ -1426,6 +1414,8 @@ void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
 // step alone and the others exit at once.
 constexpr int kBigThreads = 256;
 constexpr int kBigGrid = 768;
+static_assert(kCandChunk <= kCollideThreads && kCandChunk <= kBigThreads,
+              "a collision round keeps one candidate per thread");
 __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_collide,
                                                              int do_sample, int end_step) {
   const int nbig = __builtin_amdgcn_readfirstlane((int)*a.big_count);
@@ -2112,12 +2102,10 @@ int64_t group_launch(const StepArgs& a) {
 size_t collide_lds_bytes(int lds_particles, int group_cells) {
   // velocity stage (holding the ordering tables before the gather), round
   // owners and ordered sources per particle (holding the candidate words
-  // after it); per-cell offsets and data; candidate staging; statistics and
-  // scan slots
+  // after it); per-cell offsets and data; statistics and scan slots
   return sizeof(float4) * lds_particles + 2 * sizeof(uint32_t) * lds_particles +
          sizeof(int) * 3 * (group_cells + 1) +
-         (sizeof(float) + 2 * sizeof(int)) * group_cells + (5 * sizeof(int) + 1) * kCandChunk +
-         sizeof(int) * 20 + 16;
+         (sizeof(float) + 2 * sizeof(int)) * group_cells + sizeof(int) * 20 + 16;
 }
 
 int big_run_slots(int lds_big, int group_cells) {
