@@ -356,8 +356,8 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
   unsigned long long todo = __ballot(keep);
   int my_leader = 0, in_run = 0, run_len = 0;
   while (todo) {
-    const int leader = __ffsll(todo) - 1;
-    const int lc = __shfl(cell, leader);
+    const int leader = __ffsll(todo) - 1;  // wave-uniform: read the lane directly
+    const int lc = __builtin_amdgcn_readlane(cell, leader);
     const unsigned long long m = __ballot(keep && cell == lc);
     if (keep && cell == lc) {
       my_leader = leader;
@@ -374,10 +374,12 @@ __global__ __launch_bounds__(256) void k_move(StepArgs a) {
     a.rank[p] = base + in_run;
   }
   // wall-hit and removal statistics: one atomic per wave into a spread slot
-  int hsum = hits_here;
-  for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
-  if (lane_id() == 0 && hsum)
-    atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_HITS], (unsigned long long)hsum);
+  if (__ballot(hits_here != 0)) {  // most waves have no wall hit
+    int hsum = hits_here;
+    for (int off = 32; off > 0; off >>= 1) hsum += __shfl_xor(hsum, off);
+    if (lane_id() == 0)
+      atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_HITS], (unsigned long long)hsum);
+  }
   const int ngone = __popcll(__ballot(gone));
   if (lane_id() == 0 && ngone)
     atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + ST_REMOVED], (unsigned long long)ngone);
