@@ -332,7 +332,7 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
 }
 
 // Free flight, cell index and reservation of a slot in the destination cell.
-__global__ __launch_bounds__(256) void k_move(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_move(StepArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = a.ctr->n;
   const uint32_t step = (uint32_t)a.ctr->step;
