@@ -43,7 +43,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
-  size_t gfirst, inst_pstart, params, owner, newcount, ccount, newstart, cstart, bsum, lastcnt,
+  size_t gfirst, inst_pstart, params, newcount, ccount, newstart, cstart, bsum, lastcnt,
       xsum, stats, rf2, dir, inj_off, done, big_list, big_count;
   int64_t gfirst_len;
 };
@@ -198,7 +198,6 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->gfirst = take(4 * I->gfirst_len);
   I->inst_pstart = take(8 * (n_inst + 1));
   I->params = take(sizeof(InstParam) * n_inst);
-  I->owner = take(4 * cap);
   I->newcount = take(4 * C);
   I->ccount = take(4 * C);
   I->newstart = take(4 * (C + 1));
@@ -355,7 +354,6 @@ StepArgs args(const dig_ctx* c) {
   a.big_count = (uint32_t*)(w + c->I.big_count);
   a.lds_big = c->Lbig;
   a.big_runs = big_run_slots(c->Lbig, c->Gc);
-  a.owner = (uint32_t*)(w + c->I.owner);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);
   a.n_inst = c->n_inst;

@@ -96,7 +96,6 @@ struct StepArgs {
   int64_t* inst_pstart;
   int64_t* bsum;       // chunk sums of the cell scan
   int32_t* lastcnt;    // last count of each scan chunk
-  uint32_t* owner;
   unsigned long long* stats;  // [kStatSlots][ST_N]
   const InstParam* params;
   dig_counters* ctr;

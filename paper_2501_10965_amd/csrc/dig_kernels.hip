@@ -731,8 +731,9 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // round.
 template <class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
-                                     uint32_t* owner, int nc, int c_lo, uint32_t step, int iu,
-                                     double my_vol, bool vol_mine, uint4* cw) {
+                                     uint32_t* owner, uint32_t omask, int nc, int c_lo,
+                                     uint32_t step, int iu, double my_vol, bool vol_mine,
+                                     uint4* cw) {
   uint32_t* cphi = (uint32_t*)(cw + kCandChunk);
   // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
   // (nc <= group_cells <= 4 * blockDim)
@@ -842,7 +843,10 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   // candidate runs once it is the earliest pending candidate of both its
   // particles.  Ownership keys carry the round, (0xFFFF - r) << 16 | q, so a
   // key of round r is below every key of earlier rounds: the owner words are
-  // reset once per chunk (in the staging pass), not before every round --------
+  // reset once per chunk (in the staging pass), not before every round.
+  // Particle e owns word e & omask: a shared word only delays the later
+  // candidate by a round (the earliest pending one always holds both of its
+  // words), so a table smaller than the group is safe -------------------------
   // Thread q keeps candidate q of the chunk in registers (both collide
   // kernels run kCandChunk or more threads).
   const int K = KG;
@@ -865,8 +869,8 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       j += (j >= i);
       ci = S.start[cc] + i;
       cj = S.start[cc] + j;
-      owner[ci] = 0xFFFFFFFFu;
-      owner[cj] = 0xFFFFFFFFu;
+      owner[(uint32_t)ci & omask] = 0xFFFFFFFFu;
+      owner[(uint32_t)cj & omask] = 0xFFFFFFFFu;
       w2 = r.z;
       w3 = r.w;
       if (cw) {
@@ -877,14 +881,15 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     __syncthreads();
     for (uint32_t r = 0;; ++r) {
       const uint32_t key = ((0xFFFFu - r) << 16) | (uint32_t)q;  // r < kCandChunk rounds
+      const uint32_t oi = (uint32_t)ci & omask, oj = (uint32_t)cj & omask;
       if (pend) {
-        atomicMin(&owner[ci], key);
-        atomicMin(&owner[cj], key);
+        atomicMin(&owner[oi], key);
+        atomicMin(&owner[oj], key);
       }
       __syncthreads();
       int more = 0;
       if (pend) {
-        if (owner[ci] != key || owner[cj] != key) {
+        if (owner[oi] != key || owner[oj] != key) {
           more = 1;
         } else {
           pend = false;
@@ -1285,7 +1290,9 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   __syncthreads();
   LdsStore ls{sv};
   GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
-  uint32_t* owner = a.owner + e_lo;  // round owners of the global-memory path
+  // round owners of a group collided in global memory: the velocity stage,
+  // unused by such a group, as a table of the largest power of two words
+  const uint32_t gmask = (1u << (31 - __clz(4 * L))) - 1u;
   // the ordered sources are dead after the gather: the large cells' collision
   // words go there when it holds a chunk of them (L >= 5 kCandChunk) at a
   // 16-byte boundary (sord starts at byte 20 L)
@@ -1304,9 +1311,11 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.obs += c0;
       Sg.inst += c0;
       if (fast)
-        collide_cells(a, Sg, ls, lown, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0, cw);
+        collide_cells(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
+                      c0 == 0, cw);
       else
-        collide_cells(a, Sg, gs, owner, c1 - c0, c_lo + c0, step, iu, my_vol, c0 == 0, cw);
+        collide_cells(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu, my_vol,
+                      c0 == 0, cw);
       c0 = c1;
       if (c0 < nc) __syncthreads();  // the next segment reuses the staging arrays
     }

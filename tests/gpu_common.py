@@ -38,7 +38,9 @@ def gpu_buffer(sim: DSMC, b: int, n: int) -> dict:
 def oracle_state(w, arrays, start, sgmax, step, cap=None, next_id=None):
     n = len(arrays["x"])
     s = oracle.State(w, cap or max(n, 1) * 2 + 64)
-    s.load(arrays["x"], arrays["y"], arrays["vx"], arrays["vy"], arrays["vz"], arrays["er"],
+    # a 1D state has no y: the GPU buffer holds whatever was there before
+    y = arrays["y"] if w["dim"] == 2 else np.zeros(n, np.float32)
+    s.load(arrays["x"], y, arrays["vx"], arrays["vy"], arrays["vz"], arrays["er"],
            arrays["id"], start=start, sgmax=sgmax, step=step, next_id=next_id)
     return s
 
