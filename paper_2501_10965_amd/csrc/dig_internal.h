@@ -17,6 +17,7 @@ enum : uint32_t {
 constexpr int kMaxHits = 8;      // wall events per particle and step
 constexpr int kRunMax = 4096;    // run table of the sort kernel
 constexpr int kCandChunk = 128;  // candidates staged per round set
+constexpr int kRoundChunkMax = 256;  // large-cell round sets where the stage holds their words
 constexpr int kSeqMaxDefault = 192;  // cells up to this size: one lane, candidates in order
 constexpr int kMinGroupParticles = 256;
 // Statistics counters are spread over kStatSlots cache lines (slot = block

@@ -725,16 +725,16 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // by all lanes together.  Larger cells run in parallel rounds.  Both give the
 // order of the sequential algorithm exactly.
 //
-// cw: room for kCandChunk uint4 + kCandChunk words (5 kCandChunk uint32) in
-// which the large cells' candidates keep the words an accepted collision
-// uses, drawn with the pair; null: an accepted candidate draws them in its
-// round.
+// rchunk: candidates of the large cells per chunk of rounds (at most the
+// thread count); cw: room for rchunk uint4 + rchunk words (5 rchunk uint32)
+// in which they keep the words an accepted collision uses, drawn with the
+// pair; null: an accepted candidate draws them in its round.
 template <class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, uint32_t omask, int nc, int c_lo,
                                      uint32_t step, int iu, double my_vol, bool vol_mine,
-                                     uint4* cw) {
-  uint32_t* cphi = (uint32_t*)(cw + kCandChunk);
+                                     uint4* cw, int rchunk) {
+  uint32_t* cphi = (uint32_t*)(cw + rchunk);
   // candidate counts, FP64 Iround as in the oracle; cells cb..cb+per-1 per thread
   // (nc <= group_cells <= 4 * blockDim)
   const int per = (nc + (int)blockDim.x - 1) / (int)blockDim.x;
@@ -848,11 +848,11 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   // candidate by a round (the earliest pending one always holds both of its
   // words), so a table smaller than the group is safe -------------------------
   // Thread q keeps candidate q of the chunk in registers (both collide
-  // kernels run kCandChunk or more threads).
+  // kernels run kRoundChunkMax threads).
   const int K = KG;
   const int q = threadIdx.x;
-  for (int kb = 0; kb < K; kb += kCandChunk) {
-    const int kc = min(kCandChunk, K - kb);
+  for (int kb = 0; kb < K; kb += rchunk) {
+    const int kc = min(rchunk, K - kb);
     bool pend = q < kc;
     int ci = 0, cj = 0, cc = 0;
     uint32_t w2 = 0, w3 = 0;
@@ -880,7 +880,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
     }
     __syncthreads();
     for (uint32_t r = 0;; ++r) {
-      const uint32_t key = ((0xFFFFu - r) << 16) | (uint32_t)q;  // r < kCandChunk rounds
+      const uint32_t key = ((0xFFFFu - r) << 16) | (uint32_t)q;  // r < rchunk rounds
       const uint32_t oi = (uint32_t)ci & omask, oj = (uint32_t)cj & omask;
       if (pend) {
         atomicMin(&owner[oi], key);
@@ -1294,9 +1294,12 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
   // unused by such a group, as a table of the largest power of two words
   const uint32_t gmask = (1u << (31 - __clz(4 * L))) - 1u;
   // the ordered sources are dead after the gather: the large cells' collision
-  // words go there when it holds a chunk of them (L >= 5 kCandChunk) at a
-  // 16-byte boundary (sord starts at byte 20 L)
-  uint4* cw = (5 * kCandChunk <= L && L % 4 == 0) ? (uint4*)sord : nullptr;
+  // words go there when it holds a chunk of them (L >= 5 rchunk) at a 16-byte
+  // boundary (sord starts at byte 20 L); chunks of kRoundChunkMax candidates
+  // where it holds that many
+  const bool al = L % 4 == 0;
+  const int rchunk = (al && 5 * kRoundChunkMax <= L) ? kRoundChunkMax : kCandChunk;
+  uint4* cw = (al && 5 * rchunk <= L) ? (uint4*)sord : nullptr;
   if (do_collide) {
     // instances are contiguous and increasing in c: one call per instance
     // segment, almost always the whole group
@@ -1312,10 +1315,10 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.inst += c0;
       if (fast)
         collide_cells(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
-                      c0 == 0, cw);
+                      c0 == 0, cw, rchunk);
       else
         collide_cells(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu, my_vol,
-                      c0 == 0, cw);
+                      c0 == 0, cw, rchunk);
       c0 = c1;
       if (c0 < nc) __syncthreads();  // the next segment reuses the staging arrays
     }
@@ -1425,7 +1428,8 @@ void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
 // step alone and the others exit at once.
 constexpr int kBigThreads = 256;
 constexpr int kBigGrid = 768;
-static_assert(kCandChunk <= kCollideThreads && kCandChunk <= kBigThreads,
+static_assert(kRoundChunkMax == kCollideThreads && kRoundChunkMax == kBigThreads &&
+                  kCandChunk <= kRoundChunkMax,
               "a collision round keeps one candidate per thread");
 __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_collide,
                                                              int do_sample, int end_step) {
