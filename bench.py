@@ -136,6 +136,8 @@ def run_cavity(args):
     w = wl.cavity_2d(seed=2001)
     ns = w["ns"]
     sim = DSMC(w, group_particles=args.group_particles, group_cells=args.group_cells)
+    if args.seq_max >= 0:
+        sim.tuning(seq_max=args.seq_max)
     sim.init()
     A = default_A(w["omega"])
     state = {"step": 0, "cycle": 0, "n": sim.counters()["n"]}
@@ -516,6 +518,9 @@ def main():
     ap.add_argument("--synth-iters", type=int, default=2000)
     ap.add_argument("--group-particles", type=int, default=0)
     ap.add_argument("--group-cells", type=int, default=0)
+    ap.add_argument("--seq-max", type=int, default=-1,
+                    help="cavity: cells up to this size run their candidates on one lane "
+                         "(with --no-autotune; -1 keeps the library default)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
