@@ -139,7 +139,7 @@ int64_t group_launch(const StepArgs& a);
 int scan_blocks(int ncell);
 size_t collide_lds_bytes(int lds_particles, int group_cells);
 // LDS of the oversize-group collide: the stage and everything else
-constexpr size_t kBigLdsBytes = 50 * 1024;
+constexpr size_t kBigLdsBytes = 38 * 1024;
 bool big_stage_fits(int lds_big, int group_cells);
 int big_run_slots(int lds_big, int group_cells);
 hipError_t collide_setup();

@@ -1420,14 +1420,15 @@ void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
 }
 
 // The groups k_collide listed as larger than its stage: a persistent grid of
-// kBigThreads-thread workgroups (three per CU: the stage of lds_big particles
-// takes a third of the CU's LDS), each taking listed groups in turn.  With
+// kBigThreads-thread workgroups (four per CU, as many as its registers allow:
+// most listed groups exceed the stage and collide in global memory, where
+// more groups in flight pay off), each taking listed groups in turn.  With
 // groups listed, every workgroup takes a ticket when done and the last one
 // empties the list and, with end_step, closes the step as k_collide does;
 // with none (the common case at moderate cell sizes) workgroup 0 closes the
 // step alone and the others exit at once.
 constexpr int kBigThreads = 256;
-constexpr int kBigGrid = 768;
+constexpr int kBigGrid = 1024;
 static_assert(kRoundChunkMax == kCollideThreads && kRoundChunkMax == kBigThreads &&
                   kCandChunk <= kRoundChunkMax,
               "a collision round keeps one candidate per thread");
