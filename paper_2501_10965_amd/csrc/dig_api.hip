@@ -1064,12 +1064,12 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
     return DIG_OK;
   };
   st = trial(best, &best.ms_per_step);
-  const int32_t Ts[] = {512, 1024, 2048, 4096};
+  const int32_t Ts[] = {512, 1024, 2048, 4096, 8192};
   const int32_t Gcs[] = {32, 64, 128, 256};
   const int32_t Sqs[] = {0, 64, 128, 192, 384};
   for (int axis = 0; axis < 3 && st == DIG_OK; ++axis) {
     const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : Sqs;
-    const int nv = axis == 2 ? 5 : 4;
+    const int nv = axis == 1 ? 4 : 5;
     const dig_tuning base = best;
     for (int k = 0; k < nv && st == DIG_OK; ++k) {
       dig_tuning t = base;

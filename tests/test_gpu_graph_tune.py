@@ -84,13 +84,13 @@ def test_autotune_is_result_invariant_and_cached(tmp_path):
     a, b = _pair(w)
     cache = str(tmp_path / "tune.txt")
     t = a.autotune(steps_per_trial=2, cache_path=cache)
-    assert t["group_particles"] in (512, 1024, 2048, 4096)
+    assert t["group_particles"] in (512, 1024, 2048, 4096, 8192)
     assert t["group_cells"] in (32, 64, 128, 256)
     assert t["seq_max"] in (0, 64, 128, 192, 384)
     assert t["ms_per_step"] > 0
     assert a.tuning() == {**t, "ms_per_step": 0.0}
     taken = a.counters()["step"]
-    assert taken >= 2 * 14
+    assert taken >= 2 * 15
     # the tuning steps are ordinary steps: the default configuration gives the
     # same state after the same number of steps
     b.step(taken)
