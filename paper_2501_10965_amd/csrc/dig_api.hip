@@ -263,6 +263,14 @@ InstParam make_param(const dig_config& c, int32_t cell0) {
     p.rin = (float)ri;
     p.rout = (float)ro;
     p.dthf = (float)annulus_dtheta(c);
+    // inverse of the face radii r_j = r_in + (r_out - r_in) (q^j - 1) / (q^ny - 1)
+    if (c.q == 1.0) {
+      p.rk = (float)((double)c.ny / (c.r_out - c.r_in));
+      p.rlq = 0.0f;
+    } else {
+      p.rk = (float)((pow(c.q, (double)c.ny) - 1.0) / (c.r_out - c.r_in));
+      p.rlq = (float)(1.0 / log2(c.q));
+    }
     p.vol = annulus_cell_area(c, 0);
     p.bc_type[2] = p.bc_type[3] = DIG_BC_PERIODIC;
     if (c.bc[1].type == DIG_BC_FREESTREAM) {

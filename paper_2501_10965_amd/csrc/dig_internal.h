@@ -42,9 +42,10 @@ struct InstParam {
   double mu0, omega, dx, dy;
   // annulus: FP32 squared radii of the inner and outer circles (rounded from
   // FP64), their radii, the angular width of a cell; freestream reservoir:
-  // outer radius squared, mean particle count per angular sector
+  // outer radius squared, mean particle count per angular sector; the radial
+  // index guess j ~ log2(1 + (r - r_in) rk) rlq (rlq = 0: j ~ (r - r_in) rk)
   float rin2, rout2, rin, rout;
-  float res2, dthf, pad3, pad4;
+  float res2, dthf, rk, rlq;
   double res_mean, rho_inf;
 };
 enum : uint32_t { TAG_INFLOW = 10 };

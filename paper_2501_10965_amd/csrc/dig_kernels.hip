@@ -92,21 +92,24 @@ static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
 }
 
 // ---------------------------------------------------------------------------
-// Annulus cell map.  The radial index compares the FP32 squared radius with
-// the FP32 table of squared face radii; the angular index starts from atan2
-// and is settled by the signs of FP32 cross products with the face
-// directions.  Both are rounded operations without contraction, so the
-// oracle takes the same decisions from the same stored position.
+// Annulus cell map.  The radial index is the largest j with rf2[j] <= r^2
+// (clamped to the ring) for the FP32 squared radius and the FP32 table of
+// squared face radii: a guess from the inverse of the face-radius formula,
+// settled by comparisons with the table (one or two loads instead of a binary
+// search).  The angular index starts from atan2 and is settled by the signs
+// of FP32 cross products with the face directions.  The decisions are rounded
+// comparisons without contraction, so the oracle takes the same ones from the
+// same stored position.
 static __device__ int annulus_cell(const StepArgs& a, const InstParam& I, float x, float y) {
 #pragma clang fp contract(off)
   const float r2 = x * x + y * y;
   const int nr = I.ny, nt = I.nx;
-  int lo = 0, hi = nr - 1;  // largest j with rf2[j] <= r2 (clamped to the ring)
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.rf2[mid] <= r2) lo = mid; else hi = mid - 1;
-  }
-  const int j = lo;
+  const float s = (fsqrt(r2) - I.rin) * I.rk;
+  float gj = I.rlq > 0.0f ? __log2f(1.0f + s) * I.rlq : s;
+  gj = fminf(fmaxf(gj, 0.0f), (float)(nr - 1));  // a NaN guess becomes 0
+  int j = (int)gj;
+  while (j > 0 && a.rf2[j] > r2) --j;
+  while (j < nr - 1 && a.rf2[j + 1] <= r2) ++j;
   float th = atan2f(y, x);
   if (th < 0.0f) th += 6.28318530717958648f;
   int i = (int)(th * (float)nt * 0.15915494309189535f);
