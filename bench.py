@@ -242,7 +242,7 @@ def run_batch(args):
                group_cells=args.group_cells)
     sim.init_batch()
     n = sim.counters()["n"]
-    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
+    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=10)
     graph = 50
     k0 = sim.counters()["step"]
     sim.step(max(args.warmup - k0, 0) // graph * graph + graph, graph=True)
@@ -353,7 +353,7 @@ def run_cylinder(args):
     sim = DSMC(w, cap_factor=1.7, group_particles=args.group_particles,
                group_cells=args.group_cells)
     sim.init()
-    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=3)
+    tuning = None if args.no_autotune else sim.autotune(steps_per_trial=10)
     k0 = sim.counters()["step"]
     sim.step(max(args.warmup - k0, 0), graph=True)
     sim.profile("on")
