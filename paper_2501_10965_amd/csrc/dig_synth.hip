@@ -326,11 +326,9 @@ __global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* wa
                              const double* wall_cfg, unsigned long long* red) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
-  // iteration 1 reads its step from the parity-1 slot
-  if (c == 0) {
-    red[2] = 0x7FF0000000000000ull;
-    red[3] = 0ull;
-  }
+  // iteration 1 reads its step from the parity-1 slot, which the host resets
+  // before this launch (a reset inside it would race with the other blocks'
+  // atomics)
   if (c >= C) return;
   const double rho = m[c];
   const double u[3] = {m[C + c], m[2 * C + c], m[3 * C + c]};
@@ -474,6 +472,11 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
     return DIG_ERR_HIP;
   const int bs = 256, nb = (C + bs - 1) / bs;
   hipLaunchKernelGGL(k_synth_mask_hot, dim3(nb), dim3(bs), 0, s, hot, mask, H, C);
+  // parity-1 reduction slots: dtau (min, from +inf; +inf and 0 have the bit
+  // patterns of the FP64 values) and the change (max, from 0)
+  if (launch_fill_f64((double*)red + 2, 1, INFINITY, s) != hipSuccess ||
+      launch_fill_f64((double*)red + 3, 1, 0.0, s) != hipSuccess)
+    return DIG_ERR_HIP;
   hipLaunchKernelGGL(k_synth_init, dim3(nb), dim3(bs), 0, s, g, m_half, W0, wall,
                      opts->wall_mode, (const double*)dwcfg, red);
   const int check = opts->check_every > 0 ? opts->check_every : 32;

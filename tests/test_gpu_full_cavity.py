@@ -160,3 +160,28 @@ def test_full_size_modification_then_graph_steps(tuned):
     for name in ("start", "sgmax", "acc"):
         np.testing.assert_array_equal(np_(sims[0].array(name)), np_(sims[1].array(name)),
                                       err_msg=name)
+
+
+def test_full_size_dig_cycles_repeat_bit_for_bit():
+    """DIG cycles (50 steps, closure, synthetic solve of 2000 pseudo-time
+    steps, modification) on the full cavity give the same particles on a rerun
+    in fresh device memory and under another launch configuration."""
+    from paper_2501_10965_amd.dig import DIG
+
+    def run(tune):
+        d = DIG(wl.cavity_2d())
+        if tune:
+            d.sim.tuning(*tune)
+        out = []
+        for _ in range(3):
+            d.cycle()
+            out.append((gpu_state(d.sim), d.sim.counters()["n"]))
+        return out
+
+    say("  DIG cycles: default, rerun, other tuning")
+    a = run(None)
+    for other in (run(None), run((512, 128, 0))):
+        for (sa, na), (sb, nb) in zip(a, other):
+            assert na == nb
+            for k in sa:
+                np.testing.assert_array_equal(sa[k], sb[k], err_msg=k)

@@ -41,6 +41,21 @@ def test_synth_matches_oracle_fixed_steps(mode):
     assert abs(g[0].sum() - m[0].sum()) <= 1e-12 * m[0].sum()
 
 
+def test_synth_full_grid_matches_oracle_on_every_call():
+    """The 200 x 200 cavity grid (157 workgroups per launch).  The first
+    pseudo-time step is the minimum of the cells' step bounds over the whole
+    grid, so every call agrees with the oracle, whatever order the workgroups
+    run in."""
+    w, m, hot, mask = _case2d(n=200, seed=5)
+    say("case synth full grid")
+    ref, it, _ = synth.solve(w, m, hot=hot, mask=mask, max_iter=4, tol=0.0, wall_mode="dsmc")
+    args = [torch.tensor(a, device="cuda") for a in (m, hot, mask)]
+    for rep in range(3):
+        out, git, _ = synth_solve(w, *args, max_iter=4, tol=0.0, wall_mode="dsmc")
+        assert git == 4 and it == 4
+        np.testing.assert_allclose(np_(out), ref, rtol=1e-9, atol=1e-12)
+
+
 def test_synth_fourier_converges_to_closed_form():
     w = wl.fourier_1d(nx=32)
     say("case synth fourier")
