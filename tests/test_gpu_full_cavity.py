@@ -15,7 +15,9 @@ every cell is compared, from seeded cell-sorted states:
 * the particle modification toward a per-cell target: counts, ids and order
   exactly, positions within 1e-6, velocities within 2e-6;
 * 50 steps launched as captured graphs equal the same steps launched eagerly,
-  bit for bit."""
+  bit for bit;
+* whole DIG cycles repeat bit for bit in fresh device memory and under another
+  launch configuration."""
 import numpy as np
 import pytest
 import torch
