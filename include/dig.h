@@ -277,7 +277,8 @@ dig_status dsmc_tuning(dig_ctx* ctx, const dig_tuning* in_host, dig_tuning* out_
 
 /* Autotuner for the step kernels: coordinate search over group_particles in
  * {512, 1024, 2048, 4096, 8192}, group_cells in {32, 64, 128, 256} and seq_max in
- * {0, 64, 128, 192, 384}, timing steps_per_trial real steps per candidate with
+ * {0, 64, 128, 192, 384} (two passes over the three axes, each configuration
+ * timed once), timing steps_per_trial real steps per candidate with
  * HIP events on `stream` (one untimed step before each).  The timed steps are
  * ordinary steps of the simulation: the state advances by every step taken,
  * exactly as dsmc_step would advance it, whichever configuration ran them.

@@ -1075,17 +1075,30 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
   const int32_t Ts[] = {512, 1024, 2048, 4096, 8192};
   const int32_t Gcs[] = {32, 64, 128, 256};
   const int32_t Sqs[] = {0, 64, 128, 192, 384};
-  for (int axis = 0; axis < 3 && st == DIG_OK; ++axis) {
-    const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : Sqs;
-    const int nv = axis == 1 ? 4 : 5;
-    const dig_tuning base = best;
-    for (int k = 0; k < nv && st == DIG_OK; ++k) {
-      dig_tuning t = base;
-      int32_t* field = axis == 0 ? &t.group_particles : axis == 1 ? &t.group_cells : &t.seq_max;
-      if (*field == vals[k]) continue;
-      *field = vals[k];
-      st = trial(t, &t.ms_per_step);
-      if (st == DIG_OK && t.ms_per_step < best.ms_per_step) best = t;
+  // two passes over the three axes (the best group size can depend on the
+  // other two); a configuration is timed once
+  std::vector<dig_tuning> tried{best};
+  auto seen = [&](const dig_tuning& t) {
+    for (const dig_tuning& u : tried)
+      if (u.group_particles == t.group_particles && u.group_cells == t.group_cells &&
+          u.seq_max == t.seq_max)
+        return true;
+    return false;
+  };
+  for (int pass = 0; pass < 2 && st == DIG_OK; ++pass) {
+    for (int axis = 0; axis < 3 && st == DIG_OK; ++axis) {
+      const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : Sqs;
+      const int nv = axis == 1 ? 4 : 5;
+      const dig_tuning base = best;
+      for (int k = 0; k < nv && st == DIG_OK; ++k) {
+        dig_tuning t = base;
+        int32_t* field = axis == 0 ? &t.group_particles : axis == 1 ? &t.group_cells : &t.seq_max;
+        *field = vals[k];
+        if (seen(t)) continue;
+        tried.push_back(t);
+        st = trial(t, &t.ms_per_step);
+        if (st == DIG_OK && t.ms_per_step < best.ms_per_step) best = t;
+      }
     }
   }
   (void)hipEventDestroy(e0);
