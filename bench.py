@@ -524,7 +524,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the DSMC domain decomposition "
+        print("bench.py: the library runs on one GPU only (the DSMC domain decomposition "
               "across GPUs is a design, not an implementation); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
