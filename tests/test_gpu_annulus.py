@@ -1,7 +1,8 @@
 """Flow past a cylinder (annulus with open outer boundary) on the GPU vs the
 FP64 oracle, stage by stage from a common injected state: inflow counts and
 particles, free flight with circular walls, the single-precision polar cell
-map (bit-exact on the GPU's stored positions, including removal), stable sort
+map (bit-exact on the GPU's stored positions, including removal, and for
+particles on and next to every face radius), stable sort
 and compaction, collisions and per-cell-area sampling; then the initial state,
 a closed annulus in equilibrium, and the full-size cylinder (500 x 400 cells,
 50M particles) for a few graph-captured steps."""
@@ -94,6 +95,41 @@ def test_annulus_stage_parity(mach, outer):
     gfld = np_(sim.sample("instant"))
     scale = np.abs(ofld).max(axis=1, keepdims=True) + 1e-300
     assert np.all(np.abs(gfld - ofld) <= 1e-9 * scale)
+
+
+def test_annulus_cell_map_at_face_radii():
+    """Particles at rest on every radial face radius and one float step either
+    side of it (also just inside the inner circle and outside the outer one),
+    at the angular face directions and between them: the cell map, which
+    guesses the radial index from the face-radius formula and settles it on
+    the table of squared face radii, matches the oracle's exactly."""
+    w = small(mach=0.0, outer="diffuse")
+    nr, nt = w["ny"], w["nx"]
+    rs = []
+    for j in range(nr + 1):
+        r = np.float32(oracle.annulus_face(w, j))
+        rs += [np.nextafter(r, np.float32(0)), r, np.nextafter(r, np.float32(100))]
+    rs = np.array(rs, np.float32)
+    th = np.concatenate([np.arange(nt), np.arange(nt) + 0.37]) * (2 * np.pi / nt)
+    R, T = np.meshgrid(rs.astype(np.float64), th)
+    x = (R * np.cos(T)).astype(np.float32).ravel()
+    y = (R * np.sin(T)).astype(np.float32).ravel()
+    n = len(x)
+    nc = nr * nt
+    z = np.zeros(n, np.float32)
+    arr = dict(x=x, y=y, vx=z, vy=z, vz=z, er=np.ones(n, np.float32),
+               id=np.arange(n, dtype=np.uint32))
+    sg = np.full(nc, oracle.sgmax_default(w), np.float32)
+    cell = oracle_state(w, arr, np.zeros(nc + 1, np.int64), sg, 3).cells()
+    say(f"case annulus faces: {n} particles")
+    order = np.argsort(cell, kind="stable")
+    arr = {k: v[order] for k, v in arr.items()}
+    start = np.concatenate([[0], np.cumsum(np.bincount(cell, minlength=nc))])
+    sim = DSMC(w, capacity=2 * n + 1000)
+    sim.inject(arr, start, step=3, next_id=n, sgmax=sg)
+    sim.stage(STAGES["move"] | STAGES["sort"])
+    np.testing.assert_array_equal(np_(sim.array("cell"))[:n], cell[order])
+    np.testing.assert_array_equal(np_(sim.array("start")), start)
 
 
 def test_annulus_init_matches_oracle():
