@@ -81,7 +81,8 @@ typedef struct {
   int32_t geometry;     /* DIG_GEOM_* */
   double r_in, r_out, q;  /* annulus radii and radial stretch ratio (q >= 1) */
   double kn;            /* Knudsen number (Section 2) */
-  double omega, alpha;  /* viscosity index in [0.5, 1]; alpha must be 1 */
+  double omega, alpha;  /* viscosity index in [0.5, 1]; scattering alpha in [1, 2]
+                          (1: VHS, isotropic; otherwise VSS) */
   int32_t dr;           /* rotational degrees of freedom; must be 2 */
   double zrot;          /* rotational collision number Z; P_inelastic <= 1 */
   double dt, weight;    /* time step; particle weight N_eff (mass per particle) */

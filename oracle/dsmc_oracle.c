@@ -69,11 +69,13 @@ double orc_mu0(const orc_config* c) { return c->kn * sqrt(2.0 / M_PI); }
  * 30 p / ((5 - 2w)(7 - 2w) mu), which ties the collision rate to the
  * viscosity mu0 T^omega above. */
 double orc_csigma(const orc_config* c) {
-  double w = c->omega;
+  double w = c->omega, a = c->alpha;
   double num = 15.0 * M_PI;
   double den = sqrt(2.0) * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) * pow(4.0, 1.0 - w) *
                tgamma(2.5 - w) * c->kn;
-  return num / den;
+  /* VSS: the same viscosity takes a cross-section (a + 1)(a + 2) / (6 a)
+   * times the VHS one (collision frequency 5 (a+1)(a+2) p / (a (5-2w)(7-2w) mu)) */
+  return num / den * ((a + 1.0) * (a + 2.0) / (6.0 * a));
 }
 
 /* Fraction of inelastic collisions, equation P_inelastic (Section 2.2). */
@@ -410,8 +412,11 @@ void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int6
 
 /* ------------------------------------------------------------------------ */
 /* Collisions in every cell (Section 2.2): no-time-counter candidate pairs,
- * VHS acceptance, Borgnakke-Larsen exchange with double relaxation, isotropic
- * scattering (VSS with alpha = 1).  The state arrays are in cell order. */
+ * VHS acceptance, Borgnakke-Larsen exchange with double relaxation, then
+ * scattering: isotropic for alpha = 1, otherwise the VSS deflection
+ * cos(chi) = 2 u^(1/alpha) - 1 from the pre-collision relative velocity with a
+ * uniform azimuth (Bird's rotation of the relative velocity).  The state
+ * arrays are in cell order. */
 void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
                  double* vy, double* vz, double* er, float* sgmax, uint32_t step,
                  orc_collide_stats* st, double* obs_out, double* margin_out) {
@@ -472,10 +477,32 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
         if (st) st->inelastic += 1;
       }
       double gp = 2.0 * sqrt(et);
-      double ct = 2.0 * orc_u01(r1[3]) - 1.0;
-      double stt = sqrt(1.0 - ct * ct);
-      double ph = 2.0 * M_PI * orc_u01(r2[0]);
-      double nx = ct, ny = stt * cos(ph), nz = stt * sin(ph);
+      double nx, ny, nz;
+      if (c->alpha == 1.0) {
+        double ct = 2.0 * orc_u01(r1[3]) - 1.0;
+        double stt = sqrt(1.0 - ct * ct);
+        double ph = 2.0 * M_PI * orc_u01(r2[0]);
+        nx = ct;
+        ny = stt * cos(ph);
+        nz = stt * sin(ph);
+      } else {
+        double gm = sqrt(g2);
+        double ux = gxv / gm, uy = gyv / gm, uz = gzv / gm;
+        double cc = 2.0 * pow(orc_u01(r1[3]), 1.0 / c->alpha) - 1.0;
+        double sc = sqrt(fmax(0.0, 1.0 - cc * cc));
+        double eps = 2.0 * M_PI * orc_u01(r2[0]);
+        double se = sin(eps), ce = cos(eps);
+        double pp = sqrt(uy * uy + uz * uz);
+        if (pp > 1e-6) {
+          nx = cc * ux + sc * se * pp;
+          ny = cc * uy + sc * (ce * uz - ux * uy * se) / pp;
+          nz = cc * uz - sc * (ce * uy + ux * uz * se) / pp;
+        } else { /* relative velocity along x: rotate about x from y */
+          nx = cc * ux;
+          ny = sc * ce;
+          nz = sc * se;
+        }
+      }
       double cx = 0.5 * (vx[i] + vx[j]), cy = 0.5 * (vy[i] + vy[j]), cz = 0.5 * (vz[i] + vz[j]);
       vx[i] = cx + 0.5 * gp * nx;
       vy[i] = cy + 0.5 * gp * ny;

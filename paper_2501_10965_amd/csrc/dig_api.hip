@@ -49,13 +49,15 @@ struct Internal {
 };
 
 // Gas constants in paper units (Section 2): mu0 from the Knudsen number, the
-// VHS constant that gives the collision frequency 30 p / ((5-2w)(7-2w) mu),
-// and P_inelastic of equation P_inelastic.
+// cross-section constant that gives the collision frequency
+// 5 (a+1)(a+2) p / (a (5-2w)(7-2w) mu) (30 p / ((5-2w)(7-2w) mu) for VHS,
+// a = 1), and P_inelastic of equation P_inelastic.
 double vhs_constant(const dig_config& c) {
-  const double w = c.omega;
+  const double w = c.omega, a = c.alpha;
   return 15.0 * M_PI /
          (sqrt(2.0) * (5.0 - 2.0 * w) * (7.0 - 2.0 * w) * pow(4.0, 1.0 - w) * tgamma(2.5 - w) *
-          c.kn);
+          c.kn) *
+         ((a + 1.0) * (a + 2.0) / (6.0 * a));
 }
 double p_inelastic(const dig_config& c) {
   const double w = c.omega, a = c.alpha;
@@ -133,7 +135,8 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
     if (!(c.kn > 0.0)) return fail(DIG_ERR_INVALID, at + "Kn must be > 0");
     if (!(c.omega >= 0.5 && c.omega <= 1.0))
       return fail(DIG_ERR_INVALID, at + "omega must lie in [0.5, 1]");
-    if (c.alpha != 1.0) return fail(DIG_ERR_INVALID, at + "alpha must be 1 (VHS scattering)");
+    if (!(c.alpha >= 1.0 && c.alpha <= 2.0))
+      return fail(DIG_ERR_INVALID, at + "alpha must lie in [1, 2] (1: VHS, else VSS)");
     if (c.dr != 2) return fail(DIG_ERR_INVALID, at + "d_r must be 2");
     if (!(c.zrot > 0.0) || p_inelastic(c) > 1.0)
       return fail(DIG_ERR_INVALID, at + "Z must give P_inelastic <= 1");
@@ -250,6 +253,8 @@ InstParam make_param(const dig_config& c, int32_t cell0) {
   p.key1 = (uint32_t)(c.seed >> 32);
   p.inst = c.instance_id;
   p.pin = p_inelastic(c);
+  p.vss = c.alpha != 1.0 ? 1u : 0u;
+  p.ainv = (float)(1.0 / c.alpha);
   p.weight = c.weight;
   p.dt = c.dt;
   p.vol = cell_volume(c);
@@ -361,6 +366,8 @@ StepArgs args(const dig_ctx* c) {
   a.big_list = (int32_t*)(w + c->I.big_list);
   a.big_count = (uint32_t*)(w + c->I.big_count);
   a.lds_big = c->Lbig;
+  a.vss_any = 0;
+  for (const InstParam& q : c->params) a.vss_any |= q.vss ? 1 : 0;
   a.big_runs = big_run_slots(c->Lbig, c->Gc);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);

@@ -47,6 +47,9 @@ struct InstParam {
   float rin2, rout2, rin, rout;
   float res2, dthf, rk, rlq;
   double res_mean, rho_inf;
+  // scattering: isotropic (vss = 0, alpha = 1) or VSS with 1/alpha
+  float ainv;
+  uint32_t vss;
 };
 enum : uint32_t { TAG_INFLOW = 10 };
 
@@ -116,6 +119,7 @@ struct StepArgs {
   int32_t big_runs;     // its run-table capacity
   int32_t* big_list;    // groups too large for the collide's stage, listed by it
   uint32_t* big_count;  // entries in big_list (emptied by k_collide_big)
+  int32_t vss_any;      // some instance scatters with VSS (alpha != 1)
 };
 enum { ST_REMOVED = 5, ST_INJECTED = 6 };
 

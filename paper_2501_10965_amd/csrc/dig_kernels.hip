@@ -685,8 +685,11 @@ static __device__ __forceinline__ bool vhs_accept(const InstParam& I, float sgm,
 
 // Accepted collision: Borgnakke-Larsen exchange for the first then the
 // second particle (double relaxation, tests w3 and r1.y, Beta(1, 5/2 - omega)
-// splits r1.x and r1.z), then isotropic scattering (cos theta from r1.w, phi
-// from w8) that conserves momentum and the total energy.
+// splits r1.x and r1.z), then scattering that conserves momentum and the
+// total energy: isotropic (cos theta from r1.w, phi from w8), or for VSS the
+// deflection cos chi = 2 u^(1/alpha) - 1 (u from r1.w) from the pre-collision
+// relative velocity with azimuth from w8 (Bird's rotation).
+template <bool VSS>
 static __device__ __forceinline__ void apply_collision(const InstParam& I, float g2, uint32_t w3,
                                                        uint4 r1, uint32_t w8, float4& va,
                                                        float4& vb, int* inel) {
@@ -704,11 +707,37 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
     ++*inel;
   }
   const float hg = fsqrt(et);  // half of |g'| = 2 sqrt(et)
-  const float ct = 2.0f * u01f(r1.w) - 1.0f;
-  const float st = fsqrt(fmaxf(0.0f, 1.0f - ct * ct));
-  const float ph = 6.28318530717958648f * u01f(w8);
-  const float sp = __sinf(ph), cp = __cosf(ph);
-  const float nx = ct, ny = st * cp, nz = st * sp;
+  float nx, ny, nz;
+  bool iso = true;  // the VHS kernels carry no VSS code
+  if constexpr (VSS) iso = !I.vss;
+  if (iso) {
+    const float ct = 2.0f * u01f(r1.w) - 1.0f;
+    const float st = fsqrt(fmaxf(0.0f, 1.0f - ct * ct));
+    const float ph = 6.28318530717958648f * u01f(w8);
+    const float sp = __sinf(ph), cp = __cosf(ph);
+    nx = ct;
+    ny = st * cp;
+    nz = st * sp;
+  } else {
+    const float ux0 = va.x - vb.x, uy0 = va.y - vb.y, uz0 = va.z - vb.z;
+    const float gi = 1.0f / fsqrt(g2);
+    const float ux = ux0 * gi, uy = uy0 * gi, uz = uz0 * gi;
+    const float cc = 2.0f * fpow(u01f(r1.w), I.ainv) - 1.0f;
+    const float sc = fsqrt(fmaxf(0.0f, 1.0f - cc * cc));
+    const float ep = 6.28318530717958648f * u01f(w8);
+    const float se = __sinf(ep), ce = __cosf(ep);
+    const float pp = fsqrt(uy * uy + uz * uz);
+    if (pp > 1e-6f) {
+      const float ip = 1.0f / pp;
+      nx = cc * ux + sc * se * pp;
+      ny = cc * uy + sc * (ce * uz - ux * uy * se) * ip;
+      nz = cc * uz - sc * (ce * uy + ux * uz * se) * ip;
+    } else {  // relative velocity along x: rotate about x from y
+      nx = cc * ux;
+      ny = sc * ce;
+      nz = sc * se;
+    }
+  }
   const float cx = 0.5f * (va.x + vb.x), cy = 0.5f * (va.y + vb.y), cz = 0.5f * (va.z + vb.z);
   va.x = cx + hg * nx;
   va.y = cy + hg * ny;
@@ -732,7 +761,7 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // thread count); cw: room for rchunk uint4 + rchunk words (5 rchunk uint32)
 // in which they keep the words an accepted collision uses, drawn with the
 // pair; null: an accepted candidate draws them in its round.
-template <class Store>
+template <bool VSS, class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, uint32_t omask, int nc, int c_lo,
                                      uint32_t step, int iu, double my_vol, bool vol_mine,
@@ -830,7 +859,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         ++l_cand;
         l_sat += sg > sgm;
         if (acc) {
-          apply_collision(I, g2, w0.z, w[1], w0.w, va, vb, &l_inel);
+          apply_collision<VSS>(I, g2, w0.z, w[1], w0.w, va, vb, &l_inel);
           ++l_acc;
           P.st(i, va);
           P.st(j, vb);
@@ -916,7 +945,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
               r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
               w8 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
             }
-            apply_collision(I, g2, w3, r1, w8, va, vb, &l_inel);
+            apply_collision<VSS>(I, g2, w3, r1, w8, va, vb, &l_inel);
             ++l_acc;
             P.st(ci, va);
             P.st(cj, vb);
@@ -1136,7 +1165,7 @@ enum { kModeStaged = 0, kModeSmall = 1, kModeBig = 2 };
 
 // two_pass: the cells' moment sums in two passes (fewer live registers, for
 // the 80-VGPR budget of six waves per SIMD) rather than one.
-template <int mode, bool two_pass = false>
+template <int mode, bool VSS, bool two_pass = false>
 static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int L,
                                                      int run_slots, int do_collide,
                                                      int do_sample) {
@@ -1317,10 +1346,11 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.obs += c0;
       Sg.inst += c0;
       if (fast)
-        collide_cells(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
+        collide_cells<VSS>(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
                       c0 == 0, cw, rchunk);
       else
-        collide_cells(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu, my_vol,
+        collide_cells<VSS>(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu,
+                           my_vol,
                       c0 == 0, cw, rchunk);
       c0 = c1;
       if (c0 < nc) __syncthreads();  // the next segment reuses the staging arrays
@@ -1406,12 +1436,14 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 // this kernel.
 // MINW: waves per SIMD the register budget must allow.  6 (80 VGPRs) is
 // launched where the LDS stage leaves room for 6 workgroups per CU, 1 (no
-// constraint) otherwise.
-template <int MINW, int mode>
+// constraint) otherwise.  VSS: compiled with VSS scattering (instances with
+// alpha = 1 still scatter isotropically); launched only where an instance
+// uses it.
+template <int MINW, int mode, bool VSS>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
-  collide_group<mode, MINW == 6>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles,
-                                 kRunSlots, do_collide, do_sample);
+  collide_group<mode, VSS, MINW == 6>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles,
+                                      kRunSlots, do_collide, do_sample);
   if (!end_step || threadIdx.x != 0) return;
   const uint32_t prev = atomicAdd(a.done, 1u);
   if (prev == gridDim.x - 1) {
@@ -1435,6 +1467,7 @@ constexpr int kBigGrid = 1024;
 static_assert(kRoundChunkMax == kCollideThreads && kRoundChunkMax == kBigThreads &&
                   kCandChunk <= kRoundChunkMax,
               "a collision round keeps one candidate per thread");
+template <bool VSS>
 __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_collide,
                                                              int do_sample, int end_step) {
   const int nbig = __builtin_amdgcn_readfirstlane((int)*a.big_count);
@@ -1448,7 +1481,7 @@ __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_
   }
   for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
     const int g = __builtin_amdgcn_readfirstlane(a.big_list[i]);
-    collide_group<kModeBig>(a, g, a.lds_big, a.big_runs, do_collide, do_sample);
+    collide_group<kModeBig, VSS>(a, g, a.lds_big, a.big_runs, do_collide, do_sample);
     __syncthreads();  // the next group reuses the shared memory
   }
   __syncthreads();
@@ -2143,7 +2176,11 @@ bool big_stage_fits(int lds_big, int group_cells) {
 }
 
 hipError_t collide_setup() {
-  return hipFuncSetAttribute((const void*)k_collide_big,
+  const hipError_t e = hipFuncSetAttribute((const void*)k_collide_big<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kBigLdsBytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_collide_big<true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLdsBytes);
 }
 
@@ -2172,8 +2209,9 @@ hipError_t launch_order(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
-                          bool fused, hipStream_t s) {
+template <bool VSS>
+static hipError_t launch_collide_t(const StepArgs& a, bool collide, bool sample, bool end_step,
+                                   bool fused, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
   const dim3 grid((int)group_launch(a)), block(kCollideThreads);
   const int f0 = collide ? 1 : 0, f1 = sample ? 1 : 0;
@@ -2185,22 +2223,28 @@ hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end
   const bool six = 6 * (lds + 1024) <= 160 * 1024;
   if (fused) {
     if (six)
-      hipLaunchKernelGGL((k_collide<6, kModeSmall>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<6, kModeSmall, VSS>), grid, block, lds, s, a, f0, f1, f2);
     else
-      hipLaunchKernelGGL((k_collide<1, kModeSmall>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<1, kModeSmall, VSS>), grid, block, lds, s, a, f0, f1, f2);
   } else {
     if (six)
-      hipLaunchKernelGGL((k_collide<6, kModeStaged>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<6, kModeStaged, VSS>), grid, block, lds, s, a, f0, f1, f2);
     else
-      hipLaunchKernelGGL((k_collide<1, kModeStaged>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<1, kModeStaged, VSS>), grid, block, lds, s, a, f0, f1, f2);
   }
   if (fused) {
     if (!big_stage_fits(a.lds_big, a.group_cells)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_collide_big, dim3(kBigGrid), dim3(kBigThreads),
+    hipLaunchKernelGGL(k_collide_big<VSS>, dim3(kBigGrid), dim3(kBigThreads),
                        collide_lds_bytes(a.lds_big, a.group_cells), s, a, f0, f1,
                        end_step ? 1 : 0);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
+                          bool fused, hipStream_t s) {
+  return a.vss_any ? launch_collide_t<true>(a, collide, sample, end_step, fused, s)
+                   : launch_collide_t<false>(a, collide, sample, end_step, fused, s);
 }
 
 hipError_t launch_inject(const StepArgs& a, hipStream_t s) {

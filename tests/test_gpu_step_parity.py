@@ -31,8 +31,11 @@ def case_workloads():
     big = wl.box(1, 3, kn=0.2, ppc=3000, seed=31,
                  bc=[("diffuse", 1.0, (0, 0, 0)), ("diffuse", 1.5, (0, 0, 0)),
                      ("periodic", 1, (0, 0, 0)), ("periodic", 1, (0, 0, 0))])
+    vss = wl.cavity_2d(seed=203, n=24, ppc=40, kn=0.05)
+    vss["alpha"] = 1.6  # VSS scattering
+    vss["dt"] *= 4.0
     return {"fourier1d": fourier, "couette1d": couette, "cavity2d": cav, "specular2d": spec,
-            "bigcells1d": big}
+            "bigcells1d": big, "vss2d": vss}
 
 
 CASES = case_workloads()

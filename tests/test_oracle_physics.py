@@ -13,10 +13,12 @@ import dig_workloads as wl
 import oracle
 
 
-def zero_d_box(n, kn=0.1, omega=0.74, zrot=5.0, Tt=1.0, Tr=None, seed=7, dt_frac=0.2):
+def zero_d_box(n, kn=0.1, omega=0.74, zrot=5.0, Tt=1.0, Tr=None, seed=7, dt_frac=0.2,
+               alpha=1.0):
     """A single periodic cell: collisions only (0D relaxation box)."""
     w = wl.box(1, 1, kn=kn, omega=omega, zrot=zrot, ppc=n, seed=seed, Tt=Tt,
                Tr=Tt if Tr is None else Tr, dt_frac=dt_frac, tref=max(Tt, Tr or Tt))
+    w["alpha"] = alpha
     s = oracle.new_state(w, cap=n)
     return w, s
 
@@ -47,13 +49,15 @@ def test_knudsen_definition_reynolds_of_cavity_table():
         assert math.sqrt(2.0) / oracle.mu0(w) == pytest.approx(re, rel=2e-3)
 
 
-@pytest.mark.parametrize("omega", [0.74, 0.5])
-def test_ntc_vhs_equilibrium_collision_rate(omega):
+@pytest.mark.parametrize("omega,alpha", [(0.74, 1.0), (0.5, 1.0), (0.74, 1.6)])
+def test_ntc_vhs_equilibrium_collision_rate(omega, alpha):
     """Accepted collisions per unit time in an equilibrium box equal
-    (N/2) nu (N-1)/N with nu = 30 p / ((5-2w)(7-2w) mu) (VHS; for w = 1/2 the
-    hard-sphere sqrt(2) n pi d^2 cbar).  No majorant saturation allowed."""
+    (N/2) nu (N-1)/N with nu = 5 (a+1)(a+2) p / (a (5-2w)(7-2w) mu): for
+    VHS (a = 1) 30 p / ((5-2w)(7-2w) mu), for w = 1/2 the hard-sphere
+    sqrt(2) n pi d^2 cbar; for VSS the cross-section that keeps the same
+    viscosity.  No majorant saturation allowed."""
     n = 4000
-    w, s = zero_d_box(n, omega=omega, seed=11 if omega > 0.6 else 12)
+    w, s = zero_d_box(n, omega=omega, seed=11 if omega > 0.6 else 12, alpha=alpha)
     mu0 = oracle.mu0(w)
     acc = 0
     expect = 0.0
@@ -62,7 +66,8 @@ def test_ntc_vhs_equilibrium_collision_rate(omega):
         s.step_no = step
         Tt, _ = temps(s)
         p = 1.0 * Tt
-        nu = 30.0 * p / ((5 - 2 * omega) * (7 - 2 * omega) * mu0 * Tt ** omega)
+        nu = (5.0 * (alpha + 1) * (alpha + 2) / alpha) * p / (
+            (5 - 2 * omega) * (7 - 2 * omega) * mu0 * Tt ** omega)
         expect += 0.5 * n * nu * w["dt"] * (n - 1) / n
         st = s.collide()
         acc += st["accepted"]
@@ -70,15 +75,16 @@ def test_ntc_vhs_equilibrium_collision_rate(omega):
     assert sat == 0
     z = (acc - expect) / math.sqrt(expect)
     assert abs(z) < 4.0, (acc, expect, z)
-    if omega == 0.74:
+    if omega == 0.74 and alpha == 1.0:
         # the workload time unit: one mean collision time per TAU_C_PER_KN * Kn
         tau_c = 1.0 / (30.0 / ((5 - 2 * omega) * (7 - 2 * omega) * mu0))
         assert tau_c == pytest.approx(wl.TAU_C_PER_KN * w["kn"], rel=1e-12)
 
 
-def test_collisions_conserve_momentum_and_energy_exactly():
+@pytest.mark.parametrize("alpha", [1.0, 1.6])
+def test_collisions_conserve_momentum_and_energy_exactly(alpha):
     n = 300
-    w, s = zero_d_box(n, Tt=1.3, Tr=0.7, seed=3)
+    w, s = zero_d_box(n, Tt=1.3, Tr=0.7, seed=3, alpha=alpha)
     s.sgmax[:] *= 4.0  # many candidates
     for step in range(5):
         s.step_no = step
@@ -92,6 +98,64 @@ def test_collisions_conserve_momentum_and_energy_exactly():
         e1 = 0.5 * (v ** 2).sum() + s.er[:n].sum()
         assert abs(e1 - e0) <= 1e-12 * e0
         assert (s.er[:n] >= 0).all()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.6])
+def test_scattering_deflection_moments(alpha):
+    """Every accepted collision turns the relative velocity by an angle chi with
+    cos chi = 2 u^(1/alpha) - 1, u uniform (VSS; isotropic for alpha = 1):
+    over many single collisions the mean of cos chi is (alpha - 1)/(alpha + 1)
+    and the mean of cos^2 chi is 4 alpha/(alpha + 2) - 4 alpha/(alpha + 1) + 1,
+    within 5 standard errors, and the azimuth about the relative velocity is
+    uniform (mean of cos and sin of the turned direction's component there
+    is 0)."""
+    m = 100_000  # cells of two particles, one candidate each
+    w = wl.box(1, m, kn=0.1, ppc=2, seed=5, zrot=5.0)
+    w["alpha"] = alpha
+    n = 2 * m
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((3, m))
+    d /= np.linalg.norm(d, axis=0)
+    vol = oracle.cell_volume(w)
+    sgm = np.float32(vol / (w["weight"] * w["dt"]))  # a mean of one candidate
+    if float(sgm) * w["weight"] * w["dt"] / vol > 1.0:
+        sgm = np.nextafter(sgm, np.float32(0))
+    # relative speed large enough that every candidate is accepted
+    g_min = (float(sgm) / oracle.csigma(w)) ** (1.0 / (2.0 - 2.0 * w["omega"]))
+    G = 3.0 * g_min * (1.0 + rng.random(m))
+    v = np.zeros((3, n))
+    v[:, 0::2] = 0.5 * G * d
+    v[:, 1::2] = -0.5 * G * d
+    s = oracle.State(w, n)
+    s.load((np.arange(n) // 2 + 0.5).astype(np.float64), np.zeros(n), v[0], v[1], v[2],
+           np.ones(n), np.arange(n, dtype=np.uint32), start=np.arange(0, n + 1, 2),
+           sgmax=np.full(m, sgm, np.float32), step=4)
+    st = s.collide()
+    assert st["saturated"] == st["candidates"]  # ratio above 1: all accepted
+    g0 = v[:, 0::2] - v[:, 1::2]
+    g1 = np.stack([s.vx[0:n:2] - s.vx[1:n:2], s.vy[0:n:2] - s.vy[1:n:2],
+                   s.vz[0:n:2] - s.vz[1:n:2]])
+    moved = np.abs(g1 - g0).sum(axis=0) > 0
+    assert moved.sum() > 0.99 * m
+    g0, g1 = g0[:, moved], g1[:, moved]
+    c = (g0 * g1).sum(axis=0) / (np.linalg.norm(g0, axis=0) * np.linalg.norm(g1, axis=0))
+    k = len(c)
+    for vals, expect in ((c, (alpha - 1) / (alpha + 1)),
+                         (c * c, 4 * alpha / (alpha + 2) - 4 * alpha / (alpha + 1) + 1)):
+        z = (vals.mean() - expect) / (vals.std() / math.sqrt(k))
+        assert abs(z) < 5.0, (alpha, vals.mean(), expect, z)
+    # azimuth: the turned direction's part normal to g0, against a fixed
+    # perpendicular pair built from g0
+    u = g0 / np.linalg.norm(g0, axis=0)
+    a = np.where(np.abs(u[0]) < 0.9, 1.0, 0.0)
+    ref = np.stack([a, 1.0 - a, np.zeros(k)])
+    e1 = ref - (ref * u).sum(axis=0) * u
+    e1 /= np.linalg.norm(e1, axis=0)
+    e2 = np.cross(u.T, e1.T).T
+    n1 = g1 / np.linalg.norm(g1, axis=0)
+    for comp in ((n1 * e1).sum(axis=0), (n1 * e2).sum(axis=0)):
+        z = comp.mean() / (comp.std() / math.sqrt(k))
+        assert abs(z) < 5.0
 
 
 def test_jeans_landau_rotational_relaxation_rate():
