@@ -14,6 +14,7 @@ same workload descriptions in ``dig_workloads``.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -66,47 +67,85 @@ _i64 = C.POINTER(C.c_int64)
 _u8 = C.POINTER(C.c_uint8)
 
 
+def _configure(L):
+    """Sets the argument and result types of the oracle's C entry points."""
+    cp = C.POINTER(Config)
+    L.orc_philox.argtypes = [_u32, _u32, _u32]
+    L.orc_draw.argtypes = [cp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _u32]
+    L.orc_u01.argtypes = [C.c_uint32]
+    L.orc_u01.restype = C.c_double
+    L.orc_pick.argtypes = [C.c_uint32, C.c_uint32]
+    L.orc_pick.restype = C.c_uint32
+    for fn in ("orc_mu0", "orc_csigma", "orc_pinelastic", "orc_cell_volume"):
+        getattr(L, fn).argtypes = [cp]
+        getattr(L, fn).restype = C.c_double
+    L.orc_cell_volume_at.argtypes = [cp, C.c_int32]
+    L.orc_cell_volume_at.restype = C.c_double
+    L.orc_annulus_face.argtypes = [cp, C.c_int32]
+    L.orc_annulus_face.restype = C.c_double
+    L.orc_inject.argtypes = [cp, C.c_int64, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
+                             C.c_uint32, C.c_uint64]
+    L.orc_inject.restype = C.c_int64
+    L.orc_init.argtypes = [cp, _d, C.c_int32, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
+                           _i64]
+    L.orc_init.restype = C.c_int64
+    L.orc_move.argtypes = [cp, C.c_int64, _d, _d, _d, _d, _d, _d, _u32, C.c_uint32]
+    L.orc_move.restype = C.c_int64
+    L.orc_cell_index.argtypes = [cp, C.c_int64, _d, _d, _i32]
+    L.orc_sort.argtypes = [C.c_int64, _i32, C.c_int32, _i64, _i64]
+    L.orc_collide.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _f, C.c_uint32,
+                              C.POINTER(Stats), _d, _d]
+    L.orc_sample_sums.argtypes = [C.c_int32, _i64, _d, _d, _d, _d, _d]
+    L.orc_sums_to_fields.argtypes = [cp, C.c_int32, _d, C.c_double, _d]
+    L.orc_adjust.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _d, _d, _u32, _d,
+                             C.c_uint32, C.c_uint64, C.c_int64, _d, _d, _d, _d, _d,
+                             _d, _u32, _i64, _i64, C.POINTER(C.c_uint64)]
+    L.orc_adjust.restype = C.c_int
+    L.orc_closure.argtypes = [cp, _d, _d, C.c_double, _d, _u8, _d, _d]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_SO):
             build()
-        L = C.CDLL(_SO)
-        cp = C.POINTER(Config)
-        L.orc_philox.argtypes = [_u32, _u32, _u32]
-        L.orc_draw.argtypes = [cp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _u32]
-        L.orc_u01.argtypes = [C.c_uint32]
-        L.orc_u01.restype = C.c_double
-        L.orc_pick.argtypes = [C.c_uint32, C.c_uint32]
-        L.orc_pick.restype = C.c_uint32
-        for fn in ("orc_mu0", "orc_csigma", "orc_pinelastic", "orc_cell_volume"):
-            getattr(L, fn).argtypes = [cp]
-            getattr(L, fn).restype = C.c_double
-        L.orc_cell_volume_at.argtypes = [cp, C.c_int32]
-        L.orc_cell_volume_at.restype = C.c_double
-        L.orc_annulus_face.argtypes = [cp, C.c_int32]
-        L.orc_annulus_face.restype = C.c_double
-        L.orc_inject.argtypes = [cp, C.c_int64, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
-                                 C.c_uint32, C.c_uint64]
-        L.orc_inject.restype = C.c_int64
-        L.orc_init.argtypes = [cp, _d, C.c_int32, C.c_int64, _d, _d, _d, _d, _d, _d, _u32,
-                               _i64]
-        L.orc_init.restype = C.c_int64
-        L.orc_move.argtypes = [cp, C.c_int64, _d, _d, _d, _d, _d, _d, _u32, C.c_uint32]
-        L.orc_move.restype = C.c_int64
-        L.orc_cell_index.argtypes = [cp, C.c_int64, _d, _d, _i32]
-        L.orc_sort.argtypes = [C.c_int64, _i32, C.c_int32, _i64, _i64]
-        L.orc_collide.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _f, C.c_uint32,
-                                  C.POINTER(Stats), _d, _d]
-        L.orc_sample_sums.argtypes = [C.c_int32, _i64, _d, _d, _d, _d, _d]
-        L.orc_sums_to_fields.argtypes = [cp, C.c_int32, _d, C.c_double, _d]
-        L.orc_adjust.argtypes = [cp, C.c_int32, _i64, _d, _d, _d, _d, _d, _d, _u32, _d,
-                                 C.c_uint32, C.c_uint64, C.c_int64, _d, _d, _d, _d, _d,
-                                 _d, _u32, _i64, _i64, C.POINTER(C.c_uint64)]
-        L.orc_adjust.restype = C.c_int
-        L.orc_closure.argtypes = [cp, _d, _d, C.c_double, _d, _u8, _d, _d]
-        _lib = L
+        _lib = _configure(C.CDLL(_SO))
     return _lib
+
+
+def build_variant(edits, out_dir: str) -> str:
+    """Compiles a copy of the C oracle with textual edits applied.
+
+    edits: sequence of (old, new) strings; each `old` must occur exactly once
+    in the source.  Used only by tests that plant a plausible mistake in the
+    oracle to show that a pin catches it.  Returns the path of the library."""
+    text = open(_SRC[0], encoding="utf-8").read()
+    for old, new in edits:
+        if text.count(old) != 1:
+            raise ValueError(f"edit target occurs {text.count(old)} times: {old!r}")
+        text = text.replace(old, new)
+    os.makedirs(out_dir, exist_ok=True)
+    tag = abs(hash(tuple(edits))) % (1 << 40)
+    src = os.path.join(out_dir, f"variant_{tag:x}.c")
+    so = os.path.join(out_dir, f"libvariant_{tag:x}.so")
+    with open(src, "w", encoding="utf-8") as f:
+        f.write(text)
+    subprocess.run(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+                    "-shared", "-fPIC", "-I", _DIR, "-o", so, src, "-lm"], check=True)
+    return so
+
+
+@contextlib.contextmanager
+def variant(edits, out_dir: str):
+    """Within the block, every oracle call uses a copy compiled with `edits`."""
+    global _lib
+    saved = lib()
+    _lib = _configure(C.CDLL(build_variant(edits, out_dir)))
+    try:
+        yield _lib
+    finally:
+        _lib = saved
 
 
 def _p(a: np.ndarray, t):

@@ -54,17 +54,12 @@ def _conductivities(mu, A, dr):
     return kt, kr
 
 
-def solve(w, m_half, hot=None, mask=None, A=None, max_iter=2000, tol=1e-5, cfl=0.5,
-          wall_mode="dsmc"):
-    """Returns (m_next [6, C], iterations, last relative change)."""
+def _prepare(w, m_half, hot, mask, A, wall_mode):
+    """Grid, gas constants, masked higher-order terms, wall face states and the
+    conservative start state W of a solve."""
     nx, ny, hx, hy = _grid_params(w)
-    C = nx * ny
     dr = w.get("dr", 2)
     om = w["omega"]
-    mu0 = w["kn"] * np.sqrt(2.0 / np.pi)
-    Z = w["zrot"]
-    gam = (5.0 + dr) / (3.0 + dr)
-    cv = (3.0 + dr) / 2.0
     if A is None:
         A = (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * om))
     two = w["dim"] == 2
@@ -107,82 +102,135 @@ def solve(w, m_half, hot=None, mask=None, A=None, max_iter=2000, tol=1e-5, cfl=0
                             tr=tr0[idx].copy())
         axis = f // 2
         walls[f]["u"][axis] = np.zeros_like(walls[f]["u"][axis])
+    return dict(nx=nx, ny=ny, hx=hx, hy=hy, dr=dr, om=om, A=A, two=two, H=H, W=W,
+                bct=bct, walls=walls, mu0=w["kn"] * np.sqrt(2.0 / np.pi), Z=w["zrot"],
+                gam=(5.0 + dr) / (3.0 + dr), cv=(3.0 + dr) / 2.0)
 
-    def prims(W):
-        rho = W[0]
-        u = W[1:4] / rho
-        tr = 2.0 * W[5] / (dr * rho)
-        tt = (W[4] / rho - 0.5 * (u ** 2).sum(axis=0) - 0.5 * dr * tr) * 2.0 / 3.0
-        return rho, u, tt, tr
 
-    it = 0
-    change = np.inf
-    for it in range(1, max_iter + 1):
-        rho, u, tt, tr = prims(W)
-        mu = mu0 * tt ** om
-        kt_c, kr_c = _conductivities(mu, A, dr)
-        # cell-centred central derivatives used for tangential face terms
-        def dcen(f, axis):
-            out = np.zeros_like(f)
-            if axis == 1 and not two:
-                return out
-            n = f.shape[1] if axis == 0 else f.shape[0]
-            h = hx if axis == 0 else hy
-            per = bct[2 * axis] == "periodic"
-            if axis == 0:
-                if per:
-                    out[:] = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * h)
-                elif n > 1:
-                    out[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / (2 * h)
-                    out[:, 0] = (f[:, 1] - f[:, 0]) / h
-                    out[:, -1] = (f[:, -1] - f[:, -2]) / h
-            else:
-                if per:
-                    out[:] = (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / (2 * h)
-                elif n > 1:
-                    out[1:-1] = (f[2:] - f[:-2]) / (2 * h)
-                    out[0] = (f[1] - f[0]) / h
-                    out[-1] = (f[-1] - f[-2]) / h
-            return out
+def _prims(W, dr):
+    rho = W[0]
+    u = W[1:4] / rho
+    tr = 2.0 * W[5] / (dr * rho)
+    tt = (W[4] / rho - 0.5 * (u ** 2).sum(axis=0) - 0.5 * dr * tr) * 2.0 / 3.0
+    return rho, u, tt, tr
 
-        du = [[dcen(u[i], a) for a in range(2)] for i in range(3)]
-        R = np.zeros_like(W)
-        # local time step accumulators
-        inv_dt = np.zeros((ny, nx))
-        c = np.sqrt(gam * tt)
-        ktot = kt_c + kr_c
-        nu = np.maximum(4.0 * mu / (3.0 * rho), gam * ktot / (rho * cv))
-        for axis in range(2 if two else 1):
-            h = hx if axis == 0 else hy
-            inv_dt += (np.abs(u[axis]) + c) / h + 2.0 * nu / h ** 2
-            F = _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam,
-                             mu0, om, A, nx, ny)
-            # F has shape (6, ny, nx+1) for axis 0 or (6, ny+1, nx) for axis 1
-            if axis == 0:
-                R -= (F[:, :, 1:] - F[:, :, :-1]) / h
-            else:
-                R -= (F[:, 1:, :] - F[:, :-1, :]) / h
-        tau = mu / (rho * tt)
-        T = (3.0 * tt + dr * tr) / (3.0 + dr)
-        R[5] += 0.5 * dr * rho * (T - tr) / (Z * tau)
-        dtau = min(np.min(cfl / inv_dt), np.min(0.5 * Z * tau))
-        Wn = W + dtau * R
-        rn, un, ttn, trn = prims(Wn)
-        ch = np.max(np.abs(rn - rho) / rho)
-        ch = max(ch, np.max(np.abs(un - u) / np.sqrt(tt)))
-        ch = max(ch, np.max(np.abs(ttn - tt) / tt))
-        ch = max(ch, np.max(np.abs(trn - tr) / np.maximum(tr, 1e-300)))
-        W = Wn
-        change = ch
-        if ch < tol:
-            break
-    rho, u, tt, tr = prims(W)
+
+def _dcen(P, f, axis):
+    """Cell-centred derivative along `axis`: central inside, one-sided at
+    walls, wrapped across periodic faces (used for tangential face terms)."""
+    out = np.zeros_like(f)
+    if axis == 1 and not P["two"]:
+        return out
+    n = f.shape[1] if axis == 0 else f.shape[0]
+    h = P["hx"] if axis == 0 else P["hy"]
+    per = P["bct"][2 * axis] == "periodic"
+    if axis == 0:
+        if per:
+            out[:] = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * h)
+        elif n > 1:
+            out[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / (2 * h)
+            out[:, 0] = (f[:, 1] - f[:, 0]) / h
+            out[:, -1] = (f[:, -1] - f[:, -2]) / h
+    else:
+        if per:
+            out[:] = (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / (2 * h)
+        elif n > 1:
+            out[1:-1] = (f[2:] - f[:-2]) / (2 * h)
+            out[0] = (f[1] - f[0]) / h
+            out[-1] = (f[-1] - f[-2]) / h
+    return out
+
+
+def _axis_fluxes(P, W, axis):
+    """Total face fluxes normal to `axis` of state W (see _face_fluxes)."""
+    rho, u, tt, tr = _prims(W, P["dr"])
+    mu = P["mu0"] * tt ** P["om"]
+    du = [[_dcen(P, u[i], a) for a in range(2)] for i in range(3)]
+    h = P["hx"] if axis == 0 else P["hy"]
+    return _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"], h,
+                        P["two"], P["dr"], P["gam"], P["mu0"], P["om"], P["A"], P["nx"],
+                        P["ny"])
+
+
+def _residual(P, W):
+    """R = -(sum of face-flux differences)/h + rotational relaxation source,
+    and the explicit stability bound inv_dt of every cell.  Also returns the
+    primitive state and the relaxation time."""
+    rho, u, tt, tr = _prims(W, P["dr"])
+    dr, gam, two = P["dr"], P["gam"], P["two"]
+    mu = P["mu0"] * tt ** P["om"]
+    kt_c, kr_c = _conductivities(mu, P["A"], dr)
+    du = [[_dcen(P, u[i], a) for a in range(2)] for i in range(3)]
+    R = np.zeros_like(W)
+    inv_dt = np.zeros((P["ny"], P["nx"]))
+    c = np.sqrt(gam * tt)
+    ktot = kt_c + kr_c
+    nu = np.maximum(4.0 * mu / (3.0 * rho), gam * ktot / (rho * P["cv"]))
+    for axis in range(2 if two else 1):
+        h = P["hx"] if axis == 0 else P["hy"]
+        inv_dt += (np.abs(u[axis]) + c) / h + 2.0 * nu / h ** 2
+        F = _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"], h,
+                         two, dr, gam, P["mu0"], P["om"], P["A"], P["nx"], P["ny"])
+        # F has shape (6, ny, nx+1) for axis 0 or (6, ny+1, nx) for axis 1
+        if axis == 0:
+            R -= (F[:, :, 1:] - F[:, :, :-1]) / h
+        else:
+            R -= (F[:, 1:, :] - F[:, :-1, :]) / h
+    tau = mu / (rho * tt)
+    T = (3.0 * tt + dr * tr) / (3.0 + dr)
+    R[5] += 0.5 * dr * rho * (T - tr) / (P["Z"] * tau)
+    return R, inv_dt, (rho, u, tt, tr), tau
+
+
+def _relative_change(old, new):
+    rho, u, tt, tr = old
+    rn, un, ttn, trn = new
+    ch = np.max(np.abs(rn - rho) / rho)
+    ch = max(ch, np.max(np.abs(un - u) / np.sqrt(tt)))
+    ch = max(ch, np.max(np.abs(ttn - tt) / tt))
+    ch = max(ch, np.max(np.abs(trn - tr) / np.maximum(tr, 1e-300)))
+    return ch
+
+
+def _output(P, W):
+    rho, u, tt, tr = _prims(W, P["dr"])
+    C = P["nx"] * P["ny"]
     out = np.zeros((6, C))
     out[0] = rho.ravel()
     out[1:4] = u.reshape(3, C)
     out[4] = tt.ravel()
     out[5] = tr.ravel()
-    return out, it, change
+    return out
+
+
+def solve(w, m_half, hot=None, mask=None, A=None, max_iter=2000, tol=1e-5, cfl=0.5,
+          wall_mode="dsmc"):
+    """Explicit pseudo-time marching.  Returns (m_next [6, C], iterations,
+    last relative change)."""
+    P = _prepare(w, m_half, hot, mask, A, wall_mode)
+    W = P["W"]
+    it = 0
+    change = np.inf
+    for it in range(1, max_iter + 1):
+        R, inv_dt, prim, tau = _residual(P, W)
+        dtau = min(np.min(cfl / inv_dt), np.min(0.5 * P["Z"] * tau))
+        Wn = W + dtau * R
+        ch = _relative_change(prim, _prims(Wn, P["dr"]))
+        W = Wn
+        change = ch
+        if ch < tol:
+            break
+    return _output(P, W), it, change
+
+
+def face_fluxes(w, fields, axis, hot=None, A=None, wall_mode="wall"):
+    """Total flux (inviscid HLLC + NSF viscous and heat + masked higher-order
+    terms) through every face normal to `axis` for the primitive fields
+    [rho, ux, uy, uz, Tt, Tr] (first six rows of `fields`), the arithmetic of
+    one pseudo-time step.  Shape (6, ny, nx+1) for axis 0, (6, ny+1, nx) for
+    axis 1; rows mass, momentum x y z, total energy, rotational energy."""
+    P = _prepare(w, fields, hot, None, A, wall_mode)
+    return _axis_fluxes(P, P["W"], axis)
 
 
 def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam, mu0, om, A,
