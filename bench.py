@@ -1,7 +1,15 @@
 #!/usr/bin/env python
 """DSMC + DIG hot-path benchmark on one MI355X.
 
-Default workload: the DIG-coupled 2D lid-driven cavity (200 x 200 cells, 50
+Default workload (--workload cylinder): the largest single-GPU
+configuration, Mach 5 flow of a diatomic gas past a cylinder (annulus
+0.5 < r < 5.5, 500 x 400 stretched polar cells, about 50M particles at the
+freestream density, Kn 0.01, freestream inflow and outflow every step, plain
+DSMC), timed after an untimed pre-roll from the start at rest that lets the
+bow shock form.  Its working set (about 3 GB) is far beyond the 256 MB
+last-level cache, so the collide roofline is an HBM figure.
+
+--workload cavity: the DIG-coupled 2D lid-driven cavity (200 x 200 cells, 50
 particles per cell = 2,000,000 particles, Kn = 0.01, lid Ma = 0.3,
 omega = 0.74, Z = 5, N_s = 50).  A timed "step" is one DSMC step (move + walls,
 cell index + stable sort, NTC/VHS/BL collide, FP64 sampling); every N_s steps
@@ -18,6 +26,9 @@ solve as the target ("dig_loop").
 
 --workload batch: 64 uneven 1D instances (13,671,119 particles) advanced
 together by graph replays, plain DSMC.
+
+--workload sweep: the cavity family from 1M to 100M particles, showing where
+the step leaves the last-level cache and becomes HBM-bound.
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 (HIP events around every kernel inside the timed region), and the FP64 oracle
@@ -187,7 +198,8 @@ def run_cavity(args):
     counts = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(args.steps, counts)
+    step0 = state["step"]
+    cycles_timed = len(run(args.steps, counts))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = sim.profile("read")
@@ -222,12 +234,17 @@ def run_cavity(args):
         dig = {"value": ps2 / (t3 - t2), "unit": "particle-steps/s", "cycles": args.dig_cycles,
                "synth_iterations": its, "ms_per_cycle": (t3 - t2) / args.dig_cycles * 1e3,
                "dsmc_ms_per_cycle": ns * out["ms_per_step"]}
+    dig_what = ("no DIG cycle falls inside it" if cycles_timed == 0 else
+                f"{cycles_timed} DIG cycle(s) (closure + modification toward the "
+                f"time-averaged field) fall inside it")
     out.update(particles=int(n_avg), cells=w["nx"] * w["ny"], err_bits=ctr["err"],
                collisions_per_particle_step=ctr["accepted"] * 2 / max(ctr["step"] * n_avg, 1),
-               tuning=tuning, dig_loop=dig,
-               workload=f"{w['name']} 200x200 cells, 50 ppc (2M particles), Kn 0.01, lid Ma 0.3,"
-                        " DIG every 50 steps (closure + modification toward the time-averaged "
-                        "field in the timed region)")
+               tuning=tuning, dig_loop=dig, dig_cycles_timed=cycles_timed,
+               timed_steps=[step0, step0 + args.steps],
+               workload=f"{w['name']} 200x200 cells, 50 ppc (2M particles, working set inside "
+                        f"the 256 MB last-level cache), Kn 0.01, lid Ma 0.3, DIG every 50 "
+                        f"steps; the timed window is steps {step0}-{step0 + args.steps} and "
+                        f"{dig_what}")
     return out, w
 
 
@@ -340,22 +357,26 @@ def run_mlp(args):
 
 def run_cylinder(args):
     """Mach 5 flow past a cylinder: 500 x 400 stretched polar cells, ~50M
-    particles, freestream inflow and outflow every step, plain DSMC from a gas
-    at rest (the timed steps are the start of the transient)."""
+    particles at the freestream density, freestream inflow and outflow every
+    step, plain DSMC.  The gas starts at rest (as in the paper); `preroll`
+    steps (graph replays, untimed) let the freestream cross the domain and the
+    bow shock form before the autotuner, the breakdown and the timed window."""
     import torch
 
     import dig_workloads as wl
     from paper_2501_10965_amd.dsmc import DSMC
 
     w = wl.cylinder()
-    # the bow shock and the inflow reservoir raise the count well above the
-    # initial 50M over the timed steps
-    sim = DSMC(w, cap_factor=1.7, group_particles=args.group_particles,
+    # the bow shock and the inflow reservoir raise the count from the initial
+    # 50M to about 81M by the end of the pre-roll
+    sim = DSMC(w, cap_factor=2.2, group_particles=args.group_particles,
                group_cells=args.group_cells)
     sim.init()
+    progress(f"cylinder: {sim.counters()['n']} particles at rest; pre-roll {args.preroll} steps")
+    sim.step(args.preroll, graph=True)
     tuning = None if args.no_autotune else sim.autotune(steps_per_trial=10)
     k0 = sim.counters()["step"]
-    sim.step(max(args.warmup - k0, 0), graph=True)
+    sim.step(max(args.warmup, 1), graph=True)
     sim.profile("on")
     sim.step(10)
     breakdown = sim.profile("read")
@@ -385,14 +406,66 @@ def run_cylinder(args):
     out["graph_replay"] = {"value": ng * steps / (tg1 - tg0), "unit": "particle-steps/s",
                            "steps": steps, "ms_per_step": (tg1 - tg0) / steps * 1e3}
     out.update(particles=int(n_avg), cells=sim.ncell, err_bits=c2["err"], tuning=tuning,
-               dig_loop=None,
+               dig_loop=None, timed_steps=[c0["step"], c1["step"]],
                inflow_per_step=(c1["injected"] - c0["injected"]) / steps,
                removed_per_step=(c1["removed"] - c0["removed"]) / steps,
                collisions_per_particle_step=(c1["accepted"] - c0["accepted"]) * 2 /
                max(n_avg * steps, 1),
-               workload="Mach 5 cylinder, Kn 0.01, 500x400 stretched polar cells, ~50M "
-                        "particles, freestream inflow/outflow, plain DSMC (early transient)")
+               workload=f"{w['name']}: Mach 5 flow past a cylinder, Kn 0.01, 500x400 "
+                        f"stretched polar cells, {n_avg / 1e6:.1f}M particles, freestream "
+                        f"inflow/outflow every step, plain DSMC (move, sort, collide, sample); "
+                        f"timed steps {c0['step']}-{c1['step']} of a start from rest "
+                        f"(pre-roll {args.preroll} steps, then {k0 - args.preroll} autotuner "
+                        f"steps: the freestream has crossed the domain, the bow shock "
+                        f"stands)")
     return out, w
+
+
+def run_sweep(args):
+    """Cavity family at 1M to 100M particles (50 per cell): where the working
+    set leaves the 256 MB last-level cache, the step becomes HBM-bound."""
+    import math
+
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd.dsmc import DSMC
+
+    rows = []
+    for mp in args.sweep:
+        n = int(round(math.sqrt(mp * 1e6 / 50)))
+        w = wl.cavity_2d(seed=2001, n=n, ppc=50, kn=0.01 * 200 / n)
+        sim = DSMC(w, cap_factor=1.05)
+        sim.init()
+        sim.step(20, graph=True)
+        tuning = sim.autotune(steps_per_trial=5)
+        sim.profile("on")
+        sim.step(10)
+        bd = sim.profile("read")
+        sim.profile("off")
+        torch.cuda.synchronize()
+        c0 = sim.counters()
+        t0 = time.perf_counter()
+        sim.step(args.steps, graph=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c1 = sim.counters()
+        npart = 0.5 * (c0["n"] + c1["n"])
+        state_mb = (2 * 28 + 16) * npart / 1e6 + (4 * 3 + 8 + 2 * 17 * 8) * n * n / 1e6
+        us = {k: v[0] / max(v[1], 1) * 1e3 for k, v in bd.items() if v[1]}
+        col = us["collide"] * 1e-6
+        ach = (collide_particle_bytes(2) * npart + PER_CELL_BYTES * n * n) / col / 1e9
+        row = {"particles": int(npart), "cells": n * n, "working_set_MB": round(state_mb, 1),
+               "particle_steps_per_s": npart * args.steps / (t1 - t0),
+               "ms_per_step": (t1 - t0) / args.steps * 1e3,
+               "collide_us": round(us["collide"], 1), "move_us": round(us["move"], 1),
+               "collide_GBs": round(ach, 1), "collide_frac": round(ach / HBM_PEAK_GBS, 4),
+               "tuning": tuning}
+        progress(f"sweep {mp}M: {json.dumps(row)}")
+        rows.append(row)
+        del sim
+        torch.cuda.empty_cache()
+    return rows
 
 
 def run_steady(args):
@@ -460,11 +533,28 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, steps, dig: bool):
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
+
+
+def _oracle_sample(w, steps, dig):
+    """The oracle on one core: (particle-steps, seconds, final particle count)."""
     import oracle
 
-    progress(f"oracle baseline on {w['name']}, {steps} steps")
-    nthreads = 1
     s = oracle.new_state(w)
     t0 = time.perf_counter()
     ps = 0
@@ -480,12 +570,41 @@ def cpu_baseline(w, steps, dig: bool):
             s.adjust(f[0:6].copy(), it)
             s.reset_average()
             it += 1
-    sec = time.perf_counter() - t0
-    what = (f"{steps} DSMC steps with {steps // ns} DIG cycles (closure + modification)"
-            if dig else f"{steps} DSMC steps")
-    return {"value": ps / sec, "unit": "particle-steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{w['name']}: {s.n} particles, {what}, FP64, single thread",
-            "seconds": round(sec, 2)}
+    return ps, time.perf_counter() - t0, s.n
+
+
+def _oracle_worker(job):
+    w, steps, dig = job
+    return _oracle_sample(w, steps, dig)
+
+
+def cpu_baseline(w, steps, dig: bool, par_steps=None):
+    """The FP64 oracle (single-threaded C) on the host: one copy alone, then one
+    copy per usable core (capped at 16, the host share of one GPU), each on
+    its own seed, run at once; the all-core rate is the sum of their rates."""
+    import multiprocessing as mp
+
+    model, usable = host_cpu()
+    progress(f"oracle baseline on {w['name']}, {steps} steps, one core")
+    ps1, sec1, n1 = _oracle_sample(w, steps, dig)
+    procs = max(1, min(usable, 16))
+    par_steps = par_steps or steps
+    jobs = [(dict(w, seed=w["seed"] + 7919 * (k + 1)), par_steps, dig) for k in range(procs)]
+    progress(f"oracle baseline, {procs} processes at once, {par_steps} steps each")
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    agg = sum(ps / sec for ps, sec, _ in res)
+    what = (f"{steps} DSMC steps with {steps // w.get('ns', 50)} DIG cycles (closure + "
+            f"modification)" if dig else f"{steps} DSMC steps")
+    return {"value": agg, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"{w['name']}: {n1} particles, {what}, FP64; {procs} independent copies "
+                      f"(seeds differ) of {par_steps} steps each, one per core, run at once; "
+                      f"value = sum of their rates",
+            "per_core_value": ps1 / sec1, "per_core_seconds": round(sec1, 2),
+            "all_core_wall_seconds": round(wall, 2), "host_cpu_model": model,
+            "host_usable_cores": usable, "host_nproc": os.cpu_count()}
 
 
 def copy_calibration():
@@ -507,8 +626,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=150)
-    ap.add_argument("--workload", choices=["cavity", "batch", "mlp", "cylinder", "steady"],
-                    default="cavity")
+    ap.add_argument("--workload",
+                    choices=["cylinder", "cavity", "batch", "mlp", "steady", "sweep"],
+                    default="cylinder")
+    ap.add_argument("--preroll", type=int, default=2000,
+                    help="cylinder: untimed steps from the start at rest before the window")
+    ap.add_argument("--sweep", type=float, nargs="+", default=[1, 2, 5, 10, 20, 50, 100],
+                    help="sweep: particle counts in millions")
     ap.add_argument("--steady-threshold", type=float, default=0.02)
     ap.add_argument("--dig-max-cycles", type=int, default=160)
     ap.add_argument("--cpu-steps", type=int, default=200)
@@ -558,15 +682,22 @@ def main():
                 "inference_samples_per_s": res["inference_samples_per_s"]}
         print(json.dumps(line), flush=True)
         return
+    if args.workload == "sweep":
+        rows = run_sweep(args)
+        print(json.dumps({"metric": "DSMC particle-steps/s vs particle count (cavity, 50 "
+                                    "particles per cell)", "unit": "particle-steps/s",
+                          "steps": args.steps, "rows": rows}), flush=True)
+        return
     if args.workload == "batch":
         res, wcpu = run_batch(args)
         cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, 300, dig=False)
     elif args.workload == "cylinder":
         res, wcpu = run_cylinder(args)
-        # bounded sample: the same geometry and flow with 4M particles
+        # bounded sample: the same geometry and flow with 4M particles, from rest
         import dig_workloads as wl
         wsmall = wl.cylinder(n_target=4_000_000)
-        cpu = None if args.no_cpu_baseline else cpu_baseline(wsmall, 50, dig=False)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(wsmall, 40, dig=False,
+                                                             par_steps=20)
     else:
         res, wcpu = run_cavity(args)
         cpu = None if args.no_cpu_baseline else cpu_baseline(wcpu, args.cpu_steps, dig=True)
@@ -585,6 +716,9 @@ def main():
         "graph_replay": res["graph_replay"], "dig_loop": res["dig_loop"],
         "kernel_source_digest": source_digest(),
     }
+    for k in ("timed_steps", "inflow_per_step", "removed_per_step", "dig_cycles_timed"):
+        if k in res:
+            line[k] = res[k]
     print(json.dumps(line), flush=True)
 
 

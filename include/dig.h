@@ -128,7 +128,8 @@ enum {
   DIG_EBIT_GROUPS = 2u,        /* more cell groups than launched: state invalid */
   DIG_EBIT_TARGET = 4u,        /* dig_adjust target non-finite or non-positive */
   DIG_EBIT_CAPACITY = 8u,      /* dig_adjust or inflow would exceed the capacity */
-  DIG_EBIT_INFLOW = 16u        /* inflow clamped at the capacity (fewer particles entered) */
+  DIG_EBIT_INFLOW = 16u        /* a step's inflow would have exceeded the capacity: none of
+                                  that step's inflow entered (the rest of the step ran) */
 };
 
 /* Workspace planning.  cfgs[n_inst] describe the instances advanced
@@ -227,6 +228,31 @@ dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_ho
                        double* m_next_dev, void* workspace_dev, size_t workspace_bytes,
                        int32_t max_iter, double tol, int32_t* iters_host, double* change_host,
                        dig_stream_t stream);
+
+/* Checkpoint and resume (restart of a long run).  dsmc_save writes an image
+ * of the state that later steps read: the current cell-sorted particles
+ * (positions, velocities, rotational energies, ids), the cell start table,
+ * every cell's majorant, the time-average accumulator, the counters (particle
+ * count, step, samples, next id, statistics, error bits), the tuning, and a
+ * fingerprint of the instance parameters; a hash over the whole image closes
+ * it.  host_buf = NULL: *bytes receives the size needed and nothing is
+ * written; otherwise host_buf must hold *bytes >= that size (else
+ * DIG_ERR_INVALID, *bytes = size needed) and *bytes receives the size
+ * written.  Synchronises `stream`.  Errors: DIG_ERR_STATE (no state, or a
+ * partial step pending), DIG_ERR_HIP.
+ *
+ * dsmc_load replaces the state of a context created with the same
+ * configuration (any capacity that holds the saved particles) by the image
+ * of `bytes` bytes at host_buf.  Stepping on from a loaded image gives the
+ * same results, bit for bit, as stepping on from the saved state.  The image
+ * is checked before any device work: wrong magic or version, another
+ * configuration, a truncated or corrupted image, or a particle state that
+ * does not match its cells give DIG_ERR_INVALID (more particles than the
+ * capacity: DIG_ERR_CAPACITY), and the context's state is left unchanged.
+ * Captured step graphs are dropped.  Synchronises `stream` (the copies read
+ * host_buf). */
+dig_status dsmc_save(dig_ctx* ctx, void* host_buf, size_t* bytes, dig_stream_t stream);
+dig_status dsmc_load(dig_ctx* ctx, const void* host_buf, size_t bytes, dig_stream_t stream);
 
 /* Synchronises and copies the device counters into *out. */
 dig_status dsmc_query(dig_ctx* ctx, dig_counters* out_host, dig_stream_t stream);

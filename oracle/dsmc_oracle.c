@@ -486,22 +486,37 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
         ny = stt * cos(ph);
         nz = stt * sin(ph);
       } else {
+        /* VSS: deflection chi about the unit relative velocity u with a
+         * uniform azimuth.  The azimuth is measured from the coordinate axis
+         * least aligned with u (first on ties), taken as the first of three
+         * cyclically ordered components (a, b, c); then
+         * n = cc u + sc (se p e_a' + ...) in Bird's rotation form with
+         * p = sqrt(b^2 + c^2) >= sqrt(2/3), so the rotation is well
+         * conditioned for every direction of u.  The choice of axis is a
+         * decision taken in floating point: its gap enters the margin. */
         double gm = sqrt(g2);
-        double ux = gxv / gm, uy = gyv / gm, uz = gzv / gm;
+        double u3[3] = {gxv / gm, gyv / gm, gzv / gm};
+        double m0 = fabs(u3[0]), m1 = fabs(u3[1]), m2 = fabs(u3[2]);
+        int k = 0;
+        if (m1 < m0) k = 1;
+        if (m2 < (k == 0 ? m0 : m1)) k = 2;
+        double lo = fabs(u3[k]), next = INFINITY;
+        for (int q = 0; q < 3; ++q)
+          if (q != k && fabs(u3[q]) < next) next = fabs(u3[q]);
+        if (next - lo < margin) margin = next - lo;
+        double ua = u3[k], ub = u3[(k + 1) % 3], uc = u3[(k + 2) % 3];
         double cc = 2.0 * pow(orc_u01(r1[3]), 1.0 / c->alpha) - 1.0;
         double sc = sqrt(fmax(0.0, 1.0 - cc * cc));
         double eps = 2.0 * M_PI * orc_u01(r2[0]);
         double se = sin(eps), ce = cos(eps);
-        double pp = sqrt(uy * uy + uz * uz);
-        if (pp > 1e-6) {
-          nx = cc * ux + sc * se * pp;
-          ny = cc * uy + sc * (ce * uz - ux * uy * se) / pp;
-          nz = cc * uz - sc * (ce * uy + ux * uz * se) / pp;
-        } else { /* relative velocity along x: rotate about x from y */
-          nx = cc * ux;
-          ny = sc * ce;
-          nz = sc * se;
-        }
+        double pp = sqrt(ub * ub + uc * uc);
+        double n3[3];
+        n3[k] = cc * ua + sc * se * pp;
+        n3[(k + 1) % 3] = cc * ub + sc * (ce * uc - ua * ub * se) / pp;
+        n3[(k + 2) % 3] = cc * uc - sc * (ce * ub + ua * uc * se) / pp;
+        nx = n3[0];
+        ny = n3[1];
+        nz = n3[2];
       }
       double cx = 0.5 * (vx[i] + vx[j]), cy = 0.5 * (vy[i] + vy[j]), cz = 0.5 * (vz[i] + vz[j]);
       vx[i] = cx + 0.5 * gp * nx;

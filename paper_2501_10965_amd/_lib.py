@@ -95,7 +95,7 @@ EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "
            "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_profile_kinds",
            "dsmc_tuning", "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
            "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "closure_features",
-           "closure_blend", "dig_last_error",
+           "closure_blend", "dsmc_save", "dsmc_load", "dig_last_error",
            "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     L.closure_assemble.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, vp, vp, vp, vp,
                                    vp]
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
+    L.dsmc_save.argtypes = [vp, vp, C.POINTER(C.c_size_t), vp]
+    L.dsmc_load.argtypes = [vp, vp, C.c_size_t, vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]
     L.dsmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), vp]
     L.dsmc_profile_kinds.argtypes = [vp, C.c_uint32, C.c_int32]

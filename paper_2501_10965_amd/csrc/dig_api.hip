@@ -1,10 +1,12 @@
 // Host side of libdig: validation, workspace layout, launches, errors.
 #include <math.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -254,7 +256,7 @@ InstParam make_param(const dig_config& c, int32_t cell0) {
   p.inst = c.instance_id;
   p.pin = p_inelastic(c);
   p.vss = c.alpha != 1.0 ? 1u : 0u;
-  p.ainv = (float)(1.0 / c.alpha);
+  p.ainv = 1.0 / c.alpha;
   p.weight = c.weight;
   p.dt = c.dt;
   p.vol = cell_volume(c);
@@ -320,6 +322,7 @@ struct dig_ctx {
     int64_t n;
     hipGraph_t g;
     hipGraphExec_t x;
+    hipEvent_t done;  // recorded after the latest launch of this graph
   };
   std::vector<Graph> graphs;
   hipStream_t cap = nullptr;  // capture stream, default priority
@@ -508,11 +511,13 @@ void apply_tuning(dig_ctx* c, int32_t T, int32_t Gc, int32_t seq) {
   c->Lbig = lds_big_for(Gc);
 }
 
+// Destroys the captured graphs.  A replay may still be in flight on the
+// stream it was launched on: wait for each graph's own completion event (not
+// for the whole device).
 void drop_graphs(dig_ctx* c) {
-  if (c->graphs.empty()) return;
-  // a replay may still be in flight on the caller's stream
-  (void)hipDeviceSynchronize();
   for (auto& g : c->graphs) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
     (void)hipGraphExecDestroy(g.x);
     (void)hipGraphDestroy(g.g);
   }
@@ -990,10 +995,18 @@ dig_status graph_steps(dig_ctx* c, int32_t k, hipStream_t stream) {
       (void)hipGraphDestroy(g);
       return hip_fail(e, "hipGraphInstantiate");
     }
-    c->graphs.push_back({k, cur0, c->T, c->Gc, c->seq_max, nup, g, x});
+    hipEvent_t done = nullptr;
+    e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(x);
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    c->graphs.push_back({k, cur0, c->T, c->Gc, c->seq_max, nup, g, x, done});
     hit = &c->graphs.back();
   }
   HIP_TRY(hipGraphLaunch(hit->x, stream));
+  HIP_TRY(hipEventRecord(hit->done, stream));
   c->cur = cur0 ^ (k & 1);
   return DIG_OK;
 }
@@ -1120,6 +1133,202 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
     }
   }
   if (out) *out = best;
+  return DIG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint image: a header, then the current particle state and the
+// per-cell state that later steps read.
+struct SaveHeader {
+  char magic[8];  // "DIGSAVE1"
+  uint32_t version;
+  int32_t dim, n_inst, ncell;
+  int64_t n;
+  uint64_t cfg_hash;       // instance parameters as the kernels see them
+  uint64_t payload_bytes;  // bytes after the header
+  dig_counters ctr;
+  int32_t T, Gc, seq, pad;  // tuning at the time of the save
+  uint64_t hash;            // over the header up to this field and the payload
+};
+constexpr uint32_t kSaveVersion = 1;
+
+// Word-wise multiplicative hash: detects truncation and corruption (not an
+// authentication code).
+uint64_t mix_hash(const unsigned char* p, size_t n, uint64_t h) {
+  const uint64_t P = 0x100000001b3ULL;
+  size_t k = 0;
+  for (; k + 8 <= n; k += 8) {
+    uint64_t w;
+    memcpy(&w, p + k, 8);
+    h = (h ^ w) * P;
+    h ^= h >> 29;
+  }
+  for (; k < n; ++k) h = (h ^ p[k]) * P;
+  return h;
+}
+
+uint64_t cfg_hash(const dig_ctx* c) {
+  uint64_t h = 0xcbf29ce484222325ULL;
+  h = mix_hash((const unsigned char*)c->params.data(), sizeof(InstParam) * c->params.size(), h);
+  const int32_t dims[3] = {c->dim, c->n_inst, c->ncell};
+  return mix_hash((const unsigned char*)dims, sizeof(dims), h);
+}
+
+// Payload: x, y, vx, vy, vz, er (f32), id (u32) of n particles; start
+// (i32, C + 1); majorant (f32, C); accumulator (f64, 17 C); statistics slots.
+size_t payload_bytes(int64_t n, int64_t C) {
+  return (size_t)n * 28 + 4 * (size_t)(C + 1) + 4 * (size_t)C + 8 * 17 * (size_t)C +
+         sizeof(unsigned long long) * kStatSlots * ST_N;
+}
+
+uint64_t image_hash(const SaveHeader& h, const unsigned char* payload) {
+  uint64_t v = mix_hash((const unsigned char*)&h, offsetof(SaveHeader, hash),
+                        0x84222325cbf29ce4ULL);
+  return mix_hash(payload, h.payload_bytes, v);
+}
+
+// Host-side checks of a checkpoint's particle state against the context:
+// start is a non-decreasing table from 0 to n, and every box particle lies
+// in the cell its position maps to.
+bool image_state_ok(const dig_ctx* c, const unsigned char* p, int64_t n) {
+  const float *x = (const float*)p, *y = x + n;
+  const int32_t* start = (const int32_t*)(p + (size_t)n * 28);
+  if (start[0] != 0 || start[c->ncell] != n) return false;
+  for (int32_t k = 0; k < c->ncell; ++k)
+    if (start[k + 1] < start[k]) return false;
+  for (int i = 0; i < c->n_inst; ++i) {
+    const InstParam& q = c->params[i];
+    for (int32_t k = q.cell0; k < q.cell0 + q.ncell; ++k)
+      for (int32_t e = start[k]; e < start[k + 1]; ++e) {
+        if (!std::isfinite(x[e]) || (q.dim == 2 && !std::isfinite(y[e]))) return false;
+        if (q.geom != DIG_GEOM_BOX) continue;
+        const float fx = floorf(x[e]), fy = q.dim == 2 ? floorf(y[e]) : 0.0f;
+        if (fx < 0.0f || fx >= (float)q.nx || fy < 0.0f || fy >= (float)q.ny) return false;
+        if (q.cell0 + (int32_t)fx + q.nx * (int32_t)fy != k) return false;
+      }
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+dig_status dsmc_save(dig_ctx* c, void* host_buf, size_t* bytes, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!bytes) return fail(DIG_ERR_INVALID, "null size");
+  if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  hipStream_t s = (hipStream_t)stream;
+  StepArgs a = args(c);
+  SaveHeader h;
+  memset(&h, 0, sizeof(h));
+  HIP_TRY(hipMemcpyAsync(&h.ctr, a.ctr, sizeof(dig_counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t n = h.ctr.n;
+  const int64_t C = c->ncell;
+  const size_t need = sizeof(SaveHeader) + payload_bytes(n, C);
+  if (!host_buf) {
+    *bytes = need;
+    return DIG_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(DIG_ERR_INVALID, "checkpoint buffer too small: need " + std::to_string(need));
+  }
+  unsigned char* p = (unsigned char*)host_buf + sizeof(SaveHeader);
+  const void* src[7] = {a.A.x, a.A.y, a.A.vx, a.A.vy, a.A.vz, a.A.er, a.A.id};
+  for (int k = 0; k < 7; ++k)
+    HIP_TRY(hipMemcpyAsync(p + (size_t)k * 4 * n, src[k], 4 * (size_t)n, hipMemcpyDeviceToHost,
+                           s));
+  unsigned char* q = p + (size_t)n * 28;
+  HIP_TRY(hipMemcpyAsync(q, a.start, 4 * (C + 1), hipMemcpyDeviceToHost, s));
+  q += 4 * (C + 1);
+  HIP_TRY(hipMemcpyAsync(q, a.sgmax, 4 * C, hipMemcpyDeviceToHost, s));
+  q += 4 * C;
+  HIP_TRY(hipMemcpyAsync(q, a.acc, 8 * 17 * C, hipMemcpyDeviceToHost, s));
+  q += 8 * 17 * C;
+  HIP_TRY(hipMemcpyAsync(q, a.stats, sizeof(unsigned long long) * kStatSlots * ST_N,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  memcpy(h.magic, "DIGSAVE1", 8);
+  h.version = kSaveVersion;
+  h.dim = c->dim;
+  h.n_inst = c->n_inst;
+  h.ncell = c->ncell;
+  h.n = n;
+  h.cfg_hash = cfg_hash(c);
+  h.payload_bytes = payload_bytes(n, C);
+  h.ctr.cur = 0;
+  h.T = c->T;
+  h.Gc = c->Gc;
+  h.seq = c->seq_max;
+  h.hash = image_hash(h, p);
+  memcpy(host_buf, &h, sizeof(h));
+  *bytes = need;
+  return DIG_OK;
+}
+
+dig_status dsmc_load(dig_ctx* c, const void* host_buf, size_t bytes, dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!host_buf) return fail(DIG_ERR_INVALID, "null checkpoint");
+  if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
+  if (bytes < sizeof(SaveHeader)) return fail(DIG_ERR_INVALID, "checkpoint truncated");
+  SaveHeader h;
+  memcpy(&h, host_buf, sizeof(h));
+  if (memcmp(h.magic, "DIGSAVE1", 8) != 0 || h.version != kSaveVersion)
+    return fail(DIG_ERR_INVALID, "not a checkpoint of this library version");
+  if (h.dim != c->dim || h.n_inst != c->n_inst || h.ncell != c->ncell ||
+      h.cfg_hash != cfg_hash(c))
+    return fail(DIG_ERR_INVALID, "checkpoint of a different configuration");
+  if (h.n < 0 || h.n > c->capacity)
+    return fail(DIG_ERR_CAPACITY, "checkpoint holds more particles than the capacity");
+  const int64_t n = h.n, C = c->ncell;
+  if (h.payload_bytes != payload_bytes(n, C) || bytes != sizeof(SaveHeader) + h.payload_bytes)
+    return fail(DIG_ERR_INVALID, "checkpoint truncated or of the wrong size");
+  const unsigned char* p = (const unsigned char*)host_buf + sizeof(SaveHeader);
+  if (image_hash(h, p) != h.hash) return fail(DIG_ERR_INVALID, "checkpoint corrupted");
+  if (!image_state_ok(c, p, n))
+    return fail(DIG_ERR_INVALID, "checkpoint particle state inconsistent with its cells");
+  if (check_tuning(h.T, h.Gc, h.seq) != DIG_OK)
+    return fail(DIG_ERR_INVALID, "checkpoint tuning out of range");
+  // valid: replace the state (the particles go to buffer 0)
+  hipStream_t s = (hipStream_t)stream;
+  drop_graphs(c);
+  apply_tuning(c, h.T, h.Gc, h.seq);
+  c->cur = 0;
+  c->phase = 0;
+  c->n_host = n > 0 ? n : 1;
+  StepArgs a = args(c);
+  void* dst[7] = {a.A.x, a.A.y, a.A.vx, a.A.vy, a.A.vz, a.A.er, a.A.id};
+  for (int k = 0; k < 7; ++k)
+    HIP_TRY(hipMemcpyAsync(dst[k], p + (size_t)k * 4 * n, 4 * (size_t)n, hipMemcpyHostToDevice,
+                           s));
+  const unsigned char* q = p + (size_t)n * 28;
+  HIP_TRY(hipMemcpyAsync(a.start, q, 4 * (C + 1), hipMemcpyHostToDevice, s));
+  q += 4 * (C + 1);
+  HIP_TRY(hipMemcpyAsync(a.sgmax, q, 4 * C, hipMemcpyHostToDevice, s));
+  q += 4 * C;
+  HIP_TRY(hipMemcpyAsync(a.acc, q, 8 * 17 * C, hipMemcpyHostToDevice, s));
+  q += 8 * 17 * C;
+  HIP_TRY(hipMemcpyAsync(a.stats, q, sizeof(unsigned long long) * kStatSlots * ST_N,
+                         hipMemcpyHostToDevice, s));
+  // cell counts, groups and instance ranges from the start table, as after
+  // dsmc_inject; then the counters of the saved state
+  hipLaunchKernelGGL(k_counts_from_start, dim3((c->ncell + 255) / 256), dim3(256), 0, s,
+                     a.start, a.count, c->ncell);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_scan(a, a.count, false, s));
+  HIP_TRY(launch_fill_i32((int32_t*)a.done, 1, 0, s));
+  HIP_TRY(launch_fill_i32((int32_t*)a.big_count, 1, 0, s));
+  HIP_TRY(hipMemcpyAsync(a.ctr, &h.ctr, sizeof(dig_counters), hipMemcpyHostToDevice, s));
+  // the copies read the caller's buffer and the local header
+  HIP_TRY(hipStreamSynchronize(s));
+  c->n_host = n;
+  c->has_state = true;
   return DIG_OK;
 }
 

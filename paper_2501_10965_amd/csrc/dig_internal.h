@@ -47,9 +47,10 @@ struct InstParam {
   float rin2, rout2, rin, rout;
   float res2, dthf, rk, rlq;
   double res_mean, rho_inf;
-  // scattering: isotropic (vss = 0, alpha = 1) or VSS with 1/alpha
-  float ainv;
+  // scattering: isotropic (vss = 0, alpha = 1) or VSS with 1/alpha (the
+  // deflection angle is taken in FP64)
   uint32_t vss;
+  double ainv;
 };
 enum : uint32_t { TAG_INFLOW = 10 };
 

@@ -687,8 +687,9 @@ static __device__ __forceinline__ bool vhs_accept(const InstParam& I, float sgm,
 // second particle (double relaxation, tests w3 and r1.y, Beta(1, 5/2 - omega)
 // splits r1.x and r1.z), then scattering that conserves momentum and the
 // total energy: isotropic (cos theta from r1.w, phi from w8), or for VSS the
-// deflection cos chi = 2 u^(1/alpha) - 1 (u from r1.w) from the pre-collision
-// relative velocity with azimuth from w8 (Bird's rotation).
+// deflection cos chi = 2 u^(1/alpha) - 1 (u from r1.w) about the
+// pre-collision relative velocity with azimuth from w8 (Bird's rotation
+// formulas, from the coordinate axis least aligned with that velocity).
 template <bool VSS>
 static __device__ __forceinline__ void apply_collision(const InstParam& I, float g2, uint32_t w3,
                                                        uint4 r1, uint32_t w8, float4& va,
@@ -711,32 +712,44 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
   bool iso = true;  // the VHS kernels carry no VSS code
   if constexpr (VSS) iso = !I.vss;
   if (iso) {
+    // ct = 2u - 1 is exact; sin theta from (1 - ct)(1 + ct), both factors
+    // exact, keeps its relative accuracy near ct = +-1
     const float ct = 2.0f * u01f(r1.w) - 1.0f;
-    const float st = fsqrt(fmaxf(0.0f, 1.0f - ct * ct));
+    const float st = fsqrt(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
     const float ph = 6.28318530717958648f * u01f(w8);
     const float sp = __sinf(ph), cp = __cosf(ph);
     nx = ct;
     ny = st * cp;
     nz = st * sp;
   } else {
+    // azimuth from the coordinate axis least aligned with the relative
+    // velocity (first on ties), in cyclic component order (a, b, c), so that
+    // p = sqrt(b^2 + c^2) >= sqrt(2/3) and the rotation stays well
+    // conditioned for every direction
     const float ux0 = va.x - vb.x, uy0 = va.y - vb.y, uz0 = va.z - vb.z;
     const float gi = 1.0f / fsqrt(g2);
     const float ux = ux0 * gi, uy = uy0 * gi, uz = uz0 * gi;
-    const float cc = 2.0f * fpow(u01f(r1.w), I.ainv) - 1.0f;
-    const float sc = fsqrt(fmaxf(0.0f, 1.0f - cc * cc));
+    const float mx = fabsf(ux), my = fabsf(uy), mz = fabsf(uz);
+    const int k = (my < mx) ? ((mz < my) ? 2 : 1) : ((mz < mx) ? 2 : 0);
+    const float ua = k == 0 ? ux : (k == 1 ? uy : uz);
+    const float ub = k == 0 ? uy : (k == 1 ? uz : ux);
+    const float uc = k == 0 ? uz : (k == 1 ? ux : uy);
+    // cos chi = 2 v - 1 and sin chi = 2 sqrt(v (1 - v)), v = u^(1/alpha), in
+    // FP64: near-forward deflections (v close to 1) would lose the relative
+    // accuracy of 1 - v, and so of sin chi, in FP32
+    const double v = pow(u01d(r1.w), I.ainv);
+    const float cc = (float)(2.0 * v - 1.0);
+    const float sc = (float)(2.0 * sqrt(v * (1.0 - v)));
     const float ep = 6.28318530717958648f * u01f(w8);
     const float se = __sinf(ep), ce = __cosf(ep);
-    const float pp = fsqrt(uy * uy + uz * uz);
-    if (pp > 1e-6f) {
-      const float ip = 1.0f / pp;
-      nx = cc * ux + sc * se * pp;
-      ny = cc * uy + sc * (ce * uz - ux * uy * se) * ip;
-      nz = cc * uz - sc * (ce * uy + ux * uz * se) * ip;
-    } else {  // relative velocity along x: rotate about x from y
-      nx = cc * ux;
-      ny = sc * ce;
-      nz = sc * se;
-    }
+    const float pp = fsqrt(ub * ub + uc * uc);
+    const float ip = 1.0f / pp;
+    const float na = cc * ua + sc * se * pp;
+    const float nb = cc * ub + sc * (ce * uc - ua * ub * se) * ip;
+    const float nc = cc * uc - sc * (ce * ub + ua * uc * se) * ip;
+    nx = k == 0 ? na : (k == 1 ? nc : nb);
+    ny = k == 0 ? nb : (k == 1 ? na : nc);
+    nz = k == 0 ? nc : (k == 1 ? nb : na);
   }
   const float cx = 0.5f * (va.x + vb.x), cy = 0.5f * (va.y + vb.y), cz = 0.5f * (va.z + vb.z);
   va.x = cx + hg * nx;
@@ -1534,13 +1547,15 @@ __global__ __launch_bounds__(256) void k_inject_count(StepArgs a) {
     if (threadIdx.x == 0) s_run += s_w[0] + s_w[1] + s_w[2] + s_w[3];
     __syncthreads();
   }
-  // inj_off[nt]: all sectors; inj_off[nt + 1]: what fits in the capacity
+  // inj_off[nt]: all sectors; inj_off[nt + 1]: the particles that enter.
+  // An inflow that would exceed the capacity is not clamped: none of it
+  // enters (the state keeps its particles and ids) and the error bit is set.
   if (threadIdx.x == 0) {
     int64_t tot = s_run;
     const int64_t n0 = a.ctr->n;
     a.inj_off[nt] = (int32_t)tot;
     if (n0 + tot > a.capacity) {
-      tot = a.capacity - n0;
+      tot = 0;
       atomicOr(&a.ctr->err, (uint32_t)DIG_EBIT_INFLOW);
     }
     a.inj_off[nt + 1] = (int32_t)tot;

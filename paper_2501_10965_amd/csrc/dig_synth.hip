@@ -227,7 +227,12 @@ __device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays&
 }
 
 // Fluxes of every face of the grid: threads [0, nfx) take the x faces, the
-// rest the y faces.  Thread 0 also resets the next iteration's reductions.
+// rest the y faces.  Thread 0 also resets the next iteration's reductions
+// (parity it + 1).  That is safe only through stream order: the last kernel
+// to touch those slots is the update of iteration it - 1, which read its
+// time step from them, and it has completed before this launch starts on the
+// same stream; the update of this iteration, the next to use them, starts
+// after this launch has completed.
 __global__ __launch_bounds__(256) void k_synth_flux(SynthGrid g, SynthArrays s, int it) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {

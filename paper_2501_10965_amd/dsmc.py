@@ -75,6 +75,18 @@ class DSMC:
         L.check(self.lib.dsmc_query(self.ctx, C.byref(c), _stream()))
         return c.as_dict()
 
+    def save(self) -> bytes:
+        """Checkpoint image of the current state (dsmc_save)."""
+        need = C.c_size_t(0)
+        L.check(self.lib.dsmc_save(self.ctx, None, C.byref(need), _stream()))
+        buf = C.create_string_buffer(need.value)
+        L.check(self.lib.dsmc_save(self.ctx, buf, C.byref(need), _stream()))
+        return buf.raw[: need.value]
+
+    def load(self, image: bytes):
+        """Replaces the state by a checkpoint image (dsmc_load)."""
+        L.check(self.lib.dsmc_load(self.ctx, image, len(image), _stream()))
+
     def state(self, n: int | None = None) -> dict:
         """Views of the current (cell-sorted) particle buffer."""
         ctr = self.counters()
