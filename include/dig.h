@@ -229,6 +229,24 @@ dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_ho
                        int32_t max_iter, double tol, int32_t* iters_host, double* change_host,
                        dig_stream_t stream);
 
+/* synth_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same solve, with its scratch in a static device array of
+ * DIG_SYNTH_STATIC_BYTES (32 MiB) that the library holds on each GPU it runs
+ * on until the process ends, instead of a caller workspace.  The caller still
+ * passes the inputs and m_next_dev.  Calls no allocation routine.  Grids
+ * whose dig_synth_workspace_bytes exceed DIG_SYNTH_STATIC_BYTES (about
+ * 110,000 cells) give DIG_ERR_INVALID.  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents (each call initialises
+ * what it reads): calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define DIG_SYNTH_STATIC_BYTES (32u << 20)
+dig_status synth_solve_static(const dig_config* cfg_host, const dig_synth_opts* opts_host,
+                              const double* m_half_dev, const double* hot_dev,
+                              const uint8_t* mask_dev, double* m_next_dev, int32_t max_iter,
+                              double tol, int32_t* iters_host, double* change_host,
+                              dig_stream_t stream);
+
 /* Checkpoint and resume (restart of a long run).  dsmc_save writes an image
  * of the state that later steps read: the current cell-sorted particles
  * (positions, velocities, rotational energies, ids), the cell start table,

@@ -12,6 +12,7 @@ BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
 GEOM = {"box": 0, "annulus": 1}
 STAGE_MOVE, STAGE_SORT, STAGE_COLLIDE, STAGE_ALL = 1, 2, 4, 7
 SAMPLE_INSTANT, SAMPLE_AVERAGE, SAMPLE_RESET = 0, 1, 2
+SYNTH_STATIC_BYTES = 32 << 20
 EBIT_SORT_OVERFLOW, EBIT_GROUPS, EBIT_TARGET, EBIT_CAPACITY, EBIT_INFLOW = 1, 2, 4, 8, 16
 
 
@@ -95,7 +96,7 @@ EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "
            "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_profile_kinds",
            "dsmc_tuning", "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
            "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "closure_features",
-           "closure_blend", "dsmc_save", "dsmc_load", "dig_last_error",
+           "closure_blend", "dsmc_save", "dsmc_load", "synth_solve_static", "dig_last_error",
            "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
@@ -148,6 +149,9 @@ def load(path: str = LIB_PATH):
     L.closure_assemble.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, vp, vp, vp, vp,
                                    vp]
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
+    L.synth_solve_static.argtypes = [cp, C.POINTER(DigSynthOpts), vp, vp, vp, vp, C.c_int32,
+                                     C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     vp]
     L.dsmc_save.argtypes = [vp, vp, C.POINTER(C.c_size_t), vp]
     L.dsmc_load.argtypes = [vp, vp, C.c_size_t, vp]
     L.dig_constants.argtypes = [vp, C.c_int32, C.POINTER(C.c_double)]

@@ -10,8 +10,10 @@
 // the wall-adjacent cell) and explicit pseudo-time steps that are the same in
 // every cell, so the total mass is conserved exactly.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "dig_internal.h"
@@ -516,6 +518,66 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   *iters = it;
   *change = last;
   return DIG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of synth_solve_static: one copy of this array per GPU the library
+// runs on, held until the process ends.  Its host-side name is not a device
+// address: host code uses only the address looked up below.
+constexpr size_t kStaticSynthBytes = (size_t)DIG_SYNTH_STATIC_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticSynthBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array, looked up once per
+// device with that device current.
+dig_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return report(DIG_ERR_HIP, "synth_solve_static: hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices)
+    return report(DIG_ERR_INVALID, "synth_solve_static: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return report(DIG_ERR_HIP, "synth_solve_static: hipGetSymbolAddress(scratch) failed");
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return DIG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dig_status synth_solve_static(const dig_config* cfg, const dig_synth_opts* opts,
+                              const double* m_half, const double* hot, const uint8_t* mask,
+                              double* m_next, int32_t max_iter, double tol, int32_t* iters,
+                              double* change, dig_stream_t stream) {
+  if (!cfg) return report(DIG_ERR_INVALID, "synth_solve_static: null config");
+  if (cfg->nx < 1 || cfg->ny < 1) return report(DIG_ERR_INVALID, "synth_solve_static: bad grid");
+  const size_t need = synth_layout(cfg).total;
+  if (need > kStaticSynthBytes) {
+    static thread_local char msg[160];
+    snprintf(msg, sizeof(msg),
+             "synth_solve_static: the grid needs %zu bytes of scratch, more than the static "
+             "%zu",
+             need, kStaticSynthBytes);
+    return report(DIG_ERR_INVALID, msg);
+  }
+  void* ws = nullptr;
+  const dig_status st = static_scratch(&ws);
+  if (st != DIG_OK) return st;
+  return synth_solve(cfg, opts, m_half, hot, mask, m_next, ws, kStaticSynthBytes, max_iter, tol,
+                     iters, change, stream);
 }
 
 }  // extern "C"
