@@ -210,17 +210,28 @@ dig_status closure_assemble(dig_ctx* ctx, const double* fields_dev, const double
  * of cfg (single instance), HLLC inviscid fluxes, central viscous and heat
  * fluxes, Dirichlet walls (wall_mode 0: the config's wall temperature and
  * velocity; 1: slip and jump taken from the DSMC field's wall-adjacent cells),
- * explicit pseudo-time steps common to all cells (total mass conserved).
+ * and pseudo-time steps toward the steady state, either explicit steps
+ * common to all cells (DIG_SYNTH_EXPLICIT: total mass conserved exactly) or
+ * implicit LU-SGS steps (DIG_SYNTH_LUSGS, the scheme named in Section 4:
+ * matrix-free, with viscous spectral radii in the diagonal and a
+ * point-implicit rotational source; cells in two colours, (ix + iy) even
+ * first, so that each sweep is two parallel passes; the state scaled to the
+ * initial total mass after every step; a periodic axis needs an even cell
+ * count).  Both reach the same steady discrete solution.
  * Stops after max_iter steps or when the largest relative change of
  * (rho, u, Tt, Tr) in one step falls below tol (checked every check_every
  * steps, default 32; synchronises at each check).  workspace_dev: at least
  * dig_synth_workspace_bytes(cfg) bytes, 256-byte aligned, caller-owned.
  * Errors: DIG_ERR_INVALID (bad arguments), DIG_ERR_NUMERIC (non-finite state). */
+enum { DIG_SYNTH_EXPLICIT = 0, DIG_SYNTH_LUSGS = 1 };
 typedef struct {
   double A[4];           /* heat-flux relaxation matrix Att, Atr, Art, Arr */
-  double cfl;            /* pseudo-time step factor (explicit stability below 1) */
+  double cfl;            /* pseudo-time step factor (explicit: stability below 1;
+                            LU-SGS: local time step of cfl times the explicit bound) */
   int32_t wall_mode;     /* 0 wall values, 1 DSMC slip / jump */
   int32_t check_every;   /* convergence check period (0 = 32) */
+  int32_t scheme;        /* DIG_SYNTH_EXPLICIT or DIG_SYNTH_LUSGS */
+  int32_t reserved;      /* 0 */
 } dig_synth_opts;
 size_t dig_synth_workspace_bytes(const dig_config* cfg_host);
 dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_host,
@@ -236,7 +247,7 @@ dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_ho
  * on until the process ends, instead of a caller workspace.  The caller still
  * passes the inputs and m_next_dev.  Calls no allocation routine.  Grids
  * whose dig_synth_workspace_bytes exceed DIG_SYNTH_STATIC_BYTES (about
- * 110,000 cells) give DIG_ERR_INVALID.  Every call on one GPU shares that
+ * 80,000 cells) give DIG_ERR_INVALID.  Every call on one GPU shares that
  * GPU's array, which keeps the last call's contents (each call initialises
  * what it reads): calls that overlap in time on one GPU (other host threads,
  * other streams) race and must be serialised by the caller. */
@@ -426,16 +437,28 @@ dig_status closure_features(dig_ctx* ctx, const double* fields_dev, const double
  * with the equilibrium mask set keep HoT = 0 (NSF); cells with
  * kn_lo <= Kn_GLL < kn_hi take the network's prediction y_dev [C][7]
  * (de-standardised; sigma_zz = -(sigma_xx + sigma_yy), z components 0)
- * unless, in some component, |prediction - DSMC| exceeds
- * judge_abs + judge_rel |DSMC| in the scaled units of the targets (then the
- * DSMC-extracted term stays); all other cells keep the DSMC-extracted term.
- * hot_dev [12][C] is updated in place; src_dev [C] (nullable) receives
- * 0 NSF, 1 DSMC, 2 network, 3 network rejected. */
+ * unless the DSMC-extracted terms, as judge, reject it: in some component
+ * |prediction - DSMC| (in the targets' scaled units, sigma/p and
+ * q/(p sqrt(Tt))) exceeds judge_sigma standard errors of the DSMC term plus
+ * judge_rel |DSMC| (then the DSMC-extracted term stays).  The standard error
+ * comes from the sampling noise of the cell's time average, taken as
+ * M = N x judge_steps independent particle samples (N = the mean particle
+ * count, row 19 of fields_dev; judge_steps = the averaged steps divided by
+ * the correlation time in steps): per-particle standard deviations of the
+ * moment sums of an equilibrium cell (sqrt(4/3), 1, sqrt(4/3) for
+ * sigma xx, xy, yy; sqrt(5/2) for q_t; 1 for q_r) over sqrt(M), combined
+ * with the noise the NSF terms take from the central differences of the
+ * neighbours' mean velocity (variance Tt/M), Tt (2 Tt^2/(3 M)) and
+ * Tr (Tr^2/M), with mu and kappa from A_host (as closure_assemble).  All
+ * other cells keep the DSMC-extracted term.  hot_dev [12][C] is updated in
+ * place; src_dev [C] (nullable) receives 0 NSF, 1 DSMC, 2 network,
+ * 3 network rejected.  Errors: DIG_ERR_INVALID (null pointer, kn_lo > kn_hi,
+ * negative tolerance, judge_steps <= 0, singular A). */
 dig_status closure_blend(dig_ctx* ctx, const double* fields_dev, const double* kngll_dev,
                          const uint8_t* mask_dev, const float* y_dev,
-                         const dig_mlp_scaling* scaling_host, double kn_lo, double kn_hi,
-                         double judge_abs, double judge_rel, double* hot_dev, uint8_t* src_dev,
-                         dig_stream_t stream);
+                         const dig_mlp_scaling* scaling_host, const double* A_host, double kn_lo,
+                         double kn_hi, double judge_sigma, double judge_rel, double judge_steps,
+                         double* hot_dev, uint8_t* src_dev, dig_stream_t stream);
 
 const char* dig_last_error(void);
 void dsmc_destroy(dig_ctx* ctx);

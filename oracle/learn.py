@@ -88,11 +88,66 @@ def features(w, F, kn, scaling, hot=None):
     return f, (y if hot is not None else None)
 
 
-def blend(F, kn, mask, ypred, scaling, hot, kn_lo, kn_hi, judge_abs, judge_rel):
+# Per-particle standard deviations of the scaled DSMC-extracted terms of an
+# equilibrium cell (Maxwellian velocities, exponential rotational energy),
+# the peculiar velocity c taken about the cell's sample mean: sigma_xx/p and
+# sigma_yy/p from (2/3) c_x^2 - (c_y^2 + c_z^2)/3 (variance 4/3 T^2),
+# sigma_xy/p from c_x c_y (variance T^2); q_t/(p sqrt(T)) from
+# c_x |c|^2 / 2, which to first order is v_x |v|^2 / 2 - (5/2) T v_x
+# (variance 35/4 - 25/2 + 25/4 = 5/2, in T^3); q_r/(p sqrt(T)) from c_x er,
+# to first order v_x er - T v_x (variance 2 - 2 + 1 = 1, in T^3).
+DIRECT_SD = [math.sqrt(4.0 / 3.0), 1.0, math.sqrt(4.0 / 3.0), math.sqrt(2.5),
+             math.sqrt(2.5), 1.0, 1.0]
+
+
+def judge_se(w, F, A, judge_steps):
+    """Standard error [C, 7] of the DSMC-extracted higher-order terms of the
+    time-averaged field F (target order, scaled by p or p sqrt(Tt)) from the
+    sampling noise of M = N x judge_steps independent particle samples per
+    cell (N the mean particle count, row 19): the direct moment sum
+    (DIRECT_SD / sqrt(M)) and the NSF terms subtracted from it, whose central
+    differences over 2h carry the noise of the mean velocity (variance Tt/M),
+    Tt (2 Tt^2 / (3 M)) and Tr (Tr^2 / M) of the two neighbours."""
+    C = F.shape[1]
+    rho, tt, tr, N = F[0], F[4], F[5], F[19]
+    hx = w["lx"] / w["nx"]
+    two = w["dim"] == 2
+    ihx2 = 1.0 / (2.0 * hx * hx)
+    ihy2 = 1.0 / (2.0 * (w["ly"] / w["ny"]) ** 2) if two else 0.0
+    mu0 = w["kn"] * math.sqrt(2.0 / math.pi)
+    att, atr, art, arr = A
+    det = att * arr - atr * art
+    dr = w.get("dr", 2)
+    se = np.full((C, 7), np.inf)
+    for c in range(C):
+        if not (rho[c] > 0 and tt[c] > 0 and N[c] > 0):
+            continue
+        M = N[c] * judge_steps
+        mu = mu0 * tt[c] ** w["omega"]
+        kt = 0.5 * mu * (arr * 5.0 - atr * dr) / det
+        kr = 0.5 * mu * (-art * 5.0 + att * dr) / det
+        p = rho[c] * tt[c]
+        pq = p * math.sqrt(tt[c])
+        vu, vt, vr = tt[c] / M, 2.0 * tt[c] ** 2 / (3.0 * M), tr[c] ** 2 / M
+        nsf = [mu * mu * vu * (16.0 / 9.0 * ihx2 + 4.0 / 9.0 * ihy2) / (p * p),
+               mu * mu * vu * (ihx2 + ihy2) / (p * p),
+               mu * mu * vu * (16.0 / 9.0 * ihy2 + 4.0 / 9.0 * ihx2) / (p * p),
+               kt * kt * vt * ihx2 / (pq * pq), kt * kt * vt * ihy2 / (pq * pq),
+               kr * kr * vr * ihx2 / (pq * pq), kr * kr * vr * ihy2 / (pq * pq)]
+        for j in range(7):
+            se[c, j] = math.sqrt(DIRECT_SD[j] ** 2 / M + nsf[j])
+    return se
+
+
+def blend(w, F, kn, mask, ypred, scaling, A, hot, kn_lo, kn_hi, judge_sigma, judge_rel,
+          judge_steps):
     """Returns (new hot [12, C], source code [C]): 0 NSF, 1 DSMC, 2 network,
-    3 network rejected by the judge."""
+    3 network rejected by the judge.  Inside the band a prediction is rejected
+    when, in some component, |network - DSMC| (scaled) exceeds judge_sigma
+    standard errors of the DSMC term (judge_se) plus judge_rel |DSMC|."""
     hot = hot.copy()
     C = F.shape[1]
+    se = judge_se(w, F, A, judge_steps)
     src = np.where(mask != 0, 0, 1).astype(np.uint8)
     for c in range(C):
         rho, tt = F[0, c], F[4, c]
@@ -106,7 +161,7 @@ def blend(F, kn, mask, ypred, scaling, hot, kn_lo, kn_hi, judge_abs, judge_rel):
             s = p if j < 3 else pq
             pr[j] = (ypred[c, j] * scaling["y_std"][j] + scaling["y_mean"][j]) * s
             ds = hot[hk, c]
-            if abs(pr[j] - ds) / s > judge_abs + judge_rel * abs(ds) / s:
+            if abs(pr[j] - ds) / s > judge_sigma * se[c, j] + judge_rel * abs(ds) / s:
                 ok = False
         if not ok:
             src[c] = 3

@@ -223,6 +223,115 @@ def solve(w, m_half, hot=None, mask=None, A=None, max_iter=2000, tol=1e-5, cfl=0
     return _output(P, W), it, change
 
 
+def _euler_flux(W, axis, dr):
+    """Inviscid flux of the conservative state W along `axis` (cell values)."""
+    rho, u, tt, tr = _prims(W, dr)
+    p = rho * tt
+    un = u[axis]
+    F = np.empty_like(W)
+    F[0] = W[0] * un
+    for k in range(3):
+        F[1 + k] = W[1 + k] * un + (p if k == axis else 0.0)
+    F[4] = (W[4] + p) * un
+    F[5] = W[5] * un
+    return F
+
+
+def _neighbour(a, axis, side, periodic):
+    """Values of the neighbour on `side` (+1 or -1) along `axis` of every cell
+    (cell arrays [..., ny, nx]); zero where that neighbour is a wall."""
+    ax = -1 if axis == 0 else -2
+    out = np.roll(a, -side, axis=ax)
+    if not periodic:
+        idx = [slice(None)] * a.ndim
+        idx[ax] = -1 if side > 0 else 0
+        out[tuple(idx)] = 0.0
+    return out
+
+
+def solve_lusgs(w, m_half, hot=None, mask=None, A=None, max_iter=500, tol=1e-5, cfl=1e6,
+                wall_mode="dsmc"):
+    """Implicit pseudo-time solve of the same discrete steady equations as
+    `solve` (same residual R), by LU-SGS: one symmetric Gauss-Seidel sweep
+    pair per iteration on the approximately factored implicit operator, in
+    matrix-free form (Yoon and Jameson).
+
+    Per cell i, with r_a = |u_a| + c + 2 nu / h_a the spectral radius along
+    axis a (nu as in `solve`) and j running over the neighbours across
+    interior or periodic faces (n_ij the unit normal from i to j):
+
+      D_i dW_i + sum_j (dF_j . n_ij - r_j dW_j) / (2 h) = R_i,
+      D_i = (1 + 1/cfl) sum_a r_a / h_a   (+ 1/(Z tau) on the rotational row),
+
+    where dF_j = F(W_j + dW_j) - F(W_j) is the change of the inviscid flux of
+    the neighbour.  The cells are ordered in two colours, (i + j) even first
+    (a red-black ordering; every neighbour of a cell has the other colour):
+    the lower sweep gives dW* = R / D on the first colour, then
+    dW* = (R - sum_j (dF*_j . n_ij - r_j dW*_j) / (2h)) / D on the second;
+    the upper sweep keeps dW = dW* on the second colour and sets
+    dW = dW* - sum_j (dF_j . n_ij - r_j dW_j) / (2h D) on the first.
+    After the update, every conservative variable is scaled by the ratio of
+    the initial to the current total mass (the implicit operator is not
+    conservative; the box is closed or periodic, so the steady state keeps
+    the initial mass).  Stops as `solve` does.  Periodic axes need an even
+    cell count (two colours).  Returns (m_next [6, C], iterations, change)."""
+    P = _prepare(w, m_half, hot, mask, A, wall_mode)
+    W = P["W"]
+    nx, ny, two, dr = P["nx"], P["ny"], P["two"], P["dr"]
+    axes = (0, 1) if two else (0,)
+    per = {a: P["bct"][2 * a] == "periodic" for a in axes}
+    for a in axes:
+        if per[a] and (nx if a == 0 else ny) % 2:
+            raise ValueError("periodic axes need an even cell count")
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    first = ((ii + jj) % 2 == 0)          # first colour
+    mass0 = W[0].sum()
+    it = 0
+    change = np.inf
+    for it in range(1, max_iter + 1):
+        R, inv_dt, prim, tau = _residual(P, W)
+        rho, u, tt, tr = prim
+        mu = P["mu0"] * tt ** P["om"]
+        kt_c, kr_c = _conductivities(mu, P["A"], dr)
+        c = np.sqrt(P["gam"] * tt)
+        nu = np.maximum(4.0 * mu / (3.0 * rho), P["gam"] * (kt_c + kr_c) / (rho * P["cv"]))
+        h = {0: P["hx"], 1: P["hy"]}
+        r = {a: np.abs(u[a]) + c + 2.0 * nu / h[a] for a in axes}
+        D = np.zeros_like(W)
+        for a in axes:
+            D += (1.0 + 1.0 / cfl) * r[a] / h[a]
+        D[5] += 1.0 / (P["Z"] * tau)
+        F = {a: _euler_flux(W, a, dr) for a in axes}
+
+        def offdiag(dW):
+            """sum_j (dF_j . n_ij - r_j dW_j) / (2 h) of every cell from the
+            neighbours' increments dW (zero where not yet known)."""
+            out = np.zeros_like(W)
+            for a in axes:
+                dF = _euler_flux(W + dW, a, dr) - F[a]
+                for side in (1, -1):
+                    t = side * dF - r[a] * dW
+                    out += _neighbour(t, a, side, per[a]) / (2.0 * h[a])
+            return out
+
+        dW = np.zeros_like(W)
+        # lower sweep: first colour, then second
+        dW[:, first] = R[:, first] / D[:, first]
+        rhs = R - offdiag(np.where(first, dW, 0.0))
+        dW[:, ~first] = rhs[:, ~first] / D[:, ~first]
+        # upper sweep: second colour unchanged, then first
+        corr = offdiag(np.where(first, 0.0, dW))
+        dW[:, first] = dW[:, first] - corr[:, first] / D[:, first]
+        Wn = W + dW
+        Wn = Wn * (mass0 / Wn[0].sum())
+        ch = _relative_change(prim, _prims(Wn, dr))
+        W = Wn
+        change = ch
+        if ch < tol:
+            break
+    return _output(P, W), it, change
+
+
 def face_fluxes(w, fields, axis, hot=None, A=None, wall_mode="wall"):
     """Total flux (inviscid HLLC + NSF viscous and heat + masked higher-order
     terms) through every face normal to `axis` for the primitive fields

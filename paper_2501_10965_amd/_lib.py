@@ -13,6 +13,7 @@ GEOM = {"box": 0, "annulus": 1}
 STAGE_MOVE, STAGE_SORT, STAGE_COLLIDE, STAGE_ALL = 1, 2, 4, 7
 SAMPLE_INSTANT, SAMPLE_AVERAGE, SAMPLE_RESET = 0, 1, 2
 SYNTH_STATIC_BYTES = 32 << 20
+SYNTH_SCHEMES = {"explicit": 0, "lusgs": 1}
 EBIT_SORT_OVERFLOW, EBIT_GROUPS, EBIT_TARGET, EBIT_CAPACITY, EBIT_INFLOW = 1, 2, 4, 8, 16
 
 
@@ -45,7 +46,7 @@ class DigLayout(C.Structure):
 
 class DigSynthOpts(C.Structure):
     _fields_ = [("A", C.c_double * 4), ("cfl", C.c_double), ("wall_mode", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("scheme", C.c_int32), ("reserved", C.c_int32)]
 
 
 class DigCounters(C.Structure):
@@ -138,8 +139,9 @@ def load(path: str = LIB_PATH):
     L.mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_int64, vp]
     L.mlp_destroy.argtypes = [vp]
     L.closure_features.argtypes = [vp, vp, vp, vp, C.POINTER(DigMlpScaling), vp, vp, vp]
-    L.closure_blend.argtypes = [vp, vp, vp, vp, vp, C.POINTER(DigMlpScaling), C.c_double,
-                                C.c_double, C.c_double, C.c_double, vp, vp, vp]
+    L.closure_blend.argtypes = [vp, vp, vp, vp, vp, C.POINTER(DigMlpScaling),
+                                C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double,
+                                C.c_double, C.c_double, vp, vp, vp]
     L.mlp_destroy.restype = None
     L.dsmc_tuning.argtypes = [vp, C.POINTER(DigTuning), C.POINTER(DigTuning)]
     L.dsmc_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(DigTuning), vp]

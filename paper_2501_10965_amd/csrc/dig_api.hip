@@ -851,17 +851,22 @@ dig_status closure_features(dig_ctx* c, const double* fields, const double* kngl
 
 dig_status closure_blend(dig_ctx* c, const double* fields, const double* kngll,
                          const uint8_t* mask, const float* y, const dig_mlp_scaling* scaling,
-                         double kn_lo, double kn_hi, double judge_abs, double judge_rel,
-                         double* hot, uint8_t* src, dig_stream_t stream) {
+                         const double* A, double kn_lo, double kn_hi, double judge_sigma,
+                         double judge_rel, double judge_steps, double* hot, uint8_t* src,
+                         dig_stream_t stream) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
-  if (!fields || !kngll || !mask || !y || !hot) return fail(DIG_ERR_INVALID, "null argument");
-  if (!(kn_lo <= kn_hi) || !(judge_abs >= 0.0) || !(judge_rel >= 0.0))
+  if (!fields || !kngll || !mask || !y || !hot || !A)
+    return fail(DIG_ERR_INVALID, "null argument");
+  if (!(kn_lo <= kn_hi) || !(judge_sigma >= 0.0) || !(judge_rel >= 0.0) || !(judge_steps > 0.0))
     return fail(DIG_ERR_INVALID, "bad band or judge tolerance");
+  const double det = A[0] * A[3] - A[1] * A[2];
+  if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
   MlpScale sc;
   dig_status st = scaling_of(scaling, &sc);
   if (st != DIG_OK) return st;
-  HIP_TRY(launch_learn_blend(args(c), fields, kngll, mask, y, sc, kn_lo, kn_hi, judge_abs,
-                             judge_rel, hot, src, (hipStream_t)stream));
+  const JudgeGas J{A[0], A[1], A[2], A[3], det};
+  HIP_TRY(launch_learn_blend(args(c), fields, kngll, mask, y, sc, J, kn_lo, kn_hi, judge_sigma,
+                             judge_rel, judge_steps, hot, src, (hipStream_t)stream));
   return DIG_OK;
 }
 

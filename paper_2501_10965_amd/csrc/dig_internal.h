@@ -133,9 +133,14 @@ struct MlpScale {
 hipError_t launch_learn_features(const StepArgs& a, const double* F, const double* kn,
                                  const double* hot, const MlpScale& sc, float* x, float* t,
                                  hipStream_t s);
+// Heat-flux relaxation matrix A of the judge's NSF noise (det = Att Arr - Atr Art).
+struct JudgeGas {
+  double Att, Atr, Art, Arr, det;
+};
 hipError_t launch_learn_blend(const StepArgs& a, const double* F, const double* kn,
                               const uint8_t* mask, const float* y, const MlpScale& sc,
-                              double kn_lo, double kn_hi, double judge_abs, double judge_rel,
+                              const JudgeGas& J, double kn_lo, double kn_hi,
+                              double judge_sigma, double judge_rel, double judge_steps,
                               double* hot, uint8_t* src, hipStream_t s);
 
 // Sets the thread-local message returned by dig_last_error; returns s.

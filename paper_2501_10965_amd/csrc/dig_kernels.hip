@@ -2106,26 +2106,59 @@ __global__ void k_learn_features(StepArgs a, const double* F, const double* kn,
 // more than judge_abs + judge_rel |DSMC| in some component (then DSMC);
 // otherwise the DSMC-extracted term.  src: 0 NSF, 1 DSMC, 2 network,
 // 3 network rejected.
+// Judge of the learned closure: standard error of the scaled DSMC-extracted
+// term j of a cell from its sampling noise, M = N judge_steps independent
+// particle samples (N the cell's mean particle count): the moment sum
+// (per-particle standard deviations of an equilibrium cell, the peculiar
+// velocity about the cell mean) and the NSF terms subtracted from it, whose
+// central differences over 2h carry the noise of the neighbours' mean
+// velocity (variance Tt/M), Tt (2 Tt^2/(3M)) and Tr (Tr^2/M).
+__device__ void judge_se(const InstParam& I, double rho, double tt, double tr, double N,
+                         double judge_steps, const JudgeGas& J, double se[7]) {
+  const double M = N * judge_steps;
+  const double ihx2 = 1.0 / (2.0 * I.dx * I.dx);
+  const double ihy2 = I.dim == 2 ? 1.0 / (2.0 * I.dy * I.dy) : 0.0;
+  const double mu = I.mu0 * pow(tt, I.omega);
+  const double kt = 0.5 * mu * (J.Arr * 5.0 - J.Atr * I.dr) / J.det;
+  const double kr = 0.5 * mu * (-J.Art * 5.0 + J.Att * I.dr) / J.det;
+  const double p = rho * tt, pq = p * sqrt(tt);
+  const double vu = tt / M, vt = 2.0 * tt * tt / (3.0 * M), vr = tr * tr / M;
+  const double nsf[7] = {mu * mu * vu * (16.0 / 9.0 * ihx2 + 4.0 / 9.0 * ihy2) / (p * p),
+                         mu * mu * vu * (ihx2 + ihy2) / (p * p),
+                         mu * mu * vu * (16.0 / 9.0 * ihy2 + 4.0 / 9.0 * ihx2) / (p * p),
+                         kt * kt * vt * ihx2 / (pq * pq), kt * kt * vt * ihy2 / (pq * pq),
+                         kr * kr * vr * ihx2 / (pq * pq), kr * kr * vr * ihy2 / (pq * pq)};
+  const double d2[7] = {4.0 / 3.0, 1.0, 4.0 / 3.0, 2.5, 2.5, 1.0, 1.0};
+  for (int j = 0; j < 7; ++j) se[j] = sqrt(d2[j] / M + nsf[j]);
+}
+
 __global__ void k_learn_blend(StepArgs a, const double* F, const double* kn,
-                              const uint8_t* mask, const float* yp, MlpScale sc, double kn_lo,
-                              double kn_hi, double judge_abs, double judge_rel, double* hot,
-                              uint8_t* src) {
+                              const uint8_t* mask, const float* yp, MlpScale sc, JudgeGas J,
+                              double kn_lo, double kn_hi, double judge_sigma, double judge_rel,
+                              double judge_steps, double* hot, uint8_t* src) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = a.ncell;
   if (c >= C) return;
   const double rho = F[c], tt = F[4 * C + c];
+  const double N = F[19 * (int64_t)C + c];
   uint8_t s = mask[c] ? 0 : 1;
   const double k = kn[c];
   if (!mask[c] && rho > 0.0 && tt > 0.0 && k >= kn_lo && k < kn_hi) {
     const double p = rho * tt, pq = p * sqrt(tt);
     const int hk[7] = {0, 3, 1, 6, 7, 9, 10};
+    double se[7];
+    if (N > 0.0) {
+      judge_se(a.params[a.cell_inst[c]], rho, tt, F[5 * C + c], N, judge_steps, J, se);
+    } else {
+      for (int j = 0; j < 7; ++j) se[j] = INFINITY;
+    }
     double pr[7];
     bool ok = true;
     for (int j = 0; j < 7; ++j) {
       const double sc_j = j < 3 ? p : pq;
       pr[j] = ((double)yp[(int64_t)c * 7 + j] * sc.y_std[j] + sc.y_mean[j]) * sc_j;
       const double ds = hot[(int64_t)hk[j] * C + c];
-      if (fabs(pr[j] - ds) / sc_j > judge_abs + judge_rel * fabs(ds) / sc_j) ok = false;
+      if (fabs(pr[j] - ds) / sc_j > judge_sigma * se[j] + judge_rel * fabs(ds) / sc_j) ok = false;
     }
     if (ok) {
       hot[0 * (int64_t)C + c] = pr[0];
@@ -2364,10 +2397,12 @@ hipError_t launch_learn_features(const StepArgs& a, const double* F, const doubl
 
 hipError_t launch_learn_blend(const StepArgs& a, const double* F, const double* kn,
                               const uint8_t* mask, const float* y, const MlpScale& sc,
-                              double kn_lo, double kn_hi, double judge_abs, double judge_rel,
+                              const JudgeGas& J, double kn_lo, double kn_hi,
+                              double judge_sigma, double judge_rel, double judge_steps,
                               double* hot, uint8_t* src, hipStream_t s) {
   hipLaunchKernelGGL(k_learn_blend, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, F, kn,
-                     mask, y, sc, kn_lo, kn_hi, judge_abs, judge_rel, hot, src);
+                     mask, y, sc, J, kn_lo, kn_hi, judge_sigma, judge_rel, judge_steps, hot,
+                     src);
   return hipGetLastError();
 }
 

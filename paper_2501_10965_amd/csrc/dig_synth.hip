@@ -275,34 +275,47 @@ __device__ __forceinline__ void red_max(unsigned long long* a, double v) {
   atomicMax(a, (unsigned long long)__double_as_longlong(v));
 }
 
+// Steady residual of cell c (flux differences over the cell plus the
+// rotational relaxation source); returns the relaxation time tau.
+__device__ double cell_residual(const SynthGrid& g, const SynthArrays& s, int c, const Prim& p,
+                                double R[6]) {
+  const int ix = c % g.nx, iy = c / g.nx;
+  const int nfx = (g.nx + 1) * g.ny;
+  for (int k = 0; k < 6; ++k) {
+    const double* Fx = s.Fx + (size_t)k * nfx;
+    R[k] = -(Fx[ix + 1 + (g.nx + 1) * iy] - Fx[ix + (g.nx + 1) * iy]) / g.hx;
+    if (g.dim == 2) {
+      const double* Fy = s.Fy + (size_t)k * (g.nx * (g.ny + 1));
+      R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.hy;
+    }
+  }
+  const double mu = g.mu0 * pow(p.tt, g.omega);
+  const double tau = mu / (p.rho * p.tt);
+  const double T = (3.0 * p.tt + g.dr * p.tr) / (3.0 + g.dr);
+  R[5] += 0.5 * g.dr * p.rho * (T - p.tr) / (g.zrot * tau);
+  return tau;
+}
+
+// Largest relative change of (rho, u / sqrt(Tt), Tt, Tr) from p to q.
+__device__ double rel_change(const Prim& p, const Prim& q) {
+  double ch = fabs(q.rho - p.rho) / p.rho;
+  for (int k = 0; k < 3; ++k) ch = fmax(ch, fabs(q.u[k] - p.u[k]) / sqrt(p.tt));
+  ch = fmax(ch, fabs(q.tt - p.tt) / p.tt);
+  return fmax(ch, fabs(q.tr - p.tr) / fmax(p.tr, 1e-300));
+}
+
 __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
   double dtb = 0.0, ch = 0.0;
   if (c < C) {
     const double dtau = __longlong_as_double((long long)s.red[(it & 1) * 2 + 0]);
-    const int ix = c % g.nx, iy = c / g.nx;
     const Prim p = prim_of(s.W, C, c, g.dr);
     double R[6];
-    const int nfx = (g.nx + 1) * g.ny;
-    for (int k = 0; k < 6; ++k) {
-      const double* Fx = s.Fx + (size_t)k * nfx;
-      R[k] = -(Fx[ix + 1 + (g.nx + 1) * iy] - Fx[ix + (g.nx + 1) * iy]) / g.hx;
-      if (g.dim == 2) {
-        const double* Fy = s.Fy + (size_t)k * (g.nx * (g.ny + 1));
-        R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.hy;
-      }
-    }
-    const double mu = g.mu0 * pow(p.tt, g.omega);
-    const double tau = mu / (p.rho * p.tt);
-    const double T = (3.0 * p.tt + g.dr * p.tr) / (3.0 + g.dr);
-    R[5] += 0.5 * g.dr * p.rho * (T - p.tr) / (g.zrot * tau);
+    cell_residual(g, s, c, p, R);
     for (int k = 0; k < 6; ++k) s.Wn[k * C + c] = s.W[k * C + c] + dtau * R[k];
     const Prim q = prim_of(s.Wn, C, c, g.dr);
-    ch = fabs(q.rho - p.rho) / p.rho;
-    for (int k = 0; k < 3; ++k) ch = fmax(ch, fabs(q.u[k] - p.u[k]) / sqrt(p.tt));
-    ch = fmax(ch, fabs(q.tt - p.tt) / p.tt);
-    ch = fmax(ch, fabs(q.tr - p.tr) / fmax(p.tr, 1e-300));
+    ch = rel_change(p, q);
     dtb = dt_bound(g, q);
   }
   // block reductions, then one atomic per block
@@ -325,6 +338,200 @@ __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
     }
     red_min(&s.red[((it + 1) & 1) * 2 + 0], mn);
     red_max(&s.red[((it + 1) & 1) * 2 + 1], mx);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Implicit pseudo-time steps by LU-SGS (the paper's scheme for the synthetic
+// equations), matrix-free in the form of Yoon and Jameson: per cell
+//   D dW_i + sum_j (dF_j . n_ij - r_j dW_j) / (2 h) = R_i,
+//   D = (1 + 1/cfl) sum_a r_a / h_a  (+ 1/(Z tau) on the rotational row),
+// r_a = |u_a| + c + 2 nu / h_a, dF_j = F(W_j + dW_j) - F(W_j) the change of
+// the neighbour's inviscid flux, j over the neighbours across interior and
+// periodic faces.  The cells are ordered in two colours ((ix + iy) even
+// first; every neighbour has the other colour), so both sweeps are two
+// parallel passes: lower sweep dW = R / D on the first colour (k_lusgs_cells)
+// and dW = (R - sum_j ...) / D on the second (k_lusgs_lower); upper sweep
+// dW -= sum_j ... / D on the first colour (k_lusgs_upper).  The new state is
+// then scaled by the ratio of the initial to the current total mass
+// (k_lusgs_scale): the implicit operator is not conservative, the steady
+// state of a closed or periodic box keeps the initial mass.
+
+struct LusgsArrays {
+  double* dW;    // [6][C] increments
+  double* R;     // [6][C] steady residuals
+  double* D;     // [2][C] diagonal (rows 0-4, row 5)
+  double* rad;   // [2][C] spectral radii along x and y
+  double* part;  // [nb] per-block mass partial sums; [nb] the initial mass
+  unsigned long long* chg;  // [2] relative change (max) by iteration parity
+  int nb;        // blocks of the cell kernels
+};
+
+__device__ __forceinline__ bool first_colour(const SynthGrid& g, int c) {
+  return ((c % g.nx + c / g.nx) & 1) == 0;
+}
+
+template <int axis>
+__device__ __forceinline__ void euler_of(const double U[6], int dr, double F[6]) {
+  Prim p;
+  p.rho = U[0];
+  for (int k = 0; k < 3; ++k) p.u[k] = U[1 + k] / p.rho;
+  p.tr = 2.0 * U[5] / (dr * p.rho);
+  const double uu = p.u[0] * p.u[0] + p.u[1] * p.u[1] + p.u[2] * p.u[2];
+  p.tt = (U[4] / p.rho - 0.5 * uu - 0.5 * dr * p.tr) * 2.0 / 3.0;
+  euler_flux<axis>(U, p, F);
+}
+
+// sum_j (dF_j . n_ij - r_j dW_j) / (2 h) over the neighbours of cell c of
+// the other colour (their increments in L.dW are final).
+template <int axis>
+__device__ void add_neighbours(const SynthGrid& g, const SynthArrays& s, const LusgsArrays& L,
+                               int c, double acc[6]) {
+  const int C = g.nx * g.ny;
+  const int n = axis == 0 ? g.nx : g.ny;
+  const int i = axis == 0 ? c % g.nx : c / g.nx;
+  const double h = axis == 0 ? g.hx : g.hy;
+  for (int side = 1; side >= -1; side -= 2) {
+    int j = i + side;
+    if (j < 0 || j >= n) {
+      if (!g.bc_periodic[axis]) continue;
+      j = (j + n) % n;
+    }
+    const int cj = axis == 0 ? j + g.nx * (c / g.nx) : (c % g.nx) + g.nx * j;
+    double U[6], V[6], F0[6], F1[6];
+    for (int k = 0; k < 6; ++k) {
+      U[k] = s.W[(size_t)k * C + cj];
+      V[k] = U[k] + L.dW[(size_t)k * C + cj];
+    }
+    euler_of<axis>(U, g.dr, F0);
+    euler_of<axis>(V, g.dr, F1);
+    const double r = L.rad[(size_t)axis * C + cj];
+    for (int k = 0; k < 6; ++k) {
+      const double t = (double)side * (F1[k] - F0[k]) - r * L.dW[(size_t)k * C + cj];
+      acc[k] += t / (2.0 * h);
+    }
+  }
+}
+
+// Residual, diagonal and spectral radii of every cell; lower sweep on the
+// first colour.  Block 0 also resets this iteration's change slot (safe in
+// stream order: its last reader, the host check of iteration it - 2, and its
+// last writer, k_lusgs_scale of iteration it - 2, precede this launch).
+__global__ void k_lusgs_cells(SynthGrid g, SynthArrays s, LusgsArrays L, int it) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  if (c == 0) L.chg[it & 1] = 0ull;
+  if (c >= C) return;
+  const Prim p = prim_of(s.W, C, c, g.dr);
+  double R[6];
+  const double tau = cell_residual(g, s, c, p, R);
+  const double mu = g.mu0 * pow(p.tt, g.omega);
+  double kt, kr;
+  conductivities(g, mu, &kt, &kr);
+  const double cs = sqrt(g.gam * p.tt);
+  const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
+  const double rx = fabs(p.u[0]) + cs + 2.0 * nu / g.hx;
+  double d = rx / g.hx;
+  double ry = 0.0;
+  if (g.dim == 2) {
+    ry = fabs(p.u[1]) + cs + 2.0 * nu / g.hy;
+    d += ry / g.hy;
+  }
+  const double D0 = (1.0 + 1.0 / g.cfl) * d;
+  const double D5 = D0 + 1.0 / (g.zrot * tau);
+  for (int k = 0; k < 6; ++k) L.R[(size_t)k * C + c] = R[k];
+  L.D[c] = D0;
+  L.D[C + c] = D5;
+  L.rad[c] = rx;
+  L.rad[C + c] = ry;
+  if (first_colour(g, c))
+    for (int k = 0; k < 6; ++k) L.dW[(size_t)k * C + c] = R[k] / (k == 5 ? D5 : D0);
+}
+
+// Lower sweep on the second colour.
+__global__ void k_lusgs_lower(SynthGrid g, SynthArrays s, LusgsArrays L) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  if (c >= C || first_colour(g, c)) return;
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  add_neighbours<0>(g, s, L, c, acc);
+  if (g.dim == 2) add_neighbours<1>(g, s, L, c, acc);
+  for (int k = 0; k < 6; ++k)
+    L.dW[(size_t)k * C + c] = (L.R[(size_t)k * C + c] - acc[k]) / L.D[(k == 5 ? C : 0) + c];
+}
+
+// Fixed-order block sum (the same tree in every block and every call).
+__device__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  return t;
+}
+
+// Upper sweep on the first colour, then the new state W + dW of every cell
+// and the per-block sums of its mass.
+__global__ void k_lusgs_upper(SynthGrid g, SynthArrays s, LusgsArrays L) {
+  __shared__ double sh[16];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  double rho_new = 0.0;
+  if (c < C) {
+    double dW[6];
+    for (int k = 0; k < 6; ++k) dW[k] = L.dW[(size_t)k * C + c];
+    if (first_colour(g, c)) {
+      double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      add_neighbours<0>(g, s, L, c, acc);
+      if (g.dim == 2) add_neighbours<1>(g, s, L, c, acc);
+      for (int k = 0; k < 6; ++k) dW[k] = dW[k] - acc[k] / L.D[(k == 5 ? C : 0) + c];
+    }
+    for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] = s.W[(size_t)k * C + c] + dW[k];
+    rho_new = s.Wn[c];
+  }
+  const double t = block_sum(rho_new, sh);
+  if (threadIdx.x == 0) L.part[blockIdx.x] = t;
+}
+
+// Initial total mass from the start state (one block, fixed order).
+__global__ void k_lusgs_mass0(SynthGrid g, const double* W, LusgsArrays L) {
+  __shared__ double sh[16];
+  const int C = g.nx * g.ny;
+  double v = 0.0;
+  for (int b = 0; b < L.nb; ++b) {
+    const int c = b * (int)blockDim.x + threadIdx.x;
+    const double t = block_sum(c < C ? W[c] : 0.0, sh);
+    if (threadIdx.x == 0) v += t;
+  }
+  if (threadIdx.x == 0) L.part[L.nb] = v;
+}
+
+// Scale the new state to the initial mass; relative change of the iteration.
+__global__ void k_lusgs_scale(SynthGrid g, SynthArrays s, LusgsArrays L, int it) {
+  __shared__ double s_scale;
+  __shared__ double s_max[16];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = g.nx * g.ny;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int b = 0; b < L.nb; ++b) m += L.part[b];
+    s_scale = L.part[L.nb] / m;
+  }
+  __syncthreads();
+  double ch = 0.0;
+  if (c < C) {
+    const Prim p = prim_of(s.W, C, c, g.dr);
+    for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] *= s_scale;
+    ch = rel_change(p, prim_of(s.Wn, C, c, g.dr));
+  }
+  for (int off = 32; off > 0; off >>= 1) ch = fmax(ch, __shfl_xor(ch, off));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = ch;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) ch = fmax(ch, s_max[k]);
+    red_max(&L.chg[it & 1], ch);
   }
 }
 
@@ -393,8 +600,9 @@ thread_local std::string g_serr;
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct SynthLayout {
-  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, total;
+  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, total;
 };
+constexpr int kSynthBlock = 256;
 
 SynthLayout synth_layout(const dig_config* c) {
   const size_t C = (size_t)c->nx * c->ny;
@@ -414,6 +622,13 @@ SynthLayout synth_layout(const dig_config* c) {
   L.wall = take(8 * 4 * 5 * nmax);
   L.wcfg = take(8 * 16);
   L.red = take(8 * 4);
+  // LU-SGS increments, residuals, diagonal, spectral radii, mass partials
+  L.dW = take(8 * 6 * C);
+  L.R = take(8 * 6 * C);
+  L.D = take(8 * 2 * C);
+  L.rad = take(8 * 2 * C);
+  L.part = take(8 * ((C + kSynthBlock - 1) / kSynthBlock + 1));
+  L.chg = take(8 * 2);
   L.total = o;
   return L;
 }
@@ -435,11 +650,18 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   if (cfg->dim == 1 && cfg->ny != 1) return DIG_ERR_INVALID;
   if (cfg->geometry != DIG_GEOM_BOX) return report(DIG_ERR_INVALID, "synth_solve: box only");
   if (max_iter < 0 || !(opts->cfl > 0.0)) return DIG_ERR_INVALID;
+  if (opts->scheme != DIG_SYNTH_EXPLICIT && opts->scheme != DIG_SYNTH_LUSGS)
+    return report(DIG_ERR_INVALID, "synth_solve: unknown scheme");
   const SynthLayout L = synth_layout(cfg);
   if (ws_bytes < L.total) return DIG_ERR_INVALID;
   for (int ax = 0; ax < cfg->dim; ++ax)
     if ((cfg->bc[2 * ax].type == DIG_BC_PERIODIC) != (cfg->bc[2 * ax + 1].type == DIG_BC_PERIODIC))
       return DIG_ERR_INVALID;
+  // two colours: a periodic axis needs an even cell count
+  if (opts->scheme == DIG_SYNTH_LUSGS)
+    for (int ax = 0; ax < cfg->dim; ++ax)
+      if (cfg->bc[2 * ax].type == DIG_BC_PERIODIC && ((ax == 0 ? cfg->nx : cfg->ny) & 1))
+        return report(DIG_ERR_INVALID, "synth_solve: LU-SGS needs an even count on a periodic axis");
   hipStream_t s = (hipStream_t)stream;
   unsigned char* w = (unsigned char*)workspace;
   SynthGrid g;
@@ -477,7 +699,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   unsigned long long* red = (unsigned long long*)(w + L.red);
   if (hipMemcpyAsync(dwcfg, wcfg, sizeof(wcfg), hipMemcpyHostToDevice, s) != hipSuccess)
     return DIG_ERR_HIP;
-  const int bs = 256, nb = (C + bs - 1) / bs;
+  const int bs = kSynthBlock, nb = (C + bs - 1) / bs;
   hipLaunchKernelGGL(k_synth_mask_hot, dim3(nb), dim3(bs), 0, s, hot, mask, H, C);
   // parity-1 reduction slots: dtau (min, from +inf; +inf and 0 have the bit
   // patterns of the FP64 values) and the change (max, from 0)
@@ -491,6 +713,42 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   double* nxt = W1;
   int it = 0;
   double last = INFINITY;
+  if (opts->scheme == DIG_SYNTH_LUSGS) {
+    LusgsArrays la{(double*)(w + L.dW), (double*)(w + L.R), (double*)(w + L.D),
+                   (double*)(w + L.rad), (double*)(w + L.part),
+                   (unsigned long long*)(w + L.chg), nb};
+    hipLaunchKernelGGL(k_lusgs_mass0, dim3(1), dim3(bs), 0, s, g, (const double*)W0, la);
+    for (it = 1; it <= max_iter; ++it) {
+      SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
+      const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
+      hipLaunchKernelGGL(k_synth_flux, dim3((nft + bs - 1) / bs), dim3(bs), 0, s, g, a, it);
+      hipLaunchKernelGGL(k_lusgs_cells, dim3(nb), dim3(bs), 0, s, g, a, la, it);
+      hipLaunchKernelGGL(k_lusgs_lower, dim3(nb), dim3(bs), 0, s, g, a, la);
+      hipLaunchKernelGGL(k_lusgs_upper, dim3(nb), dim3(bs), 0, s, g, a, la);
+      hipLaunchKernelGGL(k_lusgs_scale, dim3(nb), dim3(bs), 0, s, g, a, la, it);
+      double* t = cur;
+      cur = nxt;
+      nxt = t;
+      if (it % check == 0 || it == max_iter) {
+        unsigned long long bits = 0;
+        if (hipMemcpyAsync(&bits, la.chg + (it & 1), 8, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return DIG_ERR_HIP;
+        double v;
+        memcpy(&v, &bits, 8);
+        last = v;
+        if (!(v >= 0.0)) return DIG_ERR_NUMERIC;
+        if (v < tol) break;
+      }
+    }
+    if (it > max_iter) it = max_iter;
+    hipLaunchKernelGGL(k_synth_out, dim3(nb), dim3(bs), 0, s, g, cur, m_next);
+    if (hipGetLastError() != hipSuccess) return DIG_ERR_HIP;
+    *iters = it;
+    *change = last;
+    return DIG_OK;
+  }
   for (it = 1; it <= max_iter; ++it) {
     SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
     const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);

@@ -238,14 +238,18 @@ class DSMC:
         return x, t
 
     def blend(self, fields, kngll, mask, y, scaling: dict, hot: torch.Tensor, kn_lo: float,
-              kn_hi: float, judge_abs: float, judge_rel: float):
-        """Three-band closure in place on hot; returns the per-cell source code."""
+              kn_hi: float, judge_sigma: float, judge_rel: float, judge_steps: float, A=None):
+        """Three-band closure in place on hot; returns the per-cell source code.
+        judge_steps: independent samples per particle in the averaged fields."""
         src = torch.empty(self.ncell, dtype=torch.uint8, device=self.device)
         sc = L.DigMlpScaling.of(scaling)
+        om = self.workloads[0]["omega"]
+        A = A if A is not None else (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * om))
+        a = (C.c_double * 4)(*[float(v) for v in A])
         L.check(self.lib.closure_blend(
             self.ctx, _ptr(fields.contiguous()), _ptr(kngll.contiguous()), _ptr(mask.contiguous()),
-            _ptr(y.contiguous()), C.byref(sc), float(kn_lo), float(kn_hi), float(judge_abs),
-            float(judge_rel), _ptr(hot), _ptr(src), _stream()))
+            _ptr(y.contiguous()), C.byref(sc), a, float(kn_lo), float(kn_hi), float(judge_sigma),
+            float(judge_rel), float(judge_steps), _ptr(hot), _ptr(src), _stream()))
         return src
 
     def profile(self, mode: str, kinds=None, every: int = 1):
@@ -272,12 +276,15 @@ class DSMC:
 
 
 def synth_solve(w: dict, m_half: torch.Tensor, hot: torch.Tensor | None = None,
-                mask: torch.Tensor | None = None, A=None, cfl: float = 0.5,
+                mask: torch.Tensor | None = None, A=None, cfl: float | None = None,
                 wall_mode: str = "dsmc", max_iter: int = 2000, tol: float = 1e-5,
-                check_every: int = 128):
+                check_every: int = 128, scheme: str = "explicit"):
     """Synthetic-equation solve on the GPU; returns (m_next [6, C], iterations,
-    last relative change).  The change is checked every check_every
+    last relative change).  scheme "explicit" (cfl default 0.5) or "lusgs"
+    (implicit, cfl default 1e6).  The change is checked every check_every
     iterations (each check synchronises the host)."""
+    if cfl is None:
+        cfl = 0.5 if scheme == "explicit" else 1e6
     lib = L.load()
     cfg = L.make_config(w)
     nc = w["nx"] * w.get("ny", 1)
@@ -292,6 +299,7 @@ def synth_solve(w: dict, m_half: torch.Tensor, hot: torch.Tensor | None = None,
     opts.cfl = float(cfl)
     opts.wall_mode = {"wall": 0, "dsmc": 1}[wall_mode]
     opts.check_every = int(check_every)
+    opts.scheme = L.SYNTH_SCHEMES[scheme]
     m = m_half.contiguous()
     out = torch.empty((6, nc), dtype=torch.float64, device=dev)
     h = hot.contiguous() if hot is not None else None

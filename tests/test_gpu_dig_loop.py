@@ -48,7 +48,7 @@ def test_dig_with_learned_closure_hook():
     w = wl.cavity_2d(seed=93, n=16, ppc=30, kn=0.1)
     say("case dig learned hook")
     net = MLP(wl2.mlp_init(3), max_batch=64)
-    hook = learn.LearnedClosure(net, learn.UNIT_SCALING, kn_lo=0.0, judge_abs=1e9)
+    hook = learn.LearnedClosure(net, learn.UNIT_SCALING, kn_lo=0.0, judge_sigma=1e9)
     d = DIG(w, ns=10, n_m=200, closure=hook)
     for _ in range(2):
         f = np_(d.cycle())

@@ -34,8 +34,10 @@ def _fields(w, seed):
     F[4] = 1.0 + 0.2 * rng.random(C)
     F[5] = 1.0 + 0.2 * rng.random(C)
     F[6:18] = 0.05 * rng.standard_normal((12, C))
+    F[19] = 20.0 + 40.0 * rng.random(C)  # mean particle counts
     F[0, 7] = 0.0  # an empty cell
     F[4, 7] = 0.0
+    F[19, 7] = 0.0
     return F
 
 
@@ -76,12 +78,13 @@ def test_blend_matches_oracle():
           * rng.standard_normal((C, 7))).astype(np.float32)
     kn_lo, kn_hi = float(np.quantile(kn[np.isfinite(kn)], 0.2)), \
         float(np.quantile(kn[np.isfinite(kn)], 0.8))
-    ref, src_ref = olearn.blend(F, kn, mask, yo.astype(np.float64), sc, hot, kn_lo, kn_hi, 0.3,
-                                0.5)
+    ref, src_ref = olearn.blend(w, F, kn, mask, yo.astype(np.float64), sc, A, hot, kn_lo,
+                                kn_hi, 3.0, 0.1, 5.0)
     sim = DSMC(w)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda")  # noqa: E731
     h = dev(hot)
-    src = sim.blend(dev(F), dev(kn), dev(mask), dev(yo), sc, h, kn_lo, kn_hi, 0.3, 0.5)
+    src = sim.blend(dev(F), dev(kn), dev(mask), dev(yo), sc, h, kn_lo, kn_hi, 3.0, 0.1, 5.0,
+                    A=A)
     np.testing.assert_array_equal(np_(src), src_ref)
     assert set(np.unique(src_ref)) >= {1, 2, 3}
     np.testing.assert_allclose(np_(h), ref, rtol=1e-12, atol=1e-15)
@@ -151,3 +154,48 @@ def test_trained_network_beats_dsmc_extraction_on_held_out_case():
         f"network {emlp:.4f} (reference rms {float((tref[sel] ** 2).mean().sqrt()):.4f})")
     assert emlp < 0.25 * e50
     assert emlp < 0.9 * e4000
+
+
+def test_judge_in_the_benchmark_configuration():
+    """The DIG cavity of the benchmark (200 x 200 cells, 2M particles, Kn 0.01,
+    lid Ma 0.3): the DSMC terms of one DIG cycle (50 steps) judge predictions.
+    An independent 1000-step extraction, a prediction as good as a trained
+    network can be, is accepted in most band cells; the same prediction
+    pushed 8 standard errors away in one component is rejected everywhere,
+    and the DSMC-extracted terms stay in those cells."""
+    w = wl.cavity_2d(seed=2001)
+    A = learn.default_A(w["omega"])
+    sim = DSMC(w)
+    sim.init()
+    say("case judge: cavity 200x200, 2M particles")
+    sim.step(3000, graph=True)
+    sim.reset_average()
+    sim.step(1000, graph=True)
+    f_long = sim.sample("average")
+    sim.reset_average()
+    sim.step(50, graph=True)
+    f = sim.sample("average")
+    hot, mask, kn, _ = sim.closure(f, A, 0.01)
+    h_long, _, _, _ = sim.closure(f_long, A, 0.0)
+    _, t_long = sim.features(f_long, kn, learn.UNIT_SCALING, hot=h_long)
+    steps = learn.judge_steps(w, 50)
+    band = (~mask.bool()) & torch.isfinite(kn)
+    assert int(band.sum()) > 1000
+    h1 = hot.clone()
+    src = sim.blend(f, kn, mask, t_long, learn.UNIT_SCALING, h1, 0.0, math.inf, 3.0, 0.1,
+                    steps, A=A)
+    acc = float((src[band] == 2).double().mean())
+    say(f"  judge steps {steps:.1f}: accepted {acc:.3f} of {int(band.sum())} band cells")
+    assert acc > 0.85
+    # pushed 8 standard errors (oracle model) in q_t,x
+    se = olearn.judge_se(w, np_(f), A, steps)
+    bad = t_long.clone()
+    bad[:, 3] += torch.tensor(8.0 * np.where(np.isfinite(se[:, 3]), se[:, 3], 0.0),
+                              dtype=torch.float32, device="cuda")
+    h2 = hot.clone()
+    src2 = sim.blend(f, kn, mask, bad, learn.UNIT_SCALING, h2, 0.0, math.inf, 3.0, 0.1, steps,
+                     A=A)
+    rej = (src2[band] == 3).double().mean()
+    assert float(rej) > 0.99
+    keep = band & (src2 == 3)
+    assert torch.equal(h2[:, keep], hot[:, keep])

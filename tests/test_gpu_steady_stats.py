@@ -3,10 +3,15 @@
 
 The two trajectories decorrelate, so the comparison is statistical.  The
 slowest thermal mode of the slab decays over a few hundred steps, so batch
-means within one run are correlated; the error bars come from ten independent
+means within one run are correlated; the error bars come from 80 independent
 seeds per side instead (time averages over the last 1000 steps of each run).
-Per-cell differences of n, Tt, Tr and q are held to 3 sigma for almost all
-cells (none beyond 5 sigma), and 10-cell block averages of n, Tt, Tr to 1 %.
+
+* Every cell's seed-averaged n, Tt and Tr agree to 1 % (the sampling noise
+  of the difference is about 0.2 %).
+* The z-scores of the per-cell differences of n, Tt, Tr, q_t,x and q_r,x
+  (500 values) exceed 3 as rarely as a Gaussian allows: at most 6 beyond 3
+  (expected 1.6; the binomial tail beyond 6 is about 1e-3) and none beyond
+  4.5.
 """
 import numpy as np
 import pytest
@@ -17,15 +22,15 @@ from gpu_common import DSMC, np_, say
 
 pytestmark = pytest.mark.gpu
 
-SEEDS = list(range(1101, 1111))
+SEEDS = list(range(1101, 1181))
 
 
 def average_gpu(w):
     sim = DSMC(w)
     sim.init()
-    sim.step(1000)
+    sim.step(1000, graph=True)
     sim.reset_average()
-    sim.step(1000)
+    sim.step(1000, graph=True)
     return np_(sim.sample("average")).copy()
 
 
@@ -41,21 +46,25 @@ def average_oracle(w):
 
 def test_fourier_steady_fields_agree_statistically():
     g, o = [], []
-    for seed in SEEDS:
+    for k, seed in enumerate(SEEDS):
         w = wl.fourier_1d(seed=seed)
-        say(f"case fourier seed {seed}")
+        if k % 10 == 0:
+            say(f"case fourier seeds {seed}..{seed + 9}")
         g.append(average_gpu(w))
         o.append(average_oracle(w))
     g = np.array(g)  # [seeds, 20, C]
     o = np.array(o)
     m_g, m_o = g.mean(axis=0), o.mean(axis=0)
     se = np.sqrt(g.var(axis=0, ddof=1) / len(g) + o.var(axis=0, ddof=1) / len(o))
+    zs = []
     for f, name in ((0, "rho"), (4, "Tt"), (5, "Tr"), (12, "qt_x"), (15, "qr_x")):
         z = (m_g[f] - m_o[f]) / se[f]
-        say(f"  {name}: max|z|={np.abs(z).max():.2f} frac>3={np.mean(np.abs(z) > 3):.3f}")
-        assert np.mean(np.abs(z) > 3) <= 0.05, name
-        assert np.abs(z).max() < 5.5, name
-    for f in (0, 4, 5):
-        bg = m_g[f].reshape(10, 10).mean(axis=1)
-        bo = m_o[f].reshape(10, 10).mean(axis=1)
-        assert np.all(np.abs(bg / bo - 1) < 0.01), (f, bg / bo)
+        zs.append(z)
+        say(f"  {name}: max|z|={np.abs(z).max():.2f} beyond 3: {int(np.sum(np.abs(z) > 3))}")
+    z = np.abs(np.concatenate(zs))
+    assert np.sum(z > 3.0) <= 6, np.sort(z)[-8:]
+    assert z.max() < 4.5
+    for f, name in ((0, "rho"), (4, "Tt"), (5, "Tr")):
+        rel = np.abs(m_g[f] / m_o[f] - 1.0)
+        say(f"  {name}: largest per-cell relative difference {rel.max():.4f}")
+        assert np.all(rel < 0.01), (name, rel.max())
