@@ -317,12 +317,17 @@ dig_status dsmc_profile_kinds(dig_ctx* ctx, uint32_t mask, int32_t every);
 /* Launch configuration of the step kernels.  group_particles / group_cells as
  * in dsmc_create; seq_max: cells with at most this many particles run their
  * collision candidates in order on one lane, larger cells in parallel rounds
- * (range [0, 4096]).  Every choice gives bit-identical results; only the speed
- * differs.  ms_per_step is filled by dsmc_autotune (0 otherwise). */
+ * (range [0, 4096]); big_stage_kib: LDS budget of the kernel that collides
+ * the cell groups larger than the small-group stage (range [38, 150]; 38: four
+ * workgroups per compute unit, groups above about 1280 particles collide in
+ * HBM; larger budgets hold larger groups with fewer workgroups per unit).
+ * Every choice gives bit-identical results; only the speed differs.
+ * ms_per_step is filled by dsmc_autotune (0 otherwise). */
 typedef struct {
   int32_t group_particles;
   int32_t group_cells;
   int32_t seq_max;
+  int32_t big_stage_kib;
   double ms_per_step;
 } dig_tuning;
 
@@ -332,14 +337,16 @@ typedef struct {
 dig_status dsmc_tuning(dig_ctx* ctx, const dig_tuning* in_host, dig_tuning* out_host);
 
 /* Autotuner for the step kernels: coordinate search over group_particles in
- * {512, 1024, 2048, 4096, 8192}, group_cells in {32, 64, 128, 256} and seq_max in
- * {0, 64, 128, 192, 384} (two passes over the three axes, each configuration
- * timed once), timing steps_per_trial real steps per candidate with
+ * {512, 1024, 2048, 4096, 8192}, group_cells in {32, 64, 128, 256}, seq_max in
+ * {0, 64, 128, 192, 384} and big_stage_kib in {38, 50, 76} (the last only for
+ * contexts with open boundaries or at least 256 particles per cell on
+ * average; two passes over the axes, each configuration timed once), timing
+ * steps_per_trial real steps per candidate with
  * HIP events on `stream` (one untimed step before each).  The timed steps are
  * ordinary steps of the simulation: the state advances by every step taken,
  * exactly as dsmc_step would advance it, whichever configuration ran them.
  * cache_path (nullable): a text file of lines
- *   "<arch> <dim> <log2 particles> <log2 cells> <T> <Gc> <seq_max> <ms>";
+ *   "<arch> <dim> <log2 particles> <log2 cells> <T> <Gc> <seq_max> <big_kib> <ms>";
  * a line matching this device and size class is applied without trials, and a
  * new choice is appended.  The choice is applied and copied into *out.
  * Synchronises.  Errors: DIG_ERR_STATE, DIG_ERR_HIP, DIG_ERR_INVALID. */

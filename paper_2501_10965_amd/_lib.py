@@ -62,7 +62,8 @@ class DigCounters(C.Structure):
 
 class DigTuning(C.Structure):
     _fields_ = [("group_particles", C.c_int32), ("group_cells", C.c_int32),
-                ("seq_max", C.c_int32), ("ms_per_step", C.c_double)]
+                ("seq_max", C.c_int32), ("big_stage_kib", C.c_int32),
+                ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -309,6 +309,7 @@ struct dig_ctx {
   bool has_state = false;
   int phase = 0;  // 0: ready to move, 1: moved (cells reserved), 2: sorted
   int32_t seq_max = kSeqMaxDefault;
+  int32_t big_kib = (int32_t)(kBigLdsBytes / 1024);  // oversize-group stage budget
   int32_t inj_sectors = 0;  // angular sectors with freestream inflow
   // event pairs (start, stop) bracketing launches, with the kernel kind of each
   struct EvPool {
@@ -318,7 +319,7 @@ struct dig_ctx {
   };
   // captured step graphs, keyed by what the captured launches depend on
   struct Graph {
-    int32_t nsteps, cur, T, Gc, seq;
+    int32_t nsteps, cur, T, Gc, seq, big;
     int64_t n;
     hipGraph_t g;
     hipGraphExec_t x;
@@ -488,13 +489,16 @@ int32_t lds_particles_for(int32_t T, int32_t Gc) {
 
 // Stage of the oversize-group collide: the largest multiple of 256 particles
 // whose layout fits its LDS budget (about 5900 particles); 0 if none does.
-int32_t lds_big_for(int32_t Gc) {
-  int32_t Lb = (int32_t)(kBigLdsBytes / 24 / 256 * 256);
-  while (Lb > 0 && !big_stage_fits(Lb, Gc)) Lb -= 256;
+int32_t lds_big_for(int32_t Gc, int32_t kib) {
+  const size_t budget = (size_t)kib * 1024;
+  int32_t Lb = (int32_t)(budget / 24 / 256 * 256);
+  while (Lb > 0 && !big_stage_fits(Lb, Gc, budget)) Lb -= 256;
   return Lb;
 }
 
-dig_status check_tuning(int32_t T, int32_t Gc, int32_t seq) {
+dig_status check_tuning(int32_t T, int32_t Gc, int32_t seq, int32_t big) {
+  if (big < (int32_t)(kBigLdsBytes / 1024) || big > (int32_t)(kBigLdsMax / 1024))
+    return fail(DIG_ERR_INVALID, "big_stage_kib must lie in [38, 150]");
   if (T < kMinGroupParticles || T > 16384)
     return fail(DIG_ERR_INVALID, "group_particles must lie in [256, 16384]");
   if (Gc < kMinGroupCells || Gc > 256)
@@ -503,12 +507,13 @@ dig_status check_tuning(int32_t T, int32_t Gc, int32_t seq) {
   return DIG_OK;
 }
 
-void apply_tuning(dig_ctx* c, int32_t T, int32_t Gc, int32_t seq) {
+void apply_tuning(dig_ctx* c, int32_t T, int32_t Gc, int32_t seq, int32_t big) {
+  c->big_kib = big;
   c->T = T;
   c->Gc = Gc;
   c->seq_max = seq;
   c->Lp = lds_particles_for(T, Gc);
-  c->Lbig = lds_big_for(Gc);
+  c->Lbig = lds_big_for(Gc, big);
 }
 
 // Destroys the captured graphs.  A replay may still be in flight on the
@@ -584,7 +589,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   if (((uintptr_t)ws) % kAlign) return fail(DIG_ERR_INVALID, "workspace not 256-byte aligned");
   const int32_t T = group_particles > 0 ? group_particles : 1024;
   const int32_t Gc = group_cells > 0 ? group_cells : 64;
-  st = check_tuning(T, Gc, kSeqMaxDefault);
+  st = check_tuning(T, Gc, kSeqMaxDefault, (int32_t)(kBigLdsBytes / 1024));
   if (st != DIG_OK) return st;
   dig_ctx* c = new dig_ctx;
   c->cfg.assign(cfgs, cfgs + n_inst);
@@ -593,7 +598,7 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->dim = cfgs[0].dim;
   c->capacity = capacity;
   c->n_host = capacity;
-  apply_tuning(c, T, Gc, kSeqMaxDefault);
+  apply_tuning(c, T, Gc, kSeqMaxDefault, (int32_t)(kBigLdsBytes / 1024));
   plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1), &c->L, &c->I);
   if (ws_bytes < c->L.total_bytes) {
     const std::string msg =
@@ -952,13 +957,15 @@ dig_status dsmc_tuning(dig_ctx* c, const dig_tuning* in, dig_tuning* out) {
     out->group_particles = c->T;
     out->group_cells = c->Gc;
     out->seq_max = c->seq_max;
+    out->big_stage_kib = c->big_kib;
     out->ms_per_step = 0.0;
   }
   if (in) {
     if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
-    dig_status st = check_tuning(in->group_particles, in->group_cells, in->seq_max);
+    dig_status st =
+        check_tuning(in->group_particles, in->group_cells, in->seq_max, in->big_stage_kib);
     if (st != DIG_OK) return st;
-    apply_tuning(c, in->group_particles, in->group_cells, in->seq_max);
+    apply_tuning(c, in->group_particles, in->group_cells, in->seq_max, in->big_stage_kib);
   }
   return DIG_OK;
 }
@@ -977,7 +984,7 @@ dig_status graph_steps(dig_ctx* c, int32_t k, hipStream_t stream) {
   dig_ctx::Graph* hit = nullptr;
   for (auto& g : c->graphs)
     if (g.nsteps == k && g.cur == cur0 && g.n == nup && g.T == c->T && g.Gc == c->Gc &&
-        g.seq == c->seq_max)
+        g.seq == c->seq_max && g.big == c->big_kib)
       hit = &g;
   if (!hit) {
     if (c->graphs.size() >= 8) drop_graphs(c);
@@ -1007,7 +1014,7 @@ dig_status graph_steps(dig_ctx* c, int32_t k, hipStream_t stream) {
       (void)hipGraphDestroy(g);
       return hip_fail(e, "hipEventCreateWithFlags");
     }
-    c->graphs.push_back({k, cur0, c->T, c->Gc, c->seq_max, nup, g, x, done});
+    c->graphs.push_back({k, cur0, c->T, c->Gc, c->seq_max, c->big_kib, nup, g, x, done});
     hit = &c->graphs.back();
   }
   HIP_TRY(hipGraphLaunch(hit->x, stream));
@@ -1057,22 +1064,24 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
     return r;
   };
   const int ln = lg2(c->n_host), lc = lg2(c->ncell);
-  dig_tuning best{c->T, c->Gc, c->seq_max, 0.0};
+  dig_tuning best{c->T, c->Gc, c->seq_max, c->big_kib, 0.0};
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char a[64];
-      int d, n, cl, T, Gc, sq;
+      int d, n, cl, T, Gc, sq, bk;
       double ms;
       bool found = false;
-      while (fscanf(f, "%63s %d %d %d %d %d %d %lf", a, &d, &n, &cl, &T, &Gc, &sq, &ms) == 8)
+      while (fscanf(f, "%63s %d %d %d %d %d %d %d %lf", a, &d, &n, &cl, &T, &Gc, &sq, &bk, &ms) ==
+             9)
         if (arch == a && d == c->dim && n == ln && cl == lc &&
-            check_tuning(T, Gc, sq) == DIG_OK) {
-          best = dig_tuning{T, Gc, sq, ms};
+            check_tuning(T, Gc, sq, bk) == DIG_OK) {
+          best = dig_tuning{T, Gc, sq, bk, ms};
           found = true;
         }
       fclose(f);
       if (found) {
-        apply_tuning(c, best.group_particles, best.group_cells, best.seq_max);
+        apply_tuning(c, best.group_particles, best.group_cells, best.seq_max,
+                     best.big_stage_kib);
         if (out) *out = best;
         return DIG_OK;
       }
@@ -1083,7 +1092,7 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
   HIP_TRY(hipEventCreate(&e1));
   dig_status st = DIG_OK;
   auto trial = [&](const dig_tuning& t, double* ms) -> dig_status {
-    apply_tuning(c, t.group_particles, t.group_cells, t.seq_max);
+    apply_tuning(c, t.group_particles, t.group_cells, t.seq_max, t.big_stage_kib);
     dig_status r = run_stages(c, DIG_STAGE_ALL, s);
     if (r != DIG_OK) return r;
     if (hipEventRecord(e0, s) != hipSuccess) return fail(DIG_ERR_HIP, "event record");
@@ -1100,24 +1109,31 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
   const int32_t Ts[] = {512, 1024, 2048, 4096, 8192};
   const int32_t Gcs[] = {32, 64, 128, 256};
   const int32_t Sqs[] = {0, 64, 128, 192, 384};
+  const int32_t Bks[] = {38, 50, 76};
   // two passes over the three axes (the best group size can depend on the
   // other two); a configuration is timed once
   std::vector<dig_tuning> tried{best};
   auto seen = [&](const dig_tuning& t) {
     for (const dig_tuning& u : tried)
       if (u.group_particles == t.group_particles && u.group_cells == t.group_cells &&
-          u.seq_max == t.seq_max)
+          u.seq_max == t.seq_max && u.big_stage_kib == t.big_stage_kib)
         return true;
     return false;
   };
   for (int pass = 0; pass < 2 && st == DIG_OK; ++pass) {
-    for (int axis = 0; axis < 3 && st == DIG_OK; ++axis) {
-      const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : Sqs;
-      const int nv = axis == 1 ? 4 : 5;
+    for (int axis = 0; axis < 4 && st == DIG_OK; ++axis) {
+      const int32_t* vals = axis == 0 ? Ts : axis == 1 ? Gcs : axis == 2 ? Sqs : Bks;
+      const int nv = axis == 1 ? 4 : axis == 3 ? 3 : 5;
+      // the stage of oversize groups matters only where some group exceeds
+      // the small-group stage
+      if (axis == 3 && c->inj_sectors == 0 && c->n_host / c->ncell < 256) continue;
       const dig_tuning base = best;
       for (int k = 0; k < nv && st == DIG_OK; ++k) {
         dig_tuning t = base;
-        int32_t* field = axis == 0 ? &t.group_particles : axis == 1 ? &t.group_cells : &t.seq_max;
+        int32_t* field = axis == 0   ? &t.group_particles
+                         : axis == 1 ? &t.group_cells
+                         : axis == 2 ? &t.seq_max
+                                     : &t.big_stage_kib;
         *field = vals[k];
         if (seen(t)) continue;
         tried.push_back(t);
@@ -1128,12 +1144,13 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  apply_tuning(c, best.group_particles, best.group_cells, best.seq_max);
+  apply_tuning(c, best.group_particles, best.group_cells, best.seq_max, best.big_stage_kib);
   if (st != DIG_OK) return st;
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
-      fprintf(f, "%s %d %d %d %d %d %d %.6f\n", arch.c_str(), c->dim, ln, lc,
-              best.group_particles, best.group_cells, best.seq_max, best.ms_per_step);
+      fprintf(f, "%s %d %d %d %d %d %d %d %.6f\n", arch.c_str(), c->dim, ln, lc,
+              best.group_particles, best.group_cells, best.seq_max, best.big_stage_kib,
+              best.ms_per_step);
       fclose(f);
     }
   }
@@ -1155,7 +1172,7 @@ struct SaveHeader {
   uint64_t cfg_hash;       // instance parameters as the kernels see them
   uint64_t payload_bytes;  // bytes after the header
   dig_counters ctr;
-  int32_t T, Gc, seq, pad;  // tuning at the time of the save
+  int32_t T, Gc, seq, big;  // tuning at the time of the save
   uint64_t hash;            // over the header up to this field and the payload
 };
 constexpr uint32_t kSaveVersion = 1;
@@ -1271,6 +1288,7 @@ dig_status dsmc_save(dig_ctx* c, void* host_buf, size_t* bytes, dig_stream_t str
   h.T = c->T;
   h.Gc = c->Gc;
   h.seq = c->seq_max;
+  h.big = c->big_kib;
   h.hash = image_hash(h, p);
   memcpy(host_buf, &h, sizeof(h));
   *bytes = need;
@@ -1298,12 +1316,12 @@ dig_status dsmc_load(dig_ctx* c, const void* host_buf, size_t bytes, dig_stream_
   if (image_hash(h, p) != h.hash) return fail(DIG_ERR_INVALID, "checkpoint corrupted");
   if (!image_state_ok(c, p, n))
     return fail(DIG_ERR_INVALID, "checkpoint particle state inconsistent with its cells");
-  if (check_tuning(h.T, h.Gc, h.seq) != DIG_OK)
+  if (check_tuning(h.T, h.Gc, h.seq, h.big) != DIG_OK)
     return fail(DIG_ERR_INVALID, "checkpoint tuning out of range");
   // valid: replace the state (the particles go to buffer 0)
   hipStream_t s = (hipStream_t)stream;
   drop_graphs(c);
-  apply_tuning(c, h.T, h.Gc, h.seq);
+  apply_tuning(c, h.T, h.Gc, h.seq, h.big);
   c->cur = 0;
   c->phase = 0;
   c->n_host = n > 0 ? n : 1;

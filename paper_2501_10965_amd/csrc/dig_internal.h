@@ -149,9 +149,12 @@ dig_status report(dig_status s, const char* msg);
 int64_t group_launch(const StepArgs& a);
 int scan_blocks(int ncell);
 size_t collide_lds_bytes(int lds_particles, int group_cells);
-// LDS of the oversize-group collide: the stage and everything else
+// LDS of the oversize-group collide: the stage budget is a tuning choice
+// (38 KiB: four workgroups per CU; larger stages hold larger cells with fewer
+// workgroups per CU), at most kBigLdsMax.
 constexpr size_t kBigLdsBytes = 38 * 1024;
-bool big_stage_fits(int lds_big, int group_cells);
+constexpr size_t kBigLdsMax = 150 * 1024;
+bool big_stage_fits(int lds_big, int group_cells, size_t budget);
 int big_run_slots(int lds_big, int group_cells);
 hipError_t collide_setup();
 hipError_t launch_move(const StepArgs& a, hipStream_t s);

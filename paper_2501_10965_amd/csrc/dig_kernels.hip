@@ -2218,18 +2218,18 @@ int big_run_slots(int lds_big, int group_cells) {
   return (int)std::min<int64_t>(kRunMax, std::min(a, b));
 }
 
-bool big_stage_fits(int lds_big, int group_cells) {
+bool big_stage_fits(int lds_big, int group_cells, size_t budget) {
   return lds_big >= 512 && big_run_slots(lds_big, group_cells) >= kRunSlots &&
-         collide_lds_bytes(lds_big, group_cells) <= kBigLdsBytes;
+         collide_lds_bytes(lds_big, group_cells) <= budget;
 }
 
 hipError_t collide_setup() {
   const hipError_t e = hipFuncSetAttribute((const void*)k_collide_big<false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kBigLdsBytes);
+                                           (int)kBigLdsMax);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_collide_big<true>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLdsBytes);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLdsMax);
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
@@ -2281,7 +2281,7 @@ static hipError_t launch_collide_t(const StepArgs& a, bool collide, bool sample,
       hipLaunchKernelGGL((k_collide<1, kModeStaged, VSS>), grid, block, lds, s, a, f0, f1, f2);
   }
   if (fused) {
-    if (!big_stage_fits(a.lds_big, a.group_cells)) return hipErrorInvalidValue;
+    if (!big_stage_fits(a.lds_big, a.group_cells, kBigLdsMax)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_collide_big<VSS>, dim3(kBigGrid), dim3(kBigThreads),
                        collide_lds_bytes(a.lds_big, a.group_cells), s, a, f0, f1,
                        end_step ? 1 : 0);

@@ -171,14 +171,17 @@ class DSMC:
         fn = self.lib.dsmc_step_graph if graph else self.lib.dsmc_step
         L.check(fn(self.ctx, int(nsteps), _stream()))
 
-    def tuning(self, group_particles=None, group_cells=None, seq_max=None) -> dict:
+    def tuning(self, group_particles=None, group_cells=None, seq_max=None,
+               big_stage_kib=None) -> dict:
         """Current launch configuration; arguments given replace its fields."""
         cur = L.DigTuning()
         L.check(self.lib.dsmc_tuning(self.ctx, None, C.byref(cur)))
-        if group_particles is None and group_cells is None and seq_max is None:
+        if group_particles is None and group_cells is None and seq_max is None and \
+                big_stage_kib is None:
             return cur.as_dict()
         new = L.DigTuning(group_particles or cur.group_particles, group_cells or cur.group_cells,
-                          cur.seq_max if seq_max is None else seq_max, 0.0)
+                          cur.seq_max if seq_max is None else seq_max,
+                          big_stage_kib or cur.big_stage_kib, 0.0)
         L.check(self.lib.dsmc_tuning(self.ctx, C.byref(new), None))
         return new.as_dict()
 

@@ -45,7 +45,7 @@ def tuned():
 
 def _context(w, t, arrays, start, sg, capacity):
     sim = DSMC(w, capacity=capacity)
-    sim.tuning(t["group_particles"], t["group_cells"], t["seq_max"])
+    sim.tuning(t["group_particles"], t["group_cells"], t["seq_max"], t["big_stage_kib"])
     sim.inject(arrays, start, step=STEP0, next_id=len(arrays["x"]), sgmax=sg)
     sim.reset_average()
     return sim

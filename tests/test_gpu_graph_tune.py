@@ -100,8 +100,8 @@ def test_autotune_is_result_invariant_and_cached(tmp_path):
     c.init()
     t2 = c.autotune(steps_per_trial=2, cache_path=cache)
     assert c.counters()["step"] == 0
-    assert (t2["group_particles"], t2["group_cells"], t2["seq_max"]) == \
-        (t["group_particles"], t["group_cells"], t["seq_max"])
+    assert (t2["group_particles"], t2["group_cells"], t2["seq_max"], t2["big_stage_kib"]) == \
+        (t["group_particles"], t["group_cells"], t["seq_max"], t["big_stage_kib"])
     assert open(cache).read().count("\n") == 1
 
 
@@ -110,7 +110,8 @@ def test_tuning_rejects_out_of_range():
     s = DSMC(w)
     s.init()
     from paper_2501_10965_amd import _lib as L
-    for bad in (dict(group_particles=128), dict(group_cells=512), dict(seq_max=5000)):
+    for bad in (dict(group_particles=128), dict(group_cells=512), dict(seq_max=5000),
+                dict(big_stage_kib=20), dict(big_stage_kib=200)):
         with pytest.raises(L.DigError):
             s.tuning(**bad)
     assert s.tuning()["group_particles"] == 1024
