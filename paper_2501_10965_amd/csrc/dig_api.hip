@@ -110,6 +110,16 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
     const dig_config& c = cfgs[i];
     const std::string at = "instance " + std::to_string(i) + ": ";
     if (c.dim != 1 && c.dim != 2) return fail(DIG_ERR_INVALID, at + "dim must be 1 or 2");
+    bool finite = std::isfinite(c.lx) && std::isfinite(c.ly) && std::isfinite(c.r_in) &&
+                  std::isfinite(c.r_out) && std::isfinite(c.q) && std::isfinite(c.kn) &&
+                  std::isfinite(c.omega) && std::isfinite(c.alpha) && std::isfinite(c.zrot) &&
+                  std::isfinite(c.dt) && std::isfinite(c.weight) &&
+                  std::isfinite(c.sgmax_init) && std::isfinite(c.tref);
+    for (int f = 0; f < 4; ++f)
+      finite = finite && std::isfinite(c.bc[f].T) && std::isfinite(c.bc[f].rho) &&
+               std::isfinite(c.bc[f].U[0]) && std::isfinite(c.bc[f].U[1]) &&
+               std::isfinite(c.bc[f].U[2]);
+    if (!finite) return fail(DIG_ERR_INVALID, at + "every real parameter must be finite");
     if (c.dim != cfgs[0].dim) return fail(DIG_ERR_INVALID, at + "all instances must share dim");
     if (c.nx < 1 || c.ny < 1 || (c.dim == 1 && c.ny != 1))
       return fail(DIG_ERR_INVALID, at + "bad cell counts");

@@ -10,9 +10,11 @@
 // the wall-adjacent cell) and explicit pseudo-time steps that are the same in
 // every cell, so the total mass is conserved exactly.
 #include <math.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <mutex>
 #include <string>
 
@@ -641,27 +643,74 @@ size_t dig_synth_workspace_bytes(const dig_config* cfg) {
   return synth_layout(cfg).total;
 }
 
-dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const double* m_half,
-                       const double* hot, const uint8_t* mask, double* m_next,
-                       void* workspace, size_t ws_bytes, int32_t max_iter, double tol,
-                       int32_t* iters, double* change, dig_stream_t stream) {
-  if (!cfg || !opts || !m_half || !m_next || !workspace || !iters || !change) return DIG_ERR_INVALID;
-  if (cfg->dim != 1 && cfg->dim != 2) return DIG_ERR_INVALID;
-  if (cfg->dim == 1 && cfg->ny != 1) return DIG_ERR_INVALID;
-  if (cfg->geometry != DIG_GEOM_BOX) return report(DIG_ERR_INVALID, "synth_solve: box only");
-  if (max_iter < 0 || !(opts->cfl > 0.0)) return DIG_ERR_INVALID;
-  if (opts->scheme != DIG_SYNTH_EXPLICIT && opts->scheme != DIG_SYNTH_LUSGS)
-    return report(DIG_ERR_INVALID, "synth_solve: unknown scheme");
-  const SynthLayout L = synth_layout(cfg);
-  if (ws_bytes < L.total) return DIG_ERR_INVALID;
-  for (int ax = 0; ax < cfg->dim; ++ax)
+// Argument checks of both solve entry points (host only, before any device
+// work); the workspace is checked by the caller.
+static dig_status check_synth_args(const char* fn, const dig_config* cfg,
+                                   const dig_synth_opts* opts, const double* m_half,
+                                   const double* m_next, int32_t max_iter, double tol,
+                                   const int32_t* iters, const double* change) {
+  auto bad = [&](const char* why) {
+    static thread_local char msg[200];
+    snprintf(msg, sizeof(msg), "%s: %s", fn, why);
+    return report(DIG_ERR_INVALID, msg);
+  };
+  if (!cfg || !opts || !m_half || !m_next || !iters || !change) return bad("null argument");
+  if (cfg->dim != 1 && cfg->dim != 2) return bad("dim must be 1 or 2");
+  if (cfg->nx < 1 || cfg->ny < 1 || (cfg->dim == 1 && cfg->ny != 1))
+    return bad("bad cell counts");
+  if ((int64_t)cfg->nx * cfg->ny > (int64_t)INT32_MAX / 64) return bad("too many cells");
+  if (cfg->geometry != DIG_GEOM_BOX) return bad("box geometry only");
+  if (!(cfg->lx > 0.0) || !std::isfinite(cfg->lx) ||
+      (cfg->dim == 2 && (!(cfg->ly > 0.0) || !std::isfinite(cfg->ly))))
+    return bad("bad domain size");
+  if (!(cfg->kn > 0.0) || !std::isfinite(cfg->kn)) return bad("Kn must be finite and > 0");
+  if (!(cfg->omega >= 0.5 && cfg->omega <= 1.0)) return bad("omega must lie in [0.5, 1]");
+  if (cfg->dr != 2) return bad("d_r must be 2");
+  if (!(cfg->zrot > 0.0) || !std::isfinite(cfg->zrot)) return bad("Z must be finite and > 0");
+  for (int ax = 0; ax < cfg->dim; ++ax) {
+    for (int side = 0; side < 2; ++side) {
+      const dig_bc& b = cfg->bc[2 * ax + side];
+      if (b.type != DIG_BC_PERIODIC && b.type != DIG_BC_DIFFUSE && b.type != DIG_BC_SPECULAR)
+        return bad("bad face type for a box");
+      if (b.type == DIG_BC_DIFFUSE &&
+          (!(b.T > 0.0) || !std::isfinite(b.T) || !std::isfinite(b.U[0]) ||
+           !std::isfinite(b.U[1]) || !std::isfinite(b.U[2])))
+        return bad("a diffuse wall needs a finite T > 0 and a finite velocity");
+    }
     if ((cfg->bc[2 * ax].type == DIG_BC_PERIODIC) != (cfg->bc[2 * ax + 1].type == DIG_BC_PERIODIC))
-      return DIG_ERR_INVALID;
+      return bad("periodic faces must come in pairs");
+  }
+  if (max_iter < 0) return bad("max_iter must be >= 0");
+  if (!(tol >= 0.0)) return bad("tol must be >= 0");
+  if (!(opts->cfl > 0.0) || !std::isfinite(opts->cfl)) return bad("cfl must be finite and > 0");
+  if (opts->scheme != DIG_SYNTH_EXPLICIT && opts->scheme != DIG_SYNTH_LUSGS)
+    return bad("unknown scheme");
+  if (opts->check_every < 0) return bad("check_every must be >= 0");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(opts->A[k])) return bad("A must be finite");
+  if (!(fabs(opts->A[0] * opts->A[3] - opts->A[1] * opts->A[2]) > 0.0))
+    return bad("A is singular");
   // two colours: a periodic axis needs an even cell count
   if (opts->scheme == DIG_SYNTH_LUSGS)
     for (int ax = 0; ax < cfg->dim; ++ax)
       if (cfg->bc[2 * ax].type == DIG_BC_PERIODIC && ((ax == 0 ? cfg->nx : cfg->ny) & 1))
-        return report(DIG_ERR_INVALID, "synth_solve: LU-SGS needs an even count on a periodic axis");
+        return bad("LU-SGS needs an even cell count on a periodic axis");
+  return DIG_OK;
+}
+
+dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const double* m_half,
+                       const double* hot, const uint8_t* mask, double* m_next,
+                       void* workspace, size_t ws_bytes, int32_t max_iter, double tol,
+                       int32_t* iters, double* change, dig_stream_t stream) {
+  {
+    const dig_status st =
+        check_synth_args("synth_solve", cfg, opts, m_half, m_next, max_iter, tol, iters, change);
+    if (st != DIG_OK) return st;
+  }
+  const SynthLayout L = synth_layout(cfg);
+  if (!workspace || ((uintptr_t)workspace) % 256)
+    return report(DIG_ERR_INVALID, "synth_solve: workspace null or not 256-byte aligned");
+  if (ws_bytes < L.total) return report(DIG_ERR_INVALID, "synth_solve: workspace too small");
   hipStream_t s = (hipStream_t)stream;
   unsigned char* w = (unsigned char*)workspace;
   SynthGrid g;
@@ -682,7 +731,6 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   g.Atr = opts->A[1];
   g.Art = opts->A[2];
   g.Arr = opts->A[3];
-  if (!(fabs(g.Att * g.Arr - g.Atr * g.Art) > 0.0)) return DIG_ERR_INVALID;
   g.bc_periodic[0] = cfg->bc[0].type == DIG_BC_PERIODIC;
   g.bc_periodic[1] = cfg->dim == 2 ? cfg->bc[2].type == DIG_BC_PERIODIC : 1;
   const int C = g.nx * g.ny;
@@ -820,8 +868,11 @@ dig_status synth_solve_static(const dig_config* cfg, const dig_synth_opts* opts,
                               const double* m_half, const double* hot, const uint8_t* mask,
                               double* m_next, int32_t max_iter, double tol, int32_t* iters,
                               double* change, dig_stream_t stream) {
-  if (!cfg) return report(DIG_ERR_INVALID, "synth_solve_static: null config");
-  if (cfg->nx < 1 || cfg->ny < 1) return report(DIG_ERR_INVALID, "synth_solve_static: bad grid");
+  {
+    const dig_status st = check_synth_args("synth_solve_static", cfg, opts, m_half, m_next,
+                                           max_iter, tol, iters, change);
+    if (st != DIG_OK) return st;
+  }
   const size_t need = synth_layout(cfg).total;
   if (need > kStaticSynthBytes) {
     static thread_local char msg[160];
