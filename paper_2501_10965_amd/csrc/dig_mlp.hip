@@ -1,9 +1,11 @@
 // Learned closure network on the CDNA4 matrix cores: forward, back-propagation
 // and Adam for a 4-layer perceptron (9 -> 128 -> 128 -> 128 -> 7, padded to
-// 32 inputs and 16 outputs, tanh hidden layers).  Products use
-// v_mfma_f32_16x16x16_bf16: BF16 operands, FP32 accumulation.  A workgroup of
+// 32 inputs and 16 outputs, tanh hidden layers).  Products use gfx950's
+// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  A workgroup of
 // four waves carries a tile of 64 samples through all layers with the
-// activations in LDS; weights (78 KB in BF16) stay in L2.
+// activations in LDS.  Inference runs a persistent grid whose waves keep
+// their share of every weight matrix (88 VGPRs of BF16) in registers for the
+// whole launch; training kernels read the BF16 weights from L2.
 #include <math.h>
 #include <string.h>
 
@@ -15,6 +17,7 @@ namespace dig {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = 32, kH = 128, kOutP = 16, kNIn = 9, kNOut = 7;
@@ -42,20 +45,26 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
 }
 
-// tanh for activations that are rounded to bfloat16 right after: from the
-// identity tanh x = sign(x) (1 - e^{-2|x|}) / (1 + e^{-2|x|}) with the
-// hardware exponential and reciprocal, and from the Taylor series
-// x - x^3/3 + 2x^5/15 - 17x^7/315 for |x| < 2^-4, where the identity loses
-// relative accuracy; the result is within a few FP32 ulps of tanh, far below
-// half a bfloat16 unit.
+// tanh for activations that are rounded to bfloat16 right after:
+// 1 - 2 / (e^{2x} + 1) with the hardware base-2 exponential and reciprocal
+// (both about 1 ulp; saturates to +-1 through e^{2x} -> inf or 0), and
+// x (1 - x^2/3) for |x| < 2^-6, where the quotient form loses relative
+// accuracy; within about 1e-6 relative of tanh, far below half a bfloat16
+// unit (2^-9).
 __device__ __forceinline__ float tanh_act(float x) {
-  const float ax = fabsf(x);
-  const float e = __expf(-2.0f * ax);
-  const float big = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
-  const float x2 = x * x;
-  const float small = ax * (1.0f + x2 * (-1.0f / 3.0f + x2 * (2.0f / 15.0f - x2 * (17.0f / 315.0f))));
-  return copysignf(ax < 0.0625f ? small : big, x);
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // e^{2x}
+  const float big = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  const float small = x * (1.0f - 0.33333333333333333f * (x * x));
+  return fabsf(x) < 0.015625f ? small : big;
 }
+
+// gfx950 MFMA, 16 x 16 outputs, K = 32.  Lane l supplies A[l%16][8(l/16)+j]
+// and B[8(l/16)+j][l%16] (j = 0..7) and receives D[4(l/16)+r][l%16].
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t* p) { return *(const bf16x8*)p; }
 
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -81,8 +90,14 @@ struct MlpDev {
   float* loss;
   uint16_t* wb;    // BF16 weights [out][in]
   uint16_t* wbt;   // BF16 weights [in][out]
-  uint16_t *a0, *a1, *a2, *a3;  // activations [B][32], [B][128] x3
-  uint16_t *g3, *g2, *g1, *g0;  // pre-activation gradients [B][16], [B][128] x3
+  // training batch, feature-major (row f holds feature f of all B samples):
+  // activations a0 [32][B], a1..a3 [128][B]; pre-activation gradients
+  // g2, g1, g0 [128][B] and g3T [16][B]; g3 [B][16] sample-major
+  uint16_t *a0, *a1, *a2, *a3;
+  uint16_t *g3, *g2, *g1, *g0, *g3T;
+  float* lpart;    // per-wave loss partial sums of a training batch
+  float* wpart;    // [kWMaxChunks][DIG_MLP_NPARAM] gradient partial sums
+  int64_t B;       // rows of the training arrays
 };
 
 // One 128-wide layer for a tile of 64 samples: out = act(W in + b), with
@@ -93,18 +108,31 @@ struct MlpDev {
 template <int K>
 __device__ __forceinline__ void mma_rows(const uint16_t* __restrict__ W, const uint16_t* in,
                                          int wave, int lane, f32x4 acc[2][4]) {
-  const int li = lane & 15, lk = 4 * (lane >> 4);
+  const int li = lane & 15;
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  if constexpr (K % 32 == 0) {
+    const int lk = 8 * (lane >> 4);
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x4 a0 = ld4(W + (32 * wave + li) * K + k0 + lk);
-    const bf16x4 a1 = ld4(W + (32 * wave + 16 + li) * K + k0 + lk);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const bf16x8 a0 = ld8(W + (32 * wave + li) * K + k0 + lk);
+      const bf16x8 a1 = ld8(W + (32 * wave + 16 + li) * K + k0 + lk);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const bf16x8 b = ld8(in + (16 * ct + li) * kLds + k0 + lk);
+        acc[0][ct] = mfma32(a0, b, acc[0][ct]);
+        acc[1][ct] = mfma32(a1, b, acc[1][ct]);
+      }
+    }
+  } else {  // K = 16 (the padded output layer's back-propagation)
+    const int lk = 4 * (lane >> 4);
+    const bf16x4 a0 = ld4(W + (32 * wave + li) * K + lk);
+    const bf16x4 a1 = ld4(W + (32 * wave + 16 + li) * K + lk);
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
-      const bf16x4 b = ld4(in + (16 * ct + li) * kLds + k0 + lk);
+      const bf16x4 b = ld4(in + (16 * ct + li) * kLds + lk);
       acc[0][ct] = mfma(a0, b, acc[0][ct]);
       acc[1][ct] = mfma(a1, b, acc[1][ct]);
     }
@@ -113,8 +141,8 @@ __device__ __forceinline__ void mma_rows(const uint16_t* __restrict__ W, const u
 
 template <int K>
 __device__ void hidden_layer(const uint16_t* __restrict__ W, const float* __restrict__ b,
-                             const uint16_t* in, uint16_t* out, uint16_t* gact, int wave,
-                             int lane) {
+                             const uint16_t* in, uint16_t* out, uint16_t* gact, int64_t B,
+                             int64_t s0, int wave, int lane) {
   f32x4 acc[2][4];
   mma_rows<K>(W, in, wave, lane, acc);
   const int li = lane & 15, lg = lane >> 4;
@@ -130,7 +158,12 @@ __device__ void hidden_layer(const uint16_t* __restrict__ W, const float* __rest
       const uint16_t h2 = to_bf16(tanh_act(acc[rt][ct][2] + b2));
       const uint16_t h3 = to_bf16(tanh_act(acc[rt][ct][3] + b3));
       st4(out + s * kLds + n0, h0, h1, h2, h3);
-      if (gact) st4(gact + s * kH + n0, h0, h1, h2, h3);
+      if (gact) {
+        gact[(int64_t)n0 * B + s0 + s] = h0;
+        gact[(int64_t)(n0 + 1) * B + s0 + s] = h1;
+        gact[(int64_t)(n0 + 2) * B + s0 + s] = h2;
+        gact[(int64_t)(n0 + 3) * B + s0 + s] = h3;
+      }
     }
   }
 }
@@ -139,8 +172,8 @@ __device__ void hidden_layer(const uint16_t* __restrict__ W, const float* __rest
 // WT = W^T [128][K], gin [64][K] in LDS and a the layer's output activation.
 template <int K>
 __device__ void back_layer(const uint16_t* __restrict__ WT, const uint16_t* gin, uint16_t* gout,
-                           const uint16_t* __restrict__ a, uint16_t* gglob, int wave,
-                           int lane) {
+                           const uint16_t* __restrict__ a, uint16_t* gglob, int64_t B,
+                           int64_t s0, int wave, int lane) {
   f32x4 acc[2][4];
   mma_rows<K>(WT, gin, wave, lane, acc);
   const int li = lane & 15, lg = lane >> 4;
@@ -150,15 +183,15 @@ __device__ void back_layer(const uint16_t* __restrict__ WT, const uint16_t* gin,
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
       const int s = 16 * ct + li;
-      const bf16x4 av = ld4(a + s * kH + n0);
       uint16_t h[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float x = from_bf16((uint16_t)av[r]);
+        const int64_t at = (int64_t)(n0 + r) * B + s0 + s;
+        const float x = from_bf16(a[at]);
         h[r] = to_bf16(acc[rt][ct][r] * (1.0f - x * x));
+        gglob[at] = h[r];
       }
       st4(gout + s * kLds + n0, h[0], h[1], h[2], h[3]);
-      st4(gglob + s * kH + n0, h[0], h[1], h[2], h[3]);
     }
   }
 }
@@ -179,16 +212,16 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev d, const float* __r
     const float v = (k < kNIn && gs < n) ? x[gs * kNIn + k] : 0.0f;
     const uint16_t h = to_bf16(v);
     bufA[s * kLds + k] = h;
-    if (TRAIN) d.a0[gs * kIn + k] = h;
+    if (TRAIN) d.a0[(int64_t)k * d.B + gs] = h;
   }
   __syncthreads();
-  hidden_layer<kIn>(d.wb + qw(0), d.p + pb(0), bufA, bufB, TRAIN ? d.a1 + s0 * kH : nullptr,
+  hidden_layer<kIn>(d.wb + qw(0), d.p + pb(0), bufA, bufB, TRAIN ? d.a1 : nullptr, d.B, s0,
                     wave, lane);
   __syncthreads();
-  hidden_layer<kH>(d.wb + qw(1), d.p + pb(1), bufB, bufA, TRAIN ? d.a2 + s0 * kH : nullptr,
+  hidden_layer<kH>(d.wb + qw(1), d.p + pb(1), bufB, bufA, TRAIN ? d.a2 : nullptr, d.B, s0,
                    wave, lane);
   __syncthreads();
-  hidden_layer<kH>(d.wb + qw(2), d.p + pb(2), bufA, bufB, TRAIN ? d.a3 + s0 * kH : nullptr,
+  hidden_layer<kH>(d.wb + qw(2), d.p + pb(2), bufA, bufB, TRAIN ? d.a3 : nullptr, d.B, s0,
                    wave, lane);
   __syncthreads();
   // output layer: wave w takes samples 16w..16w+15, all 16 (padded) outputs
@@ -196,9 +229,9 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev d, const float* __r
   const uint16_t* W3 = d.wb + qw(3);
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int k0 = 0; k0 < kH; k0 += 16)
-    acc = mfma(ld4(W3 + li * kH + k0 + 4 * lg), ld4(bufB + (16 * wave + li) * kLds + k0 + 4 * lg),
-               acc);
+  for (int k0 = 0; k0 < kH; k0 += 32)
+    acc = mfma32(ld8(W3 + li * kH + k0 + 8 * lg),
+                 ld8(bufB + (16 * wave + li) * kLds + k0 + 8 * lg), acc);
   const int s = 16 * wave + li;
   const int64_t gs = s0 + s;
   float lsum = 0.0f;
@@ -213,12 +246,112 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev d, const float* __r
     } else {
       const float dv = real ? yv - t[gs * kNOut + j] : 0.0f;
       lsum += dv * dv;
-      d.g3[gs * kOutP + j] = to_bf16(dv * scale);
+      const uint16_t gv = to_bf16(dv * scale);
+      d.g3[gs * kOutP + j] = gv;
+      d.g3T[(int64_t)j * d.B + gs] = gv;
     }
   }
   if (TRAIN) {
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
-    if (lane == 0) atomicAdd(d.loss, lsum / (7.0f * (float)n));
+    if (lane == 0) d.lpart[blockIdx.x * (kThreads / 64) + wave] = lsum;
+  }
+}
+
+// Loss of a training batch: the per-wave partial sums of the forward pass
+// added in a fixed order (deterministic), over 7 n.
+__global__ __launch_bounds__(256) void k_mlp_loss(MlpDev d, int nparts, int64_t n) {
+  __shared__ float sh[4];
+  float v = 0.0f;
+  for (int i = threadIdx.x; i < nparts; i += 256) v += d.lpart[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) d.loss[0] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) / (7.0f * (float)n);
+}
+
+// One hidden layer of the inference kernel from register-resident weights:
+// out = bf16(tanh(W in + b)) for 64 samples, wave w computing neurons
+// 32w..32w+31.  W[rt][kb]: rows 32w + 16 rt + (l % 16), inputs 32 kb + 8 (l / 16) + j.
+template <int KB>
+__device__ __forceinline__ void infer_layer(const bf16x8 (&W)[2][KB], const float* __restrict__ b,
+                                            const uint16_t* in, uint16_t* out, int wave,
+                                            int lane) {
+  const int li = lane & 15, lg = lane >> 4;
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const bf16x8 bv = ld8(in + (16 * ct + li) * kLds + 32 * kb + 8 * lg);
+      acc[0][ct] = mfma32(W[0][kb], bv, acc[0][ct]);
+      acc[1][ct] = mfma32(W[1][kb], bv, acc[1][ct]);
+    }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int n0 = 32 * wave + 16 * rt + 4 * lg;
+    const float b0 = b[n0], b1 = b[n0 + 1], b2 = b[n0 + 2], b3 = b[n0 + 3];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      st4(out + (16 * ct + li) * kLds + n0, to_bf16(tanh_act(acc[rt][ct][0] + b0)),
+          to_bf16(tanh_act(acc[rt][ct][1] + b1)), to_bf16(tanh_act(acc[rt][ct][2] + b2)),
+          to_bf16(tanh_act(acc[rt][ct][3] + b3)));
+  }
+}
+
+// Inference over n samples: a persistent grid, tiles of 64 samples taken in
+// a grid stride.  Each wave loads once the BF16 weights it multiplies by
+// (rows 32w..32w+31 of the three hidden layers, all 16 padded rows of the
+// output layer: 22 x 8 values per lane) and keeps them in registers.
+__global__ __launch_bounds__(kThreads, 2) void k_mlp_infer(MlpDev d, const float* __restrict__ x,
+                                                         float* __restrict__ y, int64_t n,
+                                                         int64_t ntiles) {
+  __shared__ __attribute__((aligned(16))) uint16_t bufA[kTile * kLds];
+  __shared__ __attribute__((aligned(16))) uint16_t bufB[kTile * kLds];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  bf16x8 w0[2][1], w1[2][4], w2[2][4], w3[4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int row = 32 * wave + 16 * rt + li;
+    w0[rt][0] = ld8(d.wb + qw(0) + row * kIn + 8 * lg);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      w1[rt][kb] = ld8(d.wb + qw(1) + row * kH + 32 * kb + 8 * lg);
+      w2[rt][kb] = ld8(d.wb + qw(2) + row * kH + 32 * kb + 8 * lg);
+    }
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) w3[kb] = ld8(d.wb + qw(3) + li * kH + 32 * kb + 8 * lg);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t s0 = tile * kTile;
+    for (int i = threadIdx.x; i < kTile * kIn; i += kThreads) {
+      const int sl = i / kIn, k = i % kIn;
+      const int64_t gs = s0 + sl;
+      bufA[sl * kLds + k] = to_bf16((k < kNIn && gs < n) ? x[gs * kNIn + k] : 0.0f);
+    }
+    __syncthreads();
+    infer_layer<1>(w0, d.p + pb(0), bufA, bufB, wave, lane);
+    __syncthreads();
+    infer_layer<4>(w1, d.p + pb(1), bufB, bufA, wave, lane);
+    __syncthreads();
+    infer_layer<4>(w2, d.p + pb(2), bufA, bufB, wave, lane);
+    __syncthreads();
+    // output layer: wave w takes samples 16w..16w+15, all 16 (padded) outputs
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+      acc = mfma32(w3[kb], ld8(bufB + (16 * wave + li) * kLds + 32 * kb + 8 * lg), acc);
+    const int64_t gs = s0 + 16 * wave + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 4 * lg + r;
+      if (j < kNOut && gs < n) y[gs * kNOut + j] = acc[r] + d.p[pb(3) + j];
+    }
+    // the next tile's input goes to bufA, last read before the barrier above;
+    // bufB is rewritten only after the barrier that follows that input
   }
 }
 
@@ -233,88 +366,102 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(MlpDev d) {
     gA[s * kLds + j] = d.g3[(s0 + s) * kOutP + j];
   }
   __syncthreads();
-  back_layer<kOutP>(d.wbt + qw(3), gA, gB, d.a3 + s0 * kH, d.g2 + s0 * kH, wave, lane);
+  back_layer<kOutP>(d.wbt + qw(3), gA, gB, d.a3, d.g2, d.B, s0, wave, lane);
   __syncthreads();
-  back_layer<kH>(d.wbt + qw(2), gB, gA, d.a2 + s0 * kH, d.g1 + s0 * kH, wave, lane);
+  back_layer<kH>(d.wbt + qw(2), gB, gA, d.a2, d.g1, d.B, s0, wave, lane);
   __syncthreads();
-  back_layer<kH>(d.wbt + qw(1), gA, gB, d.a1 + s0 * kH, d.g0 + s0 * kH, wave, lane);
+  back_layer<kH>(d.wbt + qw(1), gA, gB, d.a1, d.g0, d.B, s0, wave, lane);
 }
 
-// Weight and bias gradients: dW_l = sum over samples of g_l (x) a_l, one
-// workgroup per 16x16 block of a weight matrix, the samples as the MFMA
-// reduction axis.  The kGradWaves waves of a workgroup each reduce a
-// contiguous share of the samples (loads issued kGradAhead MFMA steps ahead),
-// then wave 0 adds the shares in wave order: deterministic, no atomics.
-// Tiles: layer 3 (8), layer 2 (64), layer 1 (64), layer 0 (16).
-constexpr int kGradTiles = 8 + 64 + 64 + 16;
-constexpr int kGradWaves = 8;
-constexpr int kGradAhead = 4;
+// Weight and bias gradients of a batch: dW_l[o][i] = sum_s g_l[s][o] a_l[s][i]
+// and db_l[o] = sum_s g_l[s][o], from the feature-major activations and
+// gradients.  Split over samples: wave q of the grid takes one 32 x 32 block
+// (l, o-block, i-block) of one weight matrix and one chunk of samples, a
+// 2 x 2 grid of 16 x 16 MFMA tiles with the samples as the reduction axis
+// (A = rows of g^T, B = rows of a^T: 8 consecutive samples per lane, one
+// 16-byte load each), and writes its partial block (and, for i-block 0, its
+// partial bias sums); k_mlp_wred adds the chunks' partials in chunk order, so
+// the result does not depend on timing.  Blocks: layer 0: 4 (128 outputs) x 1
+// (32 padded inputs); layers 1, 2: 4 x 4; layer 3: 1 (16 padded outputs, one
+// row tile) x 4.
+constexpr int kWBlocks = 4 + 16 + 16 + 4;
+constexpr int kWMaxChunks = 64;
 
-__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_wgrad(MlpDev d, int64_t rows) {
-  __shared__ f32x4 s_acc[kGradWaves][64];
-  __shared__ float s_b[kGradWaves][64];
-  int tile = blockIdx.x, l;
-  if (tile < 8) {
-    l = 3;
-  } else if (tile < 72) {
-    l = 2;
-    tile -= 8;
-  } else if (tile < 136) {
-    l = 1;
-    tile -= 72;
-  } else {
-    l = 0;
-    tile -= 136;
-  }
-  const int ni = din(l) / 16;
-  const int ot = tile / ni, it = tile % ni;
-  const uint16_t* g = l == 3 ? d.g3 : l == 2 ? d.g2 : l == 1 ? d.g1 : d.g0;
-  const uint16_t* a = l == 3 ? d.a3 : l == 2 ? d.a2 : l == 1 ? d.a1 : d.a0;
-  const int ldo = dout(l), ldi = din(l);
+__global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev d, int64_t rows, int nchunks,
+                                                   int64_t chunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  // this wave's steps of 16 samples: [k0, k1)
-  const int64_t steps = rows / 16;
-  const int64_t share = (steps + kGradWaves - 1) / kGradWaves;
-  const int64_t k0 = min(steps, wave * share), k1 = min(steps, k0 + share);
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  float bsum = 0.0f;
-  for (int64_t kb = k0; kb < k1; kb += kGradAhead) {
-    bf16x4 A[kGradAhead], B[kGradAhead];
+  const int q = (int)blockIdx.x * 4 + wave;
+  const int blk = q / nchunks, ck = q % nchunks;
+  if (blk >= kWBlocks) return;
+  int l, b = blk;
+  if (b < 4) {
+    l = 0;
+  } else if ((b -= 4) < 16) {
+    l = 1;
+  } else if ((b -= 16) < 16) {
+    l = 2;
+  } else {
+    b -= 16;
+    l = 3;
+  }
+  const int nib = din(l) / 32, ob = b / nib, ib = b % nib;
+  const int nrt = l == 3 ? 1 : 2;
+  const uint16_t* gT = l == 3 ? d.g3T : l == 2 ? d.g2 : l == 1 ? d.g1 : d.g0;
+  const uint16_t* aT = l == 3 ? d.a3 : l == 2 ? d.a2 : l == 1 ? d.a1 : d.a0;
+  const int64_t s_lo = (int64_t)ck * chunk;
+  const int64_t s_hi = s_lo + chunk < rows ? s_lo + chunk : rows;
+  f32x4 acc[2][2];
 #pragma unroll
-    for (int u = 0; u < kGradAhead; ++u) {
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t s = (kb + u) * 16 + 4 * lg + j;
-        const bool ok = kb + u < k1;
-        A[u][j] = ok ? (short)g[s * ldo + ot * 16 + li] : (short)0;
-        B[u][j] = ok ? (short)a[s * ldi + it * 16 + li] : (short)0;
+    for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float bs[2] = {0.0f, 0.0f};
+  const uint16_t* ga = gT + (int64_t)(32 * ob + li) * d.B + 8 * lg;
+  const uint16_t* gb = gT + (int64_t)(32 * ob + 16 + li) * d.B + 8 * lg;
+  const uint16_t* a0p = aT + (int64_t)(32 * ib + li) * d.B + 8 * lg;
+  const uint16_t* a1p = aT + (int64_t)(32 * ib + 16 + li) * d.B + 8 * lg;
+  for (int64_t s = s_lo; s < s_hi; s += 32) {
+    const bf16x8 A0 = ld8(ga + s);
+    const bf16x8 A1 = nrt == 2 ? ld8(gb + s) : A0;
+    const bf16x8 B0 = ld8(a0p + s), B1 = ld8(a1p + s);
+    acc[0][0] = mfma32(A0, B0, acc[0][0]);
+    acc[0][1] = mfma32(A0, B1, acc[0][1]);
+    if (nrt == 2) {
+      acc[1][0] = mfma32(A1, B0, acc[1][0]);
+      acc[1][1] = mfma32(A1, B1, acc[1][1]);
+    }
+    if (ib == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        bs[0] += (float)A0[j];
+        bs[1] += (float)A1[j];
       }
     }
+  }
+  float* part = d.wpart + (int64_t)ck * DIG_MLP_NPARAM;
+  for (int rt = 0; rt < nrt; ++rt) {
 #pragma unroll
-    for (int u = 0; u < kGradAhead; ++u) {
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bsum += from_bf16((uint16_t)A[u][j]);
-      acc = mfma(A[u], B[u], acc);
+      for (int r = 0; r < 4; ++r)
+        part[pw(l) + (32 * ob + 16 * rt + 4 * lg + r) * din(l) + 32 * ib + 16 * ct + li] =
+            acc[rt][ct][r];
+    if (ib == 0) {
+      float v = bs[rt];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lg == 0) part[pb(l) + 32 * ob + 16 * rt + li] = v;
     }
   }
-  s_acc[wave][lane] = acc;
-  s_b[wave][lane] = bsum;
-  __syncthreads();
-  if (wave != 0) return;
-  for (int w = 1; w < kGradWaves; ++w) {
-    const f32x4 o = s_acc[w][lane];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] += o[r];
-    bsum += s_b[w][lane];
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    d.g[pw(l) + (ot * 16 + 4 * lg + r) * ldi + it * 16 + li] = acc[r];
-  if (it == 0) {
-    bsum += __shfl_xor(bsum, 16);
-    bsum += __shfl_xor(bsum, 32);
-    if (lg == 0) d.g[pb(l) + ot * 16 + li] = bsum;
-  }
+}
+
+// Gradient of every parameter: the chunk partials added in chunk order.
+__global__ void k_mlp_wred(MlpDev d, int nchunks) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= DIG_MLP_NPARAM) return;
+  float v = 0.0f;
+  for (int c = 0; c < nchunks; ++c) v += d.wpart[(int64_t)c * DIG_MLP_NPARAM + i];
+  d.g[i] = v;
 }
 
 // BF16 copies of parameter i (no-op for biases).
@@ -358,7 +505,7 @@ constexpr size_t kAlignM = 256;
 size_t up(size_t v) { return (v + kAlignM - 1) / kAlignM * kAlignM; }
 
 struct MlpOffsets {
-  size_t wb, wbt, a0, a1, a2, a3, g3, g2, g1, g0;
+  size_t wb, wbt, a0, a1, a2, a3, g3, g2, g1, g0, g3T, lpart, wpart;
 };
 
 void plan(int32_t max_batch, dig_mlp_layout* L, MlpOffsets* O) {
@@ -386,6 +533,9 @@ void plan(int32_t max_batch, dig_mlp_layout* L, MlpOffsets* O) {
   O->g2 = take(2 * B * kH);
   O->g1 = take(2 * B * kH);
   O->g0 = take(2 * B * kH);
+  O->g3T = take(2 * B * kOutP);
+  O->lpart = take(4 * (B / kTile) * (kThreads / 64));
+  O->wpart = take(4 * (size_t)kWMaxChunks * DIG_MLP_NPARAM);
   L->total_bytes = o;
 }
 
@@ -398,6 +548,7 @@ struct dig_mlp {
   unsigned char* ws;
   dig_mlp_layout L;
   MlpOffsets O;
+  int64_t infer_grid;  // workgroups of the persistent inference launch
   MlpDev dev() const {
     MlpDev d;
     d.p = (float*)(ws + L.params);
@@ -415,6 +566,10 @@ struct dig_mlp {
     d.g2 = (uint16_t*)(ws + O.g2);
     d.g1 = (uint16_t*)(ws + O.g1);
     d.g0 = (uint16_t*)(ws + O.g0);
+    d.lpart = (float*)(ws + O.lpart);
+    d.g3T = (uint16_t*)(ws + O.g3T);
+    d.wpart = (float*)(ws + O.wpart);
+    d.B = L.max_batch;
     return d;
   }
 };
@@ -449,6 +604,13 @@ dig_status mlp_create(void* ws, size_t bytes, int32_t max_batch, dig_stream_t st
   dig_mlp* m = new dig_mlp;
   m->ws = (unsigned char*)ws;
   plan(max_batch, &m->L, &m->O);
+  {
+    // two workgroups per compute unit (register-resident weights)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    m->infer_grid = 2 * (int64_t)(cus > 0 ? cus : 256);
+  }
   if (bytes < m->L.total_bytes) {
     delete m;
     return report(DIG_ERR_INVALID, "workspace too small");
@@ -479,8 +641,10 @@ dig_status mlp_forward(dig_mlp* m, const float* x, float* y, int64_t n, dig_stre
   if (!m || (n > 0 && (!x || !y))) return report(DIG_ERR_INVALID, "null argument");
   if (n < 0 || n > ((int64_t)1 << 36)) return report(DIG_ERR_INVALID, "bad sample count");
   if (n == 0) return DIG_OK;
-  hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((unsigned)((n + kTile - 1) / kTile)), dim3(kThreads),
-                     0, (hipStream_t)stream, m->dev(), x, (const float*)nullptr, y, n);
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  const int64_t grid = tiles < m->infer_grid ? tiles : m->infer_grid;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)grid), dim3(kThreads), 0, (hipStream_t)stream,
+                     m->dev(), x, y, n, tiles);
   return hip_check("mlp_forward");
 }
 
@@ -490,12 +654,23 @@ dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_s
   hipStream_t s = (hipStream_t)stream;
   MlpDev d = m->dev();
   const unsigned tiles = (unsigned)((n + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_mlp_zero, dim3(1), dim3(64), 0, s, d.loss, (int64_t)1);
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(tiles), dim3(kThreads), 0, s, d, x, t, (float*)nullptr,
                      n);
+  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, d, (int)(tiles * (kThreads / 64)), n);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(tiles), dim3(kThreads), 0, s, d);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles), dim3(64 * kGradWaves), 0, s, d,
-                     (int64_t)tiles * kTile);
+  // sample chunks of the weight gradients: a multiple of 32 samples, at most
+  // kWMaxChunks chunks, about 256 samples or more each
+  const int64_t rows = (int64_t)tiles * kTile;
+  int64_t nch = rows / 256;
+  nch = nch < 1 ? 1 : (nch > kWMaxChunks ? kWMaxChunks : nch);
+  int64_t chunk = (rows + nch - 1) / nch;
+  chunk = (chunk + 31) / 32 * 32;
+  nch = (rows + chunk - 1) / chunk;
+  const int64_t waves = (int64_t)kWBlocks * nch;
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d, rows,
+                     (int)nch, chunk);
+  hipLaunchKernelGGL(k_mlp_wred, dim3((DIG_MLP_NPARAM + 255) / 256), dim3(256), 0, s, d,
+                     (int)nch);
   return hip_check("mlp_grad");
 }
 
