@@ -158,7 +158,8 @@ def run_cavity(args):
         hot, mask, _, _ = sim.closure(f, A, 0.01)
         if target == "synth":
             tgt, it, ch = synth_solve(w, f, hot, mask, A, wall_mode="dsmc",
-                                      max_iter=args.synth_iters, tol=1e-5)
+                                      max_iter=args.synth_iters, tol=1e-5,
+                                      scheme=args.synth_scheme)
         else:
             tgt, it = f[0:6], 0
         sim.adjust(tgt, state["cycle"])
@@ -483,7 +484,8 @@ def run_steady(args):
     """Time to steady state at a fixed centreline-velocity error on the
     cavity: plain DSMC, DIG with DSMC-extracted terms, DIG with the learned
     closure (trained here on the cavity family; its training time is reported
-    separately)."""
+    separately), all on the same GPU; optionally also DIG with the explicit
+    synthetic solve."""
     import math
 
     import torch
@@ -493,17 +495,23 @@ def run_steady(args):
     from paper_2501_10965_amd.mlp import MLP
 
     w = wl.cavity_2d(seed=2001)
-    P, W, thr = 20, 20, args.steady_threshold
+    P, W, thr, cols = 20, args.steady_window, args.steady_threshold, args.steady_columns
     progress("reference run")
-    ref = steady.reference_profile(w, 60000, 120000, P)
+    ref = steady.reference_profile(w, 60000, 120000, P, cols)
     arms = {}
     progress("plain DSMC arm")
-    tr = steady.run_plain(w, ref, w["ns"], 1200, W, thr, P)
+    tr = steady.run_plain(w, ref, w["ns"], args.dig_max_cycles * 4, W, thr, P, cols)
     arms["dsmc"] = tr
-    progress("DIG arm (DSMC-extracted terms)")
-    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, ns=w["ns"],
-                           n_m=args.synth_iters, wall_mode="wall")
+    dig_kw = dict(ns=w["ns"], n_m=args.synth_iters, wall_mode="wall", scheme=args.synth_scheme,
+                  columns=cols)
+    progress(f"DIG arm (DSMC-extracted terms, {args.synth_scheme} synthetic solve)")
+    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, **dig_kw)
     arms["dig"] = tr
+    if args.steady_explicit_arm:
+        progress("DIG arm (explicit synthetic solve, 2000 iterations)")
+        tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, ns=w["ns"], n_m=2000,
+                               wall_mode="wall", scheme="explicit", columns=cols)
+        arms["dig_explicit"] = tr
     progress("closure-network training")
     KNS = [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5]
     MAS = [0.1, 0.25, 0.5, 1.0]
@@ -526,8 +534,7 @@ def run_steady(args):
     progress("DIG arm (learned closure)")
     hook = learn.LearnedClosure(net, sc, kn_lo=0.01, judge_sigma=3.0, judge_rel=0.1,
                                 avg_steps=w["ns"])
-    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, closure=hook, ns=w["ns"],
-                           n_m=args.synth_iters, wall_mode="wall")
+    tr, d = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, closure=hook, **dig_kw)
     arms["dig_learned"] = tr
     res = {}
     for name, tr in arms.items():
@@ -537,6 +544,11 @@ def run_steady(args):
                      "final_err": round(tr.history[-1][2], 5) if tr.history else None,
                      "err_at": [(round(a, 3), b, round(e, 5)) for a, b, e in tr.history[::10]]}
     res["dig_learned"]["training_seconds"] = round(train_s, 2)
+    src = hook.last_src
+    if src is not None:
+        res["dig_learned"]["last_cycle_sources"] = {
+            k: int((src == v).sum()) for k, v in (("nsf", 0), ("dsmc", 1), ("network", 2),
+                                                  ("rejected", 3))}
     base = res["dsmc"]["seconds"]
     return res, base
 
@@ -645,13 +657,20 @@ def main():
                     help="cylinder: untimed steps from the start at rest before the window")
     ap.add_argument("--sweep", type=float, nargs="+", default=[1, 2, 5, 10, 20, 50, 100],
                     help="sweep: particle counts in millions")
-    ap.add_argument("--steady-threshold", type=float, default=0.02)
-    ap.add_argument("--dig-max-cycles", type=int, default=160)
+    ap.add_argument("--steady-threshold", type=float, default=0.01)
+    ap.add_argument("--steady-window", type=int, default=40,
+                    help="steady: cycles in the sliding average of the observable")
+    ap.add_argument("--steady-columns", type=int, default=8,
+                    help="steady: centre columns averaged into the centreline profile")
+    ap.add_argument("--steady-explicit-arm", action="store_true")
+    ap.add_argument("--synth-scheme", choices=["explicit", "lusgs"], default="lusgs")
+    ap.add_argument("--dig-max-cycles", type=int, default=400)
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--dig-cycles", type=int, default=2)
-    ap.add_argument("--synth-iters", type=int, default=2000)
+    ap.add_argument("--synth-iters", type=int, default=400,
+                    help="synthetic-solve iterations per DIG cycle (N_m)")
     ap.add_argument("--group-particles", type=int, default=0)
     ap.add_argument("--group-cells", type=int, default=0)
     ap.add_argument("--seq-max", type=int, default=-1,
@@ -677,9 +696,11 @@ def main():
                 "warmup": 0, "ms_per_step": None, "higher_is_better": False,
                 "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                 "config": {"workload": "cavity 200x200, 2M particles, Kn 0.01, lid Ma 0.3; "
-                           "centreline u_x, 20 block averages, window 20 cycles of 50 steps, "
+                           f"centreline u_x ({args.steady_columns} centre columns, 20 block "
+                           f"averages), window {args.steady_window} cycles of 50 steps, "
                            f"RMS error <= {args.steady_threshold} of the reference range; "
-                           "reference 60k + 120k plain-DSMC steps"},
+                           "reference 60k + 120k plain-DSMC steps; DIG synthetic solve "
+                           f"{args.synth_scheme}, N_m = {args.synth_iters}"},
                 "plain_dsmc_seconds": base, "arms": res}
         print(json.dumps(line), flush=True)
         return

@@ -30,9 +30,9 @@ def default_A(omega: float):
 class DIG:
     def __init__(self, w: dict, mode: str = "dig", ns: int = 50, n_m: int = 2000,
                  tol: float = 1e-5, kn_ref: float = 0.01, A=None, wall_mode: str = "dsmc",
-                 closure=None, capacity: int | None = None, cfl: float = 0.5,
+                 closure=None, capacity: int | None = None, cfl: float | None = None,
                  nsf_init: bool = True, init_iters: int | None = None, graph: bool = True,
-                 **dsmc_kw):
+                 scheme: str = "explicit", **dsmc_kw):
         assert mode in ("dig", "dsmc")
         self.w = w
         self.mode = mode
@@ -42,7 +42,8 @@ class DIG:
         self.kn_ref = kn_ref
         self.A = A if A is not None else default_A(w["omega"])
         self.wall_mode = wall_mode
-        self.cfl = cfl
+        self.cfl = cfl  # None: the scheme's default
+        self.scheme = scheme  # synthetic solve: "explicit" or "lusgs" (implicit)
         self.graph = graph
         # optional learned closure: (sim, fields, hot, mask, kn, smooth=...) -> hot, where
         # smooth holds the latest macroscopic solution in rows 0..5
@@ -59,7 +60,8 @@ class DIG:
         m[0:6] = f0
         if nsf_init and self.mode == "dig":
             out, it, ch = synth_solve(self.w, m, None, None, self.A, cfl=self.cfl,
-                                      wall_mode="wall", max_iter=iters, tol=self.tol)
+                                      wall_mode="wall", max_iter=iters, tol=self.tol,
+                                      scheme=self.scheme)
             f0 = out
         # the latest macroscopic solution (inputs of a learned closure)
         self.m_prev = f0[0:6].clone()
@@ -81,7 +83,7 @@ class DIG:
                 hot = self.closure_fn(self.sim, f, hot, mask, kn, smooth=smooth)
             m_next, it, ch = synth_solve(self.w, f, hot, mask, self.A, cfl=self.cfl,
                                          wall_mode=self.wall_mode, max_iter=self.n_m,
-                                         tol=self.tol)
+                                         tol=self.tol, scheme=self.scheme)
             self.sim.adjust(m_next, self.cycle_no)
             self.m_prev = m_next
             rec.update(synth_iters=it, synth_change=ch,

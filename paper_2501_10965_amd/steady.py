@@ -4,8 +4,8 @@ with DSMC-extracted higher-order terms, and DIG with the learned closure.
 The convergence observable is the paper's for the cavity (Section 4.1): the
 velocity u_x along the vertical centreline x = 0.5.  It is taken from the
 DSMC samples of every cycle (N_s steps), averaged over a sliding window of the
-last `window` cycles, reduced to `points` block averages along y (the two
-centre columns), and compared with a reference profile from a long plain-DSMC
+last `window` cycles, reduced to `points` block averages along y (of the
+`columns` centre columns), and compared with a reference profile from a long plain-DSMC
 run: err = RMS over the points of |profile - reference| / (max - min of the
 reference).  Steady state is the first wall time after which err stays at or
 below the threshold.  Wall time counts every GPU operation of the method (DSMC
@@ -23,12 +23,16 @@ from .dig import DIG
 from .dsmc import DSMC
 
 
-def centreline(f: torch.Tensor, nx: int, ny: int, points: int) -> torch.Tensor:
-    ux = f[1].view(ny, nx)[:, nx // 2 - 1: nx // 2 + 1].mean(1)
+def centreline(f: torch.Tensor, nx: int, ny: int, points: int, columns: int = 2) -> torch.Tensor:
+    """u_x of the `columns` centre columns, averaged across them and over
+    `points` blocks along y."""
+    h = columns // 2
+    ux = f[1].view(ny, nx)[:, nx // 2 - h: nx // 2 + h].mean(1)
     return ux.view(points, ny // points).mean(1)
 
 
-def reference_profile(w: dict, transient: int, average: int, points: int) -> torch.Tensor:
+def reference_profile(w: dict, transient: int, average: int, points: int,
+                      columns: int = 2) -> torch.Tensor:
     """Plain DSMC from rest: `transient` steps, then the average of `average`."""
     sim = DSMC(w)
     sim.init()
@@ -36,7 +40,7 @@ def reference_profile(w: dict, transient: int, average: int, points: int) -> tor
     sim.reset_average()
     sim.step(average, graph=True)
     f = sim.sample("average")
-    return centreline(f, w["nx"], w["ny"], points)
+    return centreline(f, w["nx"], w["ny"], points, columns)
 
 
 class Tracker:
@@ -68,7 +72,7 @@ class Tracker:
         return t
 
 
-def run_plain(w, ref, ns, max_cycles, window, threshold, points):
+def run_plain(w, ref, ns, max_cycles, window, threshold, points, columns=2):
     sim = DSMC(w)
     sim.init()
     tr = Tracker(ref, window, threshold)
@@ -81,13 +85,13 @@ def run_plain(w, ref, ns, max_cycles, window, threshold, points):
         f = sim.sample("average")
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-        tr.add(centreline(f, w["nx"], w["ny"], points), wall, (k + 1) * ns)
+        tr.add(centreline(f, w["nx"], w["ny"], points, columns), wall, (k + 1) * ns)
         if _settled(tr, window):
             break
     return tr
 
 
-def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, **kw):
+def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, columns=2, **kw):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     d = DIG(w, closure=closure, **kw)
@@ -100,7 +104,7 @@ def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, **kw):
         f = d.cycle()
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-        tr.add(centreline(f, w["nx"], w["ny"], points), wall, (k + 1) * d.ns)
+        tr.add(centreline(f, w["nx"], w["ny"], points, columns), wall, (k + 1) * d.ns)
         if _settled(tr, window):
             break
     return tr, d
