@@ -125,20 +125,43 @@ def random_sorted_state(w, seed, n_per_cell_mean=None, rng_kind="poisson"):
     energies.  Returns (x, y, vx, vy, vz, er, id, start) in float32/uint32."""
     rng = np.random.default_rng(seed)
     nc = w["nx"] * w["ny"]
-    lam = w["ppc"] if n_per_cell_mean is None else n_per_cell_mean
-    counts = rng.poisson(lam, size=nc) if rng_kind == "poisson" else np.full(nc, lam)
+    if n_per_cell_mean is not None:
+        lam = n_per_cell_mean
+    elif w.get("geometry") == "graded":
+        fx = np.diff(np.asarray(w["xfaces"]))
+        fy = np.diff(np.asarray(w["yfaces"])) if w["dim"] == 2 else np.ones(1)
+        lam = w["init"]["rho"] * np.outer(fy, fx).ravel() / w["weight"]
+    else:
+        lam = w["ppc"]
+    counts = rng.poisson(lam, size=nc) if rng_kind == "poisson" else \
+        np.full(nc, int(lam)) if np.isscalar(lam) else np.rint(lam).astype(np.int64)
     start = np.zeros(nc + 1, dtype=np.int64)
     start[1:] = np.cumsum(counts)
     n = int(start[-1])
     cell = np.repeat(np.arange(nc), counts)
     ix = cell % w["nx"]
     iy = cell // w["nx"]
-    x = (ix + rng.random(n)).astype(np.float32)
-    y = ((iy + rng.random(n)) if w["dim"] == 2 else np.zeros(n)).astype(np.float32)
-    # keep positions strictly inside their cell after rounding to float32
-    x = np.minimum(x, np.nextafter((ix + 1).astype(np.float32), np.float32(0)))
-    if w["dim"] == 2:
-        y = np.minimum(y, np.nextafter((iy + 1).astype(np.float32), np.float32(0)))
+    if w.get("geometry") == "graded":
+        # physical units, uniform in the cell, strictly inside its FP32 faces
+        fx = np.asarray(w["xfaces"])
+        x = fx[ix] + rng.random(n) * (fx[ix + 1] - fx[ix])
+        x = np.clip(x.astype(np.float32), np.nextafter(fx[ix].astype(np.float32), np.float32(2)),
+                    np.nextafter(fx[ix + 1].astype(np.float32), np.float32(0)))
+        if w["dim"] == 2:
+            fy = np.asarray(w["yfaces"])
+            y = fy[iy] + rng.random(n) * (fy[iy + 1] - fy[iy])
+            y = np.clip(y.astype(np.float32),
+                        np.nextafter(fy[iy].astype(np.float32), np.float32(2)),
+                        np.nextafter(fy[iy + 1].astype(np.float32), np.float32(0)))
+        else:
+            y = np.zeros(n, dtype=np.float32)
+    else:
+        x = (ix + rng.random(n)).astype(np.float32)
+        y = ((iy + rng.random(n)) if w["dim"] == 2 else np.zeros(n)).astype(np.float32)
+        # keep positions strictly inside their cell after rounding to float32
+        x = np.minimum(x, np.nextafter((ix + 1).astype(np.float32), np.float32(0)))
+        if w["dim"] == 2:
+            y = np.minimum(y, np.nextafter((iy + 1).astype(np.float32), np.float32(0)))
     i = w["init"]
     s = math.sqrt(i["Tt"])
     vx = (i["u"][0] + s * rng.standard_normal(n)).astype(np.float32)
@@ -147,6 +170,73 @@ def random_sorted_state(w, seed, n_per_cell_mean=None, rng_kind="poisson"):
     er = (i["Tr"] * rng.exponential(size=n)).astype(np.float32)
     ids = rng.permutation(n).astype(np.uint32)
     return dict(x=x, y=y, vx=vx, vy=vy, vz=vz, er=er, id=ids, start=start)
+
+
+def wall_refined_faces(n, length=1.0, first=0.001):
+    """Face coordinates of n cells on [0, length] refined toward both ends:
+    the width of cell k is first * q^min(k, n - 1 - k), with the ratio q found
+    by bisection so that the widths add up to `length` (q = 1 when first
+    = length / n).  Returns n + 1 float64 values from 0 to length."""
+    k = np.minimum(np.arange(n), n - 1 - np.arange(n)).astype(np.float64)
+
+    def total(q):
+        return float(np.sum(first * q ** k))
+
+    if abs(total(1.0) - length) < 1e-14 * length:
+        q = 1.0
+    else:
+        lo, hi = 1.0, 2.0
+        while total(hi) < length:
+            hi *= 2.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if total(mid) < length:
+                lo = mid
+            else:
+                hi = mid
+        q = 0.5 * (lo + hi)
+    widths = first * q ** k
+    faces = np.concatenate([[0.0], np.cumsum(widths)])
+    faces *= length / faces[-1]
+    faces[-1] = length
+    return faces
+
+
+def graded_box(dim, xfaces, yfaces=None, kn=0.05, zrot=5.0, omega=OMEGA_N2, ppc=50,
+               dt_frac=0.2, bc=None, seed=1, instance=0, rho=1.0, u=(0.0, 0.0, 0.0), Tt=1.0,
+               Tr=None, tref=None, dt=None):
+    """A box with cells of different widths between the face tables xfaces
+    (nx + 1 values from 0 to lx) and yfaces (dim 2).  One particle weight for
+    all cells, set so that the mean count per cell is `ppc` at density rho;
+    counts then follow the cell volumes (Iround(rho V / N_eff))."""
+    xfaces = np.asarray(xfaces, dtype=np.float64)
+    nx = len(xfaces) - 1
+    if dim == 2:
+        yfaces = np.asarray(yfaces, dtype=np.float64)
+        ny = len(yfaces) - 1
+    else:
+        yfaces, ny = np.array([0.0, 1.0]), 1
+    lx, ly = float(xfaces[-1]), float(yfaces[-1])
+    w = box(dim, nx, ny, lx=lx, ly=ly, kn=kn, zrot=zrot, omega=omega, ppc=ppc,
+            dt_frac=dt_frac, bc=bc, seed=seed, instance=instance, rho=rho, u=u, Tt=Tt, Tr=Tr,
+            tref=tref, dt=dt)
+    w.update(geometry="graded", xfaces=xfaces.tolist(), yfaces=yfaces.tolist(), ppc=0,
+             weight=rho * lx * (ly if dim == 2 else 1.0) / (ppc * nx * ny),
+             n_target=int(ppc * nx * ny))
+    return w
+
+
+def cavity_graded(seed=2101, n=100, first=0.001, ppc=50, kn=0.01, lid=LID_MA03, zrot=5.0,
+                  dt_frac=0.2):
+    """Lid-driven cavity on n x n cells refined toward all four walls (first
+    cell width `first`), diffuse walls at T = 1, lid (y = 1) moving in +x."""
+    f = wall_refined_faces(n, 1.0, first)
+    bc = [_bc("diffuse", 1.0), _bc("diffuse", 1.0), _bc("diffuse", 1.0),
+          _bc("diffuse", 1.0, (lid, 0.0, 0.0))]
+    w = graded_box(2, f, f, kn=kn, zrot=zrot, ppc=ppc, bc=bc, seed=seed, dt_frac=dt_frac)
+    w["ns"] = 50
+    w["name"] = f"cavity_graded_{n}x{n}_first{first}_kn{kn}"
+    return w
 
 
 def mlp_init(seed=7):

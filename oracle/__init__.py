@@ -26,7 +26,7 @@ _SO = os.path.join(_DIR, "liboracle.so")
 _SRC = [os.path.join(_DIR, "dsmc_oracle.c")]
 
 BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
-GEOM = {"box": 0, "annulus": 1}
+GEOM = {"box": 0, "annulus": 1, "graded": 2}
 TAG = {"init": 1, "init_n": 2, "wall": 3, "ncand": 4, "coll": 5, "dig_n": 6,
        "dig_del": 7, "dig_src": 8, "dig_empty": 9, "inflow": 10}
 
@@ -49,7 +49,8 @@ class Config(C.Structure):
                 ("dt", C.c_double), ("weight", C.c_double),
                 ("bc_type", C.c_int32 * 4), ("bc_T", C.c_double * 4),
                 ("bc_U", (C.c_double * 3) * 4), ("bc_rho", C.c_double * 4),
-                ("seed", C.c_uint64), ("instance", C.c_uint32)]
+                ("seed", C.c_uint64), ("instance", C.c_uint32),
+                ("xf", C.POINTER(C.c_double)), ("yf", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -180,6 +181,14 @@ def make_config(w: dict) -> Config:
         c.bc_rho[f] = bc[3] if len(bc) > 3 else 0.0
     c.seed = w["seed"]
     c.instance = w.get("instance", 0)
+    if c.geometry == GEOM["graded"]:
+        # the face tables live as long as the configuration
+        c._xf = np.ascontiguousarray(w["xfaces"], dtype=np.float64)
+        c._yf = np.ascontiguousarray(w["yfaces"] if c.dim == 2 else [0.0, 1.0],
+                                     dtype=np.float64)
+        assert len(c._xf) == c.nx + 1 and len(c._yf) == (c.ny + 1 if c.dim == 2 else 2)
+        c.xf = c._xf.ctypes.data_as(C.POINTER(C.c_double))
+        c.yf = c._yf.ctypes.data_as(C.POINTER(C.c_double))
     return c
 
 

@@ -97,6 +97,12 @@ double orc_annulus_face(const orc_config* c, int32_t j) {
 }
 
 double orc_cell_volume_at(const orc_config* c, int32_t cell) {
+  if (c->geometry == ORC_GEOM_GRADED) {
+    int32_t i = cell % c->nx, j = cell / c->nx;
+    double w = c->xf[i + 1] - c->xf[i];
+    if (c->dim == 1) return w;
+    return w * (c->yf[j + 1] - c->yf[j]);
+  }
   if (c->geometry != ORC_GEOM_ANNULUS) return orc_cell_volume(c);
   int32_t j = cell / c->nx;
   double ra = orc_annulus_face(c, j), rb = orc_annulus_face(c, j + 1);
@@ -153,6 +159,10 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
         double th = (2.0 * M_PI / (double)c->nx) * ((double)ix + orc_u01(a[1]));
         x[n] = r * cos(th);
         y[n] = r * sin(th);
+      } else if (c->geometry == ORC_GEOM_GRADED) {
+        /* uniform over the cell between its faces */
+        x[n] = c->xf[ix] + orc_u01(a[0]) * (c->xf[ix + 1] - c->xf[ix]);
+        y[n] = (c->dim == 2) ? c->yf[iy] + orc_u01(a[1]) * (c->yf[iy + 1] - c->yf[iy]) : 0.0;
       } else {
         x[n] = ix + orc_u01(a[0]);
         y[n] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
@@ -246,8 +256,11 @@ static int64_t move_annulus(const orc_config* c, int64_t n, double* x, double* y
 int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* vx,
                  double* vy, double* vz, double* er, const uint32_t* id, uint32_t step) {
   if (c->geometry == ORC_GEOM_ANNULUS) return move_annulus(c, n, x, y, vx, vy, vz, er, id, step);
-  double dx = c->lx / c->nx, dy = (c->dim == 2) ? c->ly / c->ny : 1.0;
-  double gx = c->nx, gy = c->ny;
+  /* uniform box: grid units; graded box: physical units (the walls at 0 and
+   * lx, ly; periodic axes wrap over lx, ly) */
+  int graded = c->geometry == ORC_GEOM_GRADED;
+  double dx = graded ? 1.0 : c->lx / c->nx, dy = graded ? 1.0 : (c->dim == 2) ? c->ly / c->ny : 1.0;
+  double gx = graded ? c->lx : c->nx, gy = graded ? c->ly : c->ny;
   int64_t hits_total = 0;
   for (int64_t p = 0; p < n; ++p) {
     double t = c->dt;
@@ -377,6 +390,30 @@ void orc_cell_index(const orc_config* c, int64_t n, const double* x, const doubl
     for (int64_t p = 0; p < n; ++p) cell[p] = annulus_cell(c, rf2, dir, x[p], y[p]);
     free(rf2);
     free(dir);
+    return;
+  }
+  if (c->geometry == ORC_GEOM_GRADED) {
+    /* the cell whose faces bracket the position, decided in single
+     * precision (the position as stored in FP32) against the FP32 faces:
+     * the largest i <= n - 1 with face[i] <= x, else 0 */
+    float* fx = (float*)malloc(sizeof(float) * (size_t)(c->nx + 1));
+    float* fy = (float*)malloc(sizeof(float) * (size_t)(c->ny + 1));
+    for (int32_t i = 0; i <= c->nx; ++i) fx[i] = (float)c->xf[i];
+    for (int32_t j = 0; j <= c->ny; ++j) fy[j] = (c->dim == 2) ? (float)c->yf[j] : 0.0f;
+    for (int64_t p = 0; p < n; ++p) {
+      int32_t ix = 0, iy = 0;
+      float xs = (float)x[p];
+      for (int32_t i = 1; i < c->nx; ++i)
+        if (fx[i] <= xs) ix = i;
+      if (c->dim == 2) {
+        float ys = (float)y[p];
+        for (int32_t j = 1; j < c->ny; ++j)
+          if (fy[j] <= ys) iy = j;
+      }
+      cell[p] = ix + c->nx * iy;
+    }
+    free(fx);
+    free(fy);
     return;
   }
   for (int64_t p = 0; p < n; ++p) {
@@ -628,6 +665,19 @@ void orc_sums_to_fields(const orc_config* c, int32_t ncell, const double* sums,
   }
 }
 
+/* A point of cell (ix, iy) at fractions (ua, ub) of its extent, in the
+ * position units of the geometry (grid units or physical units). */
+static void cell_point(const orc_config* c, int32_t ix, int32_t iy, double ua, double ub,
+                       double* x, double* y) {
+  if (c->geometry == ORC_GEOM_GRADED) {
+    *x = c->xf[ix] + ua * (c->xf[ix + 1] - c->xf[ix]);
+    *y = (c->dim == 2) ? c->yf[iy] + ub * (c->yf[iy + 1] - c->yf[iy]) : 0.0;
+  } else {
+    *x = ix + ua;
+    *y = (c->dim == 2) ? iy + ub : 0.0;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* DIG particle modification (Section 3.2): target count by Iround, random
  * deletion (partial Fisher-Yates) or cloning of random existing particles at
@@ -641,7 +691,6 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
                uint64_t next_id, int64_t cap, double* ox, double* oy, double* ovx,
                double* ovy, double* ovz, double* oer, uint32_t* oid, int64_t* ostart,
                int64_t* n_out, uint64_t* next_id_out) {
-  double V = orc_cell_volume(c);
   const double *trho = target, *tux = target + ncell, *tuy = target + 2 * ncell,
                *tuz = target + 3 * ncell, *ttt = target + 4 * ncell, *ttr = target + 5 * ncell;
   /* validation and target counts */
@@ -657,7 +706,7 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
     }
     uint32_t w[4];
     orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_N, 0, w);
-    nt[cell] = (int64_t)iround(r * V / c->weight, orc_u01(w[0]));
+    nt[cell] = (int64_t)iround(r * orc_cell_volume_at(c, cell) / c->weight, orc_u01(w[0]));
     total += nt[cell];
   }
   if (total > cap) {
@@ -707,8 +756,7 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
         uint32_t w[4];
         orc_draw(c, (uint32_t)cell, dig_iter, ORC_TAG_DIG_SRC, (uint32_t)k, w);
         int64_t src = b + orc_pick(w[0], (uint32_t)N);
-        ox[pos] = ix + orc_u01(w[1]);
-        oy[pos] = (c->dim == 2) ? iy + orc_u01(w[2]) : 0.0;
+        cell_point(c, ix, iy, orc_u01(w[1]), orc_u01(w[2]), &ox[pos], &oy[pos]);
         ovx[pos] = vx[src]; ovy[pos] = vy[src]; ovz[pos] = vz[src];
         oer[pos] = er[src];
         oid[pos] = (uint32_t)(next_id + created);
@@ -725,8 +773,7 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
         double z0, z1, z2, z3;
         box_muller(orc_u01(a[2]), orc_u01(a[3]), &z0, &z1);
         box_muller(orc_u01(bb[0]), orc_u01(bb[1]), &z2, &z3);
-        ox[pos] = ix + orc_u01(a[0]);
-        oy[pos] = (c->dim == 2) ? iy + orc_u01(a[1]) : 0.0;
+        cell_point(c, ix, iy, orc_u01(a[0]), orc_u01(a[1]), &ox[pos], &oy[pos]);
         ovx[pos] = tux[cell] + st * z0;
         ovy[pos] = tuy[cell] + st * z1;
         ovz[pos] = tuz[cell] + st * z2;
@@ -777,21 +824,43 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
  * by orc_sums_to_fields.  Outputs hot = [12][ncell] (sigma xx,yy,zz,xy,xz,yz,
  * q_t xyz, q_r xyz) = DSMC - NSF, zeroed where Kn_GLL < kn_ref (mask = 1);
  * nsf (optional) = the NSF terms themselves. */
+/* Cell-centre coordinate of cell i along `axis` (graded box), and the
+ * distance between the centres of cells a and b = a + 1 (mod n across a
+ * periodic axis: the wrapped distance). */
+static double centre(const orc_config* c, int axis, int32_t i) {
+  const double* f = (axis == 0) ? c->xf : c->yf;
+  return 0.5 * (f[i] + f[i + 1]);
+}
+
+static double centre_gap(const orc_config* c, int axis, int32_t a, int32_t b) {
+  int32_t n = (axis == 0) ? c->nx : c->ny;
+  double L = (axis == 0) ? c->lx : c->ly;
+  if (c->geometry != ORC_GEOM_GRADED) return L / n;
+  double d = centre(c, axis, b) - centre(c, axis, a);
+  if (b < a) d += L; /* across the periodic seam */
+  (void)n;
+  return d;
+}
+
+/* Derivative of f along `axis` at cell (ix, iy): the difference of the two
+ * neighbours over the distance between their centres (central), the
+ * one-sided difference at a wall; across a periodic seam the neighbours
+ * wrap.  Exact for linear fields on any grid. */
 static double grad_axis(const orc_config* c, const double* f, int32_t ix, int32_t iy, int axis) {
   int32_t n = (axis == 0) ? c->nx : c->ny;
   if (axis == 1 && c->dim == 1) return 0.0;
   if (n < 2) return 0.0;
-  double h = (axis == 0) ? c->lx / c->nx : c->ly / c->ny;
   int32_t i = (axis == 0) ? ix : iy;
   int periodic = c->bc_type[2 * axis] == ORC_BC_PERIODIC;
 #define AT(ii) ((axis == 0) ? f[(ii) + c->nx * iy] : f[ix + c->nx * (ii)])
-  if (i > 0 && i < n - 1) return (AT(i + 1) - AT(i - 1)) / (2.0 * h);
+  if (i > 0 && i < n - 1)
+    return (AT(i + 1) - AT(i - 1)) / (centre_gap(c, axis, i - 1, i) + centre_gap(c, axis, i, i + 1));
   if (periodic) {
     int32_t ip = (i + 1) % n, im = (i - 1 + n) % n;
-    return (AT(ip) - AT(im)) / (2.0 * h);
+    return (AT(ip) - AT(im)) / (centre_gap(c, axis, im, i) + centre_gap(c, axis, i, ip));
   }
-  if (i == 0) return (AT(1) - AT(0)) / h;
-  return (AT(n - 1) - AT(n - 2)) / h;
+  if (i == 0) return (AT(1) - AT(0)) / centre_gap(c, axis, 0, 1);
+  return (AT(n - 1) - AT(n - 2)) / centre_gap(c, axis, n - 2, n - 1);
 #undef AT
 }
 

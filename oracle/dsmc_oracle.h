@@ -11,8 +11,10 @@
  *
  * Units are the paper's (Section 2): length L0, density rho0, temperature T0,
  * speed sqrt(R T0); molecular mass = 1, so rho is the number density times
- * the particle weight.  Positions are held in grid units (x/dx, y/dy) so that
- * the cell index is floor() of the position.
+ * the particle weight.  In a uniform box, positions are held in grid units
+ * (x/dx, y/dy) so that the cell index is floor() of the position; an annulus
+ * and a graded box (cells of different widths between per-axis face tables)
+ * hold them in physical units.
  */
 #ifndef DSMC_ORACLE_H
 #define DSMC_ORACLE_H
@@ -23,7 +25,7 @@ extern "C" {
 #endif
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_DIFFUSE = 1, ORC_BC_SPECULAR = 2, ORC_BC_FREESTREAM = 3 };
-enum { ORC_GEOM_BOX = 0, ORC_GEOM_ANNULUS = 1 };
+enum { ORC_GEOM_BOX = 0, ORC_GEOM_ANNULUS = 1, ORC_GEOM_GRADED = 2 };
 
 /* Philox stream tags (third counter word, high byte). */
 enum {
@@ -48,6 +50,10 @@ typedef struct {
   double   bc_rho[4];    /* freestream density */
   uint64_t seed;
   uint32_t instance;
+  /* graded box: face coordinates along x (nx + 1) and y (ny + 1, dim 2),
+   * strictly increasing from 0 to lx (ly) */
+  const double* xf;
+  const double* yf;
 } orc_config;
 
 typedef struct {

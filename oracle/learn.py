@@ -18,16 +18,36 @@ import numpy as np
 HOT_OF_TARGET = [0, 3, 1, 6, 7, 9, 10]  # sigma_xx, sigma_xy, sigma_yy, qt_x, qt_y, qr_x, qr_y
 
 
+def _centres(w, axis):
+    """Cell-centre coordinates along `axis` (uniform or graded grid) and the
+    axis length."""
+    n = w["nx"] if axis == 0 else w["ny"]
+    L = w["lx"] if axis == 0 else w["ly"]
+    if w.get("geometry") == "graded":
+        f = np.asarray(w["xfaces"] if axis == 0 else w["yfaces"], dtype=np.float64)
+        return 0.5 * (f[1:] + f[:-1]), L
+    return (np.arange(n) + 0.5) * (L / n), L
+
+
 def gradient(w, f, axis):
-    """d f / d x_axis on the uniform grid: central differences inside, one-sided
-    at wall faces, wrapped at periodic faces; zero along y in 1D."""
+    """d f / d x_axis: the difference of the two neighbours over the distance
+    between their centres inside, one-sided at wall faces, wrapped at periodic
+    faces (the wrapped distance); zero along y in 1D.  On a uniform grid the
+    distances are 2h and h."""
     nx = w["nx"]
     ny = w.get("ny", 1) if w["dim"] == 2 else 1
     if axis == 1 and w["dim"] == 1:
         return np.zeros_like(f)
     g = f.reshape(ny, nx)
+    graded = w.get("geometry") == "graded"
     h = (w["lx"] / nx) if axis == 0 else (w["ly"] / ny)
+    xc, L = _centres(w, axis)
     n = nx if axis == 0 else ny
+
+    def gap(a, b):  # centre distance from cell a to cell b = a + 1 (mod n)
+        if not graded:
+            return h
+        return xc[b] - xc[a] + (L if b < a else 0.0)
     out = np.zeros_like(g)
     if n < 2:
         return out.reshape(-1)
@@ -42,13 +62,14 @@ def gradient(w, f, axis):
             return g[tuple(s2)]
 
         if 0 < i < n - 1:
-            d = (at(i + 1) - at(i - 1)) / (2 * h)
+            d = (at(i + 1) - at(i - 1)) / (gap(i - 1, i) + gap(i, i + 1))
         elif periodic:
-            d = (at((i + 1) % n) - at((i - 1) % n)) / (2 * h)
+            ip, im = (i + 1) % n, (i - 1) % n
+            d = (at(ip) - at(im)) / (gap(im, i) + gap(i, ip))
         elif i == 0:
-            d = (at(1) - at(0)) / h
+            d = (at(1) - at(0)) / gap(0, 1)
         else:
-            d = (at(n - 1) - at(n - 2)) / h
+            d = (at(n - 1) - at(n - 2)) / gap(n - 2, n - 1)
         s3 = list(sl)
         s3[ax] = i
         out[tuple(s3)] = d
@@ -107,13 +128,21 @@ def judge_se(w, F, A, judge_steps):
     cell (N the mean particle count, row 19): the direct moment sum
     (DIRECT_SD / sqrt(M)) and the NSF terms subtracted from it, whose central
     differences over 2h carry the noise of the mean velocity (variance Tt/M),
-    Tt (2 Tt^2 / (3 M)) and Tr (Tr^2 / M) of the two neighbours."""
+    Tt (2 Tt^2 / (3 M)) and Tr (Tr^2 / M) of the two neighbours.  On a graded
+    grid h is the cell's own width along each axis (the neighbours' distance
+    is about twice that)."""
     C = F.shape[1]
     rho, tt, tr, N = F[0], F[4], F[5], F[19]
-    hx = w["lx"] / w["nx"]
     two = w["dim"] == 2
-    ihx2 = 1.0 / (2.0 * hx * hx)
-    ihy2 = 1.0 / (2.0 * (w["ly"] / w["ny"]) ** 2) if two else 0.0
+    nx, ny = w["nx"], (w["ny"] if two else 1)
+    if w.get("geometry") == "graded":
+        wx = np.diff(np.asarray(w["xfaces"], dtype=np.float64))
+        wy = np.diff(np.asarray(w["yfaces"], dtype=np.float64)) if two else np.ones(1)
+    else:
+        wx = np.full(nx, w["lx"] / nx)
+        wy = np.full(ny, w["ly"] / ny) if two else np.ones(1)
+    ihx2_c = np.tile(1.0 / (2.0 * wx * wx), ny)
+    ihy2_c = np.repeat(1.0 / (2.0 * wy * wy), nx) if two else np.zeros(C)
     mu0 = w["kn"] * math.sqrt(2.0 / math.pi)
     att, atr, art, arr = A
     det = att * arr - atr * art
@@ -123,6 +152,7 @@ def judge_se(w, F, A, judge_steps):
         if not (rho[c] > 0 and tt[c] > 0 and N[c] > 0):
             continue
         M = N[c] * judge_steps
+        ihx2, ihy2 = ihx2_c[c], ihy2_c[c]
         mu = mu0 * tt[c] ** w["omega"]
         kt = 0.5 * mu * (arr * 5.0 - atr * dr) / det
         kr = 0.5 * mu * (-art * 5.0 + att * dr) / det

@@ -12,12 +12,14 @@ scheme below is this project's reading, written out plainly:
 
 * unknowns per cell W = [rho, rho ux, rho uy, rho uz, rho E, rho e_r] with
   E = (3 Tt + d_r Tr)/2 + |u|^2/2 and e_r = d_r Tr / 2; pressure p = rho Tt;
-* finite volumes on the uniform grid; inviscid face flux by HLLC (Toro) with
+* finite volumes on the grid of the workload (uniform, or graded: cells of
+  different widths between per-axis face tables); inviscid face flux by HLLC (Toro) with
   Davis wave-speed estimates u_n -/+ c, c = sqrt(gamma Tt),
   gamma = (5 + d_r)/(3 + d_r); tangential velocity and rotational energy are
   carried by the contact wave, so a stationary contact gives no mass flux;
 * viscous and heat fluxes at a face from the NSF relations with the face
-  normal derivative (right - left)/h and the tangential derivative averaged
+  normal derivative (right - left)/d, d the distance between the two cell
+  centres (h on a uniform grid), and the tangential derivative averaged
   from the two cells' central differences; mu = mu0 Tt^omega evaluated at the
   mean of the two cells' Tt, kappa from A; HoT at a face = mean of the two
   cells' (masked) HoT;
@@ -26,6 +28,10 @@ scheme below is this project's reading, written out plainly:
   wall-adjacent cell of the DSMC field M^{n+1/2} (mode "dsmc": slip and jump
   taken from DSMC); face density = adjacent cell density; derivatives at the
   wall face use the half cell (interior - wall)/(h/2);
+* cell-centred derivatives: the difference of the two neighbours over the
+  distance between their centres, one-sided at walls (exact for linear
+  fields on any grid); the divergence of a cell divides the face-flux
+  difference by its own width;
 * rotational relaxation source (d_r rho / 2)(T - Tr)/(Z tau), tau = mu/p;
 * explicit pseudo-time marching with one step for all cells (so that the
   total mass is conserved exactly): the minimum over cells of
@@ -44,6 +50,31 @@ def _grid_params(w):
     hx = w["lx"] / nx
     hy = (w["ly"] / ny) if w["dim"] == 2 else 1.0
     return nx, ny, hx, hy
+
+
+def _axis_geometry(w, axis, n, h):
+    """(widths [n], gaps [n + 1]) of one axis: the cell widths, and for
+    every face the distance between the centres on either side of it (a
+    wall face: half the width of its cell; a periodic seam: the wrapped
+    distance).  Uniform grids: h everywhere, h/2 at walls."""
+    periodic = w["bc"][2 * axis][0] == "periodic"
+    if w.get("geometry") == "graded" and (axis == 0 or w["dim"] == 2):
+        f = np.asarray(w["xfaces"] if axis == 0 else w["yfaces"], dtype=np.float64)
+        width = f[1:] - f[:-1]
+        c = 0.5 * (f[1:] + f[:-1])
+        gap = np.empty(n + 1)
+        gap[1:-1] = c[1:] - c[:-1]
+        if periodic:
+            gap[0] = gap[-1] = c[0] + (f[-1] - c[-1])
+        else:
+            gap[0] = c[0] - f[0]
+            gap[-1] = f[-1] - c[-1]
+        return width, gap
+    width = np.full(n, h)
+    gap = np.full(n + 1, h)
+    if not periodic:
+        gap[0] = gap[-1] = 0.5 * h
+    return width, gap
 
 
 def _conductivities(mu, A, dr):
@@ -102,7 +133,16 @@ def _prepare(w, m_half, hot, mask, A, wall_mode):
                             tr=tr0[idx].copy())
         axis = f // 2
         walls[f]["u"][axis] = np.zeros_like(walls[f]["u"][axis])
-    return dict(nx=nx, ny=ny, hx=hx, hy=hy, dr=dr, om=om, A=A, two=two, H=H, W=W,
+    wx, gx = _axis_geometry(w, 0, nx, hx)
+    if two:
+        wy, gy = _axis_geometry(w, 1, ny, hy)
+    else:
+        wy, gy = np.ones(1), np.ones(2)
+    # widths broadcast over cell arrays [..., ny, nx], gaps over face arrays;
+    # vol: cell volumes (areas in 2D, lengths in 1D)
+    vol = np.outer(wy, wx) if two else wx[None, :]
+    return dict(nx=nx, ny=ny, hx=hx, hy=hy, width={0: wx, 1: wy[:, None]}, vol=vol,
+                gap={0: gx, 1: gy[:, None]}, dr=dr, om=om, A=A, two=two, H=H, W=W,
                 bct=bct, walls=walls, mu0=w["kn"] * np.sqrt(2.0 / np.pi), Z=w["zrot"],
                 gam=(5.0 + dr) / (3.0 + dr), cv=(3.0 + dr) / 2.0)
 
@@ -122,22 +162,23 @@ def _dcen(P, f, axis):
     if axis == 1 and not P["two"]:
         return out
     n = f.shape[1] if axis == 0 else f.shape[0]
-    h = P["hx"] if axis == 0 else P["hy"]
+    g = P["gap"][axis].ravel()          # [n + 1]: centre distances across faces
+    span = g[:-1] + g[1:]               # [n]: distance between the two neighbours
     per = P["bct"][2 * axis] == "periodic"
     if axis == 0:
         if per:
-            out[:] = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / (2 * h)
+            out[:] = (np.roll(f, -1, 1) - np.roll(f, 1, 1)) / span
         elif n > 1:
-            out[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / (2 * h)
-            out[:, 0] = (f[:, 1] - f[:, 0]) / h
-            out[:, -1] = (f[:, -1] - f[:, -2]) / h
+            out[:, 1:-1] = (f[:, 2:] - f[:, :-2]) / span[1:-1]
+            out[:, 0] = (f[:, 1] - f[:, 0]) / g[1]
+            out[:, -1] = (f[:, -1] - f[:, -2]) / g[n - 1]
     else:
         if per:
-            out[:] = (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / (2 * h)
+            out[:] = (np.roll(f, -1, 0) - np.roll(f, 1, 0)) / span[:, None]
         elif n > 1:
-            out[1:-1] = (f[2:] - f[:-2]) / (2 * h)
-            out[0] = (f[1] - f[0]) / h
-            out[-1] = (f[-1] - f[-2]) / h
+            out[1:-1] = (f[2:] - f[:-2]) / span[1:-1, None]
+            out[0] = (f[1] - f[0]) / g[1]
+            out[-1] = (f[-1] - f[-2]) / g[n - 1]
     return out
 
 
@@ -146,10 +187,9 @@ def _axis_fluxes(P, W, axis):
     rho, u, tt, tr = _prims(W, P["dr"])
     mu = P["mu0"] * tt ** P["om"]
     du = [[_dcen(P, u[i], a) for a in range(2)] for i in range(3)]
-    h = P["hx"] if axis == 0 else P["hy"]
-    return _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"], h,
-                        P["two"], P["dr"], P["gam"], P["mu0"], P["om"], P["A"], P["nx"],
-                        P["ny"])
+    return _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"],
+                        P["gap"][axis], P["two"], P["dr"], P["gam"], P["mu0"], P["om"],
+                        P["A"], P["nx"], P["ny"])
 
 
 def _residual(P, W):
@@ -167,10 +207,11 @@ def _residual(P, W):
     ktot = kt_c + kr_c
     nu = np.maximum(4.0 * mu / (3.0 * rho), gam * ktot / (rho * P["cv"]))
     for axis in range(2 if two else 1):
-        h = P["hx"] if axis == 0 else P["hy"]
+        h = P["width"][axis]
         inv_dt += (np.abs(u[axis]) + c) / h + 2.0 * nu / h ** 2
-        F = _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"], h,
-                         two, dr, gam, P["mu0"], P["om"], P["A"], P["nx"], P["ny"])
+        F = _face_fluxes(axis, W, rho, u, tt, tr, mu, du, P["H"], P["walls"], P["bct"],
+                         P["gap"][axis], two, dr, gam, P["mu0"], P["om"], P["A"], P["nx"],
+                         P["ny"])
         # F has shape (6, ny, nx+1) for axis 0 or (6, ny+1, nx) for axis 1
         if axis == 0:
             R -= (F[:, :, 1:] - F[:, :, :-1]) / h
@@ -270,8 +311,9 @@ def solve_lusgs(w, m_half, hot=None, mask=None, A=None, max_iter=500, tol=1e-5, 
     dW* = (R - sum_j (dF*_j . n_ij - r_j dW*_j) / (2h)) / D on the second;
     the upper sweep keeps dW = dW* on the second colour and sets
     dW = dW* - sum_j (dF_j . n_ij - r_j dW_j) / (2h D) on the first.
-    After the update, every conservative variable is scaled by the ratio of
-    the initial to the current total mass (the implicit operator is not
+    Here h is the width of the receiving cell i along the axis.  After the
+    update, every conservative variable is scaled by the ratio of the initial
+    to the current total mass, sum of rho V (the implicit operator is not
     conservative; the box is closed or periodic, so the steady state keeps
     the initial mass).  Stops as `solve` does.  Periodic axes need an even
     cell count (two colours).  Returns (m_next [6, C], iterations, change)."""
@@ -285,7 +327,8 @@ def solve_lusgs(w, m_half, hot=None, mask=None, A=None, max_iter=500, tol=1e-5, 
             raise ValueError("periodic axes need an even cell count")
     jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     first = ((ii + jj) % 2 == 0)          # first colour
-    mass0 = W[0].sum()
+    vol = P["vol"]
+    mass0 = (W[0] * vol).sum()
     it = 0
     change = np.inf
     for it in range(1, max_iter + 1):
@@ -295,7 +338,7 @@ def solve_lusgs(w, m_half, hot=None, mask=None, A=None, max_iter=500, tol=1e-5, 
         kt_c, kr_c = _conductivities(mu, P["A"], dr)
         c = np.sqrt(P["gam"] * tt)
         nu = np.maximum(4.0 * mu / (3.0 * rho), P["gam"] * (kt_c + kr_c) / (rho * P["cv"]))
-        h = {0: P["hx"], 1: P["hy"]}
+        h = P["width"]
         r = {a: np.abs(u[a]) + c + 2.0 * nu / h[a] for a in axes}
         D = np.zeros_like(W)
         for a in axes:
@@ -323,7 +366,7 @@ def solve_lusgs(w, m_half, hot=None, mask=None, A=None, max_iter=500, tol=1e-5, 
         corr = offdiag(np.where(first, 0.0, dW))
         dW[:, first] = dW[:, first] - corr[:, first] / D[:, first]
         Wn = W + dW
-        Wn = Wn * (mass0 / Wn[0].sum())
+        Wn = Wn * (mass0 / (Wn[0] * vol).sum())
         ch = _relative_change(prim, _prims(Wn, dr))
         W = Wn
         change = ch
@@ -342,9 +385,10 @@ def face_fluxes(w, fields, axis, hot=None, A=None, wall_mode="wall"):
     return _axis_fluxes(P, P["W"], axis)
 
 
-def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam, mu0, om, A,
+def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, gap, two, dr, gam, mu0, om, A,
                  nx, ny):
-    """Total (inviscid + viscous + heat) flux through the faces normal to axis."""
+    """Total (inviscid + viscous + heat) flux through the faces normal to axis;
+    gap: the centre distance across every face (half a cell at a wall)."""
     # left/right states on every face; boundary faces filled below
     if axis == 0:
         nf = (ny, nx + 1)
@@ -398,11 +442,11 @@ def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam
     # ---------------- viscous / heat on interior / periodic faces
     tf = 0.5 * (tl + tR)
     uf = 0.5 * (ul + ur)
-    dn = [(ur[i] - ul[i]) / h for i in range(3)]                 # d u_i / d x_axis
+    dn = [(ur[i] - ul[i]) / gap for i in range(3)]               # d u_i / d x_axis
     dt_ = [0.5 * (dul[i][1 - axis] + dur[i][1 - axis]) for i in range(3)] if two else \
         [np.zeros(nf)] * 3                                        # d u_i / d x_other
-    dTt = (tR - tl) / h
-    dTr = (trr - trl) / h
+    dTt = (tR - tl) / gap
+    dTr = (trr - trl) / gap
     Hf = 0.5 * (Hl + Hr)
     V = _visc(axis, tf, uf, dn, dt_, dTt, dTr, Hf, mu0, om, A, dr, two)
     F = F + V
@@ -415,22 +459,24 @@ def _face_fluxes(axis, W, rho, u, tt, tr, mu, du, H, walls, bct, h, two, dr, gam
                 ci = 0 if side == 0 else nx - 1
                 cell = lambda a: a[..., :, ci]
                 sl = (slice(None), slice(None), fi)
+                half = gap[fi]
             else:
                 fi = 0 if side == 0 else ny
                 ci = 0 if side == 0 else ny - 1
                 cell = lambda a: a[..., ci, :]
                 sl = (slice(None), fi, slice(None))
+                half = gap[fi, 0]
             sgn = 1.0 if side == 0 else -1.0      # (interior - wall) / (h/2) * sgn = d/dx
             rc, uc, tc, trc = cell(rho), cell(u), cell(tt), cell(tr)
             Fw = np.zeros((6,) + rc.shape)
             Fw[1 + axis] = rc * tc                 # pressure on the wall
             uw = np.array(wl["u"])
             tfw = 0.5 * (tc + wl["tt"])
-            dnw = [sgn * (uc[i] - uw[i]) / (0.5 * h) for i in range(3)]
+            dnw = [sgn * (uc[i] - uw[i]) / half for i in range(3)]
             dtw = [cell(du[i][1 - axis]) for i in range(3)] if two else \
                 [np.zeros(rc.shape)] * 3
-            dTtw = sgn * (tc - wl["tt"]) / (0.5 * h)
-            dTrw = sgn * (trc - wl["tr"]) / (0.5 * h)
+            dTtw = sgn * (tc - wl["tt"]) / half
+            dTrw = sgn * (trc - wl["tr"]) / half
             Hw = cell(H)
             Vw = _visc(axis, tfw, uw, dnw, dtw, dTtw, dTrw, Hw, mu0, om, A, dr, two)
             Fw = Fw + Vw
