@@ -69,8 +69,13 @@ typedef struct {
  * r_j = r_in + (r_out - r_in) (q^j - 1) / (q^ny - 1) (q = 1: uniform);
  * cell (i, j) has index i + nx j; positions in physical units.  Faces:
  * bc[0] the inner circle (DIFFUSE or SPECULAR), bc[1] the outer circle
- * (DIFFUSE, SPECULAR or FREESTREAM); bc[2], bc[3] unused. */
-enum { DIG_GEOM_BOX = 0, DIG_GEOM_ANNULUS = 1 };
+ * (DIFFUSE, SPECULAR or FREESTREAM); bc[2], bc[3] unused.  GRADED (dim 1
+ * or 2): a box whose cells have different widths, the wall-refined grids of
+ * the DIG runs of Section 4.1 (Table 1): cell (i, j) spans
+ * [xfaces[i], xfaces[i+1]] x [yfaces[j], yfaces[j+1]]; the face tables are
+ * strictly increasing from 0 to lx (ly); positions in physical units; faces
+ * and walls as for BOX. */
+enum { DIG_GEOM_BOX = 0, DIG_GEOM_ANNULUS = 1, DIG_GEOM_GRADED = 2 };
 
 /* One simulation instance (Section 4 gas: VSS/VHS omega 0.74, alpha 1,
  * d_r = 2, constant Z).  Faces are ordered x-, x+, y-, y+. */
@@ -91,6 +96,10 @@ typedef struct {
   uint32_t instance_id; /* Philox counter word 2, low 24 bits */
   double sgmax_init;    /* initial majorant of sigma_T g; <= 0: default below */
   double tref;          /* default majorant = C (6 sqrt(2 tref))^(2 - 2 omega) */
+  const double* xfaces; /* GRADED: host array of nx + 1 face coordinates, 0 .. lx; read
+                          during the call that takes the config (copied by
+                          dsmc_create), not kept; NULL otherwise */
+  const double* yfaces; /* GRADED, dim 2: ny + 1 face coordinates, 0 .. ly */
 } dig_config;
 
 /* Byte offsets of the device arrays inside the caller's workspace.  Particle

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_PKG, "libdig.so")
 
 DIG_OK, DIG_ERR_INVALID, DIG_ERR_CAPACITY, DIG_ERR_HIP, DIG_ERR_STATE, DIG_ERR_NUMERIC = range(6)
 BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
-GEOM = {"box": 0, "annulus": 1}
+GEOM = {"box": 0, "annulus": 1, "graded": 2}
 STAGE_MOVE, STAGE_SORT, STAGE_COLLIDE, STAGE_ALL = 1, 2, 4, 7
 SAMPLE_INSTANT, SAMPLE_AVERAGE, SAMPLE_RESET = 0, 1, 2
 SYNTH_STATIC_BYTES = 32 << 20
@@ -30,7 +30,8 @@ class DigConfig(C.Structure):
                 ("omega", C.c_double), ("alpha", C.c_double), ("dr", C.c_int32),
                 ("zrot", C.c_double), ("dt", C.c_double), ("weight", C.c_double),
                 ("bc", DigBC * 4), ("seed", C.c_uint64), ("instance_id", C.c_uint32),
-                ("sgmax_init", C.c_double), ("tref", C.c_double)]
+                ("sgmax_init", C.c_double), ("tref", C.c_double),
+                ("xfaces", C.POINTER(C.c_double)), ("yfaces", C.POINTER(C.c_double))]
 
 
 class DigLayout(C.Structure):
@@ -211,4 +212,11 @@ def make_config(w: dict) -> DigConfig:
     c.instance_id = w.get("instance", 0)
     c.sgmax_init = w.get("sgmax_init", 0.0)
     c.tref = w.get("tref", 1.0)
+    if c.geometry == GEOM["graded"]:
+        # face tables held by the configuration object for its lifetime
+        c._xf = (C.c_double * (c.nx + 1))(*[float(v) for v in w["xfaces"]])
+        c.xfaces = C.cast(c._xf, C.POINTER(C.c_double))
+        if c.dim == 2:
+            c._yf = (C.c_double * (c.ny + 1))(*[float(v) for v in w["yfaces"]])
+            c.yfaces = C.cast(c._yf, C.POINTER(C.c_double))
     return c

@@ -46,7 +46,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      xsum, stats, rf2, dir, inj_off, done, big_list, big_count;
+      xsum, stats, rf2, dir, inj_off, done, big_list, big_count, fc32, fc64;
   int64_t gfirst_len;
 };
 
@@ -100,6 +100,40 @@ double default_majorant(const dig_config& c) {
   return vhs_constant(c) * pow(6.0 * sqrt(2.0 * c.tref), 2.0 - 2.0 * c.omega);
 }
 
+// Graded box: what is wrong with the face tables ("" when nothing): each
+// table present, finite, strictly increasing (also in FP32, so that every
+// cell can be located), from exactly 0 to the domain length.
+std::string faces_problem(const dig_config& c) {
+  for (int axis = 0; axis < c.dim; ++axis) {
+    const double* f = axis == 0 ? c.xfaces : c.yfaces;
+    const int n = axis == 0 ? c.nx : c.ny;
+    const double L = axis == 0 ? c.lx : c.ly;
+    const char* name = axis == 0 ? "xfaces" : "yfaces";
+    if (!f) return std::string("graded box needs ") + name;
+    if (!(f[0] == 0.0) || !(f[n] == L))
+      return std::string(name) + " must run from 0 to the domain length";
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(f[i + 1]) || !(f[i + 1] > f[i]) || !((float)f[i + 1] > (float)f[i]))
+        return std::string(name) + " must be finite and strictly increasing (also in FP32)";
+  }
+  return "";
+}
+
+double graded_volume(const dig_config& c, int k) {
+  const int i = k % c.nx, j = k / c.nx;
+  const double w = c.xfaces[i + 1] - c.xfaces[i];
+  return c.dim == 1 ? w : w * (c.yfaces[j + 1] - c.yfaces[j]);
+}
+
+// Entries of the face tables of a set of instances (graded boxes only).
+int64_t face_entries(const dig_config* cfgs, int32_t n_inst) {
+  int64_t n = 0;
+  for (int i = 0; i < n_inst; ++i)
+    if (cfgs[i].geometry == DIG_GEOM_GRADED)
+      n += (cfgs[i].nx + 1) + (cfgs[i].dim == 2 ? cfgs[i].ny + 1 : 0);
+  return n;
+}
+
 dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, int64_t* ncell) {
   if (!cfgs) return fail(DIG_ERR_INVALID, "null config");
   if (n_inst < 1) return fail(DIG_ERR_INVALID, "n_inst must be >= 1");
@@ -123,8 +157,13 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
     if (c.dim != cfgs[0].dim) return fail(DIG_ERR_INVALID, at + "all instances must share dim");
     if (c.nx < 1 || c.ny < 1 || (c.dim == 1 && c.ny != 1))
       return fail(DIG_ERR_INVALID, at + "bad cell counts");
-    if (c.geometry != DIG_GEOM_BOX && c.geometry != DIG_GEOM_ANNULUS)
+    if (c.geometry != DIG_GEOM_BOX && c.geometry != DIG_GEOM_ANNULUS &&
+        c.geometry != DIG_GEOM_GRADED)
       return fail(DIG_ERR_INVALID, at + "unknown geometry");
+    if (c.geometry == DIG_GEOM_GRADED) {
+      const std::string why = faces_problem(c);
+      if (!why.empty()) return fail(DIG_ERR_INVALID, at + why);
+    }
     if (c.geometry == DIG_GEOM_ANNULUS) {
       if (c.dim != 2 || n_inst != 1)
         return fail(DIG_ERR_INVALID, at + "an annulus is 2D and alone in its context");
@@ -178,7 +217,7 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
 }
 
 void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t geo_ny,
-                 dig_layout* L, Internal* I) {
+                 int64_t nfaces, dig_layout* L, Internal* I) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -227,6 +266,8 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->rf2 = take(4 * (geo_ny + 1));
   I->dir = take(8 * (geo_nx + 1));
   I->inj_off = take(4 * (geo_nx + 2));
+  I->fc32 = take(4 * nfaces);
+  I->fc64 = take(8 * nfaces);
   L->total_bytes = o;
 }
 
@@ -236,9 +277,10 @@ int32_t geo_dims(const dig_config* cfgs, int axis) {
   return axis == 0 ? cfgs[0].nx : cfgs[0].ny;
 }
 
-InstParam make_param(const dig_config& c, int32_t cell0) {
+InstParam make_param(const dig_config& c, int32_t cell0, int32_t face0) {
   InstParam p;
   memset(&p, 0, sizeof(p));
+  p.face0 = -1;
   p.dim = c.dim;
   p.nx = c.nx;
   p.ny = c.ny;
@@ -273,6 +315,15 @@ InstParam make_param(const dig_config& c, int32_t cell0) {
   p.mu0 = c.kn * sqrt(2.0 / M_PI);
   p.omega = c.omega;
   p.geom = (uint32_t)c.geometry;
+  if (c.geometry == DIG_GEOM_GRADED) {
+    // physical units: unit scale, walls at the domain lengths
+    p.face0 = face0;
+    p.dx = p.dy = 1.0;
+    p.inv_dx = p.inv_dy = 1.0f;
+    p.gx = (float)c.lx;
+    p.gy = c.dim == 2 ? (float)c.ly : 1.0f;
+    p.vol = graded_volume(c, 0);
+  }
   if (c.geometry == DIG_GEOM_ANNULUS) {
     const double ri = annulus_face(c, 0), ro = annulus_face(c, c.ny);
     p.rin2 = (float)(ri * ri);
@@ -308,6 +359,8 @@ struct dig_ctx {
   std::vector<int32_t> cell_inst_host;
   std::vector<double> cvol_host;
   std::vector<float> rf2_host, dir_host;
+  std::vector<float> fc32_host;   // graded boxes: face tables, instance after instance
+  std::vector<double> fc64_host;
   dig_layout L;
   Internal I;
   unsigned char* ws = nullptr;
@@ -400,6 +453,8 @@ StepArgs args(const dig_ctx* c) {
   // with inflow and outflow the count changes every step on the device
   if (c->inj_sectors > 0) a.n_upper = c->capacity;
   a.cvol = (const double*)(w + L.cvol);
+  a.fc32 = (const float*)(w + c->I.fc32);
+  a.fc64 = (const double*)(w + c->I.fc64);
   a.rf2 = (const float*)(w + c->I.rf2);
   a.dir = (const float2*)(w + c->I.dir);
   a.inj_off = (int32_t*)(w + c->I.inj_off);
@@ -583,7 +638,8 @@ dig_status dig_plan(const dig_config* cfgs, int32_t n_inst, int64_t capacity, di
   dig_status st = validate(cfgs, n_inst, capacity, &C);
   if (st != DIG_OK) return st;
   Internal I;
-  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1), out, &I);
+  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1),
+              face_entries(cfgs, n_inst), out, &I);
   return DIG_OK;
 }
 
@@ -609,7 +665,8 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   c->capacity = capacity;
   c->n_host = capacity;
   apply_tuning(c, T, Gc, kSeqMaxDefault, (int32_t)(kBigLdsBytes / 1024));
-  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1), &c->L, &c->I);
+  plan_layout(capacity, C, n_inst, geo_dims(cfgs, 0), geo_dims(cfgs, 1),
+              face_entries(cfgs, n_inst), &c->L, &c->I);
   if (ws_bytes < c->L.total_bytes) {
     const std::string msg =
         "workspace too small: need " + std::to_string(c->L.total_bytes) + " bytes";
@@ -628,13 +685,31 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
   int32_t cell0 = 0;
   for (int i = 0; i < n_inst; ++i) {
     const dig_config& g = cfgs[i];
-    c->params.push_back(make_param(g, cell0));
+    const int32_t face0 = (int32_t)c->fc64_host.size();
+    c->params.push_back(make_param(g, cell0, face0));
     for (int k = 0; k < g.nx * g.ny; ++k) {
       c->cell_inst_host.push_back(i);
-      c->cvol_host.push_back(g.geometry == DIG_GEOM_ANNULUS ? annulus_cell_area(g, k / g.nx)
-                                                            : cell_volume(g));
+      c->cvol_host.push_back(g.geometry == DIG_GEOM_ANNULUS  ? annulus_cell_area(g, k / g.nx)
+                             : g.geometry == DIG_GEOM_GRADED ? graded_volume(g, k)
+                                                             : cell_volume(g));
+    }
+    if (g.geometry == DIG_GEOM_GRADED) {
+      // the context keeps its own copy of the face tables
+      for (int k = 0; k <= g.nx; ++k) c->fc64_host.push_back(g.xfaces[k]);
+      if (g.dim == 2)
+        for (int k = 0; k <= g.ny; ++k) c->fc64_host.push_back(g.yfaces[k]);
     }
     cell0 += g.nx * g.ny;
+  }
+  for (double f : c->fc64_host) c->fc32_host.push_back((float)f);
+  for (int i = 0; i < n_inst; ++i) {
+    dig_config& g = c->cfg[i];
+    if (g.geometry == DIG_GEOM_GRADED) {
+      g.xfaces = c->fc64_host.data() + c->params[i].face0;
+      g.yfaces = g.dim == 2 ? g.xfaces + g.nx + 1 : nullptr;
+    } else {
+      g.xfaces = g.yfaces = nullptr;
+    }
   }
   if (cfgs[0].geometry == DIG_GEOM_ANNULUS) {
     const dig_config& g = cfgs[0];
@@ -662,6 +737,12 @@ dig_status dsmc_create(const dig_config* cfgs, int32_t n_inst, int64_t capacity,
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !c->dir_host.empty())
     e = hipMemcpyAsync((void*)a.dir, c->dir_host.data(), 4 * c->dir_host.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !c->fc64_host.empty())
+    e = hipMemcpyAsync((void*)a.fc64, c->fc64_host.data(), 8 * c->fc64_host.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !c->fc32_host.empty())
+    e = hipMemcpyAsync((void*)a.fc32, c->fc32_host.data(), 4 * c->fc32_host.size(),
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_i32(a.count, C, 0, s);
   if (e == hipSuccess) e = launch_fill_i32((int32_t*)a.done, 1, 0, s);
@@ -777,8 +858,8 @@ dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_strea
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!target) return fail(DIG_ERR_INVALID, "null target");
   if (c->n_inst != 1) return fail(DIG_ERR_INVALID, "dig_adjust needs a single-instance context");
-  if (c->cfg[0].geometry != DIG_GEOM_BOX)
-    return fail(DIG_ERR_INVALID, "dig_adjust supports box geometry only");
+  if (c->cfg[0].geometry == DIG_GEOM_ANNULUS)
+    return fail(DIG_ERR_INVALID, "dig_adjust supports boxes only (uniform or graded)");
   if (!c->has_state) return fail(DIG_ERR_STATE, "no particle state");
   if (c->phase != 0) return fail(DIG_ERR_STATE, "a partial step is pending (dsmc_stage)");
   hipStream_t s = (hipStream_t)stream;
@@ -826,8 +907,8 @@ dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, d
   const double det = A[0] * A[3] - A[1] * A[2];
   if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
   for (const auto& g : c->cfg)
-    if (g.geometry != DIG_GEOM_BOX)
-      return fail(DIG_ERR_INVALID, "closure_assemble supports box geometry only");
+    if (g.geometry == DIG_GEOM_ANNULUS)
+      return fail(DIG_ERR_INVALID, "closure_assemble supports boxes only (uniform or graded)");
   StepArgs a = args(c);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(timed(c, DIG_K_CLOSURE, s, [&] {
@@ -856,7 +937,8 @@ dig_status closure_features(dig_ctx* c, const double* fields, const double* kngl
                             dig_stream_t stream) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!fields || !kngll || !x || (t && !hot)) return fail(DIG_ERR_INVALID, "null argument");
-  if (c->cfg[0].geometry != DIG_GEOM_BOX) return fail(DIG_ERR_INVALID, "box geometry only");
+  if (c->cfg[0].geometry == DIG_GEOM_ANNULUS)
+    return fail(DIG_ERR_INVALID, "boxes only (uniform or graded)");
   MlpScale sc;
   dig_status st = scaling_of(scaling, &sc);
   if (st != DIG_OK) return st;
@@ -915,7 +997,7 @@ dig_status dig_constants(dig_ctx* c, int32_t inst, double* out) {
   out[0] = vhs_constant(g);
   out[1] = p_inelastic(g);
   out[2] = g.kn * sqrt(2.0 / M_PI);
-  out[3] = cell_volume(g);
+  out[3] = g.geometry == DIG_GEOM_GRADED ? graded_volume(g, 0) : cell_volume(g);
   out[4] = default_majorant(g);
   return DIG_OK;
 }
@@ -1206,7 +1288,8 @@ uint64_t cfg_hash(const dig_ctx* c) {
   uint64_t h = 0xcbf29ce484222325ULL;
   h = mix_hash((const unsigned char*)c->params.data(), sizeof(InstParam) * c->params.size(), h);
   const int32_t dims[3] = {c->dim, c->n_inst, c->ncell};
-  return mix_hash((const unsigned char*)dims, sizeof(dims), h);
+  h = mix_hash((const unsigned char*)dims, sizeof(dims), h);
+  return mix_hash((const unsigned char*)c->fc64_host.data(), 8 * c->fc64_host.size(), h);
 }
 
 // Payload: x, y, vx, vy, vz, er (f32), id (u32) of n particles; start
@@ -1225,6 +1308,17 @@ uint64_t image_hash(const SaveHeader& h, const unsigned char* payload) {
 // Host-side checks of a checkpoint's particle state against the context:
 // start is a non-decreasing table from 0 to n, and every box particle lies
 // in the cell its position maps to.
+// Cell of a position along one graded axis: the largest i <= n - 1 with
+// f[i] <= v (FP32 faces), else 0 -- the kernels' rule.
+int32_t host_face_cell(const float* f, int32_t n, float v) {
+  int32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) / 2;
+    if (f[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 bool image_state_ok(const dig_ctx* c, const unsigned char* p, int64_t n) {
   const float *x = (const float*)p, *y = x + n;
   const int32_t* start = (const int32_t*)(p + (size_t)n * 28);
@@ -1236,10 +1330,20 @@ bool image_state_ok(const dig_ctx* c, const unsigned char* p, int64_t n) {
     for (int32_t k = q.cell0; k < q.cell0 + q.ncell; ++k)
       for (int32_t e = start[k]; e < start[k + 1]; ++e) {
         if (!std::isfinite(x[e]) || (q.dim == 2 && !std::isfinite(y[e]))) return false;
-        if (q.geom != DIG_GEOM_BOX) continue;
-        const float fx = floorf(x[e]), fy = q.dim == 2 ? floorf(y[e]) : 0.0f;
-        if (fx < 0.0f || fx >= (float)q.nx || fy < 0.0f || fy >= (float)q.ny) return false;
-        if (q.cell0 + (int32_t)fx + q.nx * (int32_t)fy != k) return false;
+        if (q.geom == DIG_GEOM_ANNULUS) continue;
+        // inside the domain, in the cell the kernels would place it in
+        const float yv = q.dim == 2 ? y[e] : 0.0f;
+        if (x[e] < 0.0f || x[e] > q.gx || (q.dim == 2 && (yv < 0.0f || yv > q.gy))) return false;
+        int32_t ix, iy = 0;
+        if (q.geom == DIG_GEOM_GRADED) {
+          const float* fx = c->fc32_host.data() + q.face0;
+          ix = host_face_cell(fx, q.nx, x[e]);
+          if (q.dim == 2) iy = host_face_cell(fx + q.nx + 1, q.ny, yv);
+        } else {
+          ix = std::min((int32_t)floorf(x[e]), q.nx - 1);
+          if (q.dim == 2) iy = std::min((int32_t)floorf(yv), q.ny - 1);
+        }
+        if (q.cell0 + ix + q.nx * iy != k) return false;
       }
   }
   return true;

@@ -30,7 +30,10 @@ constexpr int kMinGroupCells = 32;
 // Per-instance constants, resident in the workspace.
 struct InstParam {
   int32_t dim, nx, ny, cell0;
-  int32_t ncell, dr, pad0, pad1;
+  int32_t ncell, dr;
+  int32_t face0;  // graded box: offset of this instance's x faces in the face
+                  // tables (nx + 1 entries, then ny + 1 y faces in 2D); -1 otherwise
+  int32_t pad1;
   int32_t bc_type[4];
   float bc_T[4];
   float bc_U[4][3];
@@ -110,6 +113,8 @@ struct StepArgs {
   int32_t seq_max;  // cells with at most this many particles collide on one lane
   int64_t n_upper;
   const double* cvol;  // [ncell] cell volumes
+  const float* fc32;   // graded boxes: FP32 face coordinates (cell location)
+  const double* fc64;  // graded boxes: FP64 face coordinates (positions, distances)
   const float* rf2;    // annulus: [ny + 1] FP32 squared face radii
   const float2* dir;   // annulus: [nx + 1] FP32 (cos, sin) of the angular faces
   int32_t* inj_off;    // freestream: [nx + 2] inflow offsets per angular sector

@@ -91,6 +91,28 @@ static __device__ __forceinline__ float keep_inside(float v, int cellidx) {
   return v < top ? v : __uint_as_float(__float_as_uint(top) - 1u);  // largest float below top
 }
 
+// Graded box: the cell of a coordinate along one axis, the largest
+// i <= n - 1 with f[i] <= v for the FP32 faces f (else 0).
+static __device__ __forceinline__ int face_cell(const float* f, int n, float v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (f[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Graded box: the point at fraction u of cell i along one axis,
+// f[i] + u (f[i+1] - f[i]) in FP64, as an FP32 coordinate that lies in the
+// cell (between its FP32 faces, below the upper one).
+static __device__ __forceinline__ float graded_point(const double* f64, const float* f32, int i,
+                                                     double u) {
+  const float v = (float)(f64[i] + u * (f64[i + 1] - f64[i]));
+  const float lo = f32[i], hi = f32[i + 1];
+  if (v < lo) return lo;
+  return v < hi ? v : __uint_as_float(__float_as_uint(hi) - 1u);
+}
+
 // ---------------------------------------------------------------------------
 // Annulus cell map.  The radial index is the largest j with rf2[j] <= r^2
 // (clamped to the ring) for the FP32 squared radius and the FP32 table of
@@ -324,6 +346,12 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
     }
   }
   *hits = hit;
+  if (P.geom == DIG_GEOM_GRADED) {
+    const float* f = a.fc32 + P.face0;
+    const int ix = face_cell(f, P.nx, x);
+    const int iy = two ? face_cell(f + P.nx + 1, P.ny, y) : 0;
+    return P.cell0 + ix + P.nx * iy;
+  }
   int ix = (int)floorf(x);
   ix = ix < 0 ? 0 : (ix > P.nx - 1 ? P.nx - 1 : ix);
   int iy = 0;
@@ -1669,6 +1697,11 @@ __global__ void k_init_fill(StepArgs a, const double* fields) {
     sincosf(I.dthf * ((float)ix + u01f(r0.y)), &sn, &cs);
     a.A.x[p] = r * cs;
     a.A.y[p] = r * sn;
+  } else if (I.geom == DIG_GEOM_GRADED) {
+    const double* f64 = a.fc64 + I.face0;
+    const float* f32 = a.fc32 + I.face0;
+    a.A.x[p] = graded_point(f64, f32, ix, u01d(r0.x));
+    if (I.dim == 2) a.A.y[p] = graded_point(f64 + I.nx + 1, f32 + I.nx + 1, iy, u01d(r0.y));
   } else {
     a.A.x[p] = keep_inside((float)ix + u01f(r0.x), ix);
     if (I.dim == 2) a.A.y[p] = keep_inside((float)iy + u01f(r0.y), iy);
@@ -1835,6 +1868,23 @@ struct Slot {
   uint32_t id;
 };
 
+// A point of box cell (ix, iy) from two random words: grid units (ix + u,
+// iy + u) in a uniform box, physical units between the faces in a graded one.
+static __device__ __forceinline__ void cell_point(const StepArgs& a, const InstParam& I, int ix,
+                                                  int iy, uint32_t wx, uint32_t wy, float* x,
+                                                  float* y) {
+  if (I.geom == DIG_GEOM_GRADED) {
+    const double* f64 = a.fc64 + I.face0;
+    const float* f32 = a.fc32 + I.face0;
+    *x = graded_point(f64, f32, ix, u01d(wx));
+    *y = I.dim == 2 ? graded_point(f64 + I.nx + 1, f32 + I.nx + 1, iy, u01d(wy)) : 0.0f;
+  } else {
+    *x = keep_inside((float)ix + u01f(wx), ix);
+    *y = I.dim == 2 ? keep_inside((float)iy + u01f(wy), iy) : 0.0f;
+  }
+}
+
+
 // One wave per cell: deletion by partial Fisher-Yates, clones, then the
 // FP64 linear transform; writes the cell's new particles into buffer B.
 constexpr int kAdjLds = 2048;
@@ -1912,8 +1962,7 @@ __global__ __launch_bounds__(256) void k_adjust_build(StepArgs a, const double* 
         const int k = o - N;
         const uint4 w = draw(I, ent, iter, TAG_DIG_SRC, (uint32_t)k);
         const int q = b + (int)pick(w.x, (uint32_t)N);
-        s.x = keep_inside((float)ix + u01f(w.y), ix);
-        s.y = I.dim == 2 ? keep_inside((float)iy + u01f(w.z), iy) : 0.0f;
+        cell_point(a, I, ix, iy, w.y, w.z, &s.x, &s.y);
         s.vx = a.A.vx[q];
         s.vy = a.A.vy[q];
         s.vz = a.A.vz[q];
@@ -1927,8 +1976,7 @@ __global__ __launch_bounds__(256) void k_adjust_build(StepArgs a, const double* 
         const double ra = sqrt(-2.0 * log(u01d(r0.z)));
         const double rb = sqrt(-2.0 * log(u01d(r1.x)));
         const double p0 = 2.0 * M_PI * u01d(r0.w), p1 = 2.0 * M_PI * u01d(r1.y);
-        s.x = keep_inside((float)ix + u01f(r0.x), ix);
-        s.y = I.dim == 2 ? keep_inside((float)iy + u01f(r0.y), iy) : 0.0f;
+        cell_point(a, I, ix, iy, r0.x, r0.y, &s.x, &s.y);
         s.vx = (float)(tux + st * (ra * cos(p0)));
         s.vy = (float)(tuy + st * (ra * sin(p0)));
         s.vz = (float)(tuz + st * (rb * cos(p1)));
@@ -1985,21 +2033,41 @@ __global__ __launch_bounds__(256) void k_adjust_build(StepArgs a, const double* 
 
 // ---------------------------------------------------------------------------
 // Closure assembly: NSF terms, HoT = DSMC - NSF, Kn_GLL and the adaptive mask.
-static __device__ double grad_axis(const InstParam& I, const double* f, int C, int base,
-                                   int ix, int iy, int axis) {
+// Distance between the centres of cells u and v = u + 1 (mod n) along one
+// axis: h on a uniform grid; on a graded one from the FP64 faces f (the
+// wrapped distance across a periodic seam, L the axis length).
+static __device__ __forceinline__ double centre_gap(const double* f, double h, double L, int u,
+                                                   int v) {
+  if (!f) return h;
+  double d = 0.5 * (f[v] + f[v + 1]) - 0.5 * (f[u] + f[u + 1]);
+  if (v < u) d += L;
+  return d;
+}
+
+// Derivative along `axis` at cell (ix, iy): the difference of the two
+// neighbours over the distance between their centres, one-sided at walls,
+// wrapped across periodic faces (exact for linear fields on any grid).
+static __device__ double grad_axis(const StepArgs& a, const InstParam& I, const double* f, int C,
+                                   int base, int ix, int iy, int axis) {
   if (axis == 1 && I.dim == 1) return 0.0;
   const int n = axis == 0 ? I.nx : I.ny;
   if (n < 2) return 0.0;
   const double h = axis == 0 ? I.dx : I.dy;
+  const double* fc = I.geom == DIG_GEOM_GRADED
+                         ? a.fc64 + I.face0 + (axis == 0 ? 0 : I.nx + 1) : nullptr;
+  const double L = fc ? fc[n] : 0.0;
   const int i = axis == 0 ? ix : iy;
   auto at = [&](int k) {
     return axis == 0 ? f[base + k + I.nx * iy] : f[base + ix + I.nx * k];
   };
-  if (i > 0 && i < n - 1) return (at(i + 1) - at(i - 1)) / (2.0 * h);
-  if (I.bc_type[2 * axis] == DIG_BC_PERIODIC)
-    return (at((i + 1) % n) - at((i - 1 + n) % n)) / (2.0 * h);
-  if (i == 0) return (at(1) - at(0)) / h;
-  return (at(n - 1) - at(n - 2)) / h;
+  if (i > 0 && i < n - 1)
+    return (at(i + 1) - at(i - 1)) / (centre_gap(fc, h, L, i - 1, i) + centre_gap(fc, h, L, i, i + 1));
+  if (I.bc_type[2 * axis] == DIG_BC_PERIODIC) {
+    const int ip = (i + 1) % n, im = (i - 1 + n) % n;
+    return (at(ip) - at(im)) / (centre_gap(fc, h, L, im, i) + centre_gap(fc, h, L, i, ip));
+  }
+  if (i == 0) return (at(1) - at(0)) / centre_gap(fc, h, L, 0, 1);
+  return (at(n - 1) - at(n - 2)) / centre_gap(fc, h, L, n - 2, n - 1);
 }
 
 __global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, double Art,
@@ -2022,7 +2090,7 @@ __global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, d
     double d[7][2];
     const double* arr[7] = {ux, uy, uz, F + 4 * C, F + 5 * C, F, speed};
     for (int k = 0; k < 7; ++k)
-      for (int ax = 0; ax < 2; ++ax) d[k][ax] = grad_axis(I, arr[k], C, base, ix, iy, ax);
+      for (int ax = 0; ax < 2; ++ax) d[k][ax] = grad_axis(a, I, arr[k], C, base, ix, iy, ax);
     const double mu = I.mu0 * pow(tt, I.omega);
     const double div = d[0][0] + d[1][1];
     q[0] = -mu * (2.0 * d[0][0] - 2.0 / 3.0 * div);
@@ -2078,14 +2146,14 @@ __global__ void k_learn_features(StepArgs a, const double* F, const double* kn,
     const double mu = I.mu0 * pow(tt, I.omega);
     const double lam = mu / (rho * tt) * sqrt(M_PI * tt / 2.0);
     const double su = lam / sqrt(tt), st = lam / tt;
-    f[0] = su * grad_axis(I, F + C, C, base, ix, iy, 0);
-    f[1] = su * grad_axis(I, F + C, C, base, ix, iy, 1);
-    f[2] = su * grad_axis(I, F + 2 * C, C, base, ix, iy, 0);
-    f[3] = su * grad_axis(I, F + 2 * C, C, base, ix, iy, 1);
-    f[4] = st * grad_axis(I, F + 4 * C, C, base, ix, iy, 0);
-    f[5] = st * grad_axis(I, F + 4 * C, C, base, ix, iy, 1);
-    f[6] = st * grad_axis(I, F + 5 * C, C, base, ix, iy, 0);
-    f[7] = st * grad_axis(I, F + 5 * C, C, base, ix, iy, 1);
+    f[0] = su * grad_axis(a, I, F + C, C, base, ix, iy, 0);
+    f[1] = su * grad_axis(a, I, F + C, C, base, ix, iy, 1);
+    f[2] = su * grad_axis(a, I, F + 2 * C, C, base, ix, iy, 0);
+    f[3] = su * grad_axis(a, I, F + 2 * C, C, base, ix, iy, 1);
+    f[4] = st * grad_axis(a, I, F + 4 * C, C, base, ix, iy, 0);
+    f[5] = st * grad_axis(a, I, F + 4 * C, C, base, ix, iy, 1);
+    f[6] = st * grad_axis(a, I, F + 5 * C, C, base, ix, iy, 0);
+    f[7] = st * grad_axis(a, I, F + 5 * C, C, base, ix, iy, 1);
     f[8] = kn[c];
     if (hot) {
       const double p = rho * tt, pq = p * sqrt(tt);
@@ -2113,11 +2181,12 @@ __global__ void k_learn_features(StepArgs a, const double* F, const double* kn,
 // velocity about the cell mean) and the NSF terms subtracted from it, whose
 // central differences over 2h carry the noise of the neighbours' mean
 // velocity (variance Tt/M), Tt (2 Tt^2/(3M)) and Tr (Tr^2/M).
-__device__ void judge_se(const InstParam& I, double rho, double tt, double tr, double N,
-                         double judge_steps, const JudgeGas& J, double se[7]) {
+__device__ void judge_se(const InstParam& I, double hx, double hy, double rho, double tt,
+                         double tr, double N, double judge_steps, const JudgeGas& J,
+                         double se[7]) {
   const double M = N * judge_steps;
-  const double ihx2 = 1.0 / (2.0 * I.dx * I.dx);
-  const double ihy2 = I.dim == 2 ? 1.0 / (2.0 * I.dy * I.dy) : 0.0;
+  const double ihx2 = 1.0 / (2.0 * hx * hx);
+  const double ihy2 = I.dim == 2 ? 1.0 / (2.0 * hy * hy) : 0.0;
   const double mu = I.mu0 * pow(tt, I.omega);
   const double kt = 0.5 * mu * (J.Arr * 5.0 - J.Atr * I.dr) / J.det;
   const double kr = 0.5 * mu * (-J.Art * 5.0 + J.Att * I.dr) / J.det;
@@ -2148,7 +2217,16 @@ __global__ void k_learn_blend(StepArgs a, const double* F, const double* kn,
     const int hk[7] = {0, 3, 1, 6, 7, 9, 10};
     double se[7];
     if (N > 0.0) {
-      judge_se(a.params[a.cell_inst[c]], rho, tt, F[5 * C + c], N, judge_steps, J, se);
+      const InstParam& I = a.params[a.cell_inst[c]];
+      // the cell's own widths (graded box) or the uniform spacing
+      double hx = I.dx, hy = I.dy;
+      if (I.geom == DIG_GEOM_GRADED) {
+        const double* f = a.fc64 + I.face0;
+        const int lc = c - I.cell0, ix = lc % I.nx, iy = lc / I.nx;
+        hx = f[ix + 1] - f[ix];
+        if (I.dim == 2) hy = f[I.nx + 1 + iy + 1] - f[I.nx + 1 + iy];
+      }
+      judge_se(I, hx, hy, rho, tt, F[5 * C + c], N, judge_steps, J, se);
     } else {
       for (int j = 0; j < 7; ++j) se[j] = INFINITY;
     }

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <vector>
 #include <string>
 
 #include "dig_internal.h"
@@ -27,6 +28,10 @@ struct SynthGrid {
   double hx, hy, mu0, omega, zrot, gam, cv, cfl;
   double Att, Atr, Art, Arr;
   int bc_periodic[2];  // axis periodic?
+  // cell widths wx [nx], wy [ny] and, for every face, the distance between
+  // the centres on either side of it, gx [nx + 1], gy [ny + 1] (half a cell
+  // at a wall, the wrapped distance at a periodic seam); uniform grids: h
+  const double *wx, *wy, *gx, *gy;
 };
 
 struct SynthArrays {
@@ -65,17 +70,19 @@ __device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int
                          int axis) {
   if (axis == 1 && g.dim == 1) return 0.0;
   const int n = axis == 0 ? g.nx : g.ny;
-  const double h = axis == 0 ? g.hx : g.hy;
+  const double* gap = axis == 0 ? g.gx : g.gy;
   const int i = axis == 0 ? ix : iy;
   auto uk = [&](int j) {
     const int c = axis == 0 ? j + g.nx * iy : ix + g.nx * j;
     return W[(1 + k) * C + c] / W[c];
   };
-  if (g.bc_periodic[axis]) return (uk((i + 1) % n) - uk((i - 1 + n) % n)) / (2.0 * h);
+  // the two neighbours over the distance between their centres
+  if (g.bc_periodic[axis])
+    return (uk((i + 1) % n) - uk((i - 1 + n) % n)) / (gap[i] + gap[i + 1]);
   if (n < 2) return 0.0;
-  if (i > 0 && i < n - 1) return (uk(i + 1) - uk(i - 1)) / (2.0 * h);
-  if (i == 0) return (uk(1) - uk(0)) / h;
-  return (uk(n - 1) - uk(n - 2)) / h;
+  if (i > 0 && i < n - 1) return (uk(i + 1) - uk(i - 1)) / (gap[i] + gap[i + 1]);
+  if (i == 0) return (uk(1) - uk(0)) / gap[1];
+  return (uk(n - 1) - uk(n - 2)) / gap[n - 1];
 }
 
 // NSF + HoT stress and heat flux through a face normal to `axis`.
@@ -140,7 +147,8 @@ __device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays&
   const int fa = t % nfa, fb = t / nfa;  // axis 0: fa = fx, fb = iy; axis 1: fa = ix, fb = fy
   const int n = axis == 0 ? g.nx : g.ny;
   const int f = axis == 0 ? fa : fb;      // face index along the axis
-  const double h = axis == 0 ? g.hx : g.hy;
+  // distance between the centres across this face (half a cell at a wall)
+  const double h = (axis == 0 ? g.gx : g.gy)[f];
   const int periodic = g.bc_periodic[axis];
   auto cell_at = [&](int along) {
     return axis == 0 ? along + g.nx * fb : fa + g.nx * along;
@@ -214,13 +222,13 @@ __device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays&
     const double sgn = side == 0 ? 1.0 : -1.0;
     double dn[3], dtn[3], Hf[12];
     for (int i = 0; i < 3; ++i) {
-      dn[i] = sgn * (p.u[i] - uw[i]) / (0.5 * h);
+      dn[i] = sgn * (p.u[i] - uw[i]) / h;
       dtn[i] = g.dim == 2 ? dcen_u(g, s.W, C, ix, iy, i, 1 - axis) : 0.0;
     }
     for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
     double V[6];
-    visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / (0.5 * h),
-                    sgn * (p.tr - trw) / (0.5 * h), Hf, V);
+    visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / h,
+                    sgn * (p.tr - trw) / h, Hf, V);
     for (int k = 0; k < 6; ++k) F[k] = V[k];
     F[1 + axis] += p.rho * p.tt;
     F[0] = 0.0;
@@ -251,22 +259,27 @@ __global__ __launch_bounds__(256) void k_synth_flux(SynthGrid g, SynthArrays s, 
   }
 }
 
-__device__ double inv_local_dt(const SynthGrid& g, const Prim& p) {
+// Explicit stability bound of cell c (widths wx, wy of the cell).
+__device__ double inv_local_dt(const SynthGrid& g, const Prim& p, int c) {
   const double mu = g.mu0 * pow(p.tt, g.omega);
   double kt, kr;
   conductivities(g, mu, &kt, &kr);
-  const double c = sqrt(g.gam * p.tt);
+  const double cs = sqrt(g.gam * p.tt);
   const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
+  const double hx = g.wx[c % g.nx];
   double inv = 0.0;
-  inv += (fabs(p.u[0]) + c) / g.hx + 2.0 * nu / (g.hx * g.hx);
-  if (g.dim == 2) inv += (fabs(p.u[1]) + c) / g.hy + 2.0 * nu / (g.hy * g.hy);
+  inv += (fabs(p.u[0]) + cs) / hx + 2.0 * nu / (hx * hx);
+  if (g.dim == 2) {
+    const double hy = g.wy[c / g.nx];
+    inv += (fabs(p.u[1]) + cs) / hy + 2.0 * nu / (hy * hy);
+  }
   return inv;
 }
 
-__device__ double dt_bound(const SynthGrid& g, const Prim& p) {
+__device__ double dt_bound(const SynthGrid& g, const Prim& p, int c) {
   const double mu = g.mu0 * pow(p.tt, g.omega);
   const double tau = mu / (p.rho * p.tt);
-  return fmin(g.cfl / inv_local_dt(g, p), 0.5 * g.zrot * tau);
+  return fmin(g.cfl / inv_local_dt(g, p, c), 0.5 * g.zrot * tau);
 }
 
 // Positive doubles order like their bit patterns: min/max via 64-bit atomics.
@@ -285,10 +298,10 @@ __device__ double cell_residual(const SynthGrid& g, const SynthArrays& s, int c,
   const int nfx = (g.nx + 1) * g.ny;
   for (int k = 0; k < 6; ++k) {
     const double* Fx = s.Fx + (size_t)k * nfx;
-    R[k] = -(Fx[ix + 1 + (g.nx + 1) * iy] - Fx[ix + (g.nx + 1) * iy]) / g.hx;
+    R[k] = -(Fx[ix + 1 + (g.nx + 1) * iy] - Fx[ix + (g.nx + 1) * iy]) / g.wx[ix];
     if (g.dim == 2) {
       const double* Fy = s.Fy + (size_t)k * (g.nx * (g.ny + 1));
-      R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.hy;
+      R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.wy[iy];
     }
   }
   const double mu = g.mu0 * pow(p.tt, g.omega);
@@ -318,7 +331,7 @@ __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
     for (int k = 0; k < 6; ++k) s.Wn[k * C + c] = s.W[k * C + c] + dtau * R[k];
     const Prim q = prim_of(s.Wn, C, c, g.dr);
     ch = rel_change(p, q);
-    dtb = dt_bound(g, q);
+    dtb = dt_bound(g, q, c);
   }
   // block reductions, then one atomic per block
   __shared__ double s_min[4], s_max[4];
@@ -348,6 +361,7 @@ __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
 // equations), matrix-free in the form of Yoon and Jameson: per cell
 //   D dW_i + sum_j (dF_j . n_ij - r_j dW_j) / (2 h) = R_i,
 //   D = (1 + 1/cfl) sum_a r_a / h_a  (+ 1/(Z tau) on the rotational row),
+// h, h_a the widths of cell i,
 // r_a = |u_a| + c + 2 nu / h_a, dF_j = F(W_j + dW_j) - F(W_j) the change of
 // the neighbour's inviscid flux, j over the neighbours across interior and
 // periodic faces.  The cells are ordered in two colours ((ix + iy) even
@@ -355,8 +369,8 @@ __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
 // parallel passes: lower sweep dW = R / D on the first colour (k_lusgs_cells)
 // and dW = (R - sum_j ...) / D on the second (k_lusgs_lower); upper sweep
 // dW -= sum_j ... / D on the first colour (k_lusgs_upper).  The new state is
-// then scaled by the ratio of the initial to the current total mass
-// (k_lusgs_scale): the implicit operator is not conservative, the steady
+// then scaled by the ratio of the initial to the current total mass, sum of
+// rho V (k_lusgs_scale): the implicit operator is not conservative, the steady
 // state of a closed or periodic box keeps the initial mass.
 
 struct LusgsArrays {
@@ -392,7 +406,7 @@ __device__ void add_neighbours(const SynthGrid& g, const SynthArrays& s, const L
   const int C = g.nx * g.ny;
   const int n = axis == 0 ? g.nx : g.ny;
   const int i = axis == 0 ? c % g.nx : c / g.nx;
-  const double h = axis == 0 ? g.hx : g.hy;
+  const double h = (axis == 0 ? g.wx : g.wy)[i];  // width of the receiving cell
   for (int side = 1; side >= -1; side -= 2) {
     int j = i + side;
     if (j < 0 || j >= n) {
@@ -432,12 +446,14 @@ __global__ void k_lusgs_cells(SynthGrid g, SynthArrays s, LusgsArrays L, int it)
   conductivities(g, mu, &kt, &kr);
   const double cs = sqrt(g.gam * p.tt);
   const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
-  const double rx = fabs(p.u[0]) + cs + 2.0 * nu / g.hx;
-  double d = rx / g.hx;
+  const double hx = g.wx[c % g.nx];
+  const double rx = fabs(p.u[0]) + cs + 2.0 * nu / hx;
+  double d = rx / hx;
   double ry = 0.0;
   if (g.dim == 2) {
-    ry = fabs(p.u[1]) + cs + 2.0 * nu / g.hy;
-    d += ry / g.hy;
+    const double hy = g.wy[c / g.nx];
+    ry = fabs(p.u[1]) + cs + 2.0 * nu / hy;
+    d += ry / hy;
   }
   const double D0 = (1.0 + 1.0 / g.cfl) * d;
   const double D5 = D0 + 1.0 / (g.zrot * tau);
@@ -460,6 +476,11 @@ __global__ void k_lusgs_lower(SynthGrid g, SynthArrays s, LusgsArrays L) {
   if (g.dim == 2) add_neighbours<1>(g, s, L, c, acc);
   for (int k = 0; k < 6; ++k)
     L.dW[(size_t)k * C + c] = (L.R[(size_t)k * C + c] - acc[k]) / L.D[(k == 5 ? C : 0) + c];
+}
+
+// Volume of cell c (area in 2D, length in 1D): the mass of a cell is rho V.
+__device__ __forceinline__ double cell_vol(const SynthGrid& g, int c) {
+  return g.dim == 2 ? g.wx[c % g.nx] * g.wy[c / g.nx] : g.wx[c % g.nx];
 }
 
 // Fixed-order block sum (the same tree in every block and every call).
@@ -491,7 +512,7 @@ __global__ void k_lusgs_upper(SynthGrid g, SynthArrays s, LusgsArrays L) {
       for (int k = 0; k < 6; ++k) dW[k] = dW[k] - acc[k] / L.D[(k == 5 ? C : 0) + c];
     }
     for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] = s.W[(size_t)k * C + c] + dW[k];
-    rho_new = s.Wn[c];
+    rho_new = s.Wn[c] * cell_vol(g, c);
   }
   const double t = block_sum(rho_new, sh);
   if (threadIdx.x == 0) L.part[blockIdx.x] = t;
@@ -504,7 +525,7 @@ __global__ void k_lusgs_mass0(SynthGrid g, const double* W, LusgsArrays L) {
   double v = 0.0;
   for (int b = 0; b < L.nb; ++b) {
     const int c = b * (int)blockDim.x + threadIdx.x;
-    const double t = block_sum(c < C ? W[c] : 0.0, sh);
+    const double t = block_sum(c < C ? W[c] * cell_vol(g, c) : 0.0, sh);
     if (threadIdx.x == 0) v += t;
   }
   if (threadIdx.x == 0) L.part[L.nb] = v;
@@ -572,7 +593,7 @@ __global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* wa
   for (int k = 0; k < 3; ++k) p.u[k] = u[k];
   p.tt = tt;
   p.tr = tr;
-  red_min(&red[2], dt_bound(g, p));
+  red_min(&red[2], dt_bound(g, p, c));
 }
 
 __global__ void k_synth_mask_hot(const double* hot, const uint8_t* mask, double* H, int C) {
@@ -602,7 +623,7 @@ thread_local std::string g_serr;
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct SynthLayout {
-  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, total;
+  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, geo, total;
 };
 constexpr int kSynthBlock = 256;
 
@@ -631,6 +652,8 @@ SynthLayout synth_layout(const dig_config* c) {
   L.rad = take(8 * 2 * C);
   L.part = take(8 * ((C + kSynthBlock - 1) / kSynthBlock + 1));
   L.chg = take(8 * 2);
+  // grid geometry: widths wx, wy and centre distances gx, gy
+  L.geo = take(8 * (2 * (size_t)c->nx + 2 * (size_t)c->ny + 2));
   L.total = o;
   return L;
 }
@@ -659,7 +682,19 @@ static dig_status check_synth_args(const char* fn, const dig_config* cfg,
   if (cfg->nx < 1 || cfg->ny < 1 || (cfg->dim == 1 && cfg->ny != 1))
     return bad("bad cell counts");
   if ((int64_t)cfg->nx * cfg->ny > (int64_t)INT32_MAX / 64) return bad("too many cells");
-  if (cfg->geometry != DIG_GEOM_BOX) return bad("box geometry only");
+  if (cfg->geometry != DIG_GEOM_BOX && cfg->geometry != DIG_GEOM_GRADED)
+    return bad("boxes only (uniform or graded)");
+  if (cfg->geometry == DIG_GEOM_GRADED)
+    for (int ax = 0; ax < cfg->dim; ++ax) {
+      const double* f = ax == 0 ? cfg->xfaces : cfg->yfaces;
+      const int n = ax == 0 ? cfg->nx : cfg->ny;
+      if (!f) return bad("a graded box needs its face tables");
+      if (!(f[0] == 0.0) || !(f[n] == (ax == 0 ? cfg->lx : cfg->ly)))
+        return bad("face tables must run from 0 to the domain length");
+      for (int i = 0; i < n; ++i)
+        if (!std::isfinite(f[i + 1]) || !(f[i + 1] > f[i]))
+          return bad("face tables must be finite and strictly increasing");
+    }
   if (!(cfg->lx > 0.0) || !std::isfinite(cfg->lx) ||
       (cfg->dim == 2 && (!(cfg->ly > 0.0) || !std::isfinite(cfg->ly))))
     return bad("bad domain size");
@@ -696,6 +731,32 @@ static dig_status check_synth_args(const char* fn, const dig_config* cfg,
       if (cfg->bc[2 * ax].type == DIG_BC_PERIODIC && ((ax == 0 ? cfg->nx : cfg->ny) & 1))
         return bad("LU-SGS needs an even cell count on a periodic axis");
   return DIG_OK;
+}
+
+// Widths [n] and centre distances across the faces [n + 1] of one axis, in
+// that order in `out`: uniform grids h and h (h/2 at a wall); graded grids
+// from the face table (half the cell at a wall, the wrapped distance across
+// a periodic seam).
+static void axis_geometry(const dig_config* cfg, int axis, std::vector<double>& out) {
+  const int n = axis == 0 ? cfg->nx : cfg->ny;
+  const bool periodic = cfg->bc[2 * axis].type == DIG_BC_PERIODIC;
+  const double* f = axis == 0 ? cfg->xfaces : cfg->yfaces;
+  if (cfg->geometry == DIG_GEOM_GRADED && (axis == 0 || cfg->dim == 2)) {
+    std::vector<double> c(n);
+    for (int i = 0; i < n; ++i) {
+      out.push_back(f[i + 1] - f[i]);
+      c[i] = 0.5 * (f[i + 1] + f[i]);
+    }
+    const double g0 = periodic ? c[0] + (f[n] - c[n - 1]) : c[0] - f[0];
+    const double gn = periodic ? c[0] + (f[n] - c[n - 1]) : f[n] - c[n - 1];
+    out.push_back(g0);
+    for (int i = 1; i < n; ++i) out.push_back(c[i] - c[i - 1]);
+    out.push_back(gn);
+    return;
+  }
+  const double h = axis == 0 ? cfg->lx / cfg->nx : (cfg->dim == 2 ? cfg->ly / cfg->ny : 1.0);
+  for (int i = 0; i < n; ++i) out.push_back(h);
+  for (int i = 0; i <= n; ++i) out.push_back((i == 0 || i == n) && !periodic ? 0.5 * h : h);
 }
 
 dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const double* m_half,
@@ -747,6 +808,20 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   unsigned long long* red = (unsigned long long*)(w + L.red);
   if (hipMemcpyAsync(dwcfg, wcfg, sizeof(wcfg), hipMemcpyHostToDevice, s) != hipSuccess)
     return DIG_ERR_HIP;
+  // grid geometry: wx [nx], gx [nx + 1], wy [ny], gy [ny + 1]
+  std::vector<double> geo;
+  axis_geometry(cfg, 0, geo);
+  axis_geometry(cfg, 1, geo);
+  double* dgeo = (double*)(w + L.geo);
+  if (hipMemcpyAsync(dgeo, geo.data(), 8 * geo.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return DIG_ERR_HIP;
+  g.wx = dgeo;
+  g.gx = dgeo + g.nx;
+  g.wy = dgeo + 2 * g.nx + 1;
+  g.gy = g.wy + g.ny;
+  // every path below synchronises before returning while geo is alive, but
+  // the one without iterations
+  if (max_iter == 0 && hipStreamSynchronize(s) != hipSuccess) return DIG_ERR_HIP;
   const int bs = kSynthBlock, nb = (C + bs - 1) / bs;
   hipLaunchKernelGGL(k_synth_mask_hot, dim3(nb), dim3(bs), 0, s, hot, mask, H, C);
   // parity-1 reduction slots: dtau (min, from +inf; +inf and 0 have the bit

@@ -39,7 +39,9 @@ class DSMC:
         self.lib = L.load()
         self.workloads = list(workloads) if isinstance(workloads, (list, tuple)) else [workloads]
         self.n_inst = len(self.workloads)
-        self.cfgs = (L.DigConfig * self.n_inst)(*[L.make_config(w) for w in self.workloads])
+        # the configuration objects own the face tables the array points to
+        self._cfg_objs = [L.make_config(w) for w in self.workloads]
+        self.cfgs = (L.DigConfig * self.n_inst)(*self._cfg_objs)
         self.ncells = [w["nx"] * w.get("ny", 1) for w in self.workloads]
         self.ncell = int(sum(self.ncells))
         self.cell0 = np.concatenate([[0], np.cumsum(self.ncells)]).astype(np.int64)

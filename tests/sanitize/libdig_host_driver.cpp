@@ -130,6 +130,31 @@ int main() {
     b.edit(&c);
     expect_invalid(dig_plan(&c, 1, 10000, &L), b.what);
   }
+  // graded boxes: valid tables, then broken ones
+  double xf[9] = {0.0, 0.01, 0.03, 0.07, 0.5, 0.93, 0.97, 0.99, 1.0};
+  double yf[5] = {0.0, 0.1, 0.5, 0.9, 1.0};
+  dig_config gr = box(2, 8, 4);
+  gr.geometry = DIG_GEOM_GRADED;
+  gr.xfaces = xf;
+  gr.yfaces = yf;
+  expect(dig_plan(&gr, 1, 10000, &L) == DIG_OK, "graded plan");
+  expect(dig_synth_workspace_bytes(&gr) > 0, "graded synth workspace");
+  gr.yfaces = nullptr;
+  expect_invalid(dig_plan(&gr, 1, 10000, &L), "graded box without y faces");
+  gr.yfaces = yf;
+  xf[3] = 0.02;
+  expect_invalid(dig_plan(&gr, 1, 10000, &L), "graded faces not increasing");
+  xf[3] = 0.07;
+  xf[8] = 0.98;
+  expect_invalid(dig_plan(&gr, 1, 10000, &L), "graded faces short of lx");
+  xf[8] = 1.0;
+  yf[2] = NAN;
+  expect_invalid(dig_plan(&gr, 1, 10000, &L), "graded faces not finite");
+  yf[2] = 0.5;
+  xf[2] = 0.01 + 1e-12;
+  expect_invalid(dig_plan(&gr, 1, 10000, &L), "graded faces equal in FP32");
+  xf[2] = 0.03;
+  expect(dig_plan(&gr, 1, 10000, &L) == DIG_OK, "graded plan after repair");
   dig_config two[2] = {annulus(), annulus()};
   expect_invalid(dig_plan(two, 2, 10000, &L), "two annulus instances");
   dig_config mixed[2] = {box(1, 10, 1), box(2, 10, 10)};
