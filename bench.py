@@ -155,7 +155,7 @@ def run_cavity(args):
 
     def dig_cycle(target=None):
         f = sim.sample("average")
-        hot, mask, _, _ = sim.closure(f, A, 0.01)
+        hot, mask, _, _ = sim.closure(f, A, 0.01, n_min=1.0)
         if target == "synth":
             tgt, it, ch = synth_solve(w, f, hot, mask, A, wall_mode="dsmc",
                                       max_iter=args.synth_iters, tol=1e-5,

@@ -203,10 +203,14 @@ dig_status dig_adjust(dig_ctx* ctx, const double* target_dev, uint32_t dig_iter,
  * fields_dev = [20][C] from dsmc_sample.  A_host = relaxation matrix
  * (Att, Atr, Art, Arr) of equation kappa_A.  Outputs: hot_dev [12][C]
  * (sigma xx yy zz xy xz yz, q_t xyz, q_r xyz) = DSMC - NSF, zeroed where
- * Kn_GLL < kn_ref; mask_dev [C] (1 = equilibrium, HoT zeroed); kngll_dev [C];
- * nsf_dev [12][C] or NULL.  Gradients: central, one-sided at walls. */
+ * Kn_GLL < kn_ref or where the cell's mean particle count (row 19 of
+ * fields_dev) is below n_min (terms extracted from so few samples are
+ * sampling noise; n_min = 0 switches this off); mask_dev [C] (1 = equilibrium,
+ * HoT zeroed); kngll_dev [C]; nsf_dev [12][C] or NULL.  Gradients: the
+ * neighbours' difference over the distance between their centres, one-sided
+ * at walls.  Errors: DIG_ERR_INVALID (null pointer, singular A, n_min < 0). */
 dig_status closure_assemble(dig_ctx* ctx, const double* fields_dev, const double* A_host,
-                            double kn_ref, double* hot_dev, uint8_t* mask_dev,
+                            double kn_ref, double n_min, double* hot_dev, uint8_t* mask_dev,
                             double* kngll_dev, double* nsf_dev, dig_stream_t stream);
 
 /* Synthetic-equation solve, DIG step 3 (Section 3): the steady equations of
@@ -445,6 +449,19 @@ typedef struct {
  * closure_assemble.  Targets, standardised: HoT sigma_xx/p, sigma_xy/p,
  * sigma_yy/p, HoT q_t,x, q_t,y, q_r,x, q_r,y over p sqrt(Tt).  Empty cells:
  * zeros.  x_dev [C][9] f32; t_dev [C][7] f32 or NULL. */
+/* Empty cells of a time average, before the closure of a DIG cycle: every
+ * cell of fields_dev [20][C] without a usable sample (mean particle count,
+ * row 19, not positive; rho or Tt not positive; Tr negative; or a non-finite
+ * value in rows 0..5) takes rho, u, Tt, Tr from fallback_dev [6][C] (the
+ * previous macroscopic solution), zero stresses and heat fluxes, the total
+ * temperature (3 Tt + d_r Tr) / (3 + d_r) of the fallback and N = 0, so that
+ * closure_assemble with n_min > 0 keeps its NSF closure and the synthetic
+ * solve starts from a state in every cell.  The thinnest cells of a
+ * wall-refined grid (Section 4.1) can stay empty over a whole cycle.  In
+ * place, on `stream`.  Errors: DIG_ERR_INVALID (null pointer). */
+dig_status fields_fill_empty(dig_ctx* ctx, double* fields_dev, const double* fallback_dev,
+                             dig_stream_t stream);
+
 dig_status closure_features(dig_ctx* ctx, const double* fields_dev, const double* kngll_dev,
                             const double* hot_dev, const dig_mlp_scaling* scaling_host,
                             float* x_dev, float* t_dev, dig_stream_t stream);

@@ -102,7 +102,7 @@ def _configure(L):
                              C.c_uint32, C.c_uint64, C.c_int64, _d, _d, _d, _d, _d,
                              _d, _u32, _i64, _i64, C.POINTER(C.c_uint64)]
     L.orc_adjust.restype = C.c_int
-    L.orc_closure.argtypes = [cp, _d, _d, C.c_double, _d, _u8, _d, _d]
+    L.orc_closure.argtypes = [cp, _d, _d, C.c_double, C.c_double, _d, _u8, _d, _d]
     return L
 
 
@@ -383,18 +383,43 @@ class State:
         return 0
 
 
-def closure(w: dict, fields: np.ndarray, A, kn_ref: float):
+def closure(w: dict, fields: np.ndarray, A, kn_ref: float, n_min: float = 0.0):
     cfg = make_config(w)
     ncell = w["nx"] * w.get("ny", 1)
     f = np.ascontiguousarray(fields, dtype=np.float64)
+    assert f.shape == (20, ncell), f.shape  # rows as produced by the sampling (row 19: N)
     a = np.ascontiguousarray(A, dtype=np.float64)
     hot = np.zeros((12, ncell))
     nsf = np.zeros((12, ncell))
     mask = np.zeros(ncell, dtype=np.uint8)
     kn = np.zeros(ncell)
-    lib().orc_closure(C.byref(cfg), _p(f, _d), _p(a, _d), float(kn_ref), _p(hot, _d),
+    lib().orc_closure(C.byref(cfg), _p(f, _d), _p(a, _d), float(kn_ref), float(n_min), _p(hot, _d),
                       _p(mask, _u8), _p(kn, _d), _p(nsf, _d))
     return hot, mask, kn, nsf
+
+
+def fill_empty(fields: np.ndarray, fallback: np.ndarray, dr: int = 2) -> np.ndarray:
+    """Cells of a time average [20, C] without a usable sample (mean count,
+    row 19, not positive; rho or Tt not positive; Tr negative; or rows 0..5
+    not finite) take rho, u, Tt, Tr from fallback [6, C] (the previous
+    macroscopic solution of the DIG loop), zero stresses and heat fluxes,
+    the total temperature (3 Tt + d_r Tr) / (3 + d_r) of the fallback, and
+    N = 0.  Returns a new array.  (Not in the paper: the thinnest cells of a
+    wall-refined grid can stay empty over a whole DIG cycle, and the
+    synthetic solve needs a state in every cell.)"""
+    f = np.array(fields, dtype=np.float64, copy=True)
+    fb = np.asarray(fallback, dtype=np.float64)
+    for c in range(f.shape[1]):
+        rho, tt, tr, n = f[0, c], f[4, c], f[5, c], f[19, c]
+        usable = (n > 0 and rho > 0 and tt > 0 and tr >= 0
+                  and all(np.isfinite(f[k, c]) for k in range(6)))
+        if usable:
+            continue
+        f[0:6, c] = fb[0:6, c]
+        f[6:18, c] = 0.0
+        f[18, c] = (3.0 * fb[4, c] + dr * fb[5, c]) / (3.0 + dr)
+        f[19, c] = 0.0
+    return f
 
 
 def sgmax_default(w: dict) -> float:

@@ -823,6 +823,8 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
 /* Closure assembly (Sections 2.3 and 3.1).  fields = [20][ncell] as produced
  * by orc_sums_to_fields.  Outputs hot = [12][ncell] (sigma xx,yy,zz,xy,xz,yz,
  * q_t xyz, q_r xyz) = DSMC - NSF, zeroed where Kn_GLL < kn_ref (mask = 1);
+ * cells whose mean particle count (fields row 19) is below n_min also count
+ * as in equilibrium: terms extracted from so few samples are noise;
  * nsf (optional) = the NSF terms themselves. */
 /* Cell-centre coordinate of cell i along `axis` (graded box), and the
  * distance between the centres of cells a and b = a + 1 (mod n across a
@@ -865,7 +867,7 @@ static double grad_axis(const orc_config* c, const double* f, int32_t ix, int32_
 }
 
 void orc_closure(const orc_config* c, const double* fields, const double A[4], double kn_ref,
-                 double* hot, uint8_t* mask, double* kn_gll, double* nsf) {
+                 double n_min, double* hot, uint8_t* mask, double* kn_gll, double* nsf) {
   int32_t ncell = c->nx * c->ny;
   const double *rho = fields, *ux = fields + ncell, *uy = fields + 2 * ncell,
                *uz = fields + 3 * ncell, *tt = fields + 4 * ncell, *tr = fields + 5 * ncell;
@@ -922,7 +924,7 @@ void orc_closure(const orc_config* c, const double* fields, const double A[4], d
       if (gr > m) m = gr;
       kn = lam * m;
     }
-    uint8_t eq = (kn < kn_ref) ? 1 : 0;
+    uint8_t eq = (kn < kn_ref || fields[19 * (int64_t)ncell + k] < n_min) ? 1 : 0;
     for (int f = 0; f < 12; ++f) {
       hot[f * (int64_t)ncell + k] = (eq || !(rho[k] > 0.0 && tt[k] > 0.0)) ? 0.0 : h[f];
       if (nsf) nsf[f * (int64_t)ncell + k] = out_nsf[f];

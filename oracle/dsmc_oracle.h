@@ -117,7 +117,7 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
                int64_t* n_out, uint64_t* next_id_out);
 
 void orc_closure(const orc_config* c, const double* fields, const double A[4], double kn_ref,
-                 double* hot, uint8_t* mask, double* kn_gll, double* nsf);
+                 double n_min, double* hot, uint8_t* mask, double* kn_gll, double* nsf);
 
 #ifdef __cplusplus
 }

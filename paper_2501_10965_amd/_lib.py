@@ -99,7 +99,8 @@ EXPORTS = ["dig_plan", "dsmc_create", "dsmc_init", "dsmc_inject", "dsmc_step", "
            "synth_solve", "dsmc_query", "dig_constants", "dsmc_profile", "dsmc_profile_kinds",
            "dsmc_tuning", "dsmc_autotune", "dsmc_step_graph", "mlp_plan", "mlp_create", "mlp_sync", "mlp_forward",
            "mlp_grad", "mlp_adam", "mlp_train_step", "mlp_destroy", "closure_features",
-           "closure_blend", "dsmc_save", "dsmc_load", "synth_solve_static", "dig_last_error",
+           "closure_blend", "dsmc_save", "dsmc_load", "synth_solve_static", "fields_fill_empty",
+           "dig_last_error",
            "dsmc_destroy"]
 KERNELS = ["move", "scan", "place", "order", "collide", "adjust", "sample", "closure"]
 
@@ -150,8 +151,9 @@ def load(path: str = LIB_PATH):
     L.dsmc_stage.argtypes = [vp, C.c_int32, vp]
     L.dsmc_sample.argtypes = [vp, C.c_int32, vp, vp]
     L.dig_adjust.argtypes = [vp, vp, C.c_uint32, vp]
-    L.closure_assemble.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, vp, vp, vp, vp,
-                                   vp]
+    L.fields_fill_empty.argtypes = [vp, vp, vp, vp]
+    L.closure_assemble.argtypes = [vp, vp, C.POINTER(C.c_double), C.c_double, C.c_double, vp,
+                                   vp, vp, vp, vp]
     L.dsmc_query.argtypes = [vp, C.POINTER(DigCounters), vp]
     L.synth_solve_static.argtypes = [cp, C.POINTER(DigSynthOpts), vp, vp, vp, vp, C.c_int32,
                                      C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double),

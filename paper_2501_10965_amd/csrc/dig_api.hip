@@ -900,19 +900,21 @@ dig_status dig_adjust(dig_ctx* c, const double* target, uint32_t iter, dig_strea
 }
 
 dig_status closure_assemble(dig_ctx* c, const double* fields, const double* A, double kn_ref,
-                            double* hot, uint8_t* mask, double* kngll, double* nsf,
-                            dig_stream_t stream) {
+                            double n_min, double* hot, uint8_t* mask, double* kngll,
+                            double* nsf, dig_stream_t stream) {
   if (check_ctx(c)) return DIG_ERR_INVALID;
   if (!fields || !A || !hot || !mask || !kngll) return fail(DIG_ERR_INVALID, "null argument");
   const double det = A[0] * A[3] - A[1] * A[2];
   if (!(fabs(det) > 0.0)) return fail(DIG_ERR_INVALID, "singular relaxation matrix A");
+  if (!(n_min >= 0.0)) return fail(DIG_ERR_INVALID, "n_min must be >= 0");
   for (const auto& g : c->cfg)
     if (g.geometry == DIG_GEOM_ANNULUS)
       return fail(DIG_ERR_INVALID, "closure_assemble supports boxes only (uniform or graded)");
   StepArgs a = args(c);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(timed(c, DIG_K_CLOSURE, s, [&] {
-    return launch_closure(a, fields, A[0], A[1], A[2], A[3], kn_ref, hot, mask, kngll, nsf, s);
+    return launch_closure(a, fields, A[0], A[1], A[2], A[3], kn_ref, n_min, hot, mask, kngll,
+                          nsf, s);
   }));
   return DIG_OK;
 }
@@ -929,6 +931,14 @@ static dig_status scaling_of(const dig_mlp_scaling* in, MlpScale* out) {
     out->y_std[k] = in->y_std[k];
     if (!(in->y_std[k] > 0.0)) return fail(DIG_ERR_INVALID, "scaling std must be > 0");
   }
+  return DIG_OK;
+}
+
+dig_status fields_fill_empty(dig_ctx* c, double* fields, const double* fallback,
+                             dig_stream_t stream) {
+  if (check_ctx(c)) return DIG_ERR_INVALID;
+  if (!fields || !fallback) return fail(DIG_ERR_INVALID, "null argument");
+  HIP_TRY(launch_fill_empty(args(c), fields, fallback, (hipStream_t)stream));
   return DIG_OK;
 }
 

@@ -188,8 +188,10 @@ hipError_t launch_exscan2(const int32_t* in0, int32_t* out0, const int32_t* in1,
 hipError_t launch_adjust_build(const StepArgs& a, const double* target, uint32_t iter,
                                const int32_t* newstart, const int32_t* cstart,
                                hipStream_t s);
+hipError_t launch_fill_empty(const StepArgs& a, double* fields, const double* fallback,
+                             hipStream_t s);
 hipError_t launch_closure(const StepArgs& a, const double* fields, double Att, double Atr,
-                          double Art, double Arr, double kn_ref, double* hot, uint8_t* mask,
-                          double* kngll, double* nsf, hipStream_t s);
+                          double Art, double Arr, double kn_ref, double n_min, double* hot,
+                          uint8_t* mask, double* kngll, double* nsf, hipStream_t s);
 
 }  // namespace dig

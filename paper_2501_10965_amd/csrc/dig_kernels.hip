@@ -2071,8 +2071,8 @@ static __device__ double grad_axis(const StepArgs& a, const InstParam& I, const 
 }
 
 __global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, double Art,
-                          double Arr, double kn_ref, double* hot, uint8_t* mask, double* kngll,
-                          double* nsf, double* speed) {
+                          double Arr, double kn_ref, double n_min, double* hot, uint8_t* mask,
+                          double* kngll, double* nsf, double* speed) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = a.ncell;
   if (c >= C) return;
@@ -2117,7 +2117,9 @@ __global__ void k_closure(StepArgs a, const double* F, double Att, double Atr, d
     if (tr > 0.0) m = fmax(m, sqrt(d[4][0] * d[4][0] + d[4][1] * d[4][1]) / tr);
     kn = lam * m;
   }
-  const uint8_t eq = kn < kn_ref ? 1 : 0;
+  // equilibrium: Kn_GLL below kn_ref, or too few particles (mean count, row
+  // 19) for the extracted terms to be more than sampling noise
+  const uint8_t eq = (kn < kn_ref || F[19 * (int64_t)C + c] < n_min) ? 1 : 0;
   for (int f = 0; f < 12; ++f) {
     hot[(int64_t)f * C + c] = (eq || !ok) ? 0.0 : h[f];
     if (nsf) nsf[(int64_t)f * C + c] = q[f];
@@ -2454,14 +2456,38 @@ hipError_t launch_adjust_build(const StepArgs& a, const double* target, uint32_t
   return hipGetLastError();
 }
 
+// Empty cells of a time average take the fallback state (see fields_fill_empty).
+__global__ void k_fill_empty(StepArgs a, double* F, const double* fb) {
+#pragma clang fp contract(off)
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int C = a.ncell;
+  if (c >= C) return;
+  const double rho = F[c], tt = F[4 * C + c], tr = F[5 * C + c], n = F[19 * (int64_t)C + c];
+  bool usable = n > 0.0 && rho > 0.0 && tt > 0.0 && tr >= 0.0;
+  for (int k = 0; k < 6; ++k) usable = usable && isfinite(F[(int64_t)k * C + c]);
+  if (usable) return;
+  const int dr = a.params[a.cell_inst[c]].dr;
+  for (int k = 0; k < 6; ++k) F[(int64_t)k * C + c] = fb[(int64_t)k * C + c];
+  for (int k = 6; k < 18; ++k) F[(int64_t)k * C + c] = 0.0;
+  F[18 * (int64_t)C + c] = (3.0 * fb[4 * C + c] + dr * fb[5 * C + c]) / (3.0 + dr);
+  F[19 * (int64_t)C + c] = 0.0;
+}
+
+hipError_t launch_fill_empty(const StepArgs& a, double* fields, const double* fallback,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_empty, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, a, fields,
+                     fallback);
+  return hipGetLastError();
+}
+
 hipError_t launch_closure(const StepArgs& a, const double* fields, double Att, double Atr,
-                          double Art, double Arr, double kn_ref, double* hot, uint8_t* mask,
-                          double* kngll, double* nsf, hipStream_t s) {
+                          double Art, double Arr, double kn_ref, double n_min, double* hot,
+                          uint8_t* mask, double* kngll, double* nsf, hipStream_t s) {
   // speed of each cell, staged in the sums scratch (C doubles)
   hipLaunchKernelGGL(k_speed, dim3(blocks_for(a.ncell, 256)), dim3(256), 0, s, fields, a.ncell,
                      a.sums);
   hipLaunchKernelGGL(k_closure, dim3(blocks_for(a.ncell, 128)), dim3(128), 0, s, a, fields, Att,
-                     Atr, Art, Arr, kn_ref, hot, mask, kngll, nsf, a.sums);
+                     Atr, Art, Arr, kn_ref, n_min, hot, mask, kngll, nsf, a.sums);
   return hipGetLastError();
 }
 

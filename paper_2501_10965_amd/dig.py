@@ -32,7 +32,7 @@ class DIG:
                  tol: float = 1e-5, kn_ref: float = 0.01, A=None, wall_mode: str = "dsmc",
                  closure=None, capacity: int | None = None, cfl: float | None = None,
                  nsf_init: bool = True, init_iters: int | None = None, graph: bool = True,
-                 scheme: str = "explicit", **dsmc_kw):
+                 scheme: str = "explicit", n_min: float = 1.0, **dsmc_kw):
         assert mode in ("dig", "dsmc")
         self.w = w
         self.mode = mode
@@ -40,6 +40,9 @@ class DIG:
         self.n_m = n_m
         self.tol = tol
         self.kn_ref = kn_ref
+        # cells holding on average fewer particles than this keep the NSF closure
+        # (their extracted higher-order terms are sampling noise)
+        self.n_min = n_min
         self.A = A if A is not None else default_A(w["omega"])
         self.wall_mode = wall_mode
         self.cfl = cfl  # None: the scheme's default
@@ -76,7 +79,9 @@ class DIG:
         f = self.sim.sample("average")
         rec = {"cycle": self.cycle_no}
         if self.mode == "dig":
-            hot, mask, kn, _ = self.sim.closure(f, self.A, self.kn_ref)
+            # cells left empty over the cycle start from the previous solution
+            self.sim.fill_empty(f, self.m_prev)
+            hot, mask, kn, _ = self.sim.closure(f, self.A, self.kn_ref, n_min=self.n_min)
             if self.closure_fn is not None:
                 smooth = torch.zeros((20, self.ncell), dtype=torch.float64, device=f.device)
                 smooth[0:6] = self.m_prev

@@ -215,7 +215,10 @@ class DSMC:
         t = target.to(device=self.device, dtype=torch.float64).contiguous()
         L.check(self.lib.dig_adjust(self.ctx, _ptr(t), int(dig_iter), _stream()))
 
-    def closure(self, fields: torch.Tensor, A, kn_ref: float, with_nsf: bool = False):
+    def closure(self, fields: torch.Tensor, A, kn_ref: float, with_nsf: bool = False,
+                n_min: float = 0.0):
+        """closure_assemble: (hot, mask, kn_gll, nsf or None); cells with a mean
+        particle count below n_min are treated as in equilibrium."""
         nc = self.ncell
         f = fields.contiguous()
         hot = torch.empty((12, nc), dtype=torch.float64, device=self.device)
@@ -223,10 +226,19 @@ class DSMC:
         kn = torch.empty(nc, dtype=torch.float64, device=self.device)
         nsf = torch.empty((12, nc), dtype=torch.float64, device=self.device) if with_nsf else None
         a = (C.c_double * 4)(*[float(v) for v in A])
-        L.check(self.lib.closure_assemble(self.ctx, _ptr(f), a, float(kn_ref), _ptr(hot),
+        L.check(self.lib.closure_assemble(self.ctx, _ptr(f), a, float(kn_ref), float(n_min),
+                                          _ptr(hot),
                                           _ptr(mask), _ptr(kn),
                                           _ptr(nsf) if nsf is not None else None, _stream()))
         return hot, mask, kn, nsf
+
+    def fill_empty(self, fields: torch.Tensor, fallback: torch.Tensor):
+        """fields_fill_empty: cells of the time average [20, C] (in place)
+        without a usable sample take the fallback state [>=6, C]."""
+        assert fields.is_contiguous() and fields.dtype == torch.float64
+        fb = fallback[0:6].contiguous()
+        L.check(self.lib.fields_fill_empty(self.ctx, _ptr(fields), _ptr(fb), _stream()))
+        return fields
 
     def features(self, fields: torch.Tensor, kngll: torch.Tensor, scaling: dict,
                  hot: torch.Tensor | None = None):

@@ -23,12 +23,27 @@ from .dig import DIG
 from .dsmc import DSMC
 
 
-def centreline(f: torch.Tensor, nx: int, ny: int, points: int, columns: int = 2) -> torch.Tensor:
+def centreline(f: torch.Tensor, nx: int, ny: int, points: int, columns: int = 2,
+               w: dict | None = None) -> torch.Tensor:
     """u_x of the `columns` centre columns, averaged across them and over
-    `points` blocks along y."""
+    `points` equal blocks along y.  On a graded grid (w given, geometry
+    "graded") the columns are averaged with their widths and each block
+    averages the cells it overlaps, weighted by the overlap, so that profiles
+    of different grids compare at the same y blocks."""
     h = columns // 2
-    ux = f[1].view(ny, nx)[:, nx // 2 - h: nx // 2 + h].mean(1)
-    return ux.view(points, ny // points).mean(1)
+    if w is None or w.get("geometry") != "graded":
+        ux = f[1].view(ny, nx)[:, nx // 2 - h: nx // 2 + h].mean(1)
+        return ux.view(points, ny // points).mean(1)
+    fx = torch.tensor(w["xfaces"], dtype=torch.float64, device=f.device)
+    fy = torch.tensor(w["yfaces"], dtype=torch.float64, device=f.device)
+    cw = (fx[1:] - fx[:-1])[nx // 2 - h: nx // 2 + h]
+    ux = (f[1].view(ny, nx)[:, nx // 2 - h: nx // 2 + h] * cw).sum(1) / cw.sum()
+    L = float(fy[-1])
+    b = torch.linspace(0.0, L, points + 1, dtype=torch.float64, device=f.device)
+    lo = torch.maximum(b[:-1, None], fy[None, :-1])
+    hi = torch.minimum(b[1:, None], fy[None, 1:])
+    wgt = (hi - lo).clamp(min=0.0)           # [points, ny] overlap lengths
+    return (wgt * ux[None, :]).sum(1) / wgt.sum(1)
 
 
 def reference_profile(w: dict, transient: int, average: int, points: int,
@@ -85,7 +100,7 @@ def run_plain(w, ref, ns, max_cycles, window, threshold, points, columns=2):
         f = sim.sample("average")
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-        tr.add(centreline(f, w["nx"], w["ny"], points, columns), wall, (k + 1) * ns)
+        tr.add(centreline(f, w["nx"], w["ny"], points, columns, w), wall, (k + 1) * ns)
         if _settled(tr, window):
             break
     return tr
@@ -104,7 +119,7 @@ def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, columns
         f = d.cycle()
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
-        tr.add(centreline(f, w["nx"], w["ny"], points, columns), wall, (k + 1) * d.ns)
+        tr.add(centreline(f, w["nx"], w["ny"], points, columns, w), wall, (k + 1) * d.ns)
         if _settled(tr, window):
             break
     return tr, d

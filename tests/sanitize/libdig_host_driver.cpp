@@ -212,7 +212,7 @@ int main() {
   expect(dsmc_stage(nullptr, 1, nullptr) != DIG_OK, "dsmc_stage null");
   expect(dsmc_sample(nullptr, 0, nullptr, nullptr) != DIG_OK, "dsmc_sample null");
   expect(dig_adjust(nullptr, nullptr, 0, nullptr) != DIG_OK, "dig_adjust null");
-  expect(closure_assemble(nullptr, nullptr, nullptr, 0.01, nullptr, nullptr, nullptr, nullptr,
+  expect(closure_assemble(nullptr, nullptr, nullptr, 0.01, 1.0, nullptr, nullptr, nullptr, nullptr,
                           nullptr) != DIG_OK,
          "closure_assemble null");
   expect(dsmc_save(nullptr, nullptr, &bytes, nullptr) != DIG_OK, "dsmc_save null");
@@ -221,6 +221,7 @@ int main() {
   expect(dig_constants(nullptr, 0, c5) != DIG_OK, "dig_constants null");
   expect(dsmc_tuning(nullptr, nullptr, &tu) != DIG_OK, "dsmc_tuning null");
   expect(dsmc_autotune(nullptr, 5, nullptr, &tu, nullptr) != DIG_OK, "dsmc_autotune null");
+  expect(fields_fill_empty(nullptr, nullptr, nullptr, nullptr) != DIG_OK, "fields_fill_empty null");
   expect(closure_features(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                           nullptr) != DIG_OK,
          "closure_features null");

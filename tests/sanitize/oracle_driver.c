@@ -102,7 +102,7 @@ static double run_case(const char* name, orc_config* c, int ppc, int64_t cap, in
   }
   orc_sums_to_fields(c, nc, acc, (double)nsteps, avg);
   const double A[4] = {2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * c->omega)};
-  orc_closure(c, avg, A, 0.01, hot, mask, kn, nsf);
+  orc_closure(c, avg, A, 0.01, 1.0, hot, mask, kn, nsf);
   int64_t n_out = 0;
   uint64_t nid_out = 0;
   int rc = -1;

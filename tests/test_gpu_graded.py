@@ -134,9 +134,13 @@ def test_graded_closure_matches_oracle(name):
     say(f"case graded closure {name}")
     f = _smooth_fields(w, 4)
     A = [2.0 / 3.0, 0.05, 0.02, 5.0 / (7 - 2 * 0.74)]
-    hot, mask, kn, nsf = oracle.closure(w, f, A, 0.01)
+    # n_min 30: the cells holding on average fewer than 30 particles (row 19
+    # ranges over 20..60) keep the NSF closure
+    hot, mask, kn, nsf = oracle.closure(w, f, A, 0.01, n_min=30.0)
+    assert 0 < (f[19] < 30).sum() < len(f[19])
     sim = DSMC(w)
-    gh, gm, gk, gn = sim.closure(torch.tensor(f, device="cuda"), A, 0.01, with_nsf=True)
+    gh, gm, gk, gn = sim.closure(torch.tensor(f, device="cuda"), A, 0.01, with_nsf=True,
+                                 n_min=30.0)
     np.testing.assert_array_equal(np_(gm), mask)
     np.testing.assert_allclose(np_(gk), kn, rtol=1e-12)
     np.testing.assert_allclose(np_(gh), hot, rtol=1e-11, atol=1e-15)
@@ -220,3 +224,23 @@ def test_graded_checkpoint_round_trip():
     b = {k: np.array(v, copy=True) for k, v in gpu_state(sim).items()}
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_fill_empty_matches_oracle():
+    w = CASES["cavity"]
+    say("case fill empty")
+    C = w["nx"] * w["ny"]
+    f = _smooth_fields(w, 9)
+    rng = np.random.default_rng(10)
+    idx = rng.choice(C, 40, replace=False)
+    f[19, idx[:10]] = 0.0
+    f[0, idx[10:20]] = 0.0
+    f[4, idx[20:30]] = 0.0
+    f[5, idx[30:35]] = np.nan
+    f[5, idx[35:]] = -1.0
+    fb = 0.5 + rng.random((6, C))
+    ref = oracle.fill_empty(f, fb, dr=2)
+    sim = DSMC(w)
+    g = torch.tensor(f, device="cuda")
+    sim.fill_empty(g, torch.tensor(fb, device="cuda"))
+    np.testing.assert_array_equal(np_(g), ref)

@@ -171,3 +171,56 @@ def test_planted_mistake_is_caught(name, tmp_path):
         err = kn_error()
     assert err > 1e-3, f"planted mistake {name} not caught (error {err:.2e})"
     assert kn_error() < 1e-12  # the real oracle is back in place
+
+
+def test_sparse_cells_are_treated_as_equilibrium():
+    """Cells holding on average fewer than n_min particles (row 19) give no
+    higher-order terms: mask 1 and HoT 0, Kn_GLL unchanged; the other cells
+    are untouched, and n_min = 0 changes nothing."""
+    import dig_workloads as wl
+    w = wl.cavity_2d(n=8, kn=0.05)
+    rng = np.random.default_rng(12)
+    f = np.zeros((20, 64))
+    f[0] = 1.0 + 0.2 * rng.random(64)
+    f[1:4] = 0.1 * rng.standard_normal((3, 64))
+    f[4] = 1.0 + 0.3 * rng.random(64)
+    f[5] = 1.0 + 0.3 * rng.random(64)
+    f[6:18] = 0.05 * rng.standard_normal((12, 64))
+    f[19] = 0.5 + 3.0 * rng.random(64)
+    A = (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * wl.OMEGA_N2))
+    h0, m0, k0, n0 = oracle.closure(w, f, A, 0.001)
+    hz, mz, kz, nz = oracle.closure(w, f, A, 0.001, n_min=0.0)
+    assert np.array_equal(h0, hz) and np.array_equal(m0, mz)
+    h1, m1, k1, n1 = oracle.closure(w, f, A, 0.001, n_min=1.5)
+    sparse = f[19] < 1.5
+    assert 0 < sparse.sum() < 64
+    assert np.all(m1[sparse] == 1) and np.all(h1[:, sparse] == 0.0)
+    np.testing.assert_array_equal(m1[~sparse], m0[~sparse])
+    np.testing.assert_array_equal(h1[:, ~sparse], h0[:, ~sparse])
+    np.testing.assert_array_equal(k1, k0)
+    np.testing.assert_array_equal(n1, n0)
+
+
+def test_fill_empty_takes_the_fallback_only_where_no_sample_is_usable():
+    rng = np.random.default_rng(3)
+    C = 40
+    f = np.zeros((20, C))
+    f[0] = 1.0 + rng.random(C)
+    f[1:4] = rng.standard_normal((3, C))
+    f[4] = 1.0 + rng.random(C)
+    f[5] = 1.0 + rng.random(C)
+    f[6:19] = rng.standard_normal((13, C))
+    f[19] = 1.0 + 5.0 * rng.random(C)
+    bad = {3: (19, 0.0), 7: (0, 0.0), 11: (4, 0.0), 15: (5, -0.1), 21: (2, np.nan),
+           25: (4, np.inf)}
+    for c, (row, v) in bad.items():
+        f[row, c] = v
+    fb = rng.random((6, C)) + 0.5
+    out = oracle.fill_empty(f, fb, dr=2)
+    good = np.ones(C, bool)
+    good[list(bad)] = False
+    np.testing.assert_array_equal(out[:, good], f[:, good])
+    np.testing.assert_array_equal(out[0:6, ~good], fb[:, ~good])
+    assert np.all(out[6:18, ~good] == 0.0) and np.all(out[19, ~good] == 0.0)
+    np.testing.assert_allclose(out[18, ~good], (3 * fb[4, ~good] + 2 * fb[5, ~good]) / 5,
+                               rtol=1e-15)
