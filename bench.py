@@ -512,6 +512,16 @@ def run_steady(args):
         tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, ns=w["ns"], n_m=2000,
                                wall_mode="wall", scheme="explicit", columns=cols)
         arms["dig_explicit"] = tr
+    if args.steady_graded_arm:
+        # the paper's DIG grid for this Kn (Section 4.1, Table 1): 100 x 100 cells refined
+        # toward the walls (first cell 0.001), a larger time step, slip and jump from DSMC
+        g = wl.cavity_graded(seed=2101, n=100, first=0.001, ppc=50, kn=w["kn"],
+                             lid=w["bc"][3][2][0], dt_frac=0.5)
+        progress("DIG arm on the wall-refined 100 x 100 grid")
+        tr, _ = steady.run_dig(g, ref, args.dig_max_cycles, W, thr, P, ns=w["ns"],
+                               n_m=args.synth_iters, wall_mode="dsmc", scheme=args.synth_scheme,
+                               columns=2)
+        arms["dig_graded_100"] = tr
     progress("closure-network training")
     KNS = [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.5]
     MAS = [0.1, 0.25, 0.5, 1.0]
@@ -542,6 +552,10 @@ def run_steady(args):
         res[name] = {"seconds": None if t is None else round(t[0], 3),
                      "steps": None if t is None else t[1],
                      "final_err": round(tr.history[-1][2], 5) if tr.history else None,
+                     "min_err": round(min(e for _, _, e in tr.history), 5) if tr.history else None,
+                     "seconds_to": {str(x): (None if tr.time_to_steady(x) is None
+                                             else round(tr.time_to_steady(x)[0], 3))
+                                    for x in (0.05, 0.03, 0.02, 0.01)},
                      "err_at": [(round(a, 3), b, round(e, 5)) for a, b, e in tr.history[::10]]}
     res["dig_learned"]["training_seconds"] = round(train_s, 2)
     src = hook.last_src
@@ -663,6 +677,8 @@ def main():
     ap.add_argument("--steady-columns", type=int, default=8,
                     help="steady: centre columns averaged into the centreline profile")
     ap.add_argument("--steady-explicit-arm", action="store_true")
+    ap.add_argument("--steady-graded-arm", action="store_true",
+                    help="steady: also DIG on the wall-refined 100 x 100 grid")
     ap.add_argument("--synth-scheme", choices=["explicit", "lusgs"], default="lusgs")
     ap.add_argument("--dig-max-cycles", type=int, default=400)
     ap.add_argument("--cpu-steps", type=int, default=200)

@@ -75,11 +75,13 @@ class Tracker:
         self.history.append((wall, steps, err))
         return err
 
-    def time_to_steady(self):
-        """(wall, steps) of the first point after which err stays <= threshold."""
+    def time_to_steady(self, threshold: float | None = None):
+        """(wall, steps) of the first point after which err stays <= threshold
+        (the tracker's own by default)."""
+        thr = self.threshold if threshold is None else threshold
         t = None
         for wall, steps, err in self.history:
-            if err <= self.threshold:
+            if err <= thr:
                 if t is None:
                     t = (wall, steps)
             else:
