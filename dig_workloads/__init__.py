@@ -31,8 +31,9 @@ def _bc(kind, T=1.0, U=(0.0, 0.0, 0.0)):
 
 def box(dim, nx, ny=1, lx=1.0, ly=1.0, kn=0.05, zrot=5.0, omega=OMEGA_N2, ppc=50,
         dt_frac=0.2, bc=None, seed=1, instance=0, rho=1.0, u=(0.0, 0.0, 0.0), Tt=1.0,
-        Tr=None, tref=None, dt=None):
-    """A uniform box workload with uniform initial fields."""
+        Tr=None, tref=None, dt=None, dr=2):
+    """A uniform box workload with uniform initial fields.  dr: rotational
+    degrees of freedom (2..6)."""
     if bc is None:
         bc = [_bc("periodic")] * 4
     ny = ny if dim == 2 else 1
@@ -41,7 +42,7 @@ def box(dim, nx, ny=1, lx=1.0, ly=1.0, kn=0.05, zrot=5.0, omega=OMEGA_N2, ppc=50
     if dt is None:
         dt = dt_frac * TAU_C_PER_KN * kn
     temps = [Tt, Tr] + [b[1] for b in bc if b[0] == "diffuse"]
-    return dict(dim=dim, nx=nx, ny=ny, lx=lx, ly=ly, kn=kn, omega=omega, alpha=1.0, dr=2,
+    return dict(dim=dim, nx=nx, ny=ny, lx=lx, ly=ly, kn=kn, omega=omega, alpha=1.0, dr=dr,
                 zrot=zrot, dt=dt, weight=rho * vol / ppc, bc=bc, seed=seed,
                 instance=instance, ppc=ppc,
                 init=dict(rho=rho, u=tuple(u), Tt=Tt, Tr=Tr),

@@ -28,7 +28,7 @@ _SRC = [os.path.join(_DIR, "dsmc_oracle.c")]
 BC = {"periodic": 0, "diffuse": 1, "specular": 2, "freestream": 3}
 GEOM = {"box": 0, "annulus": 1, "graded": 2}
 TAG = {"init": 1, "init_n": 2, "wall": 3, "ncand": 4, "coll": 5, "dig_n": 6,
-       "dig_del": 7, "dig_src": 8, "dig_empty": 9, "inflow": 10}
+       "dig_del": 7, "dig_src": 8, "dig_empty": 9, "inflow": 10, "er": 11, "bl": 12}
 
 
 def build(force: bool = True) -> str:

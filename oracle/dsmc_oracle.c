@@ -120,6 +120,29 @@ static void box_muller(double ua, double ub, double* z0, double* z1) {
   *z1 = r * sin(2.0 * M_PI * ub);
 }
 
+/* Rotational energy of a particle in equilibrium at temperature T with d_r
+ * rotational degrees of freedom: T times a Gamma(d_r/2) variate, the sum of
+ * d_r/2 (rounded down) exponential variates plus, for odd d_r, half the
+ * square of a normal one.  u0: the first uniform (the only one for d_r = 2);
+ * the other words come from one extra draw (entity, step, ORC_TAG_ER, idx):
+ * further exponentials from its words 0 and 1, the normal from words 2, 3. */
+static double rot_energy(const orc_config* c, double T, double u0, uint32_t entity,
+                         uint32_t step, uint32_t idx) {
+  double g = -log(u0);
+  if (c->dr > 2) {
+    uint32_t w[4];
+    orc_draw(c, entity, step, ORC_TAG_ER, idx, w);
+    if (c->dr >= 4) g += -log(orc_u01(w[0]));
+    if (c->dr >= 6) g += -log(orc_u01(w[1]));
+    if (c->dr % 2 == 1) {
+      double z0, z1;
+      box_muller(orc_u01(w[2]), orc_u01(w[3]), &z0, &z1);
+      g += 0.5 * z0 * z0;
+    }
+  }
+  return T * g;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Initialisation (DIG step 1, Section 3): particles drawn from the local
  * equilibrium of fields [rho, ux, uy, uz, Tt, Tr] (each an array of ncell).
@@ -170,7 +193,7 @@ int64_t orc_init(const orc_config* c, const double* fields, int32_t ppc, int64_t
       vx[n] = ux[cell] + st * z0;
       vy[n] = uy[cell] + st * z1;
       vz[n] = uz[cell] + st * z2;
-      er[n] = -tr[cell] * log(orc_u01(b[2]));
+      er[n] = rot_energy(c, tr[cell], orc_u01(b[2]), (uint32_t)n, 0, 0);
       id[n] = (uint32_t)n;
     }
   }
@@ -243,7 +266,7 @@ static int64_t move_annulus(const orc_config* c, int64_t n, double* x, double* y
         vx[p] = vn * nx - vt * ny;
         vy[p] = vn * ny + vt * nx;
         vz[p] = sqrt(T) * z1;
-        er[p] = -T * log(orc_u01(w[3]));
+        er[p] = rot_energy(c, T, orc_u01(w[3]), id[p], step, (uint32_t)hit);
       }
       ++hits_total;
     }
@@ -328,7 +351,7 @@ int64_t orc_move(const orc_config* c, int64_t n, double* x, double* y, double* v
           vx[p] = c->bc_U[face][0] + s * z0;
         }
         vz[p] = c->bc_U[face][2] + s * z1;
-        er[p] = -T * log(orc_u01(w[3]));
+        er[p] = rot_energy(c, T, orc_u01(w[3]), id[p], step, (uint32_t)hit);
       }
       ++hit;
       ++hits_total;
@@ -454,13 +477,41 @@ void orc_sort(int64_t n, const int32_t* cell, int32_t ncell, int64_t* perm, int6
  * cos(chi) = 2 u^(1/alpha) - 1 from the pre-collision relative velocity with a
  * uniform azimuth (Bird's rotation of the relative velocity).  The state
  * arrays are in cell order. */
+/* Fraction x = er' / E_c given to the internal mode of one particle in an
+ * inelastic collision: a Beta(d_r/2, 5/2 - omega) variate (Borgnakke-Larsen
+ * with d_r internal degrees of freedom).  d_r = 2: the inverse distribution
+ * function, 1 - u^(1/(5/2 - omega)) with the word u.  Otherwise
+ * acceptance-rejection with uniform proposals against the density at its
+ * mode x* = (a - 1)/(a + b - 2): attempt t takes the words 2(t mod 2) and
+ * 2(t mod 2) + 1 of draw (cell, step, ORC_TAG_BL, 64 (2k + p) + t/2) as the
+ * proposal x and the test u, accepting when u < (x/x*)^(a-1)
+ * ((1-x)/(1-x*))^(b-1), all in FP64; after 64 rejections (probability below
+ * 1e-30) x* itself.  k: candidate, p: 0 first particle, 1 second.  The
+ * decisions enter the margin. */
+static double bl_fraction(const orc_config* c, uint32_t u, uint32_t cell, uint32_t step,
+                          int64_t k, int p, double* margin) {
+  double b = 2.5 - c->omega;
+  if (c->dr == 2) return 1.0 - pow(orc_u01(u), 1.0 / b);
+  double a = 0.5 * c->dr;
+  double xm = (a - 1.0) / (a + b - 2.0);
+  for (uint32_t t = 0; t < 64; ++t) {
+    uint32_t w[4];
+    orc_draw(c, cell, step, ORC_TAG_BL, (uint32_t)(64 * (2 * k + p)) + t / 2, w);
+    double x = orc_u01(w[2 * (t % 2)]);
+    double ut = orc_u01(w[2 * (t % 2) + 1]);
+    double ratio = pow(x / xm, a - 1.0) * pow((1.0 - x) / (1.0 - xm), b - 1.0);
+    if (margin && fabs(ut - ratio) < *margin) *margin = fabs(ut - ratio);
+    if (ut < ratio) return x;
+  }
+  return xm;
+}
+
 void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, double* vx,
                  double* vy, double* vz, double* er, float* sgmax, uint32_t step,
                  orc_collide_stats* st, double* obs_out, double* margin_out) {
   double csig = orc_csigma(c);
   double pin = orc_pinelastic(c);
   double expo = 1.0 - c->omega;            /* sigma g = C (g^2)^(1 - omega) */
-  double beta_inv = 1.0 / (2.5 - c->omega); /* Beta(1, 5/2 - omega) inverse CDF */
   for (int32_t cell = 0; cell < ncell; ++cell) {
     int64_t b = start[cell];
     int64_t N = start[cell + 1] - b;
@@ -496,19 +547,20 @@ void orc_collide(const orc_config* c, int32_t ncell, const int64_t* start, doubl
       orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 1), r1);
       orc_draw(c, (uint32_t)cell, step, ORC_TAG_COLL, (uint32_t)(3 * k + 2), r2);
       double et = 0.25 * g2; /* relative translational energy, reduced mass 1/2 */
-      if (fabs(orc_u01(r0[3]) - pin) < margin) margin = fabs(orc_u01(r0[3]) - pin);
-      if (fabs(orc_u01(r1[1]) - pin) < margin) margin = fabs(orc_u01(r1[1]) - pin);
+      double pk = pin;
+      if (fabs(orc_u01(r0[3]) - pk) < margin) margin = fabs(orc_u01(r0[3]) - pk);
+      if (fabs(orc_u01(r1[1]) - pk) < margin) margin = fabs(orc_u01(r1[1]) - pk);
       /* first picked particle, then the second: Bird's double relaxation */
-      if (orc_u01(r0[3]) < pin) {
+      if (orc_u01(r0[3]) < pk) {
         double ec = et + er[i];
-        double frac = 1.0 - pow(orc_u01(r1[0]), beta_inv);
+        double frac = bl_fraction(c, r1[0], (uint32_t)cell, step, k, 0, &margin);
         er[i] = frac * ec;
         et = ec - er[i];
         if (st) st->inelastic += 1;
       }
-      if (orc_u01(r1[1]) < pin) {
+      if (orc_u01(r1[1]) < pk) {
         double ec = et + er[j];
-        double frac = 1.0 - pow(orc_u01(r1[2]), beta_inv);
+        double frac = bl_fraction(c, r1[2], (uint32_t)cell, step, k, 1, &margin);
         er[j] = frac * ec;
         et = ec - er[j];
         if (st) st->inelastic += 1;
@@ -777,7 +829,8 @@ int orc_adjust(const orc_config* c, int32_t ncell, const int64_t* start, const d
         ovx[pos] = tux[cell] + st * z0;
         ovy[pos] = tuy[cell] + st * z1;
         ovz[pos] = tuz[cell] + st * z2;
-        oer[pos] = -ttr[cell] * log(orc_u01(bb[2]));
+        oer[pos] = rot_energy(c, ttr[cell], orc_u01(bb[2]), (uint32_t)(next_id + created), dig_iter,
+                              0);
         oid[pos] = (uint32_t)(next_id + created);
         ++created;
         ++pos;
@@ -982,7 +1035,7 @@ int64_t orc_inject(const orc_config* c, int64_t n, int64_t cap, double* x, doubl
       vx[p] = U[0] + sT * z0;
       vy[p] = U[1] + sT * z1;
       vz[p] = U[2] + sT * z2;
-      er[p] = -T * log(orc_u01(b[2]));
+      er[p] = rot_energy(c, T, orc_u01(b[2]), (uint32_t)(next_id + (uint64_t)q), step, 0);
       id[p] = (uint32_t)(next_id + (uint64_t)q);
     }
   }

@@ -31,7 +31,9 @@ enum { ORC_GEOM_BOX = 0, ORC_GEOM_ANNULUS = 1, ORC_GEOM_GRADED = 2 };
 enum {
   ORC_TAG_INIT = 1, ORC_TAG_INIT_N = 2, ORC_TAG_WALL = 3, ORC_TAG_NCAND = 4,
   ORC_TAG_COLL = 5, ORC_TAG_DIG_N = 6, ORC_TAG_DIG_DEL = 7, ORC_TAG_DIG_SRC = 8,
-  ORC_TAG_DIG_EMPTY = 9, ORC_TAG_INFLOW = 10
+  ORC_TAG_DIG_EMPTY = 9, ORC_TAG_INFLOW = 10,
+  ORC_TAG_ER = 11, /* extra words of a rotational energy with d_r > 2 */
+  ORC_TAG_BL = 12  /* Borgnakke-Larsen fraction by rejection for d_r > 2 */
 };
 
 typedef struct {
@@ -41,7 +43,7 @@ typedef struct {
   int32_t  geometry;     /* ORC_GEOM_*; annulus: nx angular x ny radial cells */
   double   r_in, r_out, q; /* annulus radii, radial stretch ratio */
   double   kn, omega, alpha;
-  int32_t  dr;           /* rotational degrees of freedom (2) */
+  int32_t  dr;           /* rotational degrees of freedom, 2..6 */
   double   zrot;         /* rotational collision number Z */
   double   dt, weight;   /* time step; particle weight N_eff (mass per particle) */
   int32_t  bc_type[4];   /* faces x-, x+, y-, y+ */
