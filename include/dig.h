@@ -78,7 +78,8 @@ typedef struct {
 enum { DIG_GEOM_BOX = 0, DIG_GEOM_ANNULUS = 1, DIG_GEOM_GRADED = 2 };
 
 /* One simulation instance (Section 4 gas: VSS/VHS omega 0.74, alpha 1,
- * d_r = 2, constant Z).  Faces are ordered x-, x+, y-, y+. */
+ * d_r = 2, constant Z; d_r up to 6 and alpha up to 2 are accepted).  Faces are
+ * ordered x-, x+, y-, y+. */
 typedef struct {
   int32_t dim;          /* 1 (slab, positions x) or 2 (positions x, y) */
   int32_t nx, ny;       /* cells per axis; ny = 1 when dim = 1 */
@@ -88,7 +89,8 @@ typedef struct {
   double kn;            /* Knudsen number (Section 2) */
   double omega, alpha;  /* viscosity index in [0.5, 1]; scattering alpha in [1, 2]
                           (1: VHS, isotropic; otherwise VSS) */
-  int32_t dr;           /* rotational degrees of freedom; must be 2 */
+  int32_t dr;           /* rotational degrees of freedom, 2..6 (Borgnakke-Larsen with
+                          Beta(d_r/2, 5/2 - omega) fractions, Gamma(d_r/2) energies) */
   double zrot;          /* rotational collision number Z; P_inelastic <= 1 */
   double dt, weight;    /* time step; particle weight N_eff (mass per particle) */
   dig_bc bc[4];

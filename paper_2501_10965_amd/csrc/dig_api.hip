@@ -188,7 +188,7 @@ dig_status validate(const dig_config* cfgs, int32_t n_inst, int64_t capacity, in
       return fail(DIG_ERR_INVALID, at + "omega must lie in [0.5, 1]");
     if (!(c.alpha >= 1.0 && c.alpha <= 2.0))
       return fail(DIG_ERR_INVALID, at + "alpha must lie in [1, 2] (1: VHS, else VSS)");
-    if (c.dr != 2) return fail(DIG_ERR_INVALID, at + "d_r must be 2");
+    if (c.dr < 2 || c.dr > 6) return fail(DIG_ERR_INVALID, at + "d_r must lie in [2, 6]");
     if (!(c.zrot > 0.0) || p_inelastic(c) > 1.0)
       return fail(DIG_ERR_INVALID, at + "Z must give P_inelastic <= 1");
     if (!(c.dt > 0.0) || !(c.weight > 0.0))
@@ -433,8 +433,8 @@ StepArgs args(const dig_ctx* c) {
   a.big_list = (int32_t*)(w + c->I.big_list);
   a.big_count = (uint32_t*)(w + c->I.big_count);
   a.lds_big = c->Lbig;
-  a.vss_any = 0;
-  for (const InstParam& q : c->params) a.vss_any |= q.vss ? 1 : 0;
+  a.ext_any = 0;
+  for (const InstParam& q : c->params) a.ext_any |= (q.vss || q.dr != 2) ? 1 : 0;
   a.big_runs = big_run_slots(c->Lbig, c->Gc);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);

@@ -55,7 +55,7 @@ struct InstParam {
   uint32_t vss;
   double ainv;
 };
-enum : uint32_t { TAG_INFLOW = 10 };
+enum : uint32_t { TAG_INFLOW = 10, TAG_ER = 11, TAG_BL = 12 };
 
 struct DevState {
   float *x, *y, *vx, *vy, *vz, *er;
@@ -125,7 +125,7 @@ struct StepArgs {
   int32_t big_runs;     // its run-table capacity
   int32_t* big_list;    // groups too large for the collide's stage, listed by it
   uint32_t* big_count;  // entries in big_list (emptied by k_collide_big)
-  int32_t vss_any;      // some instance scatters with VSS (alpha != 1)
+  int32_t ext_any;      // some instance needs the extended model (alpha != 1 or d_r != 2)
 };
 enum { ST_REMOVED = 5, ST_INJECTED = 6 };
 

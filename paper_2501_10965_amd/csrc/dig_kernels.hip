@@ -113,6 +113,26 @@ static __device__ __forceinline__ float graded_point(const double* f64, const fl
   return v < hi ? v : __uint_as_float(__float_as_uint(hi) - 1u);
 }
 
+// Rotational energy in equilibrium at temperature T is T times a
+// Gamma(d_r/2) variate: the exponential -log u0 of the word already drawn,
+// and for d_r > 2 the rest from one extra draw (entity, step, TAG_ER, idx):
+// further exponentials from its words 0 (d_r >= 4) and 1 (d_r = 6), half the
+// square of a normal from words 2 and 3 (odd d_r).  This returns that rest
+// (0 for d_r = 2), in FP64.
+static __device__ double rot_extra(const InstParam& I, double T, uint32_t entity, uint32_t step,
+                                   uint32_t idx) {
+  if (I.dr <= 2) return 0.0;
+  const uint4 w = draw(I, entity, step, TAG_ER, idx);
+  double g = 0.0;
+  if (I.dr >= 4) g += -log(u01d(w.x));
+  if (I.dr >= 6) g += -log(u01d(w.y));
+  if (I.dr & 1) {
+    const double z = sqrt(-2.0 * log(u01d(w.z))) * cos(2.0 * M_PI * u01d(w.w));
+    g += 0.5 * z * z;
+  }
+  return T * g;
+}
+
 // ---------------------------------------------------------------------------
 // Annulus cell map.  The radial index is the largest j with rf2[j] <= r^2
 // (clamped to the ring) for the FP32 squared radius and the FP32 table of
@@ -223,6 +243,7 @@ static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_
     } else {
       const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
       circle_diffuse(P, face, w, nx, ny, &vx, &vy, &vz, &er);
+      if (P.dr > 2) er += (float)rot_extra(P, P.bc_T[face], a.A.id[p], step, (uint32_t)hit);
       er_set = true;
     }
     vset = true;
@@ -329,6 +350,7 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
       }
       vz = P.bc_U[face][2] + sT * (r * sn);
       er = -T * flog(u01f(w.w));
+      if (P.dr > 2) er += (float)rot_extra(P, T, a.A.id[p], step, (uint32_t)hit);
       er_set = true;
     }
     ++hit;
@@ -718,27 +740,59 @@ static __device__ __forceinline__ bool vhs_accept(const InstParam& I, float sgm,
 // deflection cos chi = 2 u^(1/alpha) - 1 (u from r1.w) about the
 // pre-collision relative velocity with azimuth from w8 (Bird's rotation
 // formulas, from the coordinate axis least aligned with that velocity).
-template <bool VSS>
+// Borgnakke-Larsen fraction for d_r > 2: a Beta(d_r/2, 5/2 - omega) variate
+// by acceptance-rejection in FP64 with uniform proposals against the density
+// at its mode x* = (a - 1)/(a + b - 2); attempt t takes the words 2(t mod 2)
+// and 2(t mod 2) + 1 of draw (cell, step, TAG_BL, 64 (2k + p) + t/2) as the
+// proposal and the test; after 64 rejections (probability below 1e-30) x*.
+// k: candidate of the cell, p: 0 first particle, 1 second.
+static __device__ double bl_fraction(const InstParam& I, uint32_t ent, uint32_t step, uint32_t k,
+                                     uint32_t p) {
+  const double a = 0.5 * I.dr, b = 2.5 - I.omega;
+  const double xm = (a - 1.0) / (a + b - 2.0);
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t t = 0; t < 64; ++t) {
+    if ((t & 1u) == 0) w = draw(I, ent, step, TAG_BL, 64u * (2u * k + p) + t / 2u);
+    const double x = u01d((t & 1u) ? w.z : w.x);
+    const double ut = u01d((t & 1u) ? w.w : w.y);
+    const double ratio = pow(x / xm, a - 1.0) * pow((1.0 - x) / (1.0 - xm), b - 1.0);
+    if (ut < ratio) return x;
+  }
+  return xm;
+}
+
+template <bool EXT>
 static __device__ __forceinline__ void apply_collision(const InstParam& I, float g2, uint32_t w3,
                                                        uint4 r1, uint32_t w8, float4& va,
-                                                       float4& vb, int* inel) {
+                                                       float4& vb, int* inel, uint32_t ent,
+                                                       uint32_t step, uint32_t kk) {
   float et = 0.25f * g2;  // relative translational energy, reduced mass 1/2
   if (u01d(w3) < I.pin) {
     const float ec = et + va.w;
-    va.w = (1.0f - fpow(u01f(r1.x), I.beta_inv)) * ec;
+    float x = 0.0f;
+    if constexpr (EXT) {
+      if (I.dr != 2) x = (float)bl_fraction(I, ent, step, kk, 0u);
+    }
+    if (!EXT || I.dr == 2) x = 1.0f - fpow(u01f(r1.x), I.beta_inv);
+    va.w = x * ec;
     et = ec - va.w;
     ++*inel;
   }
   if (u01d(r1.y) < I.pin) {
     const float ec = et + vb.w;
-    vb.w = (1.0f - fpow(u01f(r1.z), I.beta_inv)) * ec;
+    float x = 0.0f;
+    if constexpr (EXT) {
+      if (I.dr != 2) x = (float)bl_fraction(I, ent, step, kk, 1u);
+    }
+    if (!EXT || I.dr == 2) x = 1.0f - fpow(u01f(r1.z), I.beta_inv);
+    vb.w = x * ec;
     et = ec - vb.w;
     ++*inel;
   }
   const float hg = fsqrt(et);  // half of |g'| = 2 sqrt(et)
   float nx, ny, nz;
-  bool iso = true;  // the VHS kernels carry no VSS code
-  if constexpr (VSS) iso = !I.vss;
+  bool iso = true;  // the basic kernels carry no VSS code
+  if constexpr (EXT) iso = !I.vss;
   if (iso) {
     // ct = 2u - 1 is exact; sin theta from (1 - ct)(1 + ct), both factors
     // exact, keeps its relative accuracy near ct = +-1
@@ -802,7 +856,7 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // thread count); cw: room for rchunk uint4 + rchunk words (5 rchunk uint32)
 // in which they keep the words an accepted collision uses, drawn with the
 // pair; null: an accepted candidate draws them in its round.
-template <bool VSS, class Store>
+template <bool EXT, class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, uint32_t omask, int nc, int c_lo,
                                      uint32_t step, int iu, double my_vol, bool vol_mine,
@@ -900,7 +954,8 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
         ++l_cand;
         l_sat += sg > sgm;
         if (acc) {
-          apply_collision<VSS>(I, g2, w0.z, w[1], w0.w, va, vb, &l_inel);
+          apply_collision<EXT>(I, g2, w0.z, w[1], w0.w, va, vb, &l_inel,
+                               (uint32_t)(c_lo + c - I.cell0), step, (uint32_t)(k - S.soff[c]));
           ++l_acc;
           P.st(i, va);
           P.st(j, vb);
@@ -986,7 +1041,9 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
               r1 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
               w8 = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
             }
-            apply_collision<VSS>(I, g2, w3, r1, w8, va, vb, &l_inel);
+            apply_collision<EXT>(I, g2, w3, r1, w8, va, vb, &l_inel,
+                                 (uint32_t)(c_lo + cc - I.cell0), step,
+                                 (uint32_t)(kb + q - S.coff[cc]));
             ++l_acc;
             P.st(ci, va);
             P.st(cj, vb);
@@ -1206,7 +1263,7 @@ enum { kModeStaged = 0, kModeSmall = 1, kModeBig = 2 };
 
 // two_pass: the cells' moment sums in two passes (fewer live registers, for
 // the 80-VGPR budget of six waves per SIMD) rather than one.
-template <int mode, bool VSS, bool two_pass = false>
+template <int mode, bool EXT, bool two_pass = false>
 static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, int L,
                                                      int run_slots, int do_collide,
                                                      int do_sample) {
@@ -1387,10 +1444,10 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.obs += c0;
       Sg.inst += c0;
       if (fast)
-        collide_cells<VSS>(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
+        collide_cells<EXT>(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
                       c0 == 0, cw, rchunk);
       else
-        collide_cells<VSS>(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu,
+        collide_cells<EXT>(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu,
                            my_vol,
                       c0 == 0, cw, rchunk);
       c0 = c1;
@@ -1477,13 +1534,14 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
 // this kernel.
 // MINW: waves per SIMD the register budget must allow.  6 (80 VGPRs) is
 // launched where the LDS stage leaves room for 6 workgroups per CU, 1 (no
-// constraint) otherwise.  VSS: compiled with VSS scattering (instances with
-// alpha = 1 still scatter isotropically); launched only where an instance
-// uses it.
-template <int MINW, int mode, bool VSS>
+// constraint) otherwise.  EXT: compiled with the extended collision model,
+// VSS scattering and Borgnakke-Larsen fractions for d_r != 2 (instances with
+// alpha = 1 and d_r = 2 still take the basic formulas); launched only where
+// an instance needs it, so the basic kernels keep their register budget.
+template <int MINW, int mode, bool EXT>
 __global__ __launch_bounds__(kCollideThreads) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_collide(StepArgs a, int do_collide, int do_sample, int end_step) {
-  collide_group<mode, VSS, MINW == 6>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles,
+  collide_group<mode, EXT, MINW == 6>(a, xcd_group(blockIdx.x, gridDim.x), a.lds_particles,
                                       kRunSlots, do_collide, do_sample);
   if (!end_step || threadIdx.x != 0) return;
   const uint32_t prev = atomicAdd(a.done, 1u);
@@ -1508,7 +1566,7 @@ constexpr int kBigGrid = 1024;
 static_assert(kRoundChunkMax == kCollideThreads && kRoundChunkMax == kBigThreads &&
                   kCandChunk <= kRoundChunkMax,
               "a collision round keeps one candidate per thread");
-template <bool VSS>
+template <bool EXT>
 __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_collide,
                                                              int do_sample, int end_step) {
   const int nbig = __builtin_amdgcn_readfirstlane((int)*a.big_count);
@@ -1522,7 +1580,7 @@ __global__ __launch_bounds__(kBigThreads) void k_collide_big(StepArgs a, int do_
   }
   for (int i = blockIdx.x; i < nbig; i += gridDim.x) {
     const int g = __builtin_amdgcn_readfirstlane(a.big_list[i]);
-    collide_group<kModeBig, VSS>(a, g, a.lds_big, a.big_runs, do_collide, do_sample);
+    collide_group<kModeBig, EXT>(a, g, a.lds_big, a.big_runs, do_collide, do_sample);
     __syncthreads();  // the next group reuses the shared memory
   }
   __syncthreads();
@@ -1622,7 +1680,8 @@ __global__ __launch_bounds__(256) void k_inject_fill(StepArgs a) {
     a.A.vx[p] = I.bc_U[1][0] + sT * (g1 * c0);
     a.A.vy[p] = I.bc_U[1][1] + sT * (g1 * s0);
     a.A.vz[p] = I.bc_U[1][2] + sT * (g2 * c1);
-    a.A.er[p] = -T * logf(u01f(w1.z));
+    a.A.er[p] = -T * logf(u01f(w1.z)) +
+                (float)rot_extra(I, T, (uint32_t)(a.ctr->next_id + q), step, 0);
     a.A.id[p] = (uint32_t)(a.ctr->next_id + q);
   }
 }
@@ -1709,7 +1768,8 @@ __global__ void k_init_fill(StepArgs a, const double* fields) {
   a.A.vx[p] = (float)fields[1 * C + c] + st * (ra * c0);
   a.A.vy[p] = (float)fields[2 * C + c] + st * (ra * s0);
   a.A.vz[p] = (float)fields[3 * C + c] + st * (rb * c1);
-  a.A.er[p] = -(float)fields[5 * C + c] * logf(u01f(r1.z));
+  a.A.er[p] = -(float)fields[5 * C + c] * logf(u01f(r1.z)) +
+              (float)rot_extra(I, fields[5 * C + c], id, 0, 0);
   a.A.id[p] = id;
 }
 
@@ -1980,8 +2040,8 @@ __global__ __launch_bounds__(256) void k_adjust_build(StepArgs a, const double* 
         s.vx = (float)(tux + st * (ra * cos(p0)));
         s.vy = (float)(tuy + st * (ra * sin(p0)));
         s.vz = (float)(tuz + st * (rb * cos(p1)));
-        s.er = (float)(-ttr * log(u01d(r1.z)));
         s.id = (uint32_t)(next_id + cstart[c] + k);
+        s.er = (float)(-ttr * log(u01d(r1.z)) + rot_extra(I, ttr, s.id, iter, 0));
       }
       return s;
     };
@@ -2337,7 +2397,7 @@ hipError_t launch_order(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool VSS>
+template <bool EXT>
 static hipError_t launch_collide_t(const StepArgs& a, bool collide, bool sample, bool end_step,
                                    bool fused, hipStream_t s) {
   const size_t lds = collide_lds_bytes(a.lds_particles, a.group_cells);
@@ -2351,18 +2411,18 @@ static hipError_t launch_collide_t(const StepArgs& a, bool collide, bool sample,
   const bool six = 6 * (lds + 1024) <= 160 * 1024;
   if (fused) {
     if (six)
-      hipLaunchKernelGGL((k_collide<6, kModeSmall, VSS>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<6, kModeSmall, EXT>), grid, block, lds, s, a, f0, f1, f2);
     else
-      hipLaunchKernelGGL((k_collide<1, kModeSmall, VSS>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<1, kModeSmall, EXT>), grid, block, lds, s, a, f0, f1, f2);
   } else {
     if (six)
-      hipLaunchKernelGGL((k_collide<6, kModeStaged, VSS>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<6, kModeStaged, EXT>), grid, block, lds, s, a, f0, f1, f2);
     else
-      hipLaunchKernelGGL((k_collide<1, kModeStaged, VSS>), grid, block, lds, s, a, f0, f1, f2);
+      hipLaunchKernelGGL((k_collide<1, kModeStaged, EXT>), grid, block, lds, s, a, f0, f1, f2);
   }
   if (fused) {
     if (!big_stage_fits(a.lds_big, a.group_cells, kBigLdsMax)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_collide_big<VSS>, dim3(kBigGrid), dim3(kBigThreads),
+    hipLaunchKernelGGL(k_collide_big<EXT>, dim3(kBigGrid), dim3(kBigThreads),
                        collide_lds_bytes(a.lds_big, a.group_cells), s, a, f0, f1,
                        end_step ? 1 : 0);
   }
@@ -2371,7 +2431,7 @@ static hipError_t launch_collide_t(const StepArgs& a, bool collide, bool sample,
 
 hipError_t launch_collide(const StepArgs& a, bool collide, bool sample, bool end_step,
                           bool fused, hipStream_t s) {
-  return a.vss_any ? launch_collide_t<true>(a, collide, sample, end_step, fused, s)
+  return a.ext_any ? launch_collide_t<true>(a, collide, sample, end_step, fused, s)
                    : launch_collide_t<false>(a, collide, sample, end_step, fused, s);
 }
 

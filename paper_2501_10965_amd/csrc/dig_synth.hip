@@ -700,7 +700,7 @@ static dig_status check_synth_args(const char* fn, const dig_config* cfg,
     return bad("bad domain size");
   if (!(cfg->kn > 0.0) || !std::isfinite(cfg->kn)) return bad("Kn must be finite and > 0");
   if (!(cfg->omega >= 0.5 && cfg->omega <= 1.0)) return bad("omega must lie in [0.5, 1]");
-  if (cfg->dr != 2) return bad("d_r must be 2");
+  if (cfg->dr < 2 || cfg->dr > 6) return bad("d_r must lie in [2, 6]");
   if (!(cfg->zrot > 0.0) || !std::isfinite(cfg->zrot)) return bad("Z must be finite and > 0");
   for (int ax = 0; ax < cfg->dim; ++ax) {
     for (int side = 0; side < 2; ++side) {

@@ -99,7 +99,8 @@ int main() {
       {"kn negative", [](dig_config* c) { c->kn = -1.0; }},
       {"omega above 1", [](dig_config* c) { c->omega = 1.2; }},
       {"alpha above 2", [](dig_config* c) { c->alpha = 2.5; }},
-      {"d_r 3", [](dig_config* c) { c->dr = 3; }},
+      {"d_r 7", [](dig_config* c) { c->dr = 7; }},
+      {"d_r 1", [](dig_config* c) { c->dr = 1; }},
       {"Z below P_inelastic = 1", [](dig_config* c) { c->zrot = 0.1; }},
       {"dt zero", [](dig_config* c) { c->dt = 0.0; }},
       {"dt infinite", [](dig_config* c) { c->dt = INFINITY; }},

@@ -28,10 +28,13 @@ def _close(a, b, rel):
     return rel_close(a, b, rel)
 
 
-@pytest.mark.parametrize("mach,outer", [(3.0, "freestream"), (0.0, "diffuse"),
-                                        (1.0, "specular")])
-def test_annulus_stage_parity(mach, outer):
+@pytest.mark.parametrize("mach,outer,dr", [(3.0, "freestream", 2), (0.0, "diffuse", 2),
+                                           (1.0, "specular", 2), (3.0, "freestream", 3)])
+def test_annulus_stage_parity(mach, outer, dr):
+    """d_r = 3: inflow, wall re-emission and collisions with Gamma(3/2)
+    rotational energies and Beta(3/2, 5/2 - omega) exchange fractions."""
     w = small(mach=mach, outer=outer)
+    w["dr"] = dr
     w["dt"] *= 3.0  # more wall events per step
     U = mach * math.sqrt(1.4)
     st = wl.random_annulus_state(w, 5, drift=(0.5 * U, 0.0, 0.0))
@@ -39,7 +42,7 @@ def test_annulus_stage_parity(mach, outer):
     n = len(st["x"])
     nc = w["nx"] * w["ny"]
     sg = np.full(nc, oracle.sgmax_default(w), np.float32)
-    say(f"case annulus {outer} mach {mach}: n={n}")
+    say(f"case annulus {outer} mach {mach} d_r {dr}: n={n}")
     sim = DSMC(w, capacity=2 * n + 100000)
     sim.inject(st, start, step=7, next_id=n + 3, sgmax=sg)
     c0 = sim.counters()
