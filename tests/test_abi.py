@@ -49,7 +49,7 @@ def test_plan_layout_is_aligned_and_disjoint():
 
 @pytest.mark.parametrize("field,value", [("dim", 3), ("omega", 1.2), ("alpha", 2.5),
                                          ("alpha", 0.9),
-                                         ("dr", 3), ("kn", 0.0), ("dt", -1.0),
+                                         ("dr", 7), ("dr", 1), ("kn", 0.0), ("dt", -1.0),
                                          ("zrot", 0.1), ("nx", 0)])
 def test_invalid_configs_rejected(field, value):
     w = wl.fourier_1d()
