@@ -434,7 +434,11 @@ StepArgs args(const dig_ctx* c) {
   a.big_count = (uint32_t*)(w + c->I.big_count);
   a.lds_big = c->Lbig;
   a.ext_any = 0;
-  for (const InstParam& q : c->params) a.ext_any |= (q.vss || q.dr != 2) ? 1 : 0;
+  a.dr_any = 0;
+  for (const InstParam& q : c->params) {
+    a.ext_any |= (q.vss || q.dr != 2) ? 1 : 0;
+    a.dr_any |= q.dr != 2 ? 1 : 0;
+  }
   a.big_runs = big_run_slots(c->Lbig, c->Gc);
   a.params = (const InstParam*)(w + c->I.params);
   a.ctr = (dig_counters*)(w + L.counters);

@@ -126,6 +126,7 @@ struct StepArgs {
   int32_t* big_list;    // groups too large for the collide's stage, listed by it
   uint32_t* big_count;  // entries in big_list (emptied by k_collide_big)
   int32_t ext_any;      // some instance needs the extended model (alpha != 1 or d_r != 2)
+  int32_t dr_any;       // some instance has d_r != 2
 };
 enum { ST_REMOVED = 5, ST_INJECTED = 6 };
 

@@ -193,6 +193,7 @@ static __device__ __forceinline__ void circle_diffuse(const InstParam& P, int fa
 // Free flight in the annulus: reflection at the inner circle (and at the outer
 // circle when it is a wall); with a freestream outer boundary a particle that
 // ends outside it has left (returns -1).  Wall events in time order.
+template <bool EXT>
 static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_t p,
                                    uint32_t step, int* hits) {
   float x = a.A.x[p], y = a.A.y[p];
@@ -243,7 +244,9 @@ static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_
     } else {
       const uint4 w = draw(P, a.A.id[p], step, TAG_WALL, (uint32_t)hit);
       circle_diffuse(P, face, w, nx, ny, &vx, &vy, &vz, &er);
-      if (P.dr > 2) er += (float)rot_extra(P, P.bc_T[face], a.A.id[p], step, (uint32_t)hit);
+      if constexpr (EXT) {
+        if (P.dr > 2) er += (float)rot_extra(P, P.bc_T[face], a.A.id[p], step, (uint32_t)hit);
+      }
       er_set = true;
     }
     vset = true;
@@ -272,9 +275,10 @@ static __device__ int move_annulus(const StepArgs& a, const InstParam& P, int64_
 
 // ---------------------------------------------------------------------------
 // Free flight with diffuse / specular walls for one particle; returns its cell.
+template <bool EXT>
 static __device__ __forceinline__ int move_particle(const StepArgs& a, const InstParam& P,
                                                     int64_t p, uint32_t step, int* hits) {
-  if (P.geom == DIG_GEOM_ANNULUS) return move_annulus(a, P, p, step, hits);
+  if (P.geom == DIG_GEOM_ANNULUS) return move_annulus<EXT>(a, P, p, step, hits);
   const bool two = P.dim == 2;
   float x = a.A.x[p];
   float y = two ? a.A.y[p] : 0.0f;
@@ -350,7 +354,9 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
       }
       vz = P.bc_U[face][2] + sT * (r * sn);
       er = -T * flog(u01f(w.w));
-      if (P.dr > 2) er += (float)rot_extra(P, T, a.A.id[p], step, (uint32_t)hit);
+      if constexpr (EXT) {
+        if (P.dr > 2) er += (float)rot_extra(P, T, a.A.id[p], step, (uint32_t)hit);
+      }
       er_set = true;
     }
     ++hit;
@@ -385,7 +391,10 @@ static __device__ __forceinline__ int move_particle(const StepArgs& a, const Ins
 }
 
 // Free flight, cell index and reservation of a slot in the destination cell.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_move(StepArgs a) {
+// EXT: compiled with the Gamma(d_r/2) wall re-emission of d_r > 2, launched
+// only where an instance has d_r != 2 (keeps the basic kernel within 64 VGPRs).
+template <bool EXT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(EXT ? 4 : 8))) void k_move(StepArgs a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = a.ctr->n;
   const uint32_t step = (uint32_t)a.ctr->step;
@@ -395,9 +404,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const int inst = valid ? find_inst(a.inst_pstart, a.n_inst, p) : 0;
   const int iu = __builtin_amdgcn_readfirstlane(inst);
   if (__all(!valid || inst == iu)) {
-    if (valid) cell = move_particle(a, a.params[iu], p, step, &hits_here);
+    if (valid) cell = move_particle<EXT>(a, a.params[iu], p, step, &hits_here);
   } else if (valid) {
-    cell = move_particle(a, a.params[inst], p, step, &hits_here);
+    cell = move_particle<EXT>(a, a.params[inst], p, step, &hits_here);
   }
   // a particle that left through an open boundary reserves nothing
   const bool gone = valid && cell < 0;
@@ -852,11 +861,15 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
 // by all lanes together.  Larger cells run in parallel rounds.  Both give the
 // order of the sequential algorithm exactly.
 //
+// WINDOW (the oversize-group kernel, whose groups hold many candidates): the
+// large cells' candidates run in a window that refills as candidates
+// complete; otherwise in fixed chunks of rounds (fewer per-round costs where
+// a group holds about one chunk).
 // rchunk: candidates of the large cells per chunk of rounds (at most the
 // thread count); cw: room for rchunk uint4 + rchunk words (5 rchunk uint32)
 // in which they keep the words an accepted collision uses, drawn with the
 // pair; null: an accepted candidate draws them in its round.
-template <bool EXT, class Store>
+template <bool EXT, bool WINDOW, class Store>
 static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, Store P,
                                      uint32_t* owner, uint32_t omask, int nc, int c_lo,
                                      uint32_t step, int iu, double my_vol, bool vol_mine,
@@ -967,6 +980,105 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
 #pragma unroll
   for (int u = 0; u < 4; ++u)
     if (sb + u < se) atomicMax(&S.obs[sb + u], __float_as_uint(obs[u]));
+  if constexpr (WINDOW) {
+  // ---- large cells: a window of pending candidates, one per thread,
+  // executed in rounds; a candidate runs once it is the earliest pending
+  // candidate of both its particles, which reproduces the sequential order.
+  // Whenever a thread's candidate has run, the thread takes the next
+  // candidate in order (an LDS counter), so every round keeps the window
+  // full instead of draining a fixed chunk.  Candidates are numbered within
+  // epochs of 65536; ownership keys carry the round, (0xFFFF - r) << 16 |
+  // (k - epoch base), so a key of round r is below every key of earlier
+  // rounds and stale words need no reset within an epoch (every round runs at
+  // least one candidate, so an epoch has fewer than 65536 rounds).  Particle e
+  // owns word e & omask: a shared word only delays the later candidate by a
+  // round (the earliest pending one always holds both of its words), so a
+  // table smaller than the group is safe.  Which thread takes which candidate
+  // does not matter: the set of candidates pending in each round is fixed by
+  // the sequential order alone ---------------------------------------------
+  // cw (room for rchunk uint4 + rchunk words, when the dead source arrays
+  // hold a slot per thread): the words an accepted candidate needs, drawn
+  // with its pair, so that no round waits on Philox
+  if (rchunk < (int)blockDim.x) cw = nullptr;
+  const int K = KG;
+  const int q = threadIdx.x;
+  int* s_next = S.wsum + 15;  // free after the candidate-count scans
+  const uint32_t nown = omask == 0xFFFFFFFFu ? (uint32_t)S.start[nc] : omask + 1u;
+  for (int eb = 0; eb < K; eb += 65536) {
+    const int ee = min(K, eb + 65536);
+    for (uint32_t e = threadIdx.x; e < nown; e += blockDim.x) owner[e] = 0xFFFFFFFFu;
+    if (threadIdx.x == 0) *s_next = eb + (int)blockDim.x;
+    int k = eb + q < ee ? eb + q : -1;
+    int ci = 0, cj = 0, cc = 0;
+    uint32_t w2 = 0, w3 = 0;
+    // pair and acceptance words of candidate k (cell cc, particles ci, cj)
+    auto take = [&](int kn) {
+      cc = floor_index(S.coff, nc + 1, kn);
+      const int kk = kn - S.coff[cc];
+      const int N = S.start[cc + 1] - S.start[cc];
+      const InstParam& I = a.params[iu];
+      const uint4 r = draw(I, (uint32_t)(c_lo + cc - I.cell0), step, TAG_COLL, 3u * (uint32_t)kk);
+      const int i = (int)pick(r.x, (uint32_t)N);
+      int j = (int)pick(r.y, (uint32_t)(N - 1));
+      j += (j >= i);
+      ci = S.start[cc] + i;
+      cj = S.start[cc] + j;
+      w2 = r.z;
+      w3 = r.w;
+      if (cw) {
+        const uint32_t ent = (uint32_t)(c_lo + cc - I.cell0);
+        cw[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 1u);
+        cphi[q] = draw(I, ent, step, TAG_COLL, 3u * (uint32_t)kk + 2u).x;
+      }
+    };
+    if (k >= 0) take(k);
+    __syncthreads();
+    for (uint32_t r = 0;; ++r) {
+      const uint32_t key = ((0xFFFFu - r) << 16) | (uint32_t)(k - eb);
+      const uint32_t oi = (uint32_t)ci & omask, oj = (uint32_t)cj & omask;
+      if (k >= 0) {
+        atomicMin(&owner[oi], key);
+        atomicMin(&owner[oj], key);
+      }
+      __syncthreads();
+      const bool run = k >= 0 && owner[oi] == key && owner[oj] == key;
+      if (run) {
+        const InstParam& I = a.params[iu];
+        float4 va = P.ld(ci), vb = P.ld(cj);
+        float sg, g2;
+        const float sgm = S.sgm[cc];
+        const bool acc = vhs_accept(I, sgm, w2, va, vb, &sg, &g2);
+        atomicMax(&S.obs[cc], __float_as_uint(sg));
+        ++l_cand;
+        l_sat += sg > sgm;
+        if (acc) {
+          const uint32_t kk = (uint32_t)(k - S.coff[cc]);
+          const uint32_t ent = (uint32_t)(c_lo + cc - I.cell0);
+          const uint4 r1 = cw ? cw[q] : draw(I, ent, step, TAG_COLL, 3u * kk + 1u);
+          const uint32_t w8 = cw ? cphi[q] : draw(I, ent, step, TAG_COLL, 3u * kk + 2u).x;
+          apply_collision<EXT>(I, g2, w3, r1, w8, va, vb, &l_inel, ent, step, kk);
+          ++l_acc;
+          P.st(ci, va);
+          P.st(cj, vb);
+        }
+      }
+      // threads whose candidate ran take the next ones in order (one LDS
+      // atomic per wave), if any are left in this epoch
+      const unsigned long long m = __ballot(run);
+      if (m) {
+        const int leader = __ffsll(m) - 1;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(s_next, __popcll(m));
+        base = __shfl(base, leader);
+        if (run) {
+          k = base + __popcll(m & __lanemask_lt());
+          if (k < ee) take(k); else k = -1;
+        }
+      }
+      if (!__syncthreads_or(k >= 0)) break;
+    }
+  }
+  } else {
   // ---- large cells: candidates staged in chunks and executed in rounds; a
   // candidate runs once it is the earliest pending candidate of both its
   // particles.  Ownership keys carry the round, (0xFFFF - r) << 16 | q, so a
@@ -1052,6 +1164,7 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
       }
       if (!__syncthreads_or(more)) break;
     }
+  }
   }
   // statistics: wave sums first, one shared-memory atomic per wave and value
   for (int off = 32; off > 0; off >>= 1) {
@@ -1444,10 +1557,10 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       Sg.obs += c0;
       Sg.inst += c0;
       if (fast)
-        collide_cells<EXT>(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
+        collide_cells<EXT, mode == kModeBig>(a, Sg, ls, lown, 0xFFFFFFFFu, c1 - c0, c_lo + c0, step, iu, my_vol,
                       c0 == 0, cw, rchunk);
       else
-        collide_cells<EXT>(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu,
+        collide_cells<EXT, mode == kModeBig>(a, Sg, gs, (uint32_t*)sv, gmask, c1 - c0, c_lo + c0, step, iu,
                            my_vol,
                       c0 == 0, cw, rchunk);
       c0 = c1;
@@ -2373,7 +2486,10 @@ hipError_t collide_setup() {
 }
 
 hipError_t launch_move(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_move, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a);
+  if (a.dr_any)
+    hipLaunchKernelGGL(k_move<true>, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_move<false>, dim3(blocks_for(a.n_upper, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
