@@ -1181,16 +1181,19 @@ static __device__ void collide_cells(const StepArgs& a, const CollideShared& S, 
   }
 }
 
-// FP64 raw sums of a cell by an 8-lane subgroup: lane j of the subgroup sums
-// particles j, j+8, j+16, ... in slot order, then a fixed xor butterfly over
-// the 8 lanes.  The bits depend only on the cell's particle order, never on
-// launch parameters.  All 64 lanes of the wave must call it.
+// FP64 raw sums of a cell by a subgroup of W lanes (W = 8, or the whole wave
+// for cells above kWaveSumMin particles): lane j of the subgroup sums
+// particles j, j+W, j+2W, ... in slot order, then a fixed xor butterfly over
+// the W lanes.  W is a function of the cell's size alone, so the bits depend
+// only on the cell's particle order, never on launch parameters.  All 64
+// lanes of the wave must call it.
 constexpr int kSub = 8;
-template <class Store>
+constexpr int kWaveSumMin = 256;
+template <int W = kSub, class Store>
 static __device__ void sub_cell_sums(Store P, int b, int N, double s[17]) {
 #pragma unroll
   for (int f = 0; f < 17; ++f) s[f] = 0.0;
-  for (int k = lane_id() & (kSub - 1); k < N; k += kSub) {
+  for (int k = lane_id() & (W - 1); k < N; k += W) {
     const float4 v = P.ld(b + k);
     const double x = v.x, y = v.y, z = v.z, e = v.w;
     const double v2 = x * x + y * y + z * z;
@@ -1213,7 +1216,7 @@ static __device__ void sub_cell_sums(Store P, int b, int N, double s[17]) {
     s[16] += z * e;
   }
 #pragma unroll
-  for (int off = kSub / 2; off > 0; off >>= 1)
+  for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int f = 0; f < 17; ++f) s[f] += __shfl_xor(s[f], off);
 }
@@ -1251,11 +1254,11 @@ static __device__ __forceinline__ double raw_term(int f, double x, double y, dou
 
 // Sums F0 .. F0 + NF - 1 of sub_cell_sums, with the same order of additions
 // (so the same bits), for fewer live registers.
-template <int F0, int NF, class Store>
+template <int F0, int NF, int W = kSub, class Store>
 static __device__ void sub_cell_sums_part(Store P, int b, int N, double s[NF]) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) s[f] = 0.0;
-  for (int k = lane_id() & (kSub - 1); k < N; k += kSub) {
+  for (int k = lane_id() & (W - 1); k < N; k += W) {
     const float4 v = P.ld(b + k);
     const double x = v.x, y = v.y, z = v.z, e = v.w;
     double v2 = 0.0;
@@ -1264,7 +1267,7 @@ static __device__ void sub_cell_sums_part(Store P, int b, int N, double s[NF]) {
     for (int f = 0; f < NF; ++f) s[f] += raw_term(F0 + f, x, y, z, e, v2);
   }
 #pragma unroll
-  for (int off = kSub / 2; off > 0; off >>= 1)
+  for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int f = 0; f < NF; ++f) s[f] += __shfl_xor(s[f], off);
 }
@@ -1589,10 +1592,13 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
     __syncthreads();
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int sub = lane_id() / kSub, sl = lane_id() & (kSub - 1);
+    // cells up to kWaveSumMin particles: eight per wave, an 8-lane subgroup
+    // each
     for (int cb = w * (64 / kSub); cb < nc; cb += nw * (64 / kSub)) {
       const int c = cb + sub;
-      const bool ok = c < nc;
-      const int b = ok ? S.start[c] : 0, N = ok ? S.start[c + 1] - b : 0;
+      const int n_c = c < nc ? S.start[c + 1] - S.start[c] : 0;
+      const bool ok = c < nc && n_c <= kWaveSumMin;
+      const int b = ok ? S.start[c] : 0, N = ok ? n_c : 0;
       // the accumulator is read before the sums, so its latency overlaps
       // them
       double* acc = a.acc + (int64_t)(c_lo + (ok ? c : 0)) * 17;
@@ -1632,6 +1638,40 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
             const int f = sl + k * kSub;
             if (f < 17) acc[f] = prev[k] + select17(s, f);
           }
+        }
+      }
+    }
+    // larger cells: one wave each, taken in turn by the waves
+    const int l = lane_id();
+    int j = 0;
+    for (int cb = 0; cb < nc; cb += 64) {
+      const int c = cb + l;
+      unsigned long long m =
+          __ballot(c < nc && S.start[c + 1] - S.start[c] > kWaveSumMin);
+      for (; m; m &= m - 1, ++j) {
+        if (j % nw != w) continue;
+        const int cc = cb + __ffsll((long long)m) - 1;
+        const int b = S.start[cc], N = S.start[cc + 1] - b;
+        double* acc = a.acc + (int64_t)(c_lo + cc) * 17;
+        if (two_pass && fast) {
+          const double p0 = l < 9 ? acc[l] : 0.0;
+          const double p9 = l < 8 ? acc[9 + l] : 0.0;
+          {
+            double s[9];
+            sub_cell_sums_part<0, 9, 64>(ls, b, N, s);
+            if (l < 9) acc[l] = p0 + select_n<9>(s, l);
+          }
+          {
+            double s[8];
+            sub_cell_sums_part<9, 8, 64>(ls, b, N, s);
+            if (l < 8) acc[9 + l] = p9 + select_n<8>(s, l);
+          }
+        } else {
+          const double prev = l < 17 ? acc[l] : 0.0;
+          double s[17];
+          if (fast) sub_cell_sums<64>(ls, b, N, s);
+          else sub_cell_sums<64>(gs, b, N, s);
+          if (l < 17) acc[l] = prev + select17(s, l);
         }
       }
     }
@@ -1887,7 +1927,9 @@ __global__ void k_init_fill(StepArgs a, const double* fields) {
 }
 
 // ---------------------------------------------------------------------------
-// Instantaneous sums of the current state: one wave per cell.
+// Instantaneous sums of the current state: an 8-lane subgroup per cell, or
+// the whole wave for a cell above kWaveSumMin particles (the lane counts of
+// the collide's sums, so the same bits).
 __global__ __launch_bounds__(256) void k_sample_state(StepArgs a) {
   const int subs = (gridDim.x * blockDim.x) / kSub;
   const int s0 = (blockIdx.x * blockDim.x + threadIdx.x) / kSub;
@@ -1897,12 +1939,21 @@ __global__ __launch_bounds__(256) void k_sample_state(StepArgs a) {
   const int iters = (a.ncell + subs - 1) / subs;
   for (int it = 0; it < iters; ++it) {
     const int c = s0 + it * subs;
-    const bool ok = c < a.ncell;
-    const int b = ok ? a.start[c] : 0, N = ok ? a.start[c + 1] - b : 0;
+    const int n_c = c < a.ncell ? a.start[c + 1] - a.start[c] : 0;
+    const bool ok = c < a.ncell && n_c <= kWaveSumMin;
+    const int b = ok ? a.start[c] : 0, N = ok ? n_c : 0;
     double s[17];
     sub_cell_sums(gs, b, N, s);
     if (ok)
       for (int f = sl; f < 17; f += kSub) a.sums[(int64_t)c * 17 + f] = select17(s, f);
+    // this wave's larger cells, one after another with all 64 lanes
+    for (unsigned long long m = __ballot(c < a.ncell && !ok && sl == 0); m; m &= m - 1) {
+      const int cc = __shfl(c, __ffsll((long long)m) - 1);
+      const int bb = a.start[cc];
+      double t[17];
+      sub_cell_sums<64>(gs, bb, a.start[cc + 1] - bb, t);
+      if (lane_id() < 17) a.sums[(int64_t)cc * 17 + lane_id()] = select17(t, lane_id());
+    }
   }
 }
 
