@@ -87,10 +87,12 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(kernel: str, workload: str):
+def pmc_traffic(kernel: str, workload: str, n_avg: float):
     """HBM bytes per dispatch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when there is none or the kernel sources changed since it was taken."""
+    when there is none or the kernel sources changed since it was taken.
+    Where the summary records its particle count, the bytes are scaled per
+    particle to n_avg (the cylinder's count grows over a long window)."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -100,7 +102,9 @@ def pmc_traffic(kernel: str, workload: str):
     w = re.search(r"write_bytes_per_dispatch:\s*([\d.eE+]+)", text)
     if not (m and f and w) or m.group(1) != source_digest():
         return None
-    return float(f.group(1)) + float(w.group(1))
+    t = float(f.group(1)) + float(w.group(1))
+    n = re.search(r"particles_per_dispatch:\s*([\d.eE+]+)", text)
+    return round(t * n_avg / float(n.group(1))) if n else t
 
 
 def roofline(prof, breakdown, n_avg, ncell, workload, dim):
@@ -116,7 +120,7 @@ def roofline(prof, breakdown, n_avg, ncell, workload, dim):
     alg = collide_particle_bytes(dim) * n_avg + PER_CELL_BYTES * ncell
     ach = alg / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload, n_avg),
             "kernel": "k_collide + k_collide_big (collide stage, one launch each per step)",
             "avg_launch_us": round(avg_s * 1e6, 2),
             "algorithmic_bytes_per_launch": int(alg)}
