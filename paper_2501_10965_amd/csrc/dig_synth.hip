@@ -5,10 +5,13 @@
 // plus the DSMC higher-order terms, which are zeroed where the adaptive mask
 // is set (equations full_constitutive, ns_constitutive, kappa_A; Section 3.1).
 // The paper defers the numerics to other work; this library uses finite
-// volumes on the uniform grid with HLLC inviscid fluxes, central viscous and
-// heat fluxes, Dirichlet wall faces (wall values or the DSMC slip and jump of
-// the wall-adjacent cell) and explicit pseudo-time steps that are the same in
-// every cell, so the total mass is conserved exactly.
+// volumes on the uniform or graded box grid (cell widths, centre gaps) with
+// HLLC inviscid fluxes, central viscous and heat fluxes and Dirichlet wall
+// faces (wall values or the DSMC slip and jump of the wall-adjacent cell).
+// Two pseudo-time schemes march the same residual: explicit steps that are
+// the same in every cell (the total mass is conserved exactly), and LU-SGS
+// (the implicit scheme Section 4 names) in matrix-free form with a two-colour
+// cell order, each iteration's state scaled back to the initial mass.
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
