@@ -46,7 +46,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Internal {
   size_t gfirst, inst_pstart, params, newcount, ccount, newstart, cstart, bsum, lastcnt,
-      xsum, stats, rf2, dir, inj_off, done, big_list, big_count, fc32, fc64;
+      xsum, stats, rf2, dir, inj_off, done, big_list, big_count, fc32, fc64, vstage;
   int64_t gfirst_len;
 };
 
@@ -268,6 +268,7 @@ void plan_layout(int64_t cap, int64_t C, int32_t n_inst, int32_t geo_nx, int32_t
   I->inj_off = take(4 * (geo_nx + 2));
   I->fc32 = take(4 * nfaces);
   I->fc64 = take(8 * nfaces);
+  I->vstage = take(16 * cap);
   L->total_bytes = o;
 }
 
@@ -459,6 +460,7 @@ StepArgs args(const dig_ctx* c) {
   a.cvol = (const double*)(w + L.cvol);
   a.fc32 = (const float*)(w + c->I.fc32);
   a.fc64 = (const double*)(w + c->I.fc64);
+  a.vstage = (float4*)(w + c->I.vstage);
   a.rf2 = (const float*)(w + c->I.rf2);
   a.dir = (const float2*)(w + c->I.dir);
   a.inj_off = (int32_t*)(w + c->I.inj_off);

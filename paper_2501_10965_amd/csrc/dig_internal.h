@@ -125,6 +125,9 @@ struct StepArgs {
   int32_t big_runs;     // its run-table capacity
   int32_t* big_list;    // groups too large for the collide's stage, listed by it
   uint32_t* big_count;  // entries in big_list (emptied by k_collide_big)
+  // velocities and rotational energies of the groups collided in global
+  // memory, one record per particle at the destination slot
+  float4* vstage;
   int32_t ext_any;      // some instance needs the extended model (alpha != 1 or d_r != 2)
   int32_t dr_any;       // some instance has d_r != 2
 };

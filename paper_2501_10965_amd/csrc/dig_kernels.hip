@@ -705,6 +705,13 @@ struct LdsStore {
   __device__ float4 ld(int i) const { return v[i]; }
   __device__ void st(int i, float4 q) const { v[i] = q; }
 };
+// A group's velocities and rotational energies in global memory, one
+// 16-byte record per particle.
+struct RecordStore {
+  float4* v;
+  __device__ float4 ld(int i) const { return v[i]; }
+  __device__ void st(int i, float4 q) const { v[i] = q; }
+};
 struct GlobalStore {
   float *vx, *vy, *vz, *er;
   __device__ float4 ld(int i) const { return make_float4(vx[i], vy[i], vz[i], er[i]); }
@@ -1523,19 +1530,16 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       a.B.x[d] = x[u];
       if (two) a.B.y[d] = y[u];
       a.B.id[d] = id[u];
-      if (fast) {
-        sv[e] = v[u];
-      } else {
-        a.B.vx[d] = v[u].x;
-        a.B.vy[d] = v[u].y;
-        a.B.vz[d] = v[u].z;
-        a.B.er[d] = v[u].w;
-      }
+      if (fast) sv[e] = v[u];
+      else a.vstage[d] = v[u];
     }
   }
   __syncthreads();
   LdsStore ls{sv};
-  GlobalStore gs{a.B.vx + e_lo, a.B.vy + e_lo, a.B.vz + e_lo, a.B.er + e_lo};
+  // a group beyond the stage collides in its records in global memory: a
+  // candidate touches two 16-byte records rather than eight words of four
+  // arrays, and the records of the groups in flight stay in the caches
+  RecordStore gs{a.vstage + e_lo};
   // round owners of a group collided in global memory: the velocity stage,
   // unused by such a group, as a table of the largest power of two words
   const uint32_t gmask = (1u << (31 - __clz(4 * L))) - 1u;
@@ -1578,15 +1582,14 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       atomicAdd(&a.stats[(blockIdx.x % kStatSlots) * ST_N + threadIdx.x],
                 (unsigned long long)S.stat[threadIdx.x]);
   }
-  if (fast) {
-    for (int e = threadIdx.x; e < ng; e += blockDim.x) {
-      const float4 v = sv[e];
-      const int d = e_lo + e;
-      a.B.vx[d] = v.x;
-      a.B.vy[d] = v.y;
-      a.B.vz[d] = v.z;
-      a.B.er[d] = v.w;
-    }
+  // velocities and rotational energies to the destination arrays
+  for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+    const int d = e_lo + e;
+    const float4 v = fast ? sv[e] : a.vstage[d];
+    a.B.vx[d] = v.x;
+    a.B.vy[d] = v.y;
+    a.B.vz[d] = v.z;
+    a.B.er[d] = v.w;
   }
   if (do_sample) {
     __syncthreads();
