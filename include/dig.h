@@ -355,9 +355,11 @@ dig_status dsmc_tuning(dig_ctx* ctx, const dig_tuning* in_host, dig_tuning* out_
  * {512, 1024, 2048, 4096, 8192}, group_cells in {32, 64, 128, 256}, seq_max in
  * {0, 64, 128, 192, 384} and big_stage_kib in {38, 50, 76} (the last only for
  * contexts with open boundaries or at least 256 particles per cell on
- * average; two passes over the axes, each configuration timed once), timing
- * steps_per_trial real steps per candidate with
- * HIP events on `stream` (one untimed step before each).  The timed steps are
+ * average; two passes over the axes), timing steps_per_trial real steps per
+ * candidate with HIP events on `stream` (one untimed step before each); each
+ * candidate is compared with the best configuration timed again right after
+ * it, so that a state that evolves during the search (a developing flow)
+ * does not bias the choice toward the earlier trials.  The timed steps are
  * ordinary steps of the simulation: the state advances by every step taken,
  * exactly as dsmc_step would advance it, whichever configuration ran them.
  * cache_path (nullable): a text file of lines

@@ -1218,8 +1218,9 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
   const int32_t Gcs[] = {32, 64, 128, 256};
   const int32_t Sqs[] = {0, 64, 128, 192, 384};
   const int32_t Bks[] = {38, 50, 76};
-  // two passes over the three axes (the best group size can depend on the
-  // other two); a configuration is timed once
+  // two passes over the four axes (the best group size can depend on the
+  // others); each new configuration is timed once, beside a fresh timing of
+  // the best so far
   std::vector<dig_tuning> tried{best};
   auto seen = [&](const dig_tuning& t) {
     for (const dig_tuning& u : tried)
@@ -1246,7 +1247,16 @@ dig_status dsmc_autotune(dig_ctx* c, int32_t steps_per_trial, const char* cache_
         if (seen(t)) continue;
         tried.push_back(t);
         st = trial(t, &t.ms_per_step);
-        if (st == DIG_OK && t.ms_per_step < best.ms_per_step) best = t;
+        // the state keeps evolving (a developing flow slows or speeds every
+        // step), so the best configuration is timed again right after the
+        // candidate and the two are compared at the same point of the run
+        double ms_best = 0.0;
+        if (st == DIG_OK) st = trial(best, &ms_best);
+        if (st == DIG_OK && t.ms_per_step < ms_best) {
+          best = t;
+        } else if (st == DIG_OK) {
+          best.ms_per_step = ms_best;
+        }
       }
     }
   }

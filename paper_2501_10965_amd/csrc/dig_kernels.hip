@@ -741,6 +741,9 @@ struct CollideShared {
 static __device__ __forceinline__ bool vhs_accept(const InstParam& I, float sgm, uint32_t w2,
                                                   const float4& va, const float4& vb,
                                                   float* sg_out, float* g2_out) {
+  // no contraction: every inlined copy (one-lane cells, rounds, LDS or
+  // global stores) rounds alike, so results do not depend on the path
+#pragma clang fp contract(off)
   const float gx = va.x - vb.x, gy = va.y - vb.y, gz = va.z - vb.z;
   const float g2 = gx * gx + gy * gy + gz * gz;
   const float sg = g2 > 0.0f ? I.csig * fpow(g2, I.expo) : 0.0f;
@@ -782,6 +785,7 @@ static __device__ __forceinline__ void apply_collision(const InstParam& I, float
                                                        uint4 r1, uint32_t w8, float4& va,
                                                        float4& vb, int* inel, uint32_t ent,
                                                        uint32_t step, uint32_t kk) {
+#pragma clang fp contract(off)  // as in vhs_accept
   float et = 0.25f * g2;  // relative translational energy, reduced mass 1/2
   if (u01d(w3) < I.pin) {
     const float ec = et + va.w;
@@ -1483,7 +1487,12 @@ static __device__ __forceinline__ void collide_group(const StepArgs& a, int g, i
       if (n <= kRankMax)
         for (int e = b; e < b + n; ++e) ecell[e] = (uint8_t)c;
     }
-    if (__syncthreads_or(big)) {
+    // the reduction is no memory fence: the fences publish the entry -> cell
+    // map to the counting below
+    __threadfence_block();
+    const bool any_big = __syncthreads_or(big);
+    __threadfence_block();
+    if (any_big) {
       order_runs(S.start, nc, ng, (const int32_t*)sraw, sord, rkey, rre, roff, S.wsum, run_slots);
     } else {
       // every cell small: an entry's place in its cell is the number of the

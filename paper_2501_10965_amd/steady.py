@@ -64,7 +64,9 @@ class Tracker:
         self.range = float(ref.max() - ref.min())
         self.buf = collections.deque(maxlen=window)
         self.threshold = threshold
-        self.history = []  # (wall seconds, steps, err)
+        # (wall seconds, steps, RMS error, largest pointwise error), both
+        # relative to the reference profile's range
+        self.history = []
 
     def add(self, prof: torch.Tensor, wall: float, steps: int):
         self.buf.append(prof)
@@ -72,15 +74,18 @@ class Tracker:
             return None
         avg = torch.stack(list(self.buf)).mean(0)
         err = float(((avg - self.ref) ** 2).mean().sqrt()) / self.range
-        self.history.append((wall, steps, err))
+        err_max = float((avg - self.ref).abs().max()) / self.range
+        self.history.append((wall, steps, err, err_max))
         return err
 
-    def time_to_steady(self, threshold: float | None = None):
-        """(wall, steps) of the first point after which err stays <= threshold
-        (the tracker's own by default)."""
+    def time_to_steady(self, threshold: float | None = None, metric: str = "rms"):
+        """(wall, steps) of the first point after which the error ("rms" or
+        "max") stays <= threshold (the tracker's own by default)."""
         thr = self.threshold if threshold is None else threshold
+        k = 2 if metric == "rms" else 3
         t = None
-        for wall, steps, err in self.history:
+        for h in self.history:
+            wall, steps, err = h[0], h[1], h[k]
             if err <= thr:
                 if t is None:
                     t = (wall, steps)
@@ -131,4 +136,4 @@ def _settled(tr: Tracker, window: int) -> bool:
     """Stop once the error has stayed below the threshold for 4 windows."""
     h = tr.history
     need = 4 * window
-    return len(h) >= need and all(e <= tr.threshold for _, _, e in h[-need:])
+    return len(h) >= need and all(e[2] <= tr.threshold for e in h[-need:])
