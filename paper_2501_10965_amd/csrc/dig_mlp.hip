@@ -460,6 +460,8 @@ __global__ void k_mlp_wred(MlpDev d, int nchunks) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= DIG_MLP_NPARAM) return;
   float v = 0.0f;
+  // loads of eight chunks in flight, added in chunk order
+#pragma unroll 8
   for (int c = 0; c < nchunks; ++c) v += d.wpart[(int64_t)c * DIG_MLP_NPARAM + i];
   d.g[i] = v;
 }
