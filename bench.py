@@ -506,10 +506,14 @@ def run_steady(args):
     progress("plain DSMC arm")
     tr = steady.run_plain(w, ref, w["ns"], args.dig_max_cycles * 4, W, thr, P, cols)
     arms["dsmc"] = tr
-    dig_kw = dict(ns=w["ns"], n_m=args.synth_iters, wall_mode="wall", scheme=args.synth_scheme,
+    # DIG cycles of N_s steps; the sliding window covers the same number of
+    # DSMC steps as the plain arm's
+    ns = args.steady_dig_ns or w["ns"]
+    Wd = max(1, W * w["ns"] // ns)
+    dig_kw = dict(ns=ns, n_m=args.synth_iters, wall_mode="wall", scheme=args.synth_scheme,
                   columns=cols)
-    progress(f"DIG arm (DSMC-extracted terms, {args.synth_scheme} synthetic solve)")
-    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, **dig_kw)
+    progress(f"DIG arm (DSMC-extracted terms, {args.synth_scheme} synthetic solve, N_s {ns})")
+    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, **dig_kw)
     arms["dig"] = tr
     if args.steady_explicit_arm:
         progress("DIG arm (explicit synthetic solve, 2000 iterations)")
@@ -547,8 +551,8 @@ def run_steady(args):
     train_s = time.perf_counter() - t0
     progress("DIG arm (learned closure)")
     hook = learn.LearnedClosure(net, sc, kn_lo=0.01, judge_sigma=3.0, judge_rel=0.1,
-                                avg_steps=w["ns"])
-    tr, d = steady.run_dig(w, ref, args.dig_max_cycles, W, thr, P, closure=hook, **dig_kw)
+                                avg_steps=ns)
+    tr, d = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, closure=hook, **dig_kw)
     arms["dig_learned"] = tr
     res = {}
     for name, tr in arms.items():
@@ -691,6 +695,9 @@ def main():
     ap.add_argument("--steady-graded-arm", action="store_true",
                     help="steady: also DIG on the wall-refined 100 x 100 grid")
     ap.add_argument("--synth-scheme", choices=["explicit", "lusgs"], default="lusgs")
+    ap.add_argument("--steady-dig-ns", type=int, default=0,
+                    help="steady: DSMC steps per DIG cycle (N_s) of the DIG arms "
+                         "(0: the workload's 50)")
     ap.add_argument("--dig-max-cycles", type=int, default=400)
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -728,7 +735,8 @@ def main():
                            f"RMS error <= {args.steady_threshold} of the reference range "
                            "(the largest pointwise error reported beside it); "
                            "reference 60k + 120k plain-DSMC steps; DIG synthetic solve "
-                           f"{args.synth_scheme}, N_m = {args.synth_iters}"},
+                           f"{args.synth_scheme}, N_m = {args.synth_iters}, N_s = "
+                           f"{args.steady_dig_ns or 50}"},
                 "plain_dsmc_seconds": base, "arms": res}
         print(json.dumps(line), flush=True)
         return
