@@ -498,10 +498,10 @@ def run_steady(args):
     from paper_2501_10965_amd import learn, steady
     from paper_2501_10965_amd.mlp import MLP
 
-    w = wl.cavity_2d(seed=2001)
+    w = wl.cavity_2d(seed=2001, ppc=args.steady_ppc)
     P, W, thr, cols = 20, args.steady_window, args.steady_threshold, args.steady_columns
     progress("reference run")
-    ref = steady.reference_profile(w, 60000, 120000, P, cols)
+    ref = steady.reference_profile(w, args.steady_ref_steps[0], args.steady_ref_steps[1], P, cols)
     arms = {}
     progress("plain DSMC arm")
     tr = steady.run_plain(w, ref, w["ns"], args.dig_max_cycles * 4, W, thr, P, cols)
@@ -510,8 +510,8 @@ def run_steady(args):
     # DSMC steps as the plain arm's
     ns = args.steady_dig_ns or w["ns"]
     Wd = max(1, W * w["ns"] // ns)
-    dig_kw = dict(ns=ns, n_m=args.synth_iters, wall_mode="wall", scheme=args.synth_scheme,
-                  columns=cols)
+    dig_kw = dict(ns=ns, n_m=args.synth_iters, wall_mode=args.steady_wall_mode,
+                  scheme=args.synth_scheme, columns=cols)
     progress(f"DIG arm (DSMC-extracted terms, {args.synth_scheme} synthetic solve, N_s {ns})")
     tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, **dig_kw)
     arms["dig"] = tr
@@ -695,6 +695,13 @@ def main():
     ap.add_argument("--steady-graded-arm", action="store_true",
                     help="steady: also DIG on the wall-refined 100 x 100 grid")
     ap.add_argument("--synth-scheme", choices=["explicit", "lusgs"], default="lusgs")
+    ap.add_argument("--steady-wall-mode", choices=["wall", "dsmc"], default="wall",
+                    help="steady: wall faces of the DIG arms' synthetic solve: the walls' "
+                         "values, or the DSMC slip and jump of the wall-adjacent cells")
+    ap.add_argument("--steady-ppc", type=int, default=50,
+                    help="steady: particles per cell of the cavity")
+    ap.add_argument("--steady-ref-steps", type=int, nargs=2, default=[60000, 120000],
+                    help="steady: transient and averaged steps of the reference run")
     ap.add_argument("--steady-dig-ns", type=int, default=0,
                     help="steady: DSMC steps per DIG cycle (N_s) of the DIG arms "
                          "(0: the workload's 50)")
@@ -729,12 +736,14 @@ def main():
                 "value": learned, "unit": "s", "n_gpus": 1, "steps": None,
                 "warmup": 0, "ms_per_step": None, "higher_is_better": False,
                 "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                "config": {"workload": "cavity 200x200, 2M particles, Kn 0.01, lid Ma 0.3; "
+                "config": {"workload": f"cavity 200x200, {args.steady_ppc} particles per cell "
+                           f"({args.steady_ppc * 40000 / 1e6:g}M), Kn 0.01, lid Ma 0.3; "
                            f"centreline u_x ({args.steady_columns} centre columns, 20 block "
                            f"averages), window {args.steady_window} cycles of 50 steps, "
                            f"RMS error <= {args.steady_threshold} of the reference range "
                            "(the largest pointwise error reported beside it); "
-                           "reference 60k + 120k plain-DSMC steps; DIG synthetic solve "
+                           f"reference {args.steady_ref_steps[0]} + {args.steady_ref_steps[1]} "
+                           "plain-DSMC steps; DIG synthetic solve "
                            f"{args.synth_scheme}, N_m = {args.synth_iters}, N_s = "
                            f"{args.steady_dig_ns or 50}"},
                 "plain_dsmc_seconds": base, "arms": res}
