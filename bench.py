@@ -511,9 +511,10 @@ def run_steady(args):
     ns = args.steady_dig_ns or w["ns"]
     Wd = max(1, W * w["ns"] // ns)
     dig_kw = dict(ns=ns, n_m=args.synth_iters, wall_mode=args.steady_wall_mode,
-                  scheme=args.synth_scheme, columns=cols)
+                  scheme=args.synth_scheme, columns=cols, handoff=args.steady_handoff or None)
+    runs = {}
     progress(f"DIG arm (DSMC-extracted terms, {args.synth_scheme} synthetic solve, N_s {ns})")
-    tr, _ = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, **dig_kw)
+    tr, runs["dig"] = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, **dig_kw)
     arms["dig"] = tr
     if args.steady_explicit_arm:
         progress("DIG arm (explicit synthetic solve, 2000 iterations)")
@@ -553,6 +554,7 @@ def run_steady(args):
     hook = learn.LearnedClosure(net, sc, kn_lo=0.01, judge_sigma=3.0, judge_rel=0.1,
                                 avg_steps=ns)
     tr, d = steady.run_dig(w, ref, args.dig_max_cycles, Wd, thr, P, closure=hook, **dig_kw)
+    runs["dig_learned"] = d
     arms["dig_learned"] = tr
     res = {}
     for name, tr in arms.items():
@@ -573,6 +575,10 @@ def run_steady(args):
                      "err_at": [(round(e[0], 3), e[1], round(e[2], 5), round(e[3], 5))
                                 for e in tr.history[::10]]}
     res["dig_learned"]["training_seconds"] = round(train_s, 2)
+    for name, d in runs.items():
+        ch = [r["cycle_change"] for r in d.log if "cycle_change" in r]
+        res[name]["handoff_cycle"] = d.handoff_at
+        res[name]["cycle_change"] = [round(c, 5) for c in ch[::5]]
     src = hook.last_src
     if src is not None:
         res["dig_learned"]["last_cycle_sources"] = {
@@ -698,6 +704,10 @@ def main():
     ap.add_argument("--steady-wall-mode", choices=["wall", "dsmc"], default="wall",
                     help="steady: wall faces of the DIG arms' synthetic solve: the walls' "
                          "values, or the DSMC slip and jump of the wall-adjacent cells")
+    ap.add_argument("--steady-handoff", type=float, default=0.95,
+                    help="steady: DIG arms continue as plain DSMC once the mean change of "
+                         "the macroscopic solution between cycles over 10 cycles exceeds this "
+                         "fraction of the mean over the 10 before (it has levelled off; 0: never)")
     ap.add_argument("--steady-ppc", type=int, default=50,
                     help="steady: particles per cell of the cavity")
     ap.add_argument("--steady-ref-steps", type=int, nargs=2, default=[60000, 120000],
@@ -745,7 +755,10 @@ def main():
                            f"reference {args.steady_ref_steps[0]} + {args.steady_ref_steps[1]} "
                            "plain-DSMC steps; DIG synthetic solve "
                            f"{args.synth_scheme}, N_m = {args.synth_iters}, N_s = "
-                           f"{args.steady_dig_ns or 50}"},
+                           f"{args.steady_dig_ns or 50}"
+                           + (f", DIG hands off to plain DSMC once its cycle-to-cycle change "
+                              f"levels off (ratio {args.steady_handoff} over 10-cycle means)"
+                              if args.steady_handoff else "")},
                 "plain_dsmc_seconds": base, "arms": res}
         print(json.dumps(line), flush=True)
         return

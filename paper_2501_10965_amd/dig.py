@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import time
 
+import numpy as np
 import torch
 
 from .dsmc import DSMC, synth_solve
@@ -27,12 +28,24 @@ def default_A(omega: float):
     return (2.0 / 3.0, 0.0, 0.0, 5.0 / (7.0 - 2.0 * omega))
 
 
+def _cycle_change(new: torch.Tensor, old: torch.Tensor) -> float:
+    """Relative change between two macroscopic solutions [>=6, C] (rows rho,
+    ux, uy, uz, Tt, Tr), taken on the host: the larger of the L2 changes of
+    the in-plane velocity and of Tt, each over its own norm."""
+    a = new[0:6].double().cpu().numpy()
+    b = old[0:6].double().cpu().numpy()
+    du = np.linalg.norm(a[1:3] - b[1:3]) / max(np.linalg.norm(b[1:3]), 1e-300)
+    dt = np.linalg.norm(a[4] - b[4]) / max(np.linalg.norm(b[4]), 1e-300)
+    return float(max(du, dt))
+
+
 class DIG:
     def __init__(self, w: dict, mode: str = "dig", ns: int = 50, n_m: int = 2000,
                  tol: float = 1e-5, kn_ref: float = 0.01, A=None, wall_mode: str = "dsmc",
                  closure=None, capacity: int | None = None, cfl: float | None = None,
                  nsf_init: bool = True, init_iters: int | None = None, graph: bool = True,
-                 scheme: str = "explicit", n_min: float = 1.0, **dsmc_kw):
+                 scheme: str = "explicit", n_min: float = 1.0, handoff: float | None = None,
+                 **dsmc_kw):
         assert mode in ("dig", "dsmc")
         self.w = w
         self.mode = mode
@@ -51,6 +64,14 @@ class DIG:
         # optional learned closure: (sim, fields, hot, mask, kn, smooth=...) -> hot, where
         # smooth holds the latest macroscopic solution in rows 0..5
         self.closure_fn = closure
+        # hand-off: the change of the macroscopic solution between cycles
+        # (relative L2 norm of the in-plane velocity or of the translational
+        # temperature, the larger) falls while DIG converges and then levels
+        # off at the level the sampling noise sets; once its mean over the last
+        # HANDOFF_WINDOW cycles is above `handoff` times the mean over the
+        # window before, later cycles are plain DSMC
+        self.handoff = handoff
+        self.handoff_at = None
         self.sim = DSMC(w, capacity=capacity, cap_factor=1.6, **dsmc_kw)
         self.ncell = self.sim.ncell
         self.cycle_no = 0
@@ -71,6 +92,16 @@ class DIG:
         # counts by Iround(rho V / N_eff), equilibrium velocities, rotational energies
         self.sim.init(f0.contiguous(), ppc=0)
 
+    HANDOFF_WINDOW = 10
+
+    def _levelled_off(self) -> bool:
+        ch = [r["cycle_change"] for r in self.log if "cycle_change" in r]
+        n = self.HANDOFF_WINDOW
+        if len(ch) < 2 * n:
+            return False
+        last, before = np.mean(ch[-n:]), np.mean(ch[-2 * n:-n])
+        return last > self.handoff * before
+
     def cycle(self):
         """One DIG iteration (or N_s plain DSMC steps); returns the averaged field."""
         t0 = time.perf_counter()
@@ -78,7 +109,7 @@ class DIG:
         self.sim.step(self.ns, graph=self.graph)
         f = self.sim.sample("average")
         rec = {"cycle": self.cycle_no}
-        if self.mode == "dig":
+        if self.mode == "dig" and self.handoff_at is None:
             # cells left empty over the cycle start from the previous solution
             self.sim.fill_empty(f, self.m_prev)
             hot, mask, kn, _ = self.sim.closure(f, self.A, self.kn_ref, n_min=self.n_min)
@@ -90,11 +121,15 @@ class DIG:
                                          wall_mode=self.wall_mode, max_iter=self.n_m,
                                          tol=self.tol, scheme=self.scheme)
             self.sim.adjust(m_next, self.cycle_no)
+            change = _cycle_change(m_next, self.m_prev)
             self.m_prev = m_next
-            rec.update(synth_iters=it, synth_change=ch,
+            rec.update(synth_iters=it, synth_change=ch, cycle_change=change,
                        eq_fraction=float(mask.double().mean().item()))
         torch.cuda.synchronize()
         rec["seconds"] = time.perf_counter() - t0
         self.log.append(rec)
+        if self.mode == "dig" and self.handoff is not None and self.handoff_at is None and \
+                self._levelled_off():
+            self.handoff_at = self.cycle_no
         self.cycle_no += 1
         return f
