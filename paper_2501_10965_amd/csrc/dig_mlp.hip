@@ -375,83 +375,109 @@ __global__ __launch_bounds__(kThreads) void k_mlp_bwd(MlpDev d) {
 
 // Weight and bias gradients of a batch: dW_l[o][i] = sum_s g_l[s][o] a_l[s][i]
 // and db_l[o] = sum_s g_l[s][o], from the feature-major activations and
-// gradients.  Split over samples: wave q of the grid takes one 32 x 32 block
-// (l, o-block, i-block) of one weight matrix and one chunk of samples, a
-// 2 x 2 grid of 16 x 16 MFMA tiles with the samples as the reduction axis
-// (A = rows of g^T, B = rows of a^T: 8 consecutive samples per lane, one
-// 16-byte load each), and writes its partial block (and, for i-block 0, its
-// partial bias sums); k_mlp_wred adds the chunks' partials in chunk order, so
-// the result does not depend on timing.  Blocks: layer 0: 4 (128 outputs) x 1
-// (32 padded inputs); layers 1, 2: 4 x 4; layer 3: 1 (16 padded outputs, one
-// row tile) x 4.
-constexpr int kWBlocks = 4 + 16 + 16 + 4;
-constexpr int kWMaxChunks = 64;
+// gradients.  Split over samples: workgroup (l, chunk) takes all of layer l's
+// weights for one chunk of samples.  Its rows of g^T and a^T are staged in
+// LDS kWStage samples at a time (each row read from memory once, rather than
+// once per 32 x 32 output block), and wave w computes its tiles from there
+// with 16 x 16 MFMA tiles and the samples as the reduction axis (A = rows of
+// g^T, B = rows of a^T: 8 consecutive samples per lane, one 16-byte read
+// each): layers 0-2 rows 32w..32w+31 (two row tiles) against every input
+// tile, layer 3 (16 padded outputs, one row tile) input tiles 2w and 2w+1.
+// It writes its partial block (and the bias sums of its rows); k_mlp_wred
+// adds the chunks' partials in chunk order, so the result does not depend
+// on timing.
+constexpr int kWMaxChunks = 128;
+constexpr int kWStage = 64;           // samples per LDS stage
+constexpr int kWRow = kWStage + 8;    // LDS row stride in bf16 (padded)
+constexpr int kWPieces = kWStage / 8; // 16-byte pieces per staged row
+static_assert(kWStage % 32 == 0, "whole 32-sample MFMA steps per stage");
+constexpr size_t kWLds = 2 * 128 * kWRow * sizeof(uint16_t);
 
-__global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev d, int64_t rows, int nchunks,
-                                                   int64_t chunk) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const int q = (int)blockIdx.x * 4 + wave;
-  const int blk = q / nchunks, ck = q % nchunks;
-  if (blk >= kWBlocks) return;
-  int l, b = blk;
-  if (b < 4) {
-    l = 0;
-  } else if ((b -= 4) < 16) {
-    l = 1;
-  } else if ((b -= 16) < 16) {
-    l = 2;
-  } else {
-    b -= 16;
-    l = 3;
-  }
-  const int nib = din(l) / 32, ob = b / nib, ib = b % nib;
-  const int nrt = l == 3 ? 1 : 2;
+// One workgroup's share of layer l: RT row tiles from rt0, CT input tiles
+// from ct0 per wave; BIAS: the wave also sums its rows' bias gradients.
+template <int RT, int CT>
+__device__ __forceinline__ void wgrad_layer(const MlpDev& d, int l, int64_t s_lo, int64_t s_hi,
+                                            int ck, int rt0, int ct0, bool bias,
+                                            uint16_t* sA, uint16_t* sB) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int O = dout(l), I = din(l);
   const uint16_t* gT = l == 3 ? d.g3T : l == 2 ? d.g2 : l == 1 ? d.g1 : d.g0;
   const uint16_t* aT = l == 3 ? d.a3 : l == 2 ? d.a2 : l == 1 ? d.a1 : d.a0;
-  const int64_t s_lo = (int64_t)ck * chunk;
-  const int64_t s_hi = s_lo + chunk < rows ? s_lo + chunk : rows;
-  f32x4 acc[2][2];
+  f32x4 acc[RT][CT];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  float bs[2] = {0.0f, 0.0f};
-  const uint16_t* ga = gT + (int64_t)(32 * ob + li) * d.B + 8 * lg;
-  const uint16_t* gb = gT + (int64_t)(32 * ob + 16 + li) * d.B + 8 * lg;
-  const uint16_t* a0p = aT + (int64_t)(32 * ib + li) * d.B + 8 * lg;
-  const uint16_t* a1p = aT + (int64_t)(32 * ib + 16 + li) * d.B + 8 * lg;
-  for (int64_t s = s_lo; s < s_hi; s += 32) {
-    const bf16x8 A0 = ld8(ga + s);
-    const bf16x8 A1 = nrt == 2 ? ld8(gb + s) : A0;
-    const bf16x8 B0 = ld8(a0p + s), B1 = ld8(a1p + s);
-    acc[0][0] = mfma32(A0, B0, acc[0][0]);
-    acc[0][1] = mfma32(A0, B1, acc[0][1]);
-    if (nrt == 2) {
-      acc[1][0] = mfma32(A1, B0, acc[1][0]);
-      acc[1][1] = mfma32(A1, B1, acc[1][1]);
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float bs[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) bs[rt] = 0.0f;
+  const bf16x8 zero = {};
+  for (int64_t s0 = s_lo; s0 < s_hi; s0 += kWStage) {
+    __syncthreads();  // the previous stage has been read
+    // 16-byte pieces, kWPieces per row of the stage; a 32-sample step is
+    // read when it starts before the chunk's end, later steps are zeros
+    for (int pc = threadIdx.x; pc < (O + I) * kWPieces; pc += blockDim.x) {
+      const bool isA = pc < O * kWPieces;
+      const int q = isA ? pc : pc - O * kWPieces;
+      const int row = q / kWPieces, c8 = (q % kWPieces) * 8;
+      const bool ok = s0 + (c8 & ~31) < s_hi;
+      const bf16x8 v = ok ? ld8((isA ? gT : aT) + (int64_t)row * d.B + s0 + c8) : zero;
+      *(bf16x8*)((isA ? sA : sB) + row * kWRow + c8) = v;
     }
-    if (ib == 0) {
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        bs[0] += (float)A0[j];
-        bs[1] += (float)A1[j];
+    for (int k = 0; k < kWStage / 32; ++k) {
+      bf16x8 A[RT], Bv[CT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        A[rt] = ld8(sA + (16 * (rt0 + rt) + li) * kWRow + 32 * k + 8 * lg);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        Bv[ct] = ld8(sB + (16 * (ct0 + ct) + li) * kWRow + 32 * k + 8 * lg);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma32(A[rt], Bv[ct], acc[rt][ct]);
+      if (bias) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bs[rt] += (float)A[rt][j];
       }
     }
   }
   float* part = d.wpart + (int64_t)ck * DIG_MLP_NPARAM;
-  for (int rt = 0; rt < nrt; ++rt) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+  for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        part[pw(l) + (32 * ob + 16 * rt + 4 * lg + r) * din(l) + 32 * ib + 16 * ct + li] =
-            acc[rt][ct][r];
-    if (ib == 0) {
+        part[pw(l) + (16 * (rt0 + rt) + 4 * lg + r) * I + 16 * (ct0 + ct) + li] = acc[rt][ct][r];
+    if (bias) {
       float v = bs[rt];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
-      if (lg == 0) part[pb(l) + 32 * ob + 16 * rt + li] = v;
+      if (lg == 0) part[pb(l) + 16 * (rt0 + rt) + li] = v;
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_wgrad(MlpDev d, int64_t rows, int nchunks,
+                                                   int64_t chunk) {
+  extern __shared__ __align__(16) unsigned char smem_w[];
+  uint16_t* sA = (uint16_t*)smem_w;
+  uint16_t* sB = sA + 128 * kWRow;
+  const int wave = threadIdx.x >> 6;
+  const int l = (int)blockIdx.x / nchunks, ck = (int)blockIdx.x % nchunks;
+  const int64_t s_lo = (int64_t)ck * chunk;
+  const int64_t s_hi = s_lo + chunk < rows ? s_lo + chunk : rows;
+  if (l == 3) {
+    wgrad_layer<1, 2>(d, l, s_lo, s_hi, ck, 0, 2 * wave, wave == 0, sA, sB);
+  } else if (l == 0) {
+    wgrad_layer<2, 2>(d, l, s_lo, s_hi, ck, 2 * wave, 0, true, sA, sB);
+  } else {
+    wgrad_layer<2, 8>(d, l, s_lo, s_hi, ck, 2 * wave, 0, true, sA, sB);
   }
 }
 
@@ -460,8 +486,8 @@ __global__ void k_mlp_wred(MlpDev d, int nchunks) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= DIG_MLP_NPARAM) return;
   float v = 0.0f;
-  // loads of eight chunks in flight, added in chunk order
-#pragma unroll 8
+  // loads of sixteen chunks in flight, added in chunk order
+#pragma unroll 16
   for (int c = 0; c < nchunks; ++c) v += d.wpart[(int64_t)c * DIG_MLP_NPARAM + i];
   d.g[i] = v;
 }
@@ -617,6 +643,12 @@ dig_status mlp_create(void* ws, size_t bytes, int32_t max_batch, dig_stream_t st
     delete m;
     return report(DIG_ERR_INVALID, "workspace too small");
   }
+  // the weight-gradient kernel stages its rows in LDS (kWLds bytes)
+  if (hipFuncSetAttribute((const void*)k_mlp_wgrad, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kWLds) != hipSuccess) {
+    delete m;
+    return report(DIG_ERR_HIP, "mlp_create: LDS attribute of the weight-gradient kernel");
+  }
   MlpDev d = m->dev();
   hipStream_t s = (hipStream_t)stream;
   for (float* p : {d.g, d.m, d.v, d.loss}) {
@@ -668,8 +700,7 @@ dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_s
   int64_t chunk = (rows + nch - 1) / nch;
   chunk = (chunk + 31) / 32 * 32;
   nch = (rows + chunk - 1) / chunk;
-  const int64_t waves = (int64_t)kWBlocks * nch;
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, d, rows,
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)(4 * nch)), dim3(256), kWLds, s, d, rows,
                      (int)nch, chunk);
   hipLaunchKernelGGL(k_mlp_wred, dim3((DIG_MLP_NPARAM + 255) / 256), dim3(256), 0, s, d,
                      (int)nch);
