@@ -106,11 +106,16 @@ typedef struct {
 
 /* Byte offsets of the device arrays inside the caller's workspace.  Particle
  * arrays hold `capacity` elements, cell arrays `ncell`.  Buffer `cur`
- * (returned by dsmc_query) holds the current, cell-sorted particle state. */
+ * (returned by dsmc_query) holds the current, cell-sorted particle state.
+ * total_bytes also covers the library's own scratch after these arrays (cell
+ * group and scan tables, geometry tables, and one 16-byte record per
+ * particle in which cell groups too large for on-chip memory collide). */
 typedef struct {
   size_t total_bytes;
   int64_t capacity, ncell;
-  size_t x[2], y[2], vx[2], vy[2], vz[2], er[2], id[2]; /* f32 x4 (grid units), f32, u32 */
+  size_t x[2], y[2], vx[2], vy[2], vz[2], er[2], id[2]; /* f32 (x, y: grid units on a uniform
+                                                           box, physical units on a graded box
+                                                           or the annulus), u32 id */
   size_t cell, rank, perm_raw, perm;                    /* i32 per particle */
   size_t start;      /* i32 [ncell + 1]: first particle of each cell */
   size_t count;      /* i32 [ncell] */
