@@ -438,7 +438,10 @@ dig_status mlp_grad(dig_mlp* mlp, const float* x_dev, const float* t_dev, int64_
 dig_status mlp_adam(dig_mlp* mlp, float lr, float beta1, float beta2, float eps, int64_t t,
                     dig_stream_t stream);
 
-/* mlp_grad followed by mlp_adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+/* The result of mlp_grad followed by mlp_adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8), bit for bit: same loss, stored gradient, moments and parameters.
+ * The loss, the gradient reduction and the update run as one launch.
+ * Errors: INVALID (as mlp_grad, or t < 1 or lr < 0). */
 dig_status mlp_train_step(dig_mlp* mlp, const float* x_dev, const float* t_dev, int64_t n,
                           float lr, int64_t t, dig_stream_t stream);
 

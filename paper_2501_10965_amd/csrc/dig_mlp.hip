@@ -259,7 +259,9 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd(MlpDev d, const float* __r
 
 // Loss of a training batch: the per-wave partial sums of the forward pass
 // added in a fixed order (deterministic), over 7 n.
-__global__ __launch_bounds__(256) void k_mlp_loss(MlpDev d, int nparts, int64_t n) {
+// Loss of a training batch from the per-wave partial sums, in a fixed order
+// (a 256-thread workgroup, every thread taking part).
+__device__ __forceinline__ void loss_sum(const MlpDev& d, int nparts, int64_t n) {
   __shared__ float sh[4];
   float v = 0.0f;
   for (int i = threadIdx.x; i < nparts; i += 256) v += d.lpart[i];
@@ -267,6 +269,10 @@ __global__ __launch_bounds__(256) void k_mlp_loss(MlpDev d, int nparts, int64_t 
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) d.loss[0] = (((sh[0] + sh[1]) + sh[2]) + sh[3]) / (7.0f * (float)n);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_loss(MlpDev d, int nparts, int64_t n) {
+  loss_sum(d, nparts, n);
 }
 
 // One hidden layer of the inference kernel from register-resident weights:
@@ -505,11 +511,11 @@ __device__ __forceinline__ void write_copies(const MlpDev& d, int i, float val) 
   }
 }
 
-__global__ void k_mlp_adam(MlpDev d, float lr, float b1, float b2, float eps, float c1,
-                           float c2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= DIG_MLP_NPARAM) return;
-  const float g = d.g[i];
+// Adam update of parameter i with gradient g (no contraction, so the
+// separate and the fused launches round alike).
+__device__ __forceinline__ void adam_update(const MlpDev& d, int i, float g, float lr, float b1,
+                                            float b2, float eps, float c1, float c2) {
+#pragma clang fp contract(off)
   const float m = b1 * d.m[i] + (1.0f - b1) * g;
   const float v = b2 * d.v[i] + (1.0f - b2) * g * g;
   d.m[i] = m;
@@ -517,6 +523,29 @@ __global__ void k_mlp_adam(MlpDev d, float lr, float b1, float b2, float eps, fl
   const float p = d.p[i] - lr * (m / c1) / (sqrtf(v / c2) + eps);
   d.p[i] = p;
   write_copies(d, i, p);
+}
+
+__global__ void k_mlp_adam(MlpDev d, float lr, float b1, float b2, float eps, float c1,
+                           float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= DIG_MLP_NPARAM) return;
+  adam_update(d, i, d.g[i], lr, b1, b2, eps, c1, c2);
+}
+
+// A training step's tail in one launch: workgroup 0 also sums the loss; each
+// parameter's gradient is the chunk partials added in chunk order (as the
+// plain reduction adds them), stored, and applied by Adam.
+__global__ __launch_bounds__(256) void k_mlp_wred_adam(MlpDev d, int nchunks, int nparts,
+                                                       int64_t n, float lr, float b1, float b2,
+                                                       float eps, float c1, float c2) {
+  if (blockIdx.x == 0) loss_sum(d, nparts, n);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= DIG_MLP_NPARAM) return;
+  float v = 0.0f;
+#pragma unroll 16
+  for (int c = 0; c < nchunks; ++c) v += d.wpart[(int64_t)c * DIG_MLP_NPARAM + i];
+  d.g[i] = v;
+  adam_update(d, i, v, lr, b1, b2, eps, c1, c2);
 }
 
 __global__ void k_mlp_sync(MlpDev d) {
@@ -682,15 +711,24 @@ dig_status mlp_forward(dig_mlp* m, const float* x, float* y, int64_t n, dig_stre
   return hip_check("mlp_forward");
 }
 
-dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_stream_t stream) {
-  if (!m || !x || !t) return report(DIG_ERR_INVALID, "null argument");
-  if (n < 1 || n > m->L.max_batch) return report(DIG_ERR_INVALID, "n outside [1, max_batch]");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+struct AdamArgs {
+  float lr, b1, b2, eps, c1, c2;
+};
+
+// Forward, backward and weight gradients of a batch. With `adam` the loss,
+// the gradient reduction and the Adam update run as one launch; without it
+// the loss and the reduction run on their own.
+dig_status launch_grad(dig_mlp* m, const float* x, const float* t, int64_t n, hipStream_t s,
+                       const AdamArgs* adam) {
   MlpDev d = m->dev();
   const unsigned tiles = (unsigned)((n + kTile - 1) / kTile);
+  const int nparts = (int)(tiles * (kThreads / 64));
   hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(tiles), dim3(kThreads), 0, s, d, x, t, (float*)nullptr,
                      n);
-  hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, d, (int)(tiles * (kThreads / 64)), n);
+  if (!adam) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, d, nparts, n);
   hipLaunchKernelGGL(k_mlp_bwd, dim3(tiles), dim3(kThreads), 0, s, d);
   // sample chunks of the weight gradients: a multiple of 32 samples, at most
   // kWMaxChunks chunks, about 256 samples or more each
@@ -702,16 +740,34 @@ dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_s
   nch = (rows + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)(4 * nch)), dim3(256), kWLds, s, d, rows,
                      (int)nch, chunk);
-  hipLaunchKernelGGL(k_mlp_wred, dim3((DIG_MLP_NPARAM + 255) / 256), dim3(256), 0, s, d,
-                     (int)nch);
-  return hip_check("mlp_grad");
+  const dim3 pgrid((DIG_MLP_NPARAM + 255) / 256);
+  if (adam)
+    hipLaunchKernelGGL(k_mlp_wred_adam, pgrid, dim3(256), 0, s, d, (int)nch, nparts, n, adam->lr,
+                       adam->b1, adam->b2, adam->eps, adam->c1, adam->c2);
+  else
+    hipLaunchKernelGGL(k_mlp_wred, pgrid, dim3(256), 0, s, d, (int)nch);
+  return hip_check(adam ? "mlp_train_step" : "mlp_grad");
+}
+
+// Adam's hyper-parameters lie in range (NaN fails every comparison).
+bool adam_args_ok(float lr, float beta1, float beta2, float eps, int64_t t) {
+  return t >= 1 && beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f &&
+         eps > 0.0f && lr >= 0.0f;
+}
+}  // namespace
+
+extern "C" {
+
+dig_status mlp_grad(dig_mlp* m, const float* x, const float* t, int64_t n, dig_stream_t stream) {
+  if (!m || !x || !t) return report(DIG_ERR_INVALID, "null argument");
+  if (n < 1 || n > m->L.max_batch) return report(DIG_ERR_INVALID, "n outside [1, max_batch]");
+  return launch_grad(m, x, t, n, (hipStream_t)stream, nullptr);
 }
 
 dig_status mlp_adam(dig_mlp* m, float lr, float beta1, float beta2, float eps, int64_t t,
                     dig_stream_t stream) {
   if (!m) return report(DIG_ERR_INVALID, "null network");
-  if (t < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
-      !(eps > 0.0f) || !(lr >= 0.0f))
+  if (!adam_args_ok(lr, beta1, beta2, eps, t))
     return report(DIG_ERR_INVALID, "bad Adam hyper-parameters");
   const float c1 = (float)(1.0 - pow((double)beta1, (double)t));
   const float c2 = (float)(1.0 - pow((double)beta2, (double)t));
@@ -722,9 +778,14 @@ dig_status mlp_adam(dig_mlp* m, float lr, float beta1, float beta2, float eps, i
 
 dig_status mlp_train_step(dig_mlp* m, const float* x, const float* t, int64_t n, float lr,
                           int64_t step, dig_stream_t stream) {
-  const dig_status st = mlp_grad(m, x, t, n, stream);
-  if (st != DIG_OK) return st;
-  return mlp_adam(m, lr, 0.9f, 0.999f, 1e-8f, step, stream);
+  if (!m || !x || !t) return report(DIG_ERR_INVALID, "null argument");
+  if (n < 1 || n > m->L.max_batch) return report(DIG_ERR_INVALID, "n outside [1, max_batch]");
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  if (!adam_args_ok(lr, b1, b2, eps, step))
+    return report(DIG_ERR_INVALID, "bad Adam hyper-parameters");
+  const AdamArgs A{lr, b1, b2, eps, (float)(1.0 - pow((double)b1, (double)step)),
+                   (float)(1.0 - pow((double)b2, (double)step))};
+  return launch_grad(m, x, t, n, (hipStream_t)stream, &A);
 }
 
 void mlp_destroy(dig_mlp* m) { delete m; }

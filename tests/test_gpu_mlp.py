@@ -157,3 +157,28 @@ def test_training_follows_oracle_and_reduces_loss():
     lg, lo = np.array(lg), np.array(lo)
     assert np.all(np.abs(lg - lo) <= 0.02 * lo), (lg, lo)
     assert lg[-1] < 0.5 * lg[0]
+
+
+def test_train_step_equals_grad_then_adam():
+    """The fused training step (loss, reduction and Adam in one launch) gives
+    bit for bit what mlp_grad followed by mlp_adam gives, over several steps
+    and a ragged batch."""
+    say("case mlp fused train step")
+    p = wl.mlp_init(12)
+    a = MLP(p, max_batch=1024)
+    b = MLP(p, max_batch=1024)
+    for step in range(1, 5):
+        n = 1000 - 37 * step
+        x, t = batch(20 + step, n)
+        xg, tg = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+        la = float(a.train_step(xg, tg, 2e-3).item())
+        lb = float(b.grad(xg, tg).item())
+        b.adam(2e-3, step)
+        assert la == lb, (step, la, lb)
+        assert torch.equal(a.grads, b.grads), step
+        pa, pb = a.get_params(), b.get_params()
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), (step, k)
+    ya = a.forward(torch.from_numpy(batch(30, 300)[0]).cuda())
+    yb = b.forward(torch.from_numpy(batch(30, 300)[0]).cuda())
+    assert torch.equal(ya, yb)
