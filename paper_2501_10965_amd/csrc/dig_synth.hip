@@ -68,24 +68,38 @@ __device__ __forceinline__ void conductivities(const SynthGrid& g, double mu, do
   *kr = 0.5 * mu * (-g.Art * 5.0 + g.Att * g.dr) / det;
 }
 
-// central derivative of velocity component k along axis at cell (ix, iy)
+// central derivative of velocity component k along axis at cell (ix, iy):
+// the two neighbours (one-sided at a wall) over the distance between their
+// centres.  The neighbours are chosen first and then loaded without a branch,
+// so the loads of all calls issue together.
 __device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int iy, int k,
                          int axis) {
   if (axis == 1 && g.dim == 1) return 0.0;
   const int n = axis == 0 ? g.nx : g.ny;
   const double* gap = axis == 0 ? g.gx : g.gy;
   const int i = axis == 0 ? ix : iy;
-  auto uk = [&](int j) {
-    const int c = axis == 0 ? j + g.nx * iy : ix + g.nx * j;
-    return W[(1 + k) * C + c] / W[c];
-  };
-  // the two neighbours over the distance between their centres
-  if (g.bc_periodic[axis])
-    return (uk((i + 1) % n) - uk((i - 1 + n) % n)) / (gap[i] + gap[i + 1]);
-  if (n < 2) return 0.0;
-  if (i > 0 && i < n - 1) return (uk(i + 1) - uk(i - 1)) / (gap[i] + gap[i + 1]);
-  if (i == 0) return (uk(1) - uk(0)) / gap[1];
-  return (uk(n - 1) - uk(n - 2)) / gap[n - 1];
+  const bool per = g.bc_periodic[axis] != 0;
+  const bool inner = per || (i > 0 && i < n - 1);
+  int jp, jm;
+  if (n < 2) {
+    jp = jm = i;
+  } else if (per) {
+    jp = (i + 1) % n;
+    jm = (i - 1 + n) % n;
+  } else {
+    jp = i == 0 ? 1 : (i == n - 1 ? n - 1 : i + 1);
+    jm = i == 0 ? 0 : (i == n - 1 ? n - 2 : i - 1);
+  }
+  // centre distance: gap[i] + gap[i + 1] inside, gap[1] or gap[n - 1] at a wall
+  const int ga = inner ? i : (i == 0 ? 1 : n - 1);
+  const double g0 = gap[ga];
+  const double g1 = gap[i + 1];
+  const int cp = axis == 0 ? jp + g.nx * iy : ix + g.nx * jp;
+  const int cm = axis == 0 ? jm + g.nx * iy : ix + g.nx * jm;
+  const double up = W[(1 + k) * C + cp] / W[cp];
+  const double um = W[(1 + k) * C + cm] / W[cm];
+  if (!per && n < 2) return 0.0;
+  return (up - um) / (inner ? g0 + g1 : g0);
 }
 
 // NSF + HoT stress and heat flux through a face normal to `axis`.
@@ -139,62 +153,91 @@ __device__ __forceinline__ void hllc_star(const double U[6], const Prim& p, doub
   out[5] = f * U[5] / p.rho;
 }
 
-// Flux through face (fi, fj) normal to `axis`: x faces are (fx, iy) with
-// fx in [0, nx], y faces (ix, fy) with fy in [0, ny].
+// Faces: x faces are (fx, iy) with fx in [0, nx], y faces (ix, fy) with fy
+// in [0, ny]; face t of an axis is fa + nfa * fb (axis 0: fa = fx, fb = iy;
+// axis 1: fa = ix, fb = fy).
 template <int axis>
-__device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays& s, int t) {
-  const int C = g.nx * g.ny;
-  const int nfa = axis == 0 ? g.nx + 1 : g.nx;
-  const int nfb = axis == 0 ? g.ny : g.ny + 1;
-  if (t >= nfa * nfb) return;
-  const int fa = t % nfa, fb = t / nfa;  // axis 0: fa = fx, fb = iy; axis 1: fa = ix, fb = fy
-  const int n = axis == 0 ? g.nx : g.ny;
-  const int f = axis == 0 ? fa : fb;      // face index along the axis
-  // distance between the centres across this face (half a cell at a wall)
-  const double h = (axis == 0 ? g.gx : g.gy)[f];
-  const int periodic = g.bc_periodic[axis];
-  auto cell_at = [&](int along) {
+struct FaceAt {
+  int fa, fb, f, n;
+  bool wall;
+  __device__ FaceAt(const SynthGrid& g, int t) {
+    const int nfa = axis == 0 ? g.nx + 1 : g.nx;
+    fa = t % nfa;
+    fb = t / nfa;
+    n = axis == 0 ? g.nx : g.ny;
+    f = axis == 0 ? fa : fb;  // face index along the axis
+    wall = !g.bc_periodic[axis] && (f == 0 || f == n);
+  }
+  __device__ int cell(const SynthGrid& g, int along) const {
     return axis == 0 ? along + g.nx * fb : fa + g.nx * along;
-  };
-  auto cell_xy = [&](int along, int* ix, int* iy) {
-    if (axis == 0) { *ix = along; *iy = fb; } else { *ix = fa; *iy = along; }
-  };
-  double F[6];
-  if (periodic || (f > 0 && f < n)) {
-    const int al = (f - 1 + n) % n, ar = f % n;
-    const int cl = cell_at(al), cr = cell_at(ar);
-    const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
-    double Ul[6], Ur[6], Fl[6], Fr[6];
-    for (int k = 0; k < 6; ++k) {
-      Ul[k] = s.W[k * C + cl];
-      Ur[k] = s.W[k * C + cr];
-    }
-    euler_flux<axis>(Ul, pl, Fl);
-    euler_flux<axis>(Ur, pr, Fr);
-    const double cL = sqrt(g.gam * pl.tt), cR = sqrt(g.gam * pr.tt);
-    const double SL = fmin(pl.u[axis] - cL, pr.u[axis] - cR);
-    const double SR = fmax(pl.u[axis] + cL, pr.u[axis] + cR);
-    const double pL = pl.rho * pl.tt, pR = pr.rho * pr.tt;
-    const double Ss = (pR - pL + pl.rho * pl.u[axis] * (SL - pl.u[axis]) -
-                       pr.rho * pr.u[axis] * (SR - pr.u[axis])) /
-                      (pl.rho * (SL - pl.u[axis]) - pr.rho * (SR - pr.u[axis]));
-    if (SL >= 0.0) {
-      for (int k = 0; k < 6; ++k) F[k] = Fl[k];
-    } else if (Ss >= 0.0) {
-      double Us[6];
-      hllc_star<axis>(Ul, pl, SL, Ss, Us);
-      for (int k = 0; k < 6; ++k) F[k] = Fl[k] + SL * (Us[k] - Ul[k]);
-    } else if (SR > 0.0) {
-      double Us[6];
-      hllc_star<axis>(Ur, pr, SR, Ss, Us);
-      for (int k = 0; k < 6; ++k) F[k] = Fr[k] + SR * (Us[k] - Ur[k]);
+  }
+  __device__ void xy(int along, int* ix, int* iy) const {
+    if (axis == 0) {
+      *ix = along;
+      *iy = fb;
     } else {
-      for (int k = 0; k < 6; ++k) F[k] = Fr[k];
+      *ix = fa;
+      *iy = along;
     }
-    // viscous part
+  }
+};
+
+// HLLC flux through interior or periodic face t; false (F untouched) at a wall.
+template <int axis>
+__device__ __forceinline__ bool face_inviscid(const SynthGrid& g, const SynthArrays& s, int t,
+                                              double F[6]) {
+  const FaceAt<axis> fc(g, t);
+  if (fc.wall) return false;
+  const int C = g.nx * g.ny;
+  const int cl = fc.cell(g, (fc.f - 1 + fc.n) % fc.n), cr = fc.cell(g, fc.f % fc.n);
+  const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
+  double Ul[6], Ur[6], Fl[6], Fr[6];
+  for (int k = 0; k < 6; ++k) {
+    Ul[k] = s.W[k * C + cl];
+    Ur[k] = s.W[k * C + cr];
+  }
+  euler_flux<axis>(Ul, pl, Fl);
+  euler_flux<axis>(Ur, pr, Fr);
+  const double cL = sqrt(g.gam * pl.tt), cR = sqrt(g.gam * pr.tt);
+  const double SL = fmin(pl.u[axis] - cL, pr.u[axis] - cR);
+  const double SR = fmax(pl.u[axis] + cL, pr.u[axis] + cR);
+  const double pL = pl.rho * pl.tt, pR = pr.rho * pr.tt;
+  const double Ss = (pR - pL + pl.rho * pl.u[axis] * (SL - pl.u[axis]) -
+                     pr.rho * pr.u[axis] * (SR - pr.u[axis])) /
+                    (pl.rho * (SL - pl.u[axis]) - pr.rho * (SR - pr.u[axis]));
+  if (SL >= 0.0) {
+    for (int k = 0; k < 6; ++k) F[k] = Fl[k];
+  } else if (Ss >= 0.0) {
+    double Us[6];
+    hllc_star<axis>(Ul, pl, SL, Ss, Us);
+    for (int k = 0; k < 6; ++k) F[k] = Fl[k] + SL * (Us[k] - Ul[k]);
+  } else if (SR > 0.0) {
+    double Us[6];
+    hllc_star<axis>(Ur, pr, SR, Ss, Us);
+    for (int k = 0; k < 6; ++k) F[k] = Fr[k] + SR * (Us[k] - Ur[k]);
+  } else {
+    for (int k = 0; k < 6; ++k) F[k] = Fr[k];
+  }
+  return true;
+}
+
+// Viscous and heat flux through face t (NSF plus the masked HoT, averaged
+// over the two cells); at a wall the whole flux: Dirichlet wall state, the
+// wall pressure on the normal momentum, zero mass flux.
+template <int axis>
+__device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArrays& s, int t,
+                                             double F[6]) {
+  const FaceAt<axis> fc(g, t);
+  const int C = g.nx * g.ny;
+  // distance between the centres across this face (half a cell at a wall)
+  const double h = (axis == 0 ? g.gx : g.gy)[fc.f];
+  if (!fc.wall) {
+    const int al = (fc.f - 1 + fc.n) % fc.n, ar = fc.f % fc.n;
+    const int cl = fc.cell(g, al), cr = fc.cell(g, ar);
+    const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
     int ixl, iyl, ixr, iyr;
-    cell_xy(al, &ixl, &iyl);
-    cell_xy(ar, &ixr, &iyr);
+    fc.xy(al, &ixl, &iyl);
+    fc.xy(ar, &ixr, &iyr);
     const double tf = 0.5 * (pl.tt + pr.tt);
     double uf[3], dn[3], dtn[3], Hf[12];
     for (int i = 0; i < 3; ++i) {
@@ -205,61 +248,77 @@ __device__ __forceinline__ void face_flux(const SynthGrid& g, const SynthArrays&
                           : 0.0;
     }
     for (int k = 0; k < 12; ++k) Hf[k] = 0.5 * (s.H[k * C + cl] + s.H[k * C + cr]);
-    double V[6];
-    visc_flux<axis>(g, tf, uf, dn, dtn, (pr.tt - pl.tt) / h, (pr.tr - pl.tr) / h, Hf, V);
-    for (int k = 0; k < 6; ++k) F[k] += V[k];
-  } else {
-    // wall face: Dirichlet state, zero mass flux
-    const int side = f == 0 ? 0 : 1;
-    const int face = 2 * axis + side;
-    const int al = side == 0 ? 0 : n - 1;
-    const int c = cell_at(al);
-    int ix, iy;
-    cell_xy(al, &ix, &iy);
-    const Prim p = prim_of(s.W, C, c, g.dr);
-    const int nmax = g.nx > g.ny ? g.nx : g.ny;
-    const int wi = axis == 0 ? fb : fa;  // position along the wall
-    const double* wv = s.wall + (size_t)face * 5 * nmax;
-    const double uw[3] = {wv[0 * nmax + wi], wv[1 * nmax + wi], wv[2 * nmax + wi]};
-    const double ttw = wv[3 * nmax + wi], trw = wv[4 * nmax + wi];
-    const double sgn = side == 0 ? 1.0 : -1.0;
-    double dn[3], dtn[3], Hf[12];
-    for (int i = 0; i < 3; ++i) {
-      dn[i] = sgn * (p.u[i] - uw[i]) / h;
-      dtn[i] = g.dim == 2 ? dcen_u(g, s.W, C, ix, iy, i, 1 - axis) : 0.0;
-    }
-    for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
-    double V[6];
-    visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / h,
-                    sgn * (p.tr - trw) / h, Hf, V);
-    for (int k = 0; k < 6; ++k) F[k] = V[k];
-    F[1 + axis] += p.rho * p.tt;
-    F[0] = 0.0;
+    visc_flux<axis>(g, tf, uf, dn, dtn, (pr.tt - pl.tt) / h, (pr.tr - pl.tr) / h, Hf, F);
+    return;
   }
-  double* out = axis == 0 ? s.Fx : s.Fy;
-  const int nf = nfa * nfb;
-  for (int k = 0; k < 6; ++k) out[(size_t)k * nf + t] = F[k];
+  const int side = fc.f == 0 ? 0 : 1;
+  const int face = 2 * axis + side;
+  const int al = side == 0 ? 0 : fc.n - 1;
+  const int c = fc.cell(g, al);
+  int ix, iy;
+  fc.xy(al, &ix, &iy);
+  const Prim p = prim_of(s.W, C, c, g.dr);
+  const int nmax = g.nx > g.ny ? g.nx : g.ny;
+  const int wi = axis == 0 ? fc.fb : fc.fa;  // position along the wall
+  const double* wv = s.wall + (size_t)face * 5 * nmax;
+  const double uw[3] = {wv[0 * nmax + wi], wv[1 * nmax + wi], wv[2 * nmax + wi]};
+  const double ttw = wv[3 * nmax + wi], trw = wv[4 * nmax + wi];
+  const double sgn = side == 0 ? 1.0 : -1.0;
+  double dn[3], dtn[3], Hf[12];
+  for (int i = 0; i < 3; ++i) {
+    dn[i] = sgn * (p.u[i] - uw[i]) / h;
+    dtn[i] = g.dim == 2 ? dcen_u(g, s.W, C, ix, iy, i, 1 - axis) : 0.0;
+  }
+  for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
+  visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / h,
+                  sgn * (p.tr - trw) / h, Hf, F);
+  F[1 + axis] += p.rho * p.tt;
+  F[0] = 0.0;
 }
 
-// Fluxes of every face of the grid: threads [0, nfx) take the x faces, the
-// rest the y faces.  Thread 0 also resets the next iteration's reductions
-// (parity it + 1).  That is safe only through stream order: the last kernel
-// to touch those slots is the update of iteration it - 1, which read its
-// time step from them, and it has completed before this launch starts on the
-// same stream; the update of this iteration, the next to use them, starts
-// after this launch has completed.
+// Fluxes of every face of the grid, x faces first.  A workgroup takes 128
+// faces: waves 0-1 their HLLC fluxes, waves 2-3 their viscous and heat
+// fluxes (two chains of half the length: the grid has too few faces to hide
+// latency otherwise); the inviscid waves add the two and store.  Thread 0
+// also resets the next iteration's reductions (parity it + 1).  That is safe
+// only through stream order: the last kernel to touch those slots is the
+// update of iteration it - 1, which read its time step from them, and it has
+// completed before this launch starts on the same stream; the update of this
+// iteration, the next to use them, starts after this launch has completed.
+constexpr int kFluxFaces = 128;
+
 __global__ __launch_bounds__(256) void k_synth_flux(SynthGrid g, SynthArrays s, int it) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {
+  __shared__ double Vs[6][kFluxFaces];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     s.red[((it + 1) & 1) * 2 + 0] = 0x7FF0000000000000ull;  // +inf
     s.red[((it + 1) & 1) * 2 + 1] = 0ull;
   }
+  const bool visc = threadIdx.x >= kFluxFaces;
+  const int i = threadIdx.x & (kFluxFaces - 1);
+  const int t = blockIdx.x * kFluxFaces + i;
   const int nfx = (g.nx + 1) * g.ny;
-  if (t < nfx) {
-    face_flux<0>(g, s, t);
-  } else if (g.dim == 2 && t < nfx + g.nx * (g.ny + 1)) {
-    face_flux<1>(g, s, t - nfx);
+  const int nft = nfx + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
+  double F[6];
+  bool interior = false;
+  if (t < nft) {
+    if (visc) {
+      if (t < nfx)
+        face_viscous<0>(g, s, t, F);
+      else
+        face_viscous<1>(g, s, t - nfx, F);
+      for (int k = 0; k < 6; ++k) Vs[k][i] = F[k];
+    } else {
+      interior = t < nfx ? face_inviscid<0>(g, s, t, F) : face_inviscid<1>(g, s, t - nfx, F);
+    }
   }
+  __syncthreads();
+  if (visc || t >= nft) return;
+  for (int k = 0; k < 6; ++k) F[k] = interior ? F[k] + Vs[k][i] : Vs[k][i];
+  const bool xf = t < nfx;
+  double* out = xf ? s.Fx : s.Fy;
+  const int nf = xf ? nfx : nft - nfx;
+  const int tf = xf ? t : t - nfx;
+  for (int k = 0; k < 6; ++k) out[(size_t)k * nf + tf] = F[k];
 }
 
 // Explicit stability bound of cell c (widths wx, wy of the cell).
@@ -381,9 +440,9 @@ struct LusgsArrays {
   double* R;     // [6][C] steady residuals
   double* D;     // [2][C] diagonal (rows 0-4, row 5)
   double* rad;   // [2][C] spectral radii along x and y
-  double* part;  // [nb] per-block mass partial sums; [nb] the initial mass
+  double* part;  // [nparts] per-workgroup mass sums of the new state, then of the initial one
   unsigned long long* chg;  // [2] relative change (max) by iteration parity
-  int nb;        // blocks of the cell kernels
+  int nparts;    // workgroups of the sweep kernels (64 pairs of cells each)
 };
 
 __device__ __forceinline__ bool first_colour(const SynthGrid& g, int c) {
@@ -401,35 +460,87 @@ __device__ __forceinline__ void euler_of(const double U[6], int dr, double F[6])
   euler_flux<axis>(U, p, F);
 }
 
-// sum_j (dF_j . n_ij - r_j dW_j) / (2 h) over the neighbours of cell c of
-// the other colour (their increments in L.dW are final).
+// Term (side dF - r dW) / (2 h) of cell c's neighbour across its face on
+// `side` (+1 or -1) of `axis`, h the width of cell c, dF the change of the
+// neighbour's inviscid flux by its increment (final in L.dW: the neighbour has
+// the other colour); false where the face is a wall.
 template <int axis>
-__device__ void add_neighbours(const SynthGrid& g, const SynthArrays& s, const LusgsArrays& L,
-                               int c, double acc[6]) {
+__device__ __forceinline__ bool neighbour_term(const SynthGrid& g, const SynthArrays& s,
+                                               const LusgsArrays& L, int c, int side,
+                                               double out[6]) {
   const int C = g.nx * g.ny;
   const int n = axis == 0 ? g.nx : g.ny;
   const int i = axis == 0 ? c % g.nx : c / g.nx;
   const double h = (axis == 0 ? g.wx : g.wy)[i];  // width of the receiving cell
-  for (int side = 1; side >= -1; side -= 2) {
-    int j = i + side;
-    if (j < 0 || j >= n) {
-      if (!g.bc_periodic[axis]) continue;
-      j = (j + n) % n;
-    }
-    const int cj = axis == 0 ? j + g.nx * (c / g.nx) : (c % g.nx) + g.nx * j;
-    double U[6], V[6], F0[6], F1[6];
-    for (int k = 0; k < 6; ++k) {
-      U[k] = s.W[(size_t)k * C + cj];
-      V[k] = U[k] + L.dW[(size_t)k * C + cj];
-    }
-    euler_of<axis>(U, g.dr, F0);
-    euler_of<axis>(V, g.dr, F1);
-    const double r = L.rad[(size_t)axis * C + cj];
-    for (int k = 0; k < 6; ++k) {
-      const double t = (double)side * (F1[k] - F0[k]) - r * L.dW[(size_t)k * C + cj];
-      acc[k] += t / (2.0 * h);
-    }
+  int j = i + side;
+  if (j < 0 || j >= n) {
+    if (!g.bc_periodic[axis]) return false;
+    j = (j + n) % n;
   }
+  const int cj = axis == 0 ? j + g.nx * (c / g.nx) : (c % g.nx) + g.nx * j;
+  double U[6], V[6], F0[6], F1[6];
+  for (int k = 0; k < 6; ++k) {
+    U[k] = s.W[(size_t)k * C + cj];
+    V[k] = U[k] + L.dW[(size_t)k * C + cj];
+  }
+  euler_of<axis>(U, g.dr, F0);
+  euler_of<axis>(V, g.dr, F1);
+  const double r = L.rad[(size_t)axis * C + cj];
+  for (int k = 0; k < 6; ++k) {
+    const double t = (double)side * (F1[k] - F0[k]) - r * L.dW[(size_t)k * C + cj];
+    out[k] = t / (2.0 * h);
+  }
+  return true;
+}
+
+// Layout of the two sweep kernels: a workgroup of 256 threads takes 64 pairs
+// of cells (2p, 2p + 1).  Row-major order alternates the colours (across rows
+// too when nx is odd; rows of even nx hold whole pairs), so a pair holds one
+// cell of each colour.  Wave q computes neighbour slot q of the pair's cell
+// of the swept colour, slots in the order (x, +1), (x, -1), (y, +1), (y, -1);
+// the cell's sum then adds the slots in that order, from zero, as a plain
+// loop over the neighbours would.  Four short chains per cell instead of one
+// long one: the grid holds too few cells to hide latency otherwise.
+constexpr int kSweepPairs = 64;
+
+__device__ __forceinline__ int pair_cell(const SynthGrid& g, int pair, bool first) {
+  const int c0 = 2 * pair;
+  return first_colour(g, c0) == first ? c0 : c0 + 1;
+}
+
+struct SweepLds {
+  double t[4][6][kSweepPairs];
+  int ok[4][kSweepPairs];
+};
+
+// Every thread of the workgroup: slot (wave) terms of the workgroup's cells
+// of the swept colour, into S.
+__device__ __forceinline__ void sweep_terms(const SynthGrid& g, const SynthArrays& s,
+                                            const LusgsArrays& L, bool first, SweepLds& S) {
+  const int C = g.nx * g.ny;
+  const int q = threadIdx.x >> 6, i = threadIdx.x & 63;
+  const int c = pair_cell(g, blockIdx.x * kSweepPairs + i, first);
+  double v[6];
+  bool ok = false;
+  if (c < C) {
+    const int side = (q & 1) ? -1 : 1;
+    if (q < 2)
+      ok = neighbour_term<0>(g, s, L, c, side, v);
+    else if (g.dim == 2)
+      ok = neighbour_term<1>(g, s, L, c, side, v);
+  }
+  S.ok[q][i] = ok;
+  if (ok)
+    for (int k = 0; k < 6; ++k) S.t[q][k][i] = v[k];
+  __syncthreads();
+}
+
+// Sum of the slot terms of the workgroup's cell i, slot order.
+__device__ __forceinline__ void sweep_sum(const SweepLds& S, int i, double acc[6]) {
+  for (int k = 0; k < 6; ++k) acc[k] = 0.0;
+  for (int q = 0; q < 4; ++q)
+    if (S.ok[q][i])
+      for (int k = 0; k < 6; ++k) acc[k] += S.t[q][k][i];
 }
 
 // Residual, diagonal and spectral radii of every cell; lower sweep on the
@@ -469,16 +580,25 @@ __global__ void k_lusgs_cells(SynthGrid g, SynthArrays s, LusgsArrays L, int it)
     for (int k = 0; k < 6; ++k) L.dW[(size_t)k * C + c] = R[k] / (k == 5 ? D5 : D0);
 }
 
-// Lower sweep on the second colour.
-__global__ void k_lusgs_lower(SynthGrid g, SynthArrays s, LusgsArrays L) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// Lower sweep on the second colour.  Wave 0 loads what it needs to finish
+// its cells before the slot terms, so both rounds of loads overlap.
+__global__ __launch_bounds__(256) void k_lusgs_lower(SynthGrid g, SynthArrays s, LusgsArrays L) {
+  __shared__ SweepLds S;
   const int C = g.nx * g.ny;
-  if (c >= C || first_colour(g, c)) return;
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  add_neighbours<0>(g, s, L, c, acc);
-  if (g.dim == 2) add_neighbours<1>(g, s, L, c, acc);
-  for (int k = 0; k < 6; ++k)
-    L.dW[(size_t)k * C + c] = (L.R[(size_t)k * C + c] - acc[k]) / L.D[(k == 5 ? C : 0) + c];
+  const int i = threadIdx.x & 63;
+  const int c = pair_cell(g, blockIdx.x * kSweepPairs + i, false);
+  const bool fin = threadIdx.x < kSweepPairs && c < C;
+  double R[6], D0 = 1.0, D5 = 1.0;
+  if (fin) {
+    for (int k = 0; k < 6; ++k) R[k] = L.R[(size_t)k * C + c];
+    D0 = L.D[c];
+    D5 = L.D[C + c];
+  }
+  sweep_terms(g, s, L, false, S);
+  if (!fin) return;
+  double acc[6];
+  sweep_sum(S, i, acc);
+  for (int k = 0; k < 6; ++k) L.dW[(size_t)k * C + c] = (R[k] - acc[k]) / (k == 5 ? D5 : D0);
 }
 
 // Volume of cell c (area in 2D, length in 1D): the mass of a cell is rho V.
@@ -498,59 +618,111 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Upper sweep on the first colour, then the new state W + dW of every cell
-// and the per-block sums of its mass.
-__global__ void k_lusgs_upper(SynthGrid g, SynthArrays s, LusgsArrays L) {
+// Upper sweep on the first colour, then the new state W + dW of both cells
+// of every pair (wave 0 the first colour, wave 1 the second) and the
+// workgroup's sum of their masses.  Waves 0 and 1 load their cells' state,
+// increment and diagonal before the slot terms.
+__global__ __launch_bounds__(256) void k_lusgs_upper(SynthGrid g, SynthArrays s, LusgsArrays L) {
+  __shared__ SweepLds S;
   __shared__ double sh[16];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
-  double rho_new = 0.0;
-  if (c < C) {
-    double dW[6];
-    for (int k = 0; k < 6; ++k) dW[k] = L.dW[(size_t)k * C + c];
-    if (first_colour(g, c)) {
-      double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      add_neighbours<0>(g, s, L, c, acc);
-      if (g.dim == 2) add_neighbours<1>(g, s, L, c, acc);
-      for (int k = 0; k < 6; ++k) dW[k] = dW[k] - acc[k] / L.D[(k == 5 ? C : 0) + c];
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+  const int c = pair_cell(g, blockIdx.x * kSweepPairs + i, w == 0);
+  const bool fin = w < 2 && c < C;
+  double dW[6], Wc[6], D0 = 1.0, D5 = 1.0;
+  if (fin) {
+    for (int k = 0; k < 6; ++k) {
+      dW[k] = L.dW[(size_t)k * C + c];
+      Wc[k] = s.W[(size_t)k * C + c];
     }
-    for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] = s.W[(size_t)k * C + c] + dW[k];
-    rho_new = s.Wn[c] * cell_vol(g, c);
+    D0 = L.D[c];
+    D5 = L.D[C + c];
+  }
+  sweep_terms(g, s, L, true, S);
+  double rho_new = 0.0;
+  if (fin) {
+    if (w == 0) {
+      double acc[6];
+      sweep_sum(S, i, acc);
+      for (int k = 0; k < 6; ++k) dW[k] = dW[k] - acc[k] / (k == 5 ? D5 : D0);
+    }
+    for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] = Wc[k] + dW[k];
+    rho_new = (Wc[0] + dW[0]) * cell_vol(g, c);
   }
   const double t = block_sum(rho_new, sh);
   if (threadIdx.x == 0) L.part[blockIdx.x] = t;
 }
 
-// Initial total mass from the start state (one block, fixed order).
-__global__ void k_lusgs_mass0(SynthGrid g, const double* W, LusgsArrays L) {
+// Per-workgroup mass sums of the start state, over the same cells and by the
+// same tree as those of the new states (a state that does not change keeps
+// the scale at exactly 1).
+__global__ __launch_bounds__(256) void k_lusgs_mass0(SynthGrid g, const double* W,
+                                                     LusgsArrays L) {
   __shared__ double sh[16];
   const int C = g.nx * g.ny;
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
   double v = 0.0;
-  for (int b = 0; b < L.nb; ++b) {
-    const int c = b * (int)blockDim.x + threadIdx.x;
-    const double t = block_sum(c < C ? W[c] * cell_vol(g, c) : 0.0, sh);
-    if (threadIdx.x == 0) v += t;
+  if (w < 2) {
+    const int c = pair_cell(g, blockIdx.x * kSweepPairs + i, w == 0);
+    if (c < C) v = W[c] * cell_vol(g, c);
   }
-  if (threadIdx.x == 0) L.part[L.nb] = v;
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) L.part[L.nparts + blockIdx.x] = t;
+}
+
+// Two fixed-order block sums at once, each by the tree of block_sum.
+__device__ void block_sum2(double* a, double* b, double* sh /* [32] */) {
+  double va = *a, vb = *b;
+  for (int off = 32; off > 0; off >>= 1) {
+    va += __shfl_xor(va, off);
+    vb += __shfl_xor(vb, off);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = va;
+    sh[16 + w] = vb;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    ta += sh[k];
+    tb += sh[16 + k];
+  }
+  *a = ta;
+  *b = tb;
 }
 
 // Scale the new state to the initial mass; relative change of the iteration.
-__global__ void k_lusgs_scale(SynthGrid g, SynthArrays s, LusgsArrays L, int it) {
-  __shared__ double s_scale;
+// Every workgroup adds the per-workgroup mass sums of the new and the
+// initial state in the same fixed order; the cell's states are loaded before
+// that, so both rounds of loads overlap.
+__global__ __launch_bounds__(256) void k_lusgs_scale(SynthGrid g, SynthArrays s, LusgsArrays L,
+                                                     int it) {
+  __shared__ double sh[32];
   __shared__ double s_max[16];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int b = 0; b < L.nb; ++b) m += L.part[b];
-    s_scale = L.part[L.nb] / m;
+  double Wo[6], Wv[6];
+  if (c < C)
+    for (int k = 0; k < 6; ++k) {
+      Wo[k] = s.W[(size_t)k * C + c];
+      Wv[k] = s.Wn[(size_t)k * C + c];
+    }
+  double m = 0.0, m0 = 0.0;
+  for (int b = threadIdx.x; b < L.nparts; b += blockDim.x) {
+    m += L.part[b];
+    m0 += L.part[L.nparts + b];
   }
-  __syncthreads();
+  block_sum2(&m, &m0, sh);
+  const double scale = m0 / m;
   double ch = 0.0;
   if (c < C) {
-    const Prim p = prim_of(s.W, C, c, g.dr);
-    for (int k = 0; k < 6; ++k) s.Wn[(size_t)k * C + c] *= s_scale;
-    ch = rel_change(p, prim_of(s.Wn, C, c, g.dr));
+    for (int k = 0; k < 6; ++k) {
+      Wv[k] *= scale;
+      s.Wn[(size_t)k * C + c] = Wv[k];
+    }
+    ch = rel_change(prim_of(Wo, 1, 0, g.dr), prim_of(Wv, 1, 0, g.dr));
   }
   for (int off = 32; off > 0; off >>= 1) ch = fmax(ch, __shfl_xor(ch, off));
   if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = ch;
@@ -629,6 +801,8 @@ struct SynthLayout {
   size_t W0, W1, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, geo, total;
 };
 constexpr int kSynthBlock = 256;
+// workgroups of the LU-SGS sweep kernels: 64 pairs of cells each
+size_t sweep_groups(size_t C) { return ((C + 1) / 2 + 63) / 64; }
 
 SynthLayout synth_layout(const dig_config* c) {
   const size_t C = (size_t)c->nx * c->ny;
@@ -653,7 +827,7 @@ SynthLayout synth_layout(const dig_config* c) {
   L.R = take(8 * 6 * C);
   L.D = take(8 * 2 * C);
   L.rad = take(8 * 2 * C);
-  L.part = take(8 * ((C + kSynthBlock - 1) / kSynthBlock + 1));
+  L.part = take(8 * 2 * sweep_groups(C));
   L.chg = take(8 * 2);
   // grid geometry: widths wx, wy and centre distances gx, gy
   L.geo = take(8 * (2 * (size_t)c->nx + 2 * (size_t)c->ny + 2));
@@ -842,15 +1016,17 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   if (opts->scheme == DIG_SYNTH_LUSGS) {
     LusgsArrays la{(double*)(w + L.dW), (double*)(w + L.R), (double*)(w + L.D),
                    (double*)(w + L.rad), (double*)(w + L.part),
-                   (unsigned long long*)(w + L.chg), nb};
-    hipLaunchKernelGGL(k_lusgs_mass0, dim3(1), dim3(bs), 0, s, g, (const double*)W0, la);
+                   (unsigned long long*)(w + L.chg), (int)sweep_groups(C)};
+    const dim3 sgrid(la.nparts);
+    hipLaunchKernelGGL(k_lusgs_mass0, sgrid, dim3(bs), 0, s, g, (const double*)W0, la);
     for (it = 1; it <= max_iter; ++it) {
       SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
       const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
-      hipLaunchKernelGGL(k_synth_flux, dim3((nft + bs - 1) / bs), dim3(bs), 0, s, g, a, it);
+      hipLaunchKernelGGL(k_synth_flux, dim3((nft + kFluxFaces - 1) / kFluxFaces),
+                         dim3(2 * kFluxFaces), 0, s, g, a, it);
       hipLaunchKernelGGL(k_lusgs_cells, dim3(nb), dim3(bs), 0, s, g, a, la, it);
-      hipLaunchKernelGGL(k_lusgs_lower, dim3(nb), dim3(bs), 0, s, g, a, la);
-      hipLaunchKernelGGL(k_lusgs_upper, dim3(nb), dim3(bs), 0, s, g, a, la);
+      hipLaunchKernelGGL(k_lusgs_lower, sgrid, dim3(bs), 0, s, g, a, la);
+      hipLaunchKernelGGL(k_lusgs_upper, sgrid, dim3(bs), 0, s, g, a, la);
       hipLaunchKernelGGL(k_lusgs_scale, dim3(nb), dim3(bs), 0, s, g, a, la, it);
       double* t = cur;
       cur = nxt;
@@ -878,7 +1054,8 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   for (it = 1; it <= max_iter; ++it) {
     SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
     const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
-    hipLaunchKernelGGL(k_synth_flux, dim3((nft + bs - 1) / bs), dim3(bs), 0, s, g, a, it);
+    hipLaunchKernelGGL(k_synth_flux, dim3((nft + kFluxFaces - 1) / kFluxFaces),
+                       dim3(2 * kFluxFaces), 0, s, g, a, it);
     hipLaunchKernelGGL(k_synth_update, dim3(nb), dim3(bs), 0, s, g, a, it);
     double* t = cur;
     cur = nxt;
