@@ -352,10 +352,9 @@ __device__ __forceinline__ void red_max(unsigned long long* a, double v) {
   atomicMax(a, (unsigned long long)__double_as_longlong(v));
 }
 
-// Steady residual of cell c (flux differences over the cell plus the
-// rotational relaxation source); returns the relaxation time tau.
-__device__ double cell_residual(const SynthGrid& g, const SynthArrays& s, int c, const Prim& p,
-                                double R[6]) {
+// Flux differences over cell c (the steady residual without its source).
+__device__ __forceinline__ void flux_residual(const SynthGrid& g, const SynthArrays& s, int c,
+                                              double R[6]) {
   const int ix = c % g.nx, iy = c / g.nx;
   const int nfx = (g.nx + 1) * g.ny;
   for (int k = 0; k < 6; ++k) {
@@ -366,10 +365,23 @@ __device__ double cell_residual(const SynthGrid& g, const SynthArrays& s, int c,
       R[k] -= (Fy[ix + g.nx * (iy + 1)] - Fy[ix + g.nx * iy]) / g.wy[iy];
     }
   }
+}
+
+// Relaxation time of cell state p and its rotational relaxation source.
+__device__ __forceinline__ double relax_source(const SynthGrid& g, const Prim& p, double* tau) {
   const double mu = g.mu0 * pow(p.tt, g.omega);
-  const double tau = mu / (p.rho * p.tt);
+  *tau = mu / (p.rho * p.tt);
   const double T = (3.0 * p.tt + g.dr * p.tr) / (3.0 + g.dr);
-  R[5] += 0.5 * g.dr * p.rho * (T - p.tr) / (g.zrot * tau);
+  return 0.5 * g.dr * p.rho * (T - p.tr) / (g.zrot * *tau);
+}
+
+// Steady residual of cell c (flux differences over the cell plus the
+// rotational relaxation source); returns the relaxation time tau.
+__device__ double cell_residual(const SynthGrid& g, const SynthArrays& s, int c, const Prim& p,
+                                double R[6]) {
+  flux_residual(g, s, c, R);
+  double tau;
+  R[5] += relax_source(g, p, &tau);
   return tau;
 }
 
@@ -544,40 +556,61 @@ __device__ __forceinline__ void sweep_sum(const SweepLds& S, int i, double acc[6
 }
 
 // Residual, diagonal and spectral radii of every cell; lower sweep on the
-// first colour.  Block 0 also resets this iteration's change slot (safe in
-// stream order: its last reader, the host check of iteration it - 2, and its
-// last writer, k_lusgs_scale of iteration it - 2, precede this launch).
-__global__ void k_lusgs_cells(SynthGrid g, SynthArrays s, LusgsArrays L, int it) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// first colour.  A workgroup takes 128 cells in two roles of two waves each:
+// the flux differences, and the cell's own terms (relaxation source,
+// spectral radii, diagonal); after a barrier the first role adds the source,
+// stores the residual and, on the first colour, the increment.  Block 0 also
+// resets this iteration's change slot (safe in stream order: its last reader,
+// the host check of iteration it - 2, and its last writer, k_lusgs_scale of
+// iteration it - 2, precede this launch).
+constexpr int kCellsPerGroup = 128;
+
+__global__ __launch_bounds__(2 * kCellsPerGroup) void k_lusgs_cells(SynthGrid g, SynthArrays s,
+                                                                    LusgsArrays L, int it) {
+  __shared__ double Sd[3][kCellsPerGroup];  // source, D0, D5
+  const int role = threadIdx.x / kCellsPerGroup, i = threadIdx.x % kCellsPerGroup;
+  const int c = blockIdx.x * kCellsPerGroup + i;
   const int C = g.nx * g.ny;
-  if (c == 0) L.chg[it & 1] = 0ull;
-  if (c >= C) return;
-  const Prim p = prim_of(s.W, C, c, g.dr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.chg[it & 1] = 0ull;
   double R[6];
-  const double tau = cell_residual(g, s, c, p, R);
-  const double mu = g.mu0 * pow(p.tt, g.omega);
-  double kt, kr;
-  conductivities(g, mu, &kt, &kr);
-  const double cs = sqrt(g.gam * p.tt);
-  const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
-  const double hx = g.wx[c % g.nx];
-  const double rx = fabs(p.u[0]) + cs + 2.0 * nu / hx;
-  double d = rx / hx;
-  double ry = 0.0;
-  if (g.dim == 2) {
-    const double hy = g.wy[c / g.nx];
-    ry = fabs(p.u[1]) + cs + 2.0 * nu / hy;
-    d += ry / hy;
+  if (c < C) {
+    if (role == 0) {
+      flux_residual(g, s, c, R);
+    } else {
+      const Prim p = prim_of(s.W, C, c, g.dr);
+      double tau;
+      const double src = relax_source(g, p, &tau);
+      const double mu = g.mu0 * pow(p.tt, g.omega);
+      double kt, kr;
+      conductivities(g, mu, &kt, &kr);
+      const double cs = sqrt(g.gam * p.tt);
+      const double nu = fmax(4.0 * mu / (3.0 * p.rho), g.gam * (kt + kr) / (p.rho * g.cv));
+      const double hx = g.wx[c % g.nx];
+      const double rx = fabs(p.u[0]) + cs + 2.0 * nu / hx;
+      double d = rx / hx;
+      double ry = 0.0;
+      if (g.dim == 2) {
+        const double hy = g.wy[c / g.nx];
+        ry = fabs(p.u[1]) + cs + 2.0 * nu / hy;
+        d += ry / hy;
+      }
+      const double D0 = (1.0 + 1.0 / g.cfl) * d;
+      const double D5 = D0 + 1.0 / (g.zrot * tau);
+      L.D[c] = D0;
+      L.D[C + c] = D5;
+      L.rad[c] = rx;
+      L.rad[C + c] = ry;
+      Sd[0][i] = src;
+      Sd[1][i] = D0;
+      Sd[2][i] = D5;
+    }
   }
-  const double D0 = (1.0 + 1.0 / g.cfl) * d;
-  const double D5 = D0 + 1.0 / (g.zrot * tau);
+  __syncthreads();
+  if (role != 0 || c >= C) return;
+  R[5] += Sd[0][i];
   for (int k = 0; k < 6; ++k) L.R[(size_t)k * C + c] = R[k];
-  L.D[c] = D0;
-  L.D[C + c] = D5;
-  L.rad[c] = rx;
-  L.rad[C + c] = ry;
   if (first_colour(g, c))
-    for (int k = 0; k < 6; ++k) L.dW[(size_t)k * C + c] = R[k] / (k == 5 ? D5 : D0);
+    for (int k = 0; k < 6; ++k) L.dW[(size_t)k * C + c] = R[k] / Sd[k == 5 ? 2 : 1][i];
 }
 
 // Lower sweep on the second colour.  Wave 0 loads what it needs to finish
@@ -1024,7 +1057,8 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
       const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
       hipLaunchKernelGGL(k_synth_flux, dim3((nft + kFluxFaces - 1) / kFluxFaces),
                          dim3(2 * kFluxFaces), 0, s, g, a, it);
-      hipLaunchKernelGGL(k_lusgs_cells, dim3(nb), dim3(bs), 0, s, g, a, la, it);
+      hipLaunchKernelGGL(k_lusgs_cells, dim3((C + kCellsPerGroup - 1) / kCellsPerGroup),
+                         dim3(2 * kCellsPerGroup), 0, s, g, a, la, it);
       hipLaunchKernelGGL(k_lusgs_lower, sgrid, dim3(bs), 0, s, g, a, la);
       hipLaunchKernelGGL(k_lusgs_upper, sgrid, dim3(bs), 0, s, g, a, la);
       hipLaunchKernelGGL(k_lusgs_scale, dim3(nb), dim3(bs), 0, s, g, a, la, it);
