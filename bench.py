@@ -30,6 +30,9 @@ together by graph replays, plain DSMC.
 --workload sweep: the cavity family from 1M to 100M particles, showing where
 the step leaves the last-level cache and becomes HBM-bound.
 
+--workload synth: the synthetic-equation solve alone on the 200 x 200 cavity
+grid (LU-SGS and explicit, fixed iteration counts).
+
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 (HIP events around every kernel inside the timed region), and the FP64 oracle
 timed on the host for a bounded sample of the same workload.
@@ -365,6 +368,47 @@ def run_mlp(args):
     }
 
 
+def run_synth(args):
+    """Synthetic-equation solve on the 200 x 200 cavity grid (Kn 0.01): a
+    seeded state near rest at unit density and temperature with small
+    perturbations, masked higher-order terms of the size the DSMC extracts,
+    fixed iteration counts (LU-SGS --synth-iters, explicit 2000), timed with
+    HIP events over whole solves."""
+    import numpy as np
+    import torch
+
+    import dig_workloads as wl
+    from paper_2501_10965_amd.dsmc import synth_solve
+
+    n = 200
+    w = wl.cavity_2d(n=n, kn=0.01)
+    rng = np.random.default_rng(5)
+    nc = n * n
+    m = np.zeros((20, nc))
+    m[0] = 1.0 + 0.05 * rng.standard_normal(nc)
+    m[1:3] = 0.05 * rng.standard_normal((2, nc))
+    m[4:6] = 1.0 + 0.03 * rng.standard_normal((2, nc))
+    hot = 0.005 * rng.standard_normal((12, nc))
+    mask = (rng.random(nc) < 0.3).astype(np.uint8)
+    dev = [torch.tensor(a, device="cuda") for a in (m, hot, mask)]
+    out = {}
+    solves = max(1, min(args.steps, 20))
+    for scheme, iters in (("lusgs", args.synth_iters), ("explicit", 2000)):
+        synth_solve(w, *dev, max_iter=20, tol=0.0, scheme=scheme)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(solves):
+            synth_solve(w, *dev, max_iter=iters, tol=0.0, scheme=scheme)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / solves
+        out[scheme] = {"iterations": iters, "ms_per_solve": round(ms, 3),
+                       "us_per_iteration": round(1e3 * ms / iters, 2)}
+        progress(f"synth {scheme}: {ms:.2f} ms per solve of {iters} iterations")
+    return out, solves
+
+
 def run_cylinder(args):
     """Mach 5 flow past a cylinder: 500 x 400 stretched polar cells, ~50M
     particles at the freestream density, freestream inflow and outflow every
@@ -686,7 +730,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=150)
     ap.add_argument("--workload",
-                    choices=["cylinder", "cavity", "batch", "mlp", "steady", "sweep"],
+                    choices=["cylinder", "cavity", "batch", "mlp", "steady", "sweep", "synth"],
                     default="cylinder")
     ap.add_argument("--preroll", type=int, default=2000,
                     help="cylinder: untimed steps from the start at rest before the window")
@@ -775,6 +819,18 @@ def main():
                 "training_frac": res["training_frac"],
                 "inference_samples_per_s": res["inference_samples_per_s"]}
         print(json.dumps(line), flush=True)
+        return
+    if args.workload == "synth":
+        res, solves = run_synth(args)
+        lu = res["lusgs"]
+        print(json.dumps({"metric": "synthetic-solve iterations/s (200x200 cavity grid, LU-SGS)",
+                          "value": 1e6 / lu["us_per_iteration"], "unit": "iterations/s",
+                          "n_gpus": 1, "steps": solves, "warmup": 1,
+                          "ms_per_step": lu["ms_per_solve"], "higher_is_better": True,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "synthetic equations on the 200x200 cavity "
+                                     "grid, Kn 0.01, fixed iteration counts per solve"},
+                          "schemes": res}), flush=True)
         return
     if args.workload == "sweep":
         rows = run_sweep(args)
