@@ -9,6 +9,7 @@ a closed annulus in equilibrium, and the full-size cylinder (500 x 400 cells,
 import math
 
 import numpy as np
+import torch
 import pytest
 
 import dig_workloads as wl
@@ -197,3 +198,35 @@ def test_full_size_cylinder_steps():
     assert entered_upper > expect  # the reservoir holds more than enters
     f = np_(sim.sample("instant"))
     assert np.all(np.isfinite(f))
+
+
+def test_full_size_cylinder_inflow_is_the_one_way_flux():
+    """One step of the full-size cylinder from its freestream start: the
+    particles that entered (ids handed out to the reservoir in this step and
+    found inside the domain afterwards) number the one-way flux of the
+    drifting Maxwellian through the outer circle, within five standard
+    deviations of a count of independent entries (the reservoir reaches the
+    fastest relevant particles: its shell is (|U| + 6 sqrt(T)) dt thick)."""
+    from scipy.special import erf
+    w = wl.cylinder()
+    say("case full cylinder inflow")
+    sim = DSMC(w, cap_factor=1.3)
+    sim.init()
+    c0 = sim.counters()
+    sim.step(1)
+    c1 = sim.counters()
+    assert c1["err"] == 0
+    ids = sim.state()["id"].to(torch.int64) & 0xFFFFFFFF
+    entered = int(((ids >= c0["next_id"]) & (ids < c1["next_id"])).sum().item())
+    U, T = 5.0 * math.sqrt(1.4), 1.0
+    th = (np.arange(20000) + 0.5) * 2 * np.pi / 20000
+    s = -U * np.cos(th) / math.sqrt(2 * T)
+    flux = (math.sqrt(T / (2 * math.pi)) * (np.exp(-s * s) + math.sqrt(math.pi) * s *
+                                            (1 + erf(s)))).mean() * 2 * np.pi * 5.5
+    expect = flux * w["dt"] / w["weight"]
+    say(f"  entered {entered}, one-way flux {expect:.0f} per step")
+    assert abs(entered - expect) < 5.0 * math.sqrt(expect)
+    # every reservoir particle either entered or was removed
+    assert c1["injected"] - c0["injected"] == c1["next_id"] - c0["next_id"]
+    left_or_unused = c1["removed"] - c0["removed"]
+    assert c1["n"] == c0["n"] + (c1["injected"] - c0["injected"]) - left_or_unused
