@@ -46,10 +46,18 @@ def centreline(f: torch.Tensor, nx: int, ny: int, points: int, columns: int = 2,
     return (wgt * ux[None, :]).sum(1) / wgt.sum(1)
 
 
+def _tune(sim: DSMC, tuning: dict | None):
+    """Applies a launch configuration (results do not depend on it)."""
+    if tuning:
+        sim.tuning(**{k: tuning[k] for k in ("group_particles", "group_cells", "seq_max",
+                                             "big_stage_kib")})
+
+
 def reference_profile(w: dict, transient: int, average: int, points: int,
-                      columns: int = 2) -> torch.Tensor:
+                      columns: int = 2, tuning: dict | None = None) -> torch.Tensor:
     """Plain DSMC from rest: `transient` steps, then the average of `average`."""
     sim = DSMC(w)
+    _tune(sim, tuning)
     sim.init()
     sim.step(transient, graph=True)
     sim.reset_average()
@@ -94,8 +102,9 @@ class Tracker:
         return t
 
 
-def run_plain(w, ref, ns, max_cycles, window, threshold, points, columns=2):
+def run_plain(w, ref, ns, max_cycles, window, threshold, points, columns=2, tuning=None):
     sim = DSMC(w)
+    _tune(sim, tuning)
     sim.init()
     tr = Tracker(ref, window, threshold)
     wall = 0.0
@@ -113,12 +122,14 @@ def run_plain(w, ref, ns, max_cycles, window, threshold, points, columns=2):
     return tr
 
 
-def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, columns=2, **kw):
+def run_dig(w, ref, max_cycles, window, threshold, points, closure=None, columns=2,
+            tuning=None, **kw):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     d = DIG(w, closure=closure, **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0  # NSF initialisation counts
+    _tune(d.sim, tuning)
     tr = Tracker(ref, window, threshold)
     for k in range(max_cycles):
         torch.cuda.synchronize()
