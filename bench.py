@@ -558,7 +558,7 @@ def run_steady(args):
         progress(f"tuning {tun}")
     progress("reference run")
     ref = steady.reference_profile(w, args.steady_ref_steps[0], args.steady_ref_steps[1], P, cols,
-                                   tuning=tun)
+                                   tuning=tun, progress=progress)
     arms = {}
     progress("plain DSMC arm")
     tr = steady.run_plain(w, ref, w["ns"], args.dig_max_cycles * 4, W, thr, P, cols, tuning=tun)

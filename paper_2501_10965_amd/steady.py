@@ -54,14 +54,28 @@ def _tune(sim: DSMC, tuning: dict | None):
 
 
 def reference_profile(w: dict, transient: int, average: int, points: int,
-                      columns: int = 2, tuning: dict | None = None) -> torch.Tensor:
-    """Plain DSMC from rest: `transient` steps, then the average of `average`."""
+                      columns: int = 2, tuning: dict | None = None,
+                      progress=None, chunk: int = 5000) -> torch.Tensor:
+    """Plain DSMC from rest: `transient` steps, then the average of `average`
+    (run in chunks of `chunk` steps, `progress(message)` after each; the state
+    does not depend on the chunking)."""
     sim = DSMC(w)
     _tune(sim, tuning)
     sim.init()
-    sim.step(transient, graph=True)
+
+    def run(n, what):
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            sim.step(k, graph=True)
+            done += k
+            if progress is not None:
+                torch.cuda.synchronize()
+                progress(f"reference {what}: {done} of {n} steps")
+
+    run(transient, "transient")
     sim.reset_average()
-    sim.step(average, graph=True)
+    run(average, "average")
     f = sim.sample("average")
     return centreline(f, w["nx"], w["ny"], points, columns)
 
