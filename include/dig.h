@@ -267,7 +267,7 @@ dig_status synth_solve(const dig_config* cfg_host, const dig_synth_opts* opts_ho
  * on until the process ends, instead of a caller workspace.  The caller still
  * passes the inputs and m_next_dev.  Calls no allocation routine.  Grids
  * whose dig_synth_workspace_bytes exceed DIG_SYNTH_STATIC_BYTES (about
- * 80,000 cells) give DIG_ERR_INVALID.  Every call on one GPU shares that
+ * 70,000 cells) give DIG_ERR_INVALID.  Every call on one GPU shares that
  * GPU's array, which keeps the last call's contents (each call initialises
  * what it reads): calls that overlap in time on one GPU (other host threads,
  * other streams) race and must be serialised by the caller. */

@@ -43,6 +43,8 @@ struct SynthArrays {
   double* Fx;        // [6][ny][nx+1]
   double* Fy;        // [6][ny+1][nx]
   const double* H;   // [12][C] masked HoT (zeros when none)
+  double* P;         // [6][C] primitives (rho, ux, uy, uz, Tt, Tr) of W: written by the kernel
+                     // that produces a state, read by the next iteration's kernels
   const double* wall;  // [4 faces][5][max(nx,ny)]: ux uy uz tt tr of each wall face
   unsigned long long* red;  // [2][2]: dtau (min), change (max), by iteration parity
 };
@@ -50,6 +52,23 @@ struct SynthArrays {
 struct Prim {
   double rho, u[3], tt, tr;
 };
+
+// Stored primitives of cell c.
+__device__ __forceinline__ Prim prim_at(const double* P, int C, int c) {
+  Prim p;
+  p.rho = P[c];
+  for (int k = 0; k < 3; ++k) p.u[k] = P[(1 + k) * C + c];
+  p.tt = P[4 * C + c];
+  p.tr = P[5 * C + c];
+  return p;
+}
+
+__device__ __forceinline__ void store_prim(double* P, int C, int c, const Prim& p) {
+  P[c] = p.rho;
+  for (int k = 0; k < 3; ++k) P[(1 + k) * C + c] = p.u[k];
+  P[4 * C + c] = p.tt;
+  P[5 * C + c] = p.tr;
+}
 
 __device__ __forceinline__ Prim prim_of(const double* W, int C, int c, int dr) {
   Prim p;
@@ -72,7 +91,7 @@ __device__ __forceinline__ void conductivities(const SynthGrid& g, double mu, do
 // the two neighbours (one-sided at a wall) over the distance between their
 // centres.  The neighbours are chosen first and then loaded without a branch,
 // so the loads of all calls issue together.
-__device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int iy, int k,
+__device__ double dcen_u(const SynthGrid& g, const double* P, int C, int ix, int iy, int k,
                          int axis) {
   if (axis == 1 && g.dim == 1) return 0.0;
   const int n = axis == 0 ? g.nx : g.ny;
@@ -96,8 +115,8 @@ __device__ double dcen_u(const SynthGrid& g, const double* W, int C, int ix, int
   const double g1 = gap[i + 1];
   const int cp = axis == 0 ? jp + g.nx * iy : ix + g.nx * jp;
   const int cm = axis == 0 ? jm + g.nx * iy : ix + g.nx * jm;
-  const double up = W[(1 + k) * C + cp] / W[cp];
-  const double um = W[(1 + k) * C + cm] / W[cm];
+  const double up = P[(1 + k) * C + cp];
+  const double um = P[(1 + k) * C + cm];
   if (!per && n < 2) return 0.0;
   return (up - um) / (inner ? g0 + g1 : g0);
 }
@@ -190,7 +209,7 @@ __device__ __forceinline__ bool face_inviscid(const SynthGrid& g, const SynthArr
   if (fc.wall) return false;
   const int C = g.nx * g.ny;
   const int cl = fc.cell(g, (fc.f - 1 + fc.n) % fc.n), cr = fc.cell(g, fc.f % fc.n);
-  const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
+  const Prim pl = prim_at(s.P, C, cl), pr = prim_at(s.P, C, cr);
   double Ul[6], Ur[6], Fl[6], Fr[6];
   for (int k = 0; k < 6; ++k) {
     Ul[k] = s.W[k * C + cl];
@@ -234,7 +253,7 @@ __device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArra
   if (!fc.wall) {
     const int al = (fc.f - 1 + fc.n) % fc.n, ar = fc.f % fc.n;
     const int cl = fc.cell(g, al), cr = fc.cell(g, ar);
-    const Prim pl = prim_of(s.W, C, cl, g.dr), pr = prim_of(s.W, C, cr, g.dr);
+    const Prim pl = prim_at(s.P, C, cl), pr = prim_at(s.P, C, cr);
     int ixl, iyl, ixr, iyr;
     fc.xy(al, &ixl, &iyl);
     fc.xy(ar, &ixr, &iyr);
@@ -243,8 +262,8 @@ __device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArra
     for (int i = 0; i < 3; ++i) {
       uf[i] = 0.5 * (pl.u[i] + pr.u[i]);
       dn[i] = (pr.u[i] - pl.u[i]) / h;
-      dtn[i] = g.dim == 2 ? 0.5 * (dcen_u(g, s.W, C, ixl, iyl, i, 1 - axis) +
-                                   dcen_u(g, s.W, C, ixr, iyr, i, 1 - axis))
+      dtn[i] = g.dim == 2 ? 0.5 * (dcen_u(g, s.P, C, ixl, iyl, i, 1 - axis) +
+                                   dcen_u(g, s.P, C, ixr, iyr, i, 1 - axis))
                           : 0.0;
     }
     for (int k = 0; k < 12; ++k) Hf[k] = 0.5 * (s.H[k * C + cl] + s.H[k * C + cr]);
@@ -257,7 +276,7 @@ __device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArra
   const int c = fc.cell(g, al);
   int ix, iy;
   fc.xy(al, &ix, &iy);
-  const Prim p = prim_of(s.W, C, c, g.dr);
+  const Prim p = prim_at(s.P, C, c);
   const int nmax = g.nx > g.ny ? g.nx : g.ny;
   const int wi = axis == 0 ? fc.fb : fc.fa;  // position along the wall
   const double* wv = s.wall + (size_t)face * 5 * nmax;
@@ -267,7 +286,7 @@ __device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArra
   double dn[3], dtn[3], Hf[12];
   for (int i = 0; i < 3; ++i) {
     dn[i] = sgn * (p.u[i] - uw[i]) / h;
-    dtn[i] = g.dim == 2 ? dcen_u(g, s.W, C, ix, iy, i, 1 - axis) : 0.0;
+    dtn[i] = g.dim == 2 ? dcen_u(g, s.P, C, ix, iy, i, 1 - axis) : 0.0;
   }
   for (int k = 0; k < 12; ++k) Hf[k] = s.H[k * C + c];
   visc_flux<axis>(g, 0.5 * (p.tt + ttw), uw, dn, dtn, sgn * (p.tt - ttw) / h,
@@ -399,11 +418,12 @@ __global__ void k_synth_update(SynthGrid g, SynthArrays s, int it) {
   double dtb = 0.0, ch = 0.0;
   if (c < C) {
     const double dtau = __longlong_as_double((long long)s.red[(it & 1) * 2 + 0]);
-    const Prim p = prim_of(s.W, C, c, g.dr);
+    const Prim p = prim_at(s.P, C, c);
     double R[6];
     cell_residual(g, s, c, p, R);
     for (int k = 0; k < 6; ++k) s.Wn[k * C + c] = s.W[k * C + c] + dtau * R[k];
     const Prim q = prim_of(s.Wn, C, c, g.dr);
+    store_prim(s.P, C, c, q);  // this thread's cell only: read above
     ch = rel_change(p, q);
     dtb = dt_bound(g, q, c);
   }
@@ -577,7 +597,7 @@ __global__ __launch_bounds__(2 * kCellsPerGroup) void k_lusgs_cells(SynthGrid g,
     if (role == 0) {
       flux_residual(g, s, c, R);
     } else {
-      const Prim p = prim_of(s.W, C, c, g.dr);
+      const Prim p = prim_at(s.P, C, c);
       double tau;
       const double src = relax_source(g, p, &tau);
       const double mu = g.mu0 * pow(p.tt, g.omega);
@@ -736,12 +756,12 @@ __global__ __launch_bounds__(256) void k_lusgs_scale(SynthGrid g, SynthArrays s,
   __shared__ double s_max[16];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
-  double Wo[6], Wv[6];
-  if (c < C)
-    for (int k = 0; k < 6; ++k) {
-      Wo[k] = s.W[(size_t)k * C + c];
-      Wv[k] = s.Wn[(size_t)k * C + c];
-    }
+  double Wv[6];
+  Prim po;
+  if (c < C) {
+    for (int k = 0; k < 6; ++k) Wv[k] = s.Wn[(size_t)k * C + c];
+    po = prim_at(s.P, C, c);
+  }
   double m = 0.0, m0 = 0.0;
   for (int b = threadIdx.x; b < L.nparts; b += blockDim.x) {
     m += L.part[b];
@@ -755,7 +775,9 @@ __global__ __launch_bounds__(256) void k_lusgs_scale(SynthGrid g, SynthArrays s,
       Wv[k] *= scale;
       s.Wn[(size_t)k * C + c] = Wv[k];
     }
-    ch = rel_change(prim_of(Wo, 1, 0, g.dr), prim_of(Wv, 1, 0, g.dr));
+    const Prim q = prim_of(Wv, 1, 0, g.dr);
+    store_prim(s.P, C, c, q);  // this thread's cell only: read above
+    ch = rel_change(po, q);
   }
   for (int off = 32; off > 0; off >>= 1) ch = fmax(ch, __shfl_xor(ch, off));
   if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = ch;
@@ -767,8 +789,8 @@ __global__ __launch_bounds__(256) void k_lusgs_scale(SynthGrid g, SynthArrays s,
 }
 
 // Initial conservative state, wall face values and the first pseudo-time step.
-__global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* wall, int mode,
-                             const double* wall_cfg, unsigned long long* red) {
+__global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* P, double* wall,
+                             int mode, const double* wall_cfg, unsigned long long* red) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = g.nx * g.ny;
   // iteration 1 reads its step from the parity-1 slot, which the host resets
@@ -782,6 +804,12 @@ __global__ void k_synth_init(SynthGrid g, const double* m, double* W, double* wa
   for (int k = 0; k < 3; ++k) W[(1 + k) * C + c] = rho * u[k];
   W[4 * C + c] = rho * (0.5 * (3.0 * tt + g.dr * tr) + 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
   W[5 * C + c] = rho * 0.5 * g.dr * tr;
+  {
+    // the primitives the solve reads, as they follow from the stored state
+    double Wl[6];
+    for (int k = 0; k < 6; ++k) Wl[k] = W[(size_t)k * C + c];
+    store_prim(P, C, c, prim_of(Wl, 1, 0, g.dr));
+  }
   const int ix = c % g.nx, iy = c / g.nx;
   const int nmax = g.nx > g.ny ? g.nx : g.ny;
   for (int face = 0; face < (g.dim == 2 ? 4 : 2); ++face) {
@@ -831,7 +859,7 @@ thread_local std::string g_serr;
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct SynthLayout {
-  size_t W0, W1, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, geo, total;
+  size_t W0, W1, P, Fx, Fy, H, wall, wcfg, red, dW, R, D, rad, part, chg, geo, total;
 };
 constexpr int kSynthBlock = 256;
 // workgroups of the LU-SGS sweep kernels: 64 pairs of cells each
@@ -849,6 +877,7 @@ SynthLayout synth_layout(const dig_config* c) {
   };
   L.W0 = take(8 * 6 * C);
   L.W1 = take(8 * 6 * C);
+  L.P = take(8 * 6 * C);
   L.Fx = take(8 * 6 * (c->nx + 1) * (size_t)c->ny);
   L.Fy = take(8 * 6 * (size_t)c->nx * (c->ny + 1));
   L.H = take(8 * 12 * C);
@@ -1012,6 +1041,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   }
   double* W0 = (double*)(w + L.W0);
   double* W1 = (double*)(w + L.W1);
+  double* Pv = (double*)(w + L.P);
   double* H = (double*)(w + L.H);
   double* wall = (double*)(w + L.wall);
   double* dwcfg = (double*)(w + L.wcfg);
@@ -1039,7 +1069,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
   if (launch_fill_f64((double*)red + 2, 1, INFINITY, s) != hipSuccess ||
       launch_fill_f64((double*)red + 3, 1, 0.0, s) != hipSuccess)
     return DIG_ERR_HIP;
-  hipLaunchKernelGGL(k_synth_init, dim3(nb), dim3(bs), 0, s, g, m_half, W0, wall,
+  hipLaunchKernelGGL(k_synth_init, dim3(nb), dim3(bs), 0, s, g, m_half, W0, Pv, wall,
                      opts->wall_mode, (const double*)dwcfg, red);
   const int check = opts->check_every > 0 ? opts->check_every : 32;
   double* cur = W0;
@@ -1053,7 +1083,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
     const dim3 sgrid(la.nparts);
     hipLaunchKernelGGL(k_lusgs_mass0, sgrid, dim3(bs), 0, s, g, (const double*)W0, la);
     for (it = 1; it <= max_iter; ++it) {
-      SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
+      SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, Pv, wall, red};
       const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
       hipLaunchKernelGGL(k_synth_flux, dim3((nft + kFluxFaces - 1) / kFluxFaces),
                          dim3(2 * kFluxFaces), 0, s, g, a, it);
@@ -1086,7 +1116,7 @@ dig_status synth_solve(const dig_config* cfg, const dig_synth_opts* opts, const 
     return DIG_OK;
   }
   for (it = 1; it <= max_iter; ++it) {
-    SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, wall, red};
+    SynthArrays a{cur, nxt, (double*)(w + L.Fx), (double*)(w + L.Fy), H, Pv, wall, red};
     const int nft = (g.nx + 1) * g.ny + (g.dim == 2 ? g.nx * (g.ny + 1) : 0);
     hipLaunchKernelGGL(k_synth_flux, dim3((nft + kFluxFaces - 1) / kFluxFaces),
                        dim3(2 * kFluxFaces), 0, s, g, a, it);
