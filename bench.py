@@ -122,11 +122,19 @@ def roofline(prof, breakdown, n_avg, ncell, workload, dim):
                 "avg_launch_us": round(avg_s * 1e6, 2)}
     alg = collide_particle_bytes(dim) * n_avg + PER_CELL_BYTES * ncell
     ach = alg / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("collide", workload, n_avg),
-            "kernel": "k_collide + k_collide_big (collide stage, one launch each per step)",
-            "avg_launch_us": round(avg_s * 1e6, 2),
-            "algorithmic_bytes_per_launch": int(alg)}
+    traffic = pmc_traffic("collide", workload, n_avg)
+    out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": "k_collide + k_collide_big (collide stage, one launch each per step)",
+           "avg_launch_us": round(avg_s * 1e6, 2),
+           "algorithmic_bytes_per_launch": int(alg)}
+    if traffic:
+        # the rate of the measured HBM bytes beside the algorithmic one: what the
+        # memory system actually moves (partial sectors, re-reads) per launch
+        out["traffic_GBs"] = round(traffic / avg_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+        out["traffic_over_algorithmic"] = round(traffic / alg, 3)
+    return out
 
 
 def summarise(prof, breakdown, psteps, sec, nsteps, n_avg, ncell, dim, workload):
