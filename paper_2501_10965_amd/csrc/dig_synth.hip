@@ -305,11 +305,12 @@ __device__ __forceinline__ void face_viscous(const SynthGrid& g, const SynthArra
 // faces: waves 0-1 their HLLC fluxes, waves 2-3 their viscous and heat
 // fluxes (two chains of half the length: the grid has too few faces to hide
 // latency otherwise); the inviscid waves add the two and store.  Thread 0
-// also resets the next iteration's reductions (parity it + 1).  That is safe
-// only through stream order: the last kernel to touch those slots is the
-// update of iteration it - 1, which read its time step from them, and it has
-// completed before this launch starts on the same stream; the update of this
-// iteration, the next to use them, starts after this launch has completed.
+// of workgroup 0 also resets the next iteration's reductions (parity
+// it + 1).  That is safe only through stream order: the last kernel to touch
+// those slots is the update of iteration it - 1, which read its time step
+// from them, and it has completed before this launch starts on the same
+// stream; the update of this iteration, the next to use them, starts after
+// this launch has completed.
 constexpr int kFluxFaces = 128;
 
 __global__ __launch_bounds__(256) void k_synth_flux(SynthGrid g, SynthArrays s, int it) {
